@@ -1,0 +1,343 @@
+/*
+ * CPU FP64 oracle for the hybrid FEM/LBM transport method of Karimi and
+ * Nakshatrala (arXiv:1601.02708).  TEST INFRASTRUCTURE ONLY: nothing in the
+ * product path may link, load or call this file; only the test-suite, the
+ * smoke check and the benchmark's CPU-baseline leg use it.
+ *
+ * Plain, slow and literal: each part of the method is a separate loop over
+ * the lattice or the mesh, written in the order the paper states it.  No
+ * SIMD, no blocking, no fusion.  Build: gcc -O2 -ffp-contract=off.
+ *
+ * Lattice-unit conventions: fine spacing 1, fine step 1; node (i, j) of an
+ * N x N lattice is stored at n = j*N + i; populations are planes [9][N*N].
+ * The stored state between sub-steps is the POST-collision population f*.
+ *
+ * Parts and the passages they follow:
+ *   - D2Q9 velocities and weights with c_s^2 = 1/3            (Sec. 4.1)
+ *   - equilibrium, eq. (LBM_feq), with the quadratic term read as
+ *     -v.v/(2 c_s^2) (the printed -v.v/c_s^2 would not conserve mass)
+ *   - BGK collision, eqs. (LBE) and (Collision); first-order reaction
+ *     source -k w_i u added to the collision (not in the paper's LBM)
+ *   - macroscopic moments, eq. (LBM_Macro)
+ *   - maximum-entropy Dirichlet closure, eq. (LBM_Dir), and Neumann
+ *     closure, eq. (LBM_Neu)                                   (Sec. 4.1.1)
+ *   - Q1 finite elements, Galerkin eq. (Galerkin) and SUPG eqs. (SUPG),
+ *     (SUPG_tau), trapezoidal time stepping eq. (FEM_discrete)  (Secs. 3, 6.1)
+ *   - coarse-to-fine and fine-to-coarse transfers               (Secs. 5.1, 6.2)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* D2Q9 lattice (Sec. 4.1): rest, 4 axis, 4 diagonal velocities.            */
+/* ------------------------------------------------------------------------ */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double WT[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double CS2 = 1.0 / 3.0;
+
+void orc_d2q9(int *ex, int *ey, double *w, int *opp) {
+    for (int i = 0; i < 9; ++i) {
+        ex[i] = EX[i];
+        ey[i] = EY[i];
+        w[i] = WT[i];
+        opp[i] = OPP[i];
+    }
+}
+
+/* Equilibrium, eq. (LBM_feq):
+ *   f_i^eq = w_i u (1 + e.v/c_s^2 + (e.v)^2/(2 c_s^4) - v.v/(2 c_s^2)). */
+void orc_feq(double u, double vx, double vy, double *feq) {
+    double vv = vx * vx + vy * vy;
+    for (int i = 0; i < 9; ++i) {
+        double ev = EX[i] * vx + EY[i] * vy;
+        feq[i] = WT[i] * u * (1.0 + ev / CS2 + (ev * ev) / (2.0 * CS2 * CS2) - vv / (2.0 * CS2));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice description                                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int N;                       /* nodes per side */
+    int periodic_x, periodic_y;  /* 1: sources beyond that edge wrap (test mode) */
+    double tau;                  /* BGK relaxation time */
+    const uint8_t *solid;        /* [N*N] 1 = solid node, or NULL */
+    const double *vx, *vy;       /* [N*N] advection velocity */
+    const double *k;             /* [N*N] reaction rate per node, or NULL */
+    double kval;                 /* uniform reaction rate when k == NULL */
+    const int8_t *bc_kind;       /* [4(N-1)] 0 Dirichlet, 1 Neumann, or NULL (all Dirichlet) */
+    int clamp;                   /* Dirichlet closure: 0 as printed, 1 clamp unknowns at 0 */
+} orc_lattice;
+
+static int is_solid(const orc_lattice *L, int n) { return L->solid && L->solid[n]; }
+static double kat(const orc_lattice *L, int n) { return L->k ? L->k[n] : L->kval; }
+
+/* Perimeter slot of node (i, j), or -1 for interior nodes.  Slots run along
+ * the bottom row (j = 0, i = 0..N-1), the top row (j = N-1, i = 0..N-1), the
+ * left column (i = 0, j = 1..N-2) and the right column (i = N-1, j = 1..N-2). */
+int orc_perimeter_slot(int N, int i, int j) {
+    if (j == 0) return i;
+    if (j == N - 1) return N + i;
+    if (i == 0) return 2 * N + (j - 1);
+    if (i == N - 1) return 2 * N + (N - 2) + (j - 1);
+    return -1;
+}
+
+void orc_perimeter_node(int N, int p, int *i, int *j) {
+    if (p < N) { *i = p; *j = 0; return; }
+    if (p < 2 * N) { *i = p - N; *j = N - 1; return; }
+    if (p < 3 * N - 2) { *i = 0; *j = p - 2 * N + 1; return; }
+    *i = N - 1; *j = p - (3 * N - 2) + 1;
+}
+
+/* Outward normal direction (unnormalised, components in {-1,0,1}) of a
+ * perimeter node; corners take the sum of their two edges' normals. */
+static void outward_dir(int N, int i, int j, int *sx, int *sy) {
+    *sx = (i == 0) ? -1 : (i == N - 1) ? 1 : 0;
+    *sy = (j == 0) ? -1 : (j == N - 1) ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initialisation (Sec. 6.2, item i): f_i(x, 0) = f_i^eq(u_0(x)); the stored  */
+/* state is the post-collision value of that field.                         */
+/* ------------------------------------------------------------------------ */
+void orc_collide(const orc_lattice *L, const double *f, double *fstar);
+
+void orc_lbm_init(const orc_lattice *L, const double *u0, double *fstar) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    double *f = (double *)calloc(9 * NN, sizeof(double));
+    for (int n = 0; n < (int)NN; ++n) {
+        if (is_solid(L, n)) continue;
+        double feq[9];
+        orc_feq(u0[n], L->vx[n], L->vy[n], feq);
+        for (int i = 0; i < 9; ++i) f[i * NN + n] = feq[i];
+    }
+    orc_collide(L, f, fstar);
+    free(f);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Streaming, eq. (LBE), written as a pull: the population arriving at x     */
+/* along e_i left x - e_i one step earlier.  A source that is a solid node   */
+/* returns the population that x itself sent towards it (halfway bounce-    */
+/* back).  A source outside the patch (non-periodic edge) leaves f_i unknown */
+/* and flags it in unknown[n] (bit i).                                      */
+/* ------------------------------------------------------------------------ */
+void orc_stream(const orc_lattice *L, const double *fstar, double *f, uint16_t *unknown) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    for (int j = 0; j < N; ++j) {
+        for (int i = 0; i < N; ++i) {
+            int n = j * N + i;
+            unknown[n] = 0;
+            if (is_solid(L, n)) {
+                for (int q = 0; q < 9; ++q) f[q * NN + n] = 0.0;
+                continue;
+            }
+            for (int q = 0; q < 9; ++q) {
+                int si = i - EX[q], sj = j - EY[q];
+                int outside = 0;
+                if (si < 0 || si >= N) {
+                    if (L->periodic_x) si = (si + N) % N; else outside = 1;
+                }
+                if (sj < 0 || sj >= N) {
+                    if (L->periodic_y) sj = (sj + N) % N; else outside = 1;
+                }
+                if (outside) {
+                    f[q * NN + n] = 0.0;
+                    unknown[n] |= (uint16_t)(1u << q);
+                    continue;
+                }
+                int s = sj * N + si;
+                if (is_solid(L, s))
+                    f[q * NN + n] = fstar[OPP[q] * NN + n];
+                else
+                    f[q * NN + n] = fstar[q * NN + s];
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Maximum-entropy Dirichlet closure, eq. (LBM_Dir):                         */
+/*   f_i = w_i / (sum_{j in U} w_j) * (u^p - sum_{k not in U} f_k),  i in U, */
+/* the minimiser of H over the unknowns under sum_i f_i = u^p.  The result  */
+/* is non-negative only when the bracket R is >= 0.  When R < 0 no          */
+/* non-negative closure meets the constraint; the node is counted (return  */
+/* 1) and, with clamp == 0, the closed form is applied as printed (the      */
+/* constraint holds exactly, the unknowns are negative); with clamp != 0    */
+/* the unknowns are set to 0 instead (non-negativity kept, constraint       */
+/* missed).                                                                 */
+/* ------------------------------------------------------------------------ */
+int orc_maxent_dirichlet(double *f, unsigned unknown, double up, int clamp) {
+    double known = 0.0, wsum = 0.0;
+    for (int q = 0; q < 9; ++q) {
+        if (unknown & (1u << q)) wsum += WT[q];
+        else known += f[q];
+    }
+    double R = up - known;
+    int infeasible = R < 0.0;
+    if (infeasible && clamp) R = 0.0;
+    for (int q = 0; q < 9; ++q) if (unknown & (1u << q)) f[q] = WT[q] / wsum * R;
+    return infeasible;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Maximum-entropy Neumann closure, eq. (LBM_Neu).  With n the unit outward  */
+/* normal and M- = {i unknown : e_i.n < 0}, the unknowns are                */
+/*   f_i = w_i exp(-1 - gamma e_i.n),                                       */
+/* where gamma solves                                                       */
+/*   sum_{i in M-} w_i (e_i.n) exp(-1 - gamma e_i.n)                        */
+/*        = q^p - sum_{j not in M-} (e_j.n) f_j .                           */
+/* The left side is negative and strictly decreasing in gamma, so a root   */
+/* exists iff the right side is negative; it is found by bisection.  At a   */
+/* patch corner (diagonal normal) two unknowns have e_i.n = 0; they carry   */
+/* no flux and are set by bounce-back from the node's own post-collision    */
+/* populations.  Returns 1 when infeasible (unknowns of M- set to 0).       */
+/* ------------------------------------------------------------------------ */
+static double neumann_lhs(const double *a, unsigned set, double gamma) {
+    double s = 0.0;
+    for (int q = 0; q < 9; ++q)
+        if (set & (1u << q)) s += WT[q] * a[q] * exp(-1.0 - gamma * a[q]);
+    return s;
+}
+
+int orc_maxent_neumann(double *f, unsigned unknown, int sx, int sy, double qp,
+                       const double *fstar_self) {
+    double nrm = sqrt((double)(sx * sx + sy * sy));
+    double a[9];
+    unsigned mminus = 0;
+    for (int q = 0; q < 9; ++q) {
+        int dot = EX[q] * sx + EY[q] * sy;
+        a[q] = dot / nrm;
+        if (unknown & (1u << q)) {
+            if (dot < 0) mminus |= 1u << q;
+            else f[q] = fstar_self[OPP[q]];          /* tangential unknown at a corner */
+        }
+    }
+    double rhs = qp;
+    for (int q = 0; q < 9; ++q)
+        if (!(mminus & (1u << q))) rhs -= a[q] * f[q];
+    if (!(rhs < 0.0)) {
+        for (int q = 0; q < 9; ++q) if (mminus & (1u << q)) f[q] = 0.0;
+        return 1;
+    }
+    /* bracket: lhs(lo) > rhs > lhs(hi) */
+    double lo = -1.0, hi = 1.0;
+    while (neumann_lhs(a, mminus, lo) <= rhs) lo *= 2.0;
+    while (neumann_lhs(a, mminus, hi) >= rhs) hi *= 2.0;
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (neumann_lhs(a, mminus, mid) > rhs) lo = mid; else hi = mid;
+    }
+    double gamma = 0.5 * (lo + hi);
+    for (int q = 0; q < 9; ++q)
+        if (mminus & (1u << q)) f[q] = WT[q] * exp(-1.0 - gamma * a[q]);
+    return 0;
+}
+
+/* Apply the boundary closures at every perimeter node that has unknowns.
+ * bc_value[p] is u^p (Dirichlet) or q^p (Neumann) for perimeter slot p.
+ * Returns the number of infeasible nodes. */
+long orc_apply_bc(const orc_lattice *L, const double *fstar, double *f,
+                  const uint16_t *unknown, const double *bc_value) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    long infeasible = 0;
+    for (int p = 0; p < 4 * (N - 1); ++p) {
+        int i, j;
+        orc_perimeter_node(N, p, &i, &j);
+        int n = j * N + i;
+        if (is_solid(L, n) || unknown[n] == 0) continue;
+        double fn[9], fs[9];
+        for (int q = 0; q < 9; ++q) {
+            fn[q] = f[q * NN + n];
+            fs[q] = fstar[q * NN + n];
+        }
+        int kind = L->bc_kind ? L->bc_kind[p] : 0;
+        if (kind == 0) {
+            infeasible += orc_maxent_dirichlet(fn, unknown[n], bc_value[p], L->clamp);
+        } else {
+            int sx, sy;
+            outward_dir(N, i, j, &sx, &sy);
+            infeasible += orc_maxent_neumann(fn, unknown[n], sx, sy, bc_value[p], fs);
+        }
+        for (int q = 0; q < 9; ++q) f[q * NN + n] = fn[q];
+    }
+    return infeasible;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collision, eq. (Collision), with u from eq. (LBM_Macro) and a first-order */
+/* reaction source:  f*_i = f_i + (f_i^eq(u) - f_i)/tau - k w_i u.          */
+/* ------------------------------------------------------------------------ */
+void orc_collide(const orc_lattice *L, const double *f, double *fstar) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    for (int n = 0; n < (int)NN; ++n) {
+        if (is_solid(L, n)) {
+            for (int q = 0; q < 9; ++q) fstar[q * NN + n] = 0.0;
+            continue;
+        }
+        double u = 0.0;
+        for (int q = 0; q < 9; ++q) u += f[q * NN + n];
+        double feq[9];
+        orc_feq(u, L->vx[n], L->vy[n], feq);
+        double k = kat(L, n);
+        for (int q = 0; q < 9; ++q) {
+            double fq = f[q * NN + n];
+            fstar[q * NN + n] = fq + (feq[q] - fq) / L->tau - k * WT[q] * u;
+        }
+    }
+}
+
+/* One fine time step: stream, impose the boundary closures, collide.
+ * fdst may not alias fsrc.  Returns the infeasible-node count. */
+long orc_lbm_substep(const orc_lattice *L, const double *fsrc, double *fdst, const double *bc_value) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    double *f = (double *)malloc(9 * NN * sizeof(double));
+    uint16_t *unknown = (uint16_t *)malloc(NN * sizeof(uint16_t));
+    orc_stream(L, fsrc, f, unknown);
+    long inf = orc_apply_bc(L, fsrc, f, unknown, bc_value);
+    orc_collide(L, f, fdst);
+    free(f);
+    free(unknown);
+    return inf;
+}
+
+/* Concentration at every node from the stored post-collision populations.
+ * Summing the collision over i gives  sum f*_i = (1 - k) u,  so
+ * u = sum_i f*_i / (1 - k); solid nodes return 0. */
+void orc_concentration(const orc_lattice *L, const double *fstar, double *u) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    for (int n = 0; n < (int)NN; ++n) {
+        if (is_solid(L, n)) { u[n] = 0.0; continue; }
+        double s = 0.0;
+        for (int q = 0; q < 9; ++q) s += fstar[q * NN + n];
+        u[n] = s / (1.0 - kat(L, n));
+    }
+}
+
+/* Boltzmann H function, eq. (BH), summed over fluid nodes. */
+double orc_h_function(const orc_lattice *L, const double *f) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    double H = 0.0;
+    for (int n = 0; n < (int)NN; ++n) {
+        if (is_solid(L, n)) continue;
+        for (int q = 0; q < 9; ++q) {
+            double v = f[q * NN + n];
+            if (v > 0.0) H += v * log(v / WT[q]);
+        }
+    }
+    return H;
+}

@@ -1,0 +1,136 @@
+"""Run descriptors for the hybrid FEM/LBM workloads and the seeded problem
+arrays they expand to.
+
+Three workloads are defined, all in lattice units (fine spacing 1, fine
+step 1, coarse step = eta):
+
+* ``small``  -- 64^2 lattice, 16^2 bilinear mesh, uniform velocity
+  (0.05, 0), D = 1e-2, no reaction, 4 substeps x 100 coarse steps x 2
+  Schwarz iterations.  Correctness workload.
+* ``pore2048`` -- 2048^2 lattice with random disks (porosity 0.6), a
+  seeded 8-mode stream-function velocity (max |v| = 0.05 over fluid nodes,
+  zero in solids), D = 5e-3, first-order reaction k = 1e-4, 128^2 mesh,
+  10 substeps x 200 coarse steps x 2 Schwarz iterations.  Throughput
+  workload.
+* ``pore4096`` -- the same generators at 4096^2 with D = 1e-2, no reaction,
+  16^2 mesh, 4 substeps x 100 coarse steps x 2 Schwarz iterations.
+  Precision workload.
+
+The relaxation time follows the lattice-unit relation tau = 1/2 + D/c_s^2
+with c_s^2 = 1/3 (Sec. 4.1); the outer boundary of the coarse domain is
+Dirichlet 0 on all four edges, and the initial condition is the seeded
+Gaussian pulse on both grids.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from . import inputs
+
+
+@dataclasses.dataclass(frozen=True)
+class HybridConfig:
+    name: str
+    N: int                      # fine nodes per side
+    M: int                      # coarse elements per side
+    D: float                    # diffusion coefficient (lattice units)
+    eta: int                    # fine substeps per coarse step
+    steps: int                  # coarse steps
+    max_iter: int               # Schwarz iterations per coarse step
+    k: float = 0.0              # uniform first-order reaction rate (per lattice step)
+    porosity: Optional[float] = None     # None: no solids
+    velocity: str = "uniform"            # "uniform" or "stream"
+    v_uniform: tuple = (0.05, 0.0)
+    v_max: float = 0.05
+    overlap_elems: int = 1      # overlap width in coarse elements
+    supg: int = 1
+    bc_clamp: int = 0           # maxent Dirichlet: 0 closed form as printed, 1 clamp at 0
+    seed: int = 0
+    tau: Optional[float] = None  # None: 1/2 + 3 D
+
+    @property
+    def L(self) -> float:
+        return inputs.domain_side(self.N)
+
+    @property
+    def tau_value(self) -> float:
+        return self.tau if self.tau is not None else 0.5 + 3.0 * self.D
+
+    def replace(self, **kw) -> "HybridConfig":
+        return dataclasses.replace(self, **kw)
+
+
+SMALL = HybridConfig(name="small", N=64, M=16, D=1e-2, eta=4, steps=100, max_iter=2,
+                     velocity="uniform", v_uniform=(0.05, 0.0))
+PORE2048 = HybridConfig(name="pore2048", N=2048, M=128, D=5e-3, eta=10, steps=200,
+                        max_iter=2, k=1e-4, porosity=0.6, velocity="stream")
+PORE4096 = HybridConfig(name="pore4096", N=4096, M=16, D=1e-2, eta=4, steps=100,
+                        max_iter=2, k=0.0, porosity=0.6, velocity="stream")
+
+CONFIGS = {c.name: c for c in (SMALL, PORE2048, PORE4096)}
+
+
+@dataclasses.dataclass
+class Problem:
+    """Host arrays of one seeded workload (shared by oracle and GPU path)."""
+    cfg: HybridConfig
+    solid: np.ndarray        # uint8 [N, N]
+    vx: np.ndarray           # float32 [N, N] fine velocity (zero in solids)
+    vy: np.ndarray
+    vc: np.ndarray           # float64 [(M+1)^2, 2] coarse nodal velocity
+    u0_fine: np.ndarray      # float64 [N, N]
+    u0_coarse: np.ndarray    # float64 [(M+1)^2]
+    porosity: float
+    x0: float
+    y0: float
+    L: float
+
+
+def build_problem(cfg: HybridConfig) -> Problem:
+    N, M = cfg.N, cfg.M
+    L = cfg.L
+    x0 = inputs.patch_origin(N)
+    X, Y = inputs.fine_coords(N)
+    XC, YC = inputs.coarse_coords(M, L)
+
+    if cfg.porosity is not None:
+        pack = inputs.random_disks(N, cfg.porosity, seed=cfg.seed + 1000)
+        solid = pack.solid
+        porosity = pack.porosity
+    else:
+        solid = np.zeros((N, N), dtype=np.uint8)
+        porosity = 1.0
+
+    if cfg.velocity == "uniform":
+        vx64 = np.full((N, N), cfg.v_uniform[0])
+        vy64 = np.full((N, N), cfg.v_uniform[1])
+        vc = np.empty(((M + 1) * (M + 1), 2))
+        vc[:, 0] = cfg.v_uniform[0]
+        vc[:, 1] = cfg.v_uniform[1]
+    elif cfg.velocity == "stream":
+        sf = inputs.stream_function(cfg.seed + 2000, L)
+        vx64, vy64 = sf.velocity(X, Y)
+        fluid = solid == 0
+        vmax = float(np.sqrt(vx64 ** 2 + vy64 ** 2)[fluid].max())
+        sf.scale = cfg.v_max / vmax
+        vx64, vy64 = sf.velocity(X, Y)
+        cvx, cvy = sf.velocity(XC, YC)
+        vc = np.stack([cvx.ravel(), cvy.ravel()], axis=1)
+    else:
+        raise ValueError(cfg.velocity)
+
+    vx = vx64.astype(np.float32)
+    vy = vy64.astype(np.float32)
+    vx[solid != 0] = 0.0
+    vy[solid != 0] = 0.0
+
+    pulse = inputs.gaussian_pulse(cfg.seed, L)
+    u0_fine = pulse(X, Y)
+    u0_fine[solid != 0] = 0.0
+    u0_coarse = pulse(XC, YC).ravel()
+    return Problem(cfg=cfg, solid=solid, vx=vx, vy=vy, vc=np.ascontiguousarray(vc),
+                   u0_fine=u0_fine, u0_coarse=u0_coarse, porosity=porosity,
+                   x0=x0, y0=x0, L=L)
