@@ -1,0 +1,194 @@
+"""Benchmark: the hybrid multi-time-step FEM/LBM step on one MI355X.
+
+A "step" is one coarse step of Algorithm 1 on the pore-scale workload
+(2048^2 D2Q9 lattice with random solid disks at porosity 0.6, seeded
+8-mode stream-function velocity, D = 5e-3, reaction k = 1e-4, 128^2 Q1
+mesh, eta = 10 fine steps per coarse step, 2 Schwarz passes): 2 x
+{fine-to-coarse transfer, FP64 coarse solve, coarse-to-fine transfer,
+10 lattice sweeps}, then commit.  Inputs are synthetic and seeded and
+already resident in HBM when the timed region starts.
+
+The printed JSON line reports lattice updates per second over all nodes
+(MLUPS), the roofline of the bulk lattice sweep (algorithmic bytes per
+launch over its average duration, timed with HIP events on its stream),
+the FP64 path on the same GPU with the FP32 result's relative L2 error
+against it, and the CPU oracle timed on a bounded sample on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ADE-LBM MLUPS + % HBM peak; FP32/adjoint vs FP64 plain at stated L2 error"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1601_02708_amd", "csrc", "lbm_kernels.hip")
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def bulk_bytes(problem, elem_bytes):
+    """Algorithmic HBM bytes of one bulk sweep (interior nodes): per fluid
+    node 9 population loads + 9 stores, 2 FP32 velocity components and the
+    16-bit flag word; a solid node reads only its flag word."""
+    s = problem.solid[1:-1, 1:-1]
+    fluid = int((s == 0).sum())
+    solid = int(s.size - fluid)
+    per_fluid = 18 * elem_bytes + 8 + 2
+    return fluid * per_fluid + solid * 2, fluid, solid, per_fluid
+
+
+def load_traffic(workload, precision):
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_sha") != kernel_hash():
+        return None           # kernel changed since the counters were taken
+    return rec.get("bytes_per_launch")
+
+
+def run_gpu(problem, precision, steps, warmup, timing=True):
+    import torch
+    from paper_1601_02708_amd import hyb
+    g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
+    mi = problem.cfg.max_iter
+    for _ in range(warmup):
+        g.step(mi)
+    stream = g.stream
+    torch.cuda.synchronize()
+    if timing:
+        g.kernel_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        g.step(mi)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    kms, launches = g.kernel_time() if timing else (0.0, 0)
+    st = g.stats()
+    return g, wall, gpu_ms, kms, launches, st
+
+
+def cpu_baseline(problem):
+    """The oracle as it stands on this host: one coarse step (2 Schwarz
+    passes x eta fine steps, FP64, one thread) of the same workload."""
+    import oracle
+    o = oracle.HybridOracle(problem)
+    t0 = time.perf_counter()
+    o.step()
+    dt = time.perf_counter() - t0
+    lups = problem.cfg.max_iter * problem.cfg.eta * problem.cfg.N ** 2
+    return {"value": round(lups / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{problem.cfg.name}: first coarse step ({problem.cfg.max_iter} Schwarz passes x "
+                      f"{problem.cfg.eta} fine steps on {problem.cfg.N}^2 nodes, plus the {problem.cfg.M}^2 "
+                      f"coarse solves), FP64, single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="pore2048")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the second-precision run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the lattice patch is not sharded across GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    from paper_1601_02708_amd import configs, hyb
+
+    cfg = configs.CONFIGS[args.workload]
+    problem = configs.build_problem(cfg)
+    N = cfg.N
+    lups_step = cfg.max_iter * cfg.eta * N * N
+    fluid_frac = float((problem.solid == 0).mean())
+    elem = 4 if args.precision == "fp32" else 8
+    print(f"[bench] {cfg.name} {args.precision}: {args.warmup} warmup + {args.steps} timed coarse steps",
+          file=sys.stderr, flush=True)
+    g, wall, gpu_ms, kms, launches, st = run_gpu(problem, args.precision, args.steps, args.warmup)
+    ms_step = gpu_ms / args.steps
+    value = lups_step * args.steps / (gpu_ms / 1e3) / 1e6
+    bbytes, nfl, nsol, per_fluid = bulk_bytes(problem, elem)
+    avg_kernel_ms = kms / max(launches, 1)
+    achieved = bbytes / (avg_kernel_ms / 1e3) / 1e9
+    traffic = load_traffic(cfg.name, args.precision)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{cfg.name}: {N}^2 D2Q9 lattice, random disks (porosity {problem.porosity:.4f}), "
+                         f"8-mode stream-function velocity max 0.05, D={cfg.D}, k={cfg.k}, {cfg.M}^2 Q1 SUPG mesh, "
+                         f"eta={cfg.eta}, {cfg.max_iter} Schwarz passes per coarse step"),
+            "lattice": N, "mesh": cfg.M, "eta": cfg.eta, "schwarz": cfg.max_iter, "precision": args.precision,
+        },
+        "mflups": round(value * fluid_frac, 1),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": f"lbm_bulk_kernel<{'float' if elem == 4 else 'double'}>",
+            "algorithmic_bytes_per_launch": bbytes,
+            "avg_launch_ms": round(avg_kernel_ms, 5),
+            "launches_timed": launches,
+            "bytes_per_fluid_update": per_fluid,
+        },
+        "bulk_time_frac": round(kms / gpu_ms, 4),
+        "wall_s": round(wall, 3),
+        "krylov_iters_last": st["krylov_iters"],
+        "infeasible_closures": st["infeasible"],
+    }
+    if not args.no_compare:
+        other = "fp64" if args.precision == "fp32" else "fp32"
+        print(f"[bench] comparison run {other}", file=sys.stderr, flush=True)
+        g2, _, gpu_ms2, kms2, launches2, _ = run_gpu(problem, other, args.steps, args.warmup)
+        u1, u2 = g.concentration(), g2.concentration()
+        fluid = problem.solid == 0
+        ref, low = (u2, u1) if other == "fp64" else (u1, u2)
+        err = float(np.linalg.norm((low - ref)[fluid]) / np.linalg.norm(ref[fluid]))
+        e2 = 4 if other == "fp32" else 8
+        b2, _, _, _ = bulk_bytes(problem, e2)
+        k2 = kms2 / max(launches2, 1)
+        res[other] = {"value": round(lups_step * args.steps / (gpu_ms2 / 1e3) / 1e6, 1), "unit": "MLUPS",
+                      "ms_per_step": round(gpu_ms2 / args.steps, 4),
+                      "bulk_achieved_gbs": round(b2 / (k2 / 1e3) / 1e9, 1),
+                      "bulk_avg_launch_ms": round(k2, 5)}
+        res["fp32_rel_l2_vs_fp64"] = err
+        del g2
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, one coarse step)", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(problem)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * hyb.h -- C ABI of the MI355X library for the hybrid multi-time-step
+ * FEM/LBM coupling of Karimi and Nakshatrala (arXiv:1601.02708).
+ *
+ * Problem (Sec. 6, eq. CouplingPDE): an advection-diffusion-reaction
+ * equation on the square [0, L]^2 solved by bilinear (Q1) finite elements
+ * (the coarse subdomain, Sec. 3), overlapped by a square patch of N x N
+ * D2Q9 lattice nodes (the fine subdomain, Sec. 4) on which a lattice
+ * Boltzmann method runs eta fine steps per coarse step.  The two exchange
+ * Dirichlet data (Secs. 5 and 6.2) inside the Schwarz iteration of
+ * Algorithm 1.  Everything is in lattice units: fine spacing 1, fine step
+ * 1, coarse step eta.
+ *
+ * Geometry: fine node (i, j), 0 <= i, j < N, sits at (x0 + i, y0 + j); the
+ * mesh has M x M squares of side L/M, node (k, l) at (k L/M, l L/M).  The
+ * fine interface Gamma_{c->f} is the whole lattice perimeter: 4(N-1)
+ * "perimeter slots" numbered along the bottom row (j = 0, i = 0..N-1), the
+ * top row (j = N-1, i = 0..N-1), the left column (i = 0, j = 1..N-2) and the
+ * right column (i = N-1, j = 1..N-2).  The coarse interface Gamma_{f->c} is
+ * the set of mesh nodes inside the patch at least `overlap_elems` elements
+ * from its boundary; together with the outer edge of the mesh these nodes
+ * carry strong Dirichlet data.
+ *
+ * Memory: host arrays passed to hyb_create are copied and may be freed
+ * after it returns.  Device memory is owned by the caller: three population
+ * buffers of hyb_query()'s f_bytes and one workspace of ws_bytes, all
+ * 256-byte aligned, which must outlive the handle.  The library allocates
+ * no device memory.  Every call enqueues work on the lattice's stream and
+ * returns without waiting, except hyb_commit, hyb_stats, hyb_concentration,
+ * hyb_get_populations, hyb_set_populations and hyb_create, which synchronise
+ * that stream.  A handle is not thread-safe.
+ *
+ * Errors: every int-returning call returns HYB_OK (0) or a negative code;
+ * hyb_last_error() describes the last failure on the handle.  After
+ * HYB_EHIP the handle's device state is undefined.
+ */
+#ifndef HYB_H
+#define HYB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HYB_OK = 0,
+    HYB_EINVAL = -1,       /* invalid argument or call order */
+    HYB_EHIP = -2,         /* a HIP runtime call failed */
+    HYB_ENOCONV = -3,      /* coarse solve did not reach its tolerance */
+    HYB_ENONFINITE = -4    /* a NaN/Inf concentration appeared in the lattice */
+};
+
+enum { HYB_FP64 = 0, HYB_FP32 = 1 };            /* population storage and arithmetic */
+enum { HYB_F2C = 0, HYB_C2F = 1 };              /* hyb_interface_exchange direction */
+enum { HYB_FINE = 0, HYB_COARSE = 1 };          /* hyb_concentration field */
+enum { HYB_BC_DIRICHLET = 0, HYB_BC_NEUMANN = 1 };
+
+typedef struct hyb_handle hyb_handle;
+
+/* Coarse mesh (Sec. 3, Sec. 6.1).  May be NULL in hyb_create: the handle is
+ * then lattice-only and its interface data come from hyb_set_boundary. */
+typedef struct {
+    int M;                  /* elements per side, >= 2 */
+    double L;               /* side of the coarse domain [0, L]^2 */
+    double outer_value;     /* Dirichlet value on the four outer edges */
+    int overlap_elems;      /* width of the overlap strip in elements, >= 1 */
+    int supg;               /* 0: Galerkin, eq. (Galerkin); 1: SUPG, eqs. (SUPG), (SUPG_tau) */
+    const double *d0;       /* host [(M+1)^2] initial nodal concentration, index l*(M+1)+k */
+} hyb_mesh;
+
+/* Fine lattice (Sec. 4.1). */
+typedef struct {
+    int N;                  /* nodes per side, >= 3 */
+    double x0, y0;          /* domain coordinates of node (0, 0) */
+    int precision;          /* HYB_FP64 or HYB_FP32 */
+    double tau;             /* BGK relaxation time; <= 0 selects 1/2 + 3 D (Sec. 4.1) */
+    int eta;                /* fine steps per coarse step, >= 1 */
+    int bc_clamp;           /* maxent Dirichlet closure, eq. (LBM_Dir): 0 applied as
+                               printed, 1 unknowns clamped at 0 when the closure would
+                               make them negative */
+    const uint8_t *solid;   /* host [N*N], 1 = solid node, index j*N+i; NULL = none.
+                               Solid nodes on the perimeter are rejected. */
+    const double *u0;       /* host [N*N] initial concentration (ignored at solid nodes) */
+    void *f_buf[3];         /* device population buffers, each >= f_bytes */
+    void *workspace;        /* device workspace, >= ws_bytes */
+    void *stream;           /* hipStream_t for all work; NULL = default stream */
+} hyb_lattice;
+
+/* Advection velocity (divergence-free in the continuum, eq. AD). */
+typedef struct {
+    const float *fine;      /* host [2][N*N]: x plane then y plane, lattice units per fine step */
+    const double *coarse;   /* host [(M+1)^2][2] nodal velocity of the mesh (ignored without mesh);
+                               inside an element the velocity is its bilinear interpolant */
+} hyb_velocity;
+
+/* First-order reaction s = -k u (per unit time; the fine step is 1). */
+typedef struct {
+    double k;               /* uniform rate, 0 <= k < 1 */
+    const double *k_field;  /* host [N*N] per-node fine rate, or NULL for the uniform k;
+                               the coarse model always uses the uniform k */
+} hyb_reaction;
+
+typedef struct {
+    int64_t infeasible;     /* cumulative count of closures whose unknowns would be negative
+                               (Dirichlet) or that have no solution (Neumann) */
+    int64_t nonfinite;      /* non-finite concentrations seen by the fine kernels */
+    int32_t krylov_iters;   /* iterations of the last coarse solve */
+    int32_t krylov_converged;
+    double krylov_relres;   /* ||b - A x|| / ||b|| of the last coarse solve */
+    int64_t coarse_steps;   /* committed coarse steps */
+    int64_t fine_steps;     /* fine steps run since creation (all Schwarz passes) */
+} hyb_run_stats;
+
+/* Device memory the caller must provide for this problem. */
+int hyb_query(const hyb_mesh *mesh, const hyb_lattice *lattice, size_t *f_bytes, size_t *ws_bytes);
+
+/* Build a handle: validates the inputs, uploads geometry, velocity and the
+ * static interface lists, assembles and preconditions the coarse system
+ * A = (M + Ms) + eta/2 (K + Ks), B = (M + Ms) - eta/2 (K + Ks) (trapezoidal
+ * rule, eq. FEM_discrete, theta = 1/2) and initialises f*(0) = collide(f^eq(u0))
+ * (Sec. 6.2, item i) and d(0) = d0.  D is the diffusion coefficient (> 0). */
+int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lattice, double D,
+               const hyb_velocity *u, const hyb_reaction *k, hyb_handle **out);
+
+/* HYB_F2C: bilinear interpolation of the current lattice concentration at
+ * the Gamma_{f->c} mesh nodes (Sec. 6.2, item ii).  Solid corners are left
+ * out with the remaining weights rescaled; a node with four solid corners
+ * takes the nearest fluid node.
+ * HYB_C2F: FEM interpolant of d(t_n) and of the latest coarse solution at
+ * every perimeter slot (the two time levels of eq. MTS). */
+int hyb_interface_exchange(hyb_handle *h, int direction);
+
+/* One trapezoidal coarse step from the committed d(t_n) with the Dirichlet
+ * data of the last HYB_F2C exchange (Algorithm 1, "advance the solution in
+ * Omega_c").  Solved on the GPU by right-preconditioned BiCGSTAB (sparse
+ * approximate inverse) in FP64 to ||r|| <= 1e-14 ||b||, at most max_iter
+ * iterations (<= 0: 200).  Does not commit. */
+int hyb_coarse_step(hyb_handle *h, int max_iter);
+
+/* n_sub fine steps (Sec. 4.1, eqs. LBE, Collision): pull streaming with
+ * halfway bounce-back at solids, the maxent closure at the perimeter with
+ * the interface value of eq. (MTS), (1 - j/eta) a + (j/eta) b at fine step
+ * j, and BGK collision with the reaction source -k w_i u.  restart = 1
+ * starts from the committed state f*(t_n) at j = 0 (a new Schwarz
+ * iteration); restart = 0 continues.  j may not pass eta. */
+int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart);
+
+/* End the coarse step: checks the device error counters (synchronises),
+ * then makes the last fine state and coarse solution the committed state.
+ * Returns HYB_ENONFINITE / HYB_ENOCONV (state left uncommitted) on failure. */
+int hyb_commit(hyb_handle *h);
+
+/* Algorithm 1 for one coarse step: max_schwarz times {F2C exchange, coarse
+ * step, C2F exchange, eta fine steps from f*(t_n)}, then commit. */
+int hyb_step(hyb_handle *h, int max_schwarz);
+
+/* Lattice-only use and tests: per-slot closure kind (HYB_BC_*, NULL = all
+ * Dirichlet) and its values at the start (a) and end (b) of the coarse step
+ * (concentration for Dirichlet, outward normal flux sum_i f_i e_i.n for
+ * Neumann).  Host arrays of 4(N-1) entries; b == NULL means b = a.  A later
+ * HYB_C2F exchange overwrites a and b. */
+int hyb_set_boundary(hyb_handle *h, const int8_t *kind, const double *a, const double *b);
+
+/* Concentration readout (synchronises): HYB_FINE -> out[N*N] = sum_i f*_i / (1 - k)
+ * of the current fine state (0 at solid nodes); HYB_COARSE -> out[(M+1)^2] =
+ * latest coarse solution.  out_is_device: out is a device pointer. */
+int hyb_concentration(hyb_handle *h, int which, double *out, int out_is_device);
+
+/* Populations of the current fine state as host FP64 [9][N*N] (get), or
+ * replace the committed state f*(t_n) with them (set; cast to the storage
+ * precision).  Velocity order: rest, +x, +y, -x, -y, (+,+), (-,+), (-,-), (+,-). */
+int hyb_get_populations(hyb_handle *h, double *out);
+int hyb_set_populations(hyb_handle *h, const double *f);
+
+int hyb_stats(hyb_handle *h, hyb_run_stats *out);
+
+/* Measurement: while enabled, each fine step records a pair of HIP events
+ * on the handle's stream around its bulk lattice kernel (the interior-node
+ * sweep); hyb_kernel_time returns the summed elapsed milliseconds and the
+ * number of timed launches since the last call, and synchronises. */
+int hyb_kernel_timing(hyb_handle *h, int enable);
+int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches);
+
+/* Storage layout actually used: row pitch and plane stride in elements. */
+int hyb_layout(const hyb_handle *h, size_t *pitch, size_t *plane);
+
+void hyb_destroy(hyb_handle *h);
+const char *hyb_last_error(const hyb_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYB_H */

@@ -1,0 +1,307 @@
+// Host-side construction of the coarse operator and the interface lists.
+//
+// * Q1 elements on the uniform M x M mesh, 2 x 2 Gauss quadrature, consistent
+//   capacity matrix; Galerkin form of eq. (Galerkin) plus, with supg, the
+//   streamline-upwind terms of eq. (SUPG) with tau_e of eq. (SUPG_tau)
+//   (h_e = mesh size, p = 1, evaluated per quadrature point; the residual has
+//   no diffusion term since the Laplacian of a bilinear function vanishes).
+// * Trapezoidal rule of eq. (FEM_discrete) with theta = 1/2 for the nodal
+//   values: A = C + dt/2 T, B = C - dt/2 T with capacity C = M + Ms and
+//   transport T = K + Ks (K includes the reaction k M).
+// * Strong Dirichlet rows (identity) on the outer edge and on Gamma_{f->c}.
+// * A sparse approximate inverse P of A on a (2R+1)^2 stencil: row i of P
+//   minimises || e_i^T - P_i A ||_2 over that pattern (normal equations,
+//   Cholesky).  A P is formed once as a (2R+3)^2 stencil.
+#include <cmath>
+#include <cstring>
+
+#include "hyb_impl.h"
+
+namespace hyb {
+namespace {
+
+// upwind function chi(a) = coth(a) - 1/a of eq. (SUPG_tau); for a < 0.1 the
+// difference cancels badly, so the Laurent series through a^9 is summed.
+double upwind_chi(double a) {
+    if (a < 0.1) {
+        const double a2 = a * a;
+        double s = 2.0 / 93555.0;
+        s = -1.0 / 4725.0 + a2 * s;
+        s = 2.0 / 945.0 + a2 * s;
+        s = -1.0 / 45.0 + a2 * s;
+        s = 1.0 / 3.0 + a2 * s;
+        return a * s;
+    }
+    return std::cosh(a) / std::sinh(a) - 1.0 / a;
+}
+
+struct Stencil {
+    int M, W, R;
+    std::vector<double> c;
+    Stencil(int M_, int W_) : M(M_), W(W_), R(W_ / 2), c((size_t)(M_ + 1) * (M_ + 1) * W_ * W_, 0.0) {}
+    double &at(int node, int dk, int dl) { return c[(size_t)node * W * W + (dl + R) * W + (dk + R)]; }
+    double get(int node, int dk, int dl) const {
+        if (dk < -R || dk > R || dl < -R || dl > R) return 0.0;
+        return c[(size_t)node * W * W + (dl + R) * W + (dk + R)];
+    }
+};
+
+// small dense SPD solve (Cholesky), n <= 25; returns false if not SPD.
+bool chol_solve(std::vector<double> &G, std::vector<double> &b, int n) {
+    for (int j = 0; j < n; ++j) {
+        double d = G[j * n + j];
+        for (int k = 0; k < j; ++k) d -= G[j * n + k] * G[j * n + k];
+        if (!(d > 0.0)) return false;
+        d = std::sqrt(d);
+        G[j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double s = G[i * n + j];
+            for (int k = 0; k < j; ++k) s -= G[i * n + k] * G[j * n + k];
+            G[i * n + j] = s / d;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= G[i * n + k] * b[k];
+        b[i] = s / G[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int k = i + 1; k < n; ++k) s -= G[k * n + i] * b[k];
+        b[i] = s / G[i * n + i];
+    }
+    return true;
+}
+
+}  // namespace
+
+std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
+                         int overlap_elems, int N, double x0, double y0, const uint8_t *solid, int pitch,
+                         CoarseHost &out) {
+    const int m1 = M + 1;
+    const int n = m1 * m1;
+    const double h = L / M;
+    out.M = M;
+    out.L = L;
+    out.h = h;
+
+    // --- quadrature tables on the reference square [-1,1]^2 -------------
+    // local nodes 0:(0,0) 1:(1,0) 2:(1,1) 3:(0,1) of element (ex, ey)
+    const int lk[4] = {0, 1, 1, 0}, ll[4] = {0, 0, 1, 1};
+    const double gq = 1.0 / std::sqrt(3.0);
+    double Nv[4][4], Gx[4][4], Gy[4][4];   // [gauss point][local node]
+    for (int g = 0; g < 4; ++g) {
+        const double xi = (g & 1) ? gq : -gq, et = (g & 2) ? gq : -gq;
+        for (int a = 0; a < 4; ++a) {
+            const double sa = lk[a] ? 1.0 : -1.0, ta = ll[a] ? 1.0 : -1.0;
+            Nv[g][a] = 0.25 * (1.0 + sa * xi) * (1.0 + ta * et);
+            Gx[g][a] = 0.5 * sa * (1.0 + ta * et) / h;
+            Gy[g][a] = 0.5 * ta * (1.0 + sa * xi) / h;
+        }
+    }
+    const double wq = 0.25 * h * h;   // Gauss weight 1 times det J
+
+    Stencil A(M, 3), B(M, 3);
+    for (int ey = 0; ey < M; ++ey) {
+        for (int ex = 0; ex < M; ++ex) {
+            int node[4];
+            for (int a = 0; a < 4; ++a) node[a] = (ey + ll[a]) * m1 + (ex + lk[a]);
+            double cap[4][4] = {}, tr[4][4] = {};
+            for (int g = 0; g < 4; ++g) {
+                double vx = 0.0, vy = 0.0;
+                for (int a = 0; a < 4; ++a) {
+                    vx += Nv[g][a] * vnodes[2 * node[a]];
+                    vy += Nv[g][a] * vnodes[2 * node[a] + 1];
+                }
+                const double speed = std::sqrt(vx * vx + vy * vy);
+                double tau = 0.0;
+                if (supg && speed > 0.0) tau = h / (2.0 * speed) * upwind_chi(speed * h / (2.0 * D));
+                double adv[4];
+                for (int a = 0; a < 4; ++a) adv[a] = vx * Gx[g][a] + vy * Gy[g][a];
+                for (int a = 0; a < 4; ++a) {
+                    for (int b = 0; b < 4; ++b) {
+                        const double mass = Nv[g][a] * Nv[g][b];
+                        const double galerkin = Nv[g][a] * adv[b] + D * (Gx[g][a] * Gx[g][b] + Gy[g][a] * Gy[g][b]) +
+                                                k * mass;
+                        const double stab_cap = tau * adv[a] * Nv[g][b];
+                        const double stab_tr = tau * adv[a] * (adv[b] + k * Nv[g][b]);
+                        cap[a][b] += wq * (mass + stab_cap);
+                        tr[a][b] += wq * (galerkin + stab_tr);
+                    }
+                }
+            }
+            for (int a = 0; a < 4; ++a) {
+                for (int b = 0; b < 4; ++b) {
+                    const int dk = lk[b] - lk[a], dl = ll[b] - ll[a];
+                    A.at(node[a], dk, dl) += cap[a][b] + 0.5 * dt * tr[a][b];
+                    B.at(node[a], dk, dl) += cap[a][b] - 0.5 * dt * tr[a][b];
+                }
+            }
+        }
+    }
+
+    // --- Dirichlet sets ---------------------------------------------------
+    out.dkind.assign(n, -1);
+    out.fc_nodes.clear();
+    const double ov = overlap_elems * h, tol = 1e-9 * h;
+    const double x1 = x0 + (N - 1), y1 = y0 + (N - 1);
+    for (int l = 0; l < m1; ++l) {
+        for (int kk = 0; kk < m1; ++kk) {
+            const int id = l * m1 + kk;
+            if (kk == 0 || kk == M || l == 0 || l == M) {
+                out.dkind[id] = -2;
+                continue;
+            }
+            const double X = kk * h, Y = l * h;
+            if (X - x0 >= ov - tol && x1 - X >= ov - tol && Y - y0 >= ov - tol && y1 - Y >= ov - tol) {
+                out.dkind[id] = (int)out.fc_nodes.size();
+                out.fc_nodes.push_back(id);
+            }
+        }
+    }
+    for (int id = 0; id < n; ++id) {
+        if (out.dkind[id] == -1) continue;
+        for (int dl = -1; dl <= 1; ++dl)
+            for (int dk = -1; dk <= 1; ++dk) A.at(id, dk, dl) = 0.0;
+        A.at(id, 0, 0) = 1.0;
+    }
+
+    // --- sparse approximate inverse of A ---------------------------------
+    constexpr int R = kSpaiRadius, W = kSpaiW;
+    Stencil P(M, W);
+    std::vector<int> pk, pl;
+    std::vector<double> G, rhs;
+    for (int l = 0; l < m1; ++l) {
+        for (int kk = 0; kk < m1; ++kk) {
+            const int id = l * m1 + kk;
+            pk.clear();
+            pl.clear();
+            for (int dl = -R; dl <= R; ++dl)
+                for (int dk = -R; dk <= R; ++dk)
+                    if (kk + dk >= 0 && kk + dk <= M && l + dl >= 0 && l + dl <= M) {
+                        pk.push_back(dk);
+                        pl.push_back(dl);
+                    }
+            const int np = (int)pk.size();
+            G.assign((size_t)np * np, 0.0);
+            rhs.assign(np, 0.0);
+            for (int a = 0; a < np; ++a) {
+                const int na = (l + pl[a]) * m1 + (kk + pk[a]);
+                // rhs_a = A(na, id): column id lies at offset (-pk, -pl) from row na
+                rhs[a] = A.get(na, -pk[a], -pl[a]);
+                for (int b = a; b < np; ++b) {
+                    const int nb = (l + pl[b]) * m1 + (kk + pk[b]);
+                    // sum over columns c of A(na, c) A(nb, c)
+                    double s = 0.0;
+                    for (int dl = -1; dl <= 1; ++dl)
+                        for (int dk = -1; dk <= 1; ++dk) {
+                            const double va = A.get(na, dk, dl);
+                            if (va == 0.0) continue;
+                            s += va * A.get(nb, dk + pk[a] - pk[b], dl + pl[a] - pl[b]);
+                        }
+                    G[a * np + b] = s;
+                    G[b * np + a] = s;
+                }
+            }
+            if (!chol_solve(G, rhs, np)) return "coarse preconditioner: singular local system";
+            for (int a = 0; a < np; ++a) P.at(id, pk[a], pl[a]) = rhs[a];
+        }
+    }
+    Stencil AP(M, kApW);
+    for (int l = 0; l < m1; ++l) {
+        for (int kk = 0; kk < m1; ++kk) {
+            const int id = l * m1 + kk;
+            for (int dl = -1; dl <= 1; ++dl)
+                for (int dk = -1; dk <= 1; ++dk) {
+                    const double a = A.get(id, dk, dl);
+                    if (a == 0.0) continue;
+                    const int nk = kk + dk, nl = l + dl;
+                    const int nid = nl * m1 + nk;
+                    for (int el = -R; el <= R; ++el)
+                        for (int ek = -R; ek <= R; ++ek) {
+                            const double pv = P.get(nid, ek, el);
+                            if (pv != 0.0) AP.at(id, dk + ek, dl + el) += a * pv;
+                        }
+                }
+        }
+    }
+    out.A9 = std::move(A.c);
+    out.B9 = std::move(B.c);
+    out.P = std::move(P.c);
+    out.AP = std::move(AP.c);
+
+    // --- coarse -> fine: containing element of each perimeter slot --------
+    const int S = M + 1 + 2 * kCoarseHalo;
+    auto padded = [&](int kk, int l) { return (l + kCoarseHalo) * S + (kk + kCoarseHalo); };
+    const int nslots = 4 * (N - 1);
+    out.c2f_idx.assign((size_t)4 * nslots, 0);
+    out.c2f_w.assign((size_t)4 * nslots, 0.0);
+    for (int p = 0; p < nslots; ++p) {
+        int i, j;
+        slot_to_node(N, p, i, j);
+        const double sx = (x0 + i) / h, sy = (y0 + j) / h;
+        int ex = (int)std::floor(sx), ey = (int)std::floor(sy);
+        ex = ex < 0 ? 0 : (ex > M - 1 ? M - 1 : ex);
+        ey = ey < 0 ? 0 : (ey > M - 1 ? M - 1 : ey);
+        const double xi = sx - ex, et = sy - ey;
+        const int cidx[4] = {padded(ex, ey), padded(ex + 1, ey), padded(ex + 1, ey + 1), padded(ex, ey + 1)};
+        const double cw[4] = {(1 - xi) * (1 - et), xi * (1 - et), xi * et, (1 - xi) * et};
+        for (int c = 0; c < 4; ++c) {
+            out.c2f_idx[4 * p + c] = cidx[c];
+            out.c2f_w[4 * p + c] = cw[c];
+        }
+    }
+
+    // --- fine -> coarse: four surrounding lattice nodes --------------------
+    const int nfc = (int)out.fc_nodes.size();
+    out.fc_idx.assign((size_t)4 * nfc, 0);
+    out.fc_w.assign((size_t)4 * nfc, 0.0);
+    auto is_solid = [&](int i, int j) { return solid && solid[(size_t)j * N + i]; };
+    for (int c = 0; c < nfc; ++c) {
+        const int id = out.fc_nodes[c];
+        const double px = (id % m1) * h - x0, py = (id / m1) * h - y0;
+        int i0 = (int)std::floor(px), j0 = (int)std::floor(py);
+        i0 = i0 < 0 ? 0 : (i0 > N - 2 ? N - 2 : i0);
+        j0 = j0 < 0 ? 0 : (j0 > N - 2 ? N - 2 : j0);
+        const double gx = px - i0, gy = py - j0;
+        const int ci[4] = {i0, i0 + 1, i0 + 1, i0}, cj[4] = {j0, j0, j0 + 1, j0 + 1};
+        const double cw[4] = {(1 - gx) * (1 - gy), gx * (1 - gy), gx * gy, (1 - gx) * gy};
+        double wsum = 0.0;
+        for (int m = 0; m < 4; ++m)
+            if (!is_solid(ci[m], cj[m])) wsum += cw[m];
+        if (wsum > 0.0) {
+            for (int m = 0; m < 4; ++m) {
+                out.fc_idx[4 * c + m] = cj[m] * pitch + ci[m];
+                out.fc_w[4 * c + m] = is_solid(ci[m], cj[m]) ? 0.0 : cw[m] / wsum;
+            }
+            continue;
+        }
+        // all four corners solid: nearest fluid node, lowest j*N+i on ties,
+        // searched in growing squares around the point
+        int best = -1;
+        double bd = 0.0;
+        const int ic = (int)std::floor(px + 0.5), jc = (int)std::floor(py + 0.5);
+        for (int r = 1; r <= 2 * N && best < 0; ++r) {
+            int cand = -1;
+            double cd = 0.0;
+            for (int j = std::max(0, jc - r); j <= std::min(N - 1, jc + r); ++j)
+                for (int i = std::max(0, ic - r); i <= std::min(N - 1, ic + r); ++i) {
+                    if (is_solid(i, j)) continue;
+                    const double d2 = (i - px) * (i - px) + (j - py) * (j - py);
+                    if (cand < 0 || d2 < cd) { cand = j * N + i; cd = d2; }
+                }
+            if (cand >= 0 && std::sqrt(cd) <= r - 0.5) { best = cand; bd = cd; }
+        }
+        (void)bd;
+        if (best < 0) return "fine-to-coarse transfer: no fluid lattice node";
+        out.fc_idx[4 * c] = (best / N) * pitch + (best % N);
+        out.fc_w[4 * c] = 1.0;
+        for (int m = 1; m < 4; ++m) {
+            out.fc_idx[4 * c + m] = out.fc_idx[4 * c];
+            out.fc_w[4 * c + m] = 0.0;
+        }
+    }
+    return std::string();
+}
+
+}  // namespace hyb

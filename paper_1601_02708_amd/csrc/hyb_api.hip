@@ -1,0 +1,629 @@
+// Runtime behind the C ABI of include/hyb.h: validates and uploads the
+// problem, carves the caller's workspace, keeps the Schwarz/commit state
+// machine of Algorithm 1 (Sec. 6.2) and enqueues the kernels on the
+// caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hyb.h"
+#include "hyb_impl.h"
+
+using namespace hyb;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Row pitch and plane stride (elements).  Rows start on 256-byte
+// boundaries; planes are skewed by 128 elements so the nine streams of a
+// sweep do not hit the same HBM channel offsets in lockstep.
+int choose_pitch(int N) { return (int)align_up((size_t)N, 64); }
+long long choose_plane(int N, int pitch) { return (long long)align_up((size_t)N * pitch, 64) + 128; }
+
+int coarse_grid(int n) {
+    if (n <= 2048) return 1;
+    return std::min(128, (n + 255) / 256);
+}
+
+struct Layout {
+    int pitch = 0;
+    long long plane = 0;
+    size_t f_bytes = 0;
+    size_t mask = 0, vx = 0, vy = 0, kfield = 0, bc_kind = 0, bc_a = 0, bc_b = 0, c2f_idx = 0, c2f_w = 0;
+    size_t fc_idx = 0, fc_w = 0, ufc = 0, A9 = 0, B9 = 0, AP = 0, P = 0, dkind = 0, vec = 0, partials = 0;
+    size_t counters = 0, barrier = 0, kres = 0, total = 0;
+    int n = 0, S = 0, grid = 0;
+    size_t vec_len = 0;
+};
+
+Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield) {
+    Layout L;
+    const int N = lat->N;
+    const size_t elem = lat->precision == HYB_FP64 ? 8 : 4;
+    L.pitch = choose_pitch(N);
+    L.plane = choose_plane(N, L.pitch);
+    L.f_bytes = align_up((size_t)9 * L.plane * elem, kAlign);
+    const size_t nodes = (size_t)N * L.pitch;
+    const size_t nslots = 4 * (size_t)(N - 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    L.mask = take(nodes * 2);
+    L.vx = take(nodes * 4);
+    L.vy = take(nodes * 4);
+    L.kfield = has_kfield ? take(nodes * elem) : 0;
+    L.bc_kind = take(nslots);
+    L.bc_a = take(nslots * 8);
+    L.bc_b = take(nslots * 8);
+    L.counters = take(kCntSlots * 8);
+    L.kres = take(sizeof(KrylovResult));
+    if (mesh) {
+        const int M = mesh->M;
+        L.n = (M + 1) * (M + 1);
+        L.S = M + 1 + 2 * kCoarseHalo;
+        L.grid = coarse_grid(L.n);
+        L.vec_len = (size_t)L.S * L.S;
+        L.c2f_idx = take(nslots * 4 * 4);
+        L.c2f_w = take(nslots * 4 * 8);
+        L.fc_idx = take((size_t)L.n * 4 * 4);
+        L.fc_w = take((size_t)L.n * 4 * 8);
+        L.ufc = take((size_t)L.n * 8);
+        L.A9 = take((size_t)L.n * 9 * 8);
+        L.B9 = take((size_t)L.n * 9 * 8);
+        L.AP = take((size_t)L.n * kApW * kApW * 8);
+        L.P = take((size_t)L.n * kSpaiW * kSpaiW * 8);
+        L.dkind = take((size_t)L.n * 4);
+        L.vec = take(9 * align_up(L.vec_len * 8, kAlign));
+        L.partials = take((size_t)12 * L.grid * 8);
+        L.barrier = take(64);
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct hyb_handle {
+    std::string err;
+    // problem
+    int N = 0, M = 0, eta = 1, clamp = 0;
+    bool fp64 = true, has_mesh = false, has_kfield = false;
+    double tau = 0, omega = 0, D = 0, kuni = 0;
+    double x0 = 0, y0 = 0;
+    hipStream_t stream = nullptr;
+    Layout lay;
+    void *f[3] = {nullptr, nullptr, nullptr};
+    char *ws = nullptr;
+    // workspace views
+    uint16_t *mask = nullptr;
+    float *vx = nullptr, *vy = nullptr;
+    void *kfield = nullptr;
+    int8_t *bc_kind = nullptr;
+    double *bc_a = nullptr, *bc_b = nullptr;
+    bool kinds_set = false;
+    int *c2f_idx = nullptr, *fc_idx = nullptr;
+    double *c2f_w = nullptr, *fc_w = nullptr, *ufc = nullptr;
+    int nfc = 0;
+    CoarseDev cd{};
+    unsigned long long *counters = nullptr;
+    KrylovResult *kres = nullptr;
+    // state machine
+    int frozen = 0, cur = 0, jsub = 0;
+    bool solved_this_step = false;
+    long long coarse_steps = 0, fine_steps = 0;
+    unsigned long long seen_nonfinite = 0;
+    // kernel timing (measurement only)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;       // pairs: [2k] begin, [2k+1] end
+    size_t ev_used = 0;                    // pairs recorded and not yet read
+    double timed_ms = 0.0;
+    long long timed_launches = 0;
+
+    ~hyb_handle() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+    // fold recorded pairs into the running sums (stream must be idle)
+    hipError_t drain_events() {
+        for (size_t k = 0; k < ev_used; ++k) {
+            float ms = 0.f;
+            hipError_t e = hipEventElapsedTime(&ms, ev_pool[2 * k], ev_pool[2 * k + 1]);
+            if (e != hipSuccess) return e;
+            timed_ms += ms;
+            timed_launches += 1;
+        }
+        ev_used = 0;
+        return hipSuccess;
+    }
+
+    int fail(int code, const std::string &msg) {
+        err = msg;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char *what) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return HYB_EHIP;
+    }
+    LbmArgs lbm_args(int src, int dst) const {
+        LbmArgs a{};
+        a.src = f[src];
+        a.dst = dst >= 0 ? f[dst] : nullptr;
+        a.mask = mask;
+        a.vx = vx;
+        a.vy = vy;
+        a.kfield = has_kfield ? kfield : nullptr;
+        a.k = kuni;
+        a.omega = omega;
+        a.N = N;
+        a.pitch = lay.pitch;
+        a.plane = lay.plane;
+        a.bc_kind = kinds_set ? bc_kind : nullptr;
+        a.bc_a = bc_a;
+        a.bc_b = bc_b;
+        a.lam = 0.0;
+        a.clamp = clamp;
+        a.counters = counters;
+        return a;
+    }
+    // buffer that is neither the committed state nor `a`
+    int spare(int a) const {
+        for (int b = 0; b < 3; ++b)
+            if (b != frozen && b != a) return b;
+        return -1;
+    }
+};
+
+#define HIP_TRY(h, call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return (h)->hip_fail(e_, #call); \
+    } while (0)
+
+extern "C" {
+
+int hyb_query(const hyb_mesh *mesh, const hyb_lattice *lat, size_t *f_bytes, size_t *ws_bytes) {
+    if (!lat || lat->N < 3 || (lat->precision != HYB_FP64 && lat->precision != HYB_FP32)) return HYB_EINVAL;
+    if (mesh && mesh->M < 2) return HYB_EINVAL;
+    // per-node kfield space is reserved; callers that pass none waste N^2 elements
+    Layout L = make_layout(mesh, lat, true);
+    if (f_bytes) *f_bytes = L.f_bytes;
+    if (ws_bytes) *ws_bytes = L.total;
+    return HYB_OK;
+}
+
+int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb_velocity *u,
+               const hyb_reaction *k, hyb_handle **out) {
+    if (!out) return HYB_EINVAL;
+    *out = nullptr;
+    hyb_handle *h = new hyb_handle();
+    auto bail = [&](int code, const std::string &msg) {
+        std::fprintf(stderr, "hyb_create: %s\n", msg.c_str());
+        delete h;
+        return code;
+    };
+    if (!lat || !u || !u->fine || !lat->u0) return bail(HYB_EINVAL, "lattice, velocity and u0 are required");
+    const int N = lat->N;
+    if (N < 3) return bail(HYB_EINVAL, "N must be >= 3");
+    if (lat->precision != HYB_FP64 && lat->precision != HYB_FP32) return bail(HYB_EINVAL, "unknown precision");
+    if (!(D > 0.0)) return bail(HYB_EINVAL, "D must be > 0");
+    if (lat->eta < 1) return bail(HYB_EINVAL, "eta must be >= 1");
+    const double tau = lat->tau > 0.0 ? lat->tau : 0.5 + 3.0 * D;
+    if (!(tau > 0.5)) return bail(HYB_EINVAL, "tau must exceed 1/2");
+    const double kuni = k ? k->k : 0.0;
+    if (!(kuni >= 0.0 && kuni < 1.0)) return bail(HYB_EINVAL, "reaction rate must lie in [0, 1)");
+    if (mesh) {
+        if (mesh->M < 2 || !(mesh->L > 0.0) || !mesh->d0 || !u->coarse || mesh->overlap_elems < 1)
+            return bail(HYB_EINVAL, "invalid mesh");
+        if (lat->x0 < 0 || lat->y0 < 0 || lat->x0 + (N - 1) > mesh->L || lat->y0 + (N - 1) > mesh->L)
+            return bail(HYB_EINVAL, "lattice patch must lie inside the coarse domain");
+    }
+    h->N = N;
+    h->fp64 = lat->precision == HYB_FP64;
+    h->tau = tau;
+    h->omega = 1.0 / tau;
+    h->D = D;
+    h->eta = lat->eta;
+    h->clamp = lat->bc_clamp ? 1 : 0;
+    h->kuni = kuni;
+    h->has_kfield = k && k->k_field;
+    h->has_mesh = mesh != nullptr;
+    h->M = mesh ? mesh->M : 0;
+    h->x0 = lat->x0;
+    h->y0 = lat->y0;
+    h->stream = static_cast<hipStream_t>(lat->stream);
+    h->lay = make_layout(mesh, lat, true);
+    const Layout &L = h->lay;
+    if ((long long)9 * L.plane >= (1LL << 31)) return bail(HYB_EINVAL, "lattice too large for 32-bit indexing");
+    for (int b = 0; b < 3; ++b) {
+        if (!lat->f_buf[b] || reinterpret_cast<uintptr_t>(lat->f_buf[b]) % kAlign)
+            return bail(HYB_EINVAL, "population buffers must be non-null and 256-byte aligned");
+        h->f[b] = lat->f_buf[b];
+    }
+    if (!lat->workspace || reinterpret_cast<uintptr_t>(lat->workspace) % kAlign)
+        return bail(HYB_EINVAL, "workspace must be non-null and 256-byte aligned");
+    h->ws = static_cast<char *>(lat->workspace);
+    const int P = L.pitch;
+    const size_t nodes = (size_t)N * P;
+
+    // ---- host staging of geometry, velocity, reaction --------------------
+    std::vector<uint16_t> mask(nodes, 0);
+    auto solid = [&](int i, int j) { return lat->solid && lat->solid[(size_t)j * N + i]; };
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+            uint16_t m = 0;
+            if (solid(i, j)) {
+                if (i == 0 || j == 0 || i == N - 1 || j == N - 1)
+                    return bail(HYB_EINVAL, "solid nodes on the lattice perimeter are not supported");
+                m = kMaskSolid;
+            } else {
+                for (int q = 1; q < kQ; ++q) {
+                    const int si = i - kCx[q], sj = j - kCy[q];
+                    if (si >= 0 && si < N && sj >= 0 && sj < N && solid(si, sj)) m |= (uint16_t)(1u << q);
+                }
+            }
+            mask[(size_t)j * P + i] = m;
+        }
+    std::vector<float> vxh(nodes, 0.f), vyh(nodes, 0.f);
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+            const bool s = solid(i, j);
+            vxh[(size_t)j * P + i] = s ? 0.f : u->fine[(size_t)j * N + i];
+            vyh[(size_t)j * P + i] = s ? 0.f : u->fine[(size_t)N * N + (size_t)j * N + i];
+        }
+    h->mask = reinterpret_cast<uint16_t *>(h->ws + L.mask);
+    h->vx = reinterpret_cast<float *>(h->ws + L.vx);
+    h->vy = reinterpret_cast<float *>(h->ws + L.vy);
+    h->kfield = h->ws + L.kfield;
+    h->bc_kind = reinterpret_cast<int8_t *>(h->ws + L.bc_kind);
+    h->bc_a = reinterpret_cast<double *>(h->ws + L.bc_a);
+    h->bc_b = reinterpret_cast<double *>(h->ws + L.bc_b);
+    h->counters = reinterpret_cast<unsigned long long *>(h->ws + L.counters);
+    h->kres = reinterpret_cast<KrylovResult *>(h->ws + L.kres);
+    hipStream_t st = h->stream;
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+#define CREATE_TRY(call)                                                              \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) return bail(HYB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+    CREATE_TRY(hipMemsetAsync(h->ws, 0, L.total, st));
+    for (int b = 0; b < 3; ++b) CREATE_TRY(hipMemsetAsync(h->f[b], 0, L.f_bytes, st));
+    CREATE_TRY(up(h->mask, mask.data(), nodes * 2));
+    CREATE_TRY(up(h->vx, vxh.data(), nodes * 4));
+    CREATE_TRY(up(h->vy, vyh.data(), nodes * 4));
+    if (h->has_kfield) {
+        if (h->fp64) {
+            std::vector<double> kf(nodes, 0.0);
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < N; ++i) kf[(size_t)j * P + i] = k->k_field[(size_t)j * N + i];
+            CREATE_TRY(up(h->kfield, kf.data(), nodes * 8));
+            CREATE_TRY(hipStreamSynchronize(st));
+        } else {
+            std::vector<float> kf(nodes, 0.f);
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < N; ++i) kf[(size_t)j * P + i] = (float)k->k_field[(size_t)j * N + i];
+            CREATE_TRY(up(h->kfield, kf.data(), nodes * 4));
+        }
+        CREATE_TRY(hipStreamSynchronize(st));
+    }
+
+    // ---- coarse operator and interface lists --------------------------------
+    if (mesh) {
+        CoarseHost ch;
+        std::string msg = build_coarse(mesh->M, mesh->L, D, kuni, (double)lat->eta, mesh->supg, u->coarse,
+                                       mesh->overlap_elems, N, lat->x0, lat->y0, lat->solid, P, ch);
+        if (!msg.empty()) return bail(HYB_EINVAL, msg);
+        h->nfc = (int)ch.fc_nodes.size();
+        h->c2f_idx = reinterpret_cast<int *>(h->ws + L.c2f_idx);
+        h->c2f_w = reinterpret_cast<double *>(h->ws + L.c2f_w);
+        h->fc_idx = reinterpret_cast<int *>(h->ws + L.fc_idx);
+        h->fc_w = reinterpret_cast<double *>(h->ws + L.fc_w);
+        h->ufc = reinterpret_cast<double *>(h->ws + L.ufc);
+        CREATE_TRY(up(h->c2f_idx, ch.c2f_idx.data(), ch.c2f_idx.size() * 4));
+        CREATE_TRY(up(h->c2f_w, ch.c2f_w.data(), ch.c2f_w.size() * 8));
+        if (h->nfc) {
+            CREATE_TRY(up(h->fc_idx, ch.fc_idx.data(), ch.fc_idx.size() * 4));
+            CREATE_TRY(up(h->fc_w, ch.fc_w.data(), ch.fc_w.size() * 8));
+        }
+        CoarseDev &c = h->cd;
+        c.M = mesh->M;
+        c.n = L.n;
+        c.S = L.S;
+        c.grid = L.grid;
+        c.A9 = reinterpret_cast<const double *>(h->ws + L.A9);
+        c.B9 = reinterpret_cast<const double *>(h->ws + L.B9);
+        c.AP = reinterpret_cast<const double *>(h->ws + L.AP);
+        c.P = reinterpret_cast<const double *>(h->ws + L.P);
+        c.dkind = reinterpret_cast<const int *>(h->ws + L.dkind);
+        c.outer_value = mesh->outer_value;
+        c.ufc = h->ufc;
+        const size_t vstride = align_up(L.vec_len * 8, kAlign);
+        double *vec[9];
+        for (int v = 0; v < 9; ++v) vec[v] = reinterpret_cast<double *>(h->ws + L.vec + v * vstride);
+        c.xn = vec[0];
+        c.x1 = vec[1];
+        c.r = vec[2];
+        c.rh = vec[3];
+        c.p = vec[4];
+        c.v = vec[5];
+        c.s = vec[6];
+        c.t = vec[7];
+        c.y = vec[8];
+        c.partials = reinterpret_cast<double *>(h->ws + L.partials);
+        c.barrier = reinterpret_cast<unsigned *>(h->ws + L.barrier);
+        c.result = h->kres;
+        CREATE_TRY(up((void *)c.A9, ch.A9.data(), ch.A9.size() * 8));
+        CREATE_TRY(up((void *)c.B9, ch.B9.data(), ch.B9.size() * 8));
+        CREATE_TRY(up((void *)c.AP, ch.AP.data(), ch.AP.size() * 8));
+        CREATE_TRY(up((void *)c.P, ch.P.data(), ch.P.size() * 8));
+        CREATE_TRY(up((void *)c.dkind, ch.dkind.data(), ch.dkind.size() * 4));
+        std::vector<double> xp(L.vec_len, 0.0);
+        const int m1 = mesh->M + 1;
+        for (int l = 0; l < m1; ++l)
+            for (int kk = 0; kk < m1; ++kk) xp[(size_t)(l + kCoarseHalo) * L.S + kk + kCoarseHalo] = mesh->d0[l * m1 + kk];
+        CREATE_TRY(up(c.xn, xp.data(), xp.size() * 8));
+        CREATE_TRY(up(c.x1, xp.data(), xp.size() * 8));
+        // host staging must stay alive until the copies ran
+        CREATE_TRY(hipStreamSynchronize(st));
+    }
+
+    // ---- initial populations: f*(0) = collide(f^eq(u0)) ---------------------
+    // u0 is staged in buffer 2, which is free until the first fine step
+    CREATE_TRY(up(h->f[2], lat->u0, (size_t)N * N * 8));
+    {
+        LbmArgs a = h->lbm_args(2, 0);
+        CREATE_TRY(launch_lbm_init(a, static_cast<const double *>(h->f[2]), h->fp64, st));
+    }
+    CREATE_TRY(hipMemsetAsync(h->f[2], 0, L.f_bytes, st));
+    CREATE_TRY(hipStreamSynchronize(st));
+#undef CREATE_TRY
+    h->frozen = 0;
+    h->cur = 0;
+    h->jsub = 0;
+    *out = h;
+    return HYB_OK;
+}
+
+int hyb_interface_exchange(hyb_handle *h, int direction) {
+    if (!h) return HYB_EINVAL;
+    if (!h->has_mesh) return h->fail(HYB_EINVAL, "interface exchange needs a coarse mesh");
+    if (direction == HYB_F2C) {
+        LbmArgs a = h->lbm_args(h->cur, -1);
+        HIP_TRY(h, launch_f2c(a, h->fc_idx, h->fc_w, h->nfc, h->ufc, h->fp64, h->stream));
+    } else if (direction == HYB_C2F) {
+        const double *xb = h->solved_this_step ? h->cd.x1 : h->cd.xn;
+        HIP_TRY(h, launch_c2f(h->c2f_idx, h->c2f_w, 4 * (h->N - 1), h->cd.xn, xb, h->bc_a, h->bc_b, h->stream));
+    } else {
+        return h->fail(HYB_EINVAL, "unknown exchange direction");
+    }
+    return HYB_OK;
+}
+
+int hyb_coarse_step(hyb_handle *h, int max_iter) {
+    if (!h) return HYB_EINVAL;
+    if (!h->has_mesh) return h->fail(HYB_EINVAL, "coarse step needs a coarse mesh");
+    if (max_iter <= 0) max_iter = 200;
+    // first solve of a coarse step starts from d(t_n); later Schwarz passes
+    // start from the previous pass's solution
+    const double *guess = h->solved_this_step ? h->cd.x1 : h->cd.xn;
+    HIP_TRY(h, launch_coarse_rhs(h->cd, guess, h->stream));
+    HIP_TRY(h, launch_coarse_solve(h->cd, guess, max_iter, 1e-14, h->stream));
+    h->solved_this_step = true;
+    return HYB_OK;
+}
+
+int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
+    if (!h) return HYB_EINVAL;
+    if (n_sub < 0) return h->fail(HYB_EINVAL, "n_sub must be >= 0");
+    if (restart) {
+        h->cur = h->frozen;
+        h->jsub = 0;
+    }
+    if (h->jsub + n_sub > h->eta) return h->fail(HYB_EINVAL, "fine steps would pass the end of the coarse step");
+    for (int s = 0; s < n_sub; ++s) {
+        int dst = h->cur == h->frozen ? h->spare(-1) : h->spare(h->cur);
+        LbmArgs a = h->lbm_args(h->cur, dst);
+        a.lam = (double)(h->jsub + 1) / (double)h->eta;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->timing && h->N > 2) {
+            if (2 * (h->ev_used + 1) > h->ev_pool.size()) {
+                for (int k = 0; k < 2; ++k) {
+                    hipEvent_t e;
+                    HIP_TRY(h, hipEventCreate(&e));
+                    h->ev_pool.push_back(e);
+                }
+            }
+            e0 = h->ev_pool[2 * h->ev_used];
+            e1 = h->ev_pool[2 * h->ev_used + 1];
+            h->ev_used += 1;
+        }
+        HIP_TRY(h, launch_lbm_step(a, h->fp64, h->stream, e0, e1));
+        h->cur = dst;
+        h->jsub += 1;
+        h->fine_steps += 1;
+    }
+    return HYB_OK;
+}
+
+int hyb_commit(hyb_handle *h) {
+    if (!h) return HYB_EINVAL;
+    unsigned long long cnt[kCntSlots];
+    KrylovResult kr{};
+    HIP_TRY(h, hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&kr, h->kres, sizeof(kr), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, h->drain_events());
+    if (cnt[kCntNonfinite] != h->seen_nonfinite) {
+        h->seen_nonfinite = cnt[kCntNonfinite];
+        return h->fail(HYB_ENONFINITE, "non-finite concentration in the fine subdomain; state not committed");
+    }
+    if (h->solved_this_step && !kr.converged) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "coarse solve did not converge (%d iterations, relres %.3e%s)", kr.iters,
+                      kr.relres, kr.barrier_timeout ? ", barrier timeout" : "");
+        return h->fail(HYB_ENOCONV, buf);
+    }
+    h->frozen = h->cur;
+    h->jsub = 0;
+    if (h->solved_this_step) std::swap(h->cd.xn, h->cd.x1);
+    h->solved_this_step = false;
+    h->coarse_steps += 1;
+    return HYB_OK;
+}
+
+int hyb_step(hyb_handle *h, int max_schwarz) {
+    if (!h) return HYB_EINVAL;
+    if (!h->has_mesh) return h->fail(HYB_EINVAL, "hyb_step needs a coarse mesh");
+    if (max_schwarz < 1) return h->fail(HYB_EINVAL, "max_schwarz must be >= 1");
+    h->cur = h->frozen;
+    h->jsub = 0;
+    for (int it = 0; it < max_schwarz; ++it) {
+        int rc;
+        if ((rc = hyb_interface_exchange(h, HYB_F2C)) != HYB_OK) return rc;
+        if ((rc = hyb_coarse_step(h, 200)) != HYB_OK) return rc;
+        if ((rc = hyb_interface_exchange(h, HYB_C2F)) != HYB_OK) return rc;
+        if ((rc = hyb_lbm_substeps(h, h->eta, 1)) != HYB_OK) return rc;
+    }
+    return hyb_commit(h);
+}
+
+int hyb_set_boundary(hyb_handle *h, const int8_t *kind, const double *a, const double *b) {
+    if (!h || !a) return HYB_EINVAL;
+    const size_t ns = 4 * (size_t)(h->N - 1);
+    if (kind) {
+        for (size_t p = 0; p < ns; ++p)
+            if (kind[p] != HYB_BC_DIRICHLET && kind[p] != HYB_BC_NEUMANN)
+                return h->fail(HYB_EINVAL, "unknown boundary kind");
+        HIP_TRY(h, hipMemcpyAsync(h->bc_kind, kind, ns, hipMemcpyHostToDevice, h->stream));
+        h->kinds_set = true;
+    } else {
+        h->kinds_set = false;
+    }
+    HIP_TRY(h, hipMemcpyAsync(h->bc_a, a, ns * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->bc_b, b ? b : a, ns * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return HYB_OK;
+}
+
+int hyb_concentration(hyb_handle *h, int which, double *out, int out_is_device) {
+    if (!h || !out) return HYB_EINVAL;
+    if (which == HYB_FINE) {
+        const size_t bytes = (size_t)h->N * h->N * 8;
+        double *dev = out_is_device ? out : static_cast<double *>(h->f[h->spare(h->cur == h->frozen ? -1 : h->cur)]);
+        LbmArgs a = h->lbm_args(h->cur, -1);
+        HIP_TRY(h, launch_concentration(a, dev, h->fp64, h->stream));
+        if (!out_is_device) HIP_TRY(h, hipMemcpyAsync(out, dev, bytes, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return HYB_OK;
+    }
+    if (which == HYB_COARSE) {
+        if (!h->has_mesh) return h->fail(HYB_EINVAL, "no coarse mesh");
+        const int m1 = h->M + 1;
+        const double *src = h->solved_this_step ? h->cd.x1 : h->cd.xn;
+        const size_t rowb = (size_t)m1 * 8;
+        HIP_TRY(h, hipMemcpy2DAsync(out, rowb, src + (size_t)kCoarseHalo * h->cd.S + kCoarseHalo, (size_t)h->cd.S * 8,
+                                    rowb, m1, out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                    h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return HYB_OK;
+    }
+    return h->fail(HYB_EINVAL, "unknown field");
+}
+
+int hyb_get_populations(hyb_handle *h, double *out) {
+    if (!h || !out) return HYB_EINVAL;
+    const int N = h->N, P = h->lay.pitch;
+    const size_t elem = h->fp64 ? 8 : 4;
+    std::vector<char> stage((size_t)9 * h->lay.plane * elem);
+    HIP_TRY(h, hipMemcpyAsync(stage.data(), h->f[h->cur], stage.size(), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (int q = 0; q < kQ; ++q)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const size_t s = (size_t)q * h->lay.plane + (size_t)j * P + i;
+                out[(size_t)q * N * N + (size_t)j * N + i] =
+                    h->fp64 ? reinterpret_cast<const double *>(stage.data())[s]
+                            : (double)reinterpret_cast<const float *>(stage.data())[s];
+            }
+    return HYB_OK;
+}
+
+int hyb_set_populations(hyb_handle *h, const double *fin) {
+    if (!h || !fin) return HYB_EINVAL;
+    const int N = h->N, P = h->lay.pitch;
+    const size_t elem = h->fp64 ? 8 : 4;
+    std::vector<char> stage((size_t)9 * h->lay.plane * elem, 0);
+    for (int q = 0; q < kQ; ++q)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const size_t s = (size_t)q * h->lay.plane + (size_t)j * P + i;
+                const double v = fin[(size_t)q * N * N + (size_t)j * N + i];
+                if (h->fp64) reinterpret_cast<double *>(stage.data())[s] = v;
+                else reinterpret_cast<float *>(stage.data())[s] = (float)v;
+            }
+    HIP_TRY(h, hipMemcpyAsync(h->f[h->frozen], stage.data(), stage.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->cur = h->frozen;
+    h->jsub = 0;
+    return HYB_OK;
+}
+
+int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
+    if (!h || !out) return HYB_EINVAL;
+    unsigned long long cnt[kCntSlots];
+    KrylovResult kr{};
+    HIP_TRY(h, hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&kr, h->kres, sizeof(kr), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out->infeasible = (int64_t)cnt[kCntInfeasible];
+    out->nonfinite = (int64_t)cnt[kCntNonfinite];
+    out->krylov_iters = kr.iters;
+    out->krylov_converged = kr.converged;
+    out->krylov_relres = kr.relres;
+    out->coarse_steps = h->coarse_steps;
+    out->fine_steps = h->fine_steps;
+    return HYB_OK;
+}
+
+int hyb_kernel_timing(hyb_handle *h, int enable) {
+    if (!h) return HYB_EINVAL;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, h->drain_events());
+    h->timing = enable != 0;
+    h->timed_ms = 0.0;
+    h->timed_launches = 0;
+    return HYB_OK;
+}
+
+int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches) {
+    if (!h) return HYB_EINVAL;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, h->drain_events());
+    if (total_ms) *total_ms = h->timed_ms;
+    if (launches) *launches = h->timed_launches;
+    h->timed_ms = 0.0;
+    h->timed_launches = 0;
+    return HYB_OK;
+}
+
+int hyb_layout(const hyb_handle *h, size_t *pitch, size_t *plane) {
+    if (!h) return HYB_EINVAL;
+    if (pitch) *pitch = (size_t)h->lay.pitch;
+    if (plane) *plane = (size_t)h->lay.plane;
+    return HYB_OK;
+}
+
+void hyb_destroy(hyb_handle *h) { delete h; }
+
+const char *hyb_last_error(const hyb_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

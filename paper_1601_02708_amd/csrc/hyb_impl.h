@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libhyb (not part of the public C ABI in include/hyb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hyb {
+
+// ---------------------------------------------------------------------------
+// D2Q9 velocity set (Sec. 4.1): rest, +x, +y, -x, -y, (+,+), (-,+), (-,-), (+,-)
+// ---------------------------------------------------------------------------
+constexpr int kQ = 9;
+constexpr int kCx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kCy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int kOpp[kQ] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// Per-node lattice flags (uint16): bit q (1..8) = the upstream neighbour
+// x - e_q is a solid node inside the patch (halfway bounce-back); bit 15 =
+// the node itself is solid.
+constexpr uint16_t kMaskSolid = 1u << 15;
+
+// Device error counters (uint64 slots in the workspace).
+enum Counter { kCntInfeasible = 0, kCntNonfinite = 1, kCntSlots = 8 };
+
+// Result block written by the coarse solver.
+struct KrylovResult {
+    int iters;
+    int converged;
+    double relres;
+    unsigned barrier_timeout;
+    unsigned pad;
+};
+
+// Coarse vectors live on a padded (M+1+2H)^2 grid whose halo stays zero, so
+// stencils up to radius H need no bounds checks.
+constexpr int kCoarseHalo = 3;
+constexpr int kSpaiRadius = 2;                       // preconditioner stencil radius
+constexpr int kSpaiW = 2 * kSpaiRadius + 1;          // 5
+constexpr int kApW = 2 * (kSpaiRadius + 1) + 1;      // 7: A (radius 1) times P (radius 2)
+
+struct LbmArgs {
+    const void *src;
+    void *dst;
+    const uint16_t *mask;
+    const float *vx;
+    const float *vy;
+    const void *kfield;      // T per node or nullptr
+    double k;                // uniform reaction rate when kfield == nullptr
+    double omega;            // 1 / tau
+    int N;
+    int pitch;               // elements between rows
+    long long plane;         // elements between population planes
+    // perimeter closure
+    const int8_t *bc_kind;   // [4(N-1)] or nullptr (all Dirichlet)
+    const double *bc_a;
+    const double *bc_b;
+    double lam;              // j / eta of the step being taken
+    int clamp;
+    unsigned long long *counters;
+};
+
+// Launchers (lbm_kernels.hip); T is float or double via `fp64`.
+hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, hipStream_t s, hipEvent_t bulk_begin = nullptr,
+                           hipEvent_t bulk_end = nullptr);
+hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, bool fp64, hipStream_t s);
+hipError_t launch_concentration(const LbmArgs &a, double *out, bool fp64, hipStream_t s);
+
+struct CoarseDev {
+    int M;
+    int n;                   // (M+1)^2 mesh nodes
+    int S;                   // padded row length M + 1 + 2 kCoarseHalo
+    int grid;                // workgroups of the solver
+    const double *A9;        // [n][9] stencil of A, offsets (dk, dl) in row-major (dl, dk)
+    const double *B9;        // [n][9]
+    const double *AP;        // [n][kApW^2] stencil of A P
+    const double *P;         // [n][kSpaiW^2] stencil of P
+    const int *dkind;        // [n] -1 free, -2 outer Dirichlet, >= 0 index into ufc
+    double outer_value;
+    const double *ufc;       // fine-to-coarse values
+    double *xn;              // padded d(t_n)
+    double *x1;              // padded new solution
+    double *r, *rh, *p, *v, *s, *t, *y;   // padded Krylov vectors
+    double *partials;        // [2][grid][4]
+    unsigned *barrier;       // grid barrier counter
+    KrylovResult *result;
+};
+
+hipError_t launch_coarse_rhs(const CoarseDev &c, const double *guess, hipStream_t s);
+hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int max_iter, double tol,
+                               hipStream_t s);
+
+// Interface transfers (coarse_kernels.hip)
+hipError_t launch_c2f(const int *idx, const double *w, int nslots, const double *xa, const double *xb,
+                      double *a, double *b, hipStream_t s);
+hipError_t launch_f2c(const LbmArgs &lat, const int *idx, const double *w, int nfc, double *ufc, bool fp64,
+                      hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// host-side setup (coarse_setup.hip)
+// ---------------------------------------------------------------------------
+struct CoarseHost {
+    int M = 0;
+    double L = 0, h = 0;
+    std::vector<double> A9, B9, AP, P;
+    std::vector<int> dkind;
+    std::vector<int> fc_nodes;             // mesh node ids on Gamma_{f->c}
+    std::vector<int> fc_idx;               // [nfc][4] padded fine node offsets
+    std::vector<double> fc_w;              // [nfc][4]
+    std::vector<int> c2f_idx;              // [4(N-1)][4] padded coarse indices
+    std::vector<double> c2f_w;             // [4(N-1)][4]
+};
+
+// Assembles A, B for the trapezoidal step dt and the SPAI preconditioner;
+// fills the interface lists.  Returns an empty string or an error message.
+std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
+                         int overlap_elems, int N, double x0, double y0, const uint8_t *solid, int pitch,
+                         CoarseHost &out);
+
+// Perimeter slot <-> node mapping shared by host and device code.
+__host__ __device__ inline void slot_to_node(int N, int p, int &i, int &j) {
+    if (p < N) { i = p; j = 0; return; }
+    if (p < 2 * N) { i = p - N; j = N - 1; return; }
+    if (p < 3 * N - 2) { i = 0; j = p - 2 * N + 1; return; }
+    i = N - 1;
+    j = p - (3 * N - 2) + 1;
+}
+
+}  // namespace hyb

@@ -1,0 +1,320 @@
+// D2Q9 advection-diffusion-reaction lattice Boltzmann kernels for gfx950.
+//
+// One fine step (Sec. 4.1, eqs. LBE and Collision) is a fused pull sweep:
+// each node gathers the post-collision populations of its upstream
+// neighbours (x - e_i), replaces those whose upstream node is solid by its
+// own reversed population (halfway bounce-back), closes the populations
+// whose upstream node lies outside the patch with the maximum-entropy
+// closure of Sec. 4.1.1 (perimeter nodes only), and relaxes towards the
+// equilibrium of eq. (LBM_feq) with the first-order reaction source
+// -k w_i u.  Populations are structure-of-arrays planes [9][N][pitch].
+//
+// The sweep is HBM-bound: per fluid node 9 population loads, 9 stores, the
+// two velocity components (FP32) and the 16-bit flag word.  Interior rows
+// are handled by one workgroup each with consecutive nodes on consecutive
+// lanes (coalesced, one pass over every plane); the 4(N-1) perimeter nodes
+// run in a separate small kernel that carries the FP64 closure code, so its
+// register demand does not lower the occupancy of the bulk sweep.
+#include "hyb_impl.h"
+
+namespace hyb {
+namespace {
+
+constexpr double kW[kQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// BGK collision with reaction, written as
+//   f*_i = (1 - w) f_i + w_i [ w u (1 + 3 e.v + 9/2 (e.v)^2 - 3/2 v.v) - k u ],
+// w = 1/tau; u = sum_i f_i (eq. LBM_Macro); the bracket's polynomial is the
+// equilibrium of eq. (LBM_feq) with c_s^2 = 1/3 and the quadratic term read
+// as -v.v/(2 c_s^2).  Returns u.
+template <typename T>
+__device__ __forceinline__ T collide(T (&f)[kQ], T vx, T vy, T omega, T k) {
+    const T u = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const T A = omega * u;
+    const T base = A * (T(1) - T(1.5) * (vx * vx + vy * vy)) - k * u;
+    const T keep = T(1) - omega;
+    const T c3 = T(3) * A;
+    const T c45 = T(4.5) * A;
+    const T w0 = T(kW[0]), w1 = T(kW[1]), w5 = T(kW[5]);
+    const T dpp = vx + vy, dmp = vy - vx;   // e.v of (+,+) and (-,+)
+    f[0] = keep * f[0] + w0 * base;
+    f[1] = keep * f[1] + w1 * (base + c3 * vx + c45 * vx * vx);
+    f[3] = keep * f[3] + w1 * (base - c3 * vx + c45 * vx * vx);
+    f[2] = keep * f[2] + w1 * (base + c3 * vy + c45 * vy * vy);
+    f[4] = keep * f[4] + w1 * (base - c3 * vy + c45 * vy * vy);
+    f[5] = keep * f[5] + w5 * (base + c3 * dpp + c45 * dpp * dpp);
+    f[7] = keep * f[7] + w5 * (base - c3 * dpp + c45 * dpp * dpp);
+    f[6] = keep * f[6] + w5 * (base + c3 * dmp + c45 * dmp * dmp);
+    f[8] = keep * f[8] + w5 * (base - c3 * dmp + c45 * dmp * dmp);
+    return u;
+}
+
+__device__ __forceinline__ bool finite_val(double x) { return x - x == 0.0; }
+__device__ __forceinline__ bool finite_val(float x) { return x - x == 0.0f; }
+
+template <typename T>
+__device__ __forceinline__ T node_k(const LbmArgs &a, int n) {
+    return a.kfield ? static_cast<const T *>(a.kfield)[n] : T(a.k);
+}
+
+// ---------------------------------------------------------------------------
+// interior rows: j = 1..N-2, i = 1..N-2 (every upstream node is inside)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) lbm_bulk_kernel(LbmArgs a) {
+    const int N = a.N;
+    const int j = blockIdx.x + 1;
+    const int P = a.pitch;
+    const int S = static_cast<int>(a.plane);
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const T omega = T(a.omega);
+    for (int i = 1 + threadIdx.x; i <= N - 2; i += blockDim.x) {
+        const int n = j * P + i;
+        const unsigned m = a.mask[n];
+        if (m & kMaskSolid) continue;
+        T f[kQ];
+        f[0] = src[n];
+#pragma unroll
+        for (int q = 1; q < kQ; ++q) {
+            const int pull = q * S + n - kCx[q] - kCy[q] * P;
+            const int back = kOpp[q] * S + n;
+            f[q] = src[((m >> q) & 1u) ? back : pull];
+        }
+        const T vx = T(a.vx[n]);
+        const T vy = T(a.vy[n]);
+        const T u = collide<T>(f, vx, vy, omega, node_k<T>(a, n));
+        if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) dst[q * S + n] = f[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Maximum-entropy closures (Sec. 4.1.1), FP64.
+//
+// Dirichlet, eq. (LBM_Dir): the unknowns U share the mass deficit
+// R = u^p - sum_{known} f in proportion to w_i.  If R < 0 the node is
+// counted; with clamp the unknowns become 0, otherwise the closed form is
+// kept (constraint met, negative unknowns).
+//
+// Neumann, eq. (LBM_Neu): unknowns with e_i.n < 0 are w_i exp(-1 + g s_i),
+// s_i = -e_i.n > 0, where the Lagrange multiplier g solves
+//   ln sum_i w_i s_i exp(-1 + g s_i) = ln R',  R' = sum_known (e.n) f - q^p.
+// The left side is convex and increasing in g; Newton from the closed-form
+// start (exact when all s_i are equal, i.e. on a flat edge) converges
+// monotonically after its first step.  Tangential unknowns at a corner
+// (e_i.n = 0) are bounced back from the node's own post-collision value.
+// ---------------------------------------------------------------------------
+__device__ int closure_dirichlet(double (&f)[kQ], unsigned unknown, double up, int clamp) {
+    double known = 0.0, wsum = 0.0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        if ((unknown >> q) & 1u) wsum += kW[q];
+        else known += f[q];
+    }
+    double R = up - known;
+    const int bad = R < 0.0;
+    if (bad && clamp) R = 0.0;
+    const double scale = R / wsum;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+        if ((unknown >> q) & 1u) f[q] = kW[q] * scale;
+    return bad;
+}
+
+__device__ int closure_neumann(double (&f)[kQ], unsigned unknown, int sx, int sy, double qp,
+                               const double (&own)[kQ]) {
+    const double inv_norm = rsqrt(double(sx * sx + sy * sy));
+    unsigned out = 0;      // M-: unknowns with e.n < 0
+    double flux_known = 0.0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int dot = kCx[q] * sx + kCy[q] * sy;
+        if ((unknown >> q) & 1u) {
+            if (dot < 0) { out |= 1u << q; continue; }
+            f[q] = own[kOpp[q]];
+        }
+        flux_known += dot * inv_norm * f[q];
+    }
+    const double Rp = flux_known - qp;
+    if (!(Rp > 0.0)) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+            if ((out >> q) & 1u) f[q] = 0.0;
+        return 1;
+    }
+    double sw = 0.0, sw2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        if ((out >> q) & 1u) {
+            const double s = -(kCx[q] * sx + kCy[q] * sy) * inv_norm;
+            sw += kW[q] * s;
+            sw2 += kW[q] * s * s;
+        }
+    }
+    const double lnR = log(Rp);
+    double g = (1.0 + lnR - log(sw)) / (sw2 / sw);
+    for (int it = 0; it < 30; ++it) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            if ((out >> q) & 1u) {
+                const double s = -(kCx[q] * sx + kCy[q] * sy) * inv_norm;
+                const double e = kW[q] * s * exp(-1.0 + g * s);
+                s0 += e;
+                s1 += e * s;
+            }
+        }
+        const double step = (lnR - log(s0)) * s0 / s1;
+        g += step;
+        if (fabs(step) <= 4.0 * 2.220446049250313e-16 * (1.0 + fabs(g))) break;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        if ((out >> q) & 1u) {
+            const double s = -(kCx[q] * sx + kCy[q] * sy) * inv_norm;
+            f[q] = kW[q] * exp(-1.0 + g * s);
+        }
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// perimeter nodes: one thread per slot
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
+    const int N = a.N;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= 4 * (N - 1)) return;
+    int i, j;
+    slot_to_node(N, p, i, j);
+    const int P = a.pitch;
+    const int S = static_cast<int>(a.plane);
+    const int n = j * P + i;
+    const unsigned m = a.mask[n];
+    if (m & kMaskSolid) return;
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+
+    double f[kQ], own[kQ];
+    unsigned unknown = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        own[q] = double(src[q * S + n]);
+        const int si = i - kCx[q], sj = j - kCy[q];
+        if (si < 0 || si >= N || sj < 0 || sj >= N) {
+            unknown |= 1u << q;
+            f[q] = 0.0;
+        } else if ((m >> q) & 1u) {
+            f[q] = double(src[kOpp[q] * S + n]);
+        } else {
+            f[q] = double(src[q * S + sj * P + si]);
+        }
+    }
+    const int kind = a.bc_kind ? a.bc_kind[p] : 0;
+    const double value = (1.0 - a.lam) * a.bc_a[p] + a.lam * a.bc_b[p];
+    int bad;
+    if (kind == 0) {
+        bad = closure_dirichlet(f, unknown, value, a.clamp);
+    } else {
+        const int sx = (i == 0) ? -1 : (i == N - 1) ? 1 : 0;
+        const int sy = (j == 0) ? -1 : (j == N - 1) ? 1 : 0;
+        bad = closure_neumann(f, unknown, sx, sy, value, own);
+    }
+    if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+
+    T g[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) g[q] = T(f[q]);
+    const T u = collide<T>(g, T(a.vx[n]), T(a.vy[n]), T(a.omega), node_k<T>(a, n));
+    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) dst[q * S + n] = g[q];
+}
+
+// ---------------------------------------------------------------------------
+// initial state: f*(0) = collide(f^eq(u0)) at fluid nodes (Sec. 6.2, item i)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) lbm_init_kernel(LbmArgs a, const double *__restrict__ u0) {
+    const int N = a.N;
+    const int j = blockIdx.x;
+    const int P = a.pitch;
+    const int S = static_cast<int>(a.plane);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int n = j * P + i;
+        T f[kQ];
+        if (a.mask[n] & kMaskSolid) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) f[q] = T(0);
+        } else {
+            const T u = T(u0[j * N + i]);
+            const T vx = T(a.vx[n]), vy = T(a.vy[n]);
+            const T usq = T(1.5) * (vx * vx + vy * vy);
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const T ev = T(kCx[q]) * vx + T(kCy[q]) * vy;
+                f[q] = T(kW[q]) * u * (T(1) + T(3) * ev + T(4.5) * ev * ev - usq);
+            }
+            collide<T>(f, vx, vy, T(a.omega), node_k<T>(a, n));
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) dst[q * S + n] = f[q];
+    }
+}
+
+// u = sum_i f*_i / (1 - k): the collision removes k u from the node's mass.
+template <typename T>
+__global__ void __launch_bounds__(256) lbm_conc_kernel(LbmArgs a, double *__restrict__ out) {
+    const int N = a.N;
+    const int j = blockIdx.x;
+    const int P = a.pitch;
+    const int S = static_cast<int>(a.plane);
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int n = j * P + i;
+        double u = 0.0;
+        if (!(a.mask[n] & kMaskSolid)) {
+            for (int q = 0; q < kQ; ++q) u += double(src[q * S + n]);
+            u /= (1.0 - double(node_k<T>(a, n)));
+        }
+        out[j * N + i] = u;
+    }
+}
+
+template <typename T>
+hipError_t step_impl(const LbmArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (a.N > 2) {
+        if (e0) (void)hipEventRecord(e0, s);
+        hipLaunchKernelGGL(lbm_bulk_kernel<T>, dim3(a.N - 2), dim3(256), 0, s, a);
+        if (e1) (void)hipEventRecord(e1, s);
+    }
+    const int np = 4 * (a.N - 1);
+    hipLaunchKernelGGL(lbm_perimeter_kernel<T>, dim3((np + 127) / 128), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, hipStream_t s, hipEvent_t bulk_begin,
+                           hipEvent_t bulk_end) {
+    return fp64 ? step_impl<double>(a, s, bulk_begin, bulk_end) : step_impl<float>(a, s, bulk_begin, bulk_end);
+}
+
+hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, bool fp64, hipStream_t s) {
+    if (fp64) hipLaunchKernelGGL(lbm_init_kernel<double>, dim3(a.N), dim3(256), 0, s, a, u0);
+    else hipLaunchKernelGGL(lbm_init_kernel<float>, dim3(a.N), dim3(256), 0, s, a, u0);
+    return hipGetLastError();
+}
+
+hipError_t launch_concentration(const LbmArgs &a, double *out, bool fp64, hipStream_t s) {
+    if (fp64) hipLaunchKernelGGL(lbm_conc_kernel<double>, dim3(a.N), dim3(256), 0, s, a, out);
+    else hipLaunchKernelGGL(lbm_conc_kernel<float>, dim3(a.N), dim3(256), 0, s, a, out);
+    return hipGetLastError();
+}
+
+}  // namespace hyb

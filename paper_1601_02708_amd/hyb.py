@@ -1,0 +1,258 @@
+"""Python binding of the C ABI in include/hyb.h (ctypes; marshalling only).
+
+Every step of the method runs in libhyb.so's HIP kernels.  PyTorch only
+supplies device memory (the three population buffers and the workspace)
+and the stream.  Importing this module does not need a GPU; creating a
+``Hybrid`` does, and fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhyb.so")
+
+HYB_OK, HYB_EINVAL, HYB_EHIP, HYB_ENOCONV, HYB_ENONFINITE = 0, -1, -2, -3, -4
+HYB_FP64, HYB_FP32 = 0, 1
+HYB_F2C, HYB_C2F = 0, 1
+HYB_FINE, HYB_COARSE = 0, 1
+HYB_BC_DIRICHLET, HYB_BC_NEUMANN = 0, 1
+
+_P = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+
+
+class HybMesh(ctypes.Structure):
+    _fields_ = [("M", _i), ("L", _d), ("outer_value", _d), ("overlap_elems", _i), ("supg", _i), ("d0", _P)]
+
+
+class HybLattice(ctypes.Structure):
+    _fields_ = [("N", _i), ("x0", _d), ("y0", _d), ("precision", _i), ("tau", _d), ("eta", _i),
+                ("bc_clamp", _i), ("solid", _P), ("u0", _P), ("f_buf", _P * 3), ("workspace", _P),
+                ("stream", _P)]
+
+
+class HybVelocity(ctypes.Structure):
+    _fields_ = [("fine", _P), ("coarse", _P)]
+
+
+class HybReaction(ctypes.Structure):
+    _fields_ = [("k", _d), ("k_field", _P)]
+
+
+class HybRunStats(ctypes.Structure):
+    _fields_ = [("infeasible", ctypes.c_int64), ("nonfinite", ctypes.c_int64), ("krylov_iters", ctypes.c_int32),
+                ("krylov_converged", ctypes.c_int32), ("krylov_relres", _d), ("coarse_steps", ctypes.c_int64),
+                ("fine_steps", ctypes.c_int64)]
+
+
+# exported symbol -> (restype, argtypes); mirrors include/hyb.h
+SIGNATURES = {
+    "hyb_query": (_i, [_P, _P, _P, _P]),
+    "hyb_create": (_i, [_P, _P, _d, _P, _P, _P]),
+    "hyb_interface_exchange": (_i, [_P, _i]),
+    "hyb_coarse_step": (_i, [_P, _i]),
+    "hyb_lbm_substeps": (_i, [_P, _i, _i]),
+    "hyb_commit": (_i, [_P]),
+    "hyb_step": (_i, [_P, _i]),
+    "hyb_set_boundary": (_i, [_P, _P, _P, _P]),
+    "hyb_concentration": (_i, [_P, _i, _P, _i]),
+    "hyb_get_populations": (_i, [_P, _P]),
+    "hyb_set_populations": (_i, [_P, _P]),
+    "hyb_stats": (_i, [_P, _P]),
+    "hyb_layout": (_i, [_P, _P, _P]),
+    "hyb_kernel_timing": (_i, [_P, _i]),
+    "hyb_kernel_time": (_i, [_P, _P, _P]),
+    "hyb_destroy": (None, [_P]),
+    "hyb_last_error": (ctypes.c_char_p, [_P]),
+}
+
+_LIB = None
+
+
+class HybError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hyb error {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhyb.so (no GPU needed to load).  Raises if it is not built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Hybrid:
+    """One simulation handle: the fine lattice patch and (optionally) the
+    coarse mesh around it.  Arrays follow include/hyb.h."""
+
+    def __init__(self, *, N, x0, y0, u0, vx, vy, D, eta, precision="fp64", tau=0.0, solid=None,
+                 k=0.0, k_field=None, bc_clamp=0, mesh=None, device=None):
+        import torch
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Hybrid needs a GPU (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.dev = torch.device(device or "cuda:0")
+        self.N, self.eta = int(N), int(eta)
+        self.precision = precision
+        self._keep = []
+
+        def host(a, dt):
+            arr = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(arr)
+            return arr
+
+        u0h = host(np.asarray(u0).reshape(N, N), np.float64)
+        vel = host(np.stack([np.asarray(vx).reshape(N, N), np.asarray(vy).reshape(N, N)]), np.float32)
+        solidh = None if solid is None else host(np.asarray(solid).reshape(N, N), np.uint8)
+        kfh = None if k_field is None else host(np.asarray(k_field).reshape(N, N), np.float64)
+
+        self.lat = HybLattice()
+        self.lat.N = self.N
+        self.lat.x0, self.lat.y0 = float(x0), float(y0)
+        self.lat.precision = HYB_FP64 if precision == "fp64" else HYB_FP32
+        self.lat.tau = float(tau)
+        self.lat.eta = self.eta
+        self.lat.bc_clamp = int(bc_clamp)
+        self.lat.solid = _ptr(solidh)
+        self.lat.u0 = _ptr(u0h)
+        self.meshs = None
+        vc = None
+        if mesh is not None:
+            self.M = int(mesh["M"])
+            d0 = host(np.asarray(mesh["d0"]).ravel(), np.float64)
+            vc = host(np.asarray(mesh["v"]).reshape(-1, 2), np.float64)
+            self.meshs = HybMesh(self.M, float(mesh["L"]), float(mesh.get("outer_value", 0.0)),
+                                 int(mesh.get("overlap_elems", 1)), int(mesh.get("supg", 1)), _ptr(d0))
+        else:
+            self.M = 0
+        fb = ctypes.c_size_t()
+        wb = ctypes.c_size_t()
+        mp = ctypes.addressof(self.meshs) if self.meshs is not None else None
+        rc = lib.hyb_query(mp, ctypes.addressof(self.lat), ctypes.addressof(fb), ctypes.addressof(wb))
+        if rc != HYB_OK:
+            raise HybError(rc, "hyb_query rejected the problem")
+        self.f_bytes, self.ws_bytes = fb.value, wb.value
+        self.fbuf = [torch.empty(self.f_bytes, dtype=torch.uint8, device=self.dev) for _ in range(3)]
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.dev)
+        for b in range(3):
+            self.lat.f_buf[b] = self.fbuf[b].data_ptr()
+        self.lat.workspace = self.ws.data_ptr()
+        self.stream = torch.cuda.current_stream(self.dev)
+        self.lat.stream = self.stream.cuda_stream
+        self.vel = HybVelocity(_ptr(vel), _ptr(vc))
+        self.react = HybReaction(float(k), _ptr(kfh))
+        h = ctypes.c_void_p()
+        rc = lib.hyb_create(mp, ctypes.addressof(self.lat), float(D), ctypes.addressof(self.vel),
+                            ctypes.addressof(self.react), ctypes.addressof(h))
+        if rc != HYB_OK:
+            raise HybError(rc, "hyb_create failed (see stderr)")
+        self.h = h
+        self._keep.clear()
+
+    @classmethod
+    def from_problem(cls, problem, precision="fp64", tau=None, mesh=True, **kw):
+        cfg = problem.cfg
+        m = None
+        if mesh:
+            m = dict(M=cfg.M, L=problem.L, outer_value=kw.pop("outer_value", 0.0), overlap_elems=cfg.overlap_elems,
+                     supg=cfg.supg, d0=problem.u0_coarse, v=problem.vc)
+        return cls(N=cfg.N, x0=problem.x0, y0=problem.y0, u0=problem.u0_fine, vx=problem.vx, vy=problem.vy,
+                   D=cfg.D, eta=kw.pop("eta", cfg.eta), precision=precision,
+                   tau=cfg.tau_value if tau is None else tau, solid=problem.solid, k=cfg.k,
+                   bc_clamp=cfg.bc_clamp, mesh=m, **kw)
+
+    # -- calls ------------------------------------------------------------
+    def _check(self, rc):
+        if rc != HYB_OK:
+            raise HybError(rc, load().hyb_last_error(self.h).decode())
+        return rc
+
+    def interface_exchange(self, direction):
+        return self._check(load().hyb_interface_exchange(self.h, direction))
+
+    def coarse_step(self, max_iter=0):
+        return self._check(load().hyb_coarse_step(self.h, max_iter))
+
+    def lbm_substeps(self, n_sub, restart=1):
+        return self._check(load().hyb_lbm_substeps(self.h, n_sub, restart))
+
+    def commit(self):
+        return self._check(load().hyb_commit(self.h))
+
+    def step(self, max_schwarz):
+        return self._check(load().hyb_step(self.h, max_schwarz))
+
+    def set_boundary(self, a, b=None, kind=None):
+        P = 4 * (self.N - 1)
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (P,)))
+        b = None if b is None else np.ascontiguousarray(np.broadcast_to(np.asarray(b, np.float64), (P,)))
+        kind = None if kind is None else np.ascontiguousarray(kind, np.int8)
+        return self._check(load().hyb_set_boundary(self.h, _ptr(kind), _ptr(a), _ptr(b)))
+
+    def concentration(self, which=HYB_FINE):
+        n = self.N * self.N if which == HYB_FINE else (self.M + 1) ** 2
+        out = np.empty(n)
+        self._check(load().hyb_concentration(self.h, which, out.ctypes.data, 0))
+        return out.reshape(self.N, self.N) if which == HYB_FINE else out
+
+    def concentration_device(self, out_tensor, which=HYB_FINE):
+        return self._check(load().hyb_concentration(self.h, which, out_tensor.data_ptr(), 1))
+
+    def get_populations(self):
+        out = np.empty((9, self.N, self.N))
+        self._check(load().hyb_get_populations(self.h, out.ctypes.data))
+        return out
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, np.float64)
+        return self._check(load().hyb_set_populations(self.h, f.ctypes.data))
+
+    def stats(self):
+        s = HybRunStats()
+        self._check(load().hyb_stats(self.h, ctypes.addressof(s)))
+        return {k: getattr(s, k) for k, _ in HybRunStats._fields_}
+
+    def kernel_timing(self, enable=True):
+        return self._check(load().hyb_kernel_timing(self.h, int(enable)))
+
+    def kernel_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(load().hyb_kernel_time(self.h, ctypes.addressof(ms), ctypes.addressof(n)))
+        return ms.value, n.value
+
+    def layout(self):
+        p = ctypes.c_size_t()
+        q = ctypes.c_size_t()
+        self._check(load().hyb_layout(self.h, ctypes.addressof(p), ctypes.addressof(q)))
+        return p.value, q.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().hyb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
