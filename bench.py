@@ -9,7 +9,7 @@ mesh, eta = 10 fine steps per coarse step, 2 Schwarz passes): 2 x
 already resident in HBM when the timed region starts.
 
 The printed JSON line reports lattice updates per second over all nodes
-(MLUPS), the roofline of the bulk lattice sweep (algorithmic bytes per
+(MLUPS), the roofline of the lattice-sweep kernel (algorithmic bytes per
 launch over its average duration, timed with HIP events on its stream),
 the FP64 path on the same GPU with the FP32 result's relative L2 error
 against it, and the CPU oracle timed on a bounded sample on this host.
@@ -33,15 +33,16 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def bulk_bytes(problem, elem_bytes):
-    """Algorithmic HBM bytes of one bulk sweep (interior nodes): per fluid
-    node 9 population loads + 9 stores, 2 FP32 velocity components and the
-    16-bit flag word; a solid node reads only its flag word."""
-    s = problem.solid[1:-1, 1:-1]
-    fluid = int((s == 0).sum())
-    solid = int(s.size - fluid)
+def sweep_bytes(problem, elem_bytes):
+    """Algorithmic HBM bytes of one lattice sweep (every node of the patch):
+    per fluid node 9 population loads + 9 stores, 2 FP32 velocity
+    components and the 16-bit flag word; a solid node reads only its flag
+    word; each perimeter slot also reads its two FP64 interface values."""
+    N = problem.cfg.N
+    fluid = int((problem.solid == 0).sum())
+    solid = N * N - fluid
     per_fluid = 18 * elem_bytes + 8 + 2
-    return fluid * per_fluid + solid * 2, fluid, solid, per_fluid
+    return fluid * per_fluid + solid * 2 + 4 * (N - 1) * 16, fluid, solid, per_fluid
 
 
 def load_traffic(workload, precision):
@@ -105,6 +106,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the second-precision run")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times (a plain copy kernel of "
+                         "known size, for calibrating HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
@@ -125,7 +129,7 @@ def main():
     g, wall, gpu_ms, kms, launches, st = run_gpu(problem, args.precision, args.steps, args.warmup)
     ms_step = gpu_ms / args.steps
     value = lups_step * args.steps / (gpu_ms / 1e3) / 1e6
-    bbytes, nfl, nsol, per_fluid = bulk_bytes(problem, elem)
+    bbytes, nfl, nsol, per_fluid = sweep_bytes(problem, elem)
     avg_kernel_ms = kms / max(launches, 1)
     achieved = bbytes / (avg_kernel_ms / 1e3) / 1e9
     traffic = load_traffic(cfg.name, args.precision)
@@ -156,13 +160,13 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"lbm_bulk_kernel<{'float' if elem == 4 else 'double'}>",
+            "kernel": f"lbm_sweep_kernel<{'float' if elem == 4 else 'double'}>",
             "algorithmic_bytes_per_launch": bbytes,
             "avg_launch_ms": round(avg_kernel_ms, 5),
             "launches_timed": launches,
             "bytes_per_fluid_update": per_fluid,
         },
-        "bulk_time_frac": round(kms / gpu_ms, 4),
+        "sweep_time_frac": round(kms / gpu_ms, 4),
         "wall_s": round(wall, 3),
         "krylov_iters_last": st["krylov_iters"],
         "infeasible_closures": st["infeasible"],
@@ -176,17 +180,26 @@ def main():
         ref, low = (u2, u1) if other == "fp64" else (u1, u2)
         err = float(np.linalg.norm((low - ref)[fluid]) / np.linalg.norm(ref[fluid]))
         e2 = 4 if other == "fp32" else 8
-        b2, _, _, _ = bulk_bytes(problem, e2)
+        b2, _, _, _ = sweep_bytes(problem, e2)
         k2 = kms2 / max(launches2, 1)
         res[other] = {"value": round(lups_step * args.steps / (gpu_ms2 / 1e3) / 1e6, 1), "unit": "MLUPS",
                       "ms_per_step": round(gpu_ms2 / args.steps, 4),
-                      "bulk_achieved_gbs": round(b2 / (k2 / 1e3) / 1e9, 1),
-                      "bulk_avg_launch_ms": round(k2, 5)}
+                      "sweep_achieved_gbs": round(b2 / (k2 / 1e3) / 1e9, 1),
+                      "sweep_avg_launch_ms": round(k2, 5)}
         res["fp32_rel_l2_vs_fp64"] = err
         del g2
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one coarse step)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(problem)
+    if args.copy_mib > 0:
+        import torch
+        nbytes = args.copy_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = nbytes
     print(json.dumps(res), flush=True)
 
 

@@ -177,9 +177,11 @@ int hyb_set_populations(hyb_handle *h, const double *f);
 int hyb_stats(hyb_handle *h, hyb_run_stats *out);
 
 /* Measurement: while enabled, each fine step records a pair of HIP events
- * on the handle's stream around its bulk lattice kernel (the interior-node
- * sweep); hyb_kernel_time returns the summed elapsed milliseconds and the
- * number of timed launches since the last call, and synchronises. */
+ * on the handle's stream around its lattice-sweep kernel (the single launch
+ * that updates every node when all perimeter slots are Dirichlet, else the
+ * interior-node kernel); hyb_kernel_time returns the summed elapsed
+ * milliseconds and the number of timed launches since the last call, and
+ * synchronises. */
 int hyb_kernel_timing(hyb_handle *h, int enable);
 int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches);
 

@@ -24,17 +24,18 @@ __device__ __forceinline__ int padded_index(const CoarseDev &c, int node) {
     return (l + kCoarseHalo) * c.S + (k + kCoarseHalo);
 }
 
-// Stencil product of row `node` (width W, radius W/2) with padded vector x.
+// Stencil product of row `node` (width W, radius W/2) with padded vector x;
+// coefficients are offset-major (coef[o * n + node]).
 template <int W>
-__device__ __forceinline__ double stencil_row(const double *__restrict__ coef, int node, int pidx, int S,
+__device__ __forceinline__ double stencil_row(const double *__restrict__ coef, int n, int node, int pidx, int S,
                                               const double *__restrict__ x) {
     constexpr int R = W / 2;
-    const double *cr = coef + (size_t)node * W * W;
     double acc = 0.0;
 #pragma unroll
     for (int dl = -R; dl <= R; ++dl) {
 #pragma unroll
-        for (int dk = -R; dk <= R; ++dk) acc += cr[(dl + R) * W + (dk + R)] * x[pidx + dl * S + dk];
+        for (int dk = -R; dk <= R; ++dk)
+            acc += coef[(size_t)((dl + R) * W + (dk + R)) * n + node] * x[pidx + dl * S + dk];
     }
     return acc;
 }
@@ -66,36 +67,45 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     }
 }
 
-// Grid-wide barrier for a cooperative launch: every thread fences its
-// writes to device scope, one thread per block arrives on a counter and
-// waits until all blocks of this round have arrived.  The wait is bounded;
-// a timeout is recorded and the caller abandons the solve.
+// Grid-wide barrier for a cooperative launch.  Each block publishes the
+// round it has reached in its own flag word (no contended atomics); the
+// first wave of every block then polls all flags until each has reached
+// the round.  One thread per block fences to device scope on either side
+// (release of the block's writes, acquire of the others'), bracketed by
+// workgroup barriers.  The wait is bounded: a timeout is recorded and the
+// caller abandons the solve.
 __device__ bool grid_barrier(const CoarseDev &c, unsigned &round) {
-    __threadfence();
     __syncthreads();
-    __shared__ int timed_out;
-    if (threadIdx.x == 0) {
-        timed_out = 0;
-        if (gridDim.x > 1) {
-            round += 1;
-            const unsigned target = round * gridDim.x;
-            atomicAdd(c.barrier, 1u);
-            unsigned spins = 0;
-            while (__hip_atomic_load(c.barrier, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1u << 26) ||
-                    __hip_atomic_load(&c.result->barrier_timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    atomicOr(&c.result->barrier_timeout, 1u);
-                    timed_out = 1;
-                    break;
-                }
+    if (gridDim.x == 1) return true;
+    round += 1;
+    __shared__ int failed;
+    if (threadIdx.x < 64) {
+        if (threadIdx.x == 0) {
+            __threadfence();
+            __hip_atomic_store(&c.flags[blockIdx.x], round, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        unsigned spins = 0;
+        int st = 0;
+        for (;;) {
+            int reached = 1;
+            for (int b = threadIdx.x; b < (int)gridDim.x; b += 64)
+                reached &= __hip_atomic_load(&c.flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= round;
+            if (__all(reached)) break;
+            if (++spins > (1u << 26) ||
+                __hip_atomic_load(&c.result->barrier_timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                st = 1;
+                break;
             }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (st) atomicOr(&c.result->barrier_timeout, 1u);
+            failed = st;
         }
     }
     __syncthreads();
-    __threadfence();
-    return timed_out == 0 && __hip_atomic_load(&c.result->barrier_timeout, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT) == 0;
+    return failed == 0;
 }
 
 // Reduce NV per-thread values over the grid; the result is returned to
@@ -120,24 +130,23 @@ __device__ bool grid_sum(const CoarseDev &c, double (&v)[NV], unsigned &round, i
     return true;
 }
 
-// b = B d(t_n) on free rows, the prescribed value on Dirichlet rows;
+// b = B d(t_n) on free rows, a_ii times the prescribed value on Dirichlet rows;
 // r0 = b - A x0 (x0 = initial guess); also writes ||b||^2 partials and
-// resets the barrier counter and result block for the solve that follows.
+// resets the barrier flags and result block for the solve that follows.
 __global__ void __launch_bounds__(kBlock) coarse_rhs_kernel(CoarseDev c, const double *__restrict__ guess) {
     __shared__ double lds[16];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *c.barrier = 0u;
-        c.result->barrier_timeout = 0u;
+    if (blockIdx.x == 0) {
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) c.flags[b] = 0u;
+        if (threadIdx.x == 0) c.result->barrier_timeout = 0u;
     }
     double bb[1] = {0.0};
     for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < c.n; node += gridDim.x * blockDim.x) {
         const int pidx = padded_index(c, node);
         const int kind = c.dkind[node];
         double b;
-        if (kind == -1) b = stencil_row<3>(c.B9, node, pidx, c.S, c.xn);
-        else if (kind == -2) b = c.outer_value;
-        else b = c.ufc[kind];
-        const double r0 = b - stencil_row<3>(c.A9, node, pidx, c.S, guess);
+        if (kind == -1) b = stencil_row<3>(c.B9, c.n, node, pidx, c.S, c.xn);
+        else b = c.A9[(size_t)4 * c.n + node] * (kind == -2 ? c.outer_value : c.ufc[kind]);
+        const double r0 = b - stencil_row<3>(c.A9, c.n, node, pidx, c.S, guess);
         c.r[pidx] = r0;
         bb[0] += b * b;
     }
@@ -187,7 +196,7 @@ __global__ void __launch_bounds__(kBlock) coarse_bicgstab_kernel(CoarseDev c, co
         double d1[1] = {0.0};
         for (int node = first; node < c.n; node += stride) {
             const int pi = padded_index(c, node);
-            const double vv = stencil_row<kApW>(c.AP, node, pi, c.S, c.p);
+            const double vv = stencil_row<kApW>(c.AP, c.n, node, pi, c.S, c.p);
             c.v[pi] = vv;
             d1[0] += c.rh[pi] * vv;
         }
@@ -201,7 +210,7 @@ __global__ void __launch_bounds__(kBlock) coarse_bicgstab_kernel(CoarseDev c, co
         double d2[2] = {0.0, 0.0};
         for (int node = first; node < c.n; node += stride) {
             const int pi = padded_index(c, node);
-            const double tt = stencil_row<kApW>(c.AP, node, pi, c.S, c.s);
+            const double tt = stencil_row<kApW>(c.AP, c.n, node, pi, c.S, c.s);
             c.t[pi] = tt;
             d2[0] += tt * c.s[pi];
             d2[1] += tt * tt;
@@ -228,7 +237,7 @@ __global__ void __launch_bounds__(kBlock) coarse_bicgstab_kernel(CoarseDev c, co
     if (ok) {
         for (int node = first; node < c.n; node += stride) {
             const int pi = padded_index(c, node);
-            c.x1[pi] = guess[pi] + stencil_row<kSpaiW>(c.P, node, pi, c.S, c.y);
+            c.x1[pi] = guess[pi] + stencil_row<kSpaiW>(c.P, c.n, node, pi, c.S, c.y);
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -8,7 +8,7 @@
 // * Trapezoidal rule of eq. (FEM_discrete) with theta = 1/2 for the nodal
 //   values: A = C + dt/2 T, B = C - dt/2 T with capacity C = M + Ms and
 //   transport T = K + Ks (K includes the reaction k M).
-// * Strong Dirichlet rows (identity) on the outer edge and on Gamma_{f->c}.
+// * Strong Dirichlet rows (diagonal only) on the outer edge and on Gamma_{f->c}.
 // * A sparse approximate inverse P of A on a (2R+1)^2 stencil: row i of P
 //   minimises || e_i^T - P_i A ||_2 over that pattern (normal equations,
 //   Cholesky).  A P is formed once as a (2R+3)^2 stencil.
@@ -32,7 +32,7 @@ double upwind_chi(double a) {
         s = 1.0 / 3.0 + a2 * s;
         return a * s;
     }
-    return std::cosh(a) / std::sinh(a) - 1.0 / a;
+    return 1.0 / std::tanh(a) - 1.0 / a;   // tanh saturates to 1; cosh/sinh would overflow
 }
 
 struct Stencil {
@@ -159,11 +159,16 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
             }
         }
     }
+    // A Dirichlet row becomes a_ii e_i with the assembled diagonal a_ii (the
+    // right-hand side is scaled by a_ii too), so every row of A carries the
+    // same scale (~h^2) and the preconditioner's local systems stay well
+    // conditioned even when h is hundreds of lattice units.
     for (int id = 0; id < n; ++id) {
         if (out.dkind[id] == -1) continue;
+        const double diag = A.at(id, 0, 0);
         for (int dl = -1; dl <= 1; ++dl)
             for (int dk = -1; dk <= 1; ++dk) A.at(id, dk, dl) = 0.0;
-        A.at(id, 0, 0) = 1.0;
+        A.at(id, 0, 0) = diag > 0.0 ? diag : 1.0;
     }
 
     // --- sparse approximate inverse of A ---------------------------------
@@ -203,8 +208,11 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
                     G[b * np + a] = s;
                 }
             }
-            if (!chol_solve(G, rhs, np)) return "coarse preconditioner: singular local system";
-            for (int a = 0; a < np; ++a) P.at(id, pk[a], pl[a]) = rhs[a];
+            if (chol_solve(G, rhs, np)) {
+                for (int a = 0; a < np; ++a) P.at(id, pk[a], pl[a]) = rhs[a];
+            } else {
+                P.at(id, 0, 0) = 1.0 / A.get(id, 0, 0);   // Jacobi row as a fallback
+            }
         }
     }
     Stencil AP(M, kApW);
@@ -225,6 +233,10 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
                 }
         }
     }
+    for (double x : A.c)
+        if (!std::isfinite(x)) return "coarse operator has non-finite entries";
+    for (double x : P.c)
+        if (!std::isfinite(x)) return "coarse preconditioner has non-finite entries";
     out.A9 = std::move(A.c);
     out.B9 = std::move(B.c);
     out.P = std::move(P.c);

@@ -27,7 +27,15 @@ long long choose_plane(int N, int pitch) { return (long long)align_up((size_t)N 
 
 int coarse_grid(int n) {
     if (n <= 2048) return 1;
-    return std::min(128, (n + 255) / 256);
+    return std::min(256, (n + 255) / 256);
+}
+
+// node-major [n][W*W] -> offset-major [W*W][n]
+std::vector<double> offset_major(const std::vector<double> &c, int n, int w2) {
+    std::vector<double> t(c.size());
+    for (int node = 0; node < n; ++node)
+        for (int o = 0; o < w2; ++o) t[(size_t)o * n + node] = c[(size_t)node * w2 + o];
+    return t;
 }
 
 struct Layout {
@@ -83,7 +91,7 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
         L.dkind = take((size_t)L.n * 4);
         L.vec = take(9 * align_up(L.vec_len * 8, kAlign));
         L.partials = take((size_t)12 * L.grid * 8);
-        L.barrier = take(64);
+        L.barrier = take((size_t)L.grid * 4);
     }
     L.total = off;
     return L;
@@ -109,6 +117,7 @@ struct hyb_handle {
     int8_t *bc_kind = nullptr;
     double *bc_a = nullptr, *bc_b = nullptr;
     bool kinds_set = false;
+    bool any_neumann = false;
     int *c2f_idx = nullptr, *fc_idx = nullptr;
     double *c2f_w = nullptr, *fc_w = nullptr, *ufc = nullptr;
     int nfc = 0;
@@ -359,12 +368,15 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         c.t = vec[7];
         c.y = vec[8];
         c.partials = reinterpret_cast<double *>(h->ws + L.partials);
-        c.barrier = reinterpret_cast<unsigned *>(h->ws + L.barrier);
+        c.flags = reinterpret_cast<unsigned *>(h->ws + L.barrier);
         c.result = h->kres;
-        CREATE_TRY(up((void *)c.A9, ch.A9.data(), ch.A9.size() * 8));
-        CREATE_TRY(up((void *)c.B9, ch.B9.data(), ch.B9.size() * 8));
-        CREATE_TRY(up((void *)c.AP, ch.AP.data(), ch.AP.size() * 8));
-        CREATE_TRY(up((void *)c.P, ch.P.data(), ch.P.size() * 8));
+        const std::vector<double> A9t = offset_major(ch.A9, L.n, 9), B9t = offset_major(ch.B9, L.n, 9);
+        const std::vector<double> APt = offset_major(ch.AP, L.n, kApW * kApW);
+        const std::vector<double> Pt = offset_major(ch.P, L.n, kSpaiW * kSpaiW);
+        CREATE_TRY(up((void *)c.A9, A9t.data(), A9t.size() * 8));
+        CREATE_TRY(up((void *)c.B9, B9t.data(), B9t.size() * 8));
+        CREATE_TRY(up((void *)c.AP, APt.data(), APt.size() * 8));
+        CREATE_TRY(up((void *)c.P, Pt.data(), Pt.size() * 8));
         CREATE_TRY(up((void *)c.dkind, ch.dkind.data(), ch.dkind.size() * 4));
         std::vector<double> xp(L.vec_len, 0.0);
         const int m1 = mesh->M + 1;
@@ -446,7 +458,7 @@ int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
             e1 = h->ev_pool[2 * h->ev_used + 1];
             h->ev_used += 1;
         }
-        HIP_TRY(h, launch_lbm_step(a, h->fp64, h->stream, e0, e1));
+        HIP_TRY(h, launch_lbm_step(a, h->fp64, h->any_neumann, h->stream, e0, e1));
         h->cur = dst;
         h->jsub += 1;
         h->fine_steps += 1;
@@ -505,8 +517,11 @@ int hyb_set_boundary(hyb_handle *h, const int8_t *kind, const double *a, const d
                 return h->fail(HYB_EINVAL, "unknown boundary kind");
         HIP_TRY(h, hipMemcpyAsync(h->bc_kind, kind, ns, hipMemcpyHostToDevice, h->stream));
         h->kinds_set = true;
+        h->any_neumann = false;
+        for (size_t p = 0; p < ns; ++p) h->any_neumann |= kind[p] == HYB_BC_NEUMANN;
     } else {
         h->kinds_set = false;
+        h->any_neumann = false;
     }
     HIP_TRY(h, hipMemcpyAsync(h->bc_a, a, ns * 8, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipMemcpyAsync(h->bc_b, b ? b : a, ns * 8, hipMemcpyHostToDevice, h->stream));

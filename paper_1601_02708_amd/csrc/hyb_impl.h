@@ -65,8 +65,11 @@ struct LbmArgs {
 };
 
 // Launchers (lbm_kernels.hip); T is float or double via `fp64`.
-hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, hipStream_t s, hipEvent_t bulk_begin = nullptr,
-                           hipEvent_t bulk_end = nullptr);
+// One fine step.  general_perimeter: run the perimeter in the separate
+// kernel that supports the Neumann closure (else one fused launch with the
+// Dirichlet closure).  The optional events bracket the interior sweep.
+hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, bool general_perimeter, hipStream_t s,
+                           hipEvent_t sweep_begin = nullptr, hipEvent_t sweep_end = nullptr);
 hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, bool fp64, hipStream_t s);
 hipError_t launch_concentration(const LbmArgs &a, double *out, bool fp64, hipStream_t s);
 
@@ -75,18 +78,20 @@ struct CoarseDev {
     int n;                   // (M+1)^2 mesh nodes
     int S;                   // padded row length M + 1 + 2 kCoarseHalo
     int grid;                // workgroups of the solver
-    const double *A9;        // [n][9] stencil of A, offsets (dk, dl) in row-major (dl, dk)
-    const double *B9;        // [n][9]
-    const double *AP;        // [n][kApW^2] stencil of A P
-    const double *P;         // [n][kSpaiW^2] stencil of P
+    // stencils stored offset-major, coef[o * n + node], o = (dl + R) * W + (dk + R),
+    // so consecutive lanes (consecutive nodes) read consecutive addresses
+    const double *A9;        // [9][n] stencil of A
+    const double *B9;        // [9][n]
+    const double *AP;        // [kApW^2][n] stencil of A P
+    const double *P;         // [kSpaiW^2][n] stencil of P
     const int *dkind;        // [n] -1 free, -2 outer Dirichlet, >= 0 index into ufc
     double outer_value;
     const double *ufc;       // fine-to-coarse values
     double *xn;              // padded d(t_n)
     double *x1;              // padded new solution
     double *r, *rh, *p, *v, *s, *t, *y;   // padded Krylov vectors
-    double *partials;        // [2][grid][4]
-    unsigned *barrier;       // grid barrier counter
+    double *partials;        // [2][grid][4] reduction partials, then [grid] for ||b||^2
+    unsigned *flags;         // [grid] barrier arrival rounds
     KrylovResult *result;
 };
 

@@ -10,11 +10,13 @@
 // -k w_i u.  Populations are structure-of-arrays planes [9][N][pitch].
 //
 // The sweep is HBM-bound: per fluid node 9 population loads, 9 stores, the
-// two velocity components (FP32) and the 16-bit flag word.  Interior rows
-// are handled by one workgroup each with consecutive nodes on consecutive
-// lanes (coalesced, one pass over every plane); the 4(N-1) perimeter nodes
-// run in a separate small kernel that carries the FP64 closure code, so its
-// register demand does not lower the occupancy of the bulk sweep.
+// two velocity components (FP32) and the 16-bit flag word.  One launch per
+// fine step covers the whole patch: consecutive interior nodes sit on
+// consecutive lanes (coalesced, one pass over every plane) and the 4(N-1)
+// perimeter nodes, with the Dirichlet closure, run in the same launch.
+// When some perimeter slots use the Neumann closure (a Newton solve in
+// FP64), those nodes run in a separate kernel so its register demand does
+// not lower the occupancy of the interior sweep.
 #include "hyb_impl.h"
 
 namespace hyb {
@@ -59,36 +61,108 @@ __device__ __forceinline__ T node_k(const LbmArgs &a, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// interior rows: j = 1..N-2, i = 1..N-2 (every upstream node is inside)
+// interior node update: every upstream node of (i, j), 1 <= i, j <= N-2, is
+// inside the patch.  The nine loads use the pull address, or the node's
+// own opposite population where the flag word marks a solid upstream node.
+// Stores are non-temporal: the destination plane is not read again before
+// the whole sweep has finished, so it should not displace source lines
+// from the caches.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) lbm_bulk_kernel(LbmArgs a) {
+__device__ __forceinline__ void interior_node(const LbmArgs &a, const T *__restrict__ src, T *__restrict__ dst,
+                                              int n, int S, int P, T omega) {
+    const unsigned m = a.mask[n];
+    if (m & kMaskSolid) return;
+    T f[kQ];
+    f[0] = src[n];
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) {
+        const int pull = q * S + n - kCx[q] - kCy[q] * P;
+        const int back = kOpp[q] * S + n;
+        f[q] = src[((m >> q) & 1u) ? back : pull];
+    }
+    const T vx = T(a.vx[n]);
+    const T vy = T(a.vy[n]);
+    const T u = collide<T>(f, vx, vy, omega, node_k<T>(a, n));
+    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(f[q], &dst[q * S + n]);
+}
+
+// Perimeter node with the Dirichlet closure of eq. (LBM_Dir): unknown
+// populations (upstream node outside the patch) share the mass deficit
+// R = u^p - sum_known f in proportion to w_i; sums and R in FP64.
+template <typename T>
+__device__ __forceinline__ void perimeter_dirichlet_node(const LbmArgs &a, const T *__restrict__ src,
+                                                         T *__restrict__ dst, int p, int S, int P, T omega) {
     const int N = a.N;
-    const int j = blockIdx.x + 1;
+    int i, j;
+    slot_to_node(N, p, i, j);
+    const int n = j * P + i;
+    const unsigned m = a.mask[n];
+    if (m & kMaskSolid) return;
+    T f[kQ];
+    unsigned unknown = 0;
+    double known = 0.0, wsum = 0.0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int si = i - kCx[q], sj = j - kCy[q];
+        if (si < 0 || si >= N || sj < 0 || sj >= N) {
+            unknown |= 1u << q;
+            wsum += kW[q];
+            f[q] = T(0);
+        } else {
+            f[q] = src[((m >> q) & 1u) ? kOpp[q] * S + n : q * S + sj * P + si];
+            known += double(f[q]);
+        }
+    }
+    double R = (1.0 - a.lam) * a.bc_a[p] + a.lam * a.bc_b[p] - known;
+    const bool bad = R < 0.0;
+    if (bad && a.clamp) R = 0.0;
+    const double scale = R / wsum;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+        if ((unknown >> q) & 1u) f[q] = T(kW[q] * scale);
+    if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+    const T u = collide<T>(f, T(a.vx[n]), T(a.vy[n]), omega, node_k<T>(a, n));
+    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) dst[q * S + n] = f[q];
+}
+
+// One fine step over the whole patch in a single launch: the first
+// `per_blocks` workgroups take the 4(N-1) perimeter slots (Dirichlet
+// closure), the rest take the interior in row-major order, 256 nodes of one
+// row per workgroup, so the sweep advances through memory as a band.
+template <typename T>
+__global__ void __launch_bounds__(256) lbm_sweep_kernel(LbmArgs a, int per_blocks, int row_blocks) {
     const int P = a.pitch;
     const int S = static_cast<int>(a.plane);
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
     const T omega = T(a.omega);
-    for (int i = 1 + threadIdx.x; i <= N - 2; i += blockDim.x) {
-        const int n = j * P + i;
-        const unsigned m = a.mask[n];
-        if (m & kMaskSolid) continue;
-        T f[kQ];
-        f[0] = src[n];
-#pragma unroll
-        for (int q = 1; q < kQ; ++q) {
-            const int pull = q * S + n - kCx[q] - kCy[q] * P;
-            const int back = kOpp[q] * S + n;
-            f[q] = src[((m >> q) & 1u) ? back : pull];
-        }
-        const T vx = T(a.vx[n]);
-        const T vy = T(a.vy[n]);
-        const T u = collide<T>(f, vx, vy, omega, node_k<T>(a, n));
-        if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) dst[q * S + n] = f[q];
+    const int b = blockIdx.x;
+    if (b < per_blocks) {
+        const int p = b * blockDim.x + threadIdx.x;
+        if (p < 4 * (a.N - 1)) perimeter_dirichlet_node<T>(a, src, dst, p, S, P, omega);
+        return;
     }
+    const int r = b - per_blocks;
+    const int j = 1 + r / row_blocks;
+    const int i = 1 + (r % row_blocks) * blockDim.x + threadIdx.x;
+    if (i <= a.N - 2) interior_node<T>(a, src, dst, j * P + i, S, P, omega);
+}
+
+// Interior only (used with the general perimeter kernel when some slots
+// carry the Neumann closure).
+template <typename T>
+__global__ void __launch_bounds__(256) lbm_bulk_kernel(LbmArgs a, int row_blocks) {
+    const int P = a.pitch;
+    const int S = static_cast<int>(a.plane);
+    const int j = 1 + blockIdx.x / row_blocks;
+    const int i = 1 + (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
+    if (i <= a.N - 2)
+        interior_node<T>(a, static_cast<const T *>(a.src), static_cast<T *>(a.dst), j * P + i, S, P, T(a.omega));
 }
 
 // ---------------------------------------------------------------------------
@@ -287,22 +361,31 @@ __global__ void __launch_bounds__(256) lbm_conc_kernel(LbmArgs a, double *__rest
 }
 
 template <typename T>
-hipError_t step_impl(const LbmArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (a.N > 2) {
-        if (e0) (void)hipEventRecord(e0, s);
-        hipLaunchKernelGGL(lbm_bulk_kernel<T>, dim3(a.N - 2), dim3(256), 0, s, a);
-        if (e1) (void)hipEventRecord(e1, s);
-    }
+hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int np = 4 * (a.N - 1);
-    hipLaunchKernelGGL(lbm_perimeter_kernel<T>, dim3((np + 127) / 128), dim3(128), 0, s, a);
+    const int row_blocks = (a.N - 2 + 255) / 256;
+    const int interior_blocks = row_blocks * (a.N - 2);
+    if (e0) (void)hipEventRecord(e0, s);
+    if (!general_perimeter) {
+        const int per_blocks = (np + 255) / 256;
+        hipLaunchKernelGGL(lbm_sweep_kernel<T>, dim3(per_blocks + interior_blocks), dim3(256), 0, s, a, per_blocks,
+                           row_blocks);
+        if (e1) (void)hipEventRecord(e1, s);
+    } else {
+        if (interior_blocks > 0)
+            hipLaunchKernelGGL(lbm_bulk_kernel<T>, dim3(interior_blocks), dim3(256), 0, s, a, row_blocks);
+        if (e1) (void)hipEventRecord(e1, s);
+        hipLaunchKernelGGL(lbm_perimeter_kernel<T>, dim3((np + 127) / 128), dim3(128), 0, s, a);
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, hipStream_t s, hipEvent_t bulk_begin,
-                           hipEvent_t bulk_end) {
-    return fp64 ? step_impl<double>(a, s, bulk_begin, bulk_end) : step_impl<float>(a, s, bulk_begin, bulk_end);
+hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, bool general_perimeter, hipStream_t s,
+                           hipEvent_t sweep_begin, hipEvent_t sweep_end) {
+    return fp64 ? step_impl<double>(a, general_perimeter, s, sweep_begin, sweep_end)
+                : step_impl<float>(a, general_perimeter, s, sweep_begin, sweep_end);
 }
 
 hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, bool fp64, hipStream_t s) {
