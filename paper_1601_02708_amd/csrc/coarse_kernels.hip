@@ -3,14 +3,14 @@
 // FP64, and the two grid transfers of Sec. 6.2, item ii.
 //
 // The coarse system is tiny (at most a few 10^4 unknowns) and needs a few
-// dozen dependent passes per solve, so it is latency-bound.  The whole
-// solve is one persistent cooperative kernel: every workgroup owns a
-// contiguous range of mesh nodes, stencil products read the padded vectors
-// directly, dot products are reduced deterministically (each workgroup
-// writes a partial, every workgroup sums all partials in the same order
-// after a grid barrier), and the preconditioner P (a sparse approximate
-// inverse computed on the host) is folded into the operator A P so one
-// iteration needs two stencil products and five grid barriers.
+// dozen dependent passes per solve, so it is latency-bound.  Each thread
+// owns one mesh row; stencil products read zero-halo padded vectors; dot
+// products are reduced deterministically (each workgroup writes a partial,
+// the next kernel sums all partials in block order); the preconditioner P
+// (a sparse approximate inverse computed on the host) is folded into the
+// operator A P.  One BiCGSTAB iteration is three kernels with one reduction
+// each; a device-side flag turns the launches after convergence into
+// no-ops.
 #include "hyb_impl.h"
 
 namespace hyb {
@@ -67,80 +67,52 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     }
 }
 
-// Grid-wide barrier for a cooperative launch.  Each block publishes the
-// round it has reached in its own flag word (no contended atomics); the
-// first wave of every block then polls all flags until each has reached
-// the round.  One thread per block fences to device scope on either side
-// (release of the block's writes, acquire of the others'), bracketed by
-// workgroup barriers.  The wait is bounded: a timeout is recorded and the
-// caller abandons the solve.
-__device__ bool grid_barrier(const CoarseDev &c, unsigned &round) {
-    __syncthreads();
-    if (gridDim.x == 1) return true;
-    round += 1;
-    __shared__ int failed;
-    if (threadIdx.x < 64) {
-        if (threadIdx.x == 0) {
-            __threadfence();
-            __hip_atomic_store(&c.flags[blockIdx.x], round, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        unsigned spins = 0;
-        int st = 0;
-        for (;;) {
-            int reached = 1;
-            for (int b = threadIdx.x; b < (int)gridDim.x; b += 64)
-                reached &= __hip_atomic_load(&c.flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= round;
-            if (__all(reached)) break;
-            if (++spins > (1u << 26) ||
-                __hip_atomic_load(&c.result->barrier_timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                st = 1;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (threadIdx.x == 0) {
-            __threadfence();
-            if (st) atomicOr(&c.result->barrier_timeout, 1u);
-            failed = st;
-        }
-    }
-    __syncthreads();
-    return failed == 0;
+// Reduction partials: every kernel of the solve writes one partial per block
+// into its own slot; the next kernel sums all blocks in block order, so the
+// scalars are bit-identical in every block (deterministic).
+__device__ __forceinline__ double *slot_ptr(const CoarseDev &c, int slot) {
+    return c.partials + (size_t)slot * 4 * c.grid;
 }
-
-// Reduce NV per-thread values over the grid; the result is returned to
-// every thread.  Partials are double-buffered by `parity` so a fast block
-// cannot overwrite values a slow block is still summing.
 template <int NV>
-__device__ bool grid_sum(const CoarseDev &c, double (&v)[NV], unsigned &round, int &parity, double *lds) {
+__device__ __forceinline__ void write_partials(const CoarseDev &c, int slot, double (&v)[NV], double *lds) {
     block_sum<NV>(v, lds);
-    double *slot = c.partials + (size_t)parity * gridDim.x * 4;
     if (threadIdx.x == 0) {
+        double *s = slot_ptr(c, slot);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) slot[blockIdx.x * 4 + k] = v[k];
+        for (int k = 0; k < NV; ++k) s[k * c.grid + blockIdx.x] = v[k];
     }
-    if (!grid_barrier(c, round)) return false;
+}
+// Sums of the previous kernel's per-block partials, computed by the first
+// wave of the block (lanes stride over the blocks, then a fixed shuffle
+// tree), so every block obtains bit-identical values; broadcast via LDS.
+template <int NV>
+__device__ __forceinline__ void read_sums(const CoarseDev &c, int slot, double (&out)[NV], double *lds) {
+    if (threadIdx.x < 64) {
+        const double *s = slot_ptr(c, slot);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) s += slot[b * 4 + k];
-        v[k] = s;
+        for (int k = 0; k < NV; ++k) {
+            double acc = 0.0;
+            for (int b = threadIdx.x; b < c.grid; b += 64) acc += s[(size_t)k * c.grid + b];
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+            if (threadIdx.x == 0) lds[16 + k] = acc;
+        }
     }
-    parity ^= 1;
-    return true;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = lds[16 + k];
+    __syncthreads();
 }
 
-// b = B d(t_n) on free rows, a_ii times the prescribed value on Dirichlet rows;
-// r0 = b - A x0 (x0 = initial guess); also writes ||b||^2 partials and
-// resets the barrier flags and result block for the solve that follows.
+enum Slot { kSlotRhs = 0, kSlotA = 1, kSlotB = 2, kSlotC = 3 };
+
+// b = B d(t_n) on free rows, a_ii times the prescribed value on Dirichlet
+// rows; r0 = b - A x0 (x0 = initial guess).  Initialises the Krylov
+// vectors and the solver state for the kernels that follow.
 __global__ void __launch_bounds__(kBlock) coarse_rhs_kernel(CoarseDev c, const double *__restrict__ guess) {
-    __shared__ double lds[16];
-    if (blockIdx.x == 0) {
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) c.flags[b] = 0u;
-        if (threadIdx.x == 0) c.result->barrier_timeout = 0u;
-    }
-    double bb[1] = {0.0};
-    for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < c.n; node += gridDim.x * blockDim.x) {
+    __shared__ double lds[32];
+    double red[2] = {0.0, 0.0};
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node < c.n) {
         const int pidx = padded_index(c, node);
         const int kind = c.dkind[node];
         double b;
@@ -148,102 +120,149 @@ __global__ void __launch_bounds__(kBlock) coarse_rhs_kernel(CoarseDev c, const d
         else b = c.A9[(size_t)4 * c.n + node] * (kind == -2 ? c.outer_value : c.ufc[kind]);
         const double r0 = b - stencil_row<3>(c.A9, c.n, node, pidx, c.S, guess);
         c.r[pidx] = r0;
-        bb[0] += b * b;
+        c.rh[pidx] = r0;
+        c.p[pidx] = 0.0;
+        c.v[pidx] = 0.0;
+        c.z[pidx] = 0.0;
+        c.y[pidx] = 0.0;
+        red[0] = b * b;
+        red[1] = r0 * r0;
     }
-    block_sum<1>(bb, lds);
-    if (threadIdx.x == 0) c.partials[2 * gridDim.x * 4 + blockIdx.x] = bb[0];
+    write_partials<2>(c, kSlotRhs, red, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        KrylovState &st = *c.state;
+        st.rho = 1.0;
+        st.alpha = 1.0;
+        st.omega = 1.0;
+        st.iters = 0;
+        st.done = 0;
+    }
 }
 
-// Right-preconditioned BiCGSTAB on (A P) y = r0, x = x0 + P y.
-__global__ void __launch_bounds__(kBlock) coarse_bicgstab_kernel(CoarseDev c, const double *__restrict__ guess,
-                                                                 int max_iter, double tol) {
-    __shared__ double lds[64];
-    unsigned round = 0;
-    int parity = 0;
-    const int stride = gridDim.x * blockDim.x;
-    const int first = blockIdx.x * blockDim.x + threadIdx.x;
-
-    double bnorm2 = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) bnorm2 += c.partials[2 * gridDim.x * 4 + b];
-    const double bnorm = sqrt(bnorm2);
-
-    double red[2] = {0.0, 0.0};
-    for (int node = first; node < c.n; node += stride) {
+// Right-preconditioned BiCGSTAB on (A P) y = r0, x = x0 + P y, split into
+// three kernels per iteration so every cross-block dependency is a kernel
+// boundary (the device-scope cache maintenance happens once per launch
+// instead of once per block and barrier).  With v = A P p, z = A P v,
+// w = A P r, linearity gives
+//   p = r + beta (p - omega v),   v' = w + beta (v - omega z),
+//   s = r - alpha v',  t = A P s = w - alpha z',  z' = A P v',
+// so each kernel needs neighbour values only of vectors completed by the
+// previous kernel.
+//
+// A: sum (rh.r, r.r) of the previous iteration (or the rhs kernel); stop if
+//    ||r|| <= tol ||b||; beta; p, w = A P r, v' ; partial rh.v'.
+__global__ void __launch_bounds__(kBlock) coarse_iter_a(CoarseDev c, int first, double tol, int max_iter) {
+    __shared__ double lds[32];
+    KrylovState &st = *c.state;
+    if (st.done) return;
+    double rs[2], cs[2];
+    read_sums<2>(c, kSlotRhs, rs, lds);
+    if (!first) read_sums<2>(c, kSlotC, cs, lds);
+    const double bnorm = sqrt(rs[0]);
+    const double rho_new = first ? rs[1] : cs[0];
+    const double rnorm = sqrt(first ? rs[1] : cs[1]);
+    const bool converged = rnorm <= tol * (bnorm > 0.0 ? bnorm : 1.0);
+    const bool breakdown = !first && st.omega == 0.0;
+    if (converged || breakdown || st.iters >= max_iter || !(rnorm == rnorm)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st.done = 1;
+            st.converged = converged ? 1 : 0;
+            st.rnorm = rnorm;
+            st.bnorm = bnorm;
+        }
+        return;
+    }
+    const double beta = first ? 0.0 : (rho_new / st.rho) * (st.alpha / st.omega);
+    const double omega = st.omega;
+    double red[1] = {0.0};
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node < c.n) {
         const int pi = padded_index(c, node);
         const double r = c.r[pi];
-        c.rh[pi] = r;
-        c.p[pi] = 0.0;
-        c.v[pi] = 0.0;
-        c.y[pi] = 0.0;
-        red[0] += r * r;
-        red[1] += r * r;
+        c.p[pi] = r + beta * (c.p[pi] - omega * c.v[pi]);
+        const double w = stencil_row<kApW>(c.AP, c.n, node, pi, c.S, c.r);
+        const double vn = w + beta * (c.v[pi] - omega * c.z[pi]);
+        c.w[pi] = w;
+        c.v[pi] = vn;
+        red[0] = c.rh[pi] * vn;
     }
-    bool ok = grid_sum<2>(c, red, round, parity, lds);
-    double rnorm = sqrt(red[0]);
-    double rho = 1.0, alpha = 1.0, omega = 1.0, rho1 = red[1];
-    int it = 0;
-    const double target = tol * (bnorm > 0.0 ? bnorm : 1.0);
-    bool converged = rnorm <= target;
-    while (ok && !converged && it < max_iter) {
-        ++it;
-        const double beta = (rho1 / rho) * (alpha / omega);
-        rho = rho1;
-        for (int node = first; node < c.n; node += stride) {
-            const int pi = padded_index(c, node);
-            c.p[pi] = c.r[pi] + beta * (c.p[pi] - omega * c.v[pi]);
-        }
-        if (!(ok = grid_barrier(c, round))) break;
-        double d1[1] = {0.0};
-        for (int node = first; node < c.n; node += stride) {
-            const int pi = padded_index(c, node);
-            const double vv = stencil_row<kApW>(c.AP, c.n, node, pi, c.S, c.p);
-            c.v[pi] = vv;
-            d1[0] += c.rh[pi] * vv;
-        }
-        if (!(ok = grid_sum<1>(c, d1, round, parity, lds))) break;
-        alpha = rho / d1[0];
-        for (int node = first; node < c.n; node += stride) {
-            const int pi = padded_index(c, node);
-            c.s[pi] = c.r[pi] - alpha * c.v[pi];
-        }
-        if (!(ok = grid_barrier(c, round))) break;
-        double d2[2] = {0.0, 0.0};
-        for (int node = first; node < c.n; node += stride) {
-            const int pi = padded_index(c, node);
-            const double tt = stencil_row<kApW>(c.AP, c.n, node, pi, c.S, c.s);
-            c.t[pi] = tt;
-            d2[0] += tt * c.s[pi];
-            d2[1] += tt * tt;
-        }
-        if (!(ok = grid_sum<2>(c, d2, round, parity, lds))) break;
-        omega = d2[1] > 0.0 ? d2[0] / d2[1] : 0.0;
-        double d3[2] = {0.0, 0.0};
-        for (int node = first; node < c.n; node += stride) {
-            const int pi = padded_index(c, node);
-            const double sv = c.s[pi];
-            c.y[pi] += alpha * c.p[pi] + omega * sv;
-            const double rn = sv - omega * c.t[pi];
-            c.r[pi] = rn;
-            d3[0] += rn * rn;
-            d3[1] += c.rh[pi] * rn;
-        }
-        if (!(ok = grid_sum<2>(c, d3, round, parity, lds))) break;
-        rnorm = sqrt(d3[0]);
-        rho1 = d3[1];
-        converged = rnorm <= target;
-        if (omega == 0.0 || rho1 == 0.0) break;
+    write_partials<1>(c, kSlotA, red, lds);
+    // the state is read by every block of this kernel: it is updated by the
+    // next kernel (B), never here
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.state->rho_next = rho_new;
+}
+
+// B: alpha = rho / rh.v'; s = r - alpha v'; z' = A P v'; t = w - alpha z';
+//    partials t.s, t.t.
+__global__ void __launch_bounds__(kBlock) coarse_iter_b(CoarseDev c) {
+    __shared__ double lds[32];
+    KrylovState &st = *c.state;
+    if (st.done) return;
+    const double rho = st.rho_next;
+    double as[1];
+    read_sums<1>(c, kSlotA, as, lds);
+    const double alpha = rho / as[0];
+    double red[2] = {0.0, 0.0};
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node < c.n) {
+        const int pi = padded_index(c, node);
+        const double sv = c.r[pi] - alpha * c.v[pi];
+        const double zn = stencil_row<kApW>(c.AP, c.n, node, pi, c.S, c.v);
+        const double tv = c.w[pi] - alpha * zn;
+        c.s[pi] = sv;
+        c.z[pi] = zn;
+        c.t[pi] = tv;
+        red[0] = tv * sv;
+        red[1] = tv * tv;
     }
-    if (ok) ok = grid_barrier(c, round);
-    if (ok) {
-        for (int node = first; node < c.n; node += stride) {
-            const int pi = padded_index(c, node);
-            c.x1[pi] = guess[pi] + stencil_row<kSpaiW>(c.P, c.n, node, pi, c.S, c.y);
-        }
+    write_partials<2>(c, kSlotB, red, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st.rho = rho;
+        st.alpha = alpha;
+    }
+}
+
+// C: omega = t.s / t.t; y += alpha p + omega s; r = s - omega t;
+//    partials rh.r, r.r for the next A.
+__global__ void __launch_bounds__(kBlock) coarse_iter_c(CoarseDev c) {
+    __shared__ double lds[32];
+    KrylovState &st = *c.state;
+    if (st.done) return;
+    double bs[2];
+    read_sums<2>(c, kSlotB, bs, lds);
+    const double omega = bs[1] > 0.0 ? bs[0] / bs[1] : 0.0;
+    const double alpha = st.alpha;
+    double red[2] = {0.0, 0.0};
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node < c.n) {
+        const int pi = padded_index(c, node);
+        const double sv = c.s[pi];
+        c.y[pi] += alpha * c.p[pi] + omega * sv;
+        const double rn = sv - omega * c.t[pi];
+        c.r[pi] = rn;
+        red[0] = c.rh[pi] * rn;
+        red[1] = rn * rn;
+    }
+    write_partials<2>(c, kSlotC, red, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st.omega = omega;
+        st.iters += 1;
+    }
+}
+
+// x = x0 + P y; records iterations, convergence and ||r|| / ||b|| (the
+// state was closed by the final convergence test).
+__global__ void __launch_bounds__(kBlock) coarse_finish(CoarseDev c, const double *__restrict__ guess) {
+    const KrylovState &st = *c.state;
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node < c.n) {
+        const int pi = padded_index(c, node);
+        c.x1[pi] = guess[pi] + stencil_row<kSpaiW>(c.P, c.n, node, pi, c.S, c.y);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        c.result->iters = it;
-        c.result->converged = (ok && converged) ? 1 : 0;
-        c.result->relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
+        c.result->iters = st.iters;
+        c.result->converged = st.converged;
+        c.result->relres = st.bnorm > 0.0 ? st.rnorm / st.bnorm : st.rnorm;
     }
 }
 
@@ -293,17 +312,17 @@ hipError_t launch_coarse_rhs(const CoarseDev &c, const double *guess, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int max_iter, double tol,
+hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iterations, int max_iter, double tol,
                                hipStream_t s) {
-    if (c.grid == 1) {
-        hipLaunchKernelGGL(coarse_bicgstab_kernel, dim3(1), dim3(kBlock), 0, s, c, guess, max_iter, tol);
-        return hipGetLastError();
+    for (int it = 0; it < iterations; ++it) {
+        hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid), dim3(kBlock), 0, s, c, it == 0 ? 1 : 0, tol, max_iter);
+        hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(coarse_iter_c, dim3(c.grid), dim3(kBlock), 0, s, c);
     }
-    CoarseDev cc = c;
-    const double *g = guess;
-    void *args[] = {&cc, &g, &max_iter, &tol};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(coarse_bicgstab_kernel), dim3(c.grid),
-                                      dim3(kBlock), args, 0, s);
+    // closing convergence test after the last enqueued iteration
+    hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid), dim3(kBlock), 0, s, c, iterations == 0 ? 1 : 0, tol, 0);
+    hipLaunchKernelGGL(coarse_finish, dim3(c.grid), dim3(kBlock), 0, s, c, guess);
+    return hipGetLastError();
 }
 
 hipError_t launch_c2f(const int *idx, const double *w, int nslots, const double *xa, const double *xb, double *a,

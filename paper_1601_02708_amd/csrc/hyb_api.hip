@@ -25,10 +25,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int choose_pitch(int N) { return (int)align_up((size_t)N, 64); }
 long long choose_plane(int N, int pitch) { return (long long)align_up((size_t)N * pitch, 64) + 128; }
 
-int coarse_grid(int n) {
-    if (n <= 2048) return 1;
-    return std::min(256, (n + 255) / 256);
-}
+int coarse_grid(int n) { return (n + 255) / 256; }
 
 // node-major [n][W*W] -> offset-major [W*W][n]
 std::vector<double> offset_major(const std::vector<double> &c, int n, int w2) {
@@ -89,9 +86,9 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
         L.AP = take((size_t)L.n * kApW * kApW * 8);
         L.P = take((size_t)L.n * kSpaiW * kSpaiW * 8);
         L.dkind = take((size_t)L.n * 4);
-        L.vec = take(9 * align_up(L.vec_len * 8, kAlign));
-        L.partials = take((size_t)12 * L.grid * 8);
-        L.barrier = take((size_t)L.grid * 4);
+        L.vec = take(11 * align_up(L.vec_len * 8, kAlign));
+        L.partials = take((size_t)16 * L.grid * 8);
+        L.barrier = take(sizeof(KrylovState));
     }
     L.total = off;
     return L;
@@ -127,6 +124,8 @@ struct hyb_handle {
     // state machine
     int frozen = 0, cur = 0, jsub = 0;
     bool solved_this_step = false;
+    int last_krylov_iters = 8;          // sizes the launch budget of the next solve
+    int solve_budget = 0, solve_cap = 0;
     long long coarse_steps = 0, fine_steps = 0;
     unsigned long long seen_nonfinite = 0;
     // kernel timing (measurement only)
@@ -356,8 +355,8 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         c.outer_value = mesh->outer_value;
         c.ufc = h->ufc;
         const size_t vstride = align_up(L.vec_len * 8, kAlign);
-        double *vec[9];
-        for (int v = 0; v < 9; ++v) vec[v] = reinterpret_cast<double *>(h->ws + L.vec + v * vstride);
+        double *vec[11];
+        for (int v = 0; v < 11; ++v) vec[v] = reinterpret_cast<double *>(h->ws + L.vec + v * vstride);
         c.xn = vec[0];
         c.x1 = vec[1];
         c.r = vec[2];
@@ -367,8 +366,10 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         c.s = vec[6];
         c.t = vec[7];
         c.y = vec[8];
+        c.w = vec[9];
+        c.z = vec[10];
         c.partials = reinterpret_cast<double *>(h->ws + L.partials);
-        c.flags = reinterpret_cast<unsigned *>(h->ws + L.barrier);
+        c.state = reinterpret_cast<KrylovState *>(h->ws + L.barrier);
         c.result = h->kres;
         const std::vector<double> A9t = offset_major(ch.A9, L.n, 9), B9t = offset_major(ch.B9, L.n, 9);
         const std::vector<double> APt = offset_major(ch.AP, L.n, kApW * kApW);
@@ -427,9 +428,15 @@ int hyb_coarse_step(hyb_handle *h, int max_iter) {
     // first solve of a coarse step starts from d(t_n); later Schwarz passes
     // start from the previous pass's solution
     const double *guess = h->solved_this_step ? h->cd.x1 : h->cd.xn;
+    // iterations enqueued: a few more than the last solve needed (launches
+    // after convergence are no-ops); hyb_commit reports a solve that ran out
+    // of this budget and hyb_step then repeats the step with max_iter
+    const int budget = std::min(max_iter, std::max(6, h->last_krylov_iters + 2));
     HIP_TRY(h, launch_coarse_rhs(h->cd, guess, h->stream));
-    HIP_TRY(h, launch_coarse_solve(h->cd, guess, max_iter, 1e-14, h->stream));
+    HIP_TRY(h, launch_coarse_solve(h->cd, guess, budget, max_iter, 1e-14, h->stream));
     h->solved_this_step = true;
+    h->solve_budget = budget;
+    h->solve_cap = max_iter;
     return HYB_OK;
 }
 
@@ -478,10 +485,11 @@ int hyb_commit(hyb_handle *h) {
         h->seen_nonfinite = cnt[kCntNonfinite];
         return h->fail(HYB_ENONFINITE, "non-finite concentration in the fine subdomain; state not committed");
     }
+    if (h->solved_this_step) h->last_krylov_iters = kr.iters;
     if (h->solved_this_step && !kr.converged) {
         char buf[160];
-        std::snprintf(buf, sizeof buf, "coarse solve did not converge (%d iterations, relres %.3e%s)", kr.iters,
-                      kr.relres, kr.barrier_timeout ? ", barrier timeout" : "");
+        std::snprintf(buf, sizeof buf, "coarse solve did not converge (%d iterations, relres %.3e)", kr.iters,
+                      kr.relres);
         return h->fail(HYB_ENOCONV, buf);
     }
     h->frozen = h->cur;
@@ -496,16 +504,24 @@ int hyb_step(hyb_handle *h, int max_schwarz) {
     if (!h) return HYB_EINVAL;
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "hyb_step needs a coarse mesh");
     if (max_schwarz < 1) return h->fail(HYB_EINVAL, "max_schwarz must be >= 1");
-    h->cur = h->frozen;
-    h->jsub = 0;
-    for (int it = 0; it < max_schwarz; ++it) {
-        int rc;
-        if ((rc = hyb_interface_exchange(h, HYB_F2C)) != HYB_OK) return rc;
-        if ((rc = hyb_coarse_step(h, 200)) != HYB_OK) return rc;
-        if ((rc = hyb_interface_exchange(h, HYB_C2F)) != HYB_OK) return rc;
-        if ((rc = hyb_lbm_substeps(h, h->eta, 1)) != HYB_OK) return rc;
+    int rc = HYB_OK;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        h->cur = h->frozen;
+        h->jsub = 0;
+        h->solved_this_step = false;
+        for (int it = 0; it < max_schwarz; ++it) {
+            if ((rc = hyb_interface_exchange(h, HYB_F2C)) != HYB_OK) return rc;
+            if ((rc = hyb_coarse_step(h, 200)) != HYB_OK) return rc;
+            if ((rc = hyb_interface_exchange(h, HYB_C2F)) != HYB_OK) return rc;
+            if ((rc = hyb_lbm_substeps(h, h->eta, 1)) != HYB_OK) return rc;
+        }
+        rc = hyb_commit(h);
+        // a coarse solve that ran out of its launch budget (not of max_iter)
+        // is repeated once from the untouched committed state
+        if (rc != HYB_ENOCONV || h->solve_budget >= h->solve_cap) break;
+        h->last_krylov_iters = h->solve_cap;
     }
-    return hyb_commit(h);
+    return rc;
 }
 
 int hyb_set_boundary(hyb_handle *h, const int8_t *kind, const double *a, const double *b) {

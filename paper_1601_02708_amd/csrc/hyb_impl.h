@@ -27,13 +27,19 @@ constexpr uint16_t kMaskSolid = 1u << 15;
 // Device error counters (uint64 slots in the workspace).
 enum Counter { kCntInfeasible = 0, kCntNonfinite = 1, kCntSlots = 8 };
 
+// Scalars of the coarse BiCGSTAB shared between its kernels.
+struct KrylovState {
+    double rho, rho_next, alpha, omega, rnorm, bnorm;
+    int iters, done, converged, pad;
+};
+
 // Result block written by the coarse solver.
 struct KrylovResult {
     int iters;
     int converged;
     double relres;
-    unsigned barrier_timeout;
-    unsigned pad;
+    unsigned pad0;
+    unsigned pad1;
 };
 
 // Coarse vectors live on a padded (M+1+2H)^2 grid whose halo stays zero, so
@@ -77,7 +83,7 @@ struct CoarseDev {
     int M;
     int n;                   // (M+1)^2 mesh nodes
     int S;                   // padded row length M + 1 + 2 kCoarseHalo
-    int grid;                // workgroups of the solver
+    int grid;                // workgroups of the solver kernels (one row per thread)
     // stencils stored offset-major, coef[o * n + node], o = (dl + R) * W + (dk + R),
     // so consecutive lanes (consecutive nodes) read consecutive addresses
     const double *A9;        // [9][n] stencil of A
@@ -89,14 +95,17 @@ struct CoarseDev {
     const double *ufc;       // fine-to-coarse values
     double *xn;              // padded d(t_n)
     double *x1;              // padded new solution
-    double *r, *rh, *p, *v, *s, *t, *y;   // padded Krylov vectors
-    double *partials;        // [2][grid][4] reduction partials, then [grid] for ||b||^2
-    unsigned *flags;         // [grid] barrier arrival rounds
+    double *r, *rh, *p, *v, *s, *t, *y, *w, *z;   // padded Krylov vectors
+    double *partials;        // [4 slots][4][grid] reduction partials
+    KrylovState *state;
     KrylovResult *result;
 };
 
 hipError_t launch_coarse_rhs(const CoarseDev &c, const double *guess, hipStream_t s);
-hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int max_iter, double tol,
+// Enqueues `iterations` BiCGSTAB iterations (three kernels each; no-ops
+// once converged or past max_iter), a closing convergence test and the
+// update x1 = guess + P y.
+hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iterations, int max_iter, double tol,
                                hipStream_t s);
 
 // Interface transfers (coarse_kernels.hip)

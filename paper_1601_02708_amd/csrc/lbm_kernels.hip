@@ -130,26 +130,37 @@ __device__ __forceinline__ void perimeter_dirichlet_node(const LbmArgs &a, const
     for (int q = 0; q < kQ; ++q) dst[q * S + n] = f[q];
 }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) in
+// round-robin order.  Interior tile t of T is given to workgroup b so that
+// XCD b % 8 sweeps one contiguous eighth of the tiles in row-major order:
+// the lines a tile shares with its x- and y-neighbours (shifted pulls,
+// bounce-back reads) are then fetched into the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int T) {
+    const int x = b & 7, k = b >> 3;
+    const int q = T >> 3, r = T & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // One fine step over the whole patch in a single launch: the first
-// `per_blocks` workgroups take the 4(N-1) perimeter slots (Dirichlet
-// closure), the rest take the interior in row-major order, 256 nodes of one
-// row per workgroup, so the sweep advances through memory as a band.
+// `tiles` workgroups take the interior, 256 nodes of one row each (tile t
+// covers row 1 + t / row_blocks), the remaining workgroups take the 4(N-1)
+// perimeter slots with the Dirichlet closure.
 template <typename T>
-__global__ void __launch_bounds__(256) lbm_sweep_kernel(LbmArgs a, int per_blocks, int row_blocks) {
+__global__ void __launch_bounds__(256) lbm_sweep_kernel(LbmArgs a, int tiles, int row_blocks) {
     const int P = a.pitch;
     const int S = static_cast<int>(a.plane);
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
     const T omega = T(a.omega);
     const int b = blockIdx.x;
-    if (b < per_blocks) {
-        const int p = b * blockDim.x + threadIdx.x;
+    if (b >= tiles) {
+        const int p = (b - tiles) * blockDim.x + threadIdx.x;
         if (p < 4 * (a.N - 1)) perimeter_dirichlet_node<T>(a, src, dst, p, S, P, omega);
         return;
     }
-    const int r = b - per_blocks;
-    const int j = 1 + r / row_blocks;
-    const int i = 1 + (r % row_blocks) * blockDim.x + threadIdx.x;
+    const int t = xcd_tile(b, tiles);
+    const int j = 1 + t / row_blocks;
+    const int i = 1 + (t % row_blocks) * blockDim.x + threadIdx.x;
     if (i <= a.N - 2) interior_node<T>(a, src, dst, j * P + i, S, P, omega);
 }
 
@@ -368,8 +379,8 @@ hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hi
     if (e0) (void)hipEventRecord(e0, s);
     if (!general_perimeter) {
         const int per_blocks = (np + 255) / 256;
-        hipLaunchKernelGGL(lbm_sweep_kernel<T>, dim3(per_blocks + interior_blocks), dim3(256), 0, s, a, per_blocks,
-                           row_blocks);
+        hipLaunchKernelGGL(lbm_sweep_kernel<T>, dim3(interior_blocks + per_blocks), dim3(256), 0, s, a,
+                           interior_blocks, row_blocks);
         if (e1) (void)hipEventRecord(e1, s);
     } else {
         if (interior_blocks > 0)
