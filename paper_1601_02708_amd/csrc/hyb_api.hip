@@ -131,6 +131,7 @@ struct hyb_handle {
     // kernel timing (measurement only)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;       // pairs: [2k] begin, [2k+1] end
+    std::vector<int> ev_launches;          // sweep launches bracketed by pair k
     size_t ev_used = 0;                    // pairs recorded and not yet read
     double timed_ms = 0.0;
     long long timed_launches = 0;
@@ -145,7 +146,7 @@ struct hyb_handle {
             hipError_t e = hipEventElapsedTime(&ms, ev_pool[2 * k], ev_pool[2 * k + 1]);
             if (e != hipSuccess) return e;
             timed_ms += ms;
-            timed_launches += 1;
+            timed_launches += ev_launches[k];
         }
         ev_used = 0;
         return hipSuccess;
@@ -448,28 +449,44 @@ int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
         h->jsub = 0;
     }
     if (h->jsub + n_sub > h->eta) return h->fail(HYB_EINVAL, "fine steps would pass the end of the coarse step");
+    // kernel timing: the fused path launches only sweeps, back to back, so
+    // one event pair brackets all n_sub of them; the general path brackets
+    // each interior kernel alone (its perimeter kernel follows it)
+    const bool timed = h->timing && h->N > 2 && n_sub > 0;
+    const bool per_launch = h->any_neumann;
+    auto take_pair = [&](int launches, hipEvent_t *e0, hipEvent_t *e1) -> hipError_t {
+        if (2 * (h->ev_used + 1) > h->ev_pool.size()) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                h->ev_pool.push_back(e);
+            }
+            h->ev_launches.push_back(0);
+        }
+        *e0 = h->ev_pool[2 * h->ev_used];
+        *e1 = h->ev_pool[2 * h->ev_used + 1];
+        h->ev_launches[h->ev_used] = launches;
+        h->ev_used += 1;
+        return hipSuccess;
+    };
+    hipEvent_t g0 = nullptr, g1 = nullptr;
+    if (timed && !per_launch) {
+        HIP_TRY(h, take_pair(n_sub, &g0, &g1));
+        HIP_TRY(h, hipEventRecord(g0, h->stream));
+    }
     for (int s = 0; s < n_sub; ++s) {
         int dst = h->cur == h->frozen ? h->spare(-1) : h->spare(h->cur);
         LbmArgs a = h->lbm_args(h->cur, dst);
         a.lam = (double)(h->jsub + 1) / (double)h->eta;
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (h->timing && h->N > 2) {
-            if (2 * (h->ev_used + 1) > h->ev_pool.size()) {
-                for (int k = 0; k < 2; ++k) {
-                    hipEvent_t e;
-                    HIP_TRY(h, hipEventCreate(&e));
-                    h->ev_pool.push_back(e);
-                }
-            }
-            e0 = h->ev_pool[2 * h->ev_used];
-            e1 = h->ev_pool[2 * h->ev_used + 1];
-            h->ev_used += 1;
-        }
+        if (timed && per_launch) HIP_TRY(h, take_pair(1, &e0, &e1));
         HIP_TRY(h, launch_lbm_step(a, h->fp64, h->any_neumann, h->stream, e0, e1));
         h->cur = dst;
         h->jsub += 1;
         h->fine_steps += 1;
     }
+    if (g1) HIP_TRY(h, hipEventRecord(g1, h->stream));
     return HYB_OK;
 }
 

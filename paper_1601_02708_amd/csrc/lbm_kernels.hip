@@ -141,11 +141,151 @@ __device__ __forceinline__ int xcd_tile(int b, int T) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// Node groups: one lane owns V consecutive nodes of a row and moves each
+// population plane with one aligned V-element load and store.  All nine
+// pulls are issued without waiting for the flag word; bounce-back values
+// replace them afterwards.  V = 1 is used: on the 2048^2 and 4096^2 pore
+// workloads wider lanes (V = 2, 4 in FP32, 2 in FP64) measured equal or
+// slower.
+typedef float vec4f __attribute__((ext_vector_type(4)));
+typedef float vec2f __attribute__((ext_vector_type(2)));
+typedef double vec2d __attribute__((ext_vector_type(2)));
+typedef float vec1f __attribute__((ext_vector_type(1)));
+typedef double vec1d __attribute__((ext_vector_type(1)));
+template <typename T, int V> struct VecT;
+template <> struct VecT<float, 4> { typedef vec4f type; };
+template <> struct VecT<float, 2> { typedef vec2f type; };
+template <> struct VecT<float, 1> { typedef vec1f type; };
+template <> struct VecT<double, 2> { typedef vec2d type; };
+template <> struct VecT<double, 1> { typedef vec1d type; };
+
+// Interior group: nodes (V g .. V g + V - 1, j) of an interior row j.  For
+// every plane q the lane loads the aligned vector of row j - cy_q at its
+// own columns; the pull x - e_q needs those columns shifted by -cx_q, whose
+// one missing element comes from the neighbouring lane (wave shuffle) or,
+// at a wave edge, from a scalar load.  Bounce-back values f*_opp(x) come
+// from the aligned vector of plane opp at row j (already loaded when
+// cy_opp = 0, one predicated extra load otherwise).  Perimeter columns
+// (0 and N-1) belong to the perimeter slots and are left untouched; solid
+// nodes are written as zero.
+template <typename T, int V>
+__device__ __forceinline__ void interior_group(const LbmArgs &a, const T *__restrict__ src, T *__restrict__ dst,
+                                               int j, int g, int S, int P, T omega) {
+    typedef typename VecT<T, V>::type VT;
+    const int N = a.N;
+    const int c0 = V * g;                  // first column of the group
+    const int row = j * P;
+    const int lane = threadIdx.x & 63;
+    // flag words and velocities of the V nodes (one aligned load each);
+    // columns outside 1..N-2 act as solid here
+    unsigned m[V];
+    float vxs[V], vys[V];
+    if constexpr (V == 4) {
+        const uint2 mm = *reinterpret_cast<const uint2 *>(a.mask + row + c0);
+        m[0] = mm.x & 0xFFFFu; m[1] = mm.x >> 16; m[2] = mm.y & 0xFFFFu; m[3] = mm.y >> 16;
+    } else if constexpr (V == 2) {
+        const unsigned mm = *reinterpret_cast<const unsigned *>(a.mask + row + c0);
+        m[0] = mm & 0xFFFFu; m[1] = mm >> 16;
+    } else {
+        m[0] = a.mask[row + c0];
+    }
+    {
+        typedef typename VecT<float, V>::type VF;
+        const VF xv = *reinterpret_cast<const VF *>(a.vx + row + c0);
+        const VF yv = *reinterpret_cast<const VF *>(a.vy + row + c0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) { vxs[k] = xv[k]; vys[k] = yv[k]; }
+    }
+    bool any_fluid = false;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int c = c0 + k;
+        if (c < 1 || c > N - 2) m[k] = kMaskSolid;
+        any_fluid |= !(m[k] & kMaskSolid);
+    }
+    // every lane takes part in the shuffles below, so no early return before them
+    VT raw[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+        raw[q] = *reinterpret_cast<const VT *>(src + q * S + (j - kCy[q]) * P + c0);
+    T f[V][kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        if (kCx[q] == 0) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) f[k][q] = raw[q][k];
+        } else if (kCx[q] == 1) {       // pull from column c - 1
+            T prev = __shfl_up(raw[q][V - 1], 1, 64);
+            if (lane == 0) prev = c0 > 0 ? src[q * S + (j - kCy[q]) * P + c0 - 1] : T(0);
+            f[0][q] = prev;
+#pragma unroll
+            for (int k = 1; k < V; ++k) f[k][q] = raw[q][k - 1];
+        } else {                         // pull from column c + 1
+            T next = __shfl_down(raw[q][0], 1, 64);
+            if (lane == 63) next = src[q * S + (j - kCy[q]) * P + c0 + V];
+#pragma unroll
+            for (int k = 0; k + 1 < V; ++k) f[k][q] = raw[q][k + 1];
+            f[V - 1][q] = next;
+        }
+    }
+    if (!any_fluid) return;
+    // halfway bounce-back from the node's own opposite population
+    unsigned bb = 0;
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+        if (!(m[k] & kMaskSolid)) bb |= m[k];
+    if (bb & 0x1FEu) {
+#pragma unroll
+        for (int q = 1; q < kQ; ++q) {
+            if (!((bb >> q) & 1u)) continue;
+            const int o = kOpp[q];
+            VT own;
+            if (kCy[o] == 0) own = raw[o];
+            else own = *reinterpret_cast<const VT *>(src + o * S + row + c0);
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if ((m[k] >> q) & 1u) f[k][q] = own[k];
+        }
+    }
+    T out[V][kQ];
+    const bool edge = c0 == 0 || c0 + V > N - 1;   // group holds a perimeter or padding column
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int n = row + c0 + k;
+        if (m[k] & kMaskSolid) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) out[k][q] = T(0);
+            continue;
+        }
+        const T u = collide<T>(f[k], T(vxs[k]), T(vys[k]), omega, node_k<T>(a, n));
+        if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) out[k][q] = f[k][q];
+    }
+    if (!edge) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            VT w;
+#pragma unroll
+            for (int k = 0; k < V; ++k) w[k] = out[k][q];
+            __builtin_nontemporal_store(w, reinterpret_cast<VT *>(dst + q * S + row + c0));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const int c = c0 + k;
+            if (c < 1 || c > N - 2) continue;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) dst[q * S + row + c] = out[k][q];
+        }
+    }
+}
+
 // One fine step over the whole patch in a single launch: the first
-// `tiles` workgroups take the interior, 256 nodes of one row each (tile t
-// covers row 1 + t / row_blocks), the remaining workgroups take the 4(N-1)
-// perimeter slots with the Dirichlet closure.
-template <typename T>
+// `tiles` workgroups take the interior rows, 256 lanes x V nodes of one
+// row each (tile t covers row 1 + t / row_blocks), the remaining workgroups
+// take the 4(N-1) perimeter slots with the Dirichlet closure.
+template <typename T, int V>
 __global__ void __launch_bounds__(256) lbm_sweep_kernel(LbmArgs a, int tiles, int row_blocks) {
     const int P = a.pitch;
     const int S = static_cast<int>(a.plane);
@@ -160,8 +300,10 @@ __global__ void __launch_bounds__(256) lbm_sweep_kernel(LbmArgs a, int tiles, in
     }
     const int t = xcd_tile(b, tiles);
     const int j = 1 + t / row_blocks;
-    const int i = 1 + (t % row_blocks) * blockDim.x + threadIdx.x;
-    if (i <= a.N - 2) interior_node<T>(a, src, dst, j * P + i, S, P, omega);
+    const int g = (t % row_blocks) * blockDim.x + threadIdx.x;
+    // groups past the last column still join the wave's shuffles (their
+    // loads stay inside the row pitch, which is a multiple of 64 elements)
+    if (V * g < P) interior_group<T, V>(a, src, dst, j, g, S, P, omega);
 }
 
 // Interior only (used with the general perimeter kernel when some slots
@@ -371,6 +513,10 @@ __global__ void __launch_bounds__(256) lbm_conc_kernel(LbmArgs a, double *__rest
     }
 }
 
+// nodes per lane of the interior sweep (see VecT)
+#ifndef SWEEP_V
+#define SWEEP_V(T) 1
+#endif
 template <typename T>
 hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int np = 4 * (a.N - 1);
@@ -378,9 +524,12 @@ hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hi
     const int interior_blocks = row_blocks * (a.N - 2);
     if (e0) (void)hipEventRecord(e0, s);
     if (!general_perimeter) {
+        constexpr int V = SWEEP_V(T);
+        const int vrow_blocks = ((a.N + V - 1) / V + 255) / 256;     // groups cover columns 0..N-1
+        const int vtiles = vrow_blocks * (a.N - 2);
         const int per_blocks = (np + 255) / 256;
-        hipLaunchKernelGGL(lbm_sweep_kernel<T>, dim3(interior_blocks + per_blocks), dim3(256), 0, s, a,
-                           interior_blocks, row_blocks);
+        auto kernel = lbm_sweep_kernel<T, V>;
+        hipLaunchKernelGGL(kernel, dim3(vtiles + per_blocks), dim3(256), 0, s, a, vtiles, vrow_blocks);
         if (e1) (void)hipEventRecord(e1, s);
     } else {
         if (interior_blocks > 0)

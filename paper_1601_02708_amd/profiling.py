@@ -1,0 +1,82 @@
+"""Summarise rocprofv3 output of bench.py runs into the short text records
+kept under profiles/ (run on the host after the GPU job).
+
+    python -m paper_1601_02708_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_1601_02708_amd.profiling traffic <fetch_counter_collection.csv> \
+        <write_counter_collection.csv> <out.json> <workload> <precision> <copy_mib> "<commands>"
+
+The traffic record scales the FETCH_SIZE / WRITE_SIZE counters of the
+lattice-sweep kernel by what the same counters read for the plain copy
+bench.py --copy-mib performs in the same run (a copy of known size), and
+stores the sweep kernel's source hash so that bench.py drops the figure
+once the kernel changes.
+"""
+import csv
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SRC = os.path.join(ROOT, "paper_1601_02708_amd", "csrc", "lbm_kernels.hip")
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def stats(csv_path, out_path, command):
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = ["# rocprofv3 kernel statistics", "", f"command: `{command}`", "",
+             "| kernel | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    open(out_path, "w").write("\n".join(lines) + "\n")
+
+
+def _per_kernel(path, counter):
+    out = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_csv, write_csv, out_path, workload, precision, copy_mib, commands):
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(write_csv, "WRITE_SIZE")
+    tname = "float" if precision == "fp32" else "double"
+    sweep = [k for k in fetch if "lbm_sweep_kernel" in k and f"<{tname}" in k]
+    if not sweep:
+        raise SystemExit("no sweep kernel in the counter file")
+    # the calibration copy is the largest copyBuffer dispatch; it reads and
+    # writes copy_mib MiB each
+    copy_f = max(v for k, vs in fetch.items() if "copyBuffer" in k for v in vs)
+    copy_w = max(v for k, vs in write.items() if "copyBuffer" in k for v in vs)
+    copy_bytes_kib = float(copy_mib) * 1024.0
+    f_scale = copy_bytes_kib / copy_f
+    w_scale = copy_bytes_kib / copy_w
+    k = sweep[0]
+    f = statistics.mean(fetch[k])
+    w = statistics.mean(write[k])
+    rec = {
+        "kernel": k[:120], "workload": workload, "precision": precision, "kernel_sha": kernel_hash(),
+        "fetch_kib_per_launch": f, "write_kib_per_launch": w,
+        "copy_kib": copy_bytes_kib, "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+        "fetch_scale": f_scale, "write_scale": w_scale,
+        "bytes_per_launch": int(round((f * f_scale + w * w_scale) * 1024)),
+        "launches": len(fetch[k]), "commands": commands,
+    }
+    json.dump(rec, open(out_path, "w"), indent=1)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:9])
