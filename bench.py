@@ -34,10 +34,12 @@ def kernel_hash():
 
 
 def sweep_bytes(problem, elem_bytes):
-    """Algorithmic HBM bytes of one lattice sweep (every node of the patch):
-    per fluid node 9 population loads + 9 stores, 2 FP32 velocity
+    """Algorithmic HBM bytes of one lattice-sweep launch (every node of the
+    patch): per fluid node 9 population loads + 9 stores, 2 FP32 velocity
     components and the 16-bit flag word; a solid node reads only its flag
-    word; each perimeter slot also reads its two FP64 interface values."""
+    word; each perimeter slot also reads its two FP64 interface values.
+    The two-step launch needs the same bytes (the state between its two
+    fine steps never leaves the chip), for twice the lattice updates."""
     N = problem.cfg.N
     fluid = int((problem.solid == 0).sum())
     solid = N * N - fluid
@@ -45,20 +47,31 @@ def sweep_bytes(problem, elem_bytes):
     return fluid * per_fluid + solid * 2 + 4 * (N - 1) * 16, fluid, solid, per_fluid
 
 
-def load_traffic(workload, precision):
+def kernel_name(elem_bytes, steps_per_launch):
+    t = "float" if elem_bytes == 4 else "double"
+    if steps_per_launch == 2:
+        return f"lbm_sweep2_kernel<{t}, 64, {16 if elem_bytes == 4 else 8}>"
+    return f"lbm_sweep_kernel<{t}, 1>"
+
+
+def load_traffic(workload, precision, kernel):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
+    record of this kernel, or None when there is none or the kernel source
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_sha") != kernel_hash():
-        return None           # kernel changed since the counters were taken
+    if rec.get("kernel_sha") != kernel_hash() or kernel.split("<")[0] + "<" not in rec.get("kernel", ""):
+        return None
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(problem, precision, steps, warmup, timing=True):
+def run_gpu(problem, precision, steps, warmup, steps_per_launch=2, timing=True):
     import torch
     from paper_1601_02708_amd import hyb
     g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
+    g.set_steps_per_launch(steps_per_launch)
     mi = problem.cfg.max_iter
     for _ in range(warmup):
         g.step(mi)
@@ -110,6 +123,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pore2048")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2],
+                    help="fine steps per lattice-sweep launch (2: temporally blocked pairs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the second-precision run")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -132,13 +147,14 @@ def main():
     elem = 4 if args.precision == "fp32" else 8
     print(f"[bench] {cfg.name} {args.precision}: {args.warmup} warmup + {args.steps} timed coarse steps",
           file=sys.stderr, flush=True)
-    g, wall, gpu_ms, kms, launches, st = run_gpu(problem, args.precision, args.steps, args.warmup)
+    spl = args.steps_per_launch
+    g, wall, gpu_ms, kms, launches, st = run_gpu(problem, args.precision, args.steps, args.warmup, spl)
     ms_step = gpu_ms / args.steps
     value = lups_step * args.steps / (gpu_ms / 1e3) / 1e6
     bbytes, nfl, nsol, per_fluid = sweep_bytes(problem, elem)
     avg_kernel_ms = kms / max(launches, 1)
     achieved = bbytes / (avg_kernel_ms / 1e3) / 1e9
-    traffic = load_traffic(cfg.name, args.precision)
+    traffic = load_traffic(cfg.name, args.precision, kernel_name(elem, spl))
     res = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -166,7 +182,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"lbm_sweep_kernel<{'float' if elem == 4 else 'double'}>",
+            "kernel": kernel_name(elem, spl),
+            "fine_steps_per_launch": spl if cfg.eta % spl == 0 else None,
             "algorithmic_bytes_per_launch": bbytes,
             "avg_launch_ms": round(avg_kernel_ms, 5),
             "launches_timed": launches,
@@ -180,7 +197,7 @@ def main():
     if not args.no_compare:
         other = "fp64" if args.precision == "fp32" else "fp32"
         print(f"[bench] comparison run {other}", file=sys.stderr, flush=True)
-        g2, _, gpu_ms2, kms2, launches2, _ = run_gpu(problem, other, args.steps, args.warmup)
+        g2, _, gpu_ms2, kms2, launches2, _ = run_gpu(problem, other, args.steps, args.warmup, spl)
         u1, u2 = g.concentration(), g2.concentration()
         fluid = problem.solid == 0
         ref, low = (u2, u1) if other == "fp64" else (u1, u2)

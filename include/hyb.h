@@ -176,12 +176,22 @@ int hyb_set_populations(hyb_handle *h, const double *f);
 
 int hyb_stats(hyb_handle *h, hyb_run_stats *out);
 
-/* Measurement: while enabled, each fine step records a pair of HIP events
- * on the handle's stream around its lattice-sweep kernel (the single launch
- * that updates every node when all perimeter slots are Dirichlet, else the
- * interior-node kernel); hyb_kernel_time returns the summed elapsed
- * milliseconds and the number of timed launches since the last call, and
- * synchronises. */
+/* Fine steps per lattice-sweep launch (1 or 2; default 2).  With 2, while
+ * every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine steps in
+ * pairs, each pair in one temporally blocked launch (the state between the
+ * two steps stays on chip); an odd remainder, and every step when some
+ * slot is Neumann, uses the single-step sweep.  Results agree with the
+ * single-step path to rounding (same operations per node).  Returns
+ * HYB_EINVAL for other values.  Takes effect at the next hyb_lbm_substeps. */
+int hyb_set_steps_per_launch(hyb_handle *h, int steps);
+
+/* Measurement: while enabled, every hyb_lbm_substeps call records HIP
+ * events on the handle's stream around its lattice-sweep kernels: one pair
+ * around the whole batch when all perimeter slots are Dirichlet (only sweep
+ * kernels are launched, back to back), else one pair around each
+ * interior-node kernel.  hyb_kernel_time returns the summed elapsed
+ * milliseconds and the number of sweep launches they cover since the last
+ * call, and synchronises. */
 int hyb_kernel_timing(hyb_handle *h, int enable);
 int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches);
 

@@ -115,6 +115,7 @@ struct hyb_handle {
     double *bc_a = nullptr, *bc_b = nullptr;
     bool kinds_set = false;
     bool any_neumann = false;
+    int steps_per_launch = 2;          // 2: two-step sweep when every slot is Dirichlet
     int *c2f_idx = nullptr, *fc_idx = nullptr;
     double *c2f_w = nullptr, *fc_w = nullptr, *ufc = nullptr;
     int nfc = 0;
@@ -449,12 +450,14 @@ int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
         h->jsub = 0;
     }
     if (h->jsub + n_sub > h->eta) return h->fail(HYB_EINVAL, "fine steps would pass the end of the coarse step");
-    // kernel timing: the fused path launches only sweeps, back to back, so
-    // one event pair brackets all n_sub of them; the general path brackets
-    // each interior kernel alone (its perimeter kernel follows it)
+    // kernel timing: when every perimeter slot is Dirichlet only sweep
+    // kernels are launched, back to back, so one event pair brackets the
+    // whole batch; the general path brackets each interior kernel alone
+    // (its perimeter kernel follows it)
     const bool timed = h->timing && h->N > 2 && n_sub > 0;
-    const bool per_launch = h->any_neumann;
-    auto take_pair = [&](int launches, hipEvent_t *e0, hipEvent_t *e1) -> hipError_t {
+    const bool general = h->any_neumann;
+    const bool fuse2 = !general && h->steps_per_launch == 2;
+    auto take_pair = [&](hipEvent_t *e0, hipEvent_t *e1) -> hipError_t {
         if (2 * (h->ev_used + 1) > h->ev_pool.size()) {
             for (int k = 0; k < 2; ++k) {
                 hipEvent_t e;
@@ -466,25 +469,38 @@ int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
         }
         *e0 = h->ev_pool[2 * h->ev_used];
         *e1 = h->ev_pool[2 * h->ev_used + 1];
-        h->ev_launches[h->ev_used] = launches;
+        h->ev_launches[h->ev_used] = 0;
         h->ev_used += 1;
         return hipSuccess;
     };
     hipEvent_t g0 = nullptr, g1 = nullptr;
-    if (timed && !per_launch) {
-        HIP_TRY(h, take_pair(n_sub, &g0, &g1));
+    size_t gslot = 0;
+    if (timed && !general) {
+        HIP_TRY(h, take_pair(&g0, &g1));
+        gslot = h->ev_used - 1;
         HIP_TRY(h, hipEventRecord(g0, h->stream));
     }
-    for (int s = 0; s < n_sub; ++s) {
-        int dst = h->cur == h->frozen ? h->spare(-1) : h->spare(h->cur);
+    for (int s = 0; s < n_sub;) {
+        const int dst = h->cur == h->frozen ? h->spare(-1) : h->spare(h->cur);
         LbmArgs a = h->lbm_args(h->cur, dst);
         a.lam = (double)(h->jsub + 1) / (double)h->eta;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed && per_launch) HIP_TRY(h, take_pair(1, &e0, &e1));
-        HIP_TRY(h, launch_lbm_step(a, h->fp64, h->any_neumann, h->stream, e0, e1));
+        const int take = (fuse2 && n_sub - s >= 2) ? 2 : 1;
+        if (take == 2) {
+            a.lam2 = (double)(h->jsub + 2) / (double)h->eta;
+            HIP_TRY(h, launch_lbm_step2(a, h->fp64, h->stream));
+        } else {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed && general) {
+                HIP_TRY(h, take_pair(&e0, &e1));
+                h->ev_launches[h->ev_used - 1] = 1;
+            }
+            HIP_TRY(h, launch_lbm_step(a, h->fp64, general, h->stream, e0, e1));
+        }
+        if (g0) h->ev_launches[gslot] += 1;
         h->cur = dst;
-        h->jsub += 1;
-        h->fine_steps += 1;
+        h->jsub += take;
+        h->fine_steps += take;
+        s += take;
     }
     if (g1) HIP_TRY(h, hipEventRecord(g1, h->stream));
     return HYB_OK;
@@ -639,6 +655,13 @@ int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
     out->krylov_relres = kr.relres;
     out->coarse_steps = h->coarse_steps;
     out->fine_steps = h->fine_steps;
+    return HYB_OK;
+}
+
+int hyb_set_steps_per_launch(hyb_handle *h, int steps) {
+    if (!h) return HYB_EINVAL;
+    if (steps != 1 && steps != 2) return h->fail(HYB_EINVAL, "steps per launch must be 1 or 2");
+    h->steps_per_launch = steps;
     return HYB_OK;
 }
 

@@ -66,6 +66,7 @@ struct LbmArgs {
     const double *bc_a;
     const double *bc_b;
     double lam;              // j / eta of the step being taken
+    double lam2;             // (j + 1) / eta: second step of a two-step launch
     int clamp;
     unsigned long long *counters;
 };
@@ -76,6 +77,9 @@ struct LbmArgs {
 // Dirichlet closure).  The optional events bracket the interior sweep.
 hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, bool general_perimeter, hipStream_t s,
                            hipEvent_t sweep_begin = nullptr, hipEvent_t sweep_end = nullptr);
+// Two fine steps in one launch (Dirichlet closure on every perimeter slot):
+// a.src holds f*(j), a.dst receives f*(j+2); u^p at a.lam, then a.lam2.
+hipError_t launch_lbm_step2(const LbmArgs &a, bool fp64, hipStream_t s);
 hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, bool fp64, hipStream_t s);
 hipError_t launch_concentration(const LbmArgs &a, double *out, bool fp64, hipStream_t s);
 

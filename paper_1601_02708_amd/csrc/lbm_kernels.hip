@@ -463,6 +463,170 @@ __global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Two fine steps per launch (temporal blocking), Dirichlet closure only.
+//
+// A workgroup owns a TW x TH tile of the patch.  First half: every node of
+// the tile grown by one ring (clipped to the patch) takes fine step j+1
+// from the source buffer; the results stay in LDS.  Second half: the
+// tile's own nodes take step j+2 from LDS and go to the destination
+// buffer.  Per node the arithmetic is that of the single-step sweep
+// (pull, halfway bounce-back, eq. (LBM_Dir) closure at perimeter nodes
+// with u^p at lam = (j+1)/eta, then (j+2)/eta, collision).  Ring nodes are
+// computed by every tile that borders them, so only the tile that owns a
+// node counts its infeasible closures and non-finite values.  HBM traffic
+// for two steps is one read of the state (the ring-2 halo is mostly served
+// by L2) and one write.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int perimeter_slot(int N, int i, int j) {
+    if (j == 0) return i;
+    if (j == N - 1) return N + i;
+    if (i == 0) return 2 * N + j - 1;
+    return 3 * N - 2 + j - 1;
+}
+
+__device__ __forceinline__ unsigned outside_bits(int N, int i, int j) {
+    unsigned u = 0;
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) {
+        const int si = i - kCx[q], sj = j - kCy[q];
+        if (si < 0 || si >= N || sj < 0 || sj >= N) u |= 1u << q;
+    }
+    return u;
+}
+
+// eq. (LBM_Dir) on populations held in T, sums in FP64 (the same
+// operations, in the same order, as perimeter_dirichlet_node)
+template <typename T>
+__device__ __forceinline__ bool dirichlet_close(const LbmArgs &a, T (&f)[kQ], unsigned unknown, int p,
+                                                double lam) {
+    double known = 0.0, wsum = 0.0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        if ((unknown >> q) & 1u) wsum += kW[q];
+        else known += double(f[q]);
+    }
+    double R = (1.0 - lam) * a.bc_a[p] + lam * a.bc_b[p] - known;
+    const bool bad = R < 0.0;
+    if (bad && a.clamp) R = 0.0;
+    const double scale = R / wsum;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+        if ((unknown >> q) & 1u) f[q] = T(kW[q] * scale);
+    return bad;
+}
+
+template <typename T, int TW, int TH>
+__global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
+    constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
+    constexpr int ROUNDS1 = (R1 + 255) / 256;
+    static_assert((TW * TH) % 256 == 0 && 256 % TW == 0, "second half: whole rows per wave round");
+    constexpr int ROUNDS2 = TW * TH / 256;
+    __shared__ T lds[kQ][H1][W1];
+
+    const int N = a.N;
+    const int P = a.pitch;
+    const int S = static_cast<int>(a.plane);
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const T omega = T(a.omega);
+    const int t = xcd_tile(blockIdx.x, tiles);
+    const int x0 = (t % tiles_x) * TW;
+    const int y0 = (t / tiles_x) * TH;
+
+    // ---- first half: step j+1 on the tile and its ring, into LDS --------
+    T f[ROUNDS1][kQ];
+    unsigned m[ROUNDS1];
+    bool live[ROUNDS1];
+#pragma unroll
+    for (int k = 0; k < ROUNDS1; ++k) {
+        const int idx = threadIdx.x + 256 * k;
+        const int r = idx / W1, c = idx - (idx / W1) * W1;
+        const int i = x0 - 1 + c, j = y0 - 1 + r;
+        live[k] = idx < R1 && i >= 0 && j >= 0 && i < N && j < N;
+        m[k] = kMaskSolid;
+        if (live[k]) {
+            m[k] = a.mask[j * P + i];
+            // pulls issued before the flag word is known; upstream nodes
+            // outside the patch are clamped onto it (values then unused)
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int si = min(max(i - kCx[q], 0), N - 1);
+                const int sj = min(max(j - kCy[q], 0), N - 1);
+                f[k][q] = src[q * S + sj * P + si];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ROUNDS1; ++k) {
+        if (!live[k] || (m[k] & kMaskSolid)) continue;
+        const int idx = threadIdx.x + 256 * k;
+        const int r = idx / W1, c = idx - (idx / W1) * W1;
+        const int i = x0 - 1 + c, j = y0 - 1 + r;
+        const int n = j * P + i;
+        const bool owned = r >= 1 && r <= TH && c >= 1 && c <= TW;
+        if (m[k] & 0x1FEu) {
+#pragma unroll
+            for (int q = 1; q < kQ; ++q)
+                if ((m[k] >> q) & 1u) f[k][q] = src[kOpp[q] * S + n];
+        }
+        if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
+            const bool bad = dirichlet_close<T>(a, f[k], outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
+            if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+        }
+        const T u = collide<T>(f[k], T(a.vx[n]), T(a.vy[n]), omega, node_k<T>(a, n));
+        if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[k][q];
+    }
+
+    // flags and velocities of the owned nodes, fetched before the barrier
+    unsigned m2[ROUNDS2];
+    float vx2[ROUNDS2], vy2[ROUNDS2];
+#pragma unroll
+    for (int k = 0; k < ROUNDS2; ++k) {
+        const int idx = threadIdx.x + 256 * k;
+        const int i = x0 + idx % TW, j = y0 + idx / TW;
+        m2[k] = kMaskSolid;
+        vx2[k] = vy2[k] = 0.f;
+        if (i < N && j < N) {
+            const int n = j * P + i;
+            m2[k] = a.mask[n];
+            vx2[k] = a.vx[n];
+            vy2[k] = a.vy[n];
+        }
+    }
+    __syncthreads();
+
+    // ---- second half: step j+2 on the owned nodes, from LDS ------------
+#pragma unroll
+    for (int k = 0; k < ROUNDS2; ++k) {
+        if (m2[k] & kMaskSolid) continue;
+        const int idx = threadIdx.x + 256 * k;
+        const int r = idx / TW, c = idx % TW;
+        const int i = x0 + c, j = y0 + r;
+        const int n = j * P + i;
+        const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
+        const unsigned unknown = perim ? outside_bits(N, i, j) : 0u;
+        T g[kQ];
+        g[0] = lds[0][r + 1][c + 1];
+#pragma unroll
+        for (int q = 1; q < kQ; ++q) {
+            if ((m2[k] >> q) & 1u) g[q] = lds[kOpp[q]][r + 1][c + 1];
+            else if ((unknown >> q) & 1u) g[q] = T(0);
+            else g[q] = lds[q][r + 1 - kCy[q]][c + 1 - kCx[q]];
+        }
+        if (perim) {
+            const bool bad = dirichlet_close<T>(a, g, unknown, perimeter_slot(N, i, j), a.lam2);
+            if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+        }
+        const T u = collide<T>(g, T(vx2[k]), T(vy2[k]), omega, node_k<T>(a, n));
+        if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(g[q], &dst[q * S + n]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // initial state: f*(0) = collide(f^eq(u0)) at fluid nodes (Sec. 6.2, item i)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -540,7 +704,26 @@ hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hi
     return hipGetLastError();
 }
 
+// tile shape of the two-step sweep: LDS holds 9 planes of (TW+2) x (TH+2)
+// values, 42.8 KB in FP32 and 47.5 KB in FP64 (three workgroups per CU)
+template <typename T> struct Sweep2Tile;
+template <> struct Sweep2Tile<float> { static constexpr int TW = 64, TH = 16; };
+template <> struct Sweep2Tile<double> { static constexpr int TW = 64, TH = 8; };
+
+template <typename T>
+hipError_t step2_impl(const LbmArgs &a, hipStream_t s) {
+    constexpr int TW = Sweep2Tile<T>::TW, TH = Sweep2Tile<T>::TH;
+    const int tx = (a.N + TW - 1) / TW, ty = (a.N + TH - 1) / TH;
+    auto kernel = lbm_sweep2_kernel<T, TW, TH>;
+    hipLaunchKernelGGL(kernel, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_lbm_step2(const LbmArgs &a, bool fp64, hipStream_t s) {
+    return fp64 ? step2_impl<double>(a, s) : step2_impl<float>(a, s);
+}
 
 hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, bool general_perimeter, hipStream_t s,
                            hipEvent_t sweep_begin, hipEvent_t sweep_end) {

@@ -65,6 +65,7 @@ SIGNATURES = {
     "hyb_set_populations": (_i, [_P, _P]),
     "hyb_stats": (_i, [_P, _P]),
     "hyb_layout": (_i, [_P, _P, _P]),
+    "hyb_set_steps_per_launch": (_i, [_P, _i]),
     "hyb_kernel_timing": (_i, [_P, _i]),
     "hyb_kernel_time": (_i, [_P, _P, _P]),
     "hyb_destroy": (None, [_P]),
@@ -230,6 +231,9 @@ class Hybrid:
         s = HybRunStats()
         self._check(load().hyb_stats(self.h, ctypes.addressof(s)))
         return {k: getattr(s, k) for k, _ in HybRunStats._fields_}
+
+    def set_steps_per_launch(self, steps):
+        return self._check(load().hyb_set_steps_per_launch(self.h, int(steps)))
 
     def kernel_timing(self, enable=True):
         return self._check(load().hyb_kernel_timing(self.h, int(enable)))

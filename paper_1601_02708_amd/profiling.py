@@ -50,7 +50,10 @@ def traffic(fetch_csv, write_csv, out_path, workload, precision, copy_mib, comma
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
     tname = "float" if precision == "fp32" else "double"
-    sweep = [k for k in fetch if "lbm_sweep_kernel" in k and f"<{tname}" in k]
+    # the dominant sweep kernel: the two-step launch when it ran, else the
+    # single-step one
+    sweep = [k for k in fetch if "lbm_sweep2_kernel" in k and f"<{tname}" in k]
+    sweep = sweep or [k for k in fetch if "lbm_sweep_kernel" in k and f"<{tname}" in k]
     if not sweep:
         raise SystemExit("no sweep kernel in the counter file")
     # the calibration copy is the largest copyBuffer dispatch; it reads and

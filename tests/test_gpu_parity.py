@@ -118,6 +118,62 @@ def test_substeps_many_commits_fp64(orc):
     assert rel_l2(g.concentration(), lat.concentration(f), fluid) <= 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("N,clamp,k_field,eta", [(67, 0, False, 5), (130, 1, True, 4), (3, 0, False, 3),
+                                                  (4, 0, True, 2), (200, 0, False, 7), (65, 1, False, 6)])
+def test_two_step_sweep(orc, precision, N, clamp, k_field, eta):
+    """Fine steps taken in temporally blocked pairs (two steps per launch,
+    plus a single step for an odd count) against the oracle and against the
+    single-step sweep: random states, solids, every perimeter slot
+    Dirichlet with interface values that make some closures infeasible.
+    Sizes cover several tiles with ragged edges in x and y, and lattices
+    smaller than one tile."""
+    hyb = _gpu()
+    solid, vx, vy, kf, tau = _lattice_case(N, 300 + N, porosity=0.75 if N > 8 else 1.0, k_field=k_field)
+    rng = np.random.default_rng(3 * N + eta)
+    P = 4 * (N - 1)
+    a = rng.uniform(0.2, 1.5, P)
+    b = rng.uniform(0.2, 1.5, P)
+    f0 = inputs.random_populations(N, 11 + N, lo=0.05, hi=0.4)
+    if solid is not None:
+        f0[:, solid != 0] = 0.0
+    lat = orc.Lattice(N, tau, vx.astype(np.float64), vy.astype(np.float64), solid=solid,
+                      k=kf if k_field else 1e-3, clamp=clamp)
+    f = f0 if precision == "fp64" else f0.astype(np.float32).astype(np.float64)
+    bad = 0
+    for j in range(1, eta + 1):
+        lam = j / eta
+        f, nb = lat.substep(f, (1 - lam) * a + lam * b)
+        bad += nb
+    assert bad > 0                      # the infeasible branch is exercised
+    got = {}
+    for spl in (1, 2):
+        g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta,
+                       precision=precision, tau=tau, solid=solid, k=0.0 if k_field else 1e-3, k_field=kf,
+                       bc_clamp=clamp)
+        g.set_steps_per_launch(spl)
+        g.set_populations(f0)
+        g.set_boundary(a, b)
+        g.lbm_substeps(eta, restart=1)
+        g.commit()
+        got[spl] = g.get_populations()
+        assert g.stats()["infeasible"] == bad, spl
+        err = np.abs(got[spl] - f).max() / np.abs(f).max()
+        assert err <= (1e-13 if precision == "fp64" else 2e-6), (spl, err)
+    d = np.abs(got[2] - got[1]).max() / np.abs(got[1]).max()
+    assert d <= (1e-14 if precision == "fp64" else 1e-6), d
+
+
+def test_steps_per_launch_rejects_other_values():
+    hyb = _gpu()
+    N = 8
+    z = np.zeros((N, N))
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.1, eta=2)
+    for bad in (0, 3, -1):
+        with pytest.raises(hyb.HybError):
+            g.set_steps_per_launch(bad)
+
+
 @pytest.mark.parametrize("clamp", [0, 1])
 def test_paper_example_e01(orc, clamp):
     """Sec. 4.1.2 example on the GPU (Neumann at x = 0, Dirichlet 0
