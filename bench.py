@@ -50,7 +50,7 @@ def sweep_bytes(problem, elem_bytes):
 def kernel_name(elem_bytes, steps_per_launch):
     t = "float" if elem_bytes == 4 else "double"
     if steps_per_launch == 2:
-        return f"lbm_sweep2_kernel<{t}, 64, {16 if elem_bytes == 4 else 8}>"
+        return f"lbm_sweep2_kernel<{t}, 64, 8>"
     return f"lbm_sweep_kernel<{t}, 1>"
 
 
@@ -153,7 +153,11 @@ def main():
     value = lups_step * args.steps / (gpu_ms / 1e3) / 1e6
     bbytes, nfl, nsol, per_fluid = sweep_bytes(problem, elem)
     avg_kernel_ms = kms / max(launches, 1)
-    achieved = bbytes / (avg_kernel_ms / 1e3) / 1e9
+    # algorithmic bytes per launch = bytes per fluid lattice update x the
+    # updates one launch performs (spl fine steps over every fluid node)
+    steps_launch = spl if cfg.eta % spl == 0 else cfg.eta / -(-cfg.eta // spl)
+    launch_bytes = bbytes * steps_launch
+    achieved = launch_bytes / (avg_kernel_ms / 1e3) / 1e9
     traffic = load_traffic(cfg.name, args.precision, kernel_name(elem, spl))
     res = {
         "metric": METRIC,
@@ -183,11 +187,12 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "kernel": kernel_name(elem, spl),
-            "fine_steps_per_launch": spl if cfg.eta % spl == 0 else None,
-            "algorithmic_bytes_per_launch": bbytes,
+            "fine_steps_per_launch": steps_launch,
+            "fluid_updates_per_launch": int(nfl * steps_launch),
+            "bytes_per_fluid_update": round(bbytes / nfl, 2),
+            "algorithmic_bytes_per_launch": int(launch_bytes),
             "avg_launch_ms": round(avg_kernel_ms, 5),
             "launches_timed": launches,
-            "bytes_per_fluid_update": per_fluid,
         },
         "sweep_time_frac": round(kms / gpu_ms, 4),
         "wall_s": round(wall, 3),
@@ -207,7 +212,8 @@ def main():
         k2 = kms2 / max(launches2, 1)
         res[other] = {"value": round(lups_step * args.steps / (gpu_ms2 / 1e3) / 1e6, 1), "unit": "MLUPS",
                       "ms_per_step": round(gpu_ms2 / args.steps, 4),
-                      "sweep_achieved_gbs": round(b2 / (k2 / 1e3) / 1e9, 1),
+                      "sweep_kernel": kernel_name(e2, spl),
+                      "sweep_achieved_gbs": round(b2 * steps_launch / (k2 / 1e3) / 1e9, 1),
                       "sweep_avg_launch_ms": round(k2, 5)}
         res["fp32_rel_l2_vs_fp64"] = err
         del g2

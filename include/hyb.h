@@ -180,9 +180,11 @@ int hyb_stats(hyb_handle *h, hyb_run_stats *out);
  * every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine steps in
  * pairs, each pair in one temporally blocked launch (the state between the
  * two steps stays on chip); an odd remainder, and every step when some
- * slot is Neumann, uses the single-step sweep.  Results agree with the
- * single-step path to rounding (same operations per node).  Returns
- * HYB_EINVAL for other values.  Takes effect at the next hyb_lbm_substeps. */
+ * slot is Neumann, or when a population buffer reaches 4 GiB (the
+ * two-step kernel uses 32-bit byte offsets), uses the single-step sweep.
+ * Results agree with the single-step path to rounding (same operations
+ * per node).  Returns HYB_EINVAL for other values.  Takes effect at the
+ * next hyb_lbm_substeps. */
 int hyb_set_steps_per_launch(hyb_handle *h, int steps);
 
 /* Measurement: while enabled, every hyb_lbm_substeps call records HIP

@@ -456,7 +456,10 @@ int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
     // (its perimeter kernel follows it)
     const bool timed = h->timing && h->N > 2 && n_sub > 0;
     const bool general = h->any_neumann;
-    const bool fuse2 = !general && h->steps_per_launch == 2;
+    // the two-step kernel addresses a population buffer with 32-bit byte
+    // offsets, so it serves buffers below 4 GiB (N up to about 11500 in FP64)
+    const bool small_buf = 9.0 * (double)h->lay.plane * (h->fp64 ? 8.0 : 4.0) < 4294967295.0;
+    const bool fuse2 = !general && h->steps_per_launch == 2 && small_buf;
     auto take_pair = [&](hipEvent_t *e0, hipEvent_t *e1) -> hipError_t {
         if (2 * (h->ev_used + 1) > h->ev_pool.size()) {
             for (int k = 0; k < 2; ++k) {

@@ -515,65 +515,119 @@ __device__ __forceinline__ bool dirichlet_close(const LbmArgs &a, T (&f)[kQ], un
     return bad;
 }
 
+// Raw buffer access (gfx9 buffer instructions): the array base and size
+// live in one SGPR resource, the population plane offset q * plane is the
+// scalar offset and each lane supplies a 32-bit byte offset, so a pull
+// costs no 64-bit address arithmetic.  Offsets at or past num_records read
+// as 0 without touching memory.
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+__device__ __forceinline__ BufRsrc buf_rsrc(const void *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+    static __device__ __forceinline__ float load(BufRsrc r, unsigned v, unsigned s) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    }
+    static __device__ __forceinline__ void store_nt(float x, BufRsrc r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 2);
+    }
+};
+template <> struct Buf<double> {
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(BufRsrc(), 0, 0, 0)) Raw;
+    static __device__ __forceinline__ double load(BufRsrc r, unsigned v, unsigned s) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    }
+    static __device__ __forceinline__ void store_nt(double x, BufRsrc r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(Raw, x), r, v, s, 2);
+    }
+};
+
+#ifndef SWEEP2_WAVES
+#define SWEEP2_WAVES 1
+#endif
 template <typename T, int TW, int TH>
-__global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP2_WAVES)))
+lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
     constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
     constexpr int ROUNDS1 = (R1 + 255) / 256;
     static_assert((TW * TH) % 256 == 0 && 256 % TW == 0, "second half: whole rows per wave round");
     constexpr int ROUNDS2 = TW * TH / 256;
+    constexpr unsigned sz = sizeof(T);
     __shared__ T lds[kQ][H1][W1];
 
     const int N = a.N;
     const int P = a.pitch;
-    const int S = static_cast<int>(a.plane);
-    const T *__restrict__ src = static_cast<const T *>(a.src);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const unsigned S = static_cast<unsigned>(a.plane);
+    const unsigned NP = static_cast<unsigned>(N) * static_cast<unsigned>(P);
+    const BufRsrc fsrc = buf_rsrc(a.src, kQ * S * sz);
+    const BufRsrc fdst = buf_rsrc(a.dst, kQ * S * sz);
+    const BufRsrc mrs = buf_rsrc(a.mask, NP * 2u);
+    const BufRsrc vxr = buf_rsrc(a.vx, NP * 4u);
+    const BufRsrc vyr = buf_rsrc(a.vy, NP * 4u);
     const T omega = T(a.omega);
     const int t = xcd_tile(blockIdx.x, tiles);
     const int x0 = (t % tiles_x) * TW;
     const int y0 = (t / tiles_x) * TH;
 
     // ---- first half: step j+1 on the tile and its ring, into LDS --------
+    // Pull x - e_q reads plane q at row j - cy_q, column i - cx_q.  For
+    // i >= 1 the three row offsets of column i - 1 (rows clamped onto the
+    // patch) plus 0, 1 or 2 elements address all nine pulls; a column of
+    // N then falls in the row padding or the next row of the same plane,
+    // inside the buffer.  The left column (i = 0) clamps every pull onto
+    // the patch.  Values fetched for upstream nodes outside the patch are
+    // replaced by the closure.
     T f[ROUNDS1][kQ];
     unsigned m[ROUNDS1];
-    bool live[ROUNDS1];
+    float vx1[ROUNDS1], vy1[ROUNDS1];
 #pragma unroll
     for (int k = 0; k < ROUNDS1; ++k) {
         const int idx = threadIdx.x + 256 * k;
         const int r = idx / W1, c = idx - (idx / W1) * W1;
         const int i = x0 - 1 + c, j = y0 - 1 + r;
-        live[k] = idx < R1 && i >= 0 && j >= 0 && i < N && j < N;
         m[k] = kMaskSolid;
-        if (live[k]) {
-            m[k] = a.mask[j * P + i];
-            // pulls issued before the flag word is known; upstream nodes
-            // outside the patch are clamped onto it (values then unused)
+        if (idx < R1 && i >= 0 && j >= 0 && i < N && j < N) {
+            const unsigned n = static_cast<unsigned>(j * P + i);
+            m[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * n, 0, 0);
+            vx1[k] = Buf<float>::load(vxr, 4u * n, 0);
+            vy1[k] = Buf<float>::load(vyr, 4u * n, 0);
+            const int jm = j > 0 ? j - 1 : 0, jp = j < N - 1 ? j + 1 : N - 1;
+            if (i > 0) {
+                // byte offset of column i - 1 in rows j + 1, j, j - 1
+                const unsigned base[3] = {static_cast<unsigned>(jp * P + i - 1) * sz, (n - 1u) * sz,
+                                          static_cast<unsigned>(jm * P + i - 1) * sz};
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const int si = min(max(i - kCx[q], 0), N - 1);
-                const int sj = min(max(j - kCy[q], 0), N - 1);
-                f[k][q] = src[q * S + sj * P + si];
+                for (int q = 0; q < kQ; ++q)
+                    f[k][q] = Buf<T>::load(fsrc, base[1 + kCy[q]] + (1 - kCx[q]) * sz, q * S * sz);
+            } else {
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    const int sj = kCy[q] == 1 ? jm : kCy[q] == -1 ? jp : j;
+                    const int si = kCx[q] == -1 ? 1 : 0;           // column -1 clamped to 0
+                    f[k][q] = Buf<T>::load(fsrc, static_cast<unsigned>(sj * P + si) * sz, q * S * sz);
+                }
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < ROUNDS1; ++k) {
-        if (!live[k] || (m[k] & kMaskSolid)) continue;
+        if (m[k] & kMaskSolid) continue;
         const int idx = threadIdx.x + 256 * k;
         const int r = idx / W1, c = idx - (idx / W1) * W1;
         const int i = x0 - 1 + c, j = y0 - 1 + r;
-        const int n = j * P + i;
+        const unsigned n = static_cast<unsigned>(j * P + i);
         const bool owned = r >= 1 && r <= TH && c >= 1 && c <= TW;
         if (m[k] & 0x1FEu) {
 #pragma unroll
             for (int q = 1; q < kQ; ++q)
-                if ((m[k] >> q) & 1u) f[k][q] = src[kOpp[q] * S + n];
+                if ((m[k] >> q) & 1u) f[k][q] = Buf<T>::load(fsrc, n * sz, kOpp[q] * S * sz);
         }
         if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
             const bool bad = dirichlet_close<T>(a, f[k], outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
             if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
         }
-        const T u = collide<T>(f[k], T(a.vx[n]), T(a.vy[n]), omega, node_k<T>(a, n));
+        const T u = collide<T>(f[k], T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
         if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
         for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[k][q];
@@ -587,12 +641,11 @@ __global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x,
         const int idx = threadIdx.x + 256 * k;
         const int i = x0 + idx % TW, j = y0 + idx / TW;
         m2[k] = kMaskSolid;
-        vx2[k] = vy2[k] = 0.f;
         if (i < N && j < N) {
-            const int n = j * P + i;
-            m2[k] = a.mask[n];
-            vx2[k] = a.vx[n];
-            vy2[k] = a.vy[n];
+            const unsigned n = static_cast<unsigned>(j * P + i);
+            m2[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * n, 0, 0);
+            vx2[k] = Buf<float>::load(vxr, 4u * n, 0);
+            vy2[k] = Buf<float>::load(vyr, 4u * n, 0);
         }
     }
     __syncthreads();
@@ -604,7 +657,7 @@ __global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x,
         const int idx = threadIdx.x + 256 * k;
         const int r = idx / TW, c = idx % TW;
         const int i = x0 + c, j = y0 + r;
-        const int n = j * P + i;
+        const unsigned n = static_cast<unsigned>(j * P + i);
         const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
         const unsigned unknown = perim ? outside_bits(N, i, j) : 0u;
         T g[kQ];
@@ -619,10 +672,10 @@ __global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x,
             const bool bad = dirichlet_close<T>(a, g, unknown, perimeter_slot(N, i, j), a.lam2);
             if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
         }
-        const T u = collide<T>(g, T(vx2[k]), T(vy2[k]), omega, node_k<T>(a, n));
+        const T u = collide<T>(g, T(vx2[k]), T(vy2[k]), omega, node_k<T>(a, static_cast<int>(n)));
         if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(g[q], &dst[q * S + n]);
+        for (int q = 0; q < kQ; ++q) Buf<T>::store_nt(g[q], fdst, n * sz, q * S * sz);
     }
 }
 
@@ -705,16 +758,27 @@ hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hi
 }
 
 // tile shape of the two-step sweep: LDS holds 9 planes of (TW+2) x (TH+2)
-// values, 42.8 KB in FP32 and 47.5 KB in FP64 (three workgroups per CU)
+// values
+// tile heights: 64 x 8 in both precisions (LDS 23.8 KB in FP32, six
+// workgroups per CU; 47.5 KB in FP64, three).  On the 2048^2 and 4096^2
+// pore workloads 64 x 8 FP32 tiles ran 14% faster than 64 x 16 ones (more
+// workgroups in flight hide the memory latency of the first half); FP64
+// measured the same with 4, 8 or 12 rows.
+#ifndef SWEEP2_TH32
+#define SWEEP2_TH32 8
+#endif
+#ifndef SWEEP2_TH64
+#define SWEEP2_TH64 8
+#endif
 template <typename T> struct Sweep2Tile;
-template <> struct Sweep2Tile<float> { static constexpr int TW = 64, TH = 16; };
-template <> struct Sweep2Tile<double> { static constexpr int TW = 64, TH = 8; };
+template <> struct Sweep2Tile<float> { static constexpr int TW = 64, TH = SWEEP2_TH32; };
+template <> struct Sweep2Tile<double> { static constexpr int TW = 64, TH = SWEEP2_TH64; };
 
 template <typename T>
 hipError_t step2_impl(const LbmArgs &a, hipStream_t s) {
     constexpr int TW = Sweep2Tile<T>::TW, TH = Sweep2Tile<T>::TH;
-    const int tx = (a.N + TW - 1) / TW, ty = (a.N + TH - 1) / TH;
     auto kernel = lbm_sweep2_kernel<T, TW, TH>;
+    const int tx = (a.N + TW - 1) / TW, ty = (a.N + TH - 1) / TH;
     hipLaunchKernelGGL(kernel, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
     return hipGetLastError();
 }
