@@ -3,8 +3,10 @@
 // FP64, and the two grid transfers of Sec. 6.2, item ii.
 //
 // The coarse system is tiny (at most a few 10^4 unknowns) and needs a few
-// dozen dependent passes per solve, so it is latency-bound.  Each thread
-// owns one mesh row; stencil products read zero-halo padded vectors; dot
+// dozen dependent passes per solve, so it is latency-bound.  The two
+// kernels that apply A P give each mesh row eight lanes (one stencil row
+// each) to put eight times more waves in flight; the others use one lane
+// per row.  Stencil products read zero-halo padded vectors; dot
 // products are reduced deterministically (each workgroup writes a partial,
 // the next kernel sums all partials in block order); the preconditioner P
 // (a sparse approximate inverse computed on the host) is folded into the
@@ -40,6 +42,26 @@ __device__ __forceinline__ double stencil_row(const double *__restrict__ coef, i
     return acc;
 }
 
+// A P times padded vector x at row `node`, computed by the eight lanes of
+// a group: lane g < 7 takes stencil row dl = g - 3 (seven contiguous
+// coefficients, seven contiguous vector entries), lane 7 adds zero; the
+// xor butterfly leaves the same (bit-identical) total in all eight lanes.
+__device__ __forceinline__ double ap_row8(const CoarseDev &c, int node, int pidx, int g, bool valid,
+                                          const double *__restrict__ x) {
+    constexpr int W = kApW, R = W / 2;
+    double acc = 0.0;
+    if (valid && g < W) {
+        const double *__restrict__ cr = c.AP + (size_t)node * (W * W) + g * W;
+        const double *__restrict__ xr = x + pidx + (g - R) * c.S - R;
+#pragma unroll
+        for (int dk = 0; dk < W; ++dk) acc += cr[dk] * xr[dk];
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    return acc;
+}
+
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     // wave reduction then across the waves of the block
@@ -71,7 +93,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
 // into its own slot; the next kernel sums all blocks in block order, so the
 // scalars are bit-identical in every block (deterministic).
 __device__ __forceinline__ double *slot_ptr(const CoarseDev &c, int slot) {
-    return c.partials + (size_t)slot * 4 * c.grid;
+    return c.partials + (size_t)slot * 4 * c.pstride;
 }
 template <int NV>
 __device__ __forceinline__ void write_partials(const CoarseDev &c, int slot, double (&v)[NV], double *lds) {
@@ -79,20 +101,33 @@ __device__ __forceinline__ void write_partials(const CoarseDev &c, int slot, dou
     if (threadIdx.x == 0) {
         double *s = slot_ptr(c, slot);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s[k * c.grid + blockIdx.x] = v[k];
+        for (int k = 0; k < NV; ++k) s[k * c.pstride + blockIdx.x] = v[k];
     }
 }
-// Sums of the previous kernel's per-block partials, computed by the first
-// wave of the block (lanes stride over the blocks, then a fixed shuffle
-// tree), so every block obtains bit-identical values; broadcast via LDS.
+// Sums of the `blocks` per-block partials of an earlier kernel, computed by
+// the first wave of the block (lanes stride over the blocks, then a fixed
+// shuffle tree), so every block obtains bit-identical values; broadcast via
+// LDS.
 template <int NV>
-__device__ __forceinline__ void read_sums(const CoarseDev &c, int slot, double (&out)[NV], double *lds) {
+__device__ __forceinline__ void read_sums(const CoarseDev &c, int slot, int blocks, double (&out)[NV],
+                                          double *lds) {
     if (threadIdx.x < 64) {
         const double *s = slot_ptr(c, slot);
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
+            // batches of 16 independent loads per lane (one memory round
+            // trip per 1024 partials), summed in a fixed order
             double acc = 0.0;
-            for (int b = threadIdx.x; b < c.grid; b += 64) acc += s[(size_t)k * c.grid + b];
+            for (int base = 0; base < blocks; base += 1024) {
+                double part[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int b = base + threadIdx.x + 64 * u;
+                    part[u] = b < blocks ? s[(size_t)k * c.pstride + b] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc += part[u];
+            }
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
             if (threadIdx.x == 0) lds[16 + k] = acc;
         }
@@ -156,8 +191,8 @@ __global__ void __launch_bounds__(kBlock) coarse_iter_a(CoarseDev c, int first, 
     KrylovState &st = *c.state;
     if (st.done) return;
     double rs[2], cs[2];
-    read_sums<2>(c, kSlotRhs, rs, lds);
-    if (!first) read_sums<2>(c, kSlotC, cs, lds);
+    read_sums<2>(c, kSlotRhs, c.grid, rs, lds);
+    if (!first) read_sums<2>(c, kSlotC, c.grid, cs, lds);
     const double bnorm = sqrt(rs[0]);
     const double rho_new = first ? rs[1] : cs[0];
     const double rnorm = sqrt(first ? rs[1] : cs[1]);
@@ -175,12 +210,15 @@ __global__ void __launch_bounds__(kBlock) coarse_iter_a(CoarseDev c, int first, 
     const double beta = first ? 0.0 : (rho_new / st.rho) * (st.alpha / st.omega);
     const double omega = st.omega;
     double red[1] = {0.0};
-    const int node = blockIdx.x * blockDim.x + threadIdx.x;
-    if (node < c.n) {
-        const int pi = padded_index(c, node);
+    // eight lanes per mesh row
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int node = gt >> 3, g = gt & 7;
+    const bool valid = node < c.n;
+    const int pi = valid ? padded_index(c, node) : 0;
+    const double w = ap_row8(c, node, pi, g, valid, c.r);
+    if (valid && g == 0) {
         const double r = c.r[pi];
         c.p[pi] = r + beta * (c.p[pi] - omega * c.v[pi]);
-        const double w = stencil_row<kApW>(c.AP, c.n, node, pi, c.S, c.r);
         const double vn = w + beta * (c.v[pi] - omega * c.z[pi]);
         c.w[pi] = w;
         c.v[pi] = vn;
@@ -200,14 +238,16 @@ __global__ void __launch_bounds__(kBlock) coarse_iter_b(CoarseDev c) {
     if (st.done) return;
     const double rho = st.rho_next;
     double as[1];
-    read_sums<1>(c, kSlotA, as, lds);
+    read_sums<1>(c, kSlotA, c.grid8, as, lds);
     const double alpha = rho / as[0];
     double red[2] = {0.0, 0.0};
-    const int node = blockIdx.x * blockDim.x + threadIdx.x;
-    if (node < c.n) {
-        const int pi = padded_index(c, node);
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int node = gt >> 3, g = gt & 7;
+    const bool valid = node < c.n;
+    const int pi = valid ? padded_index(c, node) : 0;
+    const double zn = ap_row8(c, node, pi, g, valid, c.v);
+    if (valid && g == 0) {
         const double sv = c.r[pi] - alpha * c.v[pi];
-        const double zn = stencil_row<kApW>(c.AP, c.n, node, pi, c.S, c.v);
         const double tv = c.w[pi] - alpha * zn;
         c.s[pi] = sv;
         c.z[pi] = zn;
@@ -229,7 +269,7 @@ __global__ void __launch_bounds__(kBlock) coarse_iter_c(CoarseDev c) {
     KrylovState &st = *c.state;
     if (st.done) return;
     double bs[2];
-    read_sums<2>(c, kSlotB, bs, lds);
+    read_sums<2>(c, kSlotB, c.grid8, bs, lds);
     const double omega = bs[1] > 0.0 ? bs[0] / bs[1] : 0.0;
     const double alpha = st.alpha;
     double red[2] = {0.0, 0.0};
@@ -315,12 +355,12 @@ hipError_t launch_coarse_rhs(const CoarseDev &c, const double *guess, hipStream_
 hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iterations, int max_iter, double tol,
                                hipStream_t s) {
     for (int it = 0; it < iterations; ++it) {
-        hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid), dim3(kBlock), 0, s, c, it == 0 ? 1 : 0, tol, max_iter);
-        hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, it == 0 ? 1 : 0, tol, max_iter);
+        hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid8), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(coarse_iter_c, dim3(c.grid), dim3(kBlock), 0, s, c);
     }
     // closing convergence test after the last enqueued iteration
-    hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid), dim3(kBlock), 0, s, c, iterations == 0 ? 1 : 0, tol, 0);
+    hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, iterations == 0 ? 1 : 0, tol, 0);
     hipLaunchKernelGGL(coarse_finish, dim3(c.grid), dim3(kBlock), 0, s, c, guess);
     return hipGetLastError();
 }

@@ -26,6 +26,7 @@ int choose_pitch(int N) { return (int)align_up((size_t)N, 64); }
 long long choose_plane(int N, int pitch) { return (long long)align_up((size_t)N * pitch, 64) + 128; }
 
 int coarse_grid(int n) { return (n + 255) / 256; }
+int coarse_grid8(int n) { return (8 * n + 255) / 256; }
 
 // node-major [n][W*W] -> offset-major [W*W][n]
 std::vector<double> offset_major(const std::vector<double> &c, int n, int w2) {
@@ -87,7 +88,7 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
         L.P = take((size_t)L.n * kSpaiW * kSpaiW * 8);
         L.dkind = take((size_t)L.n * 4);
         L.vec = take(11 * align_up(L.vec_len * 8, kAlign));
-        L.partials = take((size_t)16 * L.grid * 8);
+        L.partials = take((size_t)16 * coarse_grid8(L.n) * 8);
         L.barrier = take(sizeof(KrylovState));
     }
     L.total = off;
@@ -349,6 +350,8 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         c.n = L.n;
         c.S = L.S;
         c.grid = L.grid;
+        c.grid8 = coarse_grid8(L.n);
+        c.pstride = c.grid8;
         c.A9 = reinterpret_cast<const double *>(h->ws + L.A9);
         c.B9 = reinterpret_cast<const double *>(h->ws + L.B9);
         c.AP = reinterpret_cast<const double *>(h->ws + L.AP);
@@ -374,11 +377,10 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         c.state = reinterpret_cast<KrylovState *>(h->ws + L.barrier);
         c.result = h->kres;
         const std::vector<double> A9t = offset_major(ch.A9, L.n, 9), B9t = offset_major(ch.B9, L.n, 9);
-        const std::vector<double> APt = offset_major(ch.AP, L.n, kApW * kApW);
         const std::vector<double> Pt = offset_major(ch.P, L.n, kSpaiW * kSpaiW);
         CREATE_TRY(up((void *)c.A9, A9t.data(), A9t.size() * 8));
         CREATE_TRY(up((void *)c.B9, B9t.data(), B9t.size() * 8));
-        CREATE_TRY(up((void *)c.AP, APt.data(), APt.size() * 8));
+        CREATE_TRY(up((void *)c.AP, ch.AP.data(), ch.AP.size() * 8));
         CREATE_TRY(up((void *)c.P, Pt.data(), Pt.size() * 8));
         CREATE_TRY(up((void *)c.dkind, ch.dkind.data(), ch.dkind.size() * 4));
         std::vector<double> xp(L.vec_len, 0.0);

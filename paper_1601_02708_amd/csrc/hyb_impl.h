@@ -87,12 +87,16 @@ struct CoarseDev {
     int M;
     int n;                   // (M+1)^2 mesh nodes
     int S;                   // padded row length M + 1 + 2 kCoarseHalo
-    int grid;                // workgroups of the solver kernels (one row per thread)
-    // stencils stored offset-major, coef[o * n + node], o = (dl + R) * W + (dk + R),
-    // so consecutive lanes (consecutive nodes) read consecutive addresses
+    int grid;                // workgroups of the one-lane-per-row kernels
+    int grid8;               // workgroups of the eight-lanes-per-row kernels
+    int pstride;             // partials per reduction value (>= grid, grid8)
+    // A9, B9, P: offset-major, coef[o * n + node], o = (dl + R) * W + (dk + R),
+    // so consecutive lanes (consecutive nodes) read consecutive addresses;
+    // AP: node-major, coef[node * 49 + o], so the eight lanes of a row read
+    // its seven stencil rows as contiguous runs
     const double *A9;        // [9][n] stencil of A
     const double *B9;        // [9][n]
-    const double *AP;        // [kApW^2][n] stencil of A P
+    const double *AP;        // [n][kApW^2] stencil of A P
     const double *P;         // [kSpaiW^2][n] stencil of P
     const int *dkind;        // [n] -1 free, -2 outer Dirichlet, >= 0 index into ufc
     double outer_value;
@@ -100,7 +104,7 @@ struct CoarseDev {
     double *xn;              // padded d(t_n)
     double *x1;              // padded new solution
     double *r, *rh, *p, *v, *s, *t, *y, *w, *z;   // padded Krylov vectors
-    double *partials;        // [4 slots][4][grid] reduction partials
+    double *partials;        // [4 slots][4][pstride] reduction partials
     KrylovState *state;
     KrylovResult *result;
 };
