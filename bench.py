@@ -47,8 +47,11 @@ def sweep_bytes(problem, elem_bytes):
     return fluid * per_fluid + solid * 2 + 4 * (N - 1) * 16, fluid, solid, per_fluid
 
 
+ELEM = {"fp64": 8, "fp32": 4, "fp16s": 2}
+
+
 def kernel_name(elem_bytes, steps_per_launch):
-    t = "float" if elem_bytes == 4 else "double"
+    t = {8: "double", 4: "float", 2: "_Float16"}[elem_bytes]
     if steps_per_launch == 2:
         return f"lbm_sweep2_kernel<{t}, 64, 8>"
     return f"lbm_sweep_kernel<{t}, 1>"
@@ -122,11 +125,11 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pore2048")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16s"])
     ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2],
                     help="fine steps per lattice-sweep launch (2: temporally blocked pairs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the second-precision run")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other-precision runs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (a plain copy kernel of "
                          "known size, for calibrating HBM traffic counters)")
@@ -144,7 +147,7 @@ def main():
     N = cfg.N
     lups_step = cfg.max_iter * cfg.eta * N * N
     fluid_frac = float((problem.solid == 0).mean())
-    elem = 4 if args.precision == "fp32" else 8
+    elem = ELEM[args.precision]
     print(f"[bench] {cfg.name} {args.precision}: {args.warmup} warmup + {args.steps} timed coarse steps",
           file=sys.stderr, flush=True)
     spl = args.steps_per_launch
@@ -170,13 +173,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {
             "workload": (f"{cfg.name}: {N}^2 D2Q9 lattice, random disks (porosity {problem.porosity:.4f}), "
                          f"8-mode stream-function velocity max 0.05, D={cfg.D}, k={cfg.k}, {cfg.M}^2 Q1 SUPG mesh, "
                          f"eta={cfg.eta}, {cfg.max_iter} Schwarz passes per coarse step"),
             "lattice": N, "mesh": cfg.M, "eta": cfg.eta, "schwarz": cfg.max_iter, "precision": args.precision,
+            "storage": {"fp64": "f64", "fp32": "f32", "fp16s": "f16 shifted"}[args.precision],
         },
         "mflups": round(value * fluid_frac, 1),
         "roofline": {
@@ -200,23 +204,28 @@ def main():
         "infeasible_closures": st["infeasible"],
     }
     if not args.no_compare:
-        other = "fp64" if args.precision == "fp32" else "fp32"
-        print(f"[bench] comparison run {other}", file=sys.stderr, flush=True)
-        g2, _, gpu_ms2, kms2, launches2, _ = run_gpu(problem, other, args.steps, args.warmup, spl)
-        u1, u2 = g.concentration(), g2.concentration()
         fluid = problem.solid == 0
-        ref, low = (u2, u1) if other == "fp64" else (u1, u2)
-        err = float(np.linalg.norm((low - ref)[fluid]) / np.linalg.norm(ref[fluid]))
-        e2 = 4 if other == "fp32" else 8
-        b2, _, _, _ = sweep_bytes(problem, e2)
-        k2 = kms2 / max(launches2, 1)
-        res[other] = {"value": round(lups_step * args.steps / (gpu_ms2 / 1e3) / 1e6, 1), "unit": "MLUPS",
-                      "ms_per_step": round(gpu_ms2 / args.steps, 4),
-                      "sweep_kernel": kernel_name(e2, spl),
-                      "sweep_achieved_gbs": round(b2 * steps_launch / (k2 / 1e3) / 1e9, 1),
-                      "sweep_avg_launch_ms": round(k2, 5)}
-        res["fp32_rel_l2_vs_fp64"] = err
-        del g2
+        conc = {args.precision: g.concentration()}
+        for other in [p for p in ("fp64", "fp16s", "fp32") if p != args.precision]:
+            print(f"[bench] comparison run {other}", file=sys.stderr, flush=True)
+            g2, _, gpu_ms2, kms2, launches2, _ = run_gpu(problem, other, args.steps, args.warmup, spl)
+            conc[other] = g2.concentration()
+            e2 = ELEM[other]
+            b2, _, _, _ = sweep_bytes(problem, e2)
+            k2 = kms2 / max(launches2, 1)
+            res[other] = {"value": round(lups_step * args.steps / (gpu_ms2 / 1e3) / 1e6, 1), "unit": "MLUPS",
+                          "ms_per_step": round(gpu_ms2 / args.steps, 4),
+                          "sweep_kernel": kernel_name(e2, spl),
+                          "sweep_achieved_gbs": round(b2 * steps_launch / (k2 / 1e3) / 1e9, 1),
+                          "sweep_avg_launch_ms": round(k2, 5)}
+            g2.close()
+            del g2
+        ref = conc["fp64"]
+        nref = np.linalg.norm(ref[fluid])
+        for p_, u_ in conc.items():
+            if p_ != "fp64":
+                key = "fp32_rel_l2_vs_fp64" if p_ == "fp32" else f"{p_}_rel_l2_vs_fp64"
+                res[key] = float(np.linalg.norm((u_ - ref)[fluid]) / nref)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one coarse step)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(problem)

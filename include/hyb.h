@@ -52,7 +52,16 @@ enum {
     HYB_ENONFINITE = -4    /* a NaN/Inf concentration appeared in the lattice */
 };
 
-enum { HYB_FP64 = 0, HYB_FP32 = 1 };            /* population storage and arithmetic */
+/* Population storage and arithmetic.  HYB_FP64, HYB_FP32: stored and
+ * computed in that precision.  HYB_FP16S: FP16 shifted storage -- each
+ * population is stored as the binary16 value g = (f - w_q c_ref) * 2^s
+ * (round to nearest even), where c_ref is the mean of u0 over the fluid
+ * nodes and 2^s the largest power of two with (4/9) U 2^s <= 16384,
+ * U = max(1, max |u0 - c_ref|), both fixed at hyb_create; arithmetic in
+ * FP32, closures in FP64.  Concentrations beyond about 4.5 U from c_ref
+ * overflow binary16 and are reported as non-finite (by the commit of the
+ * coarse step whose fine steps read the overflowed value). */
+enum { HYB_FP64 = 0, HYB_FP32 = 1, HYB_FP16S = 2 };
 enum { HYB_F2C = 0, HYB_C2F = 1 };              /* hyb_interface_exchange direction */
 enum { HYB_FINE = 0, HYB_COARSE = 1 };          /* hyb_concentration field */
 enum { HYB_BC_DIRICHLET = 0, HYB_BC_NEUMANN = 1 };
@@ -74,7 +83,7 @@ typedef struct {
 typedef struct {
     int N;                  /* nodes per side, >= 3 */
     double x0, y0;          /* domain coordinates of node (0, 0) */
-    int precision;          /* HYB_FP64 or HYB_FP32 */
+    int precision;          /* HYB_FP64, HYB_FP32 or HYB_FP16S */
     double tau;             /* BGK relaxation time; <= 0 selects 1/2 + 3 D (Sec. 4.1) */
     int eta;                /* fine steps per coarse step, >= 1 */
     int bc_clamp;           /* maxent Dirichlet closure, eq. (LBM_Dir): 0 applied as

@@ -325,20 +325,21 @@ __global__ void c2f_kernel(const int *__restrict__ idx, const double *__restrict
 }
 
 // ufc[c] = sum of the four weighted lattice concentrations around Gamma_{f->c} node c.
-template <typename T>
+template <typename S>
 __global__ void f2c_kernel(LbmArgs lat, const int *__restrict__ idx, const double *__restrict__ w, int nfc,
                            double *__restrict__ ufc) {
+    typedef typename Pop<S>::T T;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nfc) return;
-    const T *__restrict__ src = static_cast<const T *>(lat.src);
-    const int S = static_cast<int>(lat.plane);
+    const S *__restrict__ src = static_cast<const S *>(lat.src);
+    const int plane = static_cast<int>(lat.plane);
     double acc = 0.0;
     for (int m = 0; m < 4; ++m) {
         const double wm = w[4 * c + m];
         if (wm == 0.0) continue;
         const int n = idx[4 * c + m];
         double u = 0.0;
-        for (int q = 0; q < kQ; ++q) u += double(src[q * S + n]);
+        for (int q = 0; q < kQ; ++q) u += double(Pop<S>::ld(src[q * plane + n], q, lat));
         const double k = lat.kfield ? double(static_cast<const T *>(lat.kfield)[n]) : lat.k;
         acc += wm * (u / (1.0 - k));
     }
@@ -371,11 +372,13 @@ hipError_t launch_c2f(const int *idx, const double *w, int nslots, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_f2c(const LbmArgs &lat, const int *idx, const double *w, int nfc, double *ufc, bool fp64,
+hipError_t launch_f2c(const LbmArgs &lat, const int *idx, const double *w, int nfc, double *ufc, int prec,
                       hipStream_t s) {
     if (nfc == 0) return hipSuccess;
-    if (fp64) hipLaunchKernelGGL(f2c_kernel<double>, dim3((nfc + 255) / 256), dim3(256), 0, s, lat, idx, w, nfc, ufc);
-    else hipLaunchKernelGGL(f2c_kernel<float>, dim3((nfc + 255) / 256), dim3(256), 0, s, lat, idx, w, nfc, ufc);
+    const dim3 grid((nfc + 255) / 256), block(256);
+    if (prec == HYB_FP64) hipLaunchKernelGGL(f2c_kernel<double>, grid, block, 0, s, lat, idx, w, nfc, ufc);
+    else if (prec == HYB_FP32) hipLaunchKernelGGL(f2c_kernel<float>, grid, block, 0, s, lat, idx, w, nfc, ufc);
+    else hipLaunchKernelGGL(f2c_kernel<_Float16>, grid, block, 0, s, lat, idx, w, nfc, ufc);
     return hipGetLastError();
 }
 

@@ -25,6 +25,42 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int choose_pitch(int N) { return (int)align_up((size_t)N, 64); }
 long long choose_plane(int N, int pitch) { return (long long)align_up((size_t)N * pitch, 64) + 128; }
 
+bool valid_precision(int p) { return p == HYB_FP64 || p == HYB_FP32 || p == HYB_FP16S; }
+size_t storage_bytes(int p) { return p == HYB_FP64 ? 8 : p == HYB_FP32 ? 4 : 2; }
+
+// IEEE 754 binary32 <-> binary16 on the host, round to nearest even
+// (the rounding the device conversion uses).
+uint16_t f32_to_f16(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    const uint32_t sign = (u >> 16) & 0x8000u;
+    const uint32_t mag = u & 0x7fffffffu;
+    if (mag >= 0x7f800000u) return (uint16_t)(sign | 0x7c00u | (mag > 0x7f800000u ? 0x200u : 0u));
+    if (mag >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);        // >= 65520 rounds to infinity
+    if (mag < 0x38800000u) {                                          // below 2^-14: subnormal or zero
+        float f;
+        std::memcpy(&f, &mag, 4);
+        return (uint16_t)(sign | (uint32_t)std::nearbyint(f * 16777216.0f));   // exact scaling by 2^24
+    }
+    const uint32_t m = mag & 0x7fffffu;
+    uint32_t h = (((mag >> 23) - 112u) << 10) | (m >> 13);
+    const uint32_t rem = m & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) h += 1u;     // carry may reach the exponent
+    return (uint16_t)(sign | h);
+}
+float f16_to_f32(uint16_t h) {
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+    const uint32_t e = (h >> 10) & 0x1fu, m = h & 0x3ffu;
+    if (e == 0) {
+        const float f = (float)m * 5.9604644775390625e-08f;          // m * 2^-24
+        return sign ? -f : f;
+    }
+    const uint32_t bits = sign | (e == 31 ? 0x7f800000u | (m << 13) : ((e + 112u) << 23) | (m << 13));
+    float f;
+    std::memcpy(&f, &bits, 4);
+    return f;
+}
+
 int coarse_grid(int n) { return (n + 255) / 256; }
 int coarse_grid8(int n) { return (8 * n + 255) / 256; }
 
@@ -50,7 +86,7 @@ struct Layout {
 Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield) {
     Layout L;
     const int N = lat->N;
-    const size_t elem = lat->precision == HYB_FP64 ? 8 : 4;
+    const size_t elem = storage_bytes(lat->precision);
     L.pitch = choose_pitch(N);
     L.plane = choose_plane(N, L.pitch);
     L.f_bytes = align_up((size_t)9 * L.plane * elem, kAlign);
@@ -65,7 +101,7 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
     L.mask = take(nodes * 2);
     L.vx = take(nodes * 4);
     L.vy = take(nodes * 4);
-    L.kfield = has_kfield ? take(nodes * elem) : 0;
+    L.kfield = has_kfield ? take(nodes * (lat->precision == HYB_FP64 ? 8 : 4)) : 0;
     L.bc_kind = take(nslots);
     L.bc_a = take(nslots * 8);
     L.bc_b = take(nslots * 8);
@@ -101,7 +137,10 @@ struct hyb_handle {
     std::string err;
     // problem
     int N = 0, M = 0, eta = 1, clamp = 0;
-    bool fp64 = true, has_mesh = false, has_kfield = false;
+    int prec = HYB_FP64;                // population storage (HYB_FP64 / FP32 / FP16S)
+    bool fp64 = true, has_mesh = false, has_kfield = false;   // fp64: arithmetic type
+    float hs_scale = 1.f, hs_inv = 1.f, hs_cref = 0.f;        // FP16S encoding
+    std::vector<uint8_t> solid_host;    // [N*N] solid flags (readout zeroes solid nodes)
     double tau = 0, omega = 0, D = 0, kuni = 0;
     double x0 = 0, y0 = 0;
     hipStream_t stream = nullptr;
@@ -181,6 +220,9 @@ struct hyb_handle {
         a.lam = 0.0;
         a.clamp = clamp;
         a.counters = counters;
+        a.hs_scale = hs_scale;
+        a.hs_inv = hs_inv;
+        for (int q = 0; q < kQ; ++q) a.hs_wc[q] = (float)kW[q] * hs_cref;
         return a;
     }
     // buffer that is neither the committed state nor `a`
@@ -200,7 +242,7 @@ struct hyb_handle {
 extern "C" {
 
 int hyb_query(const hyb_mesh *mesh, const hyb_lattice *lat, size_t *f_bytes, size_t *ws_bytes) {
-    if (!lat || lat->N < 3 || (lat->precision != HYB_FP64 && lat->precision != HYB_FP32)) return HYB_EINVAL;
+    if (!lat || lat->N < 3 || !valid_precision(lat->precision)) return HYB_EINVAL;
     if (mesh && mesh->M < 2) return HYB_EINVAL;
     // per-node kfield space is reserved; callers that pass none waste N^2 elements
     Layout L = make_layout(mesh, lat, true);
@@ -222,7 +264,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     if (!lat || !u || !u->fine || !lat->u0) return bail(HYB_EINVAL, "lattice, velocity and u0 are required");
     const int N = lat->N;
     if (N < 3) return bail(HYB_EINVAL, "N must be >= 3");
-    if (lat->precision != HYB_FP64 && lat->precision != HYB_FP32) return bail(HYB_EINVAL, "unknown precision");
+    if (!valid_precision(lat->precision)) return bail(HYB_EINVAL, "unknown precision");
     if (!(D > 0.0)) return bail(HYB_EINVAL, "D must be > 0");
     if (lat->eta < 1) return bail(HYB_EINVAL, "eta must be >= 1");
     const double tau = lat->tau > 0.0 ? lat->tau : 0.5 + 3.0 * D;
@@ -236,6 +278,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
             return bail(HYB_EINVAL, "lattice patch must lie inside the coarse domain");
     }
     h->N = N;
+    h->prec = lat->precision;
     h->fp64 = lat->precision == HYB_FP64;
     h->tau = tau;
     h->omega = 1.0 / tau;
@@ -266,6 +309,25 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     // ---- host staging of geometry, velocity, reaction --------------------
     std::vector<uint16_t> mask(nodes, 0);
     auto solid = [&](int i, int j) { return lat->solid && lat->solid[(size_t)j * N + i]; };
+    h->solid_host.assign((size_t)N * N, 0);
+    if (lat->solid)
+        for (size_t n = 0; n < (size_t)N * N; ++n) h->solid_host[n] = lat->solid[n] ? 1 : 0;
+    if (h->prec == HYB_FP16S) {
+        // c_ref = mean of u0 over the fluid nodes; scale = 2^s, the largest
+        // power of two with (4/9) U 2^s <= 2^14, U = max(1, max |u0 - c_ref|)
+        double sum = 0.0, cnt = 0.0;
+        for (size_t n = 0; n < (size_t)N * N; ++n)
+            if (!h->solid_host[n]) { sum += lat->u0[n]; cnt += 1.0; }
+        const double cref = cnt > 0.0 ? sum / cnt : 0.0;
+        double U = 1.0;
+        for (size_t n = 0; n < (size_t)N * N; ++n)
+            if (!h->solid_host[n]) U = std::max(U, std::fabs(lat->u0[n] - cref));
+        if (!std::isfinite(U)) return bail(HYB_EINVAL, "u0 must be finite");
+        const int s2 = (int)std::floor(std::log2(16384.0 / (4.0 / 9.0 * U)));
+        h->hs_cref = (float)cref;
+        h->hs_scale = std::ldexp(1.0f, s2);
+        h->hs_inv = std::ldexp(1.0f, -s2);
+    }
     for (int j = 0; j < N; ++j)
         for (int i = 0; i < N; ++i) {
             uint16_t m = 0;
@@ -398,7 +460,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     CREATE_TRY(up(h->f[2], lat->u0, (size_t)N * N * 8));
     {
         LbmArgs a = h->lbm_args(2, 0);
-        CREATE_TRY(launch_lbm_init(a, static_cast<const double *>(h->f[2]), h->fp64, st));
+        CREATE_TRY(launch_lbm_init(a, static_cast<const double *>(h->f[2]), h->prec, st));
     }
     CREATE_TRY(hipMemsetAsync(h->f[2], 0, L.f_bytes, st));
     CREATE_TRY(hipStreamSynchronize(st));
@@ -415,7 +477,7 @@ int hyb_interface_exchange(hyb_handle *h, int direction) {
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "interface exchange needs a coarse mesh");
     if (direction == HYB_F2C) {
         LbmArgs a = h->lbm_args(h->cur, -1);
-        HIP_TRY(h, launch_f2c(a, h->fc_idx, h->fc_w, h->nfc, h->ufc, h->fp64, h->stream));
+        HIP_TRY(h, launch_f2c(a, h->fc_idx, h->fc_w, h->nfc, h->ufc, h->prec, h->stream));
     } else if (direction == HYB_C2F) {
         const double *xb = h->solved_this_step ? h->cd.x1 : h->cd.xn;
         HIP_TRY(h, launch_c2f(h->c2f_idx, h->c2f_w, 4 * (h->N - 1), h->cd.xn, xb, h->bc_a, h->bc_b, h->stream));
@@ -460,7 +522,7 @@ int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
     const bool general = h->any_neumann;
     // the two-step kernel addresses a population buffer with 32-bit byte
     // offsets, so it serves buffers below 4 GiB (N up to about 11500 in FP64)
-    const bool small_buf = 9.0 * (double)h->lay.plane * (h->fp64 ? 8.0 : 4.0) < 4294967295.0;
+    const bool small_buf = 9.0 * (double)h->lay.plane * (double)storage_bytes(h->prec) < 4294967295.0;
     const bool fuse2 = !general && h->steps_per_launch == 2 && small_buf;
     auto take_pair = [&](hipEvent_t *e0, hipEvent_t *e1) -> hipError_t {
         if (2 * (h->ev_used + 1) > h->ev_pool.size()) {
@@ -492,14 +554,14 @@ int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
         const int take = (fuse2 && n_sub - s >= 2) ? 2 : 1;
         if (take == 2) {
             a.lam2 = (double)(h->jsub + 2) / (double)h->eta;
-            HIP_TRY(h, launch_lbm_step2(a, h->fp64, h->stream));
+            HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream));
         } else {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timed && general) {
                 HIP_TRY(h, take_pair(&e0, &e1));
                 h->ev_launches[h->ev_used - 1] = 1;
             }
-            HIP_TRY(h, launch_lbm_step(a, h->fp64, general, h->stream, e0, e1));
+            HIP_TRY(h, launch_lbm_step(a, h->prec, general, h->stream, e0, e1));
         }
         if (g0) h->ev_launches[gslot] += 1;
         h->cur = dst;
@@ -589,7 +651,7 @@ int hyb_concentration(hyb_handle *h, int which, double *out, int out_is_device) 
         const size_t bytes = (size_t)h->N * h->N * 8;
         double *dev = out_is_device ? out : static_cast<double *>(h->f[h->spare(h->cur == h->frozen ? -1 : h->cur)]);
         LbmArgs a = h->lbm_args(h->cur, -1);
-        HIP_TRY(h, launch_concentration(a, dev, h->fp64, h->stream));
+        HIP_TRY(h, launch_concentration(a, dev, h->prec, h->stream));
         if (!out_is_device) HIP_TRY(h, hipMemcpyAsync(out, dev, bytes, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         return HYB_OK;
@@ -611,34 +673,42 @@ int hyb_concentration(hyb_handle *h, int which, double *out, int out_is_device) 
 int hyb_get_populations(hyb_handle *h, double *out) {
     if (!h || !out) return HYB_EINVAL;
     const int N = h->N, P = h->lay.pitch;
-    const size_t elem = h->fp64 ? 8 : 4;
+    const size_t elem = storage_bytes(h->prec);
     std::vector<char> stage((size_t)9 * h->lay.plane * elem);
     HIP_TRY(h, hipMemcpyAsync(stage.data(), h->f[h->cur], stage.size(), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    for (int q = 0; q < kQ; ++q)
+    for (int q = 0; q < kQ; ++q) {
+        const float wc = (float)kW[q] * h->hs_cref;
         for (int j = 0; j < N; ++j)
             for (int i = 0; i < N; ++i) {
                 const size_t s = (size_t)q * h->lay.plane + (size_t)j * P + i;
-                out[(size_t)q * N * N + (size_t)j * N + i] =
-                    h->fp64 ? reinterpret_cast<const double *>(stage.data())[s]
-                            : (double)reinterpret_cast<const float *>(stage.data())[s];
+                double v;
+                if (h->solid_host[(size_t)j * N + i]) v = 0.0;
+                else if (h->prec == HYB_FP64) v = reinterpret_cast<const double *>(stage.data())[s];
+                else if (h->prec == HYB_FP32) v = reinterpret_cast<const float *>(stage.data())[s];
+                else v = f16_to_f32(reinterpret_cast<const uint16_t *>(stage.data())[s]) * h->hs_inv + wc;
+                out[(size_t)q * N * N + (size_t)j * N + i] = v;
             }
+    }
     return HYB_OK;
 }
 
 int hyb_set_populations(hyb_handle *h, const double *fin) {
     if (!h || !fin) return HYB_EINVAL;
     const int N = h->N, P = h->lay.pitch;
-    const size_t elem = h->fp64 ? 8 : 4;
+    const size_t elem = storage_bytes(h->prec);
     std::vector<char> stage((size_t)9 * h->lay.plane * elem, 0);
-    for (int q = 0; q < kQ; ++q)
+    for (int q = 0; q < kQ; ++q) {
+        const float wc = (float)kW[q] * h->hs_cref;
         for (int j = 0; j < N; ++j)
             for (int i = 0; i < N; ++i) {
                 const size_t s = (size_t)q * h->lay.plane + (size_t)j * P + i;
                 const double v = fin[(size_t)q * N * N + (size_t)j * N + i];
-                if (h->fp64) reinterpret_cast<double *>(stage.data())[s] = v;
-                else reinterpret_cast<float *>(stage.data())[s] = (float)v;
+                if (h->prec == HYB_FP64) reinterpret_cast<double *>(stage.data())[s] = v;
+                else if (h->prec == HYB_FP32) reinterpret_cast<float *>(stage.data())[s] = (float)v;
+                else reinterpret_cast<uint16_t *>(stage.data())[s] = f32_to_f16(((float)v - wc) * h->hs_scale);
             }
+    }
     HIP_TRY(h, hipMemcpyAsync(h->f[h->frozen], stage.data(), stage.size(), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->cur = h->frozen;

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "hyb.h"
+
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -18,6 +20,8 @@ constexpr int kQ = 9;
 constexpr int kCx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int kCy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int kOpp[kQ] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr double kW[kQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
 // Per-node lattice flags (uint16): bit q (1..8) = the upstream neighbour
 // x - e_q is a solid node inside the patch (halfway bounce-back); bit 15 =
@@ -69,19 +73,51 @@ struct LbmArgs {
     double lam2;             // (j + 1) / eta: second step of a two-step launch
     int clamp;
     unsigned long long *counters;
+    // FP16 shifted storage: stored g = (f - w_q c_ref) * scale (binary16);
+    // f = g / scale + w_q c_ref.  hs_wc[q] = w_q c_ref, scale a power of two.
+    float hs_scale;
+    float hs_inv;
+    float hs_wc[kQ];
 };
 
-// Launchers (lbm_kernels.hip); T is float or double via `fp64`.
+// Population storage policy: FP64 and FP32 store what they compute; FP16
+// shifted storage keeps g in binary16 and computes in FP32.  ld and st
+// take the plane index q of the value.
+template <typename S> struct Pop;
+template <> struct Pop<double> {
+    typedef double T;
+    static __device__ __forceinline__ double ld(double x, int, const LbmArgs &) { return x; }
+    static __device__ __forceinline__ double st(double f, int, const LbmArgs &) { return f; }
+};
+template <> struct Pop<float> {
+    typedef float T;
+    static __device__ __forceinline__ float ld(float x, int, const LbmArgs &) { return x; }
+    static __device__ __forceinline__ float st(float f, int, const LbmArgs &) { return f; }
+};
+template <> struct Pop<_Float16> {
+    typedef float T;
+    // g * (1 / scale) is exact (power of two), so the FMA rounds once
+    static __device__ __forceinline__ float ld(_Float16 x, int q, const LbmArgs &a) {
+        return __builtin_fmaf(static_cast<float>(x), a.hs_inv, a.hs_wc[q]);
+    }
+    // round to nearest even
+    static __device__ __forceinline__ _Float16 st(float f, int q, const LbmArgs &a) {
+        return static_cast<_Float16>((f - a.hs_wc[q]) * a.hs_scale);
+    }
+};
+
+// Launchers (lbm_kernels.hip); `prec` is HYB_FP64, HYB_FP32 or HYB_FP16S
+// (storage double, float or binary16).
 // One fine step.  general_perimeter: run the perimeter in the separate
 // kernel that supports the Neumann closure (else one fused launch with the
 // Dirichlet closure).  The optional events bracket the interior sweep.
-hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, bool general_perimeter, hipStream_t s,
+hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, hipStream_t s,
                            hipEvent_t sweep_begin = nullptr, hipEvent_t sweep_end = nullptr);
 // Two fine steps in one launch (Dirichlet closure on every perimeter slot):
 // a.src holds f*(j), a.dst receives f*(j+2); u^p at a.lam, then a.lam2.
-hipError_t launch_lbm_step2(const LbmArgs &a, bool fp64, hipStream_t s);
-hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, bool fp64, hipStream_t s);
-hipError_t launch_concentration(const LbmArgs &a, double *out, bool fp64, hipStream_t s);
+hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s);
+hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, int prec, hipStream_t s);
+hipError_t launch_concentration(const LbmArgs &a, double *out, int prec, hipStream_t s);
 
 struct CoarseDev {
     int M;
@@ -119,7 +155,7 @@ hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iter
 // Interface transfers (coarse_kernels.hip)
 hipError_t launch_c2f(const int *idx, const double *w, int nslots, const double *xa, const double *xb,
                       double *a, double *b, hipStream_t s);
-hipError_t launch_f2c(const LbmArgs &lat, const int *idx, const double *w, int nfc, double *ufc, bool fp64,
+hipError_t launch_f2c(const LbmArgs &lat, const int *idx, const double *w, int nfc, double *ufc, int prec,
                       hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -1,29 +1,26 @@
 // D2Q9 advection-diffusion-reaction lattice Boltzmann kernels for gfx950.
 //
-// One fine step (Sec. 4.1, eqs. LBE and Collision) is a fused pull sweep:
+// One fine step (Sec. 4.1, eqs. LBE and Collision) is a fused pull update:
 // each node gathers the post-collision populations of its upstream
 // neighbours (x - e_i), replaces those whose upstream node is solid by its
 // own reversed population (halfway bounce-back), closes the populations
 // whose upstream node lies outside the patch with the maximum-entropy
 // closure of Sec. 4.1.1 (perimeter nodes only), and relaxes towards the
 // equilibrium of eq. (LBM_feq) with the first-order reaction source
-// -k w_i u.  Populations are structure-of-arrays planes [9][N][pitch].
+// -k w_i u.  Populations are structure-of-arrays planes [9][N][pitch] in
+// the storage type S (double, float, or binary16 holding the shifted and
+// scaled g of Pop<_Float16>); arithmetic is in Pop<S>::T (double or float),
+// the closures in FP64.
 //
-// The sweep is HBM-bound: per fluid node 9 population loads, 9 stores, the
-// two velocity components (FP32) and the 16-bit flag word.  One launch per
-// fine step covers the whole patch: consecutive interior nodes sit on
-// consecutive lanes (coalesced, one pass over every plane) and the 4(N-1)
-// perimeter nodes, with the Dirichlet closure, run in the same launch.
-// When some perimeter slots use the Neumann closure (a Newton solve in
-// FP64), those nodes run in a separate kernel so its register demand does
-// not lower the occupancy of the interior sweep.
+// Default path: two fine steps per launch (lbm_sweep2_kernel, temporal
+// blocking through LDS).  Single-step kernels serve odd step counts
+// (lbm_sweep_kernel, perimeter Dirichlet slots in the same launch) and
+// handles with Neumann slots (lbm_bulk_kernel + lbm_perimeter_kernel, whose
+// FP64 Newton solve would otherwise lower the occupancy of the sweep).
 #include "hyb_impl.h"
 
 namespace hyb {
 namespace {
-
-constexpr double kW[kQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
-                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
 // BGK collision with reaction, written as
 //   f*_i = (1 - w) f_i + w_i [ w u (1 + 3 e.v + 9/2 (e.v)^2 - 3/2 v.v) - k u ],
@@ -55,276 +52,161 @@ __device__ __forceinline__ T collide(T (&f)[kQ], T vx, T vy, T omega, T k) {
 __device__ __forceinline__ bool finite_val(double x) { return x - x == 0.0; }
 __device__ __forceinline__ bool finite_val(float x) { return x - x == 0.0f; }
 
+// per-node reaction rate (k field in the arithmetic type) or the uniform one
 template <typename T>
 __device__ __forceinline__ T node_k(const LbmArgs &a, int n) {
     return a.kfield ? static_cast<const T *>(a.kfield)[n] : T(a.k);
 }
 
-// ---------------------------------------------------------------------------
-// interior node update: every upstream node of (i, j), 1 <= i, j <= N-2, is
-// inside the patch.  The nine loads use the pull address, or the node's
-// own opposite population where the flag word marks a solid upstream node.
-// Stores are non-temporal: the destination plane is not read again before
-// the whole sweep has finished, so it should not displace source lines
-// from the caches.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void interior_node(const LbmArgs &a, const T *__restrict__ src, T *__restrict__ dst,
-                                              int n, int S, int P, T omega) {
-    const unsigned m = a.mask[n];
-    if (m & kMaskSolid) return;
-    T f[kQ];
-    f[0] = src[n];
-#pragma unroll
-    for (int q = 1; q < kQ; ++q) {
-        const int pull = q * S + n - kCx[q] - kCy[q] * P;
-        const int back = kOpp[q] * S + n;
-        f[q] = src[((m >> q) & 1u) ? back : pull];
-    }
-    const T vx = T(a.vx[n]);
-    const T vy = T(a.vy[n]);
-    const T u = collide<T>(f, vx, vy, omega, node_k<T>(a, n));
-    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(f[q], &dst[q * S + n]);
+// Perimeter slot of perimeter node (i, j) (inverse of slot_to_node).
+__device__ __forceinline__ int perimeter_slot(int N, int i, int j) {
+    if (j == 0) return i;
+    if (j == N - 1) return N + i;
+    if (i == 0) return 2 * N + j - 1;
+    return 3 * N - 2 + j - 1;
 }
 
-// Perimeter node with the Dirichlet closure of eq. (LBM_Dir): unknown
-// populations (upstream node outside the patch) share the mass deficit
-// R = u^p - sum_known f in proportion to w_i; sums and R in FP64.
+// bit q set: the upstream node x - e_q lies outside the patch
+__device__ __forceinline__ unsigned outside_bits(int N, int i, int j) {
+    unsigned u = 0;
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) {
+        const int si = i - kCx[q], sj = j - kCy[q];
+        if (si < 0 || si >= N || sj < 0 || sj >= N) u |= 1u << q;
+    }
+    return u;
+}
+
+// Dirichlet closure of eq. (LBM_Dir): the unknowns U share the mass deficit
+// R = u^p - sum_known f in proportion to w_i; sums in FP64.  u^p is the
+// eq. (MTS) value (1 - lam) a + lam b of slot p.  R < 0 (no non-negative
+// solution) is reported; with clamp the unknowns become 0, otherwise the
+// closed form is kept.
 template <typename T>
-__device__ __forceinline__ void perimeter_dirichlet_node(const LbmArgs &a, const T *__restrict__ src,
-                                                         T *__restrict__ dst, int p, int S, int P, T omega) {
-    const int N = a.N;
-    int i, j;
-    slot_to_node(N, p, i, j);
-    const int n = j * P + i;
-    const unsigned m = a.mask[n];
-    if (m & kMaskSolid) return;
-    T f[kQ];
-    unsigned unknown = 0;
+__device__ __forceinline__ bool dirichlet_close(const LbmArgs &a, T (&f)[kQ], unsigned unknown, int p,
+                                                double lam) {
     double known = 0.0, wsum = 0.0;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-        const int si = i - kCx[q], sj = j - kCy[q];
-        if (si < 0 || si >= N || sj < 0 || sj >= N) {
-            unknown |= 1u << q;
-            wsum += kW[q];
-            f[q] = T(0);
-        } else {
-            f[q] = src[((m >> q) & 1u) ? kOpp[q] * S + n : q * S + sj * P + si];
-            known += double(f[q]);
-        }
+        if ((unknown >> q) & 1u) wsum += kW[q];
+        else known += double(f[q]);
     }
-    double R = (1.0 - a.lam) * a.bc_a[p] + a.lam * a.bc_b[p] - known;
+    double R = (1.0 - lam) * a.bc_a[p] + lam * a.bc_b[p] - known;
     const bool bad = R < 0.0;
     if (bad && a.clamp) R = 0.0;
     const double scale = R / wsum;
 #pragma unroll
     for (int q = 0; q < kQ; ++q)
         if ((unknown >> q) & 1u) f[q] = T(kW[q] * scale);
-    if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
-    const T u = collide<T>(f, T(a.vx[n]), T(a.vy[n]), omega, node_k<T>(a, n));
-    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[q * S + n] = f[q];
+    return bad;
 }
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) in
-// round-robin order.  Interior tile t of T is given to workgroup b so that
-// XCD b % 8 sweeps one contiguous eighth of the tiles in row-major order:
-// the lines a tile shares with its x- and y-neighbours (shifted pulls,
-// bounce-back reads) are then fetched into the same L2.
+// round-robin order.  Tile t of T is given to workgroup b so that XCD b % 8
+// sweeps one contiguous eighth of the tiles in row-major order: the lines a
+// tile shares with its neighbours (pulls, halos) are then fetched into the
+// same L2.
 __device__ __forceinline__ int xcd_tile(int b, int T) {
     const int x = b & 7, k = b >> 3;
     const int q = T >> 3, r = T & 7;
     return x * q + (x < r ? x : r) + k;
 }
 
-// Node groups: one lane owns V consecutive nodes of a row and moves each
-// population plane with one aligned V-element load and store.  All nine
-// pulls are issued without waiting for the flag word; bounce-back values
-// replace them afterwards.  V = 1 is used: on the 2048^2 and 4096^2 pore
-// workloads wider lanes (V = 2, 4 in FP32, 2 in FP64) measured equal or
-// slower.
-typedef float vec4f __attribute__((ext_vector_type(4)));
-typedef float vec2f __attribute__((ext_vector_type(2)));
-typedef double vec2d __attribute__((ext_vector_type(2)));
-typedef float vec1f __attribute__((ext_vector_type(1)));
-typedef double vec1d __attribute__((ext_vector_type(1)));
-template <typename T, int V> struct VecT;
-template <> struct VecT<float, 4> { typedef vec4f type; };
-template <> struct VecT<float, 2> { typedef vec2f type; };
-template <> struct VecT<float, 1> { typedef vec1f type; };
-template <> struct VecT<double, 2> { typedef vec2d type; };
-template <> struct VecT<double, 1> { typedef vec1d type; };
+// ---------------------------------------------------------------------------
+// Single fine step
+// ---------------------------------------------------------------------------
 
-// Interior group: nodes (V g .. V g + V - 1, j) of an interior row j.  For
-// every plane q the lane loads the aligned vector of row j - cy_q at its
-// own columns; the pull x - e_q needs those columns shifted by -cx_q, whose
-// one missing element comes from the neighbouring lane (wave shuffle) or,
-// at a wave edge, from a scalar load.  Bounce-back values f*_opp(x) come
-// from the aligned vector of plane opp at row j (already loaded when
-// cy_opp = 0, one predicated extra load otherwise).  Perimeter columns
-// (0 and N-1) belong to the perimeter slots and are left untouched; solid
-// nodes are written as zero.
-template <typename T, int V>
-__device__ __forceinline__ void interior_group(const LbmArgs &a, const T *__restrict__ src, T *__restrict__ dst,
-                                               int j, int g, int S, int P, T omega) {
-    typedef typename VecT<T, V>::type VT;
-    const int N = a.N;
-    const int c0 = V * g;                  // first column of the group
-    const int row = j * P;
-    const int lane = threadIdx.x & 63;
-    // flag words and velocities of the V nodes (one aligned load each);
-    // columns outside 1..N-2 act as solid here
-    unsigned m[V];
-    float vxs[V], vys[V];
-    if constexpr (V == 4) {
-        const uint2 mm = *reinterpret_cast<const uint2 *>(a.mask + row + c0);
-        m[0] = mm.x & 0xFFFFu; m[1] = mm.x >> 16; m[2] = mm.y & 0xFFFFu; m[3] = mm.y >> 16;
-    } else if constexpr (V == 2) {
-        const unsigned mm = *reinterpret_cast<const unsigned *>(a.mask + row + c0);
-        m[0] = mm & 0xFFFFu; m[1] = mm >> 16;
-    } else {
-        m[0] = a.mask[row + c0];
+// Interior node (1 <= i, j <= N-2): every upstream node is inside the
+// patch.  The nine pulls are issued before the flag word is known;
+// bounce-back values replace them afterwards.  Stores are non-temporal: the
+// destination plane is not read again before the sweep has finished.
+template <typename S>
+__device__ __forceinline__ void interior_node(const LbmArgs &a, const S *__restrict__ src, S *__restrict__ dst,
+                                              int n, int plane, int P) {
+    typedef typename Pop<S>::T T;
+    S raw[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) raw[q] = src[q * plane + n - kCx[q] - kCy[q] * P];
+    const unsigned m = a.mask[n];
+    if (m & kMaskSolid) return;
+    const float vx = a.vx[n], vy = a.vy[n];
+    T f[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) f[q] = Pop<S>::ld(raw[q], q, a);
+    if (m & 0x1FEu) {
+#pragma unroll
+        for (int q = 1; q < kQ; ++q)
+            if ((m >> q) & 1u) f[q] = Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a);
     }
-    {
-        typedef typename VecT<float, V>::type VF;
-        const VF xv = *reinterpret_cast<const VF *>(a.vx + row + c0);
-        const VF yv = *reinterpret_cast<const VF *>(a.vy + row + c0);
+    const T u = collide<T>(f, T(vx), T(vy), T(a.omega), node_k<T>(a, n));
+    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
-        for (int k = 0; k < V; ++k) { vxs[k] = xv[k]; vys[k] = yv[k]; }
-    }
-    bool any_fluid = false;
-#pragma unroll
-    for (int k = 0; k < V; ++k) {
-        const int c = c0 + k;
-        if (c < 1 || c > N - 2) m[k] = kMaskSolid;
-        any_fluid |= !(m[k] & kMaskSolid);
-    }
-    // every lane takes part in the shuffles below, so no early return before them
-    VT raw[kQ];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q)
-        raw[q] = *reinterpret_cast<const VT *>(src + q * S + (j - kCy[q]) * P + c0);
-    T f[V][kQ];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        if (kCx[q] == 0) {
-#pragma unroll
-            for (int k = 0; k < V; ++k) f[k][q] = raw[q][k];
-        } else if (kCx[q] == 1) {       // pull from column c - 1
-            T prev = __shfl_up(raw[q][V - 1], 1, 64);
-            if (lane == 0) prev = c0 > 0 ? src[q * S + (j - kCy[q]) * P + c0 - 1] : T(0);
-            f[0][q] = prev;
-#pragma unroll
-            for (int k = 1; k < V; ++k) f[k][q] = raw[q][k - 1];
-        } else {                         // pull from column c + 1
-            T next = __shfl_down(raw[q][0], 1, 64);
-            if (lane == 63) next = src[q * S + (j - kCy[q]) * P + c0 + V];
-#pragma unroll
-            for (int k = 0; k + 1 < V; ++k) f[k][q] = raw[q][k + 1];
-            f[V - 1][q] = next;
-        }
-    }
-    if (!any_fluid) return;
-    // halfway bounce-back from the node's own opposite population
-    unsigned bb = 0;
-#pragma unroll
-    for (int k = 0; k < V; ++k)
-        if (!(m[k] & kMaskSolid)) bb |= m[k];
-    if (bb & 0x1FEu) {
-#pragma unroll
-        for (int q = 1; q < kQ; ++q) {
-            if (!((bb >> q) & 1u)) continue;
-            const int o = kOpp[q];
-            VT own;
-            if (kCy[o] == 0) own = raw[o];
-            else own = *reinterpret_cast<const VT *>(src + o * S + row + c0);
-#pragma unroll
-            for (int k = 0; k < V; ++k)
-                if ((m[k] >> q) & 1u) f[k][q] = own[k];
-        }
-    }
-    T out[V][kQ];
-    const bool edge = c0 == 0 || c0 + V > N - 1;   // group holds a perimeter or padding column
-#pragma unroll
-    for (int k = 0; k < V; ++k) {
-        const int n = row + c0 + k;
-        if (m[k] & kMaskSolid) {
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) out[k][q] = T(0);
-            continue;
-        }
-        const T u = collide<T>(f[k], T(vxs[k]), T(vys[k]), omega, node_k<T>(a, n));
-        if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) out[k][q] = f[k][q];
-    }
-    if (!edge) {
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            VT w;
-#pragma unroll
-            for (int k = 0; k < V; ++k) w[k] = out[k][q];
-            __builtin_nontemporal_store(w, reinterpret_cast<VT *>(dst + q * S + row + c0));
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            const int c = c0 + k;
-            if (c < 1 || c > N - 2) continue;
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) dst[q * S + row + c] = out[k][q];
-        }
-    }
+    for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(Pop<S>::st(f[q], q, a), &dst[q * plane + n]);
 }
 
-// One fine step over the whole patch in a single launch: the first
-// `tiles` workgroups take the interior rows, 256 lanes x V nodes of one
-// row each (tile t covers row 1 + t / row_blocks), the remaining workgroups
-// take the 4(N-1) perimeter slots with the Dirichlet closure.
-template <typename T, int V>
+// Perimeter slot p with the Dirichlet closure.
+template <typename S>
+__device__ __forceinline__ void perimeter_dirichlet_node(const LbmArgs &a, const S *__restrict__ src,
+                                                         S *__restrict__ dst, int p, int plane, int P) {
+    typedef typename Pop<S>::T T;
+    const int N = a.N;
+    int i, j;
+    slot_to_node(N, p, i, j);
+    const int n = j * P + i;
+    const unsigned m = a.mask[n];
+    if (m & kMaskSolid) return;
+    const unsigned unknown = outside_bits(N, i, j);
+    T f[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        if ((unknown >> q) & 1u) f[q] = T(0);
+        else if ((m >> q) & 1u) f[q] = Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a);
+        else f[q] = Pop<S>::ld(src[q * plane + (j - kCy[q]) * P + i - kCx[q]], q, a);
+    }
+    if (dirichlet_close<T>(a, f, unknown, p, a.lam)) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+    const T u = collide<T>(f, T(a.vx[n]), T(a.vy[n]), T(a.omega), node_k<T>(a, n));
+    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) dst[q * plane + n] = Pop<S>::st(f[q], q, a);
+}
+
+// One fine step over the whole patch in one launch: the first `tiles`
+// workgroups take interior rows (tile t covers row 1 + t / row_blocks,
+// 256 consecutive columns), the rest the 4(N-1) perimeter slots.
+template <typename S>
 __global__ void __launch_bounds__(256) lbm_sweep_kernel(LbmArgs a, int tiles, int row_blocks) {
     const int P = a.pitch;
-    const int S = static_cast<int>(a.plane);
-    const T *__restrict__ src = static_cast<const T *>(a.src);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
-    const T omega = T(a.omega);
+    const int plane = static_cast<int>(a.plane);
+    const S *__restrict__ src = static_cast<const S *>(a.src);
+    S *__restrict__ dst = static_cast<S *>(a.dst);
     const int b = blockIdx.x;
     if (b >= tiles) {
         const int p = (b - tiles) * blockDim.x + threadIdx.x;
-        if (p < 4 * (a.N - 1)) perimeter_dirichlet_node<T>(a, src, dst, p, S, P, omega);
+        if (p < 4 * (a.N - 1)) perimeter_dirichlet_node<S>(a, src, dst, p, plane, P);
         return;
     }
     const int t = xcd_tile(b, tiles);
     const int j = 1 + t / row_blocks;
-    const int g = (t % row_blocks) * blockDim.x + threadIdx.x;
-    // groups past the last column still join the wave's shuffles (their
-    // loads stay inside the row pitch, which is a multiple of 64 elements)
-    if (V * g < P) interior_group<T, V>(a, src, dst, j, g, S, P, omega);
+    const int i = 1 + (t % row_blocks) * blockDim.x + threadIdx.x;
+    if (i <= a.N - 2) interior_node<S>(a, src, dst, j * P + i, plane, P);
 }
 
-// Interior only (used with the general perimeter kernel when some slots
-// carry the Neumann closure).
-template <typename T>
+// Interior only (with the general perimeter kernel when some slots carry
+// the Neumann closure).
+template <typename S>
 __global__ void __launch_bounds__(256) lbm_bulk_kernel(LbmArgs a, int row_blocks) {
     const int P = a.pitch;
-    const int S = static_cast<int>(a.plane);
     const int j = 1 + blockIdx.x / row_blocks;
     const int i = 1 + (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
     if (i <= a.N - 2)
-        interior_node<T>(a, static_cast<const T *>(a.src), static_cast<T *>(a.dst), j * P + i, S, P, T(a.omega));
+        interior_node<S>(a, static_cast<const S *>(a.src), static_cast<S *>(a.dst), j * P + i,
+                         static_cast<int>(a.plane), P);
 }
 
 // ---------------------------------------------------------------------------
-// Maximum-entropy closures (Sec. 4.1.1), FP64.
+// Maximum-entropy closures (Sec. 4.1.1), FP64, for the general perimeter.
 //
-// Dirichlet, eq. (LBM_Dir): the unknowns U share the mass deficit
-// R = u^p - sum_{known} f in proportion to w_i.  If R < 0 the node is
-// counted; with clamp the unknowns become 0, otherwise the closed form is
-// kept (constraint met, negative unknowns).
+// Dirichlet, eq. (LBM_Dir): as dirichlet_close.
 //
 // Neumann, eq. (LBM_Neu): unknowns with e_i.n < 0 are w_i exp(-1 + g s_i),
 // s_i = -e_i.n > 0, where the Lagrange multiplier g solves
@@ -408,37 +290,36 @@ __device__ int closure_neumann(double (&f)[kQ], unsigned unknown, int sx, int sy
     return 0;
 }
 
-// ---------------------------------------------------------------------------
-// perimeter nodes: one thread per slot
-// ---------------------------------------------------------------------------
-template <typename T>
+// perimeter nodes, Dirichlet or Neumann per slot: one thread per slot
+template <typename S>
 __global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
+    typedef typename Pop<S>::T T;
     const int N = a.N;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= 4 * (N - 1)) return;
     int i, j;
     slot_to_node(N, p, i, j);
     const int P = a.pitch;
-    const int S = static_cast<int>(a.plane);
+    const int plane = static_cast<int>(a.plane);
     const int n = j * P + i;
     const unsigned m = a.mask[n];
     if (m & kMaskSolid) return;
-    const T *__restrict__ src = static_cast<const T *>(a.src);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const S *__restrict__ src = static_cast<const S *>(a.src);
+    S *__restrict__ dst = static_cast<S *>(a.dst);
 
     double f[kQ], own[kQ];
     unsigned unknown = 0;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-        own[q] = double(src[q * S + n]);
+        own[q] = double(Pop<S>::ld(src[q * plane + n], q, a));
         const int si = i - kCx[q], sj = j - kCy[q];
         if (si < 0 || si >= N || sj < 0 || sj >= N) {
             unknown |= 1u << q;
             f[q] = 0.0;
         } else if ((m >> q) & 1u) {
-            f[q] = double(src[kOpp[q] * S + n]);
+            f[q] = double(Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a));
         } else {
-            f[q] = double(src[q * S + sj * P + si]);
+            f[q] = double(Pop<S>::ld(src[q * plane + sj * P + si], q, a));
         }
     }
     const int kind = a.bc_kind ? a.bc_kind[p] : 0;
@@ -459,7 +340,7 @@ __global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
     const T u = collide<T>(g, T(a.vx[n]), T(a.vy[n]), T(a.omega), node_k<T>(a, n));
     if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[q * S + n] = g[q];
+    for (int q = 0; q < kQ; ++q) dst[q * plane + n] = Pop<S>::st(g[q], q, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,53 +348,16 @@ __global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
 //
 // A workgroup owns a TW x TH tile of the patch.  First half: every node of
 // the tile grown by one ring (clipped to the patch) takes fine step j+1
-// from the source buffer; the results stay in LDS.  Second half: the
-// tile's own nodes take step j+2 from LDS and go to the destination
-// buffer.  Per node the arithmetic is that of the single-step sweep
-// (pull, halfway bounce-back, eq. (LBM_Dir) closure at perimeter nodes
-// with u^p at lam = (j+1)/eta, then (j+2)/eta, collision).  Ring nodes are
-// computed by every tile that borders them, so only the tile that owns a
-// node counts its infeasible closures and non-finite values.  HBM traffic
-// for two steps is one read of the state (the ring-2 halo is mostly served
-// by L2) and one write.
+// from the source buffer; the results stay in LDS (arithmetic type).
+// Second half: the tile's own nodes take step j+2 from LDS and go to the
+// destination buffer.  Per node the arithmetic is that of the single-step
+// sweep (pull, halfway bounce-back, eq. (LBM_Dir) closure at perimeter
+// nodes with u^p at lam = (j+1)/eta, then (j+2)/eta, collision).  Ring
+// nodes are computed by every tile that borders them, so only the tile
+// that owns a node counts its infeasible closures and non-finite values.
+// HBM traffic for two steps is one read of the state (the ring-2 halo is
+// mostly served by L2) and one write.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int perimeter_slot(int N, int i, int j) {
-    if (j == 0) return i;
-    if (j == N - 1) return N + i;
-    if (i == 0) return 2 * N + j - 1;
-    return 3 * N - 2 + j - 1;
-}
-
-__device__ __forceinline__ unsigned outside_bits(int N, int i, int j) {
-    unsigned u = 0;
-#pragma unroll
-    for (int q = 1; q < kQ; ++q) {
-        const int si = i - kCx[q], sj = j - kCy[q];
-        if (si < 0 || si >= N || sj < 0 || sj >= N) u |= 1u << q;
-    }
-    return u;
-}
-
-// eq. (LBM_Dir) on populations held in T, sums in FP64 (the same
-// operations, in the same order, as perimeter_dirichlet_node)
-template <typename T>
-__device__ __forceinline__ bool dirichlet_close(const LbmArgs &a, T (&f)[kQ], unsigned unknown, int p,
-                                                double lam) {
-    double known = 0.0, wsum = 0.0;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        if ((unknown >> q) & 1u) wsum += kW[q];
-        else known += double(f[q]);
-    }
-    double R = (1.0 - lam) * a.bc_a[p] + lam * a.bc_b[p] - known;
-    const bool bad = R < 0.0;
-    if (bad && a.clamp) R = 0.0;
-    const double scale = R / wsum;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q)
-        if ((unknown >> q) & 1u) f[q] = T(kW[q] * scale);
-    return bad;
-}
 
 // Raw buffer access (gfx9 buffer instructions): the array base and size
 // live in one SGPR resource, the population plane offset q * plane is the
@@ -524,7 +368,7 @@ typedef __amdgpu_buffer_rsrc_t BufRsrc;
 __device__ __forceinline__ BufRsrc buf_rsrc(const void *p, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
 }
-template <typename T> struct Buf;
+template <typename S> struct Buf;
 template <> struct Buf<float> {
     static __device__ __forceinline__ float load(BufRsrc r, unsigned v, unsigned s) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
@@ -542,26 +386,31 @@ template <> struct Buf<double> {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(Raw, x), r, v, s, 2);
     }
 };
+template <> struct Buf<_Float16> {
+    static __device__ __forceinline__ _Float16 load(BufRsrc r, unsigned v, unsigned s) {
+        return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+    }
+    static __device__ __forceinline__ void store_nt(_Float16 x, BufRsrc r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, 2);
+    }
+};
 
-#ifndef SWEEP2_WAVES
-#define SWEEP2_WAVES 1
-#endif
-template <typename T, int TW, int TH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP2_WAVES)))
-lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
+template <typename S, int TW, int TH>
+__global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
+    typedef typename Pop<S>::T T;
     constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
     constexpr int ROUNDS1 = (R1 + 255) / 256;
     static_assert((TW * TH) % 256 == 0 && 256 % TW == 0, "second half: whole rows per wave round");
     constexpr int ROUNDS2 = TW * TH / 256;
-    constexpr unsigned sz = sizeof(T);
+    constexpr unsigned sz = sizeof(S);
     __shared__ T lds[kQ][H1][W1];
 
     const int N = a.N;
     const int P = a.pitch;
-    const unsigned S = static_cast<unsigned>(a.plane);
+    const unsigned SP = static_cast<unsigned>(a.plane);
     const unsigned NP = static_cast<unsigned>(N) * static_cast<unsigned>(P);
-    const BufRsrc fsrc = buf_rsrc(a.src, kQ * S * sz);
-    const BufRsrc fdst = buf_rsrc(a.dst, kQ * S * sz);
+    const BufRsrc fsrc = buf_rsrc(a.src, kQ * SP * sz);
+    const BufRsrc fdst = buf_rsrc(a.dst, kQ * SP * sz);
     const BufRsrc mrs = buf_rsrc(a.mask, NP * 2u);
     const BufRsrc vxr = buf_rsrc(a.vx, NP * 4u);
     const BufRsrc vyr = buf_rsrc(a.vy, NP * 4u);
@@ -578,7 +427,7 @@ lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
     // inside the buffer.  The left column (i = 0) clamps every pull onto
     // the patch.  Values fetched for upstream nodes outside the patch are
     // replaced by the closure.
-    T f[ROUNDS1][kQ];
+    S raw[ROUNDS1][kQ];
     unsigned m[ROUNDS1];
     float vx1[ROUNDS1], vy1[ROUNDS1];
 #pragma unroll
@@ -599,13 +448,13 @@ lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
                                           static_cast<unsigned>(jm * P + i - 1) * sz};
 #pragma unroll
                 for (int q = 0; q < kQ; ++q)
-                    f[k][q] = Buf<T>::load(fsrc, base[1 + kCy[q]] + (1 - kCx[q]) * sz, q * S * sz);
+                    raw[k][q] = Buf<S>::load(fsrc, base[1 + kCy[q]] + (1 - kCx[q]) * sz, q * SP * sz);
             } else {
 #pragma unroll
                 for (int q = 0; q < kQ; ++q) {
                     const int sj = kCy[q] == 1 ? jm : kCy[q] == -1 ? jp : j;
                     const int si = kCx[q] == -1 ? 1 : 0;           // column -1 clamped to 0
-                    f[k][q] = Buf<T>::load(fsrc, static_cast<unsigned>(sj * P + si) * sz, q * S * sz);
+                    raw[k][q] = Buf<S>::load(fsrc, static_cast<unsigned>(sj * P + si) * sz, q * SP * sz);
                 }
             }
         }
@@ -618,19 +467,24 @@ lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
         const int i = x0 - 1 + c, j = y0 - 1 + r;
         const unsigned n = static_cast<unsigned>(j * P + i);
         const bool owned = r >= 1 && r <= TH && c >= 1 && c <= TW;
+        T f[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) f[q] = Pop<S>::ld(raw[k][q], q, a);
         if (m[k] & 0x1FEu) {
 #pragma unroll
             for (int q = 1; q < kQ; ++q)
-                if ((m[k] >> q) & 1u) f[k][q] = Buf<T>::load(fsrc, n * sz, kOpp[q] * S * sz);
+                if ((m[k] >> q) & 1u)
+                    f[q] = Pop<S>::ld(Buf<S>::load(fsrc, n * sz, kOpp[q] * SP * sz), kOpp[q], a);
         }
         if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
-            const bool bad = dirichlet_close<T>(a, f[k], outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
+            const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
             if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
         }
-        const T u = collide<T>(f[k], T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
+        const T u = collide<T>(f, T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
         if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+        // the second half reads what the next fine step would read from HBM
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[k][q];
+        for (int q = 0; q < kQ; ++q) lds[q][r][c] = Pop<S>::ld(Pop<S>::st(f[q], q, a), q, a);
     }
 
     // flags and velocities of the owned nodes, fetched before the barrier
@@ -675,135 +529,125 @@ lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
         const T u = collide<T>(g, T(vx2[k]), T(vy2[k]), omega, node_k<T>(a, static_cast<int>(n)));
         if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) Buf<T>::store_nt(g[q], fdst, n * sz, q * S * sz);
+        for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(g[q], q, a), fdst, n * sz, q * SP * sz);
     }
 }
 
 // ---------------------------------------------------------------------------
 // initial state: f*(0) = collide(f^eq(u0)) at fluid nodes (Sec. 6.2, item i)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename S>
 __global__ void __launch_bounds__(256) lbm_init_kernel(LbmArgs a, const double *__restrict__ u0) {
+    typedef typename Pop<S>::T T;
     const int N = a.N;
     const int j = blockIdx.x;
     const int P = a.pitch;
-    const int S = static_cast<int>(a.plane);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const int plane = static_cast<int>(a.plane);
+    S *__restrict__ dst = static_cast<S *>(a.dst);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const int n = j * P + i;
-        T f[kQ];
         if (a.mask[n] & kMaskSolid) {
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) f[q] = T(0);
-        } else {
-            const T u = T(u0[j * N + i]);
-            const T vx = T(a.vx[n]), vy = T(a.vy[n]);
-            const T usq = T(1.5) * (vx * vx + vy * vy);
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const T ev = T(kCx[q]) * vx + T(kCy[q]) * vy;
-                f[q] = T(kW[q]) * u * (T(1) + T(3) * ev + T(4.5) * ev * ev - usq);
-            }
-            collide<T>(f, vx, vy, T(a.omega), node_k<T>(a, n));
+            for (int q = 0; q < kQ; ++q) dst[q * plane + n] = S(0);
+            continue;
         }
+        T f[kQ];
+        const T u = T(u0[j * N + i]);
+        const T vx = T(a.vx[n]), vy = T(a.vy[n]);
+        const T usq = T(1.5) * (vx * vx + vy * vy);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) dst[q * S + n] = f[q];
+        for (int q = 0; q < kQ; ++q) {
+            const T ev = T(kCx[q]) * vx + T(kCy[q]) * vy;
+            f[q] = T(kW[q]) * u * (T(1) + T(3) * ev + T(4.5) * ev * ev - usq);
+        }
+        collide<T>(f, vx, vy, T(a.omega), node_k<T>(a, n));
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) dst[q * plane + n] = Pop<S>::st(f[q], q, a);
     }
 }
 
 // u = sum_i f*_i / (1 - k): the collision removes k u from the node's mass.
-template <typename T>
+template <typename S>
 __global__ void __launch_bounds__(256) lbm_conc_kernel(LbmArgs a, double *__restrict__ out) {
+    typedef typename Pop<S>::T T;
     const int N = a.N;
     const int j = blockIdx.x;
     const int P = a.pitch;
-    const int S = static_cast<int>(a.plane);
-    const T *__restrict__ src = static_cast<const T *>(a.src);
+    const int plane = static_cast<int>(a.plane);
+    const S *__restrict__ src = static_cast<const S *>(a.src);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const int n = j * P + i;
         double u = 0.0;
         if (!(a.mask[n] & kMaskSolid)) {
-            for (int q = 0; q < kQ; ++q) u += double(src[q * S + n]);
+            for (int q = 0; q < kQ; ++q) u += double(Pop<S>::ld(src[q * plane + n], q, a));
             u /= (1.0 - double(node_k<T>(a, n)));
         }
         out[j * N + i] = u;
     }
 }
 
-// nodes per lane of the interior sweep (see VecT)
-#ifndef SWEEP_V
-#define SWEEP_V(T) 1
-#endif
-template <typename T>
+template <typename S>
 hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int np = 4 * (a.N - 1);
     const int row_blocks = (a.N - 2 + 255) / 256;
     const int interior_blocks = row_blocks * (a.N - 2);
     if (e0) (void)hipEventRecord(e0, s);
     if (!general_perimeter) {
-        constexpr int V = SWEEP_V(T);
-        const int vrow_blocks = ((a.N + V - 1) / V + 255) / 256;     // groups cover columns 0..N-1
-        const int vtiles = vrow_blocks * (a.N - 2);
         const int per_blocks = (np + 255) / 256;
-        auto kernel = lbm_sweep_kernel<T, V>;
-        hipLaunchKernelGGL(kernel, dim3(vtiles + per_blocks), dim3(256), 0, s, a, vtiles, vrow_blocks);
+        hipLaunchKernelGGL(lbm_sweep_kernel<S>, dim3(interior_blocks + per_blocks), dim3(256), 0, s, a,
+                           interior_blocks, row_blocks);
         if (e1) (void)hipEventRecord(e1, s);
     } else {
         if (interior_blocks > 0)
-            hipLaunchKernelGGL(lbm_bulk_kernel<T>, dim3(interior_blocks), dim3(256), 0, s, a, row_blocks);
+            hipLaunchKernelGGL(lbm_bulk_kernel<S>, dim3(interior_blocks), dim3(256), 0, s, a, row_blocks);
         if (e1) (void)hipEventRecord(e1, s);
-        hipLaunchKernelGGL(lbm_perimeter_kernel<T>, dim3((np + 127) / 128), dim3(128), 0, s, a);
+        hipLaunchKernelGGL(lbm_perimeter_kernel<S>, dim3((np + 127) / 128), dim3(128), 0, s, a);
     }
     return hipGetLastError();
 }
 
-// tile shape of the two-step sweep: LDS holds 9 planes of (TW+2) x (TH+2)
-// values
-// tile heights: 64 x 8 in both precisions (LDS 23.8 KB in FP32, six
-// workgroups per CU; 47.5 KB in FP64, three).  On the 2048^2 and 4096^2
-// pore workloads 64 x 8 FP32 tiles ran 14% faster than 64 x 16 ones (more
-// workgroups in flight hide the memory latency of the first half); FP64
-// measured the same with 4, 8 or 12 rows.
-#ifndef SWEEP2_TH32
-#define SWEEP2_TH32 8
-#endif
-#ifndef SWEEP2_TH64
-#define SWEEP2_TH64 8
-#endif
-template <typename T> struct Sweep2Tile;
-template <> struct Sweep2Tile<float> { static constexpr int TW = 64, TH = SWEEP2_TH32; };
-template <> struct Sweep2Tile<double> { static constexpr int TW = 64, TH = SWEEP2_TH64; };
+// Tile shape of the two-step sweep: LDS holds 9 planes of (TW+2) x (TH+2)
+// values of the arithmetic type.  64 x 8 in every precision (LDS 23.8 KB
+// with FP32 arithmetic, six workgroups per CU; 47.5 KB in FP64, three).  On
+// the 2048^2 and 4096^2 pore workloads 64 x 8 FP32 tiles ran 14% faster
+// than 64 x 16 ones (more workgroups in flight hide the memory latency of
+// the first half); FP64 measured the same with 4, 8 or 12 rows.
+constexpr int kTileW = 64, kTileH = 8;
 
-template <typename T>
+template <typename S>
 hipError_t step2_impl(const LbmArgs &a, hipStream_t s) {
-    constexpr int TW = Sweep2Tile<T>::TW, TH = Sweep2Tile<T>::TH;
-    auto kernel = lbm_sweep2_kernel<T, TW, TH>;
-    const int tx = (a.N + TW - 1) / TW, ty = (a.N + TH - 1) / TH;
+    auto kernel = lbm_sweep2_kernel<S, kTileW, kTileH>;
+    const int tx = (a.N + kTileW - 1) / kTileW, ty = (a.N + kTileH - 1) / kTileH;
     hipLaunchKernelGGL(kernel, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_lbm_step2(const LbmArgs &a, bool fp64, hipStream_t s) {
-    return fp64 ? step2_impl<double>(a, s) : step2_impl<float>(a, s);
+hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s) {
+    if (prec == HYB_FP64) return step2_impl<double>(a, s);
+    if (prec == HYB_FP32) return step2_impl<float>(a, s);
+    return step2_impl<_Float16>(a, s);
 }
 
-hipError_t launch_lbm_step(const LbmArgs &a, bool fp64, bool general_perimeter, hipStream_t s,
+hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, hipStream_t s,
                            hipEvent_t sweep_begin, hipEvent_t sweep_end) {
-    return fp64 ? step_impl<double>(a, general_perimeter, s, sweep_begin, sweep_end)
-                : step_impl<float>(a, general_perimeter, s, sweep_begin, sweep_end);
+    if (prec == HYB_FP64) return step_impl<double>(a, general_perimeter, s, sweep_begin, sweep_end);
+    if (prec == HYB_FP32) return step_impl<float>(a, general_perimeter, s, sweep_begin, sweep_end);
+    return step_impl<_Float16>(a, general_perimeter, s, sweep_begin, sweep_end);
 }
 
-hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, bool fp64, hipStream_t s) {
-    if (fp64) hipLaunchKernelGGL(lbm_init_kernel<double>, dim3(a.N), dim3(256), 0, s, a, u0);
-    else hipLaunchKernelGGL(lbm_init_kernel<float>, dim3(a.N), dim3(256), 0, s, a, u0);
+hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, int prec, hipStream_t s) {
+    if (prec == HYB_FP64) hipLaunchKernelGGL(lbm_init_kernel<double>, dim3(a.N), dim3(256), 0, s, a, u0);
+    else if (prec == HYB_FP32) hipLaunchKernelGGL(lbm_init_kernel<float>, dim3(a.N), dim3(256), 0, s, a, u0);
+    else hipLaunchKernelGGL(lbm_init_kernel<_Float16>, dim3(a.N), dim3(256), 0, s, a, u0);
     return hipGetLastError();
 }
 
-hipError_t launch_concentration(const LbmArgs &a, double *out, bool fp64, hipStream_t s) {
-    if (fp64) hipLaunchKernelGGL(lbm_conc_kernel<double>, dim3(a.N), dim3(256), 0, s, a, out);
-    else hipLaunchKernelGGL(lbm_conc_kernel<float>, dim3(a.N), dim3(256), 0, s, a, out);
+hipError_t launch_concentration(const LbmArgs &a, double *out, int prec, hipStream_t s) {
+    if (prec == HYB_FP64) hipLaunchKernelGGL(lbm_conc_kernel<double>, dim3(a.N), dim3(256), 0, s, a, out);
+    else if (prec == HYB_FP32) hipLaunchKernelGGL(lbm_conc_kernel<float>, dim3(a.N), dim3(256), 0, s, a, out);
+    else hipLaunchKernelGGL(lbm_conc_kernel<_Float16>, dim3(a.N), dim3(256), 0, s, a, out);
     return hipGetLastError();
 }
 

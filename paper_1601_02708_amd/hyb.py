@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhyb.so")
 
 HYB_OK, HYB_EINVAL, HYB_EHIP, HYB_ENOCONV, HYB_ENONFINITE = 0, -1, -2, -3, -4
-HYB_FP64, HYB_FP32 = 0, 1
+HYB_FP64, HYB_FP32, HYB_FP16S = 0, 1, 2
+PRECISIONS = {"fp64": HYB_FP64, "fp32": HYB_FP32, "fp16s": HYB_FP16S}
 HYB_F2C, HYB_C2F = 0, 1
 HYB_FINE, HYB_COARSE = 0, 1
 HYB_BC_DIRICHLET, HYB_BC_NEUMANN = 0, 1
@@ -129,7 +130,9 @@ class Hybrid:
         self.lat = HybLattice()
         self.lat.N = self.N
         self.lat.x0, self.lat.y0 = float(x0), float(y0)
-        self.lat.precision = HYB_FP64 if precision == "fp64" else HYB_FP32
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self.lat.precision = PRECISIONS[precision]
         self.lat.tau = float(tau)
         self.lat.eta = self.eta
         self.lat.bc_clamp = int(bc_clamp)

@@ -172,6 +172,17 @@ class StreamFunction:
         return self.scale * vx, self.scale * vy
 
 
+    def psi(self, X: np.ndarray, Y: np.ndarray):
+        """scale * psi at (X, Y) (the velocity is its rotated gradient)."""
+        x = np.asarray(X, dtype=np.float64) / self.L
+        y = np.asarray(Y, dtype=np.float64) / self.L
+        out = np.zeros(np.broadcast(x, y).shape)
+        tp = 2.0 * math.pi
+        for a, p, q, ph, ch in zip(self.a, self.p, self.q, self.phi, self.chi):
+            out += a * np.sin(tp * (p * x + ph)) * np.sin(tp * (q * y + ch))
+        return self.scale * out
+
+
 def stream_function(seed: int, L: float, n_modes: int = 8, max_wavenumber: int = 4) -> StreamFunction:
     rng = np.random.default_rng(seed)
     return StreamFunction(a=rng.standard_normal(n_modes),
@@ -180,6 +191,62 @@ def stream_function(seed: int, L: float, n_modes: int = 8, max_wavenumber: int =
                           phi=rng.uniform(0.0, 1.0, size=n_modes),
                           chi=rng.uniform(0.0, 1.0, size=n_modes),
                           L=L)
+
+
+# ----------------------------------------------------------------------------
+# pore flow: the stream function damped to zero at the grain surfaces
+# ----------------------------------------------------------------------------
+
+def wall_factor(xs: np.ndarray, ys: np.ndarray, centers: np.ndarray, radii: np.ndarray, width: float):
+    """phi = prod_k s(d_k / width) on the grid xs (columns) x ys (rows),
+    where d_k is the distance to the surface of disk k (negative inside) and
+    s(t) = 3t^2 - 2t^3 on [0, 1], 0 below and 1 above; returns phi and its
+    gradient (dphi/dx, dphi/dy), each [len(ys), len(xs)].  Every factor is
+    C^1 with zero slope at both ends, so phi is smooth where grains are
+    close together, and phi and its gradient vanish on every disk surface."""
+    xs = np.asarray(xs, dtype=np.float64)
+    ys = np.asarray(ys, dtype=np.float64)
+    phi = np.ones((len(ys), len(xs)))
+    gx = np.zeros_like(phi)
+    gy = np.zeros_like(phi)
+    for (cx, cy), r in zip(np.asarray(centers, dtype=np.float64).reshape(-1, 2), np.asarray(radii, dtype=np.float64)):
+        reach = r + width
+        i0, i1 = np.searchsorted(xs, cx - reach), np.searchsorted(xs, cx + reach, side="right")
+        j0, j1 = np.searchsorted(ys, cy - reach), np.searchsorted(ys, cy + reach, side="right")
+        if i0 >= i1 or j0 >= j1:
+            continue
+        DX = xs[None, i0:i1] - cx
+        DY = ys[j0:j1, None] - cy
+        rho = np.hypot(DX, DY)
+        t = np.clip((rho - r) / width, 0.0, 1.0)
+        sk = t * t * (3.0 - 2.0 * t)
+        dk = np.where((t > 0.0) & (t < 1.0), 6.0 * t * (1.0 - t) / width, 0.0)
+        safe = np.where(rho > 0.0, rho, 1.0)
+        box = np.s_[j0:j1, i0:i1]
+        # product rule with the old phi, then phi *= s_k
+        gx[box] = gx[box] * sk + phi[box] * dk * (DX / safe)
+        gy[box] = gy[box] * sk + phi[box] * dk * (DY / safe)
+        phi[box] *= sk
+    return phi, gx, gy
+
+
+@dataclasses.dataclass
+class PoreFlow:
+    """Velocity v = (d(psi phi)/dY, -d(psi phi)/dX): the stream function of
+    ``sf`` times the wall factor of the grains (disk centres in domain
+    coordinates).  Divergence-free, zero on and inside the grains, equal to
+    the plain stream-function flow farther than ``width`` from every grain."""
+    sf: StreamFunction
+    centers: np.ndarray
+    radii: np.ndarray
+    width: float = 6.0
+
+    def velocity_grid(self, xs: np.ndarray, ys: np.ndarray):
+        Y, X = np.meshgrid(np.asarray(ys, float), np.asarray(xs, float), indexing="ij")
+        phi, px, py = wall_factor(xs, ys, self.centers, self.radii, self.width)
+        psi = self.sf.psi(X, Y)
+        ux, uy = self.sf.velocity(X, Y)
+        return phi * ux + psi * py, phi * uy - psi * px
 
 
 # ----------------------------------------------------------------------------

@@ -394,3 +394,114 @@ def test_invalid_arguments():
         g.lbm_substeps(3, 1)
     with pytest.raises(hyb.HybError):
         g.interface_exchange(hyb.HYB_F2C)      # lattice-only handle
+
+
+# ----------------------------------------------------------------------------
+# FP16 shifted storage (binary16 g = (f - w c_ref) 2^s, FP32 arithmetic)
+# ----------------------------------------------------------------------------
+
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def fp16s_params(u0, solid):
+    """c_ref and the power-of-two scale the library derives from u0."""
+    fluid = np.ones(u0.shape, bool) if solid is None else solid == 0
+    cref = float(u0[fluid].mean())
+    U = max(1.0, float(np.abs(u0[fluid] - cref).max()))
+    s = int(np.floor(np.log2(16384.0 / (4.0 / 9.0 * U))))
+    return np.float32(cref), np.float32(2.0 ** s)
+
+
+def fp16s_roundtrip(f, cref, scale):
+    """What binary16 storage keeps of f: encode in FP32, round to nearest
+    even, decode in FP32."""
+    wc = (W9.astype(np.float32) * cref)[:, None, None]
+    g = ((f.astype(np.float32) - wc) * scale).astype(np.float16)
+    return (g.astype(np.float32) * (np.float32(1) / scale) + wc).astype(np.float64)
+
+
+def test_fp16s_storage_roundtrip():
+    """set/get populations: exactly the binary16 round trip of the stated
+    encoding (c_ref = fluid mean of u0, power-of-two scale)."""
+    hyb = _gpu()
+    N = 40
+    solid, vx, vy, _, tau = _lattice_case(N, 9)
+    rng = np.random.default_rng(2)
+    u0 = rng.uniform(0.0, 3.0, (N, N))
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=u0, vx=vx, vy=vy, D=0.02, eta=2, precision="fp16s", tau=tau, solid=solid)
+    cref, scale = fp16s_params(u0, solid)
+    f = inputs.random_populations(N, 5, lo=-0.1, hi=1.2)
+    f[:, solid != 0] = 0.0
+    g.set_populations(f)
+    got = g.get_populations()
+    want = fp16s_roundtrip(f, cref, scale)
+    want[:, solid != 0] = 0.0
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("N,eta", [(67, 5), (130, 4)])
+def test_fp16s_substeps_error_stated(orc, N, eta):
+    """Random states through eta fine steps with FP16 shifted storage, in
+    single steps and in two-step launches, against the FP64 oracle started
+    from the stored (rounded) state.  Both paths round after every fine
+    step, so they agree to a few binary16 ulps; the error against the
+    oracle is printed and held to 2e-3 (about four binary16 roundings)."""
+    hyb = _gpu()
+    solid, vx, vy, _, tau = _lattice_case(N, 500 + N)
+    rng = np.random.default_rng(N)
+    P = 4 * (N - 1)
+    a = rng.uniform(0.2, 0.6, P)
+    b = rng.uniform(0.2, 0.6, P)
+    u0 = np.full((N, N), 0.4)
+    # near-equilibrium state: f = w u (1 + 5% noise), u in [0.3, 0.5]
+    uf = rng.uniform(0.3, 0.5, (N, N))
+    f0 = W9[:, None, None] * uf[None] * (1 + 0.05 * rng.standard_normal((9, N, N)))
+    f0[:, solid != 0] = 0.0
+    cref, scale = fp16s_params(u0, solid)
+    lat = orc.Lattice(N, tau, vx.astype(np.float64), vy.astype(np.float64), solid=solid, k=1e-3)
+    f = fp16s_roundtrip(f0, cref, scale)
+    f[:, solid != 0] = 0.0
+    for j in range(1, eta + 1):
+        f, _ = lat.substep(f, (1 - j / eta) * a + j / eta * b)
+    fluid = solid == 0
+    got = {}
+    for spl in (1, 2):
+        g = hyb.Hybrid(N=N, x0=0, y0=0, u0=u0, vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta, precision="fp16s",
+                       tau=tau, solid=solid, k=1e-3)
+        g.set_steps_per_launch(spl)
+        g.set_populations(f0)
+        g.set_boundary(a, b)
+        g.lbm_substeps(eta, restart=1)
+        g.commit()
+        got[spl] = g.get_populations()
+        err = rel_l2(got[spl], f, fluid)
+        print(f"\nfp16s N={N} eta={eta} steps/launch={spl}: rel L2 vs FP64 oracle {err:.3e}")
+        assert err <= 2e-3
+    d = np.abs(got[2] - got[1]).max() / np.abs(got[1]).max()
+    assert d <= 4e-3, d
+
+
+def test_fp16s_hybrid_small_error_stated(orc):
+    """The 64^2 / 16^2 workload, all 100 coarse steps, FP16 shifted storage."""
+    hyb = _gpu()
+    p = problem("small")
+    o = _oracle_hybrid(orc, p, p.cfg.steps)
+    g = _gpu_hybrid(hyb, p, "fp16s", p.cfg.steps)
+    e_f = rel_l2(g.concentration(), o.fine_concentration())
+    e_c = rel_l2(g.concentration(hyb.HYB_COARSE), o.d)
+    print(f"\nsmall fp16s vs fp64 oracle after {p.cfg.steps} coarse steps: fine {e_f:.3e} coarse {e_c:.3e}")
+    assert e_f < 2e-2 and e_c < 2e-2
+
+
+def test_fp16s_full_size_first_step(orc):
+    """pore2048, first coarse step (2 Schwarz passes x 10 fine steps), FP16
+    shifted storage, against the oracle."""
+    hyb = _gpu()
+    p = problem("pore2048")
+    o = _oracle_hybrid(orc, p, 1)
+    g = _gpu_hybrid(hyb, p, "fp16s", 1)
+    fluid = p.solid == 0
+    e_f = rel_l2(g.concentration(), o.fine_concentration(), fluid)
+    e_c = rel_l2(g.concentration(hyb.HYB_COARSE), o.d)
+    print(f"\npore2048 fp16s first step: fine {e_f:.3e} coarse {e_c:.3e}")
+    assert e_f < 1e-2 and e_c < 1e-2
