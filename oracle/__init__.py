@@ -56,6 +56,7 @@ def lib():
             "orc_apply_bc": (c_long, [P, P, P, P, P]),
             "orc_collide": (None, [P, P, P]),
             "orc_lbm_substep": (c_long, [P, P, P, P]),
+            "orc_lbm_adjoint_substep": (c_int, [P, P, P, P, P, P, P]),
             "orc_concentration": (None, [P, P, P]),
             "orc_h_function": (c_double, [P, P]),
             "orc_supg_chi": (c_double, [c_double]),
@@ -175,6 +176,22 @@ class Lattice:
         out = np.empty_like(fsrc)
         inf = lib().orc_lbm_substep(self.ptr, _p(fsrc), _p(out), _p(bc_value))
         return out, int(inf)
+
+    def adjoint_substep(self, fsrc, bc_value, lam_in):
+        """Reverse mode of substep(fsrc, bc_value): returns (dJ/df*(t),
+        dJ/du^p per perimeter slot, dJ/dk per node) for lam_in = dJ/df*(t+1).
+        All perimeter slots must be Dirichlet."""
+        fsrc = _f64(fsrc)
+        bc_value = _f64(np.zeros(4 * (self.N - 1)) if bc_value is None else bc_value)
+        lam_in = _f64(lam_in)
+        lam_out = np.empty_like(lam_in)
+        gbc = np.zeros(4 * (self.N - 1))
+        gk = np.zeros((self.N, self.N))
+        rc = lib().orc_lbm_adjoint_substep(self.ptr, _p(fsrc), _p(bc_value), _p(lam_in), _p(lam_out), _p(gbc),
+                                           _p(gk))
+        if rc != 0:
+            raise ValueError("adjoint supports Dirichlet perimeter slots only")
+        return lam_out, gbc, gk
 
     def stream(self, fsrc):
         fsrc = _f64(fsrc)

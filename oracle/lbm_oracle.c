@@ -341,3 +341,99 @@ double orc_h_function(const orc_lattice *L, const double *f) {
     }
     return H;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of one fine step (reverse mode of orc_lbm_substep), for the      */
+/* differentiation form: given lam_in = dJ/df*(t+1), returns                 */
+/* lam_out = dJ/df*(t) and accumulates dJ/du^p (per perimeter slot) and     */
+/* dJ/dk (per node).  Written as the transpose of each forward pass, in     */
+/* reverse order:                                                           */
+/*   collision  f*_i = (1 - 1/tau) f_i + f_i^eq(u)/tau - k w_i u, u = sum f: */
+/*     dJ/df_j = (1 - 1/tau) l_j + sum_i l_i (f_i^eq(1)/tau - k w_i),       */
+/*     dJ/dk  -= u sum_i w_i l_i   (f^eq is linear in u);                   */
+/*   Dirichlet closure f_U = w_U (u^p - sum_K f_K) / W (eq. LBM_Dir):        */
+/*     G = sum_U w_U dJ/df_U / W;  dJ/df_K -= G;  dJ/du^p += G;  when the   */
+/*     closure is clamped at zero (clamp != 0 and R < 0) the unknowns are   */
+/*     constant and G = 0;                                                  */
+/*   streaming (pull, halfway bounce-back): each dJ/df_i(x) goes back to the */
+/*     population it was copied from.                                        */
+/* The forward pre-collision field and every closure's R are recomputed    */
+/* from fsrc.  Neumann slots are not supported (returns -1).                */
+/* ------------------------------------------------------------------------ */
+int orc_lbm_adjoint_substep(const orc_lattice *L, const double *fsrc, const double *bc_value,
+                            const double *lam_in, double *lam_out, double *grad_bc, double *grad_k) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    if (L->bc_kind)
+        for (int p = 0; p < 4 * (N - 1); ++p)
+            if (L->bc_kind[p] != 0) return -1;
+    double *f = (double *)malloc(9 * NN * sizeof(double));
+    double *lf = (double *)calloc(9 * NN, sizeof(double));
+    uint16_t *unknown = (uint16_t *)malloc(NN * sizeof(uint16_t));
+    /* forward pre-collision field (streamed, closed) */
+    orc_stream(L, fsrc, f, unknown);
+    double *fs = (double *)malloc(9 * NN * sizeof(double));
+    memcpy(fs, f, 9 * NN * sizeof(double));          /* streamed, before the closure */
+    orc_apply_bc(L, fsrc, f, unknown, bc_value);
+
+    /* collision */
+    for (int n = 0; n < (int)NN; ++n) {
+        if (is_solid(L, n)) continue;
+        double u = 0.0, feq1[9], s = 0.0, wl = 0.0;
+        for (int q = 0; q < 9; ++q) u += f[q * NN + n];
+        orc_feq(1.0, L->vx[n], L->vy[n], feq1);
+        double k = kat(L, n);
+        for (int i = 0; i < 9; ++i) {
+            double li = lam_in[i * NN + n];
+            s += li * (feq1[i] / L->tau - k * WT[i]);
+            wl += WT[i] * li;
+        }
+        for (int j = 0; j < 9; ++j) lf[j * NN + n] = (1.0 - 1.0 / L->tau) * lam_in[j * NN + n] + s;
+        if (grad_k) grad_k[n] -= u * wl;
+    }
+    /* Dirichlet closure */
+    for (int p = 0; p < 4 * (N - 1); ++p) {
+        int i, j;
+        orc_perimeter_node(N, p, &i, &j);
+        int n = j * N + i;
+        if (is_solid(L, n) || unknown[n] == 0) continue;
+        double known = 0.0, wsum = 0.0, g = 0.0;
+        for (int q = 0; q < 9; ++q) {
+            if (unknown[n] & (1u << q)) wsum += WT[q];
+            else known += fs[q * NN + n];
+        }
+        int clamped = L->clamp && (bc_value[p] - known < 0.0);
+        if (!clamped) {
+            for (int q = 0; q < 9; ++q)
+                if (unknown[n] & (1u << q)) g += WT[q] * lf[q * NN + n];
+            g /= wsum;
+            for (int q = 0; q < 9; ++q)
+                if (!(unknown[n] & (1u << q))) lf[q * NN + n] -= g;
+            if (grad_bc) grad_bc[p] += g;
+        }
+        for (int q = 0; q < 9; ++q)
+            if (unknown[n] & (1u << q)) lf[q * NN + n] = 0.0;
+    }
+    /* streaming */
+    memset(lam_out, 0, 9 * NN * sizeof(double));
+    for (int j = 0; j < N; ++j) {
+        for (int i = 0; i < N; ++i) {
+            int n = j * N + i;
+            if (is_solid(L, n)) continue;
+            for (int q = 0; q < 9; ++q) {
+                if (unknown[n] & (1u << q)) continue;
+                int si = i - EX[q], sj = j - EY[q];
+                if (si < 0 || si >= N) si = (si + N) % N;    /* only reached when periodic */
+                if (sj < 0 || sj >= N) sj = (sj + N) % N;
+                int s = sj * N + si;
+                if (is_solid(L, s)) lam_out[OPP[q] * NN + n] += lf[q * NN + n];
+                else lam_out[q * NN + s] += lf[q * NN + n];
+            }
+        }
+    }
+    free(fs);
+    free(f);
+    free(lf);
+    free(unknown);
+    return 0;
+}
