@@ -98,6 +98,46 @@ def run_gpu(problem, precision, steps, warmup, steps_per_launch=2, timing=True):
     return g, wall, gpu_ms, kms, launches, st
 
 
+def adjoint_rate(problem, precision, reps=3):
+    """Reverse mode of one coarse step's fine steps (hyb_lbm_substeps_record,
+    then hyb_lbm_adjoint) on the same workload; MLUPS of the adjoint sweep
+    (all nodes x eta fine steps) and of the recording forward sweep."""
+    import torch
+    from paper_1601_02708_amd import hyb
+    g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
+    g.interface_exchange(hyb.HYB_F2C)
+    g.coarse_step()
+    g.interface_exchange(hyb.HYB_C2F)
+    eta, N = problem.cfg.eta, problem.cfg.N
+    tape = g.adjoint_tape(eta)
+    P = 4 * (N - 1)
+    lam = torch.ones((9, N, N), dtype=torch.float64, device=g.dev)
+    lam_out = torch.empty_like(lam)
+    ga = torch.zeros(P, dtype=torch.float64, device=g.dev)
+    gb = torch.zeros_like(ga)
+    gk = torch.zeros((N, N), dtype=torch.float64, device=g.dev)
+    s = g.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    rec_ms = adj_ms = 0.0
+    for r in range(reps + 1):
+        ev[0].record(s)
+        g.substeps_record(eta, tape)
+        ev[1].record(s)
+        g.adjoint(eta, tape, lam, lam_out, ga, gb, gk)
+        ev[2].record(s)
+        torch.cuda.synchronize()
+        if r > 0:                       # the first pass warms up
+            rec_ms += ev[0].elapsed_time(ev[1])
+            adj_ms += ev[1].elapsed_time(ev[2])
+    lups = eta * N * N * reps
+    out = {"precision": precision, "value": round(lups / (adj_ms / 1e3) / 1e6, 1), "unit": "MLUPS",
+           "ms_per_fine_step": round(adj_ms / (reps * eta), 4),
+           "record_forward_mlups": round(lups / (rec_ms / 1e3) / 1e6, 1),
+           "note": "dJ/df*, dJ/da, dJ/db, dJ/dk over one coarse step's fine steps (tape of eta + 4 states)"}
+    g.close()
+    return out
+
+
 def cpu_baseline(problem, min_seconds=10.0, max_steps=6):
     """The oracle as it stands on this host: whole coarse steps (2 Schwarz
     passes x eta fine steps each, FP64, one thread) of the same workload,
@@ -129,6 +169,7 @@ def main():
     ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2],
                     help="fine steps per lattice-sweep launch (2: temporally blocked pairs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision runs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (a plain copy kernel of "
@@ -226,6 +267,9 @@ def main():
             if p_ != "fp64":
                 key = "fp32_rel_l2_vs_fp64" if p_ == "fp32" else f"{p_}_rel_l2_vs_fp64"
                 res[key] = float(np.linalg.norm((u_ - ref)[fluid]) / nref)
+    if not args.no_adjoint and args.precision in ("fp32", "fp64"):
+        print("[bench] adjoint", file=sys.stderr, flush=True)
+        res["adjoint"] = adjoint_rate(problem, args.precision)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one coarse step)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(problem)

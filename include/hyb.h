@@ -185,6 +185,37 @@ int hyb_set_populations(hyb_handle *h, const double *f);
 
 int hyb_stats(hyb_handle *h, hyb_run_stats *out);
 
+/* ---- differentiation form (reverse mode) of the fine sub-steps ----------
+ *
+ * The fine step (Sec. 4.1: pull streaming with halfway bounce-back, the
+ * Dirichlet closure of eq. (LBM_Dir) with u^p from eq. (MTS), BGK collision
+ * with the reaction source) is linear in (f*, u^p) for fixed velocity and
+ * reaction rate when the closure is applied as printed; where the clamp
+ * option zeroes a closure its unknowns are constant.  The adjoint maps
+ * dJ/df* at the end of n_sub fine steps to dJ/df* at the committed state
+ * f*(t_n) and accumulates dJ/da, dJ/db (the two interface arrays of
+ * hyb_set_boundary / hyb_interface_exchange, u^p = (1 - j/eta) a + (j/eta) b
+ * at fine step j) and dJ/dk (per-node reaction rate).  Supported for
+ * HYB_FP64 and HYB_FP32 storage (arithmetic in that precision) with every
+ * perimeter slot Dirichlet; HYB_EINVAL otherwise.
+ *
+ * hyb_adjoint_query: device bytes of the tape for n_sub >= 1 fine steps,
+ *   (n_sub + 4) population buffers (f_bytes each).
+ * hyb_lbm_substeps_record: like hyb_lbm_substeps(h, n_sub, 1) (single-step
+ *   launches), recording f*(0) .. f*(n_sub) in the caller's device tape
+ *   (256-byte aligned, >= tape bytes); 1 <= n_sub <= eta.
+ * hyb_lbm_adjoint: tape and n_sub of the last record (the interface values
+ *   and the handle must be unchanged since); lam_in, lam_out: device FP64
+ *   [9][N][N] (index (q*N + j)*N + i), lam_in = dJ/df*(n_sub) (kept),
+ *   lam_out = dJ/df*(0) (may alias lam_in); grad_a, grad_b: device FP64
+ *   [4(N-1)] and grad_k: device FP64 [N*N] or NULL, each ADDED to.  The
+ *   tape's last three buffers are scratch.  Enqueued on the handle's stream;
+ *   no synchronisation. */
+int hyb_adjoint_query(const hyb_handle *h, int n_sub, size_t *tape_bytes);
+int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape);
+int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *lam_in, double *lam_out,
+                    double *grad_a, double *grad_b, double *grad_k);
+
 /* Fine steps per lattice-sweep launch (1 or 2; default 2).  With 2, while
  * every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine steps in
  * pairs, each pair in one temporally blocked launch (the state between the

@@ -1,0 +1,207 @@
+// Reverse mode (adjoint) of the fine step, for the differentiation form of
+// the lattice sub-stepping.  One fine step maps f*(t) to f*(t+1) through
+// pull streaming with halfway bounce-back, the Dirichlet closure of eq.
+// (LBM_Dir) at perimeter nodes, and the BGK + reaction collision; with the
+// closure applied as printed the step is linear in (f*(t), u^p) for fixed
+// velocity and reaction rate.  Its adjoint, given l = dJ/df*(t+1):
+//
+//   collision   mu_p = (1 - w) l_p + sum_q l_q w_q (w P_q(v) - k)
+//               dJ/dk(x) += -u(x) sum_q w_q l_q
+//   closure     G = sum_U w_U mu_U / W;  nu_K = mu_K - G;  nu_U = 0;
+//               dJ/du^p += G  (G = 0 where the closure was clamped at 0)
+//   streaming   dJ/df*_p(y) = nu_p(y + e_p)   if y + e_p is a fluid node
+//                                             of the patch (it pulled f*_p(y))
+//                           + nu_q(y), q = opp(p), if y bounced back along q
+//
+// (P_q(v) = 1 + 3 e.v + 9/2 (e.v)^2 - 3/2 v.v, w = 1/tau).  The first two
+// are local to a node (adj_local_kernel), the last gathers from the
+// neighbours (adj_stream_kernel).  The forward states of the step come from
+// the tape recorded by the forward sweep.
+#include "hyb_impl.h"
+
+namespace hyb {
+namespace {
+
+__device__ __forceinline__ int slot_of(int N, int i, int j) {
+    if (j == 0) return i;
+    if (j == N - 1) return N + i;
+    if (i == 0) return 2 * N + j - 1;
+    return 3 * N - 2 + j - 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adj_local_kernel(LbmArgs a, const T *__restrict__ snext,
+                                                       const T *__restrict__ lam, T *__restrict__ nu,
+                                                       double *__restrict__ grad_a, double *__restrict__ grad_b,
+                                                       double *__restrict__ grad_k, int row_blocks) {
+    const int N = a.N, P = a.pitch;
+    const int plane = static_cast<int>(a.plane);
+    const int j = blockIdx.x / row_blocks;
+    const int i = (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int n = j * P + i;
+    const unsigned m = a.mask[n];
+    if (m & kMaskSolid) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) nu[q * plane + n] = T(0);
+        return;
+    }
+    const T vx = T(a.vx[n]), vy = T(a.vy[n]);
+    const T k = a.kfield ? static_cast<const T *>(a.kfield)[n] : T(a.k);
+    const T omega = T(a.omega);
+    const T vv = T(1.5) * (vx * vx + vy * vy);
+    T l[kQ], mu[kQ];
+    T S = T(0), wl = T(0);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        l[q] = lam[q * plane + n];
+        const T ev = T(kCx[q]) * vx + T(kCy[q]) * vy;
+        const T Pq = T(1) + T(3) * ev + T(4.5) * ev * ev - vv;
+        S += l[q] * T(kW[q]) * (omega * Pq - k);
+        wl += T(kW[q]) * l[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) mu[q] = (T(1) - omega) * l[q] + S;
+    if (grad_k) {
+        // u at the step's collision: sum f*(t+1) = (1 - k) u
+        T s = T(0);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) s += snext[q * plane + n];
+        grad_k[(size_t)j * N + i] -= double(s / (T(1) - k)) * double(wl);
+    }
+    if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
+        unsigned unknown = 0;
+#pragma unroll
+        for (int q = 1; q < kQ; ++q) {
+            const int si = i - kCx[q], sj = j - kCy[q];
+            if (si < 0 || si >= N || sj < 0 || sj >= N) unknown |= 1u << q;
+        }
+        const int p = slot_of(N, i, j);
+        bool active = true;
+        if (a.clamp) {
+            // the forward closure's R from the step's source state
+            const T *__restrict__ src = static_cast<const T *>(a.src);
+            double known = 0.0;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                if ((unknown >> q) & 1u) continue;
+                known += double((m >> q) & 1u ? src[kOpp[q] * plane + n]
+                                              : src[q * plane + (j - kCy[q]) * P + i - kCx[q]]);
+            }
+            active = !((1.0 - a.lam) * a.bc_a[p] + a.lam * a.bc_b[p] - known < 0.0);
+        }
+        double G = 0.0;
+        if (active) {
+            double wsum = 0.0;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+                if ((unknown >> q) & 1u) {
+                    G += kW[q] * double(mu[q]);
+                    wsum += kW[q];
+                }
+            G /= wsum;
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) mu[q] = ((unknown >> q) & 1u) ? T(0) : T(double(mu[q]) - G);
+        grad_a[p] += (1.0 - a.lam) * G;
+        grad_b[p] += a.lam * G;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) nu[q * plane + n] = mu[q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adj_stream_kernel(LbmArgs a, const T *__restrict__ nu, T *__restrict__ out,
+                                                        int row_blocks) {
+    const int N = a.N, P = a.pitch;
+    const int plane = static_cast<int>(a.plane);
+    const int j = blockIdx.x / row_blocks;
+    const int i = (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int n = j * P + i;
+    const unsigned m = a.mask[n];
+    if (m & kMaskSolid) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+        return;
+    }
+#pragma unroll
+    for (int p = 0; p < kQ; ++p) {
+        T acc = T(0);
+        const int xi = i + kCx[p], xj = j + kCy[p];
+        if (xi >= 0 && xi < N && xj >= 0 && xj < N) {
+            const int x = xj * P + xi;
+            if (!(a.mask[x] & kMaskSolid)) acc += nu[p * plane + x];
+        }
+        const int q = kOpp[p];
+        if ((m >> q) & 1u) acc += nu[q * plane + n];
+        out[p * plane + n] = acc;
+    }
+}
+
+// dense FP64 [9][N][N] <-> pitched planes of T
+template <typename T>
+__global__ void __launch_bounds__(256) adj_pack_kernel(LbmArgs a, const double *__restrict__ dense, T *__restrict__ pitched,
+                                                      int row_blocks) {
+    const int N = a.N, P = a.pitch;
+    const int plane = static_cast<int>(a.plane);
+    const int j = blockIdx.x / row_blocks;
+    const int i = (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) pitched[q * plane + j * P + i] = T(dense[((size_t)q * N + j) * N + i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adj_unpack_kernel(LbmArgs a, const T *__restrict__ pitched, double *__restrict__ dense,
+                                                        int row_blocks) {
+    const int N = a.N, P = a.pitch;
+    const int plane = static_cast<int>(a.plane);
+    const int j = blockIdx.x / row_blocks;
+    const int i = (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) dense[((size_t)q * N + j) * N + i] = double(pitched[q * plane + j * P + i]);
+}
+
+template <typename T>
+hipError_t adjoint_step_impl(const LbmArgs &a, const void *snext, const void *lam, void *nu, void *out,
+                             double *grad_a, double *grad_b, double *grad_k, hipStream_t s) {
+    const int rb = (a.N + 255) / 256;
+    const dim3 grid(a.N * rb), block(256);
+    hipLaunchKernelGGL(adj_local_kernel<T>, grid, block, 0, s, a, static_cast<const T *>(snext),
+                       static_cast<const T *>(lam), static_cast<T *>(nu), grad_a, grad_b, grad_k, rb);
+    hipLaunchKernelGGL(adj_stream_kernel<T>, grid, block, 0, s, a, static_cast<const T *>(nu), static_cast<T *>(out),
+                       rb);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
+                               double *grad_a, double *grad_b, double *grad_k, hipStream_t s) {
+    if (prec == HYB_FP64) return adjoint_step_impl<double>(a, snext, lam, nu, out, grad_a, grad_b, grad_k, s);
+    return adjoint_step_impl<float>(a, snext, lam, nu, out, grad_a, grad_b, grad_k, s);
+}
+
+hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,
+                               hipStream_t s) {
+    const int rb = (a.N + 255) / 256;
+    const dim3 grid(a.N * rb), block(256);
+    if (to_pitched) {
+        if (prec == HYB_FP64)
+            hipLaunchKernelGGL(adj_pack_kernel<double>, grid, block, 0, s, a, dense, static_cast<double *>(pitched), rb);
+        else
+            hipLaunchKernelGGL(adj_pack_kernel<float>, grid, block, 0, s, a, dense, static_cast<float *>(pitched), rb);
+    } else {
+        if (prec == HYB_FP64)
+            hipLaunchKernelGGL(adj_unpack_kernel<double>, grid, block, 0, s, a, static_cast<const double *>(pitched),
+                               const_cast<double *>(dense), rb);
+        else
+            hipLaunchKernelGGL(adj_unpack_kernel<float>, grid, block, 0, s, a, static_cast<const float *>(pitched),
+                               const_cast<double *>(dense), rb);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hyb

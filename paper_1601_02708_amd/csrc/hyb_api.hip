@@ -156,6 +156,8 @@ struct hyb_handle {
     bool kinds_set = false;
     bool any_neumann = false;
     int steps_per_launch = 2;          // 2: two-step sweep when every slot is Dirichlet
+    const void *rec_tape = nullptr;     // last forward recording (hyb_lbm_substeps_record)
+    int rec_n = 0;
     int *c2f_idx = nullptr, *fc_idx = nullptr;
     double *c2f_w = nullptr, *fc_w = nullptr, *ufc = nullptr;
     int nfc = 0;
@@ -730,6 +732,61 @@ int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
     out->krylov_relres = kr.relres;
     out->coarse_steps = h->coarse_steps;
     out->fine_steps = h->fine_steps;
+    return HYB_OK;
+}
+
+int hyb_adjoint_query(const hyb_handle *h, int n_sub, size_t *tape_bytes) {
+    if (!h || !tape_bytes || n_sub < 1) return HYB_EINVAL;
+    // states f*(0) .. f*(n_sub), two adjoint fields and one scratch field
+    *tape_bytes = (size_t)(n_sub + 4) * h->lay.f_bytes;
+    return HYB_OK;
+}
+
+int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
+    if (!h) return HYB_EINVAL;
+    if (h->prec == HYB_FP16S) return h->fail(HYB_EINVAL, "the adjoint supports HYB_FP64 and HYB_FP32 storage");
+    if (h->any_neumann) return h->fail(HYB_EINVAL, "the adjoint supports Dirichlet perimeter slots only");
+    if (n_sub < 1 || n_sub > h->eta) return h->fail(HYB_EINVAL, "n_sub must lie in 1..eta");
+    if (!tape || reinterpret_cast<uintptr_t>(tape) % kAlign) return h->fail(HYB_EINVAL, "tape must be 256-byte aligned");
+    const size_t fb = h->lay.f_bytes;
+    auto slot = [&](int t) { return static_cast<char *>(tape) + (size_t)t * fb; };
+    HIP_TRY(h, hipMemcpyAsync(slot(0), h->f[h->frozen], fb, hipMemcpyDeviceToDevice, h->stream));
+    for (int t = 0; t < n_sub; ++t) {
+        LbmArgs a = h->lbm_args(h->frozen, -1);
+        a.src = slot(t);
+        a.dst = slot(t + 1);
+        a.lam = (double)(t + 1) / (double)h->eta;
+        HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
+    }
+    const int dst = h->spare(-1);
+    HIP_TRY(h, hipMemcpyAsync(h->f[dst], slot(n_sub), fb, hipMemcpyDeviceToDevice, h->stream));
+    h->cur = dst;
+    h->jsub = n_sub;
+    h->fine_steps += n_sub;
+    h->rec_tape = tape;
+    h->rec_n = n_sub;
+    return HYB_OK;
+}
+
+int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *lam_in, double *lam_out,
+                    double *grad_a, double *grad_b, double *grad_k) {
+    if (!h) return HYB_EINVAL;
+    if (!tape || tape != h->rec_tape || n_sub != h->rec_n)
+        return h->fail(HYB_EINVAL, "the tape and n_sub must be those of the last hyb_lbm_substeps_record");
+    if (!lam_in || !lam_out || !grad_a || !grad_b) return h->fail(HYB_EINVAL, "null adjoint argument");
+    const size_t fb = h->lay.f_bytes;
+    char *base = static_cast<char *>(const_cast<void *>(tape));
+    auto slot = [&](int t) { return base + (size_t)t * fb; };
+    void *lcur = slot(n_sub + 1), *nu = slot(n_sub + 2), *lnext = slot(n_sub + 3);
+    LbmArgs a = h->lbm_args(h->frozen, -1);
+    HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_in, lcur, true, h->stream));
+    for (int t = n_sub - 1; t >= 0; --t) {
+        a.src = slot(t);
+        a.lam = (double)(t + 1) / (double)h->eta;
+        HIP_TRY(h, launch_adjoint_step(a, h->prec, slot(t + 1), lcur, nu, lnext, grad_a, grad_b, grad_k, h->stream));
+        std::swap(lcur, lnext);
+    }
+    HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_out, lcur, false, h->stream));
     return HYB_OK;
 }
 

@@ -116,6 +116,15 @@ hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, h
 // Two fine steps in one launch (Dirichlet closure on every perimeter slot):
 // a.src holds f*(j), a.dst receives f*(j+2); u^p at a.lam, then a.lam2.
 hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s);
+// Adjoint of one fine step (adjoint_kernels.hip), HYB_FP64 or HYB_FP32:
+// a.src = the step's source state f*(t) (read only with clamped closures),
+// snext = f*(t+1), lam = dJ/df*(t+1); nu is scratch; out = dJ/df*(t);
+// grad_a, grad_b [4(N-1)] and grad_k (dense [N][N] or null) accumulate.
+hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
+                               double *grad_a, double *grad_b, double *grad_k, hipStream_t s);
+// dense FP64 [9][N][N] to pitched planes (to_pitched) or back
+hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,
+                               hipStream_t s);
 hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, int prec, hipStream_t s);
 hipError_t launch_concentration(const LbmArgs &a, double *out, int prec, hipStream_t s);
 

@@ -66,6 +66,9 @@ SIGNATURES = {
     "hyb_set_populations": (_i, [_P, _P]),
     "hyb_stats": (_i, [_P, _P]),
     "hyb_layout": (_i, [_P, _P, _P]),
+    "hyb_adjoint_query": (_i, [_P, _i, _P]),
+    "hyb_lbm_substeps_record": (_i, [_P, _i, _P]),
+    "hyb_lbm_adjoint": (_i, [_P, _i, _P, _P, _P, _P, _P, _P]),
     "hyb_set_steps_per_launch": (_i, [_P, _i]),
     "hyb_kernel_timing": (_i, [_P, _i]),
     "hyb_kernel_time": (_i, [_P, _P, _P]),
@@ -235,6 +238,27 @@ class Hybrid:
         self._check(load().hyb_stats(self.h, ctypes.addressof(s)))
         return {k: getattr(s, k) for k, _ in HybRunStats._fields_}
 
+    # -- reverse mode -------------------------------------------------------
+    def adjoint_tape(self, n_sub):
+        """A device tape (torch uint8 tensor) for n_sub recorded fine steps."""
+        nb = ctypes.c_size_t()
+        self._check(load().hyb_adjoint_query(self.h, int(n_sub), ctypes.addressof(nb)))
+        return self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.dev)
+
+    def substeps_record(self, n_sub, tape):
+        return self._check(load().hyb_lbm_substeps_record(self.h, int(n_sub), tape.data_ptr()))
+
+    def adjoint(self, n_sub, tape, lam_in, lam_out, grad_a, grad_b, grad_k=None):
+        """Device FP64 tensors: lam_in/lam_out [9, N, N], grad_a/grad_b [4(N-1)],
+        grad_k [N, N] or None (gradients are added to)."""
+        t = self.torch
+        for x in (lam_in, lam_out, grad_a, grad_b) + (() if grad_k is None else (grad_k,)):
+            if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
+                raise ValueError("adjoint arrays must be contiguous FP64 device tensors")
+        return self._check(load().hyb_lbm_adjoint(self.h, int(n_sub), tape.data_ptr(), lam_in.data_ptr(),
+                                                  lam_out.data_ptr(), grad_a.data_ptr(), grad_b.data_ptr(),
+                                                  None if grad_k is None else grad_k.data_ptr()))
+
     def set_steps_per_launch(self, steps):
         return self._check(load().hyb_set_steps_per_launch(self.h, int(steps)))
 
@@ -263,3 +287,37 @@ class Hybrid:
             self.close()
         except Exception:
             pass
+
+
+def lattice_substeps_function():
+    """torch.autograd.Function for f*(n_sub) = F(f*(0), a, b) on a handle:
+    forward records the fine steps, backward runs the C ABI adjoint.  Usage:
+    ``LatticeSubsteps = lattice_substeps_function()`` then
+    ``LatticeSubsteps.apply(hybrid, n_sub, f0, a, b)`` with f0 [9, N, N] and
+    a, b [4(N-1)] FP64 tensors; returns f*(n_sub) [9, N, N] on f0's device."""
+    import torch
+
+    class LatticeSubsteps(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, g, n_sub, f0, a, b):
+            g.set_populations(f0.detach().cpu().numpy())
+            g.set_boundary(a.detach().cpu().numpy(), b.detach().cpu().numpy())
+            tape = g.adjoint_tape(n_sub)
+            g.substeps_record(n_sub, tape)
+            out = torch.from_numpy(g.get_populations()).to(f0.device)
+            ctx.g, ctx.n_sub, ctx.tape = g, n_sub, tape
+            ctx.dev = f0.device
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = ctx.g
+            lam = grad_out.detach().to(device=g.dev, dtype=torch.float64).contiguous()
+            lam_out = torch.empty_like(lam)
+            P = 4 * (g.N - 1)
+            ga = torch.zeros(P, dtype=torch.float64, device=g.dev)
+            gb = torch.zeros(P, dtype=torch.float64, device=g.dev)
+            g.adjoint(ctx.n_sub, ctx.tape, lam, lam_out, ga, gb)
+            return None, None, lam_out.to(ctx.dev), ga.to(ctx.dev), gb.to(ctx.dev)
+
+    return LatticeSubsteps

@@ -1,0 +1,178 @@
+"""GPU reverse mode of the fine sub-steps (C ABI hyb_lbm_substeps_record /
+hyb_lbm_adjoint) against the oracle's adjoint, plus the dot-product
+identity and the torch.autograd wrapper on the GPU."""
+import numpy as np
+import pytest
+
+from paper_1601_02708_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_02708_amd import hyb
+    return hyb, torch
+
+
+def _case(N, seed, k_field=True, vmax=0.05, tau=0.56):
+    rng = np.random.default_rng(seed)
+    solid = (inputs.random_disks(N, 0.75, seed=seed, r_min=2, r_max=6).solid if N > 8
+             else np.zeros((N, N), np.uint8))
+    vx = rng.uniform(-vmax, vmax, (N, N)).astype(np.float32)
+    vy = rng.uniform(-vmax, vmax, (N, N)).astype(np.float32)
+    vx[solid != 0] = 0
+    vy[solid != 0] = 0
+    kf = rng.uniform(0, 2e-3, (N, N)) if k_field else None
+    return rng, solid, vx, vy, kf, tau
+
+
+def _oracle_adjoint(orc, lat, f0, a, b, eta, c):
+    states = [f0]
+    bcs = [(1 - j / eta) * a + j / eta * b for j in range(1, eta + 1)]
+    for bc in bcs[:-1]:
+        states.append(lat.substep(states[-1], bc)[0])
+    lam = c
+    ga = np.zeros_like(a)
+    gb = np.zeros_like(b)
+    gk = np.zeros(f0.shape[1:])
+    for t in reversed(range(eta)):
+        lam, gbc, k = lat.adjoint_substep(states[t], bcs[t], lam)
+        lt = (t + 1) / eta
+        ga += (1 - lt) * gbc
+        gb += lt * gbc
+        gk += k
+    return lam, ga, gb, gk
+
+
+def _rel(x, y):
+    return float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+
+
+@pytest.mark.parametrize("precision,N,clamp,eta", [("fp64", 67, 0, 5), ("fp64", 130, 1, 4), ("fp64", 4, 0, 3),
+                                                   ("fp32", 67, 0, 5)])
+def test_adjoint_matches_oracle(orc, precision, N, clamp, eta):
+    hyb, torch = _gpu()
+    rng, solid, vx, vy, kf, tau = _case(N, 40 + N, k_field=True)
+    P = 4 * (N - 1)
+    a = rng.uniform(0.1, 0.6, P)
+    b = rng.uniform(0.1, 0.6, P)
+    f0 = inputs.random_populations(N, 9 + N, lo=0.01, hi=0.1)
+    f0[:, solid != 0] = 0.0
+    c = rng.standard_normal((9, N, N))
+    c[:, solid != 0] = 0.0
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta,
+                   precision=precision, tau=tau, solid=solid, k_field=kf, bc_clamp=clamp)
+    g.set_populations(f0)
+    g.set_boundary(a, b)
+    tape = g.adjoint_tape(eta)
+    g.substeps_record(eta, tape)
+    dev = g.dev
+    lam = torch.from_numpy(c).to(dev)
+    lam_out = torch.empty_like(lam)
+    ga = torch.zeros(P, dtype=torch.float64, device=dev)
+    gb = torch.zeros_like(ga)
+    gk = torch.zeros((N, N), dtype=torch.float64, device=dev)
+    g.adjoint(eta, tape, lam, lam_out, ga, gb, gk)
+    torch.cuda.synchronize()
+    lat = orc.Lattice(N, tau, vx.astype(np.float64), vy.astype(np.float64), solid=solid, k=kf, clamp=clamp)
+    fo = f0 if precision == "fp64" else f0.astype(np.float32).astype(np.float64)
+    ol, oa, ob, ok = _oracle_adjoint(orc, lat, fo, a, b, eta, c)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    errs = {"lam": _rel(lam_out.cpu().numpy(), ol), "a": _rel(ga.cpu().numpy(), oa),
+            "b": _rel(gb.cpu().numpy(), ob), "k": _rel(gk.cpu().numpy(), ok)}
+    print(f"\nadjoint {precision} N={N} clamp={clamp}: {errs}")
+    assert max(errs.values()) <= tol, errs
+    # the forward recording advanced the handle like hyb_lbm_substeps
+    g.commit()
+    fref = fo
+    for j in range(1, eta + 1):
+        fref, _ = lat.substep(fref, (1 - j / eta) * a + j / eta * b)
+    assert _rel(g.get_populations(), fref) <= (1e-13 if precision == "fp64" else 2e-6)
+
+
+def test_adjoint_dot_product_identity_on_gpu():
+    """<c, F(x, a, b)> = <F^T c, (x, a, b)> with the GPU forward and adjoint
+    (the step is linear and homogeneous with the unclamped closure)."""
+    hyb, torch = _gpu()
+    N, eta = 96, 6
+    rng, solid, vx, vy, kf, tau = _case(N, 7)
+    P = 4 * (N - 1)
+    x = rng.standard_normal((9, N, N))
+    x[:, solid != 0] = 0.0
+    a = rng.standard_normal(P)
+    b = rng.standard_normal(P)
+    c = rng.standard_normal((9, N, N))
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta, tau=tau,
+                   solid=solid, k_field=kf)
+    g.set_populations(x)
+    g.set_boundary(a, b)
+    tape = g.adjoint_tape(eta)
+    g.substeps_record(eta, tape)
+    lhs = float(np.sum(c * g.get_populations()))
+    lam = torch.from_numpy(c).to(g.dev)
+    ga = torch.zeros(P, dtype=torch.float64, device=g.dev)
+    gb = torch.zeros_like(ga)
+    g.adjoint(eta, tape, lam, lam, ga, gb)          # lam_out aliases lam_in
+    rhs = float(np.sum(lam.cpu().numpy() * x)) + float(ga.cpu().numpy() @ a) + float(gb.cpu().numpy() @ b)
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs)), (lhs, rhs)
+
+
+def test_autograd_function_gradients():
+    """torch.autograd wrapper: the gradient of J = sum(w * F(f0, a, b)) equals
+    the dot-product identity's pieces (checked by central differences along
+    random directions, exact for the linear map)."""
+    hyb, torch = _gpu()
+    N, eta = 40, 4
+    rng, solid, vx, vy, kf, tau = _case(N, 13)
+    P = 4 * (N - 1)
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta, tau=tau,
+                   solid=solid, k_field=kf)
+    Fn = hyb.lattice_substeps_function()
+    dev = g.dev
+    f0 = torch.from_numpy(inputs.random_populations(N, 3, lo=0.01, hi=0.1)).to(dev).requires_grad_(True)
+    a = torch.from_numpy(rng.uniform(0.1, 0.5, P)).to(dev).requires_grad_(True)
+    b = torch.from_numpy(rng.uniform(0.1, 0.5, P)).to(dev).requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((9, N, N))).to(dev)
+    w[:, torch.from_numpy(solid != 0).to(dev)] = 0.0
+    J = (w * Fn.apply(g, eta, f0, a, b)).sum()
+    J.backward()
+    d0 = torch.from_numpy(rng.standard_normal((9, N, N))).to(dev)
+    d0[:, torch.from_numpy(solid != 0).to(dev)] = 0.0
+    da = torch.from_numpy(rng.standard_normal(P)).to(dev)
+    db = torch.from_numpy(rng.standard_normal(P)).to(dev)
+    with torch.no_grad():
+        eps = 1e-3
+        Jp = (w * Fn.apply(g, eta, f0 + eps * d0, a + eps * da, b + eps * db)).sum()
+        Jm = (w * Fn.apply(g, eta, f0 - eps * d0, a - eps * da, b - eps * db)).sum()
+    fd = float((Jp - Jm) / (2 * eps))
+    an = float((f0.grad * d0).sum() + (a.grad * da).sum() + (b.grad * db).sum())
+    assert abs(fd - an) <= 1e-9 * max(1.0, abs(an)), (fd, an)
+
+
+def test_adjoint_rejects_unsupported():
+    hyb, torch = _gpu()
+    N = 16
+    z = np.zeros((N, N))
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.05, eta=3, precision="fp16s")
+    tape = g.adjoint_tape(2)
+    with pytest.raises(hyb.HybError):
+        g.substeps_record(2, tape)
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.05, eta=3)
+    kind = np.zeros(4 * (N - 1), np.int8)
+    kind[5] = 1
+    g.set_boundary(np.zeros(4 * (N - 1)), None, kind)
+    tape = g.adjoint_tape(2)
+    with pytest.raises(hyb.HybError):
+        g.substeps_record(2, tape)
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.05, eta=3)
+    tape = g.adjoint_tape(2)
+    g.substeps_record(2, tape)
+    lam = torch.zeros((9, N, N), dtype=torch.float64, device=g.dev)
+    ga = torch.zeros(4 * (N - 1), dtype=torch.float64, device=g.dev)
+    with pytest.raises(hyb.HybError):
+        g.adjoint(3, tape, lam, lam, ga, ga.clone())              # n_sub differs from the record
+    with pytest.raises(hyb.HybError):
+        g.substeps_record(4, g.adjoint_tape(4))                   # past eta
