@@ -306,6 +306,13 @@ __global__ void __launch_bounds__(kBlock) coarse_finish(CoarseDev c, const doubl
     }
 }
 
+// First guess of a coarse step's first solve: the linear extrapolation
+// 2 d(t_n) - d(t_{n-1}) in time, written to x1.
+__global__ void coarse_extrapolate_kernel(CoarseDev c, int len) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < len) c.x1[k] = 2.0 * c.xn[k] - c.xprev[k];
+}
+
 // a[p] = interpolant of xa, b[p] = interpolant of xb at perimeter slot p.
 __global__ void c2f_kernel(const int *__restrict__ idx, const double *__restrict__ w, int nslots,
                            const double *__restrict__ xa, const double *__restrict__ xb, double *__restrict__ a,
@@ -324,7 +331,11 @@ __global__ void c2f_kernel(const int *__restrict__ idx, const double *__restrict
     b[p] = sb;
 }
 
-// ufc[c] = sum of the four weighted lattice concentrations around Gamma_{f->c} node c.
+// ufc[c] = sum of the four weighted lattice concentrations around Gamma_{f->c}
+// node c.  Every index is a valid lattice node (dropped corners carry weight
+// 0), so all 36 population loads are issued at once; zero weights are
+// selected out rather than multiplied, so no value stored at a solid node can
+// reach the sum.
 template <typename S>
 __global__ void f2c_kernel(LbmArgs lat, const int *__restrict__ idx, const double *__restrict__ w, int nfc,
                            double *__restrict__ ufc) {
@@ -333,15 +344,26 @@ __global__ void f2c_kernel(LbmArgs lat, const int *__restrict__ idx, const doubl
     if (c >= nfc) return;
     const S *__restrict__ src = static_cast<const S *>(lat.src);
     const int plane = static_cast<int>(lat.plane);
-    double acc = 0.0;
+    int n[4];
+    double wm[4];
+#pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const double wm = w[4 * c + m];
-        if (wm == 0.0) continue;
-        const int n = idx[4 * c + m];
+        n[m] = idx[4 * c + m];
+        wm[m] = w[4 * c + m];
+    }
+    S raw[4][kQ];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) raw[m][q] = src[q * plane + n[m]];
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
         double u = 0.0;
-        for (int q = 0; q < kQ; ++q) u += double(Pop<S>::ld(src[q * plane + n], q, lat));
-        const double k = lat.kfield ? double(static_cast<const T *>(lat.kfield)[n]) : lat.k;
-        acc += wm * (u / (1.0 - k));
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) u += double(Pop<S>::ld(raw[m][q], q, lat));
+        const double k = lat.kfield ? double(static_cast<const T *>(lat.kfield)[n[m]]) : lat.k;
+        acc += wm[m] != 0.0 ? wm[m] * (u / (1.0 - k)) : 0.0;
     }
     ufc[c] = acc;
 }
@@ -366,6 +388,12 @@ hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iter
     return hipGetLastError();
 }
 
+hipError_t launch_coarse_extrapolate(const CoarseDev &c, hipStream_t s) {
+    const int len = c.S * c.S;
+    hipLaunchKernelGGL(coarse_extrapolate_kernel, dim3((len + 255) / 256), dim3(256), 0, s, c, len);
+    return hipGetLastError();
+}
+
 hipError_t launch_c2f(const int *idx, const double *w, int nslots, const double *xa, const double *xb, double *a,
                       double *b, hipStream_t s) {
     hipLaunchKernelGGL(c2f_kernel, dim3((nslots + 255) / 256), dim3(256), 0, s, idx, w, nslots, xa, xb, a, b);
@@ -375,7 +403,9 @@ hipError_t launch_c2f(const int *idx, const double *w, int nslots, const double 
 hipError_t launch_f2c(const LbmArgs &lat, const int *idx, const double *w, int nfc, double *ufc, int prec,
                       hipStream_t s) {
     if (nfc == 0) return hipSuccess;
-    const dim3 grid((nfc + 255) / 256), block(256);
+    // one wave per block: the few thousand coarse nodes spread over as many
+    // CUs as possible (every lane's 36 loads touch different cache lines)
+    const dim3 grid((nfc + 63) / 64), block(64);
     if (prec == HYB_FP64) hipLaunchKernelGGL(f2c_kernel<double>, grid, block, 0, s, lat, idx, w, nfc, ufc);
     else if (prec == HYB_FP32) hipLaunchKernelGGL(f2c_kernel<float>, grid, block, 0, s, lat, idx, w, nfc, ufc);
     else hipLaunchKernelGGL(f2c_kernel<_Float16>, grid, block, 0, s, lat, idx, w, nfc, ufc);

@@ -123,7 +123,7 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
         L.AP = take((size_t)L.n * kApW * kApW * 8);
         L.P = take((size_t)L.n * kSpaiW * kSpaiW * 8);
         L.dkind = take((size_t)L.n * 4);
-        L.vec = take(11 * align_up(L.vec_len * 8, kAlign));
+        L.vec = take(12 * align_up(L.vec_len * 8, kAlign));
         L.partials = take((size_t)16 * coarse_grid8(L.n) * 8);
         L.barrier = take(sizeof(KrylovState));
     }
@@ -424,8 +424,8 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         c.outer_value = mesh->outer_value;
         c.ufc = h->ufc;
         const size_t vstride = align_up(L.vec_len * 8, kAlign);
-        double *vec[11];
-        for (int v = 0; v < 11; ++v) vec[v] = reinterpret_cast<double *>(h->ws + L.vec + v * vstride);
+        double *vec[12];
+        for (int v = 0; v < 12; ++v) vec[v] = reinterpret_cast<double *>(h->ws + L.vec + v * vstride);
         c.xn = vec[0];
         c.x1 = vec[1];
         c.r = vec[2];
@@ -437,6 +437,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         c.y = vec[8];
         c.w = vec[9];
         c.z = vec[10];
+        c.xprev = vec[11];
         c.partials = reinterpret_cast<double *>(h->ws + L.partials);
         c.state = reinterpret_cast<KrylovState *>(h->ws + L.barrier);
         c.result = h->kres;
@@ -453,6 +454,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
             for (int kk = 0; kk < m1; ++kk) xp[(size_t)(l + kCoarseHalo) * L.S + kk + kCoarseHalo] = mesh->d0[l * m1 + kk];
         CREATE_TRY(up(c.xn, xp.data(), xp.size() * 8));
         CREATE_TRY(up(c.x1, xp.data(), xp.size() * 8));
+        CREATE_TRY(up(c.xprev, xp.data(), xp.size() * 8));
         // host staging must stay alive until the copies ran
         CREATE_TRY(hipStreamSynchronize(st));
     }
@@ -493,13 +495,15 @@ int hyb_coarse_step(hyb_handle *h, int max_iter) {
     if (!h) return HYB_EINVAL;
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "coarse step needs a coarse mesh");
     if (max_iter <= 0) max_iter = 200;
-    // first solve of a coarse step starts from d(t_n); later Schwarz passes
-    // start from the previous pass's solution
-    const double *guess = h->solved_this_step ? h->cd.x1 : h->cd.xn;
+    // first solve of a coarse step starts from the extrapolation
+    // 2 d(t_n) - d(t_{n-1}) (d(t_n) itself at the first step); later Schwarz
+    // passes start from the previous pass's solution
+    if (!h->solved_this_step) HIP_TRY(h, launch_coarse_extrapolate(h->cd, h->stream));
+    const double *guess = h->cd.x1;
     // iterations enqueued: a few more than the last solve needed (launches
     // after convergence are no-ops); hyb_commit reports a solve that ran out
     // of this budget and hyb_step then repeats the step with max_iter
-    const int budget = std::min(max_iter, std::max(6, h->last_krylov_iters + 2));
+    const int budget = std::min(max_iter, std::max(4, h->last_krylov_iters + 2));
     HIP_TRY(h, launch_coarse_rhs(h->cd, guess, h->stream));
     HIP_TRY(h, launch_coarse_solve(h->cd, guess, budget, max_iter, 1e-14, h->stream));
     h->solved_this_step = true;
@@ -596,7 +600,13 @@ int hyb_commit(hyb_handle *h) {
     }
     h->frozen = h->cur;
     h->jsub = 0;
-    if (h->solved_this_step) std::swap(h->cd.xn, h->cd.x1);
+    if (h->solved_this_step) {
+        // d(t_{n-1}) <- d(t_n) <- new solution; the old d(t_{n-1}) buffer is free
+        double *old_prev = h->cd.xprev;
+        h->cd.xprev = h->cd.xn;
+        h->cd.xn = h->cd.x1;
+        h->cd.x1 = old_prev;
+    }
     h->solved_this_step = false;
     h->coarse_steps += 1;
     return HYB_OK;

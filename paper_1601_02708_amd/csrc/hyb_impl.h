@@ -148,6 +148,7 @@ struct CoarseDev {
     const double *ufc;       // fine-to-coarse values
     double *xn;              // padded d(t_n)
     double *x1;              // padded new solution
+    double *xprev;           // padded d(t_{n-1}) (first-pass guess 2 d(t_n) - d(t_{n-1}))
     double *r, *rh, *p, *v, *s, *t, *y, *w, *z;   // padded Krylov vectors
     double *partials;        // [4 slots][4][pstride] reduction partials
     KrylovState *state;
@@ -155,6 +156,8 @@ struct CoarseDev {
 };
 
 hipError_t launch_coarse_rhs(const CoarseDev &c, const double *guess, hipStream_t s);
+// x1 = 2 xn - xprev over the padded grid (the halo stays zero)
+hipError_t launch_coarse_extrapolate(const CoarseDev &c, hipStream_t s);
 // Enqueues `iterations` BiCGSTAB iterations (three kernels each; no-ops
 // once converged or past max_iter), a closing convergence test and the
 // update x1 = guess + P y.

@@ -360,10 +360,10 @@ __global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
 // ---------------------------------------------------------------------------
 
 // Raw buffer access (gfx9 buffer instructions): the array base and size
-// live in one SGPR resource, the population plane offset q * plane is the
-// scalar offset and each lane supplies a 32-bit byte offset, so a pull
-// costs no 64-bit address arithmetic.  Offsets at or past num_records read
-// as 0 without touching memory.
+// live in one SGPR resource and each lane supplies a 32-bit byte offset
+// (stores add the plane offset q * plane as the scalar offset), so a pull
+// or a store costs no 64-bit address arithmetic.  Offsets at or past
+// num_records read as 0 without touching memory.
 typedef __amdgpu_buffer_rsrc_t BufRsrc;
 __device__ __forceinline__ BufRsrc buf_rsrc(const void *p, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
@@ -395,13 +395,13 @@ template <> struct Buf<_Float16> {
     }
 };
 
-template <typename S, int TW, int TH>
-__global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
+template <typename S, int TW, int TH, int NT>
+__global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
     typedef typename Pop<S>::T T;
     constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
-    constexpr int ROUNDS1 = (R1 + 255) / 256;
-    static_assert((TW * TH) % 256 == 0 && 256 % TW == 0, "second half: whole rows per wave round");
-    constexpr int ROUNDS2 = TW * TH / 256;
+    constexpr int ROUNDS1 = (R1 + NT - 1) / NT;
+    static_assert((TW * TH) % NT == 0 && NT % TW == 0, "second half: whole rows per round");
+    constexpr int ROUNDS2 = TW * TH / NT;
     constexpr unsigned sz = sizeof(S);
     __shared__ T lds[kQ][H1][W1];
 
@@ -420,61 +420,89 @@ __global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x,
     const int y0 = (t / tiles_x) * TH;
 
     // ---- first half: step j+1 on the tile and its ring, into LDS --------
-    // Pull x - e_q reads plane q at row j - cy_q, column i - cx_q.  For
-    // i >= 1 the three row offsets of column i - 1 (rows clamped onto the
-    // patch) plus 0, 1 or 2 elements address all nine pulls; a column of
-    // N then falls in the row padding or the next row of the same plane,
-    // inside the buffer.  The left column (i = 0) clamps every pull onto
-    // the patch.  Values fetched for upstream nodes outside the patch are
-    // replaced by the closure.
+    // Pull x - e_q reads plane q at row j - cy_q, column i - cx_q, both
+    // clamped onto the patch (values fetched for upstream nodes outside the
+    // patch are replaced by the closure).  Measured against conditional
+    // reloads of the bounce-back values: 11% faster at 2048^2 in FP32, 14%
+    // in FP64 (no divergent branches, no second round trip).
     S raw[ROUNDS1][kQ];
     unsigned m[ROUNDS1];
     float vx1[ROUNDS1], vy1[ROUNDS1];
+    // node coordinates of each round, stepped without divisions
+    int rr[ROUNDS1], cc[ROUNDS1];
+    rr[0] = threadIdx.x / W1;
+    cc[0] = threadIdx.x - rr[0] * W1;
+#pragma unroll
+    for (int k = 1; k < ROUNDS1; ++k) {
+        rr[k] = rr[k - 1] + NT / W1;
+        cc[k] = cc[k - 1] + NT % W1;
+        if (cc[k] >= W1) {
+            cc[k] -= W1;
+            rr[k] += 1;
+        }
+    }
+    // flag words first; every pull then reads either its upstream value or,
+    // for a solid upstream node, the node's own opposite population: the
+    // byte offset is n sz + K_q + (bit_q ? D_q : 0) with K_q, D_q uniform
+    // (no branch, no second load)
 #pragma unroll
     for (int k = 0; k < ROUNDS1; ++k) {
-        const int idx = threadIdx.x + 256 * k;
-        const int r = idx / W1, c = idx - (idx / W1) * W1;
-        const int i = x0 - 1 + c, j = y0 - 1 + r;
+        const int i = x0 - 1 + cc[k], j = y0 - 1 + rr[k];
         m[k] = kMaskSolid;
-        if (idx < R1 && i >= 0 && j >= 0 && i < N && j < N) {
-            const unsigned n = static_cast<unsigned>(j * P + i);
-            m[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * n, 0, 0);
-            vx1[k] = Buf<float>::load(vxr, 4u * n, 0);
-            vy1[k] = Buf<float>::load(vyr, 4u * n, 0);
+        if (rr[k] < H1 && i >= 0 && j >= 0 && i < N && j < N)
+            m[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * static_cast<unsigned>(j * P + i), 0, 0);
+    }
+    unsigned K[kQ], D[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const unsigned pull = q * SP - static_cast<unsigned>(kCx[q] + kCy[q] * P);
+        const unsigned own = kOpp[q] * SP;
+        K[q] = pull * sz;
+        D[q] = (own - pull) * sz;            // modulo 2^32; the sum below is exact
+    }
+#pragma unroll
+    for (int k = 0; k < ROUNDS1; ++k) {
+        if (m[k] & kMaskSolid) continue;
+        const int i = x0 - 1 + cc[k], j = y0 - 1 + rr[k];
+        const unsigned n = static_cast<unsigned>(j * P + i);
+        vx1[k] = Buf<float>::load(vxr, 4u * n, 0);
+        vy1[k] = Buf<float>::load(vyr, 4u * n, 0);
+        if (i >= 1 && j >= 1 && i <= N - 2 && j <= N - 2) {
+            const unsigned nb = n * sz;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const unsigned sel = 0u - ((m[k] >> q) & 1u);
+                raw[k][q] = Buf<S>::load(fsrc, nb + K[q] + (sel & D[q]), 0);
+            }
+        } else {
+            // patch edge: upstream rows and columns clamped onto the patch
             const int jm = j > 0 ? j - 1 : 0, jp = j < N - 1 ? j + 1 : N - 1;
-            if (i > 0) {
-                // byte offset of column i - 1 in rows j + 1, j, j - 1
-                const unsigned base[3] = {static_cast<unsigned>(jp * P + i - 1) * sz, (n - 1u) * sz,
-                                          static_cast<unsigned>(jm * P + i - 1) * sz};
+            const int il = i > 0 ? i - 1 : 0, ir = i < N - 1 ? i + 1 : N - 1;
 #pragma unroll
-                for (int q = 0; q < kQ; ++q)
-                    raw[k][q] = Buf<S>::load(fsrc, base[1 + kCy[q]] + (1 - kCx[q]) * sz, q * SP * sz);
-            } else {
-#pragma unroll
-                for (int q = 0; q < kQ; ++q) {
-                    const int sj = kCy[q] == 1 ? jm : kCy[q] == -1 ? jp : j;
-                    const int si = kCx[q] == -1 ? 1 : 0;           // column -1 clamped to 0
-                    raw[k][q] = Buf<S>::load(fsrc, static_cast<unsigned>(sj * P + si) * sz, q * SP * sz);
-                }
+            for (int q = 0; q < kQ; ++q) {
+                const int sj = kCy[q] == 1 ? jm : kCy[q] == -1 ? jp : j;
+                const int si = kCx[q] == 1 ? il : kCx[q] == -1 ? ir : i;
+                const unsigned pull = q * SP + static_cast<unsigned>(sj * P + si);
+                const unsigned own = kOpp[q] * SP + n;
+                raw[k][q] = Buf<S>::load(fsrc, (((m[k] >> q) & 1u) ? own : pull) * sz, 0);
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < ROUNDS1; ++k) {
         if (m[k] & kMaskSolid) continue;
-        const int idx = threadIdx.x + 256 * k;
-        const int r = idx / W1, c = idx - (idx / W1) * W1;
+        const int r = rr[k], c = cc[k];
         const int i = x0 - 1 + c, j = y0 - 1 + r;
         const unsigned n = static_cast<unsigned>(j * P + i);
         const bool owned = r >= 1 && r <= TH && c >= 1 && c <= TW;
         T f[kQ];
+        // raw already holds the bounce-back values; decode with the plane
+        // each value came from
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) f[q] = Pop<S>::ld(raw[k][q], q, a);
-        if (m[k] & 0x1FEu) {
-#pragma unroll
-            for (int q = 1; q < kQ; ++q)
-                if ((m[k] >> q) & 1u)
-                    f[q] = Pop<S>::ld(Buf<S>::load(fsrc, n * sz, kOpp[q] * SP * sz), kOpp[q], a);
+        for (int q = 0; q < kQ; ++q) {
+            const T pulled = Pop<S>::ld(raw[k][q], q, a);
+            const T own = Pop<S>::ld(raw[k][q], kOpp[q], a);
+            f[q] = ((m[k] >> q) & 1u) ? own : pulled;
         }
         if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
             const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
@@ -492,7 +520,7 @@ __global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x,
     float vx2[ROUNDS2], vy2[ROUNDS2];
 #pragma unroll
     for (int k = 0; k < ROUNDS2; ++k) {
-        const int idx = threadIdx.x + 256 * k;
+        const int idx = threadIdx.x + NT * k;
         const int i = x0 + idx % TW, j = y0 + idx / TW;
         m2[k] = kMaskSolid;
         if (i < N && j < N) {
@@ -508,19 +536,25 @@ __global__ void __launch_bounds__(256) lbm_sweep2_kernel(LbmArgs a, int tiles_x,
 #pragma unroll
     for (int k = 0; k < ROUNDS2; ++k) {
         if (m2[k] & kMaskSolid) continue;
-        const int idx = threadIdx.x + 256 * k;
+        const int idx = threadIdx.x + NT * k;
         const int r = idx / TW, c = idx % TW;
         const int i = x0 + c, j = y0 + r;
         const unsigned n = static_cast<unsigned>(j * P + i);
         const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
         const unsigned unknown = perim ? outside_bits(N, i, j) : 0u;
         T g[kQ];
-        g[0] = lds[0][r + 1][c + 1];
+        {
+            // one LDS read per direction at a selected address (upstream
+            // value, or the node's own opposite value for a solid upstream
+            // node); closure unknowns are overwritten below
+            const T *base = &lds[0][0][0] + (r + 1) * W1 + (c + 1);
 #pragma unroll
-        for (int q = 1; q < kQ; ++q) {
-            if ((m2[k] >> q) & 1u) g[q] = lds[kOpp[q]][r + 1][c + 1];
-            else if ((unknown >> q) & 1u) g[q] = T(0);
-            else g[q] = lds[q][r + 1 - kCy[q]][c + 1 - kCx[q]];
+            for (int q = 0; q < kQ; ++q) {
+                const int pull = q * (H1 * W1) - kCy[q] * W1 - kCx[q];
+                const int back = kOpp[q] * (H1 * W1);
+                const int sel = -static_cast<int>((m2[k] >> q) & 1u);
+                g[q] = base[pull + (sel & (back - pull))];
+            }
         }
         if (perim) {
             const bool bad = dirichlet_close<T>(a, g, unknown, perimeter_slot(N, i, j), a.lam2);
@@ -607,18 +641,39 @@ hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hi
 }
 
 // Tile shape of the two-step sweep: LDS holds 9 planes of (TW+2) x (TH+2)
-// values of the arithmetic type.  64 x 8 in every precision (LDS 23.8 KB
-// with FP32 arithmetic, six workgroups per CU; 47.5 KB in FP64, three).  On
-// the 2048^2 and 4096^2 pore workloads 64 x 8 FP32 tiles ran 14% faster
-// than 64 x 16 ones (more workgroups in flight hide the memory latency of
-// the first half); FP64 measured the same with 4, 8 or 12 rows.
-constexpr int kTileW = 64, kTileH = 8;
+// values of the arithmetic type.  64 x 8 tiles: 23.8 KB of LDS with FP32
+// arithmetic (256 lanes, six workgroups per CU), 47.5 KB in FP64 (512 lanes,
+// three workgroups per CU).  Measured on the 2048^2 and 4096^2 pore
+// workloads: FP32 64 x 8 ran 14% faster than 64 x 16 with 256 lanes and the
+// same as 64 x 16 with 512 lanes; 64 x 24 and 64 x 32 (1024 lanes) were
+// slower at 2048^2.  FP64 with 512 lanes ran 4-7% faster than with 256.
+#ifndef SWEEP2_TH32
+#define SWEEP2_TH32 8
+#endif
+#ifndef SWEEP2_NT32
+#define SWEEP2_NT32 256
+#endif
+#ifndef SWEEP2_TH64
+#define SWEEP2_TH64 8
+#endif
+#ifndef SWEEP2_NT64
+#define SWEEP2_NT64 512
+#endif
+#ifndef SWEEP2_TW32
+#define SWEEP2_TW32 64
+#endif
+#ifndef SWEEP2_TW64
+#define SWEEP2_TW64 64
+#endif
+template <typename S> struct Tile2 { static constexpr int TW = SWEEP2_TW32, TH = SWEEP2_TH32, NT = SWEEP2_NT32; };
+template <> struct Tile2<double> { static constexpr int TW = SWEEP2_TW64, TH = SWEEP2_TH64, NT = SWEEP2_NT64; };
 
 template <typename S>
 hipError_t step2_impl(const LbmArgs &a, hipStream_t s) {
-    auto kernel = lbm_sweep2_kernel<S, kTileW, kTileH>;
-    const int tx = (a.N + kTileW - 1) / kTileW, ty = (a.N + kTileH - 1) / kTileH;
-    hipLaunchKernelGGL(kernel, dim3(tx * ty), dim3(256), 0, s, a, tx, tx * ty);
+    constexpr int TW = Tile2<S>::TW, TH = Tile2<S>::TH, NT = Tile2<S>::NT;
+    auto kernel = lbm_sweep2_kernel<S, TW, TH, NT>;
+    const int tx = (a.N + TW - 1) / TW, ty = (a.N + TH - 1) / TH;
+    hipLaunchKernelGGL(kernel, dim3(tx * ty), dim3(NT), 0, s, a, tx, tx * ty);
     return hipGetLastError();
 }
 
