@@ -43,6 +43,23 @@ def coarse_dirichlet_sets(M, L, N, x0, y0, overlap_elems=1):
     return np.sort(idx[outer]), np.sort(idx[inner])
 
 
+def algorithm1_step(h):
+    """One coarse step of Algorithm 1 on a two-subdomain hybrid ``h`` (any
+    dimension): h.fstar and h.d hold the fine and coarse states at t_n;
+    h.fine_to_coarse, h.coarse_to_fine, h.coarse_step and h.lbm_substeps are
+    the transfers and the two solvers; h.max_iter Schwarz iterations, each
+    restarting both subdomains from t_n, the last one committed."""
+    ufc = h.fine_to_coarse(h.fstar)
+    a = h.coarse_to_fine(h.d)
+    for _ in range(h.max_iter):
+        d1 = h.coarse_step(h.d, ufc)
+        b = h.coarse_to_fine(d1)
+        F = h.lbm_substeps(h.fstar, a, b)
+        ufc = h.fine_to_coarse(F)
+    h.fstar = F
+    h.d = d1
+
+
 class HybridOracle:
     """State and steps of the two-subdomain hybrid method on the host."""
 
@@ -104,15 +121,7 @@ class HybridOracle:
 
     # -- Algorithm 1 -------------------------------------------------------
     def step(self):
-        ufc = self.fine_to_coarse(self.fstar)
-        a = self.coarse_to_fine(self.d)
-        for _ in range(self.max_iter):
-            d1 = self.coarse_step(self.d, ufc)
-            b = self.coarse_to_fine(d1)
-            F = self.lbm_substeps(self.fstar, a, b)
-            ufc = self.fine_to_coarse(F)
-        self.fstar = F
-        self.d = d1
+        algorithm1_step(self)
 
     def run(self, steps):
         for _ in range(steps):
