@@ -216,6 +216,16 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape);
 int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *lam_in, double *lam_out,
                     double *grad_a, double *grad_b, double *grad_k);
 
+/* Overlap in hyb_step (default on): with two-step launches, the interior
+ * tiles of each Schwarz pass's first launch (those whose one-node ring
+ * stays clear of the patch perimeter, so they read no interface value) run
+ * on a second stream owned by the handle while the pass's fine-to-coarse
+ * transfer, coarse solve and coarse-to-fine transfer run on the caller's
+ * stream; the remaining tiles follow on the caller's stream.  Results are
+ * bit-identical to the serial order.  enable = 0 runs everything on the
+ * caller's stream. */
+int hyb_set_overlap(hyb_handle *h, int enable);
+
 /* Fine steps per lattice-sweep launch (1 or 2; default 2).  With 2, while
  * every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine steps in
  * pairs, each pair in one temporally blocked launch (the state between the

@@ -395,8 +395,54 @@ template <> struct Buf<_Float16> {
     }
 };
 
+// Which tiles a two-step launch covers: all of the tiles_x x tiles_y grid
+// (part 0), the rectangle [ix0, ix1] x [iy0, iy1] of tiles whose ring stays
+// clear of the patch perimeter (part 1), or the other tiles (part 2).  A
+// part-1 launch reads no interface value, so it may run while the coarse
+// solve that produces them is still in flight.
+struct TileMap {
+    int tiles_x, tiles_y;
+    int part;
+    int ix0, ix1, iy0, iy1;
+    int count;               // tiles in this part
+};
+
+__device__ __forceinline__ void tile_of(const TileMap &m, int t, int &tx, int &ty) {
+    if (m.part == 0) {
+        tx = t % m.tiles_x;
+        ty = t / m.tiles_x;
+        return;
+    }
+    const int iw = m.ix1 - m.ix0 + 1;
+    if (m.part == 1) {
+        tx = m.ix0 + t % iw;
+        ty = m.iy0 + t / iw;
+        return;
+    }
+    // part 2: rows below the rectangle, then its left and right margins row
+    // by row, then the rows above it
+    const int below = m.iy0 * m.tiles_x;
+    if (t < below) {
+        tx = t % m.tiles_x;
+        ty = t / m.tiles_x;
+        return;
+    }
+    t -= below;
+    const int side = m.tiles_x - iw;           // margin tiles per middle row
+    const int middle = (m.iy1 - m.iy0 + 1) * side;
+    if (t < middle) {
+        const int r = t / side, k = t % side;
+        ty = m.iy0 + r;
+        tx = k < m.ix0 ? k : m.ix1 + 1 + (k - m.ix0);
+        return;
+    }
+    t -= middle;
+    tx = t % m.tiles_x;
+    ty = m.iy1 + 1 + t / m.tiles_x;
+}
+
 template <typename S, int TW, int TH, int NT>
-__global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, int tiles_x, int tiles) {
+__global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) {
     typedef typename Pop<S>::T T;
     constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
     constexpr int ROUNDS1 = (R1 + NT - 1) / NT;
@@ -415,9 +461,10 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, int tiles_x, 
     const BufRsrc vxr = buf_rsrc(a.vx, NP * 4u);
     const BufRsrc vyr = buf_rsrc(a.vy, NP * 4u);
     const T omega = T(a.omega);
-    const int t = xcd_tile(blockIdx.x, tiles);
-    const int x0 = (t % tiles_x) * TW;
-    const int y0 = (t / tiles_x) * TH;
+    int tx, ty;
+    tile_of(map, xcd_tile(blockIdx.x, map.count), tx, ty);
+    const int x0 = tx * TW;
+    const int y0 = ty * TH;
 
     // ---- first half: step j+1 on the tile and its ring, into LDS --------
     // Pull x - e_q reads plane q at row j - cy_q, column i - cx_q, both
@@ -669,20 +716,39 @@ template <typename S> struct Tile2 { static constexpr int TW = SWEEP2_TW32, TH =
 template <> struct Tile2<double> { static constexpr int TW = SWEEP2_TW64, TH = SWEEP2_TH64, NT = SWEEP2_NT64; };
 
 template <typename S>
-hipError_t step2_impl(const LbmArgs &a, hipStream_t s) {
+hipError_t step2_impl(const LbmArgs &a, int part, hipStream_t s) {
     constexpr int TW = Tile2<S>::TW, TH = Tile2<S>::TH, NT = Tile2<S>::NT;
     auto kernel = lbm_sweep2_kernel<S, TW, TH, NT>;
-    const int tx = (a.N + TW - 1) / TW, ty = (a.N + TH - 1) / TH;
-    hipLaunchKernelGGL(kernel, dim3(tx * ty), dim3(NT), 0, s, a, tx, tx * ty);
+    TileMap m{};
+    m.tiles_x = (a.N + TW - 1) / TW;
+    m.tiles_y = (a.N + TH - 1) / TH;
+    m.part = part;
+    // interior rectangle: tiles whose ring (x0 - 1 .. x0 + TW, y0 - 1 .. y0 + TH)
+    // lies within columns and rows 1 .. N-2
+    m.ix0 = 1;
+    m.iy0 = 1;
+    m.ix1 = (a.N - 2 - TW) / TW;
+    m.iy1 = (a.N - 2 - TH) / TH;
+    const bool has_interior = a.N - 2 - TW >= TW && a.N - 2 - TH >= TH && m.ix1 >= m.ix0 && m.iy1 >= m.iy0;
+    const int all = m.tiles_x * m.tiles_y;
+    const int inner = has_interior ? (m.ix1 - m.ix0 + 1) * (m.iy1 - m.iy0 + 1) : 0;
+    if (part != 0 && !has_interior) {
+        // no interior rectangle: part 1 is empty, part 2 is everything
+        if (part == 1) return hipSuccess;
+        m.part = 0;
+    }
+    m.count = m.part == 0 ? all : m.part == 1 ? inner : all - inner;
+    if (m.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(kernel, dim3(m.count), dim3(NT), 0, s, a, m);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s) {
-    if (prec == HYB_FP64) return step2_impl<double>(a, s);
-    if (prec == HYB_FP32) return step2_impl<float>(a, s);
-    return step2_impl<_Float16>(a, s);
+hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part) {
+    if (prec == HYB_FP64) return step2_impl<double>(a, part, s);
+    if (prec == HYB_FP32) return step2_impl<float>(a, part, s);
+    return step2_impl<_Float16>(a, part, s);
 }
 
 hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, hipStream_t s,

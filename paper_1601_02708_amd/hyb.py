@@ -69,6 +69,7 @@ SIGNATURES = {
     "hyb_adjoint_query": (_i, [_P, _i, _P]),
     "hyb_lbm_substeps_record": (_i, [_P, _i, _P]),
     "hyb_lbm_adjoint": (_i, [_P, _i, _P, _P, _P, _P, _P, _P]),
+    "hyb_set_overlap": (_i, [_P, _i]),
     "hyb_set_steps_per_launch": (_i, [_P, _i]),
     "hyb_kernel_timing": (_i, [_P, _i]),
     "hyb_kernel_time": (_i, [_P, _P, _P]),
@@ -258,6 +259,9 @@ class Hybrid:
         return self._check(load().hyb_lbm_adjoint(self.h, int(n_sub), tape.data_ptr(), lam_in.data_ptr(),
                                                   lam_out.data_ptr(), grad_a.data_ptr(), grad_b.data_ptr(),
                                                   None if grad_k is None else grad_k.data_ptr()))
+
+    def set_overlap(self, enable):
+        return self._check(load().hyb_set_overlap(self.h, int(enable)))
 
     def set_steps_per_launch(self, steps):
         return self._check(load().hyb_set_steps_per_launch(self.h, int(steps)))

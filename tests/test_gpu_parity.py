@@ -164,6 +164,28 @@ def test_two_step_sweep(orc, precision, N, clamp, k_field, eta):
     assert d <= (1e-14 if precision == "fp64" else 1e-6), d
 
 
+@pytest.mark.parametrize("name,over,precision,steps", [("small", {}, "fp64", 6),
+                                                      ("pore2048", {"N": 257, "M": 32}, "fp32", 4),
+                                                      ("pore2048", {"N": 131, "M": 16, "eta": 5}, "fp64", 3)])
+def test_overlapped_step_is_bit_identical(name, over, precision, steps):
+    """hyb_step with the interior tiles of each pass's first launch on the
+    handle's side stream (overlapping the coarse solve) equals the serial
+    order bit for bit; odd eta mixes two-step and single-step launches."""
+    hyb = _gpu()
+    p = problem(name, **over)
+    out = []
+    for ov in (1, 0):
+        g = hyb.Hybrid.from_problem(p, precision=precision)
+        g.set_overlap(ov)
+        for _ in range(steps):
+            g.step(p.cfg.max_iter)
+        out.append((g.get_populations(), g.concentration(hyb.HYB_COARSE), g.stats()["infeasible"]))
+        g.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+
+
 def test_steps_per_launch_rejects_other_values():
     hyb = _gpu()
     N = 8
