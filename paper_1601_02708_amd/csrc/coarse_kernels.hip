@@ -10,9 +10,8 @@
 // products are reduced deterministically (each workgroup writes a partial,
 // the next kernel sums all partials in block order); the preconditioner P
 // (a sparse approximate inverse computed on the host) is folded into the
-// operator A P.  One BiCGSTAB iteration is three kernels with one reduction
-// each; a device-side flag turns the launches after convergence into
-// no-ops.
+// operator A P.  One BiCGSTAB iteration is two kernels with one reduction
+// each; device-side flags turn the launches after convergence into no-ops.
 #include "hyb_impl.h"
 
 namespace hyb {
@@ -62,6 +61,37 @@ __device__ __forceinline__ double ap_row8(const CoarseDev &c, int node, int pidx
     return acc;
 }
 
+// The same product for the vector s - omega t, formed entry by entry from
+// two complete vectors (the entries equal what the row owners compute).
+__device__ __forceinline__ double ap_row8_diff(const CoarseDev &c, int node, int pidx, int g, bool valid,
+                                               const double *__restrict__ s, const double *__restrict__ t,
+                                               double omega) {
+    constexpr int W = kApW, R = W / 2;
+    double acc = 0.0;
+    if (valid && g < W) {
+        const double *__restrict__ cr = c.AP + (size_t)node * (W * W) + g * W;
+        const size_t o = pidx + (g - R) * c.S - R;
+#pragma unroll
+        for (int dk = 0; dk < W; ++dk) acc += cr[dk] * (s[o + dk] - omega * t[o + dk]);
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    return acc;
+}
+
+// Dense part of the shadow residual: the MurmurHash3 32-bit finaliser of
+// the node index, mapped to [-1, 1).
+__device__ __forceinline__ double shadow_hash(int node) {
+    unsigned x = static_cast<unsigned>(node) * 0x9E3779B9u + 0x7F4A7C15u;
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return double(x) * (2.0 / 4294967296.0) - 1.0;
+}
+
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     // wave reduction then across the waves of the block
@@ -93,7 +123,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
 // into its own slot; the next kernel sums all blocks in block order, so the
 // scalars are bit-identical in every block (deterministic).
 __device__ __forceinline__ double *slot_ptr(const CoarseDev &c, int slot) {
-    return c.partials + (size_t)slot * 4 * c.pstride;
+    return c.partials + (size_t)slot * kPartialValues * c.pstride;
 }
 template <int NV>
 __device__ __forceinline__ void write_partials(const CoarseDev &c, int slot, double (&v)[NV], double *lds) {
@@ -138,14 +168,15 @@ __device__ __forceinline__ void read_sums(const CoarseDev &c, int slot, int bloc
     __syncthreads();
 }
 
-enum Slot { kSlotRhs = 0, kSlotA = 1, kSlotB = 2, kSlotC = 3 };
+enum Slot { kSlotRhs = 0, kSlotA = 1, kSlotB = 2 };
 
 // b = B d(t_n) on free rows, a_ii times the prescribed value on Dirichlet
 // rows; r0 = b - A x0 (x0 = initial guess).  Initialises the Krylov
-// vectors and the solver state for the kernels that follow.
+// vectors and the solver state for the kernels that follow; partials
+// b.b, r0.r0 and h.r0 (h = shadow_hash).
 __global__ void __launch_bounds__(kBlock) coarse_rhs_kernel(CoarseDev c, const double *__restrict__ guess) {
     __shared__ double lds[32];
-    double red[2] = {0.0, 0.0};
+    double red[3] = {0.0, 0.0, 0.0};
     const int node = blockIdx.x * blockDim.x + threadIdx.x;
     if (node < c.n) {
         const int pidx = padded_index(c, node);
@@ -155,92 +186,140 @@ __global__ void __launch_bounds__(kBlock) coarse_rhs_kernel(CoarseDev c, const d
         else b = c.A9[(size_t)4 * c.n + node] * (kind == -2 ? c.outer_value : c.ufc[kind]);
         const double r0 = b - stencil_row<3>(c.A9, c.n, node, pidx, c.S, guess);
         c.r[pidx] = r0;
-        c.rh[pidx] = r0;
         c.p[pidx] = 0.0;
         c.v[pidx] = 0.0;
         c.z[pidx] = 0.0;
         c.y[pidx] = 0.0;
         red[0] = b * b;
         red[1] = r0 * r0;
+        red[2] = shadow_hash(node) * r0;
     }
-    write_partials<2>(c, kSlotRhs, red, lds);
+    write_partials<3>(c, kSlotRhs, red, lds);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         KrylovState &st = *c.state;
         st.rho = 1.0;
         st.alpha = 1.0;
-        st.omega = 1.0;
         st.iters = 0;
         st.done = 0;
+        st.brk = 0;
+        st.skip = 0;
     }
 }
 
-// Right-preconditioned BiCGSTAB on (A P) y = r0, x = x0 + P y, split into
-// three kernels per iteration so every cross-block dependency is a kernel
-// boundary (the device-scope cache maintenance happens once per launch
-// instead of once per block and barrier).  With v = A P p, z = A P v,
-// w = A P r, linearity gives
-//   p = r + beta (p - omega v),   v' = w + beta (v - omega z),
-//   s = r - alpha v',  t = A P s = w - alpha z',  z' = A P v',
-// so each kernel needs neighbour values only of vectors completed by the
-// previous kernel.
+// Right-preconditioned BiCGSTAB on (A P) y = r0, x = x0 + P y, two kernels
+// per iteration; every cross-block dependency is a kernel boundary (the
+// device-scope cache maintenance happens once per launch instead of once per
+// block and barrier).  Iteration k:
 //
-// A: sum (rh.r, r.r) of the previous iteration (or the rhs kernel); stop if
-//    ||r|| <= tol ||b||; beta; p, w = A P r, v' ; partial rh.v'.
-__global__ void __launch_bounds__(kBlock) coarse_iter_a(CoarseDev c, int first, double tol, int max_iter) {
+//   A(k): finish iteration k-1 -- omega = t.s / t.t, y += alpha p + omega s,
+//         r = s - omega t -- with rho_k = rh.r = rh.s - omega rh.t from
+//         B(k-1)'s sums; beta = (rho_k / rho_{k-1}) (alpha / omega);
+//         w = A P r (from the neighbours' s - omega t); p = r + beta (p -
+//         omega v); v' = A P p = w + beta (v - omega z); partials rh.v', r.r.
+//   B(k): stop if ||r_k|| <= tol ||b|| (the explicit r.r of A(k)), at a
+//         breakdown, or at k = max_iter; else alpha = rho_k / rh.v';
+//         s = r - alpha v'; z = A P v'; t = A P s = w - alpha z; partials
+//         t.s, t.t, rh.s, rh.t.
+//
+// A(0) starts from r0 and sets the shadow residual rh = r0 + gamma h, with
+// h = shadow_hash and gamma = ||r0|| / sqrt(n) (rho_0 = r0.r0 + gamma h.r0).
+// The dense part matters: a warm start leaves r0 on the Dirichlet rows,
+// which A P maps almost onto themselves, and with rh = r0 the later rh.r
+// would be rounding noise (a near breakdown that the folded rho = rh.s -
+// omega rh.t cannot survive).  The state block is read by every block of a
+// kernel and written (by block 0) only under names that kernel does not
+// read: A writes rho_next, brk, skip and (A(0)) bb = b.b; B writes rho,
+// alpha and done.
+__global__ void __launch_bounds__(kBlock) coarse_iter_a(CoarseDev c, int k) {
     __shared__ double lds[32];
     KrylovState &st = *c.state;
-    if (st.done) return;
-    double rs[2], cs[2];
-    read_sums<2>(c, kSlotRhs, c.grid, rs, lds);
-    if (!first) read_sums<2>(c, kSlotC, c.grid, cs, lds);
-    const double bnorm = sqrt(rs[0]);
-    const double rho_new = first ? rs[1] : cs[0];
-    const double rnorm = sqrt(first ? rs[1] : cs[1]);
+    if (st.done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st.skip = 1;
+        return;
+    }
+    const bool first = k == 0;
+    double rho, omega = 0.0, gamma = 0.0, bb = 0.0;
+    if (first) {
+        double rs[3];
+        read_sums<3>(c, kSlotRhs, c.grid, rs, lds);
+        bb = rs[0];
+        gamma = sqrt(rs[1] / c.n);
+        rho = rs[1] + gamma * rs[2];
+    } else {
+        double bs[4];
+        read_sums<4>(c, kSlotB, c.grid8, bs, lds);
+        omega = bs[1] > 0.0 ? bs[0] / bs[1] : 0.0;
+        rho = bs[2] - omega * bs[3];
+    }
+    const bool breakdown = !first && (omega == 0.0 || rho == 0.0);
+    const double alpha = st.alpha;
+    const double beta = (first || breakdown) ? 0.0 : (rho / st.rho) * (alpha / omega);
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int node = gt >> 3, g = gt & 7;
+    const bool valid = node < c.n;
+    const int pi = valid ? padded_index(c, node) : 0;
+    // r_k at this row; lane 0 of the row's eight also folds iteration k-1
+    double r = 0.0;
+    if (valid) {
+        if (first) {
+            r = c.r[pi];
+        } else {
+            const double sv = c.s[pi];
+            r = sv - omega * c.t[pi];
+            if (g == 0) {
+                c.y[pi] += alpha * c.p[pi] + omega * sv;
+                c.r[pi] = r;
+            }
+        }
+    }
+    const double w = first ? ap_row8(c, node, pi, g, valid, c.r) : ap_row8_diff(c, node, pi, g, valid, c.s, c.t, omega);
+    double red[2] = {0.0, 0.0};
+    if (valid && g == 0) {
+        double rh;
+        if (first) {
+            rh = r + gamma * shadow_hash(node);
+            c.rh[pi] = rh;
+        } else {
+            rh = c.rh[pi];
+        }
+        c.p[pi] = r + beta * (c.p[pi] - omega * c.v[pi]);
+        const double vn = w + beta * (c.v[pi] - omega * c.z[pi]);
+        c.w[pi] = w;
+        c.v[pi] = vn;
+        red[0] = rh * vn;
+        red[1] = r * r;
+    }
+    write_partials<2>(c, kSlotA, red, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st.rho_next = rho;
+        st.brk = breakdown ? 1 : 0;
+        st.skip = 0;
+        if (first) st.bb = bb;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) coarse_iter_b(CoarseDev c, int k, double tol, int max_iter) {
+    __shared__ double lds[32];
+    KrylovState &st = *c.state;
+    if (st.skip) return;
+    double as[2];
+    read_sums<2>(c, kSlotA, c.grid8, as, lds);
+    const double bnorm = sqrt(st.bb);
+    const double rnorm = sqrt(as[1]);
     const bool converged = rnorm <= tol * (bnorm > 0.0 ? bnorm : 1.0);
-    const bool breakdown = !first && st.omega == 0.0;
-    if (converged || breakdown || st.iters >= max_iter || !(rnorm == rnorm)) {
+    if (converged || st.brk || k >= max_iter || !(rnorm == rnorm)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st.done = 1;
             st.converged = converged ? 1 : 0;
             st.rnorm = rnorm;
             st.bnorm = bnorm;
+            st.iters = k;
         }
         return;
     }
-    const double beta = first ? 0.0 : (rho_new / st.rho) * (st.alpha / st.omega);
-    const double omega = st.omega;
-    double red[1] = {0.0};
-    // eight lanes per mesh row
-    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-    const int node = gt >> 3, g = gt & 7;
-    const bool valid = node < c.n;
-    const int pi = valid ? padded_index(c, node) : 0;
-    const double w = ap_row8(c, node, pi, g, valid, c.r);
-    if (valid && g == 0) {
-        const double r = c.r[pi];
-        c.p[pi] = r + beta * (c.p[pi] - omega * c.v[pi]);
-        const double vn = w + beta * (c.v[pi] - omega * c.z[pi]);
-        c.w[pi] = w;
-        c.v[pi] = vn;
-        red[0] = c.rh[pi] * vn;
-    }
-    write_partials<1>(c, kSlotA, red, lds);
-    // the state is read by every block of this kernel: it is updated by the
-    // next kernel (B), never here
-    if (blockIdx.x == 0 && threadIdx.x == 0) c.state->rho_next = rho_new;
-}
-
-// B: alpha = rho / rh.v'; s = r - alpha v'; z' = A P v'; t = w - alpha z';
-//    partials t.s, t.t.
-__global__ void __launch_bounds__(kBlock) coarse_iter_b(CoarseDev c) {
-    __shared__ double lds[32];
-    KrylovState &st = *c.state;
-    if (st.done) return;
     const double rho = st.rho_next;
-    double as[1];
-    read_sums<1>(c, kSlotA, c.grid8, as, lds);
     const double alpha = rho / as[0];
-    double red[2] = {0.0, 0.0};
+    double red[4] = {0.0, 0.0, 0.0, 0.0};
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = gt >> 3, g = gt & 7;
     const bool valid = node < c.n;
@@ -249,44 +328,19 @@ __global__ void __launch_bounds__(kBlock) coarse_iter_b(CoarseDev c) {
     if (valid && g == 0) {
         const double sv = c.r[pi] - alpha * c.v[pi];
         const double tv = c.w[pi] - alpha * zn;
+        const double rh = c.rh[pi];
         c.s[pi] = sv;
         c.z[pi] = zn;
         c.t[pi] = tv;
         red[0] = tv * sv;
         red[1] = tv * tv;
+        red[2] = rh * sv;
+        red[3] = rh * tv;
     }
-    write_partials<2>(c, kSlotB, red, lds);
+    write_partials<4>(c, kSlotB, red, lds);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.rho = rho;
         st.alpha = alpha;
-    }
-}
-
-// C: omega = t.s / t.t; y += alpha p + omega s; r = s - omega t;
-//    partials rh.r, r.r for the next A.
-__global__ void __launch_bounds__(kBlock) coarse_iter_c(CoarseDev c) {
-    __shared__ double lds[32];
-    KrylovState &st = *c.state;
-    if (st.done) return;
-    double bs[2];
-    read_sums<2>(c, kSlotB, c.grid8, bs, lds);
-    const double omega = bs[1] > 0.0 ? bs[0] / bs[1] : 0.0;
-    const double alpha = st.alpha;
-    double red[2] = {0.0, 0.0};
-    const int node = blockIdx.x * blockDim.x + threadIdx.x;
-    if (node < c.n) {
-        const int pi = padded_index(c, node);
-        const double sv = c.s[pi];
-        c.y[pi] += alpha * c.p[pi] + omega * sv;
-        const double rn = sv - omega * c.t[pi];
-        c.r[pi] = rn;
-        red[0] = c.rh[pi] * rn;
-        red[1] = rn * rn;
-    }
-    write_partials<2>(c, kSlotC, red, lds);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st.omega = omega;
-        st.iters += 1;
     }
 }
 
@@ -377,13 +431,13 @@ hipError_t launch_coarse_rhs(const CoarseDev &c, const double *guess, hipStream_
 
 hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iterations, int max_iter, double tol,
                                hipStream_t s) {
-    for (int it = 0; it < iterations; ++it) {
-        hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, it == 0 ? 1 : 0, tol, max_iter);
-        hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid8), dim3(kBlock), 0, s, c);
-        hipLaunchKernelGGL(coarse_iter_c, dim3(c.grid), dim3(kBlock), 0, s, c);
+    for (int k = 0; k < iterations; ++k) {
+        hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, k);
+        hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid8), dim3(kBlock), 0, s, c, k, tol, max_iter);
     }
-    // closing convergence test after the last enqueued iteration
-    hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, iterations == 0 ? 1 : 0, tol, 0);
+    // closing pair: finishes the last enqueued iteration and tests it
+    hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, iterations);
+    hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid8), dim3(kBlock), 0, s, c, iterations, tol, 0);
     hipLaunchKernelGGL(coarse_finish, dim3(c.grid), dim3(kBlock), 0, s, c, guess);
     return hipGetLastError();
 }

@@ -124,7 +124,7 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
         L.P = take((size_t)L.n * kSpaiW * kSpaiW * 8);
         L.dkind = take((size_t)L.n * 4);
         L.vec = take(12 * align_up(L.vec_len * 8, kAlign));
-        L.partials = take((size_t)16 * coarse_grid8(L.n) * 8);
+        L.partials = take((size_t)4 * kPartialValues * coarse_grid8(L.n) * 8);
         L.barrier = take(sizeof(KrylovState));
     }
     L.total = off;

@@ -33,9 +33,14 @@ enum Counter { kCntInfeasible = 0, kCntNonfinite = 1, kCntSlots = 8 };
 
 // Scalars of the coarse BiCGSTAB shared between its kernels.
 struct KrylovState {
-    double rho, rho_next, alpha, omega, rnorm, bnorm;
-    int iters, done, converged, pad;
+    double rho, rho_next, alpha, rnorm, bnorm, bb;
+    // done is raised by the stop test (second kernel of an iteration) and
+    // read by the first; skip, brk and bb (= b.b) are written by the first
+    // and read by the second, so no kernel reads a field that its own
+    // blocks write
+    int iters, done, converged, brk, skip, pad1;
 };
+constexpr int kPartialValues = 8;    // reduction values per partials slot
 
 // Result block written by the coarse solver.
 struct KrylovResult {
@@ -153,7 +158,7 @@ struct CoarseDev {
     double *x1;              // padded new solution
     double *xprev;           // padded d(t_{n-1}) (first-pass guess 2 d(t_n) - d(t_{n-1}))
     double *r, *rh, *p, *v, *s, *t, *y, *w, *z;   // padded Krylov vectors
-    double *partials;        // [4 slots][4][pstride] reduction partials
+    double *partials;        // [4 slots][kPartialValues][pstride] reduction partials
     KrylovState *state;
     KrylovResult *result;
 };
@@ -161,7 +166,7 @@ struct CoarseDev {
 hipError_t launch_coarse_rhs(const CoarseDev &c, const double *guess, hipStream_t s);
 // x1 = 2 xn - xprev over the padded grid (the halo stays zero)
 hipError_t launch_coarse_extrapolate(const CoarseDev &c, hipStream_t s);
-// Enqueues `iterations` BiCGSTAB iterations (three kernels each; no-ops
+// Enqueues `iterations` BiCGSTAB iterations (two kernels each; no-ops
 // once converged or past max_iter), a closing convergence test and the
 // update x1 = guess + P y.
 hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iterations, int max_iter, double tol,
