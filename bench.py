@@ -51,9 +51,11 @@ ELEM = {"fp64": 8, "fp32": 4, "fp16s": 2}
 
 
 def kernel_name(elem_bytes, steps_per_launch):
+    """The dominant kernel: the whole-patch launch (tile part 0) of the
+    two-step sweep, or the single-step sweep."""
     t = {8: "double", 4: "float", 2: "_Float16"}[elem_bytes]
     if steps_per_launch == 2:
-        return f"lbm_sweep2_kernel<{t}, 64, 8>"
+        return f"lbm_sweep2_kernel<{t}, 64, 8, {512 if elem_bytes == 8 else 256}, 0>"
     return f"lbm_sweep_kernel<{t}, 1>"
 
 
@@ -70,18 +72,38 @@ def load_traffic(workload, precision, kernel):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(problem, precision, steps, warmup, steps_per_launch=2, timing=True):
+def tune_overlap(problem, precision, steps_per_launch=2):
+    """Overlap depth the library's own tuning picks for this workload, found
+    on a throwaway handle (its steps are not part of any measurement)."""
+    from paper_1601_02708_amd import hyb
+    g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
+    g.set_steps_per_launch(steps_per_launch)
+    g.set_overlap(hyb.HYB_OVERLAP_AUTO)
+    for _ in range(2 * max(problem.cfg.eta // 2, 1) + 1):
+        if g.stats()["overlap_depth"] >= 0:
+            break
+        g.step(problem.cfg.max_iter)
+    depth = g.stats()["overlap_depth"]
+    g.close()
+    return depth
+
+
+def run_gpu(problem, precision, steps, warmup, steps_per_launch=2, depth=None, timing_steps=10):
+    """W warmup and K timed coarse steps at the given overlap depth; then
+    timing_steps more at depth 0 with per-launch kernel timing (every sweep
+    launch whole and on the handle's stream), for the sweep kernel's
+    average launch duration."""
     import torch
     from paper_1601_02708_amd import hyb
     g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
     g.set_steps_per_launch(steps_per_launch)
+    if depth is None:
+        depth = tune_overlap(problem, precision, steps_per_launch)
+    g.set_overlap(depth)
     mi = problem.cfg.max_iter
     for _ in range(warmup):
         g.step(mi)
     stream = g.stream
-    torch.cuda.synchronize()
-    if timing:
-        g.kernel_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -93,9 +115,18 @@ def run_gpu(problem, precision, steps, warmup, steps_per_launch=2, timing=True):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
-    kms, launches = g.kernel_time() if timing else (0.0, 0)
     st = g.stats()
-    return g, wall, gpu_ms, kms, launches, st
+    kms, launches = 0.0, 0
+    if timing_steps > 0:
+        g.set_overlap(0)
+        g.kernel_timing(True)
+        for _ in range(timing_steps):
+            g.step(mi)
+        torch.cuda.synchronize()
+        kms, launches = g.kernel_time()
+        g.kernel_timing(False)
+        g.set_overlap(depth)
+    return g, wall, gpu_ms, kms, launches, st, depth
 
 
 def adjoint_rate(problem, precision, reps=3):
@@ -168,6 +199,11 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16s"])
     ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2],
                     help="fine steps per lattice-sweep launch (2: temporally blocked pairs)")
+    ap.add_argument("--overlap", type=int, default=-1,
+                    help="overlap depth of hyb_step (-1: the library's tuning, on a separate handle)")
+    ap.add_argument("--timing-steps", type=int, default=10,
+                    help="coarse steps at overlap depth 0 after the timed ones, for the sweep kernel's "
+                         "average launch duration (roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision runs")
@@ -192,7 +228,10 @@ def main():
     print(f"[bench] {cfg.name} {args.precision}: {args.warmup} warmup + {args.steps} timed coarse steps",
           file=sys.stderr, flush=True)
     spl = args.steps_per_launch
-    g, wall, gpu_ms, kms, launches, st = run_gpu(problem, args.precision, args.steps, args.warmup, spl)
+    depth = tune_overlap(problem, args.precision, spl) if args.overlap < 0 else args.overlap
+    print(f"[bench] overlap depth {depth}", file=sys.stderr, flush=True)
+    g, wall, gpu_ms, kms, launches, st, _ = run_gpu(problem, args.precision, args.steps, args.warmup, spl, depth,
+                                                    args.timing_steps)
     ms_step = gpu_ms / args.steps
     value = lups_step * args.steps / (gpu_ms / 1e3) / 1e6
     bbytes, nfl, nsol, per_fluid = sweep_bytes(problem, elem)
@@ -239,7 +278,10 @@ def main():
             "avg_launch_ms": round(avg_kernel_ms, 5),
             "launches_timed": launches,
         },
-        "sweep_time_frac": round(kms / gpu_ms, 4),
+        # sweep kernel time per coarse step (depth-0 timing steps) over the
+        # step time of the timed (overlapped) steps
+        "sweep_time_frac": round(kms / max(args.timing_steps, 1) / ms_step, 4),
+        "overlap_depth": depth,
         "wall_s": round(wall, 3),
         "krylov_iters_last": st["krylov_iters"],
         "infeasible_closures": st["infeasible"],
@@ -249,13 +291,14 @@ def main():
         conc = {args.precision: g.concentration()}
         for other in [p for p in ("fp64", "fp16s", "fp32") if p != args.precision]:
             print(f"[bench] comparison run {other}", file=sys.stderr, flush=True)
-            g2, _, gpu_ms2, kms2, launches2, _ = run_gpu(problem, other, args.steps, args.warmup, spl)
+            g2, _, gpu_ms2, kms2, launches2, _, d2 = run_gpu(problem, other, args.steps, args.warmup, spl, None,
+                                                             args.timing_steps)
             conc[other] = g2.concentration()
             e2 = ELEM[other]
             b2, _, _, _ = sweep_bytes(problem, e2)
             k2 = kms2 / max(launches2, 1)
             res[other] = {"value": round(lups_step * args.steps / (gpu_ms2 / 1e3) / 1e6, 1), "unit": "MLUPS",
-                          "ms_per_step": round(gpu_ms2 / args.steps, 4),
+                          "ms_per_step": round(gpu_ms2 / args.steps, 4), "overlap_depth": d2,
                           "sweep_kernel": kernel_name(e2, spl),
                           "sweep_achieved_gbs": round(b2 * steps_launch / (k2 / 1e3) / 1e9, 1),
                           "sweep_avg_launch_ms": round(k2, 5)}

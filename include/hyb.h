@@ -65,6 +65,7 @@ enum { HYB_FP64 = 0, HYB_FP32 = 1, HYB_FP16S = 2 };
 enum { HYB_F2C = 0, HYB_C2F = 1 };              /* hyb_interface_exchange direction */
 enum { HYB_FINE = 0, HYB_COARSE = 1 };          /* hyb_concentration field */
 enum { HYB_BC_DIRICHLET = 0, HYB_BC_NEUMANN = 1 };
+enum { HYB_OVERLAP_AUTO = -1 };                  /* hyb_set_overlap: tune the depth */
 
 typedef struct hyb_handle hyb_handle;
 
@@ -120,6 +121,8 @@ typedef struct {
     double krylov_relres;   /* ||b - A x|| / ||b|| of the last coarse solve */
     int64_t coarse_steps;   /* committed coarse steps */
     int64_t fine_steps;     /* fine steps run since creation (all Schwarz passes) */
+    int32_t overlap_depth;  /* overlap depth hyb_step uses (-1 while it is still being tuned) */
+    int32_t pad;
 } hyb_run_stats;
 
 /* Device memory the caller must provide for this problem. */
@@ -216,15 +219,22 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape);
 int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *lam_in, double *lam_out,
                     double *grad_a, double *grad_b, double *grad_k);
 
-/* Overlap in hyb_step (default on): with two-step launches, the interior
- * tiles of each Schwarz pass's first launch (those whose one-node ring
- * stays clear of the patch perimeter, so they read no interface value) run
+/* Overlap in hyb_step (default HYB_OVERLAP_AUTO): with two-step launches,
+ * the deep interior tiles of each Schwarz pass's first `depth` launches run
  * on a second stream owned by the handle while the pass's fine-to-coarse
  * transfer, coarse solve and coarse-to-fine transfer run on the caller's
- * stream; the remaining tiles follow on the caller's stream.  Results are
- * bit-identical to the serial order.  enable = 0 runs everything on the
- * caller's stream. */
-int hyb_set_overlap(hyb_handle *h, int enable);
+ * stream; the remaining tiles follow on the caller's stream.  Launch j
+ * (j = 0 .. depth-1, fine steps 2j+1 and 2j+2) splits at the rectangle of
+ * tiles whose one-node ring stays clear of the patch perimeter shrunk by j
+ * tiles on every side: such tiles read no interface value and, with their
+ * two-node halo, only the deep tiles of launch j-1.  Depth is capped at the
+ * pass's number of two-step launches (eta / 2).  Results are bit-identical
+ * to the serial order for every depth.  depth = 0 runs everything on the
+ * caller's stream.  HYB_OVERLAP_AUTO: the handle's next 2 D successful
+ * hyb_step calls (D = eta / 2) run at depths 1 .. D twice over, each timed
+ * on the caller's stream, and later calls use the fastest; hyb_stats reports
+ * the depth (-1 while tuning).  Other negative depths: HYB_EINVAL. */
+int hyb_set_overlap(hyb_handle *h, int depth);
 
 /* Fine steps per lattice-sweep launch (1 or 2; default 2).  With 2, while
  * every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine steps in

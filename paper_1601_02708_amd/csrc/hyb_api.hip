@@ -179,15 +179,24 @@ struct hyb_handle {
     double timed_ms = 0.0;
     long long timed_launches = 0;
 
-    // overlap of each Schwarz pass's first sweep launch (interior tiles) with
-    // the pass's coarse solve: a second stream of the handle's own
-    bool overlap = true;
+    // overlap of the deep interior tiles of each Schwarz pass's first
+    // `overlap` two-step launches with the pass's transfers and coarse solve:
+    // a second stream of the handle's own, one event per deep launch
+    int overlap = HYB_OVERLAP_AUTO;
     hipStream_t side = nullptr;
-    hipEvent_t ev_main = nullptr, ev_side = nullptr;
+    hipEvent_t ev_main = nullptr, ev_f2c = nullptr;
+    std::vector<hipEvent_t> ev_deep;
+    // depth tuning (HYB_OVERLAP_AUTO): step times per depth, best of two
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+    int tune_idx = 0, tuned_depth = -1;
+    std::vector<float> tune_ms;
 
     ~hyb_handle() {
         if (ev_main) (void)hipEventDestroy(ev_main);
-        if (ev_side) (void)hipEventDestroy(ev_side);
+        if (ev_f2c) (void)hipEventDestroy(ev_f2c);
+        if (ev_t0) (void)hipEventDestroy(ev_t0);
+        if (ev_t1) (void)hipEventDestroy(ev_t1);
+        for (hipEvent_t e : ev_deep) (void)hipEventDestroy(e);
         if (side) (void)hipStreamDestroy(side);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
@@ -308,7 +317,8 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     // or 4/5 of the CUs with a CU mask made the step 28% slower)
     if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_side, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&h->ev_f2c, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&h->ev_t0) != hipSuccess || hipEventCreate(&h->ev_t1) != hipSuccess)
         return bail(HYB_EHIP, "could not create the handle's side stream and events");
     h->lay = make_layout(mesh, lat, true);
     const Layout &L = h->lay;
@@ -540,10 +550,14 @@ bool use_two_step(const hyb_handle *h) {
 }
 
 // n_sub fine steps.  first_dst >= 0 (with restart): destination of the first
-// launch; split: that first launch is a two-step launch whose interior tiles
-// were already enqueued on the side stream (prelaunch_interior), so only its
-// boundary tiles are launched here, after the side stream's event.
-int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, bool split) {
+// launch; deep = K > 0: the first K launches are two-step launches whose
+// deep tiles (part 1 of depth j for launch j = 0..K-1) were already enqueued
+// on the side stream (prelaunch_deep), so only their other tiles (part 2 of
+// the same depth) are launched here: launch j after the side stream's event
+// for launch j-1 (its halo reaches into the deep tiles of launch j-1), and
+// the first launch after them (or, when there is none, the end of the
+// call) after the event for launch K-1.
+int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, int deep) {
     if (n_sub < 0) return h->fail(HYB_EINVAL, "n_sub must be >= 0");
     if (restart) {
         h->cur = h->frozen;
@@ -552,9 +566,9 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, bool spl
     if (h->jsub + n_sub > h->eta) return h->fail(HYB_EINVAL, "fine steps would pass the end of the coarse step");
     // kernel timing: when every perimeter slot is Dirichlet only sweep
     // kernels are launched, back to back, so one event pair brackets the
-    // batch (after a split first launch, which overlaps other work); the
-    // general path brackets each interior kernel alone (its perimeter kernel
-    // follows it)
+    // batch (after split launches, which overlap other work); the general
+    // path brackets each interior kernel alone (its perimeter kernel follows
+    // it)
     const bool timed = h->timing && h->N > 2 && n_sub > 0;
     const bool general = h->any_neumann;
     const bool fuse2 = use_two_step(h);
@@ -576,14 +590,19 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, bool spl
     };
     hipEvent_t g0 = nullptr, g1 = nullptr;
     size_t gslot = 0;
-    for (int s = 0; s < n_sub;) {
+    int launch = 0;
+    for (int s = 0; s < n_sub; ++launch) {
         const bool first = s == 0;
         const int dst = (first && first_dst >= 0) ? first_dst
                         : h->cur == h->frozen ? h->spare(-1) : h->spare(h->cur);
         LbmArgs a = h->lbm_args(h->cur, dst);
         a.lam = (double)(h->jsub + 1) / (double)h->eta;
         const int take = (fuse2 && n_sub - s >= 2) ? 2 : 1;
-        const bool split_now = first && split && take == 2;
+        const bool split_now = launch < deep;
+        if (split_now && take != 2) return h->fail(HYB_EINVAL, "internal: split launch is not a two-step launch");
+        // the side stream's deep tiles this launch depends on
+        if (deep > 0 && launch >= 1 && launch <= deep)
+            HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_deep[launch - 1], 0));
         if (timed && !general && !g0 && !split_now) {
             HIP_TRY(h, take_pair(&g0, &g1));
             gslot = h->ev_used - 1;
@@ -591,12 +610,7 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, bool spl
         }
         if (take == 2) {
             a.lam2 = (double)(h->jsub + 2) / (double)h->eta;
-            if (split_now) {
-                HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_side, 0));
-                HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream, 2));
-            } else {
-                HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream));
-            }
+            HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream, split_now ? 2 : 0, split_now ? launch : 0));
         } else {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timed && general) {
@@ -612,23 +626,51 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, bool spl
         s += take;
     }
     if (g1) HIP_TRY(h, hipEventRecord(g1, h->stream));
+    // when every launch was split, no later launch joined the side stream:
+    // join it here, so the pass ends with its last buffer complete
+    if (deep > 0 && launch <= deep) HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_deep[deep - 1], 0));
     return HYB_OK;
 }
 
-// Enqueue, on the side stream, the interior tiles of the first two-step
-// launch of a Schwarz pass (fine steps 1 and 2 from the frozen state into
-// buffer dst).  They read only the frozen state, the lattice fields and no
-// interface value, so they run while the pass's coarse solve is in flight;
-// everything enqueued on the caller's stream before this call completes
-// first.
-int prelaunch_interior(hyb_handle *h, int dst) {
-    HIP_TRY(h, hipEventRecord(h->ev_main, h->stream));
-    HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_main, 0));
-    LbmArgs a = h->lbm_args(h->frozen, dst);
-    a.lam = 1.0 / (double)h->eta;
-    a.lam2 = 2.0 / (double)h->eta;
-    HIP_TRY(h, launch_lbm_step2(a, h->prec, h->side, 1));
-    HIP_TRY(h, hipEventRecord(h->ev_side, h->side));
+// Enqueue, on the side stream, the deep tiles of the first `deep` two-step
+// launches of a Schwarz pass: launch j (fine steps 2j+1, 2j+2) covers the
+// interior rectangle of depth j, from the frozen state into dst for j = 0
+// and then alternating between dst and the other free buffer.  They read
+// only earlier deep tiles, the lattice fields and no interface value, so
+// they run while the pass's coarse solve is in flight.  Launch 0 follows
+// everything enqueued on the caller's stream before the call; the later
+// launches also follow the fine-to-coarse transfer, which the caller
+// enqueues between the two calls (the buffer it reads may be the one that
+// launch 1 writes).
+int prelaunch_deep(hyb_handle *h, int dst, int deep, bool after_f2c) {
+    auto args = [&](int j, int src_buf, int dst_buf) {
+        LbmArgs a = h->lbm_args(src_buf, dst_buf);
+        a.lam = (double)(2 * j + 1) / (double)h->eta;
+        a.lam2 = (double)(2 * j + 2) / (double)h->eta;
+        return a;
+    };
+    while ((int)h->ev_deep.size() < deep) {
+        hipEvent_t e;
+        HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->ev_deep.push_back(e);
+    }
+    if (!after_f2c) {
+        HIP_TRY(h, hipEventRecord(h->ev_main, h->stream));
+        HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_main, 0));
+        HIP_TRY(h, launch_lbm_step2(args(0, h->frozen, dst), h->prec, h->side, 1, 0));
+        HIP_TRY(h, hipEventRecord(h->ev_deep[0], h->side));
+        return HYB_OK;
+    }
+    if (deep < 2) return HYB_OK;
+    HIP_TRY(h, hipEventRecord(h->ev_f2c, h->stream));
+    HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_f2c, 0));
+    int src = dst;
+    for (int j = 1; j < deep; ++j) {
+        const int out = h->spare(src);
+        HIP_TRY(h, launch_lbm_step2(args(j, src, out), h->prec, h->side, 1, j));
+        HIP_TRY(h, hipEventRecord(h->ev_deep[j], h->side));
+        src = out;
+    }
     return HYB_OK;
 }
 
@@ -638,12 +680,16 @@ extern "C" {
 
 int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
     if (!h) return HYB_EINVAL;
-    return substeps_impl(h, n_sub, restart, -1, false);
+    return substeps_impl(h, n_sub, restart, -1, 0);
 }
 
-int hyb_set_overlap(hyb_handle *h, int enable) {
+int hyb_set_overlap(hyb_handle *h, int depth) {
     if (!h) return HYB_EINVAL;
-    h->overlap = enable != 0;
+    if (depth < HYB_OVERLAP_AUTO) return h->fail(HYB_EINVAL, "overlap depth must be >= 0 or HYB_OVERLAP_AUTO");
+    h->overlap = depth;
+    h->tune_idx = 0;
+    h->tuned_depth = -1;
+    h->tune_ms.clear();
     return HYB_OK;
 }
 
@@ -684,30 +730,49 @@ int hyb_step(hyb_handle *h, int max_schwarz) {
     if (!h) return HYB_EINVAL;
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "hyb_step needs a coarse mesh");
     if (max_schwarz < 1) return h->fail(HYB_EINVAL, "max_schwarz must be >= 1");
+    // overlap depth: fixed, tuned, or the next candidate while tuning (two
+    // rounds over depths 1 .. D, each step timed on the caller's stream)
+    const int dmax = use_two_step(h) ? h->eta / 2 : 0;
+    int depth = std::min(h->overlap, dmax);
+    const bool tuning = h->overlap == HYB_OVERLAP_AUTO && dmax > 1 && h->tuned_depth < 0;
+    if (h->overlap == HYB_OVERLAP_AUTO) depth = dmax <= 1 ? dmax : tuning ? 1 + h->tune_idx % dmax : h->tuned_depth;
+    if (tuning) HIP_TRY(h, hipEventRecord(h->ev_t0, h->stream));
     int rc = HYB_OK;
     for (int attempt = 0; attempt < 2; ++attempt) {
         h->cur = h->frozen;
         h->jsub = 0;
         h->solved_this_step = false;
-        const bool split = h->overlap && h->eta >= 2 && use_two_step(h);
+        const int deep = depth;
         for (int it = 0; it < max_schwarz; ++it) {
             // the pass's first launch writes a buffer that is neither the
             // frozen state nor the one the fine-to-coarse transfer reads
             int first_dst = -1;
-            if (split) {
+            if (deep > 0) {
                 first_dst = h->cur == h->frozen ? h->spare(-1) : h->spare(h->cur);
-                if ((rc = prelaunch_interior(h, first_dst)) != HYB_OK) return rc;
+                if ((rc = prelaunch_deep(h, first_dst, deep, false)) != HYB_OK) return rc;
             }
             if ((rc = hyb_interface_exchange(h, HYB_F2C)) != HYB_OK) return rc;
+            if (deep > 1 && (rc = prelaunch_deep(h, first_dst, deep, true)) != HYB_OK) return rc;
             if ((rc = hyb_coarse_step(h, 200)) != HYB_OK) return rc;
             if ((rc = hyb_interface_exchange(h, HYB_C2F)) != HYB_OK) return rc;
-            if ((rc = substeps_impl(h, h->eta, 1, first_dst, split)) != HYB_OK) return rc;
+            if ((rc = substeps_impl(h, h->eta, 1, first_dst, deep)) != HYB_OK) return rc;
         }
+        if (tuning) HIP_TRY(h, hipEventRecord(h->ev_t1, h->stream));
         rc = hyb_commit(h);
         // a coarse solve that ran out of its launch budget (not of max_iter)
         // is repeated once from the untouched committed state
         if (rc != HYB_ENOCONV || h->solve_budget >= h->solve_cap) break;
         h->last_krylov_iters = h->solve_cap;
+    }
+    if (tuning && rc == HYB_OK) {
+        // the commit synchronised the stream, so both events are complete;
+        // a repeated step is timed whole and counts like any other
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
+        if ((int)h->tune_ms.size() < dmax) h->tune_ms.assign(dmax, 1e30f);
+        h->tune_ms[depth - 1] = std::min(h->tune_ms[depth - 1], ms);
+        if (++h->tune_idx == 2 * dmax)
+            h->tuned_depth = 1 + (int)(std::min_element(h->tune_ms.begin(), h->tune_ms.end()) - h->tune_ms.begin());
     }
     return rc;
 }
@@ -818,6 +883,10 @@ int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
     out->krylov_relres = kr.relres;
     out->coarse_steps = h->coarse_steps;
     out->fine_steps = h->fine_steps;
+    const int dmax = use_two_step(h) ? h->eta / 2 : 0;
+    out->overlap_depth = h->overlap != HYB_OVERLAP_AUTO ? std::min(h->overlap, dmax)
+                         : dmax <= 1 ? dmax : h->tuned_depth;
+    out->pad = 0;
     return HYB_OK;
 }
 

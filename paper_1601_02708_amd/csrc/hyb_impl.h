@@ -120,10 +120,12 @@ hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, h
                            hipEvent_t sweep_begin = nullptr, hipEvent_t sweep_end = nullptr);
 // Two fine steps in one launch (Dirichlet closure on every perimeter slot):
 // a.src holds f*(j), a.dst receives f*(j+2); u^p at a.lam, then a.lam2.
-// part 0: every tile; part 1: the tiles whose one-node ring stays clear of
-// the patch perimeter (they read no interface value); part 2: the others.
-// Parts 1 and 2 together update every node exactly as part 0.
-hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part = 0);
+// part 0: every tile; part 1: the tiles of the interior rectangle of the
+// given depth (depth 0: the tiles whose one-node ring stays clear of the
+// patch perimeter, so they read no interface value; depth d: that rectangle
+// shrunk by d tiles on every side); part 2: the others.  Parts 1 and 2 of
+// one depth together update every node exactly as part 0.
+hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part = 0, int depth = 0);
 // Adjoint of one fine step (adjoint_kernels.hip), HYB_FP64 or HYB_FP32:
 // a.src = the step's source state f*(t) (read only with clamped closures),
 // snext = f*(t+1), lam = dJ/df*(t+1); nu is scratch; out = dJ/df*(t);

@@ -396,10 +396,14 @@ template <> struct Buf<_Float16> {
 };
 
 // Which tiles a two-step launch covers: all of the tiles_x x tiles_y grid
-// (part 0), the rectangle [ix0, ix1] x [iy0, iy1] of tiles whose ring stays
-// clear of the patch perimeter (part 1), or the other tiles (part 2).  A
-// part-1 launch reads no interface value, so it may run while the coarse
-// solve that produces them is still in flight.
+// (part 0), a rectangle [ix0, ix1] x [iy0, iy1] of tiles (part 1), or the
+// other tiles (part 2).  The rectangle of depth 0 holds the tiles whose ring
+// stays clear of the patch perimeter: a part-1 launch of it reads no
+// interface value, so it may run while the coarse solve that produces them
+// is still in flight.  The rectangle of depth d is that one shrunk by d tiles
+// on every side; its tiles read (with their two-node halo) only nodes that
+// the depth d-1 rectangle of the previous launch wrote, so the depth-d part 1
+// of launch d+1 of a pass may run ahead of the coarse solve as well.
 struct TileMap {
     int tiles_x, tiles_y;
     int part;
@@ -407,14 +411,17 @@ struct TileMap {
     int count;               // tiles in this part
 };
 
+// Tile of the t-th workgroup of a launch of part PART (a template argument,
+// so each part is its own kernel symbol and carries no runtime branch).
+template <int PART>
 __device__ __forceinline__ void tile_of(const TileMap &m, int t, int &tx, int &ty) {
-    if (m.part == 0) {
+    if constexpr (PART == 0) {
         tx = t % m.tiles_x;
         ty = t / m.tiles_x;
         return;
     }
     const int iw = m.ix1 - m.ix0 + 1;
-    if (m.part == 1) {
+    if constexpr (PART == 1) {
         tx = m.ix0 + t % iw;
         ty = m.iy0 + t / iw;
         return;
@@ -441,7 +448,7 @@ __device__ __forceinline__ void tile_of(const TileMap &m, int t, int &tx, int &t
     ty = m.iy1 + 1 + t / m.tiles_x;
 }
 
-template <typename S, int TW, int TH, int NT>
+template <typename S, int TW, int TH, int NT, int PART>
 __global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) {
     typedef typename Pop<S>::T T;
     constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
@@ -462,7 +469,7 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) 
     const BufRsrc vyr = buf_rsrc(a.vy, NP * 4u);
     const T omega = T(a.omega);
     int tx, ty;
-    tile_of(map, xcd_tile(blockIdx.x, map.count), tx, ty);
+    tile_of<PART>(map, xcd_tile(blockIdx.x, map.count), tx, ty);
     const int x0 = tx * TW;
     const int y0 = ty * TH;
 
@@ -716,39 +723,42 @@ template <typename S> struct Tile2 { static constexpr int TW = SWEEP2_TW32, TH =
 template <> struct Tile2<double> { static constexpr int TW = SWEEP2_TW64, TH = SWEEP2_TH64, NT = SWEEP2_NT64; };
 
 template <typename S>
-hipError_t step2_impl(const LbmArgs &a, int part, hipStream_t s) {
+hipError_t step2_impl(const LbmArgs &a, int part, int depth, hipStream_t s) {
     constexpr int TW = Tile2<S>::TW, TH = Tile2<S>::TH, NT = Tile2<S>::NT;
-    auto kernel = lbm_sweep2_kernel<S, TW, TH, NT>;
     TileMap m{};
     m.tiles_x = (a.N + TW - 1) / TW;
     m.tiles_y = (a.N + TH - 1) / TH;
     m.part = part;
-    // interior rectangle: tiles whose ring (x0 - 1 .. x0 + TW, y0 - 1 .. y0 + TH)
-    // lies within columns and rows 1 .. N-2
-    m.ix0 = 1;
-    m.iy0 = 1;
-    m.ix1 = (a.N - 2 - TW) / TW;
-    m.iy1 = (a.N - 2 - TH) / TH;
-    const bool has_interior = a.N - 2 - TW >= TW && a.N - 2 - TH >= TH && m.ix1 >= m.ix0 && m.iy1 >= m.iy0;
+    // depth-0 rectangle: tiles whose ring (x0 - 1 .. x0 + TW, y0 - 1 .. y0 + TH)
+    // lies within columns and rows 1 .. N-2 (all full tiles); depth d shrinks
+    // it by d tiles on every side
+    const bool fits = a.N - 2 - TW >= TW && a.N - 2 - TH >= TH;
+    m.ix0 = 1 + depth;
+    m.iy0 = 1 + depth;
+    m.ix1 = (a.N - 2 - TW) / TW - depth;
+    m.iy1 = (a.N - 2 - TH) / TH - depth;
+    const bool has_rect = fits && m.ix1 >= m.ix0 && m.iy1 >= m.iy0;
     const int all = m.tiles_x * m.tiles_y;
-    const int inner = has_interior ? (m.ix1 - m.ix0 + 1) * (m.iy1 - m.iy0 + 1) : 0;
-    if (part != 0 && !has_interior) {
-        // no interior rectangle: part 1 is empty, part 2 is everything
+    const int inner = has_rect ? (m.ix1 - m.ix0 + 1) * (m.iy1 - m.iy0 + 1) : 0;
+    if (part != 0 && !has_rect) {
+        // empty rectangle: part 1 is empty, part 2 is everything
         if (part == 1) return hipSuccess;
         m.part = 0;
     }
     m.count = m.part == 0 ? all : m.part == 1 ? inner : all - inner;
     if (m.count == 0) return hipSuccess;
-    hipLaunchKernelGGL(kernel, dim3(m.count), dim3(NT), 0, s, a, m);
+    if (m.part == 0) hipLaunchKernelGGL((lbm_sweep2_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
+    else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep2_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
+    else hipLaunchKernelGGL((lbm_sweep2_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part) {
-    if (prec == HYB_FP64) return step2_impl<double>(a, part, s);
-    if (prec == HYB_FP32) return step2_impl<float>(a, part, s);
-    return step2_impl<_Float16>(a, part, s);
+hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part, int depth) {
+    if (prec == HYB_FP64) return step2_impl<double>(a, part, depth, s);
+    if (prec == HYB_FP32) return step2_impl<float>(a, part, depth, s);
+    return step2_impl<_Float16>(a, part, depth, s);
 }
 
 hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, hipStream_t s,

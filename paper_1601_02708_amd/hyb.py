@@ -21,6 +21,7 @@ PRECISIONS = {"fp64": HYB_FP64, "fp32": HYB_FP32, "fp16s": HYB_FP16S}
 HYB_F2C, HYB_C2F = 0, 1
 HYB_FINE, HYB_COARSE = 0, 1
 HYB_BC_DIRICHLET, HYB_BC_NEUMANN = 0, 1
+HYB_OVERLAP_AUTO = -1
 
 _P = ctypes.c_void_p
 _i = ctypes.c_int
@@ -48,7 +49,7 @@ class HybReaction(ctypes.Structure):
 class HybRunStats(ctypes.Structure):
     _fields_ = [("infeasible", ctypes.c_int64), ("nonfinite", ctypes.c_int64), ("krylov_iters", ctypes.c_int32),
                 ("krylov_converged", ctypes.c_int32), ("krylov_relres", _d), ("coarse_steps", ctypes.c_int64),
-                ("fine_steps", ctypes.c_int64)]
+                ("fine_steps", ctypes.c_int64), ("overlap_depth", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 # exported symbol -> (restype, argtypes); mirrors include/hyb.h
@@ -260,8 +261,11 @@ class Hybrid:
                                                   lam_out.data_ptr(), grad_a.data_ptr(), grad_b.data_ptr(),
                                                   None if grad_k is None else grad_k.data_ptr()))
 
-    def set_overlap(self, enable):
-        return self._check(load().hyb_set_overlap(self.h, int(enable)))
+    def set_overlap(self, depth):
+        """Deep interior tiles of the first `depth` two-step launches of each
+        Schwarz pass overlap the pass's coarse work (0: serial order;
+        HYB_OVERLAP_AUTO: the next steps tune the depth)."""
+        return self._check(load().hyb_set_overlap(self.h, int(depth)))
 
     def set_steps_per_launch(self, steps):
         return self._check(load().hyb_set_steps_per_launch(self.h, int(steps)))

@@ -164,26 +164,65 @@ def test_two_step_sweep(orc, precision, N, clamp, k_field, eta):
     assert d <= (1e-14 if precision == "fp64" else 1e-6), d
 
 
-@pytest.mark.parametrize("name,over,precision,steps", [("small", {}, "fp64", 6),
-                                                      ("pore2048", {"N": 257, "M": 32}, "fp32", 4),
-                                                      ("pore2048", {"N": 131, "M": 16, "eta": 5}, "fp64", 3)])
-def test_overlapped_step_is_bit_identical(name, over, precision, steps):
-    """hyb_step with the interior tiles of each pass's first launch on the
+@pytest.mark.parametrize("name,over,precision,steps,depths",
+                         [("small", {}, "fp64", 6, (1, 2)),
+                          ("pore2048", {"N": 257, "M": 32}, "fp32", 4, (1, 2, 5)),
+                          ("pore2048", {"N": 131, "M": 16, "eta": 5}, "fp64", 3, (1, 2, 3)),
+                          ("pore2048", {"N": 600, "M": 32}, "fp32", 3, (1, 2, 3, 4, 5, 8)),
+                          ("pore2048", {"N": 600, "M": 32, "eta": 7}, "fp64", 2, (2, 3, 4)),
+                          ("pore4096", {"N": 1536}, "fp32", 3, (1, 2, 3))])
+def test_overlapped_step_is_bit_identical(name, over, precision, steps, depths):
+    """hyb_step with the deep tiles of each pass's first launches on the
     handle's side stream (overlapping the coarse solve) equals the serial
-    order bit for bit; odd eta mixes two-step and single-step launches."""
+    order bit for bit, for every overlap depth (depths past eta / 2 are
+    capped; 600^2 keeps the depth-3 rectangle non-empty, 257^2 empties it at
+    depth 1); odd eta mixes two-step and single-step launches; with eta = 4
+    and depth 2 every launch of a pass is split, so the pass must end by
+    joining the side stream (large deep launches make a missing join show)."""
     hyb = _gpu()
     p = problem(name, **over)
     out = []
-    for ov in (1, 0):
+    for ov in (0,) + tuple(depths):
         g = hyb.Hybrid.from_problem(p, precision=precision)
         g.set_overlap(ov)
         for _ in range(steps):
             g.step(p.cfg.max_iter)
         out.append((g.get_populations(), g.concentration(hyb.HYB_COARSE), g.stats()["infeasible"]))
         g.close()
-    assert np.array_equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
-    assert out[0][2] == out[1][2]
+    for d, o in zip(depths, out[1:]):
+        assert np.array_equal(o[0], out[0][0]), d
+        assert np.array_equal(o[1], out[0][1]), d
+        assert o[2] == out[0][2], d
+
+
+def test_overlap_rejects_negative_depth():
+    hyb = _gpu()
+    N = 8
+    z = np.zeros((N, N))
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.1, eta=2)
+    g.set_overlap(hyb.HYB_OVERLAP_AUTO)
+    with pytest.raises(hyb.HybError):
+        g.set_overlap(-2)
+
+
+def test_overlap_auto_tunes_then_keeps_a_depth():
+    """HYB_OVERLAP_AUTO (the default): the first 2 D steps (D = eta / 2) try
+    depths 1 .. D twice, then one depth in 1 .. D stays; the states equal
+    the serial order's bit for bit throughout."""
+    hyb = _gpu()
+    p = problem("pore2048", N=600, M=32)
+    D = p.cfg.eta // 2
+    ref = hyb.Hybrid.from_problem(p, precision="fp32")
+    ref.set_overlap(0)
+    g = hyb.Hybrid.from_problem(p, precision="fp32")
+    assert g.stats()["overlap_depth"] == -1
+    for k in range(2 * D + 2):
+        ref.step(p.cfg.max_iter)
+        g.step(p.cfg.max_iter)
+        d = g.stats()["overlap_depth"]
+        assert (d == -1) if k < 2 * D - 1 else (1 <= d <= D), (k, d)
+    assert np.array_equal(g.get_populations(), ref.get_populations())
+    assert ref.stats()["overlap_depth"] == 0
 
 
 def test_steps_per_launch_rejects_other_values():
