@@ -79,7 +79,7 @@ def tune_overlap(problem, precision, steps_per_launch=2):
     g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
     g.set_steps_per_launch(steps_per_launch)
     g.set_overlap(hyb.HYB_OVERLAP_AUTO)
-    for _ in range(2 * max(problem.cfg.eta // 2, 1) + 1):
+    for _ in range(2 + 3 * (problem.cfg.eta // 2 + 1)):
         if g.stats()["overlap_depth"] >= 0:
             break
         g.step(problem.cfg.max_iter)

@@ -230,10 +230,11 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
  * two-node halo, only the deep tiles of launch j-1.  Depth is capped at the
  * pass's number of two-step launches (eta / 2).  Results are bit-identical
  * to the serial order for every depth.  depth = 0 runs everything on the
- * caller's stream.  HYB_OVERLAP_AUTO: the handle's next 2 D successful
- * hyb_step calls (D = eta / 2) run at depths 1 .. D twice over, each timed
- * on the caller's stream, and later calls use the fastest; hyb_stats reports
- * the depth (-1 while tuning).  Other negative depths: HYB_EINVAL. */
+ * caller's stream.  HYB_OVERLAP_AUTO: of the handle's next 1 + 3 (D + 1)
+ * successful hyb_step calls (D = eta / 2), the first runs serially and the
+ * others at depths 0 .. D three times over, each timed on the caller's
+ * stream; later calls use the depth with the fastest step; hyb_stats
+ * reports the depth (-1 while tuning).  Other negative depths: HYB_EINVAL. */
 int hyb_set_overlap(hyb_handle *h, int depth);
 
 /* Fine steps per lattice-sweep launch (1 or 2; default 2).  With 2, while

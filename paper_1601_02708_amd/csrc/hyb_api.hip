@@ -730,12 +730,15 @@ int hyb_step(hyb_handle *h, int max_schwarz) {
     if (!h) return HYB_EINVAL;
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "hyb_step needs a coarse mesh");
     if (max_schwarz < 1) return h->fail(HYB_EINVAL, "max_schwarz must be >= 1");
-    // overlap depth: fixed, tuned, or the next candidate while tuning (two
-    // rounds over depths 1 .. D, each step timed on the caller's stream)
+    // overlap depth: fixed, tuned, or the next candidate while tuning (one
+    // untimed step, then three rounds over depths 0 .. D, each step timed on
+    // the caller's stream; the fastest of each depth's three counts)
     const int dmax = use_two_step(h) ? h->eta / 2 : 0;
+    const int ncand = dmax + 1;
     int depth = std::min(h->overlap, dmax);
-    const bool tuning = h->overlap == HYB_OVERLAP_AUTO && dmax > 1 && h->tuned_depth < 0;
-    if (h->overlap == HYB_OVERLAP_AUTO) depth = dmax <= 1 ? dmax : tuning ? 1 + h->tune_idx % dmax : h->tuned_depth;
+    const bool tuning = h->overlap == HYB_OVERLAP_AUTO && dmax > 0 && h->tuned_depth < 0;
+    if (h->overlap == HYB_OVERLAP_AUTO)
+        depth = dmax == 0 ? 0 : !tuning ? h->tuned_depth : h->tune_idx == 0 ? 0 : (h->tune_idx - 1) % ncand;
     if (tuning) HIP_TRY(h, hipEventRecord(h->ev_t0, h->stream));
     int rc = HYB_OK;
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -769,10 +772,10 @@ int hyb_step(hyb_handle *h, int max_schwarz) {
         // a repeated step is timed whole and counts like any other
         float ms = 0.f;
         HIP_TRY(h, hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
-        if ((int)h->tune_ms.size() < dmax) h->tune_ms.assign(dmax, 1e30f);
-        h->tune_ms[depth - 1] = std::min(h->tune_ms[depth - 1], ms);
-        if (++h->tune_idx == 2 * dmax)
-            h->tuned_depth = 1 + (int)(std::min_element(h->tune_ms.begin(), h->tune_ms.end()) - h->tune_ms.begin());
+        if ((int)h->tune_ms.size() != ncand) h->tune_ms.assign(ncand, 1e30f);
+        if (h->tune_idx > 0) h->tune_ms[depth] = std::min(h->tune_ms[depth], ms);
+        if (++h->tune_idx == 1 + 3 * ncand)
+            h->tuned_depth = (int)(std::min_element(h->tune_ms.begin(), h->tune_ms.end()) - h->tune_ms.begin());
     }
     return rc;
 }
@@ -885,7 +888,7 @@ int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
     out->fine_steps = h->fine_steps;
     const int dmax = use_two_step(h) ? h->eta / 2 : 0;
     out->overlap_depth = h->overlap != HYB_OVERLAP_AUTO ? std::min(h->overlap, dmax)
-                         : dmax <= 1 ? dmax : h->tuned_depth;
+                         : dmax == 0 ? 0 : h->tuned_depth;
     out->pad = 0;
     return HYB_OK;
 }

@@ -206,21 +206,22 @@ def test_overlap_rejects_negative_depth():
 
 
 def test_overlap_auto_tunes_then_keeps_a_depth():
-    """HYB_OVERLAP_AUTO (the default): the first 2 D steps (D = eta / 2) try
-    depths 1 .. D twice, then one depth in 1 .. D stays; the states equal
-    the serial order's bit for bit throughout."""
+    """HYB_OVERLAP_AUTO (the default): one serial step, then three rounds
+    over depths 0 .. D (D = eta / 2), then one depth in 0 .. D stays; the
+    states equal the serial order's bit for bit throughout."""
     hyb = _gpu()
     p = problem("pore2048", N=600, M=32)
     D = p.cfg.eta // 2
+    n_tune = 1 + 3 * (D + 1)
     ref = hyb.Hybrid.from_problem(p, precision="fp32")
     ref.set_overlap(0)
     g = hyb.Hybrid.from_problem(p, precision="fp32")
     assert g.stats()["overlap_depth"] == -1
-    for k in range(2 * D + 2):
+    for k in range(n_tune + 2):
         ref.step(p.cfg.max_iter)
         g.step(p.cfg.max_iter)
         d = g.stats()["overlap_depth"]
-        assert (d == -1) if k < 2 * D - 1 else (1 <= d <= D), (k, d)
+        assert (d == -1) if k < n_tune - 1 else (0 <= d <= D), (k, d)
     assert np.array_equal(g.get_populations(), ref.get_populations())
     assert ref.stats()["overlap_depth"] == 0
 
