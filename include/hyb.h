@@ -219,6 +219,37 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape);
 int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *lam_in, double *lam_out,
                     double *grad_a, double *grad_b, double *grad_k);
 
+/* ---- differentiation form of one whole coarse step (Algorithm 1) -------
+ *
+ * One coarse step with a fixed number of Schwarz passes maps the committed
+ * state (f*(t_n), d^n) to (f*(t_{n+1}), d^{n+1}) through the fine steps
+ * above, the coarse-to-fine interpolation (Sec. 6.2 item i), the
+ * trapezoidal coarse step with strong Dirichlet rows (eq. FEM_discrete) and
+ * the fine-to-coarse transfer (Sec. 6.2 item ii); with the closure applied
+ * as printed the map is affine, and its adjoint runs the passes backwards
+ * through the transposes of those pieces (the coarse solve transposed as
+ * (A P)^T mu = P^T lam by the same BiCGSTAB kernels, FP64).
+ * Same storage and boundary restrictions as the fine-step adjoint; a coarse
+ * mesh is required.
+ *
+ * hyb_step_adjoint_query: device bytes of the tape for `passes` >= 1.
+ * hyb_step_record: hyb_step(h, passes) run with single-step launches,
+ *   recording the fine states, interface arrays and the state the transfers
+ *   read in the caller's device tape (256-byte aligned); commits the step
+ *   as hyb_step does (same errors; nothing is recorded on an error).
+ * hyb_step_adjoint: for the last record (tape pointer of that call; the
+ *   handle may have committed that step since, but no later one):
+ *   lam_f = dJ/df*(t_{n+1}) (device FP64 [9][N][N], index (q*N + j)*N + i),
+ *   lam_d = dJ/dd^{n+1} (device FP64 [(M+1)^2], mesh node l*(M+1) + k, or
+ *   NULL for zero); writes lam_f_out = dJ/df*(t_n) (may alias lam_f) and
+ *   lam_d_out = dJ/dd^n; grad_k (device FP64 [N*N] or NULL) += dJ/dk of the
+ *   fine per-node reaction rate.  Synchronises; HYB_ENOCONV if a transposed
+ *   coarse solve does not reach 1e-14 relative residual. */
+int hyb_step_adjoint_query(const hyb_handle *h, int passes, size_t *tape_bytes);
+int hyb_step_record(hyb_handle *h, int passes, void *tape);
+int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_d, double *lam_f_out,
+                     double *lam_d_out, double *grad_k);
+
 /* Overlap in hyb_step (default HYB_OVERLAP_AUTO): with two-step launches,
  * the deep interior tiles of each Schwarz pass's first `depth` launches run
  * on a second stream owned by the handle while the pass's fine-to-coarse

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["lbm_kernels.hip", "adjoint_kernels.hip", "coarse_kernels.hip", "coarse_setup.hip", "hyb_api.hip"]
+SOURCES = ["lbm_kernels.hip", "adjoint_kernels.hip", "coarse_kernels.hip", "coarse_adjoint.hip", "coarse_setup.hip",
+           "hyb_api.hip"]
 LIB = os.path.join(HERE, "libhyb.so")
 ARCH = "gfx950"
 

@@ -154,14 +154,18 @@ __global__ void __launch_bounds__(256) adj_pack_kernel(LbmArgs a, const double *
 
 template <typename T>
 __global__ void __launch_bounds__(256) adj_unpack_kernel(LbmArgs a, const T *__restrict__ pitched, double *__restrict__ dense,
-                                                        int row_blocks) {
+                                                        int row_blocks, int accumulate) {
     const int N = a.N, P = a.pitch;
     const int plane = static_cast<int>(a.plane);
     const int j = blockIdx.x / row_blocks;
     const int i = (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
     if (i >= N) return;
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dense[((size_t)q * N + j) * N + i] = double(pitched[q * plane + j * P + i]);
+    for (int q = 0; q < kQ; ++q) {
+        const size_t d = ((size_t)q * N + j) * N + i;
+        const double v = double(pitched[q * plane + j * P + i]);
+        dense[d] = accumulate ? dense[d] + v : v;
+    }
 }
 
 template <typename T>
@@ -185,7 +189,7 @@ hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, co
 }
 
 hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,
-                               hipStream_t s) {
+                               hipStream_t s, bool accumulate) {
     const int rb = (a.N + 255) / 256;
     const dim3 grid(a.N * rb), block(256);
     if (to_pitched) {
@@ -196,10 +200,10 @@ hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, 
     } else {
         if (prec == HYB_FP64)
             hipLaunchKernelGGL(adj_unpack_kernel<double>, grid, block, 0, s, a, static_cast<const double *>(pitched),
-                               const_cast<double *>(dense), rb);
+                               const_cast<double *>(dense), rb, accumulate ? 1 : 0);
         else
             hipLaunchKernelGGL(adj_unpack_kernel<float>, grid, block, 0, s, a, static_cast<const float *>(pitched),
-                               const_cast<double *>(dense), rb);
+                               const_cast<double *>(dense), rb, accumulate ? 1 : 0);
     }
     return hipGetLastError();
 }

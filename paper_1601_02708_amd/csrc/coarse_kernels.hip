@@ -206,6 +206,37 @@ __global__ void __launch_bounds__(kBlock) coarse_rhs_kernel(CoarseDev c, const d
     }
 }
 
+// r0 = rhs (a given padded vector, first guess 0): the rhs kernel of a
+// solve of (c.AP) y = rhs, with the same partials and state as
+// coarse_rhs_kernel.
+__global__ void __launch_bounds__(kBlock) coarse_rhs_given_kernel(CoarseDev c, const double *__restrict__ rhs) {
+    __shared__ double lds[32];
+    double red[3] = {0.0, 0.0, 0.0};
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node < c.n) {
+        const int pidx = padded_index(c, node);
+        const double r0 = rhs[pidx];
+        c.r[pidx] = r0;
+        c.p[pidx] = 0.0;
+        c.v[pidx] = 0.0;
+        c.z[pidx] = 0.0;
+        c.y[pidx] = 0.0;
+        red[0] = r0 * r0;
+        red[1] = r0 * r0;
+        red[2] = shadow_hash(node) * r0;
+    }
+    write_partials<3>(c, kSlotRhs, red, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        KrylovState &st = *c.state;
+        st.rho = 1.0;
+        st.alpha = 1.0;
+        st.iters = 0;
+        st.done = 0;
+        st.brk = 0;
+        st.skip = 0;
+    }
+}
+
 // Right-preconditioned BiCGSTAB on (A P) y = r0, x = x0 + P y, two kernels
 // per iteration; every cross-block dependency is a kernel boundary (the
 // device-scope cache maintenance happens once per launch instead of once per
@@ -360,6 +391,22 @@ __global__ void __launch_bounds__(kBlock) coarse_finish(CoarseDev c, const doubl
     }
 }
 
+// out = y (the solution of a solve from y = 0 without a right
+// preconditioner); records iterations, convergence and ||r|| / ||b||.
+__global__ void __launch_bounds__(kBlock) coarse_take_kernel(CoarseDev c, double *__restrict__ out) {
+    const KrylovState &st = *c.state;
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node < c.n) {
+        const int pi = padded_index(c, node);
+        out[pi] = c.y[pi];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c.result->iters = st.iters;
+        c.result->converged = st.converged;
+        c.result->relres = st.bnorm > 0.0 ? st.rnorm / st.bnorm : st.rnorm;
+    }
+}
+
 // First guess of a coarse step's first solve: the linear extrapolation
 // 2 d(t_n) - d(t_{n-1}) in time, written to x1.
 __global__ void coarse_extrapolate_kernel(CoarseDev c, int len) {
@@ -439,6 +486,19 @@ hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iter
     hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, iterations);
     hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid8), dim3(kBlock), 0, s, c, iterations, tol, 0);
     hipLaunchKernelGGL(coarse_finish, dim3(c.grid), dim3(kBlock), 0, s, c, guess);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve_given(const CoarseDev &c, const double *rhs, double *out, int iterations, int max_iter,
+                                     double tol, hipStream_t s) {
+    hipLaunchKernelGGL(coarse_rhs_given_kernel, dim3(c.grid), dim3(kBlock), 0, s, c, rhs);
+    for (int k = 0; k < iterations; ++k) {
+        hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, k);
+        hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid8), dim3(kBlock), 0, s, c, k, tol, max_iter);
+    }
+    hipLaunchKernelGGL(coarse_iter_a, dim3(c.grid8), dim3(kBlock), 0, s, c, iterations);
+    hipLaunchKernelGGL(coarse_iter_b, dim3(c.grid8), dim3(kBlock), 0, s, c, iterations, tol, 0);
+    hipLaunchKernelGGL(coarse_take_kernel, dim3(c.grid), dim3(kBlock), 0, s, c, out);
     return hipGetLastError();
 }
 

@@ -15,6 +15,9 @@
 #include <cmath>
 #include <cstring>
 
+#include <array>
+#include <algorithm>
+
 #include "hyb_impl.h"
 
 namespace hyb {
@@ -237,6 +240,22 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
         if (!std::isfinite(x)) return "coarse operator has non-finite entries";
     for (double x : P.c)
         if (!std::isfinite(x)) return "coarse preconditioner has non-finite entries";
+    // transposes for the reverse mode: entry (id, offset o) of S^T is entry
+    // (id + o, -o) of S (zero when id + o leaves the mesh)
+    auto transpose = [&](const Stencil &S) {
+        Stencil T(M, S.W);
+        for (int l = 0; l < m1; ++l)
+            for (int kk = 0; kk < m1; ++kk)
+                for (int dl = -S.R; dl <= S.R; ++dl)
+                    for (int dk = -S.R; dk <= S.R; ++dk) {
+                        const int nk = kk + dk, nl = l + dl;
+                        if (nk < 0 || nk > M || nl < 0 || nl > M) continue;
+                        T.at(l * m1 + kk, dk, dl) = S.get(nl * m1 + nk, -dk, -dl);
+                    }
+        return T;
+    };
+    out.APT = transpose(AP).c;
+    out.PT = transpose(P).c;
     out.A9 = std::move(A.c);
     out.B9 = std::move(B.c);
     out.P = std::move(P.c);
@@ -261,6 +280,22 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
         for (int c = 0; c < 4; ++c) {
             out.c2f_idx[4 * p + c] = cidx[c];
             out.c2f_w[4 * p + c] = cw[c];
+        }
+    }
+
+    // coarse -> fine transposed: per mesh node, the slots that read it
+    {
+        out.c2fT_ptr.assign(n + 1, 0);
+        auto node_of = [&](int pidx) { return (pidx / S - kCoarseHalo) * m1 + (pidx % S - kCoarseHalo); };
+        for (int e = 0; e < 4 * nslots; ++e) out.c2fT_ptr[node_of(out.c2f_idx[e]) + 1] += 1;
+        for (int id = 0; id < n; ++id) out.c2fT_ptr[id + 1] += out.c2fT_ptr[id];
+        out.c2fT_slot.assign((size_t)4 * nslots, 0);
+        out.c2fT_w.assign((size_t)4 * nslots, 0.0);
+        std::vector<int> fill(out.c2fT_ptr.begin(), out.c2fT_ptr.end() - 1);
+        for (int e = 0; e < 4 * nslots; ++e) {
+            const int at = fill[node_of(out.c2f_idx[e])]++;
+            out.c2fT_slot[at] = e / 4;
+            out.c2fT_w[at] = out.c2f_w[e];
         }
     }
 
@@ -312,6 +347,32 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
             out.fc_idx[4 * c + m] = out.fc_idx[4 * c];
             out.fc_w[4 * c + m] = 0.0;
         }
+    }
+
+    // fine -> coarse transposed: per lattice node read with a nonzero
+    // weight, the Gamma_{f->c} indices and weights (node, then index order)
+    {
+        std::vector<std::array<double, 3>> e;      // (pitched node, c, w)
+        for (int c = 0; c < nfc; ++c)
+            for (int m = 0; m < 4; ++m)
+                if (out.fc_w[4 * c + m] != 0.0) e.push_back({(double)out.fc_idx[4 * c + m], (double)c, out.fc_w[4 * c + m]});
+        std::sort(e.begin(), e.end(), [](const std::array<double, 3> &a, const std::array<double, 3> &b) {
+            return a[0] != b[0] ? a[0] < b[0] : a[1] < b[1];
+        });
+        out.f2cT_node.clear();
+        out.f2cT_ptr.assign(1, 0);
+        out.f2cT_c.clear();
+        out.f2cT_w.clear();
+        for (size_t t = 0; t < e.size(); ++t) {
+            if (t == 0 || e[t][0] != e[t - 1][0]) {
+                if (t) out.f2cT_ptr.push_back((int)t);
+                out.f2cT_node.push_back((int)e[t][0]);
+            }
+            out.f2cT_c.push_back((int)e[t][1]);
+            out.f2cT_w.push_back(e[t][2]);
+        }
+        out.f2cT_ptr.push_back((int)e.size());
+        if (e.empty()) out.f2cT_ptr.assign(1, 0);
     }
     return std::string();
 }

@@ -79,6 +79,8 @@ struct Layout {
     size_t mask = 0, vx = 0, vy = 0, kfield = 0, bc_kind = 0, bc_a = 0, bc_b = 0, c2f_idx = 0, c2f_w = 0;
     size_t fc_idx = 0, fc_w = 0, ufc = 0, A9 = 0, B9 = 0, AP = 0, P = 0, dkind = 0, vec = 0, partials = 0;
     size_t counters = 0, barrier = 0, kres = 0, total = 0;
+    size_t APT = 0, PT = 0, c2fT_ptr = 0, c2fT_slot = 0, c2fT_w = 0, f2cT_node = 0, f2cT_ptr = 0, f2cT_c = 0;
+    size_t f2cT_w = 0, fc_row = 0;
     int n = 0, S = 0, grid = 0;
     size_t vec_len = 0;
 };
@@ -126,6 +128,18 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
         L.vec = take(12 * align_up(L.vec_len * 8, kAlign));
         L.partials = take((size_t)4 * kPartialValues * coarse_grid8(L.n) * 8);
         L.barrier = take(sizeof(KrylovState));
+        // reverse mode: transposed stencils and transfer lists (at most 4
+        // lattice nodes per Gamma_{f->c} node, at most n such nodes)
+        L.APT = take((size_t)L.n * kApW * kApW * 8);
+        L.PT = take((size_t)L.n * kSpaiW * kSpaiW * 8);
+        L.c2fT_ptr = take(((size_t)L.n + 1) * 4);
+        L.c2fT_slot = take(nslots * 4 * 4);
+        L.c2fT_w = take(nslots * 4 * 8);
+        L.f2cT_node = take((size_t)L.n * 4 * 4);
+        L.f2cT_ptr = take(((size_t)L.n * 4 + 1) * 4);
+        L.f2cT_c = take((size_t)L.n * 4 * 4);
+        L.f2cT_w = take((size_t)L.n * 4 * 8);
+        L.fc_row = take((size_t)L.n * 4);
     }
     L.total = off;
     return L;
@@ -161,6 +175,14 @@ struct hyb_handle {
     int *c2f_idx = nullptr, *fc_idx = nullptr;
     double *c2f_w = nullptr, *fc_w = nullptr, *ufc = nullptr;
     int nfc = 0;
+    // reverse mode of the coarse half (hyb_step_record / hyb_step_adjoint)
+    const double *apt = nullptr, *pt = nullptr;
+    int *c2fT_ptr = nullptr, *c2fT_slot = nullptr, *f2cT_node = nullptr, *f2cT_ptr = nullptr, *f2cT_c = nullptr;
+    int *fc_row = nullptr;
+    double *c2fT_w = nullptr, *f2cT_w = nullptr;
+    int f2cT_n = 0;
+    const void *rec_step_tape = nullptr;    // last hyb_step_record
+    int rec_step_passes = 0;
     CoarseDev cd{};
     unsigned long long *counters = nullptr;
     KrylovResult *kres = nullptr;
@@ -474,6 +496,31 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         CREATE_TRY(up((void *)c.AP, ch.AP.data(), ch.AP.size() * 8));
         CREATE_TRY(up((void *)c.P, Pt.data(), Pt.size() * 8));
         CREATE_TRY(up((void *)c.dkind, ch.dkind.data(), ch.dkind.size() * 4));
+        const std::vector<double> PTt = offset_major(ch.PT, L.n, kSpaiW * kSpaiW);
+        h->apt = reinterpret_cast<const double *>(h->ws + L.APT);
+        h->pt = reinterpret_cast<const double *>(h->ws + L.PT);
+        h->c2fT_ptr = reinterpret_cast<int *>(h->ws + L.c2fT_ptr);
+        h->c2fT_slot = reinterpret_cast<int *>(h->ws + L.c2fT_slot);
+        h->c2fT_w = reinterpret_cast<double *>(h->ws + L.c2fT_w);
+        h->f2cT_node = reinterpret_cast<int *>(h->ws + L.f2cT_node);
+        h->f2cT_ptr = reinterpret_cast<int *>(h->ws + L.f2cT_ptr);
+        h->f2cT_c = reinterpret_cast<int *>(h->ws + L.f2cT_c);
+        h->f2cT_w = reinterpret_cast<double *>(h->ws + L.f2cT_w);
+        h->fc_row = reinterpret_cast<int *>(h->ws + L.fc_row);
+        h->f2cT_n = (int)ch.f2cT_node.size();
+        if (h->f2cT_n > 4 * L.n) return bail(HYB_EINVAL, "internal: transposed transfer list too long");
+        CREATE_TRY(up((void *)h->apt, ch.APT.data(), ch.APT.size() * 8));
+        CREATE_TRY(up((void *)h->pt, PTt.data(), PTt.size() * 8));
+        CREATE_TRY(up(h->c2fT_ptr, ch.c2fT_ptr.data(), ch.c2fT_ptr.size() * 4));
+        CREATE_TRY(up(h->c2fT_slot, ch.c2fT_slot.data(), ch.c2fT_slot.size() * 4));
+        CREATE_TRY(up(h->c2fT_w, ch.c2fT_w.data(), ch.c2fT_w.size() * 8));
+        CREATE_TRY(up(h->f2cT_ptr, ch.f2cT_ptr.data(), ch.f2cT_ptr.size() * 4));
+        if (h->f2cT_n) {
+            CREATE_TRY(up(h->f2cT_node, ch.f2cT_node.data(), ch.f2cT_node.size() * 4));
+            CREATE_TRY(up(h->f2cT_c, ch.f2cT_c.data(), ch.f2cT_c.size() * 4));
+            CREATE_TRY(up(h->f2cT_w, ch.f2cT_w.data(), ch.f2cT_w.size() * 8));
+        }
+        if (h->nfc) CREATE_TRY(up(h->fc_row, ch.fc_nodes.data(), ch.fc_nodes.size() * 4));
         std::vector<double> xp(L.vec_len, 0.0);
         const int m1 = mesh->M + 1;
         for (int l = 0; l < m1; ++l)
@@ -947,6 +994,186 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
     HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_out, lcur, false, h->stream));
     return HYB_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Tape of hyb_step_record: f*(t_n), then eta fine states per pass; three
+// adjoint fields; the interface arrays a and b of every pass; dJ/da, dJ/db;
+// four padded coarse vectors; dJ/du_fc; one solver result per pass.
+struct StepTape {
+    size_t states = 0, scratch = 0, bc = 0, gab = 0, coarse = 0, lufc = 0, kres = 0, total = 0;
+};
+
+StepTape step_tape_layout(const hyb_handle *h, int passes) {
+    StepTape T;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    const size_t fb = h->lay.f_bytes;
+    const size_t nslots = 4 * (size_t)(h->N - 1);
+    T.states = take((1 + (size_t)passes * h->eta) * fb);
+    T.scratch = take(3 * fb);
+    T.bc = take((1 + (size_t)passes) * nslots * 8);
+    T.gab = take(2 * nslots * 8);
+    T.coarse = take(4 * align_up(h->lay.vec_len * 8, kAlign));
+    T.lufc = take((size_t)h->lay.n * 8);
+    T.kres = take((size_t)passes * sizeof(KrylovResult));
+    T.total = off;
+    return T;
+}
+
+int step_adjoint_supported(hyb_handle *h) {
+    if (!h->has_mesh) return h->fail(HYB_EINVAL, "the step adjoint needs a coarse mesh");
+    if (h->prec == HYB_FP16S) return h->fail(HYB_EINVAL, "the adjoint supports HYB_FP64 and HYB_FP32 storage");
+    if (h->any_neumann) return h->fail(HYB_EINVAL, "the adjoint supports Dirichlet perimeter slots only");
+    return HYB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hyb_step_adjoint_query(const hyb_handle *h, int passes, size_t *tape_bytes) {
+    if (!h || !tape_bytes || passes < 1 || !h->has_mesh) return HYB_EINVAL;
+    *tape_bytes = step_tape_layout(h, passes).total;
+    return HYB_OK;
+}
+
+int hyb_step_record(hyb_handle *h, int passes, void *tape) {
+    if (!h) return HYB_EINVAL;
+    int rc = step_adjoint_supported(h);
+    if (rc != HYB_OK) return rc;
+    if (passes < 1) return h->fail(HYB_EINVAL, "passes must be >= 1");
+    if (!tape || reinterpret_cast<uintptr_t>(tape) % kAlign) return h->fail(HYB_EINVAL, "tape must be 256-byte aligned");
+    const StepTape T = step_tape_layout(h, passes);
+    const size_t fb = h->lay.f_bytes;
+    const size_t nslots = 4 * (size_t)(h->N - 1);
+    char *base = static_cast<char *>(tape);
+    auto state = [&](int p, int t) { return base + T.states + (t == 0 ? 0 : (1 + (size_t)p * h->eta + t - 1) * fb); };
+    double *bc = reinterpret_cast<double *>(base + T.bc);
+    h->rec_step_tape = nullptr;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        h->cur = h->frozen;
+        h->jsub = 0;
+        h->solved_this_step = false;
+        HIP_TRY(h, hipMemcpyAsync(state(0, 0), h->f[h->frozen], fb, hipMemcpyDeviceToDevice, h->stream));
+        const int out = h->spare(-1);
+        for (int p = 0; p < passes; ++p) {
+            if ((rc = hyb_interface_exchange(h, HYB_F2C)) != HYB_OK) return rc;
+            if ((rc = hyb_coarse_step(h, 200)) != HYB_OK) return rc;
+            if ((rc = hyb_interface_exchange(h, HYB_C2F)) != HYB_OK) return rc;
+            if (p == 0) HIP_TRY(h, hipMemcpyAsync(bc, h->bc_a, nslots * 8, hipMemcpyDeviceToDevice, h->stream));
+            HIP_TRY(h, hipMemcpyAsync(bc + (1 + p) * nslots, h->bc_b, nslots * 8, hipMemcpyDeviceToDevice, h->stream));
+            for (int t = 1; t <= h->eta; ++t) {
+                LbmArgs a = h->lbm_args(h->frozen, -1);
+                a.src = state(p, t - 1);
+                a.dst = state(p, t);
+                a.lam = (double)t / (double)h->eta;
+                HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
+            }
+            HIP_TRY(h, hipMemcpyAsync(h->f[out], state(p, h->eta), fb, hipMemcpyDeviceToDevice, h->stream));
+            h->cur = out;
+            h->jsub = h->eta;
+            h->fine_steps += h->eta;
+        }
+        rc = hyb_commit(h);
+        if (rc != HYB_ENOCONV || h->solve_budget >= h->solve_cap) break;
+        h->last_krylov_iters = h->solve_cap;
+    }
+    if (rc == HYB_OK) {
+        h->rec_step_tape = tape;
+        h->rec_step_passes = passes;
+    }
+    return rc;
+}
+
+int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_d, double *lam_f_out,
+                     double *lam_d_out, double *grad_k) {
+    if (!h) return HYB_EINVAL;
+    int rc = step_adjoint_supported(h);
+    if (rc != HYB_OK) return rc;
+    if (!tape || tape != h->rec_step_tape) return h->fail(HYB_EINVAL, "the tape must be that of the last hyb_step_record");
+    if (!lam_f || !lam_f_out || !lam_d_out) return h->fail(HYB_EINVAL, "null adjoint argument");
+    const int passes = h->rec_step_passes;
+    const StepTape T = step_tape_layout(h, passes);
+    const size_t fb = h->lay.f_bytes;
+    const size_t nslots = 4 * (size_t)(h->N - 1);
+    char *base = static_cast<char *>(const_cast<void *>(tape));
+    auto state = [&](int p, int t) { return base + T.states + (t == 0 ? 0 : (1 + (size_t)p * h->eta + t - 1) * fb); };
+    void *lcur = base + T.scratch, *nu = base + T.scratch + fb, *lnext = base + T.scratch + 2 * fb;
+    double *bc = reinterpret_cast<double *>(base + T.bc);
+    double *ga = reinterpret_cast<double *>(base + T.gab), *gb = ga + nslots;
+    const size_t vs = align_up(h->lay.vec_len * 8, kAlign);
+    double *lam_dn = reinterpret_cast<double *>(base + T.coarse);
+    double *lam_d1 = reinterpret_cast<double *>(base + T.coarse + vs);
+    double *rhs_t = reinterpret_cast<double *>(base + T.coarse + 2 * vs);
+    double *mu = reinterpret_cast<double *>(base + T.coarse + 3 * vs);
+    double *lam_ufc = reinterpret_cast<double *>(base + T.lufc);
+    KrylovResult *kr = reinterpret_cast<KrylovResult *>(base + T.kres);
+    const size_t dense_bytes = (size_t)9 * h->N * h->N * 8;
+    LbmArgs a = h->lbm_args(h->frozen, -1);
+    HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_f, lcur, true, h->stream));
+    HIP_TRY(h, hipMemsetAsync(lam_f_out, 0, dense_bytes, h->stream));
+    // the padded coarse vectors keep a zero halo (stencils read it)
+    HIP_TRY(h, hipMemsetAsync(base + T.coarse, 0, 4 * vs, h->stream));
+    CoarseDev ct = h->cd;
+    ct.AP = h->apt;
+    const int budget = std::min(200, std::max(16, 2 * h->last_krylov_iters + 6));
+    for (int p = passes - 1; p >= 0; --p) {
+        // fine steps of pass p, reversed (interface values of the pass)
+        HIP_TRY(h, hipMemsetAsync(ga, 0, 2 * nslots * 8, h->stream));
+        a.bc_a = bc;
+        a.bc_b = bc + (1 + p) * nslots;
+        for (int t = h->eta; t >= 1; --t) {
+            a.src = state(p, t - 1);
+            a.lam = (double)t / (double)h->eta;
+            HIP_TRY(h, launch_adjoint_step(a, h->prec, state(p, t), lcur, nu, lnext, ga, gb, grad_k, h->stream));
+            std::swap(lcur, lnext);
+        }
+        HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_f_out, lcur, false, h->stream, true));
+        // coarse-to-fine, coarse solve and right-hand side, transposed
+        HIP_TRY(h, launch_c2f_transpose(h->cd, h->c2fT_ptr, h->c2fT_slot, h->c2fT_w, ga, gb,
+                                        p == passes - 1 ? lam_d : nullptr, lam_dn, lam_d1, h->stream));
+        HIP_TRY(h, launch_coarse_stencil(h->cd, h->pt, kSpaiW, lam_d1, rhs_t, h->stream));
+        ct.result = kr + p;
+        HIP_TRY(h, launch_coarse_solve_given(ct, rhs_t, mu, budget, 200, 1e-14, h->stream));
+        HIP_TRY(h, launch_coarse_rhs_transpose(h->cd, h->fc_row, h->nfc, mu, lam_dn, lam_ufc, h->stream));
+        // fine-to-coarse transposed onto the state the pass's transfer read
+        if (p == 0) {
+            HIP_TRY(h, launch_f2c_transpose(a, h->prec, h->f2cT_node, h->f2cT_ptr, h->f2cT_c, h->f2cT_w, h->f2cT_n,
+                                            lam_ufc, state(0, 0), nullptr, lam_f_out, grad_k, h->stream));
+        } else {
+            HIP_TRY(h, hipMemsetAsync(lcur, 0, fb, h->stream));
+            HIP_TRY(h, launch_f2c_transpose(a, h->prec, h->f2cT_node, h->f2cT_ptr, h->f2cT_c, h->f2cT_w, h->f2cT_n,
+                                            lam_ufc, state(p - 1, h->eta), lcur, nullptr, grad_k, h->stream));
+        }
+    }
+    HIP_TRY(h, launch_coarse_repad(h->cd, lam_dn, lam_d_out, true, h->stream));
+    std::vector<KrylovResult> res(passes);
+    HIP_TRY(h, hipMemcpyAsync(res.data(), kr, passes * sizeof(KrylovResult), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (int p = 0; p < passes; ++p)
+        if (!res[p].converged) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "transposed coarse solve of pass %d did not converge (%d iterations, relres %.3e)",
+                          p, res[p].iters, res[p].relres);
+            return h->fail(HYB_ENOCONV, buf);
+        }
+    return HYB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+}  // namespace
+
+extern "C" {
 
 int hyb_set_steps_per_launch(hyb_handle *h, int steps) {
     if (!h) return HYB_EINVAL;

@@ -132,9 +132,10 @@ hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part 
 // grad_a, grad_b [4(N-1)] and grad_k (dense [N][N] or null) accumulate.
 hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
                                double *grad_a, double *grad_b, double *grad_k, hipStream_t s);
-// dense FP64 [9][N][N] to pitched planes (to_pitched) or back
+// dense FP64 [9][N][N] to pitched planes (to_pitched) or back; back with
+// accumulate adds to the dense array instead of overwriting it
 hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,
-                               hipStream_t s);
+                               hipStream_t s, bool accumulate = false);
 hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, int prec, hipStream_t s);
 hipError_t launch_concentration(const LbmArgs &a, double *out, int prec, hipStream_t s);
 
@@ -174,11 +175,45 @@ hipError_t launch_coarse_extrapolate(const CoarseDev &c, hipStream_t s);
 hipError_t launch_coarse_solve(const CoarseDev &c, const double *guess, int iterations, int max_iter, double tol,
                                hipStream_t s);
 
+// Solve (operator c.AP) y = rhs from y = 0 and write out = y (padded):
+// the rhs kernel, `iterations` BiCGSTAB iterations, the closing pair and
+// the copy; the iteration count and convergence go to *c.result.  With
+// c.AP set to the (A P)^T stencil and rhs = P^T lam this is the transposed
+// coarse solve mu = A^{-T} lam of the reverse mode.
+hipError_t launch_coarse_solve_given(const CoarseDev &c, const double *rhs, double *out, int iterations, int max_iter,
+                                     double tol, hipStream_t s);
+
 // Interface transfers (coarse_kernels.hip)
 hipError_t launch_c2f(const int *idx, const double *w, int nslots, const double *xa, const double *xb,
                       double *a, double *b, hipStream_t s);
 hipError_t launch_f2c(const LbmArgs &lat, const int *idx, const double *w, int nfc, double *ufc, int prec,
                       hipStream_t s);
+
+// Reverse mode of the coarse step and the transfers (coarse_adjoint.hip);
+// coarse vectors are padded ((M+1+2 halo)^2, zero halo) unless named dense.
+// lam_dn += C^T ga and lam_d1 = C^T gb (+ lam_d_dense when non-null) per
+// mesh node, C the coarse-to-fine interpolation (CSR ptr/slot/w over nodes)
+hipError_t launch_c2f_transpose(const CoarseDev &c, const int *ptr, const int *slot, const double *w, const double *ga,
+                                const double *gb, const double *lam_d_dense, double *lam_dn, double *lam_d1,
+                                hipStream_t s);
+// out = S in for a node-major-to-offset-major stencil S of width W (5: P^T)
+hipError_t launch_coarse_stencil(const CoarseDev &c, const double *coef, int W, const double *in, double *out,
+                                 hipStream_t s);
+// lam_dn += B^T (mu on the free rows); lam_ufc[c] = a_ii mu[row c] on the
+// Gamma_{f->c} rows (fc_row: mesh node of each)
+hipError_t launch_coarse_rhs_transpose(const CoarseDev &c, const int *fc_row, int nfc, const double *mu,
+                                       double *lam_dn, double *lam_ufc, hipStream_t s);
+// Fine-to-coarse transposed onto the lattice nodes it reads (CSR node/ptr/
+// cidx/w over ntouched pitched nodes): lam_u = sum w lam_ufc[c]; every
+// population of the node receives lam_u / (1 - k), added to lam_pitched
+// (storage T planes) or, when that is null, to lam_dense (FP64 [9][N][N]);
+// grad_k (dense [N][N], or null) += lam_u sum_q g_q / (1 - k)^2 for the
+// state g the forward transfer read.  HYB_FP64 or HYB_FP32 storage.
+hipError_t launch_f2c_transpose(const LbmArgs &lat, int prec, const int *node, const int *ptr, const int *cidx,
+                                const double *w, int ntouched, const double *lam_ufc, const void *g_state,
+                                void *lam_pitched, double *lam_dense, double *grad_k, hipStream_t s);
+// dense[(M+1)^2] = padded (unpad), or padded = dense (pad, halo untouched)
+hipError_t launch_coarse_repad(const CoarseDev &c, const double *from, double *to, bool to_dense, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // host-side setup (coarse_setup.hip)
@@ -193,6 +228,16 @@ struct CoarseHost {
     std::vector<double> fc_w;              // [nfc][4]
     std::vector<int> c2f_idx;              // [4(N-1)][4] padded coarse indices
     std::vector<double> c2f_w;             // [4(N-1)][4]
+    // reverse mode: (A P)^T (node-major, like AP) and P^T (node-major, like
+    // P) stencils; the coarse-to-fine transfer transposed per mesh node
+    // (CSR over nodes: slots and weights, in slot order); the fine-to-coarse
+    // transfer transposed per lattice node it reads (CSR over the touched
+    // pitched nodes: Gamma_{f->c} indices and nonzero weights, in index order)
+    std::vector<double> APT, PT;
+    std::vector<int> c2fT_ptr, c2fT_slot;
+    std::vector<double> c2fT_w;
+    std::vector<int> f2cT_node, f2cT_ptr, f2cT_c;
+    std::vector<double> f2cT_w;
 };
 
 // Assembles A, B for the trapezoidal step dt and the SPAI preconditioner;

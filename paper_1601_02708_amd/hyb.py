@@ -70,6 +70,9 @@ SIGNATURES = {
     "hyb_adjoint_query": (_i, [_P, _i, _P]),
     "hyb_lbm_substeps_record": (_i, [_P, _i, _P]),
     "hyb_lbm_adjoint": (_i, [_P, _i, _P, _P, _P, _P, _P, _P]),
+    "hyb_step_adjoint_query": (_i, [_P, _i, _P]),
+    "hyb_step_record": (_i, [_P, _i, _P]),
+    "hyb_step_adjoint": (_i, [_P, _P, _P, _P, _P, _P, _P]),
     "hyb_set_overlap": (_i, [_P, _i]),
     "hyb_set_steps_per_launch": (_i, [_P, _i]),
     "hyb_kernel_timing": (_i, [_P, _i]),
@@ -239,6 +242,28 @@ class Hybrid:
         s = HybRunStats()
         self._check(load().hyb_stats(self.h, ctypes.addressof(s)))
         return {k: getattr(s, k) for k, _ in HybRunStats._fields_}
+
+    # -- reverse mode of a whole coarse step ---------------------------------
+    def step_tape(self, passes):
+        """A device tape (torch uint8 tensor) for hyb_step_record(passes)."""
+        nb = ctypes.c_size_t()
+        self._check(load().hyb_step_adjoint_query(self.h, int(passes), ctypes.addressof(nb)))
+        return self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.dev)
+
+    def step_record(self, passes, tape):
+        return self._check(load().hyb_step_record(self.h, int(passes), tape.data_ptr()))
+
+    def step_adjoint(self, tape, lam_f, lam_d, lam_f_out, lam_d_out, grad_k=None):
+        """Device FP64 tensors: lam_f/lam_f_out [9, N, N], lam_d/lam_d_out
+        [(M+1)^2] (lam_d may be None), grad_k [N, N] or None (added to)."""
+        t = self.torch
+        for x in (lam_f, lam_f_out, lam_d_out) + tuple(v for v in (lam_d, grad_k) if v is not None):
+            if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
+                raise ValueError("adjoint arrays must be contiguous FP64 device tensors")
+        return self._check(load().hyb_step_adjoint(self.h, tape.data_ptr(), lam_f.data_ptr(),
+                                                   None if lam_d is None else lam_d.data_ptr(),
+                                                   lam_f_out.data_ptr(), lam_d_out.data_ptr(),
+                                                   None if grad_k is None else grad_k.data_ptr()))
 
     # -- reverse mode -------------------------------------------------------
     def adjoint_tape(self, n_sub):
