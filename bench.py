@@ -169,6 +169,46 @@ def adjoint_rate(problem, precision, reps=3):
     return out
 
 
+def step_adjoint_rate(problem, precision, reps=3):
+    """Reverse mode of one whole coarse step (hyb_step_record, then
+    hyb_step_adjoint: every Schwarz pass's fine steps, transfers and coarse
+    solve transposed); MLUPS over the step's lattice updates (passes x eta x
+    all nodes) for the adjoint and for the recording forward."""
+    import torch
+    from paper_1601_02708_amd import hyb
+    g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
+    cfg = problem.cfg
+    passes, eta, N = cfg.max_iter, cfg.eta, cfg.N
+    tape = g.step_tape(passes)
+    lam_f = torch.ones((9, N, N), dtype=torch.float64, device=g.dev)
+    lam_d = torch.ones((cfg.M + 1) ** 2, dtype=torch.float64, device=g.dev)
+    out_f = torch.empty_like(lam_f)
+    out_d = torch.empty_like(lam_d)
+    gk = torch.zeros((N, N), dtype=torch.float64, device=g.dev)
+    s = g.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    rec_ms = adj_ms = 0.0
+    for r in range(reps + 1):
+        ev[0].record(s)
+        g.step_record(passes, tape)
+        ev[1].record(s)
+        g.step_adjoint(tape, lam_f, lam_d, out_f, out_d, gk)
+        ev[2].record(s)
+        torch.cuda.synchronize()
+        if r > 0:                       # the first pass warms up
+            rec_ms += ev[0].elapsed_time(ev[1])
+            adj_ms += ev[1].elapsed_time(ev[2])
+    lups = passes * eta * N * N * reps
+    res = {"precision": precision, "value": round(lups / (adj_ms / 1e3) / 1e6, 1), "unit": "MLUPS",
+           "ms_per_coarse_step": round(adj_ms / reps, 4),
+           "record_forward_mlups": round(lups / (rec_ms / 1e3) / 1e6, 1),
+           "tape_bytes": int(tape.numel()),
+           "note": "dJ/df*(t_n), dJ/dd^n, dJ/dk through one coarse step of Algorithm 1 "
+                   "(fine steps, transfers and the transposed coarse solve of every Schwarz pass)"}
+    g.close()
+    return res
+
+
 def cpu_baseline(problem, min_seconds=10.0, max_steps=6):
     """The oracle as it stands on this host: whole coarse steps (2 Schwarz
     passes x eta fine steps each, FP64, one thread) of the same workload,
@@ -313,6 +353,7 @@ def main():
     if not args.no_adjoint and args.precision in ("fp32", "fp64"):
         print("[bench] adjoint", file=sys.stderr, flush=True)
         res["adjoint"] = adjoint_rate(problem, args.precision)
+        res["step_adjoint"] = step_adjoint_rate(problem, args.precision)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one coarse step)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(problem)
