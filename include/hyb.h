@@ -186,6 +186,12 @@ int hyb_concentration(hyb_handle *h, int which, double *out, int out_is_device);
 int hyb_get_populations(hyb_handle *h, double *out);
 int hyb_set_populations(hyb_handle *h, const double *f);
 
+/* Replace the committed coarse solution d(t_n) with host FP64 d[(M+1)^2]
+ * (node l*(M+1) + k); also taken as d(t_{n-1}) by the next step's
+ * extrapolated first guess.  Like hyb_set_populations it abandons a coarse
+ * step in progress.  Synchronises. */
+int hyb_set_coarse(hyb_handle *h, const double *d);
+
 int hyb_stats(hyb_handle *h, hyb_run_stats *out);
 
 /* ---- differentiation form (reverse mode) of the fine sub-steps ----------
@@ -243,12 +249,15 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
  *   lam_d = dJ/dd^{n+1} (device FP64 [(M+1)^2], mesh node l*(M+1) + k, or
  *   NULL for zero); writes lam_f_out = dJ/df*(t_n) (may alias lam_f) and
  *   lam_d_out = dJ/dd^n; grad_k (device FP64 [N*N] or NULL) += dJ/dk of the
- *   fine per-node reaction rate.  Synchronises; HYB_ENOCONV if a transposed
- *   coarse solve does not reach 1e-14 relative residual. */
+ *   fine per-node reaction rate; grad_outer (device FP64 [(M+1)^2] or NULL)
+ *   += dJ/dg for the value g each outer-edge node of the coarse mesh is held
+ *   at during the step (zero elsewhere; the control of a prescribed inlet).
+ *   Synchronises; HYB_ENOCONV if a transposed coarse solve does not reach
+ *   1e-14 relative residual. */
 int hyb_step_adjoint_query(const hyb_handle *h, int passes, size_t *tape_bytes);
 int hyb_step_record(hyb_handle *h, int passes, void *tape);
 int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_d, double *lam_f_out,
-                     double *lam_d_out, double *grad_k);
+                     double *lam_d_out, double *grad_k, double *grad_outer);
 
 /* Overlap in hyb_step (default HYB_OVERLAP_AUTO): with two-step launches,
  * the deep interior tiles of each Schwarz pass's first `depth` launches run

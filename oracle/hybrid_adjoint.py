@@ -203,13 +203,16 @@ class HybridStepAdjoint:
             ufc_src = states[-1]
         return ufc_src, d1, tape
 
-    def adjoint(self, tape, lam_f, lam_d):
+    def adjoint(self, tape, lam_f, lam_d, outer=False):
         """(dJ/dF, dJ/dd^n, dJ/dk) for cotangents lam_f = dJ/df*(t_{n+1})
-        [9,N,N] and lam_d = dJ/dd^{n+1} [(M+1)^2]."""
+        [9,N,N] and lam_d = dJ/dd^{n+1} [(M+1)^2]; with outer, also dJ/dg
+        for the prescribed values g of the outer-edge Dirichlet rows (per
+        mesh node, zero elsewhere)."""
         o = self.o
         N = o.N
         lam_F = np.zeros((9, N, N))
         lam_dn = np.zeros(self.A.shape[0])
+        g_outer = np.zeros(self.A.shape[0])
         gk = np.zeros((N, N))
         lam_p = np.asarray(lam_f, np.float64)
         passes = tape["passes"]
@@ -232,10 +235,14 @@ class HybridStepAdjoint:
                 lam_d1 = lam_d1 + np.asarray(lam_d, np.float64)
             ld, lvals = self.coarse_T(lam_d1)
             lam_dn += ld
+            rows = o.rows_sorted
+            g_outer[rows[~o._is_fc]] += np.asarray(lvals)[~o._is_fc]
             lf, kf = self.f2c_T(self.ufc_of_values(lvals), rec["src"])
             gk += kf
             if p == 0:
                 lam_F += lf
             else:
                 lam_p = lf
+        if outer:
+            return lam_F, lam_dn, gk, g_outer
         return lam_F, lam_dn, gk

@@ -52,10 +52,12 @@ __global__ void stencil_kernel(CoarseDev c, const double *__restrict__ coef, con
 
 // lam_dn[i] += sum over free rows j next to i of B(j, i) mu[j]; the
 // Gamma_{f->c} row of index t receives lam_ufc[t] = a_ii mu[row] (its
-// right-hand side is a_ii times the transferred value)
+// right-hand side is a_ii times the transferred value); an outer-edge row
+// adds a_ii mu to grad_outer (its right-hand side is a_ii times the
+// prescribed value)
 __global__ void rhs_transpose_kernel(CoarseDev c, const int *__restrict__ fc_row, int nfc,
                                      const double *__restrict__ mu, double *__restrict__ lam_dn,
-                                     double *__restrict__ lam_ufc) {
+                                     double *__restrict__ lam_ufc, double *__restrict__ grad_outer) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= c.n) return;
     const int m1 = c.M + 1;
@@ -73,6 +75,7 @@ __global__ void rhs_transpose_kernel(CoarseDev c, const int *__restrict__ fc_row
             s += c.B9[(size_t)((1 - dl) * 3 + (1 - dk)) * c.n + j] * mu[pad_of(c, j)];
         }
     lam_dn[pad_of(c, t)] += s;
+    if (grad_outer && c.dkind[t] == -2) grad_outer[t] += c.A9[(size_t)4 * c.n + t] * mu[pad_of(c, t)];
     if (t < nfc) {
         const int row = fc_row[t];
         lam_ufc[t] = c.A9[(size_t)4 * c.n + row] * mu[pad_of(c, row)];
@@ -137,9 +140,9 @@ hipError_t launch_coarse_stencil(const CoarseDev &c, const double *coef, int W, 
 }
 
 hipError_t launch_coarse_rhs_transpose(const CoarseDev &c, const int *fc_row, int nfc, const double *mu,
-                                       double *lam_dn, double *lam_ufc, hipStream_t s) {
+                                       double *lam_dn, double *lam_ufc, double *grad_outer, hipStream_t s) {
     hipLaunchKernelGGL(rhs_transpose_kernel, dim3(blocks_for(c.n)), dim3(kBlock), 0, s, c, fc_row, nfc, mu, lam_dn,
-                       lam_ufc);
+                       lam_ufc, grad_outer);
     return hipGetLastError();
 }
 

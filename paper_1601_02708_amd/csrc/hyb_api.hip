@@ -919,6 +919,22 @@ int hyb_set_populations(hyb_handle *h, const double *fin) {
     return HYB_OK;
 }
 
+int hyb_set_coarse(hyb_handle *h, const double *d) {
+    if (!h || !d) return HYB_EINVAL;
+    if (!h->has_mesh) return h->fail(HYB_EINVAL, "no coarse mesh");
+    const int m1 = h->M + 1;
+    std::vector<double> xp(h->lay.vec_len, 0.0);
+    for (int l = 0; l < m1; ++l)
+        for (int kk = 0; kk < m1; ++kk) xp[(size_t)(l + kCoarseHalo) * h->cd.S + kk + kCoarseHalo] = d[l * m1 + kk];
+    for (double *dst : {h->cd.xn, h->cd.x1, h->cd.xprev})
+        HIP_TRY(h, hipMemcpyAsync(dst, xp.data(), xp.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->solved_this_step = false;
+    h->cur = h->frozen;
+    h->jsub = 0;
+    return HYB_OK;
+}
+
 int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
     if (!h || !out) return HYB_EINVAL;
     unsigned long long cnt[kCntSlots];
@@ -1093,7 +1109,7 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
 }
 
 int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_d, double *lam_f_out,
-                     double *lam_d_out, double *grad_k) {
+                     double *lam_d_out, double *grad_k, double *grad_outer) {
     if (!h) return HYB_EINVAL;
     int rc = step_adjoint_supported(h);
     if (rc != HYB_OK) return rc;
@@ -1142,7 +1158,7 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
         HIP_TRY(h, launch_coarse_stencil(h->cd, h->pt, kSpaiW, lam_d1, rhs_t, h->stream));
         ct.result = kr + p;
         HIP_TRY(h, launch_coarse_solve_given(ct, rhs_t, mu, budget, 200, 1e-14, h->stream));
-        HIP_TRY(h, launch_coarse_rhs_transpose(h->cd, h->fc_row, h->nfc, mu, lam_dn, lam_ufc, h->stream));
+        HIP_TRY(h, launch_coarse_rhs_transpose(h->cd, h->fc_row, h->nfc, mu, lam_dn, lam_ufc, grad_outer, h->stream));
         // fine-to-coarse transposed onto the state the pass's transfer read
         if (p == 0) {
             HIP_TRY(h, launch_f2c_transpose(a, h->prec, h->f2cT_node, h->f2cT_ptr, h->f2cT_c, h->f2cT_w, h->f2cT_n,

@@ -200,9 +200,10 @@ hipError_t launch_c2f_transpose(const CoarseDev &c, const int *ptr, const int *s
 hipError_t launch_coarse_stencil(const CoarseDev &c, const double *coef, int W, const double *in, double *out,
                                  hipStream_t s);
 // lam_dn += B^T (mu on the free rows); lam_ufc[c] = a_ii mu[row c] on the
-// Gamma_{f->c} rows (fc_row: mesh node of each)
+// Gamma_{f->c} rows (fc_row: mesh node of each); grad_outer (dense, or
+// null) += a_ii mu on the outer-edge rows
 hipError_t launch_coarse_rhs_transpose(const CoarseDev &c, const int *fc_row, int nfc, const double *mu,
-                                       double *lam_dn, double *lam_ufc, hipStream_t s);
+                                       double *lam_dn, double *lam_ufc, double *grad_outer, hipStream_t s);
 // Fine-to-coarse transposed onto the lattice nodes it reads (CSR node/ptr/
 // cidx/w over ntouched pitched nodes): lam_u = sum w lam_ufc[c]; every
 // population of the node receives lam_u / (1 - k), added to lam_pitched

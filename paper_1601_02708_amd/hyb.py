@@ -72,7 +72,8 @@ SIGNATURES = {
     "hyb_lbm_adjoint": (_i, [_P, _i, _P, _P, _P, _P, _P, _P]),
     "hyb_step_adjoint_query": (_i, [_P, _i, _P]),
     "hyb_step_record": (_i, [_P, _i, _P]),
-    "hyb_step_adjoint": (_i, [_P, _P, _P, _P, _P, _P, _P]),
+    "hyb_step_adjoint": (_i, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "hyb_set_coarse": (_i, [_P, _P]),
     "hyb_set_overlap": (_i, [_P, _i]),
     "hyb_set_steps_per_launch": (_i, [_P, _i]),
     "hyb_kernel_timing": (_i, [_P, _i]),
@@ -253,17 +254,25 @@ class Hybrid:
     def step_record(self, passes, tape):
         return self._check(load().hyb_step_record(self.h, int(passes), tape.data_ptr()))
 
-    def step_adjoint(self, tape, lam_f, lam_d, lam_f_out, lam_d_out, grad_k=None):
+    def step_adjoint(self, tape, lam_f, lam_d, lam_f_out, lam_d_out, grad_k=None, grad_outer=None):
         """Device FP64 tensors: lam_f/lam_f_out [9, N, N], lam_d/lam_d_out
-        [(M+1)^2] (lam_d may be None), grad_k [N, N] or None (added to)."""
+        [(M+1)^2] (lam_d may be None), grad_k [N, N] and grad_outer
+        [(M+1)^2] or None (added to)."""
         t = self.torch
-        for x in (lam_f, lam_f_out, lam_d_out) + tuple(v for v in (lam_d, grad_k) if v is not None):
+        for x in (lam_f, lam_f_out, lam_d_out) + tuple(v for v in (lam_d, grad_k, grad_outer) if v is not None):
             if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
                 raise ValueError("adjoint arrays must be contiguous FP64 device tensors")
-        return self._check(load().hyb_step_adjoint(self.h, tape.data_ptr(), lam_f.data_ptr(),
-                                                   None if lam_d is None else lam_d.data_ptr(),
-                                                   lam_f_out.data_ptr(), lam_d_out.data_ptr(),
-                                                   None if grad_k is None else grad_k.data_ptr()))
+        ptr = lambda v: None if v is None else v.data_ptr()
+        return self._check(load().hyb_step_adjoint(self.h, tape.data_ptr(), lam_f.data_ptr(), ptr(lam_d),
+                                                   lam_f_out.data_ptr(), lam_d_out.data_ptr(), ptr(grad_k),
+                                                   ptr(grad_outer)))
+
+    def set_coarse(self, d):
+        """Replace the committed coarse solution (host [(M+1)^2] FP64)."""
+        d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1)
+        if d.size != (self.M + 1) ** 2:
+            raise ValueError("coarse state must have (M+1)^2 entries")
+        return self._check(load().hyb_set_coarse(self.h, _ptr(d)))
 
     # -- reverse mode -------------------------------------------------------
     def adjoint_tape(self, n_sub):
@@ -354,3 +363,109 @@ def lattice_substeps_function():
             return None, None, lam_out.to(ctx.dev), ga.to(ctx.dev), gb.to(ctx.dev)
 
     return LatticeSubsteps
+
+
+
+def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8):
+    """Reverse mode of n_steps coarse steps from the handle's committed state
+    (which is left at the end of the rollout), with the state checkpointed
+    every ``checkpoint_every`` steps on the host and each step re-run inside
+    its segment (two forward sweeps and one reverse sweep in all).
+
+    ``cotangent(n, F, d)`` returns (dJ/dF_n, dJ/dd_n) as host FP64 arrays
+    ([9, N, N], [(M+1)^2]; either may be None) for the state (F, d) after
+    step n (n = 1 .. n_steps), so J may sum over the whole trajectory.  Every
+    step runs ``passes`` Schwarz passes (hyb_step with that count).  Returns
+    host FP64 arrays (dJ/dF_0, dJ/dd_0, dJ/dk, dJ/dg_outer): the initial
+    state, the fine per-node reaction rate and the outer-edge Dirichlet
+    values (per coarse node, summed over the steps).  Each step's adjoint
+    runs on the GPU through hyb_step_record and hyb_step_adjoint; this
+    function only moves states and orchestrates."""
+    import torch
+    N, M = g.N, g.M
+    dev = g.dev
+    n1 = (M + 1) ** 2
+
+    def state():
+        return g.get_populations(), g.concentration(HYB_COARSE).copy()
+
+    def restore(st):
+        g.set_populations(st[0])
+        g.set_coarse(st[1])
+
+    # forward rollout, checkpointing the state at every segment start
+    ckpt = {}
+    for n in range(n_steps):
+        if n % checkpoint_every == 0:
+            ckpt[n] = state()
+        g.step(passes)
+    ckpt[n_steps] = state()
+    tape = g.step_tape(passes)
+    lam_f = torch.zeros((9, N, N), dtype=torch.float64, device=dev)
+    lam_d = torch.zeros(n1, dtype=torch.float64, device=dev)
+    out_f = torch.empty_like(lam_f)
+    out_d = torch.empty_like(lam_d)
+    gk = torch.zeros((N, N), dtype=torch.float64, device=dev)
+    gouter = torch.zeros(n1, dtype=torch.float64, device=dev)
+    starts = sorted(k for k in ckpt if k < n_steps)
+    for si in range(len(starts) - 1, -1, -1):
+        s0 = starts[si]
+        s1 = starts[si + 1] if si + 1 < len(starts) else n_steps
+        # re-run the segment: seg[i] is the state before step s0 + i, and
+        # seg[s1 - s0] the next checkpoint (the state after its last step)
+        restore(ckpt[s0])
+        seg = [ckpt[s0]]
+        for _ in range(s0, s1 - 1):
+            g.step(passes)
+            seg.append(state())
+        seg.append(ckpt[s1])
+        for n in range(s1 - 1, s0 - 1, -1):
+            cf, cd = cotangent(n + 1, *seg[n - s0 + 1])
+            if cf is not None:
+                lam_f += torch.from_numpy(np.ascontiguousarray(cf, np.float64)).to(dev)
+            if cd is not None:
+                lam_d += torch.from_numpy(np.ascontiguousarray(cd, np.float64).reshape(-1)).to(dev)
+            restore(seg[n - s0])
+            g.step_record(passes, tape)
+            g.step_adjoint(tape, lam_f, lam_d, out_f, out_d, gk, gouter)
+            lam_f, out_f = out_f, lam_f
+            lam_d, out_d = out_d, lam_d
+    restore(ckpt[n_steps])
+    return lam_f.cpu().numpy(), lam_d.cpu().numpy(), gk.cpu().numpy(), gouter.cpu().numpy()
+
+
+def rollout_function():
+    """torch.autograd.Function for (F_n, d_n) = n coarse steps of Algorithm 1
+    from (F_0, d_0) on a handle: ``Rollout = rollout_function()`` then
+    ``Rollout.apply(hybrid, n_steps, passes, F0, d0)`` with F0 [9, N, N] and
+    d0 [(M+1)^2] FP64 tensors; backward runs steps_adjoint (checkpointed,
+    every step's adjoint on the GPU)."""
+    import torch
+
+    class Rollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, g, n_steps, passes, F0, d0):
+            g.set_populations(F0.detach().cpu().numpy())
+            g.set_coarse(d0.detach().cpu().numpy())
+            for _ in range(n_steps):
+                g.step(passes)
+            ctx.g, ctx.n, ctx.passes, ctx.dev = g, n_steps, passes, F0.device
+            ctx.F0, ctx.d0 = F0.detach().cpu().numpy(), d0.detach().cpu().numpy()
+            return (torch.from_numpy(g.get_populations()).to(F0.device),
+                    torch.from_numpy(g.concentration(HYB_COARSE).copy()).to(F0.device))
+
+        @staticmethod
+        def backward(ctx, gF, gd):
+            g, n = ctx.g, ctx.n
+            end = (g.get_populations(), g.concentration(HYB_COARSE).copy())
+            g.set_populations(ctx.F0)
+            g.set_coarse(ctx.d0)
+            cF = None if gF is None else gF.detach().cpu().numpy()
+            cd = None if gd is None else gd.detach().cpu().numpy()
+            lF, ld, _, _ = steps_adjoint(g, n, lambda k, F, d: (cF, cd) if k == n else (None, None),
+                                         ctx.passes, checkpoint_every=max(1, n))
+            g.set_populations(end[0])
+            g.set_coarse(end[1])
+            return None, None, None, torch.from_numpy(lF).to(ctx.dev), torch.from_numpy(ld).to(ctx.dev)
+
+    return Rollout

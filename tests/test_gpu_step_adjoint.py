@@ -141,3 +141,87 @@ def test_step_adjoint_rejects():
     g2 = hyb.Hybrid(N=8, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.1, eta=2)
     with pytest.raises(hyb.HybError):                     # no coarse mesh
         g2.step_record(1, g.step_tape(1))
+
+
+def test_set_coarse_round_trip():
+    hyb, torch = _gpu()
+    p = _problem("small")
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    d = np.random.default_rng(41).standard_normal((p.cfg.M + 1) ** 2)
+    g.set_coarse(d)
+    assert np.array_equal(g.concentration(hyb.HYB_COARSE).reshape(-1), d)
+    with pytest.raises(ValueError):
+        g.set_coarse(d[:-1])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+def test_steps_adjoint_matches_oracle_over_a_trajectory(orc, precision, tol):
+    """Three coarse steps, a cotangent on the state after every step
+    (a trajectory objective), checkpoints every two steps (segments of two
+    and one steps): the GPU reverse sweep equals the oracle's composition of
+    one-step adjoints, including dJ/dk and dJ/d(outer values)."""
+    from oracle.hybrid_adjoint import HybridStepAdjoint
+    hyb, torch = _gpu()
+    p = _problem("small", k=2e-3)
+    N, M, P = p.cfg.N, p.cfg.M, p.cfg.max_iter
+    n_steps = 3
+    g = hyb.Hybrid.from_problem(p, precision=precision)
+    F0 = g.get_populations()
+    d0 = g.concentration(hyb.HYB_COARSE).reshape(-1)
+
+    def cot(n, F, d):
+        rng = np.random.default_rng(100 + n)
+        return rng.standard_normal((9, N, N)), rng.standard_normal((M + 1) ** 2)
+
+    lF, ld, gk, go = hyb.steps_adjoint(g, n_steps, cot, P, checkpoint_every=2)
+    o = orc.HybridOracle(p)
+    adj = HybridStepAdjoint(o)
+    F, d = F0, d0
+    tapes, states = [], []
+    for _ in range(n_steps):
+        F, d, tp = adj.forward(F, d)
+        tapes.append(tp)
+        states.append((F, d))
+    # the handle ends at the rollout's end state
+    assert _rel(g.get_populations(), F) <= (1e-12 if precision == "fp64" else 1e-5)
+    oF = np.zeros((9, N, N))
+    od = np.zeros((M + 1) ** 2)
+    ok = np.zeros((N, N))
+    oo = np.zeros((M + 1) ** 2)
+    for n in range(n_steps - 1, -1, -1):
+        cf, cd = cot(n + 1, *states[n])
+        oF, od, k, out = adj.adjoint(tapes[n], oF + cf, od + cd, outer=True)
+        ok += k
+        oo += out
+    errs = {"F": _rel(lF, oF), "d": _rel(ld, od), "k": _rel(gk, ok), "outer": _rel(go, oo)}
+    print(f"\nsteps adjoint {precision}: {errs}")
+    assert max(errs.values()) <= tol, errs
+
+
+def test_rollout_autograd_by_central_differences():
+    """torch.autograd through two coarse steps: the gradient of
+    J = <w, F_2> + <v, d_2> along random directions equals central
+    differences of the GPU rollout (the map is linear: exact up to the
+    coarse solver's tolerance)."""
+    hyb, torch = _gpu()
+    p = _problem("small", k=1e-3)
+    N, M, P = p.cfg.N, p.cfg.M, p.cfg.max_iter
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    Rollout = hyb.rollout_function()
+    rng = np.random.default_rng(51)
+    dev = g.dev
+    F0 = torch.from_numpy(g.get_populations()).to(dev).requires_grad_(True)
+    d0 = torch.from_numpy(g.concentration(hyb.HYB_COARSE).copy()).to(dev).requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((9, N, N))).to(dev)
+    v = torch.from_numpy(rng.standard_normal((M + 1) ** 2)).to(dev)
+    F2, d2 = Rollout.apply(g, 2, P, F0, d0)
+    J = (w * F2).sum() + (v * d2).sum()
+    J.backward()
+    dF = torch.from_numpy(rng.standard_normal((9, N, N)) * 1e-2).to(dev)
+    dd = torch.from_numpy(rng.standard_normal((M + 1) ** 2) * 1e-2).to(dev)
+    with torch.no_grad():
+        Fp, dp = Rollout.apply(g, 2, P, F0 + dF, d0 + dd)
+        Fm, dm = Rollout.apply(g, 2, P, F0 - dF, d0 - dd)
+        fd = float(((w * (Fp - Fm)).sum() + (v * (dp - dm)).sum()) / 2)
+    an = float((F0.grad * dF).sum() + (d0.grad * dd).sum())
+    assert abs(fd - an) <= 1e-9 * max(1.0, abs(an)), (fd, an)

@@ -157,3 +157,28 @@ def test_step_rate_gradient_by_central_differences(small, orc):
 
     fd = (J(k0 + eps * dk) - J(k0 - eps * dk)) / (2 * eps)
     assert _rel(fd, float(np.sum(gk * dk))) <= 1e-7
+
+
+def test_outer_value_gradient_by_central_differences(small, orc):
+    """dJ/d(outer Dirichlet value): the step is affine in the prescribed
+    outer value g, so sum_nodes dJ/dg equals the central difference of J in
+    a uniform g (exact up to rounding)."""
+    from oracle.hybrid_adjoint import HybridStepAdjoint
+    p, o, adj = small
+    rng = np.random.default_rng(7)
+    F = rng.uniform(0.0, 0.2, (9, o.N, o.N))
+    d = rng.standard_normal((o.M + 1) ** 2)
+    lam_f = rng.standard_normal((9, o.N, o.N))
+    lam_d = rng.standard_normal((o.M + 1) ** 2)
+    _, _, tape = adj.forward(F, d)
+    _, _, _, g_outer = adj.adjoint(tape, lam_f, lam_d, outer=True)
+    assert np.all(g_outer[o.fc] == 0.0)
+
+    def J(g):
+        o2 = orc.HybridOracle(p, outer_value=g)
+        o2.fstar, o2.d = F.copy(), d.copy()
+        o2.step()
+        return float(np.sum(lam_f * o2.fstar)) + float(lam_d @ o2.d)
+
+    fd = (J(0.1) - J(-0.1)) / 0.2
+    assert _rel(fd, float(g_outer.sum())) <= 1e-9
