@@ -14,9 +14,11 @@
 //                           + nu_q(y), q = opp(p), if y bounced back along q
 //
 // (P_q(v) = 1 + 3 e.v + 9/2 (e.v)^2 - 3/2 v.v, w = 1/tau).  The first two
-// are local to a node (adj_local_kernel), the last gathers from the
-// neighbours (adj_stream_kernel).  The forward states of the step come from
-// the tape recorded by the forward sweep.
+// are local to a node, the last gathers from the neighbours: one kernel per
+// reversed step computes nu for a 64 x 8 tile and its one-node ring into LDS
+// and then gathers the tile's outputs from there, so nu never goes to HBM.
+// The forward states of the step come from the tape recorded by the forward
+// sweep.
 #include "hyb_impl.h"
 
 namespace hyb {
@@ -29,28 +31,27 @@ __device__ __forceinline__ int slot_of(int N, int i, int j) {
     return 3 * N - 2 + j - 1;
 }
 
+// nu at node (i, j) (collision and closure transposed); gradients of the
+// closure and the reaction rate are accumulated when `owner` (every node has
+// exactly one owner tile, ring copies recompute nu only).
 template <typename T>
-__global__ void __launch_bounds__(256) adj_local_kernel(LbmArgs a, const T *__restrict__ snext,
-                                                       const T *__restrict__ lam, T *__restrict__ nu,
-                                                       double *__restrict__ grad_a, double *__restrict__ grad_b,
-                                                       double *__restrict__ grad_k, int row_blocks) {
+__device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
+                                       const T *__restrict__ lam, bool owner, double *__restrict__ grad_a,
+                                       double *__restrict__ grad_b, double *__restrict__ grad_k, T (&nu)[kQ]) {
     const int N = a.N, P = a.pitch;
     const int plane = static_cast<int>(a.plane);
-    const int j = blockIdx.x / row_blocks;
-    const int i = (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
-    if (i >= N) return;
     const int n = j * P + i;
     const unsigned m = a.mask[n];
     if (m & kMaskSolid) {
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) nu[q * plane + n] = T(0);
+        for (int q = 0; q < kQ; ++q) nu[q] = T(0);
         return;
     }
     const T vx = T(a.vx[n]), vy = T(a.vy[n]);
     const T k = a.kfield ? static_cast<const T *>(a.kfield)[n] : T(a.k);
     const T omega = T(a.omega);
     const T vv = T(1.5) * (vx * vx + vy * vy);
-    T l[kQ], mu[kQ];
+    T l[kQ];
     T S = T(0), wl = T(0);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
@@ -61,8 +62,8 @@ __global__ void __launch_bounds__(256) adj_local_kernel(LbmArgs a, const T *__re
         wl += T(kW[q]) * l[q];
     }
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) mu[q] = (T(1) - omega) * l[q] + S;
-    if (grad_k) {
+    for (int q = 0; q < kQ; ++q) nu[q] = (T(1) - omega) * l[q] + S;
+    if (grad_k && owner) {
         // u at the step's collision: sum f*(t+1) = (1 - k) u
         T s = T(0);
 #pragma unroll
@@ -96,46 +97,68 @@ __global__ void __launch_bounds__(256) adj_local_kernel(LbmArgs a, const T *__re
 #pragma unroll
             for (int q = 0; q < kQ; ++q)
                 if ((unknown >> q) & 1u) {
-                    G += kW[q] * double(mu[q]);
+                    G += kW[q] * double(nu[q]);
                     wsum += kW[q];
                 }
             G /= wsum;
         }
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) mu[q] = ((unknown >> q) & 1u) ? T(0) : T(double(mu[q]) - G);
-        grad_a[p] += (1.0 - a.lam) * G;
-        grad_b[p] += a.lam * G;
+        for (int q = 0; q < kQ; ++q) nu[q] = ((unknown >> q) & 1u) ? T(0) : T(double(nu[q]) - G);
+        if (owner) {
+            grad_a[p] += (1.0 - a.lam) * G;
+            grad_b[p] += a.lam * G;
+        }
     }
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) nu[q * plane + n] = mu[q];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) adj_stream_kernel(LbmArgs a, const T *__restrict__ nu, T *__restrict__ out,
-                                                        int row_blocks) {
+// One reversed fine step.  Phase 1: nu for the tile grown by one ring (0
+// outside the patch and at solid nodes), into LDS.  Phase 2, per owned
+// fluid node y: dJ/df*_p(y) = nu_p(y + e_p) (zero when y + e_p is solid or
+// outside: it pulled nothing from y) + nu_q(y), q = opp(p), when y bounced
+// back along q.
+template <typename T, int TW, int TH, int NT>
+__global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__restrict__ snext,
+                                                      const T *__restrict__ lam, T *__restrict__ out,
+                                                      double *__restrict__ grad_a, double *__restrict__ grad_b,
+                                                      double *__restrict__ grad_k, int tiles_x) {
+    constexpr int W1 = TW + 2, H1 = TH + 2;
+    __shared__ T nus[kQ][H1][W1];
     const int N = a.N, P = a.pitch;
     const int plane = static_cast<int>(a.plane);
-    const int j = blockIdx.x / row_blocks;
-    const int i = (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int n = j * P + i;
-    const unsigned m = a.mask[n];
-    if (m & kMaskSolid) {
+    const int x0 = (blockIdx.x % tiles_x) * TW, y0 = (blockIdx.x / tiles_x) * TH;
+    for (int r = threadIdx.x; r < W1 * H1; r += NT) {
+        const int lx = r % W1, ly = r / W1;
+        const int i = x0 - 1 + lx, j = y0 - 1 + ly;
+        T nu[kQ];
+        if (i < 0 || j < 0 || i >= N || j >= N) {
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
-        return;
-    }
-#pragma unroll
-    for (int p = 0; p < kQ; ++p) {
-        T acc = T(0);
-        const int xi = i + kCx[p], xj = j + kCy[p];
-        if (xi >= 0 && xi < N && xj >= 0 && xj < N) {
-            const int x = xj * P + xi;
-            if (!(a.mask[x] & kMaskSolid)) acc += nu[p * plane + x];
+            for (int q = 0; q < kQ; ++q) nu[q] = T(0);
+        } else {
+            const bool owner = lx >= 1 && lx <= TW && ly >= 1 && ly <= TH;
+            adj_nu<T>(a, i, j, snext, lam, owner, grad_a, grad_b, grad_k, nu);
         }
-        const int q = kOpp[p];
-        if ((m >> q) & 1u) acc += nu[q * plane + n];
-        out[p * plane + n] = acc;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = nu[q];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < TW * TH; r += NT) {
+        const int lx = 1 + r % TW, ly = 1 + r / TW;
+        const int i = x0 + lx - 1, j = y0 + ly - 1;
+        if (i >= N || j >= N) continue;
+        const int n = j * P + i;
+        const unsigned m = a.mask[n];
+        if (m & kMaskSolid) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+            continue;
+        }
+#pragma unroll
+        for (int p = 0; p < kQ; ++p) {
+            T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
+            const int q = kOpp[p];
+            if ((m >> q) & 1u) acc += nus[q][ly][lx];
+            out[p * plane + n] = acc;
+        }
     }
 }
 
@@ -169,14 +192,13 @@ __global__ void __launch_bounds__(256) adj_unpack_kernel(LbmArgs a, const T *__r
 }
 
 template <typename T>
-hipError_t adjoint_step_impl(const LbmArgs &a, const void *snext, const void *lam, void *nu, void *out,
-                             double *grad_a, double *grad_b, double *grad_k, hipStream_t s) {
-    const int rb = (a.N + 255) / 256;
-    const dim3 grid(a.N * rb), block(256);
-    hipLaunchKernelGGL(adj_local_kernel<T>, grid, block, 0, s, a, static_cast<const T *>(snext),
-                       static_cast<const T *>(lam), static_cast<T *>(nu), grad_a, grad_b, grad_k, rb);
-    hipLaunchKernelGGL(adj_stream_kernel<T>, grid, block, 0, s, a, static_cast<const T *>(nu), static_cast<T *>(out),
-                       rb);
+hipError_t adjoint_step_impl(const LbmArgs &a, const void *snext, const void *lam, void *out, double *grad_a,
+                             double *grad_b, double *grad_k, hipStream_t s) {
+    constexpr int TW = 64, TH = 8, NT = 256;
+    const int tiles_x = (a.N + TW - 1) / TW, tiles_y = (a.N + TH - 1) / TH;
+    hipLaunchKernelGGL((adj_step_kernel<T, TW, TH, NT>), dim3(tiles_x * tiles_y), dim3(NT), 0, s, a,
+                       static_cast<const T *>(snext), static_cast<const T *>(lam), static_cast<T *>(out), grad_a,
+                       grad_b, grad_k, tiles_x);
     return hipGetLastError();
 }
 
@@ -184,8 +206,9 @@ hipError_t adjoint_step_impl(const LbmArgs &a, const void *snext, const void *la
 
 hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
                                double *grad_a, double *grad_b, double *grad_k, hipStream_t s) {
-    if (prec == HYB_FP64) return adjoint_step_impl<double>(a, snext, lam, nu, out, grad_a, grad_b, grad_k, s);
-    return adjoint_step_impl<float>(a, snext, lam, nu, out, grad_a, grad_b, grad_k, s);
+    (void)nu;    // scratch of the two-kernel form; the fused kernel keeps nu in LDS
+    if (prec == HYB_FP64) return adjoint_step_impl<double>(a, snext, lam, out, grad_a, grad_b, grad_k, s);
+    return adjoint_step_impl<float>(a, snext, lam, out, grad_a, grad_b, grad_k, s);
 }
 
 hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,
