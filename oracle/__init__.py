@@ -32,7 +32,8 @@ c_void_p = ctypes.c_void_p
 class OrcLattice(ctypes.Structure):
     _fields_ = [("N", c_int), ("periodic_x", c_int), ("periodic_y", c_int),
                 ("tau", c_double), ("solid", c_void_p), ("vx", c_void_p), ("vy", c_void_p),
-                ("k", c_void_p), ("kval", c_double), ("bc_kind", c_void_p), ("clamp", c_int)]
+                ("k", c_void_p), ("kval", c_double), ("bc_kind", c_void_p), ("clamp", c_int),
+                ("kappa_s", c_double), ("c_sat", c_double)]
 
 
 def lib():
@@ -143,7 +144,7 @@ class Lattice:
     """An N x N D2Q9 lattice with its fields (all FP64 on the host)."""
 
     def __init__(self, N, tau, vx, vy, solid=None, k=0.0, bc_kind=None,
-                 periodic_x=False, periodic_y=False, clamp=False):
+                 periodic_x=False, periodic_y=False, clamp=False, kappa_s=0.0, c_sat=0.0):
         self.N = int(N)
         self.tau = float(tau)
         self.vx = _f64(vx).reshape(N, N)
@@ -156,7 +157,8 @@ class Lattice:
         self.bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, dtype=np.int8)
         self.s = OrcLattice(self.N, int(periodic_x), int(periodic_y), self.tau, _p(self.solid),
                             _p(self.vx), _p(self.vy), _p(self.kfield), self.kval, _p(self.bc_kind),
-                            int(clamp))
+                            int(clamp), float(kappa_s), float(c_sat))
+        self.kappa_s, self.c_sat = float(kappa_s), float(c_sat)
 
     @property
     def ptr(self):

@@ -72,6 +72,8 @@ typedef struct {
     double kval;                 /* uniform reaction rate when k == NULL */
     const int8_t *bc_kind;       /* [4(N-1)] 0 Dirichlet, 1 Neumann, or NULL (all Dirichlet) */
     int clamp;                   /* Dirichlet closure: 0 as printed, 1 clamp unknowns at 0 */
+    double kappa_s;              /* surface reaction at fluid-solid links (0: plain bounce-back) */
+    double c_sat;                /* concentration the surface reaction drives towards */
 } orc_lattice;
 
 static int is_solid(const orc_lattice *L, int n) { return L->solid && L->solid[n]; }
@@ -126,8 +128,12 @@ void orc_lbm_init(const orc_lattice *L, const double *u0, double *fstar) {
 /* Streaming, eq. (LBE), written as a pull: the population arriving at x     */
 /* along e_i left x - e_i one step earlier.  A source that is a solid node   */
 /* returns the population that x itself sent towards it (halfway bounce-    */
-/* back).  A source outside the patch (non-periodic edge) leaves f_i unknown */
-/* and flags it in unknown[n] (bit i).                                      */
+/* back); with a surface reaction of rate kappa_s at that link, the         */
+/* returned population relaxes towards w_i c_sat:                           */
+/*   f_i(x) = (1 - kappa_s) f*_opp(i)(x) + kappa_s w_i c_sat                */
+/* (the link adds kappa_s (w_i c_sat - f*_opp(i)(x)) to the fluid).  A      */
+/* source outside the patch (non-periodic edge) leaves f_i unknown and      */
+/* flags it in unknown[n] (bit i).                                          */
 /* ------------------------------------------------------------------------ */
 void orc_stream(const orc_lattice *L, const double *fstar, double *f, uint16_t *unknown) {
     int N = L->N;
@@ -156,7 +162,9 @@ void orc_stream(const orc_lattice *L, const double *fstar, double *f, uint16_t *
                 }
                 int s = sj * N + si;
                 if (is_solid(L, s))
-                    f[q * NN + n] = fstar[OPP[q] * NN + n];
+                    f[q * NN + n] = L->kappa_s == 0.0 ? fstar[OPP[q] * NN + n]
+                                                      : (1.0 - L->kappa_s) * fstar[OPP[q] * NN + n] +
+                                                            L->kappa_s * WT[q] * L->c_sat;
                 else
                     f[q * NN + n] = fstar[q * NN + s];
             }
@@ -356,7 +364,8 @@ double orc_h_function(const orc_lattice *L, const double *f) {
 /*     closure is clamped at zero (clamp != 0 and R < 0) the unknowns are   */
 /*     constant and G = 0;                                                  */
 /*   streaming (pull, halfway bounce-back): each dJ/df_i(x) goes back to the */
-/*     population it was copied from.                                        */
+/*     population it was copied from (times 1 - kappa_s across a reactive   */
+/*     link).                                                                */
 /* The forward pre-collision field and every closure's R are recomputed    */
 /* from fsrc.  Neumann slots are not supported (returns -1).                */
 /* ------------------------------------------------------------------------ */
@@ -426,7 +435,7 @@ int orc_lbm_adjoint_substep(const orc_lattice *L, const double *fsrc, const doub
                 if (si < 0 || si >= N) si = (si + N) % N;    /* only reached when periodic */
                 if (sj < 0 || sj >= N) sj = (sj + N) % N;
                 int s = sj * N + si;
-                if (is_solid(L, s)) lam_out[OPP[q] * NN + n] += lf[q * NN + n];
+                if (is_solid(L, s)) lam_out[OPP[q] * NN + n] += (1.0 - L->kappa_s) * lf[q * NN + n];
                 else lam_out[q * NN + s] += lf[q * NN + n];
             }
         }
