@@ -75,7 +75,7 @@ def convert(fstar, solid, mass, flux, kfield):
             xi, xj = i + ex[q], j + ey[q]
             if 0 <= xi < N and 0 <= xj < N and not sol[xj, xi]:
                 vals.append(u[xj, xi])
-        ubar = float(np.mean(vals)) if vals else 0.0
+        ubar = sum(vals) / len(vals) if vals else 0.0
         f[:, j, i] = np.asarray(w) * ubar * (1.0 - kfield[j, i])
     new_solid = sol & ~conv
     m[conv] = 0.0
@@ -113,8 +113,12 @@ class DissolvingHybrid(HybridOracle):
 
     def _rebuild(self):
         cfg = self.p.cfg
-        self.lat = Lattice(self.N, cfg.tau_value, self.p.vx.astype(np.float64), self.p.vy.astype(np.float64),
-                           solid=self.solid, k=cfg.k, clamp=cfg.bc_clamp, kappa_s=self.kappa_s, c_sat=self.c_sat)
+        # advection is zero wherever a solid stood initially (and stays so)
+        sol0 = np.asarray(self.p.solid) != 0
+        vx = np.where(sol0, 0.0, self.p.vx.astype(np.float64))
+        vy = np.where(sol0, 0.0, self.p.vy.astype(np.float64))
+        self.lat = Lattice(self.N, cfg.tau_value, vx, vy, solid=self.solid, k=cfg.k, clamp=cfg.bc_clamp,
+                           kappa_s=self.kappa_s, c_sat=self.c_sat)
 
     def fine_to_coarse(self, fstar):
         u = self.lat.concentration(fstar).reshape(-1)
