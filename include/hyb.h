@@ -96,6 +96,8 @@ typedef struct {
     void *f_buf[3];         /* device population buffers, each >= f_bytes */
     void *workspace;        /* device workspace, >= ws_bytes */
     void *stream;           /* hipStream_t for all work; NULL = default stream */
+    int dissolution;        /* 1: reserve the workspace of dissolving solids
+                               (hyb_set_dissolution); 0: solids are fixed */
 } hyb_lattice;
 
 /* Advection velocity (divergence-free in the continuum, eq. AD). */
@@ -297,6 +299,41 @@ int hyb_set_steps_per_launch(hyb_handle *h, int steps);
  * call, and synchronises. */
 int hyb_kernel_timing(hyb_handle *h, int enable);
 int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches);
+
+/* ---- dissolving solids ---------------------------------------------------
+ *
+ * An extension of the pore-scale setting of Sec. 7.4, whose solids stay
+ * fixed: each solid node holds a mass, and the halfway bounce-back of
+ * Sec. 4.1 carries a first-order surface reaction.  A population returned
+ * across a fluid-solid link relaxes towards w_q c_sat,
+ *   f_q(x) = (1 - kappa_s) f*_opp(q)(x) + kappa_s w_q c_sat,
+ * and the link moves kappa_s (w_q c_sat - f*_opp(q)(x)) into the fluid,
+ * taken from the solid node.  The geometry is frozen within a coarse step:
+ * every Schwarz pass sums the link fluxes of its fine steps per solid node,
+ * and the commit debits the last pass's sums from the masses.  A solid
+ * whose mass is then <= 0 becomes fluid with f*_q = w_q u_mean (1 - k),
+ * u_mean the mean concentration of its fluid neighbours (8-neighbourhood,
+ * before the commit), at zero velocity.  With the workspace reserved
+ * (hyb_lattice.dissolution = 1) the fine-to-coarse transfer (Sec. 6.2 item
+ * ii) weights the current fluid corners, sum w_m u_m / sum w_m over the
+ * fluid ones; a coarse node none of whose fluid corners carries weight
+ * keeps the nearest fluid node of the initial geometry.  Fine steps run as
+ * single-step launches while the reaction is on.
+ *
+ * hyb_set_dissolution: reaction rate 0 <= kappa_s <= 1 (0 switches the
+ *   reaction and the mass bookkeeping off), c_sat finite, mass host FP64
+ *   [N*N] (index j*N + i, read at solid nodes; NULL keeps the current
+ *   masses, 0 after hyb_create).  Only between coarse steps (no fine steps
+ *   pending); HYB_EINVAL without the reserved workspace.  Synchronises.
+ * hyb_dissolution_state: current solid flags (host u8 [N*N]), masses (host
+ *   FP64 [N*N], 0 at fluid nodes) and the number of solids converted since
+ *   hyb_create; each output may be NULL.  Synchronises.
+ * The whole-step adjoint (hyb_step_record) is not available on a handle
+ * with the reserved workspace; the fine-step adjoint is (its bounce-back
+ * carries the factor 1 - kappa_s; the recorded steps also sum the link
+ * fluxes). */
+int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const double *mass);
+int hyb_dissolution_state(hyb_handle *h, uint8_t *solid, double *mass, int64_t *converted);
 
 /* Storage layout actually used: row pitch and plane stride in elements. */
 int hyb_layout(const hyb_handle *h, size_t *pitch, size_t *plane);

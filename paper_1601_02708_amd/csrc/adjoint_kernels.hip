@@ -86,8 +86,13 @@ __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 if ((unknown >> q) & 1u) continue;
-                known += double((m >> q) & 1u ? src[kOpp[q] * plane + n]
-                                              : src[q * plane + (j - kCy[q]) * P + i - kCx[q]]);
+                if ((m >> q) & 1u) {
+                    // bounce-back, relaxed towards w_q c_sat across a reactive link
+                    const double b = double(src[kOpp[q] * plane + n]);
+                    known += a.kappa_s == 0.0 ? b : (1.0 - a.kappa_s) * b + a.kappa_s * kW[q] * a.c_sat;
+                } else {
+                    known += double(src[q * plane + (j - kCy[q]) * P + i - kCx[q]]);
+                }
             }
             active = !((1.0 - a.lam) * a.bc_a[p] + a.lam * a.bc_b[p] - known < 0.0);
         }
@@ -114,8 +119,9 @@ __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *
 // One reversed fine step.  Phase 1: nu for the tile grown by one ring (0
 // outside the patch and at solid nodes), into LDS.  Phase 2, per owned
 // fluid node y: dJ/df*_p(y) = nu_p(y + e_p) (zero when y + e_p is solid or
-// outside: it pulled nothing from y) + nu_q(y), q = opp(p), when y bounced
-// back along q.
+// outside: it pulled nothing from y) + (1 - kappa_s) nu_q(y), q = opp(p),
+// when y bounced back along q (kappa_s: surface reaction of dissolving
+// solids, 0 when off).
 template <typename T, int TW, int TH, int NT>
 __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__restrict__ snext,
                                                       const T *__restrict__ lam, T *__restrict__ out,
@@ -152,11 +158,13 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
             for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
             continue;
         }
+        // a reactive link returns 1 - kappa_s of the population (1 when off)
+        const T keep = T(1.0 - a.kappa_s);
 #pragma unroll
         for (int p = 0; p < kQ; ++p) {
             T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
             const int q = kOpp[p];
-            if ((m >> q) & 1u) acc += nus[q][ly][lx];
+            if ((m >> q) & 1u) acc += keep * nus[q][ly][lx];
             out[p * plane + n] = acc;
         }
     }

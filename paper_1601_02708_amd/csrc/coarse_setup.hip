@@ -303,6 +303,9 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
     const int nfc = (int)out.fc_nodes.size();
     out.fc_idx.assign((size_t)4 * nfc, 0);
     out.fc_w.assign((size_t)4 * nfc, 0.0);
+    out.fcr_idx.assign((size_t)4 * nfc, 0);
+    out.fcr_w.assign((size_t)4 * nfc, 0.0);
+    out.fcr_fb.assign((size_t)nfc, -1);
     auto is_solid = [&](int i, int j) { return solid && solid[(size_t)j * N + i]; };
     for (int c = 0; c < nfc; ++c) {
         const int id = out.fc_nodes[c];
@@ -314,8 +317,11 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
         const int ci[4] = {i0, i0 + 1, i0 + 1, i0}, cj[4] = {j0, j0, j0 + 1, j0 + 1};
         const double cw[4] = {(1 - gx) * (1 - gy), gx * (1 - gy), gx * gy, (1 - gx) * gy};
         double wsum = 0.0;
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m) {
             if (!is_solid(ci[m], cj[m])) wsum += cw[m];
+            out.fcr_idx[4 * c + m] = cj[m] * pitch + ci[m];
+            out.fcr_w[4 * c + m] = cw[m];
+        }
         if (wsum > 0.0) {
             for (int m = 0; m < 4; ++m) {
                 out.fc_idx[4 * c + m] = cj[m] * pitch + ci[m];
@@ -343,6 +349,7 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
         if (best < 0) return "fine-to-coarse transfer: no fluid lattice node";
         out.fc_idx[4 * c] = (best / N) * pitch + (best % N);
         out.fc_w[4 * c] = 1.0;
+        out.fcr_fb[c] = out.fc_idx[4 * c];
         for (int m = 1; m < 4; ++m) {
             out.fc_idx[4 * c + m] = out.fc_idx[4 * c];
             out.fc_w[4 * c + m] = 0.0;

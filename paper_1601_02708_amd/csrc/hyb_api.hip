@@ -81,6 +81,10 @@ struct Layout {
     size_t counters = 0, barrier = 0, kres = 0, total = 0;
     size_t APT = 0, PT = 0, c2fT_ptr = 0, c2fT_slot = 0, c2fT_w = 0, f2cT_node = 0, f2cT_ptr = 0, f2cT_c = 0;
     size_t f2cT_w = 0, fc_row = 0;
+    // dissolving solids (hyb_lattice.dissolution): per-node mass, link flux
+    // and solid flag; raw fine-to-coarse corners and fallbacks
+    bool dissolve = false;
+    size_t mass = 0, flux = 0, solid_now = 0, fcr_idx = 0, fcr_w = 0, fcr_fb = 0;
     int n = 0, S = 0, grid = 0;
     size_t vec_len = 0;
 };
@@ -109,6 +113,12 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
     L.bc_b = take(nslots * 8);
     L.counters = take(kCntSlots * 8);
     L.kres = take(sizeof(KrylovResult));
+    if (lat->dissolution) {
+        L.dissolve = true;
+        L.mass = take(nodes * 8);
+        L.flux = take(nodes * 8);
+        L.solid_now = take(nodes);
+    }
     if (mesh) {
         const int M = mesh->M;
         L.n = (M + 1) * (M + 1);
@@ -140,6 +150,11 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
         L.f2cT_c = take((size_t)L.n * 4 * 4);
         L.f2cT_w = take((size_t)L.n * 4 * 8);
         L.fc_row = take((size_t)L.n * 4);
+        if (L.dissolve) {
+            L.fcr_idx = take((size_t)L.n * 4 * 4);
+            L.fcr_w = take((size_t)L.n * 4 * 8);
+            L.fcr_fb = take((size_t)L.n * 4);
+        }
     }
     L.total = off;
     return L;
@@ -183,6 +198,15 @@ struct hyb_handle {
     int f2cT_n = 0;
     const void *rec_step_tape = nullptr;    // last hyb_step_record
     int rec_step_passes = 0;
+    // dissolving solids: workspace reserved (dissolve_ws), reaction on
+    // (dissolve_on, from hyb_set_dissolution); flux_valid: the fine steps
+    // since the last commit summed the link fluxes of the current pass
+    bool dissolve_ws = false, dissolve_on = false, flux_valid = false, solid_host_stale = false;
+    double kappa_s = 0.0, c_sat = 0.0;
+    double *mass = nullptr, *flux = nullptr;
+    uint8_t *solid_now = nullptr;
+    int *fcr_idx = nullptr, *fcr_fb = nullptr;
+    double *fcr_w = nullptr;
     CoarseDev cd{};
     unsigned long long *counters = nullptr;
     KrylovResult *kres = nullptr;
@@ -265,6 +289,10 @@ struct hyb_handle {
         a.hs_scale = hs_scale;
         a.hs_inv = hs_inv;
         for (int q = 0; q < kQ; ++q) a.hs_wc[q] = (float)kW[q] * hs_cref;
+        a.kappa_s = dissolve_on ? kappa_s : 0.0;
+        a.c_sat = c_sat;
+        a.flux = nullptr;
+        a.flux_first = 0;
         return a;
     }
     // buffer that is neither the committed state nor `a`
@@ -385,6 +413,8 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
                 if (i == 0 || j == 0 || i == N - 1 || j == N - 1)
                     return bail(HYB_EINVAL, "solid nodes on the lattice perimeter are not supported");
                 m = kMaskSolid;
+                for (int q = 1; q < kQ; ++q)
+                    if (!solid(i + kCx[q], j + kCy[q])) m |= (uint16_t)(1u << q);
             } else {
                 for (int q = 1; q < kQ; ++q) {
                     const int si = i - kCx[q], sj = j - kCy[q];
@@ -409,6 +439,12 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     h->bc_b = reinterpret_cast<double *>(h->ws + L.bc_b);
     h->counters = reinterpret_cast<unsigned long long *>(h->ws + L.counters);
     h->kres = reinterpret_cast<KrylovResult *>(h->ws + L.kres);
+    if (L.dissolve) {
+        h->dissolve_ws = true;
+        h->mass = reinterpret_cast<double *>(h->ws + L.mass);
+        h->flux = reinterpret_cast<double *>(h->ws + L.flux);
+        h->solid_now = reinterpret_cast<uint8_t *>(h->ws + L.solid_now);
+    }
     hipStream_t st = h->stream;
     auto up = [&](void *dst, const void *src, size_t bytes) {
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
@@ -423,6 +459,13 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     CREATE_TRY(up(h->mask, mask.data(), nodes * 2));
     CREATE_TRY(up(h->vx, vxh.data(), nodes * 4));
     CREATE_TRY(up(h->vy, vyh.data(), nodes * 4));
+    std::vector<uint8_t> solid_pitched;
+    if (h->dissolve_ws) {
+        solid_pitched.assign(nodes, 0);
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) solid_pitched[(size_t)j * P + i] = h->solid_host[(size_t)j * N + i];
+        CREATE_TRY(up(h->solid_now, solid_pitched.data(), nodes));
+    }
     if (h->has_kfield) {
         if (h->fp64) {
             std::vector<double> kf(nodes, 0.0);
@@ -521,6 +564,16 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
             CREATE_TRY(up(h->f2cT_w, ch.f2cT_w.data(), ch.f2cT_w.size() * 8));
         }
         if (h->nfc) CREATE_TRY(up(h->fc_row, ch.fc_nodes.data(), ch.fc_nodes.size() * 4));
+        if (h->dissolve_ws) {
+            h->fcr_idx = reinterpret_cast<int *>(h->ws + L.fcr_idx);
+            h->fcr_w = reinterpret_cast<double *>(h->ws + L.fcr_w);
+            h->fcr_fb = reinterpret_cast<int *>(h->ws + L.fcr_fb);
+            if (h->nfc) {
+                CREATE_TRY(up(h->fcr_idx, ch.fcr_idx.data(), ch.fcr_idx.size() * 4));
+                CREATE_TRY(up(h->fcr_w, ch.fcr_w.data(), ch.fcr_w.size() * 8));
+                CREATE_TRY(up(h->fcr_fb, ch.fcr_fb.data(), ch.fcr_fb.size() * 4));
+            }
+        }
         std::vector<double> xp(L.vec_len, 0.0);
         const int m1 = mesh->M + 1;
         for (int l = 0; l < m1; ++l)
@@ -554,7 +607,10 @@ int hyb_interface_exchange(hyb_handle *h, int direction) {
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "interface exchange needs a coarse mesh");
     if (direction == HYB_F2C) {
         LbmArgs a = h->lbm_args(h->cur, -1);
-        HIP_TRY(h, launch_f2c(a, h->fc_idx, h->fc_w, h->nfc, h->ufc, h->prec, h->stream));
+        if (h->dissolve_ws)
+            HIP_TRY(h, launch_f2c_dynamic(a, h->fcr_idx, h->fcr_w, h->fcr_fb, h->nfc, h->ufc, h->prec, h->stream));
+        else
+            HIP_TRY(h, launch_f2c(a, h->fc_idx, h->fc_w, h->nfc, h->ufc, h->prec, h->stream));
     } else if (direction == HYB_C2F) {
         const double *xb = h->solved_this_step ? h->cd.x1 : h->cd.xn;
         HIP_TRY(h, launch_c2f(h->c2f_idx, h->c2f_w, 4 * (h->N - 1), h->cd.xn, xb, h->bc_a, h->bc_b, h->stream));
@@ -590,10 +646,27 @@ int hyb_coarse_step(hyb_handle *h, int max_iter) {
 namespace {
 
 // the two-step kernel addresses a population buffer with 32-bit byte
-// offsets, so it serves buffers below 4 GiB (N up to about 11500 in FP64)
+// offsets, so it serves buffers below 4 GiB (N up to about 11500 in FP64);
+// with dissolving solids every fine step sums its link fluxes, which the
+// single-step sweep does
 bool use_two_step(const hyb_handle *h) {
     const bool small_buf = 9.0 * (double)h->lay.plane * (double)storage_bytes(h->prec) < 4294967295.0;
-    return !h->any_neumann && h->steps_per_launch == 2 && small_buf;
+    return !h->any_neumann && h->steps_per_launch == 2 && small_buf && !h->dissolve_on;
+}
+
+// the host copy of the solid flags after commits that may have converted
+// solids (waits for the stream)
+hipError_t refresh_solid_host(hyb_handle *h) {
+    if (!h->solid_host_stale) return hipSuccess;
+    const int N = h->N, P = h->lay.pitch;
+    std::vector<uint8_t> pitched((size_t)N * P);
+    hipError_t e = hipMemcpyAsync(pitched.data(), h->solid_now, pitched.size(), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) h->solid_host[(size_t)j * N + i] = pitched[(size_t)j * P + i];
+    h->solid_host_stale = false;
+    return hipSuccess;
 }
 
 // n_sub fine steps.  first_dst >= 0 (with restart): destination of the first
@@ -644,6 +717,12 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, int deep
                         : h->cur == h->frozen ? h->spare(-1) : h->spare(h->cur);
         LbmArgs a = h->lbm_args(h->cur, dst);
         a.lam = (double)(h->jsub + 1) / (double)h->eta;
+        if (h->dissolve_on) {
+            // the pass's first step starts the sums of its link fluxes
+            a.flux = h->flux;
+            a.flux_first = h->jsub == 0;
+            h->flux_valid = true;
+        }
         const int take = (fuse2 && n_sub - s >= 2) ? 2 : 1;
         const bool split_now = launch < deep;
         if (split_now && take != 2) return h->fail(HYB_EINVAL, "internal: split launch is not a two-step launch");
@@ -761,6 +840,14 @@ int hyb_commit(hyb_handle *h) {
     }
     h->frozen = h->cur;
     h->jsub = 0;
+    if (h->dissolve_on && h->flux_valid) {
+        // the last pass's link fluxes debit the solids; exhausted ones turn fluid
+        LbmArgs a = h->lbm_args(h->frozen, h->frozen);
+        a.flux = h->flux;
+        HIP_TRY(h, launch_dissolve_commit(a, h->prec, h->mass, h->solid_now, h->mask, h->stream));
+        h->solid_host_stale = true;
+    }
+    h->flux_valid = false;
     if (h->solved_this_step) {
         // d(t_{n-1}) <- d(t_n) <- new solution; the old d(t_{n-1}) buffer is free
         double *old_prev = h->cd.xprev;
@@ -875,6 +962,7 @@ int hyb_concentration(hyb_handle *h, int which, double *out, int out_is_device) 
 
 int hyb_get_populations(hyb_handle *h, double *out) {
     if (!h || !out) return HYB_EINVAL;
+    if (refresh_solid_host(h) != hipSuccess) return h->fail(HYB_EHIP, "could not read the solid flags");
     const int N = h->N, P = h->lay.pitch;
     const size_t elem = storage_bytes(h->prec);
     std::vector<char> stage((size_t)9 * h->lay.plane * elem);
@@ -977,6 +1065,11 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
         a.src = slot(t);
         a.dst = slot(t + 1);
         a.lam = (double)(t + 1) / (double)h->eta;
+        if (h->dissolve_on) {
+            a.flux = h->flux;
+            a.flux_first = t == 0;
+            h->flux_valid = true;
+        }
         HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
     }
     const int dst = h->spare(-1);
@@ -1047,6 +1140,7 @@ int step_adjoint_supported(hyb_handle *h) {
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "the step adjoint needs a coarse mesh");
     if (h->prec == HYB_FP16S) return h->fail(HYB_EINVAL, "the adjoint supports HYB_FP64 and HYB_FP32 storage");
     if (h->any_neumann) return h->fail(HYB_EINVAL, "the adjoint supports Dirichlet perimeter slots only");
+    if (h->dissolve_ws) return h->fail(HYB_EINVAL, "the step adjoint does not support dissolving solids");
     return HYB_OK;
 }
 
@@ -1229,5 +1323,56 @@ int hyb_layout(const hyb_handle *h, size_t *pitch, size_t *plane) {
 void hyb_destroy(hyb_handle *h) { delete h; }
 
 const char *hyb_last_error(const hyb_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const double *mass) {
+    if (!h) return HYB_EINVAL;
+    if (!h->dissolve_ws) return h->fail(HYB_EINVAL, "the handle was created without dissolution");
+    if (!(kappa_s >= 0.0 && kappa_s <= 1.0)) return h->fail(HYB_EINVAL, "kappa_s must lie in [0, 1]");
+    if (!std::isfinite(c_sat)) return h->fail(HYB_EINVAL, "c_sat must be finite");
+    if (h->jsub != 0 || h->cur != h->frozen)
+        return h->fail(HYB_EINVAL, "set the dissolution between coarse steps (fine steps are pending)");
+    if (refresh_solid_host(h) != hipSuccess) return h->fail(HYB_EHIP, "could not read the solid flags");
+    if (mass) {
+        const int N = h->N, P = h->lay.pitch;
+        std::vector<double> mp((size_t)N * P, 0.0);
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i)
+                if (h->solid_host[(size_t)j * N + i]) mp[(size_t)j * P + i] = mass[(size_t)j * N + i];
+        HIP_TRY(h, hipMemcpyAsync(h->mass, mp.data(), mp.size() * 8, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    h->kappa_s = kappa_s;
+    h->c_sat = c_sat;
+    h->dissolve_on = kappa_s > 0.0;
+    h->flux_valid = false;
+    // the sweep changes (single-step launches), so the overlap depth is tuned again
+    h->tune_idx = 0;
+    h->tuned_depth = -1;
+    h->tune_ms.clear();
+    return HYB_OK;
+}
+
+int hyb_dissolution_state(hyb_handle *h, uint8_t *solid, double *mass, int64_t *converted) {
+    if (!h) return HYB_EINVAL;
+    if (!h->dissolve_ws) return h->fail(HYB_EINVAL, "the handle was created without dissolution");
+    if (refresh_solid_host(h) != hipSuccess) return h->fail(HYB_EHIP, "could not read the solid flags");
+    const int N = h->N, P = h->lay.pitch;
+    if (solid) std::memcpy(solid, h->solid_host.data(), (size_t)N * N);
+    if (mass) {
+        std::vector<double> mp((size_t)N * P);
+        HIP_TRY(h, hipMemcpyAsync(mp.data(), h->mass, mp.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i)
+                mass[(size_t)j * N + i] = h->solid_host[(size_t)j * N + i] ? mp[(size_t)j * P + i] : 0.0;
+    }
+    if (converted) {
+        unsigned long long cnt[kCntSlots];
+        HIP_TRY(h, hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        *converted = (int64_t)cnt[kCntConverted];
+    }
+    return HYB_OK;
+}
 
 }  // extern "C"

@@ -23,13 +23,14 @@ constexpr int kOpp[kQ] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr double kW[kQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
-// Per-node lattice flags (uint16): bit q (1..8) = the upstream neighbour
-// x - e_q is a solid node inside the patch (halfway bounce-back); bit 15 =
-// the node itself is solid.
+// Per-node lattice flags (uint16).  Fluid node: bit q (1..8) = the upstream
+// neighbour x - e_q is a solid node inside the patch (halfway bounce-back).
+// Solid node: bit 15, and bit q = the neighbour x + e_q is a fluid node (the
+// fluid end of a link whose population bounces back off this node).
 constexpr uint16_t kMaskSolid = 1u << 15;
 
 // Device error counters (uint64 slots in the workspace).
-enum Counter { kCntInfeasible = 0, kCntNonfinite = 1, kCntSlots = 8 };
+enum Counter { kCntInfeasible = 0, kCntNonfinite = 1, kCntConverted = 2, kCntSlots = 8 };
 
 // Scalars of the coarse BiCGSTAB shared between its kernels.
 struct KrylovState {
@@ -83,6 +84,16 @@ struct LbmArgs {
     float hs_scale;
     float hs_inv;
     float hs_wc[kQ];
+    // surface reaction at fluid-solid links (dissolving solids): the
+    // bounce-back value relaxes towards w_q c_sat at rate kappa_s (0: off)
+    double kappa_s;
+    double c_sat;
+    // dissolving solids: flux[n] (pitched, FP64) at every solid node with a
+    // fluid neighbour receives the mass its reactive links move into the
+    // fluid during the step (overwritten when flux_first, else added to);
+    // nullptr: not tracked
+    double *flux;
+    int flux_first;
 };
 
 // Population storage policy: FP64 and FP32 store what they compute; FP16
@@ -213,6 +224,23 @@ hipError_t launch_coarse_rhs_transpose(const CoarseDev &c, const int *fc_row, in
 hipError_t launch_f2c_transpose(const LbmArgs &lat, int prec, const int *node, const int *ptr, const int *cidx,
                                 const double *w, int ntouched, const double *lam_ufc, const void *g_state,
                                 void *lam_pitched, double *lam_dense, double *grad_k, hipStream_t s);
+// Dissolving solids (dissolve_kernels.hip), HYB_FP64 / FP32 / FP16S storage;
+// per-node arrays are pitched like the flag words.
+// Commit of the geometry: at every solid node mass -= a.flux (solid nodes
+// with a fluid neighbour; the others moved nothing); a node whose mass is
+// then <= 0 becomes fluid (solid[] cleared, counters[kCntConverted] counts
+// it) and takes f*_q = w_q u_mean (1 - k) in a.dst (the committed state),
+// u_mean the mean concentration of its fluid neighbours there (flag words
+// before the commit).  Then every flag word is rebuilt from solid[].
+hipError_t launch_dissolve_commit(const LbmArgs &a, int prec, double *mass, uint8_t *solid, uint16_t *mask,
+                                  hipStream_t s);
+// Fine-to-coarse transfer with the bilinear weights of the current fluid
+// corners: idx/w the four raw corners and weights of each Gamma_{f->c}
+// node, fb[c] its fallback node (-1: none) used when no fluid corner
+// carries weight.
+hipError_t launch_f2c_dynamic(const LbmArgs &lat, const int *idx, const double *w, const int *fb, int nfc,
+                              double *ufc, int prec, hipStream_t s);
+
 // dense[(M+1)^2] = padded (unpad), or padded = dense (pad, halo untouched)
 hipError_t launch_coarse_repad(const CoarseDev &c, const double *from, double *to, bool to_dense, hipStream_t s);
 
@@ -234,6 +262,11 @@ struct CoarseHost {
     // (CSR over nodes: slots and weights, in slot order); the fine-to-coarse
     // transfer transposed per lattice node it reads (CSR over the touched
     // pitched nodes: Gamma_{f->c} indices and nonzero weights, in index order)
+    // fine-to-coarse corners before the solid rule (dissolving solids):
+    // pitched corner nodes, raw bilinear weights, and the fallback node of a
+    // coarse node whose fluid corners carry no weight (-1 otherwise)
+    std::vector<int> fcr_idx, fcr_fb;
+    std::vector<double> fcr_w;
     std::vector<double> APT, PT;
     std::vector<int> c2fT_ptr, c2fT_slot;
     std::vector<double> c2fT_w;

@@ -116,6 +116,31 @@ __device__ __forceinline__ int xcd_tile(int b, int T) {
 // Single fine step
 // ---------------------------------------------------------------------------
 
+// Bounce-back value across a link to a solid node with the surface reaction
+// of dissolving solids: (1 - kappa_s) f + kappa_s w_q c_sat (f itself when
+// the reaction is off).
+template <typename T>
+__device__ __forceinline__ T reactive(const LbmArgs &a, T f, int q) {
+    if (a.kappa_s == 0.0) return f;
+    return T((1.0 - a.kappa_s) * double(f) + a.kappa_s * kW[q] * a.c_sat);
+}
+
+// Solid node n with fluid neighbours (flag bits q): the mass its reactive
+// links move into the fluid during this step, sum over q of
+// kappa_s (w_q c_sat - f*_opp(q)(n + e_q)), in q order, into a.flux[n].
+template <typename S>
+__device__ __forceinline__ void solid_link_flux(const LbmArgs &a, const S *__restrict__ src, unsigned m, int n,
+                                                int plane, int P) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 1; q < kQ; ++q)
+        if ((m >> q) & 1u) {
+            const int x = n + kCx[q] + kCy[q] * P;
+            s += a.kappa_s * (kW[q] * a.c_sat - double(Pop<S>::ld(src[kOpp[q] * plane + x], kOpp[q], a)));
+        }
+    a.flux[n] = a.flux_first ? s : a.flux[n] + s;
+}
+
 // Interior node (1 <= i, j <= N-2): every upstream node is inside the
 // patch.  The nine pulls are issued before the flag word is known;
 // bounce-back values replace them afterwards.  Stores are non-temporal: the
@@ -128,7 +153,10 @@ __device__ __forceinline__ void interior_node(const LbmArgs &a, const S *__restr
 #pragma unroll
     for (int q = 0; q < kQ; ++q) raw[q] = src[q * plane + n - kCx[q] - kCy[q] * P];
     const unsigned m = a.mask[n];
-    if (m & kMaskSolid) return;
+    if (m & kMaskSolid) {
+        if (a.flux && (m & 0x1FEu)) solid_link_flux<S>(a, src, m, n, plane, P);
+        return;
+    }
     const float vx = a.vx[n], vy = a.vy[n];
     T f[kQ];
 #pragma unroll
@@ -137,6 +165,11 @@ __device__ __forceinline__ void interior_node(const LbmArgs &a, const S *__restr
 #pragma unroll
         for (int q = 1; q < kQ; ++q)
             if ((m >> q) & 1u) f[q] = Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a);
+        if (a.kappa_s != 0.0) {
+#pragma unroll
+            for (int q = 1; q < kQ; ++q)
+                if ((m >> q) & 1u) f[q] = reactive<T>(a, f[q], q);
+        }
     }
     const T u = collide<T>(f, T(vx), T(vy), T(a.omega), node_k<T>(a, n));
     if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
@@ -160,7 +193,7 @@ __device__ __forceinline__ void perimeter_dirichlet_node(const LbmArgs &a, const
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         if ((unknown >> q) & 1u) f[q] = T(0);
-        else if ((m >> q) & 1u) f[q] = Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a);
+        else if ((m >> q) & 1u) f[q] = reactive<T>(a, Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a), q);
         else f[q] = Pop<S>::ld(src[q * plane + (j - kCy[q]) * P + i - kCx[q]], q, a);
     }
     if (dirichlet_close<T>(a, f, unknown, p, a.lam)) atomicAdd(&a.counters[kCntInfeasible], 1ull);
@@ -317,7 +350,7 @@ __global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
             unknown |= 1u << q;
             f[q] = 0.0;
         } else if ((m >> q) & 1u) {
-            f[q] = double(Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a));
+            f[q] = double(reactive<T>(a, Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a), q));
         } else {
             f[q] = double(Pop<S>::ld(src[q * plane + sj * P + si], q, a));
         }

@@ -35,7 +35,7 @@ class HybMesh(ctypes.Structure):
 class HybLattice(ctypes.Structure):
     _fields_ = [("N", _i), ("x0", _d), ("y0", _d), ("precision", _i), ("tau", _d), ("eta", _i),
                 ("bc_clamp", _i), ("solid", _P), ("u0", _P), ("f_buf", _P * 3), ("workspace", _P),
-                ("stream", _P)]
+                ("stream", _P), ("dissolution", _i)]
 
 
 class HybVelocity(ctypes.Structure):
@@ -74,6 +74,8 @@ SIGNATURES = {
     "hyb_step_record": (_i, [_P, _i, _P]),
     "hyb_step_adjoint": (_i, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "hyb_set_coarse": (_i, [_P, _P]),
+    "hyb_set_dissolution": (_i, [_P, _d, _d, _P]),
+    "hyb_dissolution_state": (_i, [_P, _P, _P, _P]),
     "hyb_set_overlap": (_i, [_P, _i]),
     "hyb_set_steps_per_launch": (_i, [_P, _i]),
     "hyb_kernel_timing": (_i, [_P, _i]),
@@ -115,7 +117,7 @@ class Hybrid:
     coarse mesh around it.  Arrays follow include/hyb.h."""
 
     def __init__(self, *, N, x0, y0, u0, vx, vy, D, eta, precision="fp64", tau=0.0, solid=None,
-                 k=0.0, k_field=None, bc_clamp=0, mesh=None, device=None):
+                 k=0.0, k_field=None, bc_clamp=0, mesh=None, device=None, dissolution=False):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -147,6 +149,7 @@ class Hybrid:
         self.lat.bc_clamp = int(bc_clamp)
         self.lat.solid = _ptr(solidh)
         self.lat.u0 = _ptr(u0h)
+        self.lat.dissolution = int(bool(dissolution))
         self.meshs = None
         vc = None
         if mesh is not None:
@@ -273,6 +276,23 @@ class Hybrid:
         if d.size != (self.M + 1) ** 2:
             raise ValueError("coarse state must have (M+1)^2 entries")
         return self._check(load().hyb_set_coarse(self.h, _ptr(d)))
+
+    # -- dissolving solids ---------------------------------------------------
+    def set_dissolution(self, kappa_s, c_sat, mass=None):
+        """Surface reaction rate and saturation concentration at fluid-solid
+        links, and the solid masses (host [N, N], read at solid nodes)."""
+        m = None if mass is None else np.ascontiguousarray(mass, dtype=np.float64).reshape(-1)
+        if m is not None and m.size != self.N * self.N:
+            raise ValueError("mass must have N*N entries")
+        return self._check(load().hyb_set_dissolution(self.h, float(kappa_s), float(c_sat), _ptr(m)))
+
+    def dissolution_state(self):
+        """(solid flags [N, N] uint8, masses [N, N], solids converted so far)."""
+        sol = np.empty((self.N, self.N), np.uint8)
+        mass = np.empty((self.N, self.N), np.float64)
+        conv = ctypes.c_int64()
+        self._check(load().hyb_dissolution_state(self.h, _ptr(sol), _ptr(mass), ctypes.addressof(conv)))
+        return sol, mass, conv.value
 
     # -- reverse mode -------------------------------------------------------
     def adjoint_tape(self, n_sub):

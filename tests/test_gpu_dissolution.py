@@ -1,0 +1,184 @@
+"""Dissolving solids on the GPU (C ABI hyb_set_dissolution /
+hyb_dissolution_state and hyb_lattice.dissolution) against the oracle's
+DissolvingHybrid on the same seeded problem: populations, coarse solution,
+solid set, masses and converted count after every coarse step; the reactive
+fine-step adjoint against the oracle's; the reduction to fixed solids; the
+rejected calls; invariants at the full pore-scale size."""
+import numpy as np
+import pytest
+
+from paper_1601_02708_amd import configs, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_02708_amd import hyb
+    return hyb, torch
+
+
+def _rel(x, y):
+    return float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+
+
+@pytest.mark.parametrize("over,precision,steps,tol", [
+    ({"N": 65, "M": 16, "eta": 3}, "fp64", 4, 1e-12),
+    ({"N": 257, "M": 32, "eta": 4}, "fp64", 2, 1e-12),
+    ({"N": 65, "M": 16, "eta": 3}, "fp32", 3, 2e-5),
+])
+def test_dissolution_matches_oracle(orc, over, precision, steps, tol):
+    from oracle.dissolution import DissolvingHybrid
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE2048.replace(**over))
+    N, P = p.cfg.N, p.cfg.max_iter
+    mass = np.random.default_rng(7).uniform(0.002, 0.01, (N, N))
+    kappa, c_sat = 0.2, 1.0
+    g = hyb.Hybrid.from_problem(p, precision=precision, dissolution=True)
+    g.set_dissolution(kappa, c_sat, mass)
+    o = DissolvingHybrid(p, mass, kappa_s=kappa, c_sat=c_sat)
+    if precision == "fp32":
+        o.fstar = o.fstar.astype(np.float32).astype(np.float64)
+    for s in range(steps):
+        print(f"\ndissolution {over} {precision}: step {s}", flush=True)
+        g.step(P)
+        o.step()
+        sol, m, conv = g.dissolution_state()
+        assert np.array_equal(sol, o.solid), f"step {s}: solid sets differ"
+        assert conv == o.converted
+        fluid = o.solid == 0
+        F = g.get_populations()
+        errs = {"f": _rel(F[:, fluid], o.fstar[:, fluid]),
+                "d": _rel(g.concentration(hyb.HYB_COARSE).reshape(-1), o.d),
+                "mass": _rel(m, o.mass)}
+        print(f"  converted {conv}: {errs}")
+        assert max(errs.values()) <= tol, errs
+        assert not F[:, ~fluid].any()
+    assert o.converted > 0
+
+
+@pytest.mark.parametrize("precision,clamp,tol", [("fp64", 0, 1e-12), ("fp64", 1, 1e-12), ("fp32", 0, 2e-5)])
+def test_reactive_fine_step_adjoint_matches_oracle(orc, precision, clamp, tol):
+    """hyb_lbm_substeps_record / hyb_lbm_adjoint with the surface reaction:
+    the bounce-back's cotangent carries 1 - kappa_s (and a clamped closure
+    sees the reactive known populations)."""
+    hyb, torch = _gpu()
+    N, eta, tau = 67, 4, 0.56
+    rng = np.random.default_rng(300 + clamp)
+    solid = inputs.random_disks(N, 0.75, seed=301, r_min=2, r_max=6).solid
+    vx = rng.uniform(-0.05, 0.05, (N, N)).astype(np.float32)
+    vy = rng.uniform(-0.05, 0.05, (N, N)).astype(np.float32)
+    vx[solid != 0] = 0
+    vy[solid != 0] = 0
+    NP = 4 * (N - 1)
+    a = rng.uniform(0.1, 0.6, NP)
+    b = rng.uniform(0.1, 0.6, NP)
+    f0 = inputs.random_populations(N, 302, lo=0.01, hi=0.1)
+    f0[:, solid != 0] = 0.0
+    c = rng.standard_normal((9, N, N))
+    c[:, solid != 0] = 0.0
+    kappa, c_sat = 0.3, 0.8
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta,
+                   precision=precision, tau=tau, solid=solid, k=1e-3, bc_clamp=clamp, dissolution=True)
+    g.set_dissolution(kappa, c_sat, np.ones((N, N)))
+    g.set_populations(f0)
+    g.set_boundary(a, b)
+    tape = g.adjoint_tape(eta)
+    g.substeps_record(eta, tape)
+    dev = g.dev
+    lam = torch.from_numpy(c).to(dev)
+    lam_out = torch.empty_like(lam)
+    ga = torch.zeros(NP, dtype=torch.float64, device=dev)
+    gb = torch.zeros_like(ga)
+    g.adjoint(eta, tape, lam, lam_out, ga, gb, None)
+    torch.cuda.synchronize()
+    lat = orc.Lattice(N, tau, vx.astype(np.float64), vy.astype(np.float64), solid=solid, k=1e-3, clamp=clamp,
+                      kappa_s=kappa, c_sat=c_sat)
+    fo = f0 if precision == "fp64" else f0.astype(np.float32).astype(np.float64)
+    states = [fo]
+    bcs = [(1 - j / eta) * a + j / eta * b for j in range(1, eta + 1)]
+    for bc in bcs:
+        states.append(lat.substep(states[-1], bc)[0])
+    ol = c
+    oa = np.zeros(NP)
+    ob = np.zeros(NP)
+    for t in reversed(range(eta)):
+        ol, gbc, _ = lat.adjoint_substep(states[t], bcs[t], ol)
+        lt = (t + 1) / eta
+        oa += (1 - lt) * gbc
+        ob += lt * gbc
+    errs = {"lam": _rel(lam_out.cpu().numpy(), ol), "a": _rel(ga.cpu().numpy(), oa), "b": _rel(gb.cpu().numpy(), ob)}
+    print(f"\nreactive adjoint {precision} clamp={clamp}: {errs}")
+    assert max(errs.values()) <= tol, errs
+    # the recorded forward is the reactive forward
+    fluid = solid == 0
+    assert _rel(g.get_populations()[:, fluid], states[-1][:, fluid]) <= (1e-13 if precision == "fp64" else 2e-6)
+
+
+def test_no_reaction_equals_fixed_solids(orc):
+    """With the workspace reserved but kappa_s = 0 the run is the
+    fixed-solid hybrid (the transfer's weights are renormalised in another
+    order: agreement to rounding) and nothing converts."""
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE2048.replace(N=97, M=16, eta=4))
+    fixed = hyb.Hybrid.from_problem(p, precision="fp64")
+    g = hyb.Hybrid.from_problem(p, precision="fp64", dissolution=True)
+    g.set_dissolution(0.0, 1.0, np.zeros((p.cfg.N, p.cfg.N)))
+    for _ in range(3):
+        fixed.step(p.cfg.max_iter)
+        g.step(p.cfg.max_iter)
+    assert _rel(g.get_populations(), fixed.get_populations()) <= 1e-13
+    sol, m, conv = g.dissolution_state()
+    assert conv == 0 and np.array_equal(sol, p.solid.astype(np.uint8))
+
+
+def test_dissolution_rejects():
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE2048.replace(N=65, M=16, eta=3))
+    N = p.cfg.N
+    plain = hyb.Hybrid.from_problem(p, precision="fp64")
+    with pytest.raises(hyb.HybError):                     # no reserved workspace
+        plain.set_dissolution(0.1, 1.0, np.ones((N, N)))
+    with pytest.raises(hyb.HybError):
+        plain.dissolution_state()
+    g = hyb.Hybrid.from_problem(p, precision="fp64", dissolution=True)
+    for kappa in (-0.1, 1.5, float("nan")):
+        with pytest.raises(hyb.HybError):
+            g.set_dissolution(kappa, 1.0, None)
+    with pytest.raises(hyb.HybError):
+        g.set_dissolution(0.1, float("inf"), None)
+    g.set_dissolution(0.1, 1.0, np.ones((N, N)))
+    g.lbm_substeps(1, restart=1)
+    with pytest.raises(hyb.HybError):                     # fine steps pending
+        g.set_dissolution(0.2, 1.0, None)
+    with pytest.raises(hyb.HybError):                     # no whole-step adjoint
+        g.step_record(1, g.step_tape(1))
+    with pytest.raises(ValueError):
+        g.set_dissolution(0.1, 1.0, np.ones(N))
+
+
+def test_dissolution_invariants_at_pore4096_size():
+    """4096^2 patch of the pore-scale workload, FP32, two coarse steps with a
+    fast reaction: the solid set only shrinks, the count matches, remaining
+    masses stay positive and no concentration is non-finite (the reaction
+    may also deposit where the fluid exceeds c_sat, so masses can grow)."""
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE4096)
+    N = p.cfg.N
+    mass = np.random.default_rng(11).uniform(0.02, 0.2, (N, N))
+    g = hyb.Hybrid.from_problem(p, precision="fp32", dissolution=True)
+    g.set_dissolution(0.2, 1.0, mass)
+    sol0, m0, _ = g.dissolution_state()
+    prev = sol0
+    for s in range(2):
+        g.step(p.cfg.max_iter)
+        sol, m, conv = g.dissolution_state()
+        assert np.all(sol <= prev)
+        assert conv == int(sol0.sum()) - int(sol.sum())
+        assert np.all(m[sol != 0] > 0.0)
+        prev = sol
+        print(f"\npore4096 dissolution step {s}: converted {conv}", flush=True)
+    assert conv > 0
+    assert g.stats()["nonfinite"] == 0
