@@ -56,7 +56,7 @@ def kernel_name(elem_bytes, steps_per_launch):
     t = {8: "double", 4: "float", 2: "_Float16"}[elem_bytes]
     if steps_per_launch == 2:
         return f"lbm_sweep2_kernel<{t}, 64, 8, {512 if elem_bytes == 8 else 256}, 0>"
-    return f"lbm_sweep_kernel<{t}, 1>"
+    return f"lbm_sweep_kernel<{t}>"
 
 
 def load_traffic(workload, precision, kernel):
@@ -209,6 +209,72 @@ def step_adjoint_rate(problem, precision, reps=3):
     return res
 
 
+def dissolution_rate(steps=20, warmup=2, timing_steps=3):
+    """The dissolving-solid workload (4096^2, porosity 0.5, FP32, eta = 20,
+    256^2 mesh, 2 Schwarz passes, surface reaction at every fluid-solid link,
+    seeded per-solid masses): K timed coarse steps after W warmup steps on
+    the caller's stream (the commit's mass update, conversions and flag
+    rebuild included), MLUPS over all nodes, the solids converted, and the
+    two-step sweep's average launch duration with its algorithmic bytes
+    (fluid nodes as in the plain sweep, for two fine steps; each solid node
+    with a fluid neighbour also reads and writes its FP64 link-flux sum once
+    per launch)."""
+    import numpy as np
+    import torch
+    from paper_1601_02708_amd import configs, hyb
+    cfg = configs.DISSOLVE4096
+    p = configs.build_problem(cfg)
+    N = cfg.N
+    g = hyb.Hybrid.from_problem(p, precision="fp32", device="cuda:0", dissolution=True)
+    g.set_dissolution(cfg.kappa_s, cfg.c_sat, configs.solid_mass(cfg, p.solid))
+    for _ in range(warmup):
+        g.step(cfg.max_iter)
+    _, _, conv0 = g.dissolution_state()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(g.stream)
+    for _ in range(steps):
+        g.step(cfg.max_iter)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sol, _, conv1 = g.dissolution_state()
+    g.kernel_timing(True)
+    for _ in range(timing_steps):
+        g.step(cfg.max_iter)
+    kms, launches = g.kernel_time()
+    g.kernel_timing(False)
+    sol2, _, conv2 = g.dissolution_state()
+    # geometry of the timing steps (their own commits convert after them)
+    s = sol != 0
+    pad = np.pad(~s, 1, constant_values=False)
+    fluid_nb = np.zeros_like(s)
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            if di or dj:
+                fluid_nb |= pad[1 + dj:1 + dj + N, 1 + di:1 + di + N]
+    surface = int((s & fluid_nb).sum())
+    nfl = int((~s).sum())
+    launch_bytes = 2 * (nfl * (18 * 4 + 8 + 2) + (N * N - nfl) * 2 + 4 * (N - 1) * 16) + surface * 16
+    avg = kms / max(launches, 1)
+    lups = steps * cfg.max_iter * cfg.eta * N * N
+    g.close()
+    return {"workload": (f"{cfg.name}: {N}^2 D2Q9 lattice, random disks (porosity {p.porosity:.4f}), 8-mode "
+                         f"stream-function velocity max 0.05, D={cfg.D}, k={cfg.k}, {cfg.M}^2 Q1 SUPG mesh, "
+                         f"eta={cfg.eta}, {cfg.max_iter} Schwarz passes; surface reaction kappa_s={cfg.kappa_s} "
+                         f"towards c_sat={cfg.c_sat}, solid masses U{list(cfg.mass_range)}"),
+            "precision": "fp32", "value": round(lups / (ms / 1e3) / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(ms / steps, 4), "steps": steps, "warmup": warmup,
+            "converted_in_timed_steps": int(conv1 - conv0), "converted_total": int(conv2),
+            "solid_nodes_now": int(sol2.sum()),
+            "sweep_kernel": "lbm_sweep2_flux_kernel<float, 64, 8, 256> (two fine steps, link fluxes at solid nodes)",
+            "sweep_avg_launch_ms": round(avg, 5),
+            "sweep_algorithmic_bytes_per_launch": int(launch_bytes),
+            "sweep_achieved_gbs": round(launch_bytes / (avg / 1e3) / 1e9, 1),
+            "sweep_frac": round(launch_bytes / (avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(problem, min_seconds=10.0, max_steps=6):
     """The oracle as it stands on this host: whole coarse steps (2 Schwarz
     passes x eta fine steps each, FP64, one thread) of the same workload,
@@ -247,6 +313,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision runs")
+    ap.add_argument("--no-dissolution", action="store_true", help="skip the dissolving-solid workload")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (a plain copy kernel of "
                          "known size, for calibrating HBM traffic counters)")
@@ -354,6 +421,10 @@ def main():
         print("[bench] adjoint", file=sys.stderr, flush=True)
         res["adjoint"] = adjoint_rate(problem, args.precision)
         res["step_adjoint"] = step_adjoint_rate(problem, args.precision)
+    if not args.no_dissolution:
+        print("[bench] dissolving solids (dissolve4096, fp32)", file=sys.stderr, flush=True)
+        g.close()
+        res["dissolution"] = dissolution_rate()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one coarse step)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(problem)

@@ -317,8 +317,8 @@ int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches);
  * (hyb_lattice.dissolution = 1) the fine-to-coarse transfer (Sec. 6.2 item
  * ii) weights the current fluid corners, sum w_m u_m / sum w_m over the
  * fluid ones; a coarse node none of whose fluid corners carries weight
- * keeps the nearest fluid node of the initial geometry.  Fine steps run as
- * single-step launches while the reaction is on.
+ * keeps the nearest fluid node of the initial geometry.  While the
+ * reaction is on, hyb_step runs without overlap (whole-patch launches).
  *
  * hyb_set_dissolution: reaction rate 0 <= kappa_s <= 1 (0 switches the
  *   reaction and the mass bookkeeping off), c_sat finite, mass host FP64

@@ -646,13 +646,15 @@ int hyb_coarse_step(hyb_handle *h, int max_iter) {
 namespace {
 
 // the two-step kernel addresses a population buffer with 32-bit byte
-// offsets, so it serves buffers below 4 GiB (N up to about 11500 in FP64);
-// with dissolving solids every fine step sums its link fluxes, which the
-// single-step sweep does
+// offsets, so it serves buffers below 4 GiB (N up to about 11500 in FP64)
 bool use_two_step(const hyb_handle *h) {
     const bool small_buf = 9.0 * (double)h->lay.plane * (double)storage_bytes(h->prec) < 4294967295.0;
-    return !h->any_neumann && h->steps_per_launch == 2 && small_buf && !h->dissolve_on;
+    return !h->any_neumann && h->steps_per_launch == 2 && small_buf;
 }
+
+// largest overlap depth hyb_step may use: the pass's two-step launches
+// (none with dissolving solids, whose sweeps run whole-patch launches)
+int overlap_dmax(const hyb_handle *h) { return use_two_step(h) && !h->dissolve_on ? h->eta / 2 : 0; }
 
 // the host copy of the solid flags after commits that may have converted
 // solids (waits for the stream)
@@ -867,7 +869,7 @@ int hyb_step(hyb_handle *h, int max_schwarz) {
     // overlap depth: fixed, tuned, or the next candidate while tuning (one
     // untimed step, then three rounds over depths 0 .. D, each step timed on
     // the caller's stream; the fastest of each depth's three counts)
-    const int dmax = use_two_step(h) ? h->eta / 2 : 0;
+    const int dmax = overlap_dmax(h);
     const int ncand = dmax + 1;
     int depth = std::min(h->overlap, dmax);
     const bool tuning = h->overlap == HYB_OVERLAP_AUTO && dmax > 0 && h->tuned_depth < 0;
@@ -1037,7 +1039,7 @@ int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
     out->krylov_relres = kr.relres;
     out->coarse_steps = h->coarse_steps;
     out->fine_steps = h->fine_steps;
-    const int dmax = use_two_step(h) ? h->eta / 2 : 0;
+    const int dmax = overlap_dmax(h);
     out->overlap_depth = h->overlap != HYB_OVERLAP_AUTO ? std::min(h->overlap, dmax)
                          : dmax == 0 ? 0 : h->tuned_depth;
     out->pad = 0;
@@ -1345,7 +1347,8 @@ int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const doubl
     h->c_sat = c_sat;
     h->dissolve_on = kappa_s > 0.0;
     h->flux_valid = false;
-    // the sweep changes (single-step launches), so the overlap depth is tuned again
+    // the sweeps change (whole-patch launches with the reaction), so the
+    // overlap depth is tuned again
     h->tune_idx = 0;
     h->tuned_depth = -1;
     h->tune_ms.clear();

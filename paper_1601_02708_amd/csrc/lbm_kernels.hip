@@ -481,8 +481,12 @@ __device__ __forceinline__ void tile_of(const TileMap &m, int t, int &tx, int &t
     ty = m.iy1 + 1 + t / m.tiles_x;
 }
 
-template <typename S, int TW, int TH, int NT, int PART>
-__global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) {
+// Body of the two-step sweep.  FLUX (dissolving solids): bounce-back
+// values carry the surface reaction, and every owned solid node with fluid
+// neighbours adds the link fluxes of both fine steps to a.flux (step j+1
+// from the source buffer, step j+2 from the first half's results in LDS).
+template <typename S, int TW, int TH, int NT, int PART, bool FLUX>
+__device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map) {
     typedef typename Pop<S>::T T;
     constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
     constexpr int ROUNDS1 = (R1 + NT - 1) / NT;
@@ -589,7 +593,8 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) 
         for (int q = 0; q < kQ; ++q) {
             const T pulled = Pop<S>::ld(raw[k][q], q, a);
             const T own = Pop<S>::ld(raw[k][q], kOpp[q], a);
-            f[q] = ((m[k] >> q) & 1u) ? own : pulled;
+            if constexpr (FLUX) f[q] = ((m[k] >> q) & 1u) ? reactive<T>(a, own, q) : pulled;
+            else f[q] = ((m[k] >> q) & 1u) ? own : pulled;
         }
         if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
             const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
@@ -617,12 +622,52 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) 
             vy2[k] = Buf<float>::load(vyr, 4u * n, 0);
         }
     }
+    // dissolving solids: an owned solid node with fluid neighbours needs, for
+    // step j+1, the populations f*_opp(q)(x + e_q) of the source buffer (the
+    // first half fetched the same lines for the bounce-back of those
+    // neighbours) and its running flux sum
+    S g1[FLUX ? ROUNDS2 : 1][kQ];
+    double fl2[FLUX ? ROUNDS2 : 1];
+    if constexpr (FLUX) {
+#pragma unroll
+        for (int k = 0; k < ROUNDS2; ++k) {
+            if (!(m2[k] & kMaskSolid) || !(m2[k] & 0x1FEu)) continue;
+            const int idx = threadIdx.x + NT * k;
+            const unsigned n = static_cast<unsigned>((y0 + idx / TW) * P + x0 + idx % TW);
+#pragma unroll
+            for (int q = 1; q < kQ; ++q) {
+                const unsigned at = kOpp[q] * SP + static_cast<unsigned>(kCx[q] + kCy[q] * P);
+                g1[k][q] = Buf<S>::load(fsrc, (n + at) * sz, 0);
+            }
+            fl2[k] = (a.flux_first || !a.flux) ? 0.0 : a.flux[n];
+        }
+    }
     __syncthreads();
 
     // ---- second half: step j+2 on the owned nodes, from LDS ------------
 #pragma unroll
     for (int k = 0; k < ROUNDS2; ++k) {
-        if (m2[k] & kMaskSolid) continue;
+        if (m2[k] & kMaskSolid) {
+            if constexpr (FLUX) {
+                if ((m2[k] & 0x1FEu) && a.flux) {
+                    // sum over q of kappa_s (w_q c_sat - f*_opp(q)(x + e_q)),
+                    // in q order, for step j+1 then step j+2
+                    const int idx = threadIdx.x + NT * k;
+                    const int r = idx / TW, c = idx % TW;
+                    const T *base = &lds[0][0][0] + (r + 1) * W1 + (c + 1);
+                    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                    for (int q = 1; q < kQ; ++q)
+                        if ((m2[k] >> q) & 1u) {
+                            s1 += a.kappa_s * (kW[q] * a.c_sat - double(Pop<S>::ld(g1[k][q], kOpp[q], a)));
+                            const T x1 = base[kOpp[q] * (H1 * W1) + kCy[q] * W1 + kCx[q]];
+                            s2 += a.kappa_s * (kW[q] * a.c_sat - double(x1));
+                        }
+                    a.flux[(y0 + r) * P + x0 + c] = (fl2[k] + s1) + s2;
+                }
+            }
+            continue;
+        }
         const int idx = threadIdx.x + NT * k;
         const int r = idx / TW, c = idx % TW;
         const int i = x0 + c, j = y0 + r;
@@ -642,6 +687,11 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) 
                 const int sel = -static_cast<int>((m2[k] >> q) & 1u);
                 g[q] = base[pull + (sel & (back - pull))];
             }
+            if constexpr (FLUX) {
+#pragma unroll
+                for (int q = 1; q < kQ; ++q)
+                    if ((m2[k] >> q) & 1u) g[q] = reactive<T>(a, g[q], q);
+            }
         }
         if (perim) {
             const bool bad = dirichlet_close<T>(a, g, unknown, perimeter_slot(N, i, j), a.lam2);
@@ -652,6 +702,17 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) 
 #pragma unroll
         for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(g[q], q, a), fdst, n * sz, q * SP * sz);
     }
+}
+
+template <typename S, int TW, int TH, int NT, int PART>
+__global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) {
+    sweep2_body<S, TW, TH, NT, PART, false>(a, map);
+}
+
+// whole-patch two-step launch with the surface reaction of dissolving solids
+template <typename S, int TW, int TH, int NT>
+__global__ void __launch_bounds__(NT) lbm_sweep2_flux_kernel(LbmArgs a, TileMap map) {
+    sweep2_body<S, TW, TH, NT, 0, true>(a, map);
 }
 
 // ---------------------------------------------------------------------------
@@ -780,6 +841,12 @@ hipError_t step2_impl(const LbmArgs &a, int part, int depth, hipStream_t s) {
     }
     m.count = m.part == 0 ? all : m.part == 1 ? inner : all - inner;
     if (m.count == 0) return hipSuccess;
+    if (a.flux || a.kappa_s != 0.0) {
+        // dissolving solids: whole-patch launches only
+        if (m.part != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((lbm_sweep2_flux_kernel<S, TW, TH, NT>), dim3(m.count), dim3(NT), 0, s, a, m);
+        return hipGetLastError();
+    }
     if (m.part == 0) hipLaunchKernelGGL((lbm_sweep2_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
     else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep2_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
     else hipLaunchKernelGGL((lbm_sweep2_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);

@@ -182,3 +182,26 @@ def test_dissolution_invariants_at_pore4096_size():
         print(f"\npore4096 dissolution step {s}: converted {conv}", flush=True)
     assert conv > 0
     assert g.stats()["nonfinite"] == 0
+
+
+def test_dissolution_two_step_equals_single_step():
+    """The two-step sweep with link fluxes (steps in pairs, the second
+    step's fluxes from LDS) and the single-step sweep agree to rounding,
+    with identical conversions; hyb_step runs without overlap."""
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE2048.replace(N=193, M=16, eta=6))
+    N = p.cfg.N
+    mass = np.random.default_rng(8).uniform(0.002, 0.01, (N, N))
+    out = []
+    for spl in (1, 2):
+        g = hyb.Hybrid.from_problem(p, precision="fp64", dissolution=True)
+        g.set_steps_per_launch(spl)
+        g.set_dissolution(0.2, 1.0, mass)
+        for _ in range(3):
+            g.step(p.cfg.max_iter)
+        assert g.stats()["overlap_depth"] == 0
+        sol, m, conv = g.dissolution_state()
+        out.append((g.get_populations(), sol, m, conv))
+        g.close()
+    assert np.array_equal(out[0][1], out[1][1]) and out[0][3] == out[1][3] > 0
+    assert _rel(out[1][0], out[0][0]) <= 1e-13 and _rel(out[1][2], out[0][2]) <= 1e-13
