@@ -120,9 +120,11 @@ class DissolvingHybrid(HybridOracle):
         self.lat = Lattice(self.N, cfg.tau_value, vx, vy, solid=self.solid, k=cfg.k, clamp=cfg.bc_clamp,
                            kappa_s=self.kappa_s, c_sat=self.c_sat)
 
-    def fine_to_coarse(self, fstar):
-        u = self.lat.concentration(fstar).reshape(-1)
-        sol = self.solid.reshape(-1) != 0
+    def transfer(self, u, solid):
+        """Fine-to-coarse values of the concentration field u [N, N] with the
+        fluid corners of the geometry ``solid``."""
+        u = np.asarray(u).reshape(-1)
+        sol = np.asarray(solid).reshape(-1) != 0
         out = np.empty(len(self.corners))
         for c, ((nd, wr), fb) in enumerate(zip(self.corners, self.fallback)):
             wsum = sum(wr[m] for m in range(4) if not sol[nd[m]])
@@ -131,6 +133,9 @@ class DissolvingHybrid(HybridOracle):
             else:
                 out[c] = u[fb]
         return out
+
+    def fine_to_coarse(self, fstar):
+        return self.transfer(self.lat.concentration(fstar), self.solid)
 
     def lbm_substeps(self, fstar0, a, b, n_sub=None):
         n_sub = self.eta if n_sub is None else n_sub

@@ -152,15 +152,19 @@ class HybridStepAdjoint:
         np.add.at(out, self.c2f_idx.reshape(-1), (self.c2f_w * np.asarray(g)[:, None]).reshape(-1))
         return out
 
-    def f2c_T(self, lam_ufc, g_state):
+    def f2c_T(self, lam_ufc, g_state, rows=None, fluid=None):
         """T^T lam_ufc for the transfer read of state g_state: (dJ/df* [9,N,N],
-        dJ/dk [N,N]); u = sum_q f*_q / (1 - k) at fluid nodes."""
+        dJ/dk [N,N]); u = sum_q f*_q / (1 - k) at fluid nodes.  rows and
+        fluid: the transfer's rows and fluid set (default: the problem's
+        fixed geometry)."""
         N = self.o.N
+        rows = self.f2c_rows if rows is None else rows
+        fluid = self.fluid if fluid is None else fluid
         lam_u = np.zeros(N * N)
-        for (nd, w), l in zip(self.f2c_rows, lam_ufc):
+        for (nd, w), l in zip(rows, lam_ufc):
             for n, wn in zip(nd, w):
                 lam_u[n] += wn * l
-        lam_u[~self.fluid] = 0.0
+        lam_u[~fluid] = 0.0
         one_k = 1.0 - self.kfield
         lam_f = np.broadcast_to(lam_u / one_k, (9, N * N)).copy()
         s = np.asarray(g_state).reshape(9, N * N).sum(axis=0)
@@ -210,6 +214,9 @@ class HybridStepAdjoint:
         mesh node, zero elsewhere)."""
         o = self.o
         N = o.N
+        # a tape may carry the lattice, transfer rows and fluid set of its
+        # own step (dissolving solids); else those of the fixed geometry
+        lat = tape.get("lat", o.lat)
         lam_F = np.zeros((9, N, N))
         lam_dn = np.zeros(self.A.shape[0])
         g_outer = np.zeros(self.A.shape[0])
@@ -224,7 +231,7 @@ class HybridStepAdjoint:
             for j in range(o.eta, 0, -1):
                 lt = j / o.eta
                 up = (1 - lt) * rec["a"] + lt * rec["b"]
-                lam, gbc, kk = o.lat.adjoint_substep(rec["states"][j - 1], up, lam)
+                lam, gbc, kk = lat.adjoint_substep(rec["states"][j - 1], up, lam)
                 ga += (1 - lt) * gbc
                 gb += lt * gbc
                 gk += kk
@@ -237,7 +244,7 @@ class HybridStepAdjoint:
             lam_dn += ld
             rows = o.rows_sorted
             g_outer[rows[~o._is_fc]] += np.asarray(lvals)[~o._is_fc]
-            lf, kf = self.f2c_T(self.ufc_of_values(lvals), rec["src"])
+            lf, kf = self.f2c_T(self.ufc_of_values(lvals), rec["src"], tape.get("rows"), tape.get("fluid"))
             gk += kf
             if p == 0:
                 lam_F += lf
