@@ -328,12 +328,21 @@ int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches);
  * hyb_dissolution_state: current solid flags (host u8 [N*N]), masses (host
  *   FP64 [N*N], 0 at fluid nodes) and the number of solids converted since
  *   hyb_create; each output may be NULL.  Synchronises.
- * The whole-step adjoint (hyb_step_record) is not available on a handle
- * with the reserved workspace; the fine-step adjoint is (its bounce-back
- * carries the factor 1 - kappa_s; the recorded steps also sum the link
- * fluxes). */
+ * hyb_set_solids: replace the geometry and masses (host u8 / FP64 [N*N],
+ *   e.g. a checkpoint taken with hyb_dissolution_state): only nodes solid at
+ *   hyb_create may be solid (HYB_EINVAL otherwise); the flag words are
+ *   rebuilt; only between coarse steps.  Synchronises.
+ * Reverse mode: the fine-step adjoint carries the link factor 1 - kappa_s
+ * (the recorded steps also sum the link fluxes).  hyb_step_record records
+ * the step's flag words and the solids left by its commit; hyb_step_adjoint
+ * then reverses the step on that geometry, with the commit's conversion
+ * transposed for its set of converted nodes (a converted node's cotangent
+ * reaches its fluid neighbours through their mean concentration, and the
+ * (1 - k) factors enter dJ/dk); the conversion decision itself and the
+ * masses are not differentiated (piecewise constant). */
 int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const double *mass);
 int hyb_dissolution_state(hyb_handle *h, uint8_t *solid, double *mass, int64_t *converted);
+int hyb_set_solids(hyb_handle *h, const uint8_t *solid, const double *mass);
 
 /* Storage layout actually used: row pitch and plane stride in elements. */
 int hyb_layout(const hyb_handle *h, size_t *pitch, size_t *plane);

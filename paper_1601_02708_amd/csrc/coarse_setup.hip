@@ -381,6 +381,33 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
         out.f2cT_ptr.push_back((int)e.size());
         if (e.empty()) out.f2cT_ptr.assign(1, 0);
     }
+
+    // the same for a geometry that changes (dissolving solids): every raw
+    // corner (slot 0..3) and fallback node (slot 4) of every Gamma_{f->c}
+    // node, grouped per lattice node; the weights follow from the flag words
+    // of the step being reversed
+    {
+        std::vector<std::array<int, 3>> e;         // (pitched node, c, slot)
+        for (int c = 0; c < nfc; ++c) {
+            for (int m = 0; m < 4; ++m) e.push_back({out.fcr_idx[4 * c + m], c, m});
+            if (out.fcr_fb[c] >= 0) e.push_back({out.fcr_fb[c], c, 4});
+        }
+        std::sort(e.begin(), e.end());
+        out.f2cD_node.clear();
+        out.f2cD_ptr.assign(1, 0);
+        out.f2cD_c.clear();
+        out.f2cD_m.clear();
+        for (size_t t = 0; t < e.size(); ++t) {
+            if (t == 0 || e[t][0] != e[t - 1][0]) {
+                if (t) out.f2cD_ptr.push_back((int)t);
+                out.f2cD_node.push_back(e[t][0]);
+            }
+            out.f2cD_c.push_back(e[t][1]);
+            out.f2cD_m.push_back(e[t][2]);
+        }
+        out.f2cD_ptr.push_back((int)e.size());
+        if (e.empty()) out.f2cD_ptr.assign(1, 0);
+    }
     return std::string();
 }
 

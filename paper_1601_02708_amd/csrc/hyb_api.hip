@@ -85,6 +85,7 @@ struct Layout {
     // and solid flag; raw fine-to-coarse corners and fallbacks
     bool dissolve = false;
     size_t mass = 0, flux = 0, solid_now = 0, fcr_idx = 0, fcr_w = 0, fcr_fb = 0;
+    size_t f2cD_node = 0, f2cD_ptr = 0, f2cD_c = 0, f2cD_m = 0;
     int n = 0, S = 0, grid = 0;
     size_t vec_len = 0;
 };
@@ -154,6 +155,11 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
             L.fcr_idx = take((size_t)L.n * 4 * 4);
             L.fcr_w = take((size_t)L.n * 4 * 8);
             L.fcr_fb = take((size_t)L.n * 4);
+            // transposed superset: at most 5 entries per Gamma_{f->c} node
+            L.f2cD_node = take((size_t)L.n * 5 * 4);
+            L.f2cD_ptr = take(((size_t)L.n * 5 + 1) * 4);
+            L.f2cD_c = take((size_t)L.n * 5 * 4);
+            L.f2cD_m = take((size_t)L.n * 5 * 4);
         }
     }
     L.total = off;
@@ -207,6 +213,9 @@ struct hyb_handle {
     uint8_t *solid_now = nullptr;
     int *fcr_idx = nullptr, *fcr_fb = nullptr;
     double *fcr_w = nullptr;
+    int *f2cD_node = nullptr, *f2cD_ptr = nullptr, *f2cD_c = nullptr, *f2cD_m = nullptr;
+    int f2cD_n = 0;
+    std::vector<uint8_t> solid_init;    // [N*N] the geometry at hyb_create
     CoarseDev cd{};
     unsigned long long *counters = nullptr;
     KrylovResult *kres = nullptr;
@@ -390,6 +399,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     h->solid_host.assign((size_t)N * N, 0);
     if (lat->solid)
         for (size_t n = 0; n < (size_t)N * N; ++n) h->solid_host[n] = lat->solid[n] ? 1 : 0;
+    h->solid_init = h->solid_host;
     if (h->prec == HYB_FP16S) {
         // c_ref = mean of u0 over the fluid nodes; scale = 2^s, the largest
         // power of two with (4/9) U 2^s <= 2^14, U = max(1, max |u0 - c_ref|)
@@ -568,10 +578,20 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
             h->fcr_idx = reinterpret_cast<int *>(h->ws + L.fcr_idx);
             h->fcr_w = reinterpret_cast<double *>(h->ws + L.fcr_w);
             h->fcr_fb = reinterpret_cast<int *>(h->ws + L.fcr_fb);
+            h->f2cD_node = reinterpret_cast<int *>(h->ws + L.f2cD_node);
+            h->f2cD_ptr = reinterpret_cast<int *>(h->ws + L.f2cD_ptr);
+            h->f2cD_c = reinterpret_cast<int *>(h->ws + L.f2cD_c);
+            h->f2cD_m = reinterpret_cast<int *>(h->ws + L.f2cD_m);
+            h->f2cD_n = (int)ch.f2cD_node.size();
+            if (ch.f2cD_c.size() > 5 * (size_t)L.n) return bail(HYB_EINVAL, "internal: transfer superset too long");
             if (h->nfc) {
                 CREATE_TRY(up(h->fcr_idx, ch.fcr_idx.data(), ch.fcr_idx.size() * 4));
                 CREATE_TRY(up(h->fcr_w, ch.fcr_w.data(), ch.fcr_w.size() * 8));
                 CREATE_TRY(up(h->fcr_fb, ch.fcr_fb.data(), ch.fcr_fb.size() * 4));
+                CREATE_TRY(up(h->f2cD_node, ch.f2cD_node.data(), ch.f2cD_node.size() * 4));
+                CREATE_TRY(up(h->f2cD_ptr, ch.f2cD_ptr.data(), ch.f2cD_ptr.size() * 4));
+                CREATE_TRY(up(h->f2cD_c, ch.f2cD_c.data(), ch.f2cD_c.size() * 4));
+                CREATE_TRY(up(h->f2cD_m, ch.f2cD_m.data(), ch.f2cD_m.size() * 4));
             }
         }
         std::vector<double> xp(L.vec_len, 0.0);
@@ -1115,6 +1135,7 @@ namespace {
 // four padded coarse vectors; dJ/du_fc; one solver result per pass.
 struct StepTape {
     size_t states = 0, scratch = 0, bc = 0, gab = 0, coarse = 0, lufc = 0, kres = 0, total = 0;
+    size_t mask = 0, after = 0;     // dissolving solids: flag words before, solid flags after the commit
 };
 
 StepTape step_tape_layout(const hyb_handle *h, int passes) {
@@ -1134,6 +1155,11 @@ StepTape step_tape_layout(const hyb_handle *h, int passes) {
     T.coarse = take(4 * align_up(h->lay.vec_len * 8, kAlign));
     T.lufc = take((size_t)h->lay.n * 8);
     T.kres = take((size_t)passes * sizeof(KrylovResult));
+    if (h->dissolve_ws) {
+        const size_t nodes = (size_t)h->N * h->lay.pitch;
+        T.mask = take(nodes * 2);
+        T.after = take(nodes);
+    }
     T.total = off;
     return T;
 }
@@ -1142,7 +1168,6 @@ int step_adjoint_supported(hyb_handle *h) {
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "the step adjoint needs a coarse mesh");
     if (h->prec == HYB_FP16S) return h->fail(HYB_EINVAL, "the adjoint supports HYB_FP64 and HYB_FP32 storage");
     if (h->any_neumann) return h->fail(HYB_EINVAL, "the adjoint supports Dirichlet perimeter slots only");
-    if (h->dissolve_ws) return h->fail(HYB_EINVAL, "the step adjoint does not support dissolving solids");
     return HYB_OK;
 }
 
@@ -1174,6 +1199,9 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
         h->jsub = 0;
         h->solved_this_step = false;
         HIP_TRY(h, hipMemcpyAsync(state(0, 0), h->f[h->frozen], fb, hipMemcpyDeviceToDevice, h->stream));
+        if (h->dissolve_ws)
+            HIP_TRY(h, hipMemcpyAsync(base + T.mask, h->mask, (size_t)h->N * h->lay.pitch * 2, hipMemcpyDeviceToDevice,
+                                      h->stream));
         const int out = h->spare(-1);
         for (int p = 0; p < passes; ++p) {
             if ((rc = hyb_interface_exchange(h, HYB_F2C)) != HYB_OK) return rc;
@@ -1186,6 +1214,11 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
                 a.src = state(p, t - 1);
                 a.dst = state(p, t);
                 a.lam = (double)t / (double)h->eta;
+                if (h->dissolve_on) {
+                    a.flux = h->flux;
+                    a.flux_first = t == 1;
+                    h->flux_valid = true;
+                }
                 HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
             }
             HIP_TRY(h, hipMemcpyAsync(h->f[out], state(p, h->eta), fb, hipMemcpyDeviceToDevice, h->stream));
@@ -1198,6 +1231,11 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
         h->last_krylov_iters = h->solve_cap;
     }
     if (rc == HYB_OK) {
+        // the solid flags the commit left (the converted nodes are those
+        // solid before and fluid after)
+        if (h->dissolve_ws)
+            HIP_TRY(h, hipMemcpyAsync(base + T.after, h->solid_now, (size_t)h->N * h->lay.pitch,
+                                      hipMemcpyDeviceToDevice, h->stream));
         h->rec_step_tape = tape;
         h->rec_step_passes = passes;
     }
@@ -1229,7 +1267,15 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
     KrylovResult *kr = reinterpret_cast<KrylovResult *>(base + T.kres);
     const size_t dense_bytes = (size_t)9 * h->N * h->N * 8;
     LbmArgs a = h->lbm_args(h->frozen, -1);
+    const bool dissolving = h->dissolve_ws;
+    if (dissolving) a.mask = reinterpret_cast<const uint16_t *>(base + T.mask);   // the step's geometry
     HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_f, lcur, true, h->stream));
+    if (dissolving) {
+        // the commit's conversion, transposed (nu is free until the first reversed fine step)
+        HIP_TRY(h, launch_conversion_transpose(a, h->prec, reinterpret_cast<const uint8_t *>(base + T.after),
+                                               state(passes - 1, h->eta), lcur, static_cast<double *>(nu), grad_k,
+                                               h->stream));
+    }
     HIP_TRY(h, hipMemsetAsync(lam_f_out, 0, dense_bytes, h->stream));
     // the padded coarse vectors keep a zero halo (stencils read it)
     HIP_TRY(h, hipMemsetAsync(base + T.coarse, 0, 4 * vs, h->stream));
@@ -1256,14 +1302,17 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
         HIP_TRY(h, launch_coarse_solve_given(ct, rhs_t, mu, budget, 200, 1e-14, h->stream));
         HIP_TRY(h, launch_coarse_rhs_transpose(h->cd, h->fc_row, h->nfc, mu, lam_dn, lam_ufc, grad_outer, h->stream));
         // fine-to-coarse transposed onto the state the pass's transfer read
-        if (p == 0) {
+        const void *read = p == 0 ? state(0, 0) : state(p - 1, h->eta);
+        if (p > 0) HIP_TRY(h, hipMemsetAsync(lcur, 0, fb, h->stream));
+        void *to_pitched = p == 0 ? nullptr : lcur;
+        double *to_dense = p == 0 ? lam_f_out : nullptr;
+        if (dissolving)
+            HIP_TRY(h, launch_f2c_dynamic_transpose(a, h->prec, h->f2cD_node, h->f2cD_ptr, h->f2cD_c, h->f2cD_m,
+                                                    h->f2cD_n, h->fcr_idx, h->fcr_w, lam_ufc, read, to_pitched,
+                                                    to_dense, grad_k, h->stream));
+        else
             HIP_TRY(h, launch_f2c_transpose(a, h->prec, h->f2cT_node, h->f2cT_ptr, h->f2cT_c, h->f2cT_w, h->f2cT_n,
-                                            lam_ufc, state(0, 0), nullptr, lam_f_out, grad_k, h->stream));
-        } else {
-            HIP_TRY(h, hipMemsetAsync(lcur, 0, fb, h->stream));
-            HIP_TRY(h, launch_f2c_transpose(a, h->prec, h->f2cT_node, h->f2cT_ptr, h->f2cT_c, h->f2cT_w, h->f2cT_n,
-                                            lam_ufc, state(p - 1, h->eta), lcur, nullptr, grad_k, h->stream));
-        }
+                                            lam_ufc, read, to_pitched, to_dense, grad_k, h->stream));
     }
     HIP_TRY(h, launch_coarse_repad(h->cd, lam_dn, lam_d_out, true, h->stream));
     std::vector<KrylovResult> res(passes);
@@ -1352,6 +1401,33 @@ int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const doubl
     h->tune_idx = 0;
     h->tuned_depth = -1;
     h->tune_ms.clear();
+    return HYB_OK;
+}
+
+int hyb_set_solids(hyb_handle *h, const uint8_t *solid, const double *mass) {
+    if (!h || !solid || !mass) return HYB_EINVAL;
+    if (!h->dissolve_ws) return h->fail(HYB_EINVAL, "the handle was created without dissolution");
+    if (h->jsub != 0 || h->cur != h->frozen)
+        return h->fail(HYB_EINVAL, "set the solids between coarse steps (fine steps are pending)");
+    const int N = h->N, P = h->lay.pitch;
+    for (size_t n = 0; n < (size_t)N * N; ++n)
+        if (solid[n] && !h->solid_init[n])
+            return h->fail(HYB_EINVAL, "only nodes that were solid at creation can be solid");
+    std::vector<uint8_t> sp((size_t)N * P, 0);
+    std::vector<double> mp((size_t)N * P, 0.0);
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+            const size_t n = (size_t)j * N + i;
+            sp[(size_t)j * P + i] = solid[n] ? 1 : 0;
+            mp[(size_t)j * P + i] = solid[n] ? mass[n] : 0.0;
+        }
+    HIP_TRY(h, hipMemcpyAsync(h->solid_now, sp.data(), sp.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->mass, mp.data(), mp.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, launch_mask_rebuild(N, P, h->solid_now, h->mask, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (size_t n = 0; n < (size_t)N * N; ++n) h->solid_host[n] = solid[n] ? 1 : 0;
+    h->solid_host_stale = false;
+    h->flux_valid = false;
     return HYB_OK;
 }
 

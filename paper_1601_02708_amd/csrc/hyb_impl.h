@@ -240,6 +240,24 @@ hipError_t launch_dissolve_commit(const LbmArgs &a, int prec, double *mass, uint
 // carries weight.
 hipError_t launch_f2c_dynamic(const LbmArgs &lat, const int *idx, const double *w, const int *fb, int nfc,
                               double *ufc, int prec, hipStream_t s);
+// Flag words from solid[] alone (restoring a saved geometry).
+hipError_t launch_mask_rebuild(int N, int pitch, const uint8_t *solid, uint16_t *mask, hipStream_t s);
+// Reverse mode of a dissolving step (HYB_FP64 / FP32 storage; a.mask = the
+// step's flag words before its commit, after[] = solid flags after it).
+// Conversion transposed in place on lam (pitched cotangent of the committed
+// state): each converted node's cotangent, through the mean concentration of
+// its fluid neighbours in pre (the state before the commit), is added to
+// those neighbours and the node's own is cleared; H (FP64, pitched) is
+// scratch; grad_k (dense [N][N] or null) takes the (1 - k) terms.
+hipError_t launch_conversion_transpose(const LbmArgs &a, int prec, const uint8_t *after, const void *pre, void *lam,
+                                       double *H, double *grad_k, hipStream_t s);
+// Transposed fine-to-coarse transfer with the weights of the step's fluid
+// corners (lists of launch_f2c_dynamic's superset, a.mask the step's flag
+// words); otherwise as launch_f2c_transpose.
+hipError_t launch_f2c_dynamic_transpose(const LbmArgs &lat, int prec, const int *node, const int *ptr,
+                                        const int *cidx, const int *slot, int ntouched, const int *fcr_idx,
+                                        const double *fcr_w, const double *lam_ufc, const void *g_state,
+                                        void *lam_pitched, double *lam_dense, double *grad_k, hipStream_t s);
 
 // dense[(M+1)^2] = padded (unpad), or padded = dense (pad, halo untouched)
 hipError_t launch_coarse_repad(const CoarseDev &c, const double *from, double *to, bool to_dense, hipStream_t s);
@@ -267,6 +285,10 @@ struct CoarseHost {
     // coarse node whose fluid corners carry no weight (-1 otherwise)
     std::vector<int> fcr_idx, fcr_fb;
     std::vector<double> fcr_w;
+    // their transposed superset: per lattice node that is a raw corner or a
+    // fallback node, the Gamma_{f->c} indices and slots (0..3 corner, 4
+    // fallback), node then index order
+    std::vector<int> f2cD_node, f2cD_ptr, f2cD_c, f2cD_m;
     std::vector<double> APT, PT;
     std::vector<int> c2fT_ptr, c2fT_slot;
     std::vector<double> c2fT_w;

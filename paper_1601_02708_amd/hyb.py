@@ -76,6 +76,7 @@ SIGNATURES = {
     "hyb_set_coarse": (_i, [_P, _P]),
     "hyb_set_dissolution": (_i, [_P, _d, _d, _P]),
     "hyb_dissolution_state": (_i, [_P, _P, _P, _P]),
+    "hyb_set_solids": (_i, [_P, _P, _P]),
     "hyb_set_overlap": (_i, [_P, _i]),
     "hyb_set_steps_per_launch": (_i, [_P, _i]),
     "hyb_kernel_timing": (_i, [_P, _i]),
@@ -150,6 +151,7 @@ class Hybrid:
         self.lat.solid = _ptr(solidh)
         self.lat.u0 = _ptr(u0h)
         self.lat.dissolution = int(bool(dissolution))
+        self.dissolution = bool(dissolution)
         self.meshs = None
         vc = None
         if mesh is not None:
@@ -286,6 +288,15 @@ class Hybrid:
             raise ValueError("mass must have N*N entries")
         return self._check(load().hyb_set_dissolution(self.h, float(kappa_s), float(c_sat), _ptr(m)))
 
+    def set_solids(self, solid, mass):
+        """Replace the geometry (host [N, N] flags, only nodes solid at
+        creation) and the masses (host [N, N])."""
+        sol = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)
+        m = np.ascontiguousarray(mass, dtype=np.float64).reshape(-1)
+        if sol.size != self.N * self.N or m.size != self.N * self.N:
+            raise ValueError("solid and mass must have N*N entries")
+        return self._check(load().hyb_set_solids(self.h, _ptr(sol), _ptr(m)))
+
     def dissolution_state(self):
         """(solid flags [N, N] uint8, masses [N, N], solids converted so far)."""
         sol = np.empty((self.N, self.N), np.uint8)
@@ -406,10 +417,16 @@ def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8):
     dev = g.dev
     n1 = (M + 1) ** 2
 
+    # with dissolving solids a state also holds the geometry and the masses
+    dissolving = getattr(g, "dissolution", False)
+
     def state():
-        return g.get_populations(), g.concentration(HYB_COARSE).copy()
+        st = (g.get_populations(), g.concentration(HYB_COARSE).copy())
+        return st + g.dissolution_state()[:2] if dissolving else st
 
     def restore(st):
+        if dissolving:
+            g.set_solids(st[2], st[3])
         g.set_populations(st[0])
         g.set_coarse(st[1])
 
@@ -440,7 +457,7 @@ def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8):
             seg.append(state())
         seg.append(ckpt[s1])
         for n in range(s1 - 1, s0 - 1, -1):
-            cf, cd = cotangent(n + 1, *seg[n - s0 + 1])
+            cf, cd = cotangent(n + 1, *seg[n - s0 + 1][:2])
             if cf is not None:
                 lam_f += torch.from_numpy(np.ascontiguousarray(cf, np.float64)).to(dev)
             if cd is not None:
@@ -465,6 +482,9 @@ def rollout_function():
     class Rollout(torch.autograd.Function):
         @staticmethod
         def forward(ctx, g, n_steps, passes, F0, d0):
+            # with dissolving solids the rollout starts from the handle's
+            # current geometry, which backward restores
+            ctx.geom = g.dissolution_state()[:2] if getattr(g, "dissolution", False) else None
             g.set_populations(F0.detach().cpu().numpy())
             g.set_coarse(d0.detach().cpu().numpy())
             for _ in range(n_steps):
@@ -478,12 +498,17 @@ def rollout_function():
         def backward(ctx, gF, gd):
             g, n = ctx.g, ctx.n
             end = (g.get_populations(), g.concentration(HYB_COARSE).copy())
+            end_geom = g.dissolution_state()[:2] if ctx.geom is not None else None
+            if ctx.geom is not None:
+                g.set_solids(*ctx.geom)
             g.set_populations(ctx.F0)
             g.set_coarse(ctx.d0)
             cF = None if gF is None else gF.detach().cpu().numpy()
             cd = None if gd is None else gd.detach().cpu().numpy()
             lF, ld, _, _ = steps_adjoint(g, n, lambda k, F, d: (cF, cd) if k == n else (None, None),
                                          ctx.passes, checkpoint_every=max(1, n))
+            if end_geom is not None:
+                g.set_solids(*end_geom)
             g.set_populations(end[0])
             g.set_coarse(end[1])
             return None, None, None, torch.from_numpy(lF).to(ctx.dev), torch.from_numpy(ld).to(ctx.dev)

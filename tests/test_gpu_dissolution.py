@@ -153,10 +153,13 @@ def test_dissolution_rejects():
     g.lbm_substeps(1, restart=1)
     with pytest.raises(hyb.HybError):                     # fine steps pending
         g.set_dissolution(0.2, 1.0, None)
-    with pytest.raises(hyb.HybError):                     # no whole-step adjoint
-        g.step_record(1, g.step_tape(1))
     with pytest.raises(ValueError):
         g.set_dissolution(0.1, 1.0, np.ones(N))
+    g.commit()
+    fluid_node = np.zeros((N, N), np.uint8)
+    fluid_node[np.argwhere(p.solid == 0)[0][0], np.argwhere(p.solid == 0)[0][1]] = 1
+    with pytest.raises(hyb.HybError):                     # a node that was fluid cannot be solid
+        g.set_solids(fluid_node, np.ones((N, N)))
 
 
 def test_dissolution_invariants_at_pore4096_size():
@@ -205,3 +208,95 @@ def test_dissolution_two_step_equals_single_step():
         g.close()
     assert np.array_equal(out[0][1], out[1][1]) and out[0][3] == out[1][3] > 0
     assert _rel(out[1][0], out[0][0]) <= 1e-13 and _rel(out[1][2], out[0][2]) <= 1e-13
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-4)])
+def test_dissolving_step_adjoint_matches_oracle(orc, precision, tol):
+    """hyb_step_record / hyb_step_adjoint on a step with ~460 conversions:
+    the committed state, solids and masses equal the oracle's recorded step,
+    and dJ/dF, dJ/dd, dJ/dk equal the oracle's adjoint (conversion
+    transposed first, then the passes on the step's geometry)."""
+    from oracle.dissolution import DissolvingHybrid
+    from oracle.dissolution_adjoint import DissolvingStepAdjoint
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE2048.replace(N=65, M=16, eta=3))
+    N, M, P = p.cfg.N, p.cfg.M, p.cfg.max_iter
+    mass = np.random.default_rng(7).uniform(0.002, 0.01, (N, N))
+    g = hyb.Hybrid.from_problem(p, precision=precision, dissolution=True)
+    g.set_dissolution(0.2, 1.0, mass)
+    F0 = g.get_populations()
+    d0 = g.concentration(hyb.HYB_COARSE).reshape(-1)
+    rng = np.random.default_rng(61)
+    lam_f = rng.standard_normal((9, N, N))
+    lam_d = rng.standard_normal((M + 1) ** 2)
+    dev = g.dev
+    lf = torch.from_numpy(lam_f).to(dev)
+    ld = torch.from_numpy(lam_d).to(dev)
+    lf_out, ld_out = torch.empty_like(lf), torch.empty_like(ld)
+    gk = torch.zeros((N, N), dtype=torch.float64, device=dev)
+    tape = g.step_tape(P)
+    g.step_record(P, tape)
+    g.step_adjoint(tape, lf, ld, lf_out, ld_out, gk)
+    torch.cuda.synchronize()
+    o = DissolvingHybrid(p, mass, kappa_s=0.2, c_sat=1.0)
+    adj = DissolvingStepAdjoint(o)
+    F1, d1, otape = adj.forward(F0, d0)
+    sol, m, conv = g.dissolution_state()
+    assert np.array_equal(sol, o.solid) and conv == int(otape["conv"].sum()) > 0
+    fwd = 1e-12 if precision == "fp64" else 1e-5
+    fluid = o.solid == 0
+    assert _rel(g.get_populations()[:, fluid], F1[:, fluid]) <= fwd
+    oF, od, ok = adj.adjoint(otape, lam_f * fluid, lam_d)
+    # the cotangent at nodes that are solid after the commit does not enter
+    # the map (their state is zero); compare on the pre-commit fluid set
+    pre_fluid = otape["solid"] == 0
+    gF = lf_out.cpu().numpy()
+    errs = {"f": _rel(gF[:, pre_fluid], oF[:, pre_fluid]), "d": _rel(ld_out.cpu().numpy(), od),
+            "k": _rel(gk.cpu().numpy(), ok)}
+    print(f"\ndissolving step adjoint {precision}: {errs}")
+    assert max(errs.values()) <= tol, errs
+
+
+def test_dissolving_trajectory_adjoint_with_checkpoints(orc):
+    """Three dissolving coarse steps reversed with steps_adjoint
+    (checkpoints every two steps restore populations, coarse state, solids
+    and masses) against the oracle's composed one-step adjoints."""
+    from oracle.dissolution import DissolvingHybrid
+    from oracle.dissolution_adjoint import DissolvingStepAdjoint
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE2048.replace(N=65, M=16, eta=3))
+    N, M, P = p.cfg.N, p.cfg.M, p.cfg.max_iter
+    mass = np.random.default_rng(7).uniform(0.002, 0.01, (N, N))
+    g = hyb.Hybrid.from_problem(p, precision="fp64", dissolution=True)
+    g.set_dissolution(0.2, 1.0, mass)
+    F0 = g.get_populations()
+    d0 = g.concentration(hyb.HYB_COARSE).reshape(-1)
+    n_steps = 3
+
+    def cot(n, F, d):
+        r = np.random.default_rng(200 + n)
+        return r.standard_normal((9, N, N)), r.standard_normal((M + 1) ** 2)
+
+    lF, ld, gk, _ = hyb.steps_adjoint(g, n_steps, cot, P, checkpoint_every=2)
+    o = DissolvingHybrid(p, mass, kappa_s=0.2, c_sat=1.0)
+    adj = DissolvingStepAdjoint(o)
+    F, d = F0, d0
+    tapes, states = [], []
+    for _ in range(n_steps):
+        F, d, tp = adj.forward(F, d)
+        tapes.append(tp)
+        states.append((F, d, o.solid.copy()))
+    sol, _, _ = g.dissolution_state()
+    assert np.array_equal(sol, o.solid)
+    oF = np.zeros((9, N, N))
+    od = np.zeros((M + 1) ** 2)
+    ok = np.zeros((N, N))
+    for n in range(n_steps - 1, -1, -1):
+        cf, cd = cot(n + 1, None, None)
+        fluid_after = states[n][2] == 0
+        oF, od, k = adj.adjoint(tapes[n], (oF + cf) * fluid_after, od + cd)
+        ok += k
+    pre_fluid = tapes[0]["solid"] == 0
+    errs = {"F": _rel(lF[:, pre_fluid], oF[:, pre_fluid]), "d": _rel(ld, od), "k": _rel(gk, ok)}
+    print(f"\ndissolving trajectory adjoint: {errs}")
+    assert max(errs.values()) <= 1e-10, errs
