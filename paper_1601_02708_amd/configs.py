@@ -164,3 +164,70 @@ def build_problem(cfg: HybridConfig) -> Problem:
     return Problem(cfg=cfg, solid=solid, vx=vx, vy=vy, vc=np.ascontiguousarray(vc),
                    u0_fine=u0_fine, u0_coarse=u0_coarse, porosity=porosity,
                    x0=x0, y0=x0, L=L)
+
+
+# ----------------------------------------------------------------------------
+# several fine patches in one coarse domain (Algorithm 2)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Patch:
+    """One fine lattice patch: N x N nodes, node (0, 0) at domain point
+    (x0, y0); host arrays as in Problem."""
+    N: int
+    x0: float
+    y0: float
+    solid: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    u0_fine: np.ndarray
+
+
+@dataclasses.dataclass
+class MultiProblem:
+    """A coarse mesh over [0, L]^2 with several disjoint fine patches."""
+    M: int
+    L: float
+    D: float
+    k: float
+    eta: int
+    max_iter: int
+    supg: int
+    overlap_elems: int
+    bc_clamp: int
+    vc: np.ndarray            # [(M+1)^2, 2] coarse nodal velocity
+    u0_coarse: np.ndarray     # [(M+1)^2]
+    patches: list
+
+    @property
+    def tau_value(self) -> float:
+        return 0.5 + 3.0 * self.D
+
+
+def build_multi(N: int, M: int, L: float, origins, D: float = 1e-2, k: float = 0.0, eta: int = 4,
+                max_iter: int = 2, velocity=(0.05, 0.0), pulse=None, porosity=None, seed: int = 0) -> MultiProblem:
+    """Fine patches of N x N nodes at the given domain origins, uniform
+    velocity, the seeded Gaussian pulse (or the given one) as initial
+    condition on every grid, random disks per patch at the given porosity
+    (None: no solids)."""
+    pulse = inputs.gaussian_pulse(seed, L) if pulse is None else pulse
+    XC, YC = inputs.coarse_coords(M, L)
+    vc = np.empty(((M + 1) * (M + 1), 2))
+    vc[:, 0], vc[:, 1] = velocity
+    patches = []
+    for p, (x0, y0) in enumerate(origins):
+        ax = np.arange(N, dtype=np.float64)
+        Y, X = np.meshgrid(y0 + ax, x0 + ax, indexing="ij")
+        if porosity is None:
+            solid = np.zeros((N, N), np.uint8)
+        else:
+            solid = inputs.random_disks(N, porosity, seed=seed + 1000 + p, r_min=2, r_max=5).solid
+        vx = np.full((N, N), velocity[0], np.float32)
+        vy = np.full((N, N), velocity[1], np.float32)
+        vx[solid != 0] = 0.0
+        vy[solid != 0] = 0.0
+        u0 = pulse(X, Y)
+        u0[solid != 0] = 0.0
+        patches.append(Patch(N=N, x0=float(x0), y0=float(y0), solid=solid, vx=vx, vy=vy, u0_fine=u0))
+    return MultiProblem(M=M, L=float(L), D=D, k=k, eta=eta, max_iter=max_iter, supg=1, overlap_elems=1,
+                        bc_clamp=0, vc=vc, u0_coarse=pulse(XC, YC).ravel(), patches=patches)
