@@ -209,7 +209,58 @@ def step_adjoint_rate(problem, precision, reps=3):
     return res
 
 
-def dissolution_rate(steps=20, warmup=2, timing_steps=3):
+def dissolution_adjoint(g, cfg, substeps=1000, checkpoint_every=10):
+    """Reverse mode over the last `substeps` fine steps of the dissolving run
+    (substeps / eta coarse steps from the handle's state, each with its
+    Schwarz passes): J = sum of all populations after them (the fluid's
+    total concentration times 1 - k), gradient with respect to the per-node
+    reaction rate k, the initial state and the coarse state, through
+    steps_adjoint (device checkpoints of populations, coarse state, solids
+    and masses every `checkpoint_every` steps; every step re-run once,
+    recorded, and reversed on the GPU).  Also one record + adjoint pair timed
+    alone with HIP events."""
+    import numpy as np
+    import torch
+    from paper_1601_02708_amd import hyb
+    N, P = cfg.N, cfg.max_iter
+    n = substeps // cfg.eta
+    ones = np.ones((9, N, N))
+    conv0 = g.dissolution_state()[2]
+    t0 = time.perf_counter()
+    lF, ld, gk, _ = hyb.steps_adjoint(g, n, lambda k, F, d: (ones, None) if k == n else (None, None), P,
+                                      checkpoint_every=checkpoint_every, state_in_cotangent=False)
+    wall = time.perf_counter() - t0
+    conv1 = g.dissolution_state()[2]
+    # one step's record and adjoint alone, on the GPU clock
+    tape = g.step_tape(P)
+    lf = torch.ones((9, N, N), dtype=torch.float64, device=g.dev)
+    lfo = torch.empty_like(lf)
+    ld_ = torch.zeros((cfg.M + 1) ** 2, dtype=torch.float64, device=g.dev)
+    ldo = torch.empty_like(ld_)
+    gk1 = torch.zeros((N, N), dtype=torch.float64, device=g.dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(g.stream)
+    g.step_record(P, tape)
+    ev[1].record(g.stream)
+    g.step_adjoint(tape, lf, ld_, lfo, ldo, gk1)
+    ev[2].record(g.stream)
+    torch.cuda.synchronize()
+    rec_ms, adj_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    lups = P * cfg.eta * N * N
+    tape_bytes = int(tape.numel())
+    del tape
+    return {"substeps": n * cfg.eta, "coarse_steps": n, "checkpoint_every": checkpoint_every,
+            "objective": "sum of all populations after the last step", "wrt": "per-node reaction rate k, f*(t0), d(t0)",
+            "wall_s": round(wall, 2), "solids_converted_in_window": int(conv1 - conv0),
+            "grad_k_l2": float(np.linalg.norm(gk)), "grad_k_finite": bool(np.isfinite(gk).all()),
+            "step_record_ms": round(rec_ms, 3), "step_adjoint_ms": round(adj_ms, 3),
+            "step_adjoint_mlups": round(lups / (adj_ms / 1e3) / 1e6, 1), "tape_bytes": tape_bytes,
+            "mlups_whole_reverse": round(n * lups / wall / 1e6, 1),
+            "note": "wall time: forward rollout with checkpoints, segment re-runs, every step's record and "
+                    "reverse; step_* are one coarse step's record and reverse alone on the GPU clock"}
+
+
+def dissolution_rate(steps=20, warmup=2, timing_steps=3, adjoint=True):
     """The dissolving-solid workload (4096^2, porosity 0.5, FP32, eta = 20,
     256^2 mesh, 2 Schwarz passes, surface reaction at every fluid-solid link,
     seeded per-solid masses): K timed coarse steps after W warmup steps on
@@ -246,6 +297,10 @@ def dissolution_rate(steps=20, warmup=2, timing_steps=3):
     kms, launches = g.kernel_time()
     g.kernel_timing(False)
     sol2, _, conv2 = g.dissolution_state()
+    adj = None
+    if adjoint:
+        print("[bench] dissolving solids: reverse mode over the last 1000 fine steps", file=sys.stderr, flush=True)
+        adj = dissolution_adjoint(g, cfg)
     # geometry of the timing steps (their own commits convert after them)
     s = sol != 0
     pad = np.pad(~s, 1, constant_values=False)
@@ -260,6 +315,7 @@ def dissolution_rate(steps=20, warmup=2, timing_steps=3):
     avg = kms / max(launches, 1)
     lups = steps * cfg.max_iter * cfg.eta * N * N
     g.close()
+    out_adj = {} if adj is None else {"adjoint_fp32": adj}
     return {"workload": (f"{cfg.name}: {N}^2 D2Q9 lattice, random disks (porosity {p.porosity:.4f}), 8-mode "
                          f"stream-function velocity max 0.05, D={cfg.D}, k={cfg.k}, {cfg.M}^2 Q1 SUPG mesh, "
                          f"eta={cfg.eta}, {cfg.max_iter} Schwarz passes; surface reaction kappa_s={cfg.kappa_s} "
@@ -272,7 +328,59 @@ def dissolution_rate(steps=20, warmup=2, timing_steps=3):
             "sweep_avg_launch_ms": round(avg, 5),
             "sweep_algorithmic_bytes_per_launch": int(launch_bytes),
             "sweep_achieved_gbs": round(launch_bytes / (avg / 1e3) / 1e9, 1),
-            "sweep_frac": round(launch_bytes / (avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "sweep_frac": round(launch_bytes / (avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4), **out_adj}
+
+
+def hybrid1d_tables():
+    """The 1-D hybrid of Sec. 7.1 on the GPU for every printed row of the
+    Gaussian-hill tables (tests/golden/gauss1d_tables.txt): the run to
+    T = 0.4 in one launch per row (one workgroup), its coarse and fine
+    max-norm errors against the closed-form solution next to the printed
+    ones, and the GPU time per coarse step; the oracle (NumPy, one thread)
+    timed on one row."""
+    import numpy as np
+    import torch
+    from paper_1601_02708_amd import hyb, inputs
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "gauss1d_tables.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        t, r, hc, hf, L, mi, ec, ef = line.split()
+        rows.append((f"{t}r{r}", float(hc), float(hf), float(L), int(mi), float(ec), float(ef)))
+    hybrid1d_tables.rows = rows
+    out = []
+    T = 0.4
+    for key, hc, hf, L, mi, ec_p, ef_p in rows:
+        g = hyb.Hybrid1D(hc, hf, L, mi, lambda x: inputs.gaussian_hill_1d(x, 0.0))
+        n = int(round(T / g.dt_c))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(g.stream)
+        g.run(n)
+        e1.record(g.stream)
+        d, u = g.state()
+        ms = e0.elapsed_time(e1)
+        ec = float(np.abs(d - inputs.gaussian_hill_1d(g.xc, T)).max())
+        ef = float(np.abs(u - inputs.gaussian_hill_1d(g.xf, T)).max())
+        out.append({"row": key, "h_c": hc, "h_f": hf, "L_ov": L, "max_iter": mi, "eta": g.eta, "coarse_steps": n,
+                    "E_c": ec, "E_f": ef, "printed_E_c": ec_p, "printed_E_f": ef_p, "gpu_ms": round(ms, 3),
+                    "us_per_coarse_step": round(1e3 * ms / n, 2)})
+        g.close()
+    return {"rows": out, "note": "E_f reproduces the printed fine-domain floor at the finest rows; the printed "
+                                 "E_c are not reproduced (see the oracle's pins)"}
+
+
+def cpu_baseline_1d(row, gpu_rows):
+    """The 1-D oracle (NumPy, one thread) on one table row to T = 0.4."""
+    from oracle.hybrid1d import Hybrid1D
+    hc, hf, L, mi = row[1:5]
+    o = Hybrid1D(hc, hf, L, mi)
+    t0 = time.perf_counter()
+    o.run(0.4)
+    dt = time.perf_counter() - t0
+    gpu = [r for r in gpu_rows if r["row"] == row[0]][0]
+    return {"row": row[0], "seconds": round(dt, 3), "cores": 1, "kind": "oracle",
+            "gpu_seconds": round(gpu["gpu_ms"] / 1e3, 4)}
 
 
 def cpu_baseline(problem, min_seconds=10.0, max_steps=6):
@@ -314,6 +422,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision runs")
     ap.add_argument("--no-dissolution", action="store_true", help="skip the dissolving-solid workload")
+    ap.add_argument("--dissolution-only", action="store_true",
+                    help="run only the dissolving-solid workload and print its record (for profiling)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (a plain copy kernel of "
                          "known size, for calibrating HBM traffic counters)")
@@ -326,6 +436,9 @@ def main():
     import numpy as np
     from paper_1601_02708_amd import configs, hyb
 
+    if args.dissolution_only:
+        print(json.dumps({"dissolution": dissolution_rate(adjoint=not args.no_adjoint)}), flush=True)
+        return
     cfg = configs.CONFIGS[args.workload]
     problem = configs.build_problem(cfg)
     N = cfg.N
@@ -421,13 +534,18 @@ def main():
         print("[bench] adjoint", file=sys.stderr, flush=True)
         res["adjoint"] = adjoint_rate(problem, args.precision)
         res["step_adjoint"] = step_adjoint_rate(problem, args.precision)
+    print("[bench] 1-D hybrid tables", file=sys.stderr, flush=True)
+    res["hybrid1d"] = hybrid1d_tables()
     if not args.no_dissolution:
         print("[bench] dissolving solids (dissolve4096, fp32)", file=sys.stderr, flush=True)
         g.close()
-        res["dissolution"] = dissolution_rate()
+        res["dissolution"] = dissolution_rate(adjoint=not args.no_adjoint)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one coarse step)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(problem)
+        if "hybrid1d" in res:
+            row = [r for r in hybrid1d_tables.rows if r[0] == "T1r3"][0]
+            res["cpu_baseline"]["hybrid1d"] = cpu_baseline_1d(row, res["hybrid1d"]["rows"])
     if args.copy_mib > 0:
         import torch
         nbytes = args.copy_mib << 20

@@ -344,6 +344,55 @@ int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const doubl
 int hyb_dissolution_state(hyb_handle *h, uint8_t *solid, double *mass, int64_t *converted);
 int hyb_set_solids(hyb_handle *h, const uint8_t *solid, const double *mass);
 
+/* Checkpoint and restore on the device: the committed state between coarse
+ * steps -- populations f*(t_n) in their storage format, the coarse
+ * solutions d(t_n) and d(t_{n-1}) (the next step's first guess extrapolates
+ * from both), and with dissolving solids the flag words, solid flags and
+ * masses -- copied into or out of a caller's device buffer (256-byte
+ * aligned, hyb_checkpoint_query bytes; the layout is internal to the
+ * library).  A run continued from a loaded checkpoint repeats the original
+ * run bit for bit.  Save needs no pending fine steps; load abandons a coarse
+ * step in progress.  Both enqueue device copies on the handle's stream and
+ * return without waiting. */
+int hyb_checkpoint_query(const hyb_handle *h, size_t *bytes);
+int hyb_checkpoint_save(hyb_handle *h, void *ckpt);
+int hyb_checkpoint_load(hyb_handle *h, const void *ckpt);
+
+/* ---- several fine patches around one coarse subdomain -----------------
+ *
+ * Algorithm 2 (Sec. 6.3) with one coarse subdomain: every Schwarz iteration
+ * advances the coarse subdomain first, with each patch's transferred values
+ * from the previous iteration (the first from the patches' states at t_n),
+ * then advances every patch by eta fine steps from t_n with eq. (MTS) at its
+ * own perimeter.  The coarse Dirichlet rows are the outer edges and, per
+ * patch, the coarse nodes inside it at least overlap_elems elements from its
+ * boundary (patches must not share such a node).
+ *
+ * The patches are handles created with mesh = NULL (their lattice's x0, y0
+ * place them in the coarse domain), every perimeter slot Dirichlet, fixed
+ * solids, one eta and the group's stream; the group writes their interface
+ * arrays a, b (as hyb_set_boundary would) and commits them.  The group owns
+ * the coarse operator (assembled like hyb_create's from D, the nodal
+ * velocity vcoarse [(M+1)^2][2] and the uniform rate k) and per patch the
+ * transfer lists, in the caller's device workspace (hyb_group_query bytes,
+ * 256-byte aligned; lattices: the patches' lattice descriptors, N used).
+ *
+ * hyb_group_step: one coarse step with max_schwarz iterations; synchronises;
+ *   HYB_ENOCONV as hyb_step (the patches are then not committed), or a
+ *   patch's HYB_ENONFINITE.
+ * hyb_group_coarse: the committed coarse solution, host or device
+ *   [(M+1)^2]; synchronises.
+ * The patches' own calls (readouts, checkpoints) keep working; hyb_step and
+ * the reverse mode are not available on them. */
+typedef struct hyb_group hyb_group;
+int hyb_group_query(const hyb_mesh *mesh, int n_patches, const hyb_lattice *lattices, size_t *ws_bytes);
+int hyb_group_create(const hyb_mesh *mesh, int n_patches, hyb_handle *const *patches, double D,
+                     const double *vcoarse, double k, void *workspace, void *stream, hyb_group **out);
+int hyb_group_step(hyb_group *g, int max_schwarz);
+int hyb_group_coarse(hyb_group *g, double *out, int out_is_device);
+void hyb_group_destroy(hyb_group *g);
+const char *hyb_group_last_error(const hyb_group *g);
+
 /* Storage layout actually used: row pitch and plane stride in elements. */
 int hyb_layout(const hyb_handle *h, size_t *pitch, size_t *plane);
 

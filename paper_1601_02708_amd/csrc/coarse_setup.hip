@@ -78,189 +78,16 @@ bool chol_solve(std::vector<double> &G, std::vector<double> &b, int n) {
 
 }  // namespace
 
-std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
-                         int overlap_elems, int N, double x0, double y0, const uint8_t *solid, int pitch,
-                         CoarseHost &out) {
+// Interface lists of one patch against the mesh: coarse-to-fine weights of
+// its perimeter slots and the fine-to-coarse corners of out.fc_nodes (its
+// Gamma_{f->c} nodes, set by the caller), each with its transpose.
+std::string patch_lists(int M, double L, const PatchGeom &g, CoarseHost &out) {
     const int m1 = M + 1;
     const int n = m1 * m1;
     const double h = L / M;
-    out.M = M;
-    out.L = L;
-    out.h = h;
-
-    // --- quadrature tables on the reference square [-1,1]^2 -------------
-    // local nodes 0:(0,0) 1:(1,0) 2:(1,1) 3:(0,1) of element (ex, ey)
-    const int lk[4] = {0, 1, 1, 0}, ll[4] = {0, 0, 1, 1};
-    const double gq = 1.0 / std::sqrt(3.0);
-    double Nv[4][4], Gx[4][4], Gy[4][4];   // [gauss point][local node]
-    for (int g = 0; g < 4; ++g) {
-        const double xi = (g & 1) ? gq : -gq, et = (g & 2) ? gq : -gq;
-        for (int a = 0; a < 4; ++a) {
-            const double sa = lk[a] ? 1.0 : -1.0, ta = ll[a] ? 1.0 : -1.0;
-            Nv[g][a] = 0.25 * (1.0 + sa * xi) * (1.0 + ta * et);
-            Gx[g][a] = 0.5 * sa * (1.0 + ta * et) / h;
-            Gy[g][a] = 0.5 * ta * (1.0 + sa * xi) / h;
-        }
-    }
-    const double wq = 0.25 * h * h;   // Gauss weight 1 times det J
-
-    Stencil A(M, 3), B(M, 3);
-    for (int ey = 0; ey < M; ++ey) {
-        for (int ex = 0; ex < M; ++ex) {
-            int node[4];
-            for (int a = 0; a < 4; ++a) node[a] = (ey + ll[a]) * m1 + (ex + lk[a]);
-            double cap[4][4] = {}, tr[4][4] = {};
-            for (int g = 0; g < 4; ++g) {
-                double vx = 0.0, vy = 0.0;
-                for (int a = 0; a < 4; ++a) {
-                    vx += Nv[g][a] * vnodes[2 * node[a]];
-                    vy += Nv[g][a] * vnodes[2 * node[a] + 1];
-                }
-                const double speed = std::sqrt(vx * vx + vy * vy);
-                double tau = 0.0;
-                if (supg && speed > 0.0) tau = h / (2.0 * speed) * upwind_chi(speed * h / (2.0 * D));
-                double adv[4];
-                for (int a = 0; a < 4; ++a) adv[a] = vx * Gx[g][a] + vy * Gy[g][a];
-                for (int a = 0; a < 4; ++a) {
-                    for (int b = 0; b < 4; ++b) {
-                        const double mass = Nv[g][a] * Nv[g][b];
-                        const double galerkin = Nv[g][a] * adv[b] + D * (Gx[g][a] * Gx[g][b] + Gy[g][a] * Gy[g][b]) +
-                                                k * mass;
-                        const double stab_cap = tau * adv[a] * Nv[g][b];
-                        const double stab_tr = tau * adv[a] * (adv[b] + k * Nv[g][b]);
-                        cap[a][b] += wq * (mass + stab_cap);
-                        tr[a][b] += wq * (galerkin + stab_tr);
-                    }
-                }
-            }
-            for (int a = 0; a < 4; ++a) {
-                for (int b = 0; b < 4; ++b) {
-                    const int dk = lk[b] - lk[a], dl = ll[b] - ll[a];
-                    A.at(node[a], dk, dl) += cap[a][b] + 0.5 * dt * tr[a][b];
-                    B.at(node[a], dk, dl) += cap[a][b] - 0.5 * dt * tr[a][b];
-                }
-            }
-        }
-    }
-
-    // --- Dirichlet sets ---------------------------------------------------
-    out.dkind.assign(n, -1);
-    out.fc_nodes.clear();
-    const double ov = overlap_elems * h, tol = 1e-9 * h;
-    const double x1 = x0 + (N - 1), y1 = y0 + (N - 1);
-    for (int l = 0; l < m1; ++l) {
-        for (int kk = 0; kk < m1; ++kk) {
-            const int id = l * m1 + kk;
-            if (kk == 0 || kk == M || l == 0 || l == M) {
-                out.dkind[id] = -2;
-                continue;
-            }
-            const double X = kk * h, Y = l * h;
-            if (X - x0 >= ov - tol && x1 - X >= ov - tol && Y - y0 >= ov - tol && y1 - Y >= ov - tol) {
-                out.dkind[id] = (int)out.fc_nodes.size();
-                out.fc_nodes.push_back(id);
-            }
-        }
-    }
-    // A Dirichlet row becomes a_ii e_i with the assembled diagonal a_ii (the
-    // right-hand side is scaled by a_ii too), so every row of A carries the
-    // same scale (~h^2) and the preconditioner's local systems stay well
-    // conditioned even when h is hundreds of lattice units.
-    for (int id = 0; id < n; ++id) {
-        if (out.dkind[id] == -1) continue;
-        const double diag = A.at(id, 0, 0);
-        for (int dl = -1; dl <= 1; ++dl)
-            for (int dk = -1; dk <= 1; ++dk) A.at(id, dk, dl) = 0.0;
-        A.at(id, 0, 0) = diag > 0.0 ? diag : 1.0;
-    }
-
-    // --- sparse approximate inverse of A ---------------------------------
-    constexpr int R = kSpaiRadius, W = kSpaiW;
-    Stencil P(M, W);
-    std::vector<int> pk, pl;
-    std::vector<double> G, rhs;
-    for (int l = 0; l < m1; ++l) {
-        for (int kk = 0; kk < m1; ++kk) {
-            const int id = l * m1 + kk;
-            pk.clear();
-            pl.clear();
-            for (int dl = -R; dl <= R; ++dl)
-                for (int dk = -R; dk <= R; ++dk)
-                    if (kk + dk >= 0 && kk + dk <= M && l + dl >= 0 && l + dl <= M) {
-                        pk.push_back(dk);
-                        pl.push_back(dl);
-                    }
-            const int np = (int)pk.size();
-            G.assign((size_t)np * np, 0.0);
-            rhs.assign(np, 0.0);
-            for (int a = 0; a < np; ++a) {
-                const int na = (l + pl[a]) * m1 + (kk + pk[a]);
-                // rhs_a = A(na, id): column id lies at offset (-pk, -pl) from row na
-                rhs[a] = A.get(na, -pk[a], -pl[a]);
-                for (int b = a; b < np; ++b) {
-                    const int nb = (l + pl[b]) * m1 + (kk + pk[b]);
-                    // sum over columns c of A(na, c) A(nb, c)
-                    double s = 0.0;
-                    for (int dl = -1; dl <= 1; ++dl)
-                        for (int dk = -1; dk <= 1; ++dk) {
-                            const double va = A.get(na, dk, dl);
-                            if (va == 0.0) continue;
-                            s += va * A.get(nb, dk + pk[a] - pk[b], dl + pl[a] - pl[b]);
-                        }
-                    G[a * np + b] = s;
-                    G[b * np + a] = s;
-                }
-            }
-            if (chol_solve(G, rhs, np)) {
-                for (int a = 0; a < np; ++a) P.at(id, pk[a], pl[a]) = rhs[a];
-            } else {
-                P.at(id, 0, 0) = 1.0 / A.get(id, 0, 0);   // Jacobi row as a fallback
-            }
-        }
-    }
-    Stencil AP(M, kApW);
-    for (int l = 0; l < m1; ++l) {
-        for (int kk = 0; kk < m1; ++kk) {
-            const int id = l * m1 + kk;
-            for (int dl = -1; dl <= 1; ++dl)
-                for (int dk = -1; dk <= 1; ++dk) {
-                    const double a = A.get(id, dk, dl);
-                    if (a == 0.0) continue;
-                    const int nk = kk + dk, nl = l + dl;
-                    const int nid = nl * m1 + nk;
-                    for (int el = -R; el <= R; ++el)
-                        for (int ek = -R; ek <= R; ++ek) {
-                            const double pv = P.get(nid, ek, el);
-                            if (pv != 0.0) AP.at(id, dk + ek, dl + el) += a * pv;
-                        }
-                }
-        }
-    }
-    for (double x : A.c)
-        if (!std::isfinite(x)) return "coarse operator has non-finite entries";
-    for (double x : P.c)
-        if (!std::isfinite(x)) return "coarse preconditioner has non-finite entries";
-    // transposes for the reverse mode: entry (id, offset o) of S^T is entry
-    // (id + o, -o) of S (zero when id + o leaves the mesh)
-    auto transpose = [&](const Stencil &S) {
-        Stencil T(M, S.W);
-        for (int l = 0; l < m1; ++l)
-            for (int kk = 0; kk < m1; ++kk)
-                for (int dl = -S.R; dl <= S.R; ++dl)
-                    for (int dk = -S.R; dk <= S.R; ++dk) {
-                        const int nk = kk + dk, nl = l + dl;
-                        if (nk < 0 || nk > M || nl < 0 || nl > M) continue;
-                        T.at(l * m1 + kk, dk, dl) = S.get(nl * m1 + nk, -dk, -dl);
-                    }
-        return T;
-    };
-    out.APT = transpose(AP).c;
-    out.PT = transpose(P).c;
-    out.A9 = std::move(A.c);
-    out.B9 = std::move(B.c);
-    out.P = std::move(P.c);
-    out.AP = std::move(AP.c);
-
+    const int N = g.N, pitch = g.pitch;
+    const double x0 = g.x0, y0 = g.y0;
+    const uint8_t *solid = g.solid;
     // --- coarse -> fine: containing element of each perimeter slot --------
     const int S = M + 1 + 2 * kCoarseHalo;
     auto padded = [&](int kk, int l) { return (l + kCoarseHalo) * S + (kk + kCoarseHalo); };
@@ -409,6 +236,220 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
         if (e.empty()) out.f2cD_ptr.assign(1, 0);
     }
     return std::string();
+}
+
+std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
+                         int overlap_elems, const std::vector<PatchGeom> &patches, CoarseHost &out,
+                         std::vector<CoarseHost> *more) {
+    if (patches.empty()) return "no lattice patch";
+    const int m1 = M + 1;
+    const int n = m1 * m1;
+    const double h = L / M;
+    out.M = M;
+    out.L = L;
+    out.h = h;
+
+    // --- quadrature tables on the reference square [-1,1]^2 -------------
+    // local nodes 0:(0,0) 1:(1,0) 2:(1,1) 3:(0,1) of element (ex, ey)
+    const int lk[4] = {0, 1, 1, 0}, ll[4] = {0, 0, 1, 1};
+    const double gq = 1.0 / std::sqrt(3.0);
+    double Nv[4][4], Gx[4][4], Gy[4][4];   // [gauss point][local node]
+    for (int g = 0; g < 4; ++g) {
+        const double xi = (g & 1) ? gq : -gq, et = (g & 2) ? gq : -gq;
+        for (int a = 0; a < 4; ++a) {
+            const double sa = lk[a] ? 1.0 : -1.0, ta = ll[a] ? 1.0 : -1.0;
+            Nv[g][a] = 0.25 * (1.0 + sa * xi) * (1.0 + ta * et);
+            Gx[g][a] = 0.5 * sa * (1.0 + ta * et) / h;
+            Gy[g][a] = 0.5 * ta * (1.0 + sa * xi) / h;
+        }
+    }
+    const double wq = 0.25 * h * h;   // Gauss weight 1 times det J
+
+    Stencil A(M, 3), B(M, 3);
+    for (int ey = 0; ey < M; ++ey) {
+        for (int ex = 0; ex < M; ++ex) {
+            int node[4];
+            for (int a = 0; a < 4; ++a) node[a] = (ey + ll[a]) * m1 + (ex + lk[a]);
+            double cap[4][4] = {}, tr[4][4] = {};
+            for (int g = 0; g < 4; ++g) {
+                double vx = 0.0, vy = 0.0;
+                for (int a = 0; a < 4; ++a) {
+                    vx += Nv[g][a] * vnodes[2 * node[a]];
+                    vy += Nv[g][a] * vnodes[2 * node[a] + 1];
+                }
+                const double speed = std::sqrt(vx * vx + vy * vy);
+                double tau = 0.0;
+                if (supg && speed > 0.0) tau = h / (2.0 * speed) * upwind_chi(speed * h / (2.0 * D));
+                double adv[4];
+                for (int a = 0; a < 4; ++a) adv[a] = vx * Gx[g][a] + vy * Gy[g][a];
+                for (int a = 0; a < 4; ++a) {
+                    for (int b = 0; b < 4; ++b) {
+                        const double mass = Nv[g][a] * Nv[g][b];
+                        const double galerkin = Nv[g][a] * adv[b] + D * (Gx[g][a] * Gx[g][b] + Gy[g][a] * Gy[g][b]) +
+                                                k * mass;
+                        const double stab_cap = tau * adv[a] * Nv[g][b];
+                        const double stab_tr = tau * adv[a] * (adv[b] + k * Nv[g][b]);
+                        cap[a][b] += wq * (mass + stab_cap);
+                        tr[a][b] += wq * (galerkin + stab_tr);
+                    }
+                }
+            }
+            for (int a = 0; a < 4; ++a) {
+                for (int b = 0; b < 4; ++b) {
+                    const int dk = lk[b] - lk[a], dl = ll[b] - ll[a];
+                    A.at(node[a], dk, dl) += cap[a][b] + 0.5 * dt * tr[a][b];
+                    B.at(node[a], dk, dl) += cap[a][b] - 0.5 * dt * tr[a][b];
+                }
+            }
+        }
+    }
+
+    // --- Dirichlet sets ---------------------------------------------------
+    // Gamma_{f->c} of patch p: the coarse nodes inside it at least
+    // overlap_elems elements from its boundary; indices run patch by patch
+    // (each patch's transferred values are one contiguous run)
+    out.dkind.assign(n, -1);
+    for (int l = 0; l < m1; ++l)
+        for (int kk = 0; kk < m1; ++kk)
+            if (kk == 0 || kk == M || l == 0 || l == M) out.dkind[l * m1 + kk] = -2;
+    const double ov = overlap_elems * h, tol = 1e-9 * h;
+    std::vector<std::vector<int>> fcn(patches.size());
+    int nfc_all = 0;
+    for (size_t p = 0; p < patches.size(); ++p) {
+        const PatchGeom &g = patches[p];
+        const double x1 = g.x0 + (g.N - 1), y1 = g.y0 + (g.N - 1);
+        for (int l = 1; l < M; ++l) {
+            for (int kk = 1; kk < M; ++kk) {
+                const int id = l * m1 + kk;
+                const double X = kk * h, Y = l * h;
+                if (X - g.x0 >= ov - tol && x1 - X >= ov - tol && Y - g.y0 >= ov - tol && y1 - Y >= ov - tol) {
+                    if (out.dkind[id] != -1) return "a coarse node lies on the interface of two patches";
+                    out.dkind[id] = nfc_all++;
+                    fcn[p].push_back(id);
+                }
+            }
+        }
+    }
+    out.fc_nodes = fcn[0];
+    if (more) {
+        more->assign(patches.size() - 1, CoarseHost());
+        for (size_t p = 1; p < patches.size(); ++p) {
+            CoarseHost &o = (*more)[p - 1];
+            o.M = M;
+            o.L = L;
+            o.h = h;
+            o.fc_nodes = fcn[p];
+            std::string msg = patch_lists(M, L, patches[p], o);
+            if (!msg.empty()) return msg;
+        }
+    }
+    // A Dirichlet row becomes a_ii e_i with the assembled diagonal a_ii (the
+    // right-hand side is scaled by a_ii too), so every row of A carries the
+    // same scale (~h^2) and the preconditioner's local systems stay well
+    // conditioned even when h is hundreds of lattice units.
+    for (int id = 0; id < n; ++id) {
+        if (out.dkind[id] == -1) continue;
+        const double diag = A.at(id, 0, 0);
+        for (int dl = -1; dl <= 1; ++dl)
+            for (int dk = -1; dk <= 1; ++dk) A.at(id, dk, dl) = 0.0;
+        A.at(id, 0, 0) = diag > 0.0 ? diag : 1.0;
+    }
+
+    // --- sparse approximate inverse of A ---------------------------------
+    constexpr int R = kSpaiRadius, W = kSpaiW;
+    Stencil P(M, W);
+    std::vector<int> pk, pl;
+    std::vector<double> G, rhs;
+    for (int l = 0; l < m1; ++l) {
+        for (int kk = 0; kk < m1; ++kk) {
+            const int id = l * m1 + kk;
+            pk.clear();
+            pl.clear();
+            for (int dl = -R; dl <= R; ++dl)
+                for (int dk = -R; dk <= R; ++dk)
+                    if (kk + dk >= 0 && kk + dk <= M && l + dl >= 0 && l + dl <= M) {
+                        pk.push_back(dk);
+                        pl.push_back(dl);
+                    }
+            const int np = (int)pk.size();
+            G.assign((size_t)np * np, 0.0);
+            rhs.assign(np, 0.0);
+            for (int a = 0; a < np; ++a) {
+                const int na = (l + pl[a]) * m1 + (kk + pk[a]);
+                // rhs_a = A(na, id): column id lies at offset (-pk, -pl) from row na
+                rhs[a] = A.get(na, -pk[a], -pl[a]);
+                for (int b = a; b < np; ++b) {
+                    const int nb = (l + pl[b]) * m1 + (kk + pk[b]);
+                    // sum over columns c of A(na, c) A(nb, c)
+                    double s = 0.0;
+                    for (int dl = -1; dl <= 1; ++dl)
+                        for (int dk = -1; dk <= 1; ++dk) {
+                            const double va = A.get(na, dk, dl);
+                            if (va == 0.0) continue;
+                            s += va * A.get(nb, dk + pk[a] - pk[b], dl + pl[a] - pl[b]);
+                        }
+                    G[a * np + b] = s;
+                    G[b * np + a] = s;
+                }
+            }
+            if (chol_solve(G, rhs, np)) {
+                for (int a = 0; a < np; ++a) P.at(id, pk[a], pl[a]) = rhs[a];
+            } else {
+                P.at(id, 0, 0) = 1.0 / A.get(id, 0, 0);   // Jacobi row as a fallback
+            }
+        }
+    }
+    Stencil AP(M, kApW);
+    for (int l = 0; l < m1; ++l) {
+        for (int kk = 0; kk < m1; ++kk) {
+            const int id = l * m1 + kk;
+            for (int dl = -1; dl <= 1; ++dl)
+                for (int dk = -1; dk <= 1; ++dk) {
+                    const double a = A.get(id, dk, dl);
+                    if (a == 0.0) continue;
+                    const int nk = kk + dk, nl = l + dl;
+                    const int nid = nl * m1 + nk;
+                    for (int el = -R; el <= R; ++el)
+                        for (int ek = -R; ek <= R; ++ek) {
+                            const double pv = P.get(nid, ek, el);
+                            if (pv != 0.0) AP.at(id, dk + ek, dl + el) += a * pv;
+                        }
+                }
+        }
+    }
+    for (double x : A.c)
+        if (!std::isfinite(x)) return "coarse operator has non-finite entries";
+    for (double x : P.c)
+        if (!std::isfinite(x)) return "coarse preconditioner has non-finite entries";
+    // transposes for the reverse mode: entry (id, offset o) of S^T is entry
+    // (id + o, -o) of S (zero when id + o leaves the mesh)
+    auto transpose = [&](const Stencil &S) {
+        Stencil T(M, S.W);
+        for (int l = 0; l < m1; ++l)
+            for (int kk = 0; kk < m1; ++kk)
+                for (int dl = -S.R; dl <= S.R; ++dl)
+                    for (int dk = -S.R; dk <= S.R; ++dk) {
+                        const int nk = kk + dk, nl = l + dl;
+                        if (nk < 0 || nk > M || nl < 0 || nl > M) continue;
+                        T.at(l * m1 + kk, dk, dl) = S.get(nl * m1 + nk, -dk, -dl);
+                    }
+        return T;
+    };
+    out.APT = transpose(AP).c;
+    out.PT = transpose(P).c;
+    out.A9 = std::move(A.c);
+    out.B9 = std::move(B.c);
+    out.P = std::move(P.c);
+    out.AP = std::move(AP.c);
+
+    return patch_lists(M, L, patches[0], out);
+}
+
+std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
+                         int overlap_elems, int N, double x0, double y0, const uint8_t *solid, int pitch,
+                         CoarseHost &out) {
+    const std::vector<PatchGeom> one{PatchGeom{N, x0, y0, solid, pitch}};
+    return build_coarse(M, L, D, k, dt, supg, vnodes, overlap_elems, one, out, nullptr);
 }
 
 }  // namespace hyb

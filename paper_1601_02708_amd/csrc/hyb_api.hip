@@ -1404,6 +1404,100 @@ int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const doubl
     return HYB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checkpoint layout (device bytes, 256-byte aligned parts): the committed
+// populations (storage format), the coarse solutions d(t_n) and d(t_{n-1})
+// (padded), and with dissolving solids the flag words, solid flags and
+// masses.
+struct CkptLayout {
+    size_t f = 0, xn = 0, xprev = 0, mask = 0, solid = 0, mass = 0, total = 0;
+};
+
+CkptLayout ckpt_layout(const hyb_handle *h) {
+    CkptLayout C;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    const size_t nodes = (size_t)h->N * h->lay.pitch;
+    C.f = take(h->lay.f_bytes);
+    if (h->has_mesh) {
+        C.xn = take(h->lay.vec_len * 8);
+        C.xprev = take(h->lay.vec_len * 8);
+    }
+    if (h->dissolve_ws) {
+        C.mask = take(nodes * 2);
+        C.solid = take(nodes);
+        C.mass = take(nodes * 8);
+    }
+    C.total = off;
+    return C;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hyb_checkpoint_query(const hyb_handle *h, size_t *bytes) {
+    if (!h || !bytes) return HYB_EINVAL;
+    *bytes = ckpt_layout(h).total;
+    return HYB_OK;
+}
+
+int hyb_checkpoint_save(hyb_handle *h, void *ckpt) {
+    if (!h || !ckpt || reinterpret_cast<uintptr_t>(ckpt) % kAlign) return HYB_EINVAL;
+    if (h->jsub != 0 || h->cur != h->frozen)
+        return h->fail(HYB_EINVAL, "checkpoint between coarse steps (fine steps are pending)");
+    const CkptLayout C = ckpt_layout(h);
+    char *b = static_cast<char *>(ckpt);
+    const size_t nodes = (size_t)h->N * h->lay.pitch;
+    auto cp = [&](void *dst, const void *src, size_t n) {
+        return hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, h->stream);
+    };
+    HIP_TRY(h, cp(b + C.f, h->f[h->frozen], h->lay.f_bytes));
+    if (h->has_mesh) {
+        HIP_TRY(h, cp(b + C.xn, h->cd.xn, h->lay.vec_len * 8));
+        HIP_TRY(h, cp(b + C.xprev, h->cd.xprev, h->lay.vec_len * 8));
+    }
+    if (h->dissolve_ws) {
+        HIP_TRY(h, cp(b + C.mask, h->mask, nodes * 2));
+        HIP_TRY(h, cp(b + C.solid, h->solid_now, nodes));
+        HIP_TRY(h, cp(b + C.mass, h->mass, nodes * 8));
+    }
+    return HYB_OK;
+}
+
+int hyb_checkpoint_load(hyb_handle *h, const void *ckpt) {
+    if (!h || !ckpt || reinterpret_cast<uintptr_t>(ckpt) % kAlign) return HYB_EINVAL;
+    const CkptLayout C = ckpt_layout(h);
+    const char *b = static_cast<const char *>(ckpt);
+    const size_t nodes = (size_t)h->N * h->lay.pitch;
+    auto cp = [&](void *dst, const void *src, size_t n) {
+        return hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, h->stream);
+    };
+    HIP_TRY(h, cp(h->f[h->frozen], b + C.f, h->lay.f_bytes));
+    if (h->has_mesh) {
+        HIP_TRY(h, cp(h->cd.xn, b + C.xn, h->lay.vec_len * 8));
+        HIP_TRY(h, cp(h->cd.xprev, b + C.xprev, h->lay.vec_len * 8));
+    }
+    if (h->dissolve_ws) {
+        HIP_TRY(h, cp(h->mask, b + C.mask, nodes * 2));
+        HIP_TRY(h, cp(h->solid_now, b + C.solid, nodes));
+        HIP_TRY(h, cp(h->mass, b + C.mass, nodes * 8));
+        h->solid_host_stale = true;
+        h->flux_valid = false;
+    }
+    h->cur = h->frozen;
+    h->jsub = 0;
+    h->solved_this_step = false;
+    return HYB_OK;
+}
+
 int hyb_set_solids(hyb_handle *h, const uint8_t *solid, const double *mass) {
     if (!h || !solid || !mass) return HYB_EINVAL;
     if (!h->dissolve_ws) return h->fail(HYB_EINVAL, "the handle was created without dissolution");
@@ -1453,5 +1547,304 @@ int hyb_dissolution_state(hyb_handle *h, uint8_t *solid, double *mass, int64_t *
     }
     return HYB_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Several fine patches around one coarse subdomain (Algorithm 2, Sec. 6.3):
+// the patches are lattice-only handles (their perimeter values a, b are the
+// interface arrays of hyb_set_boundary); the group owns the coarse operator,
+// whose Dirichlet rows are the outer edge and every patch's Gamma_{f->c},
+// and per patch the two transfer lists.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct GroupLayout {
+    size_t A9 = 0, B9 = 0, AP = 0, P = 0, dkind = 0, vec = 0, partials = 0, state = 0, kres = 0, ufc = 0;
+    std::vector<size_t> c2f_idx, c2f_w, fc_idx, fc_w;
+    size_t total = 0;
+    int n = 0, S = 0, grid = 0;
+    size_t vec_len = 0;
+};
+
+GroupLayout group_layout(int M, const std::vector<int> &patch_N) {
+    GroupLayout G;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    G.n = (M + 1) * (M + 1);
+    G.S = M + 1 + 2 * kCoarseHalo;
+    G.grid = coarse_grid(G.n);
+    G.vec_len = (size_t)G.S * G.S;
+    G.A9 = take((size_t)G.n * 9 * 8);
+    G.B9 = take((size_t)G.n * 9 * 8);
+    G.AP = take((size_t)G.n * kApW * kApW * 8);
+    G.P = take((size_t)G.n * kSpaiW * kSpaiW * 8);
+    G.dkind = take((size_t)G.n * 4);
+    G.vec = take(12 * align_up(G.vec_len * 8, kAlign));
+    G.partials = take((size_t)4 * kPartialValues * coarse_grid8(G.n) * 8);
+    G.state = take(sizeof(KrylovState));
+    G.kres = take(sizeof(KrylovResult));
+    G.ufc = take((size_t)G.n * 8);
+    for (int N : patch_N) {
+        const size_t nslots = 4 * (size_t)(N - 1);
+        G.c2f_idx.push_back(take(nslots * 4 * 4));
+        G.c2f_w.push_back(take(nslots * 4 * 8));
+        G.fc_idx.push_back(take((size_t)G.n * 4 * 4));
+        G.fc_w.push_back(take((size_t)G.n * 4 * 8));
+    }
+    G.total = off;
+    return G;
+}
+
+}  // namespace
+
+struct hyb_group {
+    std::string err;
+    std::vector<hyb_handle *> patches;
+    std::vector<int> nfc, off;          // Gamma_{f->c} nodes of each patch and their run's start
+    std::vector<int *> c2f_idx, fc_idx;
+    std::vector<double *> c2f_w, fc_w;
+    GroupLayout lay;
+    CoarseDev cd{};
+    double *ufc = nullptr;
+    KrylovResult *kres = nullptr;
+    hipStream_t stream = nullptr;
+    int M = 0, eta = 1;
+    bool solved = false;
+    int last_iters = 8, budget = 0, cap = 0;
+    int fail(int code, const std::string &msg) {
+        err = msg;
+        return code;
+    }
+};
+
+extern "C" {
+
+int hyb_group_query(const hyb_mesh *mesh, int n, const hyb_lattice *lattices, size_t *ws_bytes) {
+    if (!mesh || mesh->M < 2 || n < 1 || !lattices || !ws_bytes) return HYB_EINVAL;
+    std::vector<int> Ns;
+    for (int p = 0; p < n; ++p) {
+        if (lattices[p].N < 3) return HYB_EINVAL;
+        Ns.push_back(lattices[p].N);
+    }
+    *ws_bytes = group_layout(mesh->M, Ns).total;
+    return HYB_OK;
+}
+
+int hyb_group_create(const hyb_mesh *mesh, int n, hyb_handle *const *patches, double D, const double *vcoarse,
+                     double k, void *workspace, void *stream, hyb_group **out) {
+    if (!out) return HYB_EINVAL;
+    *out = nullptr;
+    if (!mesh || mesh->M < 2 || !(mesh->L > 0.0) || !mesh->d0 || mesh->overlap_elems < 1 || n < 1 || !patches ||
+        !vcoarse || !(D > 0.0) || !(k >= 0.0 && k < 1.0) || !workspace ||
+        reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return HYB_EINVAL;
+    std::vector<PatchGeom> geo;
+    std::vector<int> Ns;
+    for (int p = 0; p < n; ++p) {
+        const hyb_handle *h = patches[p];
+        if (!h || h->has_mesh || h->kinds_set || h->dissolve_ws || h->eta != patches[0]->eta) {
+            std::fprintf(stderr, "hyb_group_create: patches must be lattice-only handles with Dirichlet perimeters, "
+                                 "fixed solids and one eta\n");
+            return HYB_EINVAL;
+        }
+        if (h->x0 < 0 || h->y0 < 0 || h->x0 + (h->N - 1) > mesh->L || h->y0 + (h->N - 1) > mesh->L) {
+            std::fprintf(stderr, "hyb_group_create: patch %d lies outside the coarse domain\n", p);
+            return HYB_EINVAL;
+        }
+        geo.push_back(PatchGeom{h->N, h->x0, h->y0, h->solid_host.data(), h->lay.pitch});
+        Ns.push_back(h->N);
+    }
+    CoarseHost ch;
+    std::vector<CoarseHost> more;
+    const std::string msg = build_coarse(mesh->M, mesh->L, D, k, (double)patches[0]->eta, mesh->supg, vcoarse,
+                                         mesh->overlap_elems, geo, ch, &more);
+    if (!msg.empty()) {
+        std::fprintf(stderr, "hyb_group_create: %s\n", msg.c_str());
+        return HYB_EINVAL;
+    }
+    hyb_group *g = new hyb_group();
+    g->lay = group_layout(mesh->M, Ns);
+    const GroupLayout &L = g->lay;
+    g->stream = static_cast<hipStream_t>(stream);
+    g->M = mesh->M;
+    g->eta = patches[0]->eta;
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t st = g->stream;
+    auto bail = [&](hipError_t e, const char *what) {
+        std::fprintf(stderr, "hyb_group_create: %s: %s\n", what, hipGetErrorString(e));
+        delete g;
+        return HYB_EHIP;
+    };
+#define GROUP_TRY(call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return bail(e_, #call);     \
+    } while (0)
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    GROUP_TRY(hipMemsetAsync(ws, 0, L.total, st));
+    int off = 0;
+    for (int p = 0; p < n; ++p) {
+        const CoarseHost &c = p == 0 ? ch : more[p - 1];
+        g->patches.push_back(patches[p]);
+        g->nfc.push_back((int)c.fc_nodes.size());
+        g->off.push_back(off);
+        off += (int)c.fc_nodes.size();
+        g->c2f_idx.push_back(reinterpret_cast<int *>(ws + L.c2f_idx[p]));
+        g->c2f_w.push_back(reinterpret_cast<double *>(ws + L.c2f_w[p]));
+        g->fc_idx.push_back(reinterpret_cast<int *>(ws + L.fc_idx[p]));
+        g->fc_w.push_back(reinterpret_cast<double *>(ws + L.fc_w[p]));
+        GROUP_TRY(up(g->c2f_idx[p], c.c2f_idx.data(), c.c2f_idx.size() * 4));
+        GROUP_TRY(up(g->c2f_w[p], c.c2f_w.data(), c.c2f_w.size() * 8));
+        if (!c.fc_nodes.empty()) {
+            GROUP_TRY(up(g->fc_idx[p], c.fc_idx.data(), c.fc_idx.size() * 4));
+            GROUP_TRY(up(g->fc_w[p], c.fc_w.data(), c.fc_w.size() * 8));
+        }
+    }
+    CoarseDev &c = g->cd;
+    c.M = mesh->M;
+    c.n = L.n;
+    c.S = L.S;
+    c.grid = L.grid;
+    c.grid8 = coarse_grid8(L.n);
+    c.pstride = c.grid8;
+    c.A9 = reinterpret_cast<const double *>(ws + L.A9);
+    c.B9 = reinterpret_cast<const double *>(ws + L.B9);
+    c.AP = reinterpret_cast<const double *>(ws + L.AP);
+    c.P = reinterpret_cast<const double *>(ws + L.P);
+    c.dkind = reinterpret_cast<const int *>(ws + L.dkind);
+    c.outer_value = mesh->outer_value;
+    g->ufc = reinterpret_cast<double *>(ws + L.ufc);
+    c.ufc = g->ufc;
+    const size_t vstride = align_up(L.vec_len * 8, kAlign);
+    double *vec[12];
+    for (int v = 0; v < 12; ++v) vec[v] = reinterpret_cast<double *>(ws + L.vec + v * vstride);
+    c.xn = vec[0];
+    c.x1 = vec[1];
+    c.r = vec[2];
+    c.rh = vec[3];
+    c.p = vec[4];
+    c.v = vec[5];
+    c.s = vec[6];
+    c.t = vec[7];
+    c.y = vec[8];
+    c.w = vec[9];
+    c.z = vec[10];
+    c.xprev = vec[11];
+    c.partials = reinterpret_cast<double *>(ws + L.partials);
+    c.state = reinterpret_cast<KrylovState *>(ws + L.state);
+    g->kres = reinterpret_cast<KrylovResult *>(ws + L.kres);
+    c.result = g->kres;
+    const std::vector<double> A9t = offset_major(ch.A9, L.n, 9), B9t = offset_major(ch.B9, L.n, 9);
+    const std::vector<double> Pt = offset_major(ch.P, L.n, kSpaiW * kSpaiW);
+    GROUP_TRY(up((void *)c.A9, A9t.data(), A9t.size() * 8));
+    GROUP_TRY(up((void *)c.B9, B9t.data(), B9t.size() * 8));
+    GROUP_TRY(up((void *)c.AP, ch.AP.data(), ch.AP.size() * 8));
+    GROUP_TRY(up((void *)c.P, Pt.data(), Pt.size() * 8));
+    GROUP_TRY(up((void *)c.dkind, ch.dkind.data(), ch.dkind.size() * 4));
+    std::vector<double> xp(L.vec_len, 0.0);
+    const int m1 = mesh->M + 1;
+    for (int l = 0; l < m1; ++l)
+        for (int kk = 0; kk < m1; ++kk) xp[(size_t)(l + kCoarseHalo) * L.S + kk + kCoarseHalo] = mesh->d0[l * m1 + kk];
+    GROUP_TRY(up(c.xn, xp.data(), xp.size() * 8));
+    GROUP_TRY(up(c.x1, xp.data(), xp.size() * 8));
+    GROUP_TRY(up(c.xprev, xp.data(), xp.size() * 8));
+    GROUP_TRY(hipStreamSynchronize(st));
+#undef GROUP_TRY
+    *out = g;
+    return HYB_OK;
+}
+
+int hyb_group_step(hyb_group *g, int max_schwarz) {
+    if (!g) return HYB_EINVAL;
+    if (max_schwarz < 1) return g->fail(HYB_EINVAL, "max_schwarz must be >= 1");
+    for (hyb_handle *h : g->patches)
+        if (h->stream != g->stream) return g->fail(HYB_EINVAL, "the patches must use the group's stream");
+    auto hip = [&](hipError_t e, const char *what) {
+        return e == hipSuccess ? HYB_OK : g->fail(HYB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    int rc = HYB_OK;
+    const int np = (int)g->patches.size();
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        for (hyb_handle *h : g->patches) {
+            h->cur = h->frozen;
+            h->jsub = 0;
+        }
+        g->solved = false;
+        for (int it = 0; it < max_schwarz; ++it) {
+            // every patch's transfer (its state at t_n, then its last result)
+            for (int p = 0; p < np; ++p) {
+                hyb_handle *h = g->patches[p];
+                LbmArgs a = h->lbm_args(h->cur, -1);
+                if ((rc = hip(launch_f2c(a, g->fc_idx[p], g->fc_w[p], g->nfc[p], g->ufc + g->off[p], h->prec,
+                                         g->stream), "fine-to-coarse")) != HYB_OK)
+                    return rc;
+            }
+            // the shared coarse step
+            if (!g->solved && (rc = hip(launch_coarse_extrapolate(g->cd, g->stream), "extrapolate")) != HYB_OK)
+                return rc;
+            g->budget = std::min(200, std::max(4, g->last_iters + 2));
+            g->cap = 200;
+            if ((rc = hip(launch_coarse_rhs(g->cd, g->cd.x1, g->stream), "coarse rhs")) != HYB_OK) return rc;
+            if ((rc = hip(launch_coarse_solve(g->cd, g->cd.x1, g->budget, 200, 1e-14, g->stream), "coarse solve")) !=
+                HYB_OK)
+                return rc;
+            g->solved = true;
+            // every patch's perimeter values and fine steps
+            for (int p = 0; p < np; ++p) {
+                hyb_handle *h = g->patches[p];
+                if ((rc = hip(launch_c2f(g->c2f_idx[p], g->c2f_w[p], 4 * (h->N - 1), g->cd.xn, g->cd.x1, h->bc_a,
+                                         h->bc_b, g->stream), "coarse-to-fine")) != HYB_OK)
+                    return rc;
+            }
+            for (hyb_handle *h : g->patches)
+                if ((rc = substeps_impl(h, g->eta, 1, -1, 0)) != HYB_OK) return g->fail(rc, h->err);
+        }
+        KrylovResult kr{};
+        if ((rc = hip(hipMemcpyAsync(&kr, g->kres, sizeof(kr), hipMemcpyDeviceToHost, g->stream), "result")) != HYB_OK)
+            return rc;
+        if ((rc = hip(hipStreamSynchronize(g->stream), "synchronise")) != HYB_OK) return rc;
+        g->last_iters = kr.iters;
+        if (kr.converged) break;
+        if (g->budget >= g->cap || attempt == 1) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "coarse solve did not converge (%d iterations, relres %.3e)", kr.iters,
+                          kr.relres);
+            return g->fail(HYB_ENOCONV, buf);
+        }
+        g->last_iters = g->cap;
+    }
+    // commit every patch (non-finite checks), then the coarse state
+    for (hyb_handle *h : g->patches)
+        if ((rc = hyb_commit(h)) != HYB_OK) return g->fail(rc, h->err);
+    double *old_prev = g->cd.xprev;
+    g->cd.xprev = g->cd.xn;
+    g->cd.xn = g->cd.x1;
+    g->cd.x1 = old_prev;
+    g->solved = false;
+    return HYB_OK;
+}
+
+int hyb_group_coarse(hyb_group *g, double *out, int out_is_device) {
+    if (!g || !out) return HYB_EINVAL;
+    const int m1 = g->M + 1;
+    const size_t rowb = (size_t)m1 * 8;
+    const hipError_t e = hipMemcpy2DAsync(out, rowb, g->cd.xn + (size_t)kCoarseHalo * g->cd.S + kCoarseHalo,
+                                          (size_t)g->cd.S * 8, rowb, m1,
+                                          out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream);
+    if (e != hipSuccess || hipStreamSynchronize(g->stream) != hipSuccess) return g->fail(HYB_EHIP, "coarse readout");
+    return HYB_OK;
+}
+
+void hyb_group_destroy(hyb_group *g) { delete g; }
+
+const char *hyb_group_last_error(const hyb_group *g) { return g ? g->err.c_str() : "null group"; }
 
 }  // extern "C"

@@ -301,6 +301,20 @@ struct CoarseHost {
 std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
                          int overlap_elems, int N, double x0, double y0, const uint8_t *solid, int pitch,
                          CoarseHost &out);
+// Several fine patches on one mesh (Algorithm 2): the Dirichlet rows take
+// every patch's Gamma_{f->c} (indices patch by patch: patch p's run starts
+// after the nodes of patches 0 .. p-1); out holds the operator and patch 0's
+// lists, *more (if given) the lists of patches 1 .. n-1.
+struct PatchGeom {
+    int N;
+    double x0, y0;
+    const uint8_t *solid;
+    int pitch;
+};
+std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
+                         int overlap_elems, const std::vector<PatchGeom> &patches, CoarseHost &out,
+                         std::vector<CoarseHost> *more);
+std::string patch_lists(int M, double L, const PatchGeom &g, CoarseHost &out);
 
 // Perimeter slot <-> node mapping shared by host and device code.
 __host__ __device__ inline void slot_to_node(int N, int p, int &i, int &j) {

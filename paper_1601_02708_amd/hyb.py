@@ -52,7 +52,11 @@ class HybRunStats(ctypes.Structure):
                 ("fine_steps", ctypes.c_int64), ("overlap_depth", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
-# exported symbol -> (restype, argtypes); mirrors include/hyb.h
+class Hyb1DParams(ctypes.Structure):
+    _fields_ = [("h_c", _d), ("h_f", _d), ("L_ov", _d), ("max_iter", _i), ("v", _d), ("D", _d)]
+
+
+# exported symbol -> (restype, argtypes); mirrors include/hyb.h and include/hyb1d.h
 SIGNATURES = {
     "hyb_query": (_i, [_P, _P, _P, _P]),
     "hyb_create": (_i, [_P, _P, _d, _P, _P, _P]),
@@ -77,11 +81,25 @@ SIGNATURES = {
     "hyb_set_dissolution": (_i, [_P, _d, _d, _P]),
     "hyb_dissolution_state": (_i, [_P, _P, _P, _P]),
     "hyb_set_solids": (_i, [_P, _P, _P]),
+    "hyb_checkpoint_query": (_i, [_P, _P]),
+    "hyb_checkpoint_save": (_i, [_P, _P]),
+    "hyb_checkpoint_load": (_i, [_P, _P]),
     "hyb_set_overlap": (_i, [_P, _i]),
     "hyb_set_steps_per_launch": (_i, [_P, _i]),
     "hyb_kernel_timing": (_i, [_P, _i]),
     "hyb_kernel_time": (_i, [_P, _P, _P]),
     "hyb_destroy": (None, [_P]),
+    "hyb_group_query": (_i, [_P, _i, _P, _P]),
+    "hyb_group_create": (_i, [_P, _i, _P, _d, _P, _d, _P, _P, _P]),
+    "hyb_group_step": (_i, [_P, _i]),
+    "hyb_group_coarse": (_i, [_P, _P, _i]),
+    "hyb_group_destroy": (None, [_P]),
+    "hyb_group_last_error": (ctypes.c_char_p, [_P]),
+    "hyb1d_query": (_i, [_P, _P, _P, _P, _P, _P]),
+    "hyb1d_create": (_i, [_P, _P, _P, _P, _P, _P]),
+    "hyb1d_run": (_i, [_P, _i]),
+    "hyb1d_state": (_i, [_P, _P, _P]),
+    "hyb1d_destroy": (None, [_P]),
     "hyb_last_error": (ctypes.c_char_p, [_P]),
 }
 
@@ -279,6 +297,19 @@ class Hybrid:
             raise ValueError("coarse state must have (M+1)^2 entries")
         return self._check(load().hyb_set_coarse(self.h, _ptr(d)))
 
+    # -- device checkpoints ---------------------------------------------------
+    def checkpoint(self):
+        """A device checkpoint (torch uint8 tensor) of the committed state."""
+        nb = ctypes.c_size_t()
+        self._check(load().hyb_checkpoint_query(self.h, ctypes.addressof(nb)))
+        t = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.dev)
+        self._check(load().hyb_checkpoint_save(self.h, t.data_ptr()))
+        return t
+
+    def restore(self, ckpt):
+        """Return to a state saved by checkpoint()."""
+        return self._check(load().hyb_checkpoint_load(self.h, ckpt.data_ptr()))
+
     # -- dissolving solids ---------------------------------------------------
     def set_dissolution(self, kappa_s, c_sat, mass=None):
         """Surface reaction rate and saturation concentration at fluid-solid
@@ -397,46 +428,36 @@ def lattice_substeps_function():
 
 
 
-def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8):
+def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8, state_in_cotangent=True):
     """Reverse mode of n_steps coarse steps from the handle's committed state
-    (which is left at the end of the rollout), with the state checkpointed
-    every ``checkpoint_every`` steps on the host and each step re-run inside
-    its segment (two forward sweeps and one reverse sweep in all).
+    (which is left at the end of the rollout), with the committed state
+    checkpointed on the device every ``checkpoint_every`` steps
+    (hyb_checkpoint_save: populations, coarse state and, with dissolving
+    solids, geometry and masses) and each segment re-run from its
+    checkpoint, so every step runs twice forwards and once backwards.
 
     ``cotangent(n, F, d)`` returns (dJ/dF_n, dJ/dd_n) as host FP64 arrays
     ([9, N, N], [(M+1)^2]; either may be None) for the state (F, d) after
-    step n (n = 1 .. n_steps), so J may sum over the whole trajectory.  Every
-    step runs ``passes`` Schwarz passes (hyb_step with that count).  Returns
-    host FP64 arrays (dJ/dF_0, dJ/dd_0, dJ/dk, dJ/dg_outer): the initial
-    state, the fine per-node reaction rate and the outer-edge Dirichlet
-    values (per coarse node, summed over the steps).  Each step's adjoint
-    runs on the GPU through hyb_step_record and hyb_step_adjoint; this
-    function only moves states and orchestrates."""
+    step n (n = 1 .. n_steps), so J may sum over the whole trajectory; with
+    ``state_in_cotangent`` False it receives None for F and d (no host copy
+    of the state is made).  Every step runs ``passes`` Schwarz passes
+    (hyb_step with that count).  Returns host FP64 arrays (dJ/dF_0, dJ/dd_0,
+    dJ/dk, dJ/dg_outer): the initial state, the fine per-node reaction rate
+    and the outer-edge Dirichlet values (per coarse node, summed over the
+    steps).  Each step's adjoint runs on the GPU through hyb_step_record and
+    hyb_step_adjoint; this function only orchestrates."""
     import torch
     N, M = g.N, g.M
     dev = g.dev
     n1 = (M + 1) ** 2
 
-    # with dissolving solids a state also holds the geometry and the masses
-    dissolving = getattr(g, "dissolution", False)
-
-    def state():
-        st = (g.get_populations(), g.concentration(HYB_COARSE).copy())
-        return st + g.dissolution_state()[:2] if dissolving else st
-
-    def restore(st):
-        if dissolving:
-            g.set_solids(st[2], st[3])
-        g.set_populations(st[0])
-        g.set_coarse(st[1])
-
     # forward rollout, checkpointing the state at every segment start
     ckpt = {}
     for n in range(n_steps):
         if n % checkpoint_every == 0:
-            ckpt[n] = state()
+            ckpt[n] = g.checkpoint()
         g.step(passes)
-    ckpt[n_steps] = state()
+    ckpt[n_steps] = g.checkpoint()
     tape = g.step_tape(passes)
     lam_f = torch.zeros((9, N, N), dtype=torch.float64, device=dev)
     lam_d = torch.zeros(n1, dtype=torch.float64, device=dev)
@@ -448,26 +469,29 @@ def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8):
     for si in range(len(starts) - 1, -1, -1):
         s0 = starts[si]
         s1 = starts[si + 1] if si + 1 < len(starts) else n_steps
-        # re-run the segment: seg[i] is the state before step s0 + i, and
-        # seg[s1 - s0] the next checkpoint (the state after its last step)
-        restore(ckpt[s0])
+        # re-run the segment: seg[i] is the state before step s0 + i
+        g.restore(ckpt[s0])
         seg = [ckpt[s0]]
         for _ in range(s0, s1 - 1):
             g.step(passes)
-            seg.append(state())
-        seg.append(ckpt[s1])
+            seg.append(g.checkpoint())
         for n in range(s1 - 1, s0 - 1, -1):
-            cf, cd = cotangent(n + 1, *seg[n - s0 + 1][:2])
+            g.restore(seg[n - s0])
+            g.step_record(passes, tape)
+            # the handle now holds the state after step n
+            if state_in_cotangent:
+                cf, cd = cotangent(n + 1, g.get_populations(), g.concentration(HYB_COARSE).copy())
+            else:
+                cf, cd = cotangent(n + 1, None, None)
             if cf is not None:
                 lam_f += torch.from_numpy(np.ascontiguousarray(cf, np.float64)).to(dev)
             if cd is not None:
                 lam_d += torch.from_numpy(np.ascontiguousarray(cd, np.float64).reshape(-1)).to(dev)
-            restore(seg[n - s0])
-            g.step_record(passes, tape)
             g.step_adjoint(tape, lam_f, lam_d, out_f, out_d, gk, gouter)
             lam_f, out_f = out_f, lam_f
             lam_d, out_d = out_d, lam_d
-    restore(ckpt[n_steps])
+        del seg
+    g.restore(ckpt[n_steps])
     return lam_f.cpu().numpy(), lam_d.cpu().numpy(), gk.cpu().numpy(), gouter.cpu().numpy()
 
 
@@ -514,3 +538,137 @@ def rollout_function():
             return None, None, None, torch.from_numpy(lF).to(ctx.dev), torch.from_numpy(ld).to(ctx.dev)
 
     return Rollout
+
+
+# ----------------------------------------------------------------------------
+# several fine patches around one coarse subdomain (Algorithm 2)
+# ----------------------------------------------------------------------------
+
+class HybridGroup:
+    """Lattice-only Hybrid patches (created with mesh=None) coupled through
+    one coarse mesh: ``mesh`` as for Hybrid (M, L, outer_value,
+    overlap_elems, supg, d0, v), D and the uniform coarse rate k."""
+
+    def __init__(self, patches, mesh, D, k=0.0):
+        lib = load()
+        self.patches = list(patches)
+        p0 = self.patches[0]
+        self.torch, self.dev, self.stream = p0.torch, p0.dev, p0.stream
+        self.M = int(mesh["M"])
+        d0 = np.ascontiguousarray(np.asarray(mesh["d0"]).ravel(), np.float64)
+        vc = np.ascontiguousarray(np.asarray(mesh["v"]).reshape(-1, 2), np.float64)
+        self._keep = [d0, vc]
+        self.meshs = HybMesh(self.M, float(mesh["L"]), float(mesh.get("outer_value", 0.0)),
+                             int(mesh.get("overlap_elems", 1)), int(mesh.get("supg", 1)), _ptr(d0))
+        lats = (HybLattice * len(self.patches))()
+        for i, p in enumerate(self.patches):
+            lats[i] = p.lat
+        wb = ctypes.c_size_t()
+        rc = lib.hyb_group_query(ctypes.addressof(self.meshs), len(self.patches), ctypes.addressof(lats),
+                                 ctypes.addressof(wb))
+        if rc != HYB_OK:
+            raise HybError(rc, "hyb_group_query rejected the set-up")
+        self.ws = self.torch.empty(wb.value, dtype=self.torch.uint8, device=self.dev)
+        hs = (ctypes.c_void_p * len(self.patches))(*[p.h.value for p in self.patches])
+        g = ctypes.c_void_p()
+        rc = lib.hyb_group_create(ctypes.addressof(self.meshs), len(self.patches), ctypes.addressof(hs), float(D),
+                                  _ptr(vc), float(k), self.ws.data_ptr(), self.stream.cuda_stream, ctypes.addressof(g))
+        if rc != HYB_OK:
+            raise HybError(rc, "hyb_group_create failed (see stderr)")
+        self.g = g
+
+    def step(self, max_schwarz):
+        rc = load().hyb_group_step(self.g, int(max_schwarz))
+        if rc != HYB_OK:
+            raise HybError(rc, load().hyb_group_last_error(self.g).decode())
+
+    def coarse(self):
+        out = np.empty((self.M + 1, self.M + 1))
+        rc = load().hyb_group_coarse(self.g, _ptr(out), 0)
+        if rc != HYB_OK:
+            raise HybError(rc, load().hyb_group_last_error(self.g).decode())
+        return out
+
+    def close(self):
+        if getattr(self, "g", None):
+            load().hyb_group_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------
+# one-dimensional hybrid (include/hyb1d.h)
+# ----------------------------------------------------------------------------
+
+def hybrid1d_sizes(h_c, h_f, L_ov, max_iter, v=1.0, D=1e-2):
+    """(nc, nf, eta, xf0, workspace bytes) of a 1-D set-up (no GPU needed):
+    coarse nodes x_k = k h_c, fine nodes x_i = xf0 + i h_f."""
+    prm = Hyb1DParams(float(h_c), float(h_f), float(L_ov), int(max_iter), float(v), float(D))
+    nc, nf, eta = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    xf0, ws = ctypes.c_double(), ctypes.c_size_t()
+    rc = load().hyb1d_query(ctypes.addressof(prm), ctypes.addressof(nc), ctypes.addressof(nf), ctypes.addressof(eta),
+                            ctypes.addressof(xf0), ctypes.addressof(ws))
+    if rc != HYB_OK:
+        raise HybError(rc, "hyb1d_query rejected the set-up")
+    return nc.value, nf.value, eta.value, xf0.value, ws.value
+
+
+class Hybrid1D:
+    """The 1-D hybrid of Sec. 7.1 on the GPU (one workgroup per handle).
+    ``initial(x)`` gives the initial concentration at host coordinates x
+    (used on both grids)."""
+
+    def __init__(self, h_c, h_f, L_ov, max_iter, initial, v=1.0, D=1e-2, device=None):
+        import torch
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Hybrid1D needs a GPU (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.dev = torch.device(device or "cuda:0")
+        self.nc, self.nf, self.eta, self.xf0, ws = hybrid1d_sizes(h_c, h_f, L_ov, max_iter, v, D)
+        self.prm = Hyb1DParams(float(h_c), float(h_f), float(L_ov), int(max_iter), float(v), float(D))
+        self.xc = np.arange(self.nc) * h_c
+        self.xf = self.xf0 + np.arange(self.nf) * h_f
+        self.dt_c = h_c ** 2 / (2.0 * D)
+        d0 = np.ascontiguousarray(initial(self.xc), np.float64)
+        u0 = np.ascontiguousarray(initial(self.xf), np.float64)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=self.dev)
+        self.stream = torch.cuda.current_stream(self.dev)
+        h = ctypes.c_void_p()
+        rc = lib.hyb1d_create(ctypes.addressof(self.prm), _ptr(d0), _ptr(u0), self.ws.data_ptr(),
+                              self.stream.cuda_stream, ctypes.addressof(h))
+        if rc != HYB_OK:
+            raise HybError(rc, "hyb1d_create failed (see stderr)")
+        self.h = h
+        self.t = 0.0
+
+    def run(self, n_steps):
+        rc = load().hyb1d_run(self.h, int(n_steps))
+        if rc != HYB_OK:
+            raise HybError(rc, "hyb1d_run failed")
+        self.t += n_steps * self.dt_c
+
+    def state(self):
+        """(coarse nodal values [nc], fine concentration [nf]) on the host."""
+        d = np.empty(self.nc)
+        u = np.empty(self.nf)
+        rc = load().hyb1d_state(self.h, _ptr(d), _ptr(u))
+        if rc != HYB_OK:
+            raise HybError(rc, "hyb1d_state failed")
+        return d, u
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().hyb1d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

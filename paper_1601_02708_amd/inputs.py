@@ -272,6 +272,15 @@ def gaussian_pulse(seed: int, L: float) -> Pulse:
     return Pulse(xc=float(c[0] * L), yc=float(c[1] * L), sigma=float(s * L))
 
 
+def gaussian_hill_1d(x, t: float, phi: float = 0.1, sigma0: float = 1e-2, x0: float = 0.3, v: float = 1.0,
+                     D: float = 1e-2) -> np.ndarray:
+    """The advected, spreading Gaussian hill of mass phi on the real line
+    (the 1-D example of Sec. 7.1): its initial condition at t = 0, and the
+    closed-form solution the printed errors are measured against."""
+    s2 = sigma0 ** 2 + 2.0 * D * t
+    return phi / np.sqrt(2.0 * np.pi * s2) * np.exp(-(np.asarray(x, np.float64) - x0 - v * t) ** 2 / (2.0 * s2))
+
+
 def random_populations(N: int, seed: int, lo: float = 0.2, hi: float = 1.0) -> np.ndarray:
     """Strictly positive random population field [9, N, N] (FP64) for
     single-sweep tests that start away from equilibrium."""

@@ -11,9 +11,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    text = open(os.path.join(ROOT, "include", "hyb.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hyb_[a-z_]+)\s*\(", text)))
+    names = set()
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(hyb(?:1d)?_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_header_symbols():
@@ -25,7 +29,7 @@ def test_library_exports_header_symbols():
         assert hasattr(lib, name), name
     assert sorted(hyb.SIGNATURES) == declared
     out = subprocess.run(["nm", "-D", "--defined-only", hyb.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r" T (hyb_\w+)", out))
+    exported = set(re.findall(r" T (hyb(?:1d)?_\w+)", out))
     assert set(declared) <= exported
 
 
@@ -75,3 +79,17 @@ def test_oracle_never_imports_product_kernels():
                 assert not n.startswith("paper_1601_02708_amd.csrc"), (fn, n)
         if fn.endswith(".c"):
             assert "hyb.h" not in open(os.path.join(od, fn)).read()
+
+
+def test_hybrid1d_sizes_without_gpu():
+    """The 1-D set-up of Sec. 7.1 (table row h_c = 1.25e-3, h_f = 6.25e-4,
+    L_ov = 1e-2): 1/2 + L_ov/2 = 0.505 is node 404 of the coarse grid, the
+    fine grid has 0.505 / 6.25e-4 = 808 cells, eta = 4; spacings that do not
+    fit the interface points are rejected."""
+    from paper_1601_02708_amd import hyb
+    nc, nf, eta, xf0, ws = hyb.hybrid1d_sizes(1.25e-3, 6.25e-4, 1e-2, 10)
+    assert (nc, nf, eta) == (405, 809, 4) and abs(xf0 - 0.495) < 1e-15 and ws % 256 == 0
+    with pytest.raises(hyb.HybError):
+        hyb.hybrid1d_sizes(1.25e-3, 5e-4, 1e-2, 10)          # (h_c / h_f)^2 not an integer
+    with pytest.raises(hyb.HybError):
+        hyb.hybrid1d_sizes(3e-3, 1.5e-3, 1e-2, 10)           # interface points off the grids

@@ -300,3 +300,35 @@ def test_dissolving_trajectory_adjoint_with_checkpoints(orc):
     errs = {"F": _rel(lF[:, pre_fluid], oF[:, pre_fluid]), "d": _rel(ld, od), "k": _rel(gk, ok)}
     print(f"\ndissolving trajectory adjoint: {errs}")
     assert max(errs.values()) <= 1e-10, errs
+
+
+@pytest.mark.parametrize("dissolving", [False, True])
+def test_device_checkpoint_repeats_the_run_bit_for_bit(dissolving):
+    """hyb_checkpoint_save / hyb_checkpoint_load: a run continued from a
+    loaded checkpoint equals the original continuation bit for bit
+    (populations, coarse state, and with dissolving solids the solids and
+    masses), across conversions."""
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE2048.replace(N=129, M=16, eta=4))
+    N, P = p.cfg.N, p.cfg.max_iter
+    g = hyb.Hybrid.from_problem(p, precision="fp32", dissolution=dissolving)
+    if dissolving:
+        g.set_dissolution(0.2, 1.0, np.random.default_rng(9).uniform(0.002, 0.01, (N, N)))
+    g.step(P)
+    ck = g.checkpoint()
+
+    def run():
+        for _ in range(3):
+            g.step(P)
+        out = [g.get_populations(), g.concentration(hyb.HYB_COARSE)]
+        if dissolving:
+            out += list(g.dissolution_state()[:2])
+        return out
+
+    a = run()
+    g.restore(ck)
+    b = run()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    if dissolving:
+        assert not np.array_equal(a[2], p.solid.astype(np.uint8))     # conversions happened

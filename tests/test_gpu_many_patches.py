@@ -1,0 +1,93 @@
+"""Algorithm 2 on the GPU (C ABI hyb_group_*): several lattice-only patches
+coupled through one coarse mesh, against the oracle's ManyPatchOracle on
+the same seeded problems, and one patch against the single-patch handle."""
+import numpy as np
+import pytest
+
+from paper_1601_02708_amd import configs, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_02708_amd import hyb
+    return hyb
+
+
+def _rel(x, y):
+    return float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+
+
+def _group(hyb, mp, precision):
+    patches = [hyb.Hybrid(N=p.N, x0=p.x0, y0=p.y0, u0=p.u0_fine, vx=p.vx, vy=p.vy, D=mp.D, eta=mp.eta,
+                          precision=precision, tau=mp.tau_value, solid=p.solid, k=mp.k, bc_clamp=mp.bc_clamp)
+               for p in mp.patches]
+    mesh = dict(M=mp.M, L=mp.L, outer_value=0.0, overlap_elems=mp.overlap_elems, supg=mp.supg, d0=mp.u0_coarse,
+                v=mp.vc)
+    return patches, hyb.HybridGroup(patches, mesh, mp.D, mp.k)
+
+
+CASES = {
+    "mirror": lambda: configs.build_multi(33, 16, 128.0, [(16.0, 48.0), (80.0, 48.0)], D=1e-2, eta=4, max_iter=2,
+                                          velocity=(0.0, 0.0), pulse=inputs.Pulse(64.0, 64.0, 20.0)),
+    "porous": lambda: configs.build_multi(65, 16, 260.0, [(30.0, 80.0), (150.0, 80.0)], D=1e-2, k=1e-3, eta=5,
+                                          max_iter=2, velocity=(0.04, 0.01), pulse=inputs.Pulse(120.0, 110.0, 45.0),
+                                          porosity=0.7),
+}
+
+
+@pytest.mark.parametrize("case,precision,tol", [("mirror", "fp64", 1e-12), ("porous", "fp64", 1e-12),
+                                                ("porous", "fp32", 2e-5)])
+def test_group_matches_oracle(orc, case, precision, tol):
+    from oracle.many_patches import ManyPatchOracle
+    hyb = _gpu()
+    mp = CASES[case]()
+    patches, g = _group(hyb, mp, precision)
+    o = ManyPatchOracle(mp)
+    for s in range(3):
+        g.step(mp.max_iter)
+        o.step()
+        errs = {"d": _rel(g.coarse().reshape(-1), o.d)}
+        for j, p in enumerate(patches):
+            fluid = mp.patches[j].solid == 0
+            errs[f"f{j}"] = _rel(p.get_populations()[:, fluid], o.fstar[j][:, fluid])
+        print(f"\ngroup {case} {precision} step {s}: {errs}")
+        assert max(errs.values()) <= tol, errs
+
+
+def test_one_patch_group_is_the_single_handle():
+    """A group of one patch runs Algorithm 1: it equals hyb_step of a handle
+    that owns the same mesh (rounding aside)."""
+    hyb = _gpu()
+    cfg = configs.PORE2048.replace(N=129, M=16, eta=4)
+    p = configs.build_problem(cfg)
+    single = hyb.Hybrid.from_problem(p, precision="fp64")
+    mp = configs.build_multi(cfg.N, cfg.M, p.L, [(p.x0, p.y0)], D=cfg.D, k=cfg.k, eta=cfg.eta, max_iter=cfg.max_iter)
+    mp.patches[0].solid, mp.patches[0].vx, mp.patches[0].vy = p.solid, p.vx, p.vy
+    mp.patches[0].u0_fine = p.u0_fine
+    mp.u0_coarse, mp.vc = p.u0_coarse, p.vc
+    patches, g = _group(hyb, mp, "fp64")
+    for _ in range(3):
+        single.step(cfg.max_iter)
+        g.step(cfg.max_iter)
+    assert _rel(patches[0].get_populations(), single.get_populations()) <= 1e-13
+    assert _rel(g.coarse().reshape(-1), single.concentration(hyb.HYB_COARSE).reshape(-1)) <= 1e-13
+
+
+def test_group_rejects():
+    hyb = _gpu()
+    mp = CASES["mirror"]()
+    # overlapping interface sets: the same patch twice
+    p0 = mp.patches[0]
+    a = hyb.Hybrid(N=p0.N, x0=p0.x0, y0=p0.y0, u0=p0.u0_fine, vx=p0.vx, vy=p0.vy, D=mp.D, eta=mp.eta)
+    b = hyb.Hybrid(N=p0.N, x0=p0.x0, y0=p0.y0, u0=p0.u0_fine, vx=p0.vx, vy=p0.vy, D=mp.D, eta=mp.eta)
+    mesh = dict(M=mp.M, L=mp.L, d0=mp.u0_coarse, v=mp.vc)
+    with pytest.raises(hyb.HybError):
+        hyb.HybridGroup([a, b], mesh, mp.D)
+    # a patch that owns a mesh
+    pm = configs.build_problem(configs.SMALL)
+    with pytest.raises(hyb.HybError):
+        hyb.HybridGroup([hyb.Hybrid.from_problem(pm)], dict(M=16, L=pm.L, d0=pm.u0_coarse, v=pm.vc), 1e-2)
