@@ -326,8 +326,9 @@ int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches);
  *   masses, 0 after hyb_create).  Only between coarse steps (no fine steps
  *   pending); HYB_EINVAL without the reserved workspace.  Synchronises.
  * hyb_dissolution_state: current solid flags (host u8 [N*N]), masses (host
- *   FP64 [N*N], 0 at fluid nodes) and the number of solids converted since
- *   hyb_create; each output may be NULL.  Synchronises.
+ *   FP64 [N*N], 0 at fluid nodes) and the number of nodes solid at
+ *   hyb_create that are fluid now (the conversions so far: fluid never turns
+ *   solid); each output may be NULL.  Synchronises.
  * hyb_set_solids: replace the geometry and masses (host u8 / FP64 [N*N],
  *   e.g. a checkpoint taken with hyb_dissolution_state): only nodes solid at
  *   hyb_create may be solid (HYB_EINVAL otherwise); the flag words are

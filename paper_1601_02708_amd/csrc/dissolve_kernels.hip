@@ -9,7 +9,7 @@
 // (the sweep kernels, LbmArgs::flux); the kernels below act at the commit:
 // masses are debited, exhausted solids become fluid with the equilibrium of
 // their fluid neighbours' mean concentration at zero velocity, and the flag
-// words are rebuilt.  The fine-to-coarse transfer (Sec. 6.2, item ii) then
+// words are rebuilt -- three streams over the patch, no atomics.  The fine-to-coarse transfer (Sec. 6.2, item ii) then
 // weights the current fluid corners.
 #include "hyb_impl.h"
 
@@ -35,21 +35,46 @@ __device__ __forceinline__ double node_conc(const LbmArgs &a, const S *__restric
 // Loads are unconditional (neighbour coordinates clamped onto the patch,
 // values of solid or outside neighbours discarded afterwards), so each lane
 // waits for memory twice at most instead of once per neighbour.
-template <typename S>
-__device__ __forceinline__ bool commit_node(const LbmArgs &a, double *__restrict__ mass, uint8_t *__restrict__ solid,
-                                            int i, int j) {
+// Commit, first kernel (one lane per node, a stream over the flag words):
+// solid nodes with fluid neighbours lose their link-flux sum (the others
+// moved nothing this step; their flux entry is not maintained); a node
+// whose mass is then <= 0 becomes fluid (solid[] cleared, mass 0).  No
+// atomics: one counter taking ~30k conversions per commit serialised them
+// (0.8 ms), so converted nodes are counted on the host from solid[].
+__global__ void __launch_bounds__(kBlock) dissolve_decide_kernel(LbmArgs a, double *__restrict__ mass,
+                                                                  uint8_t *__restrict__ solid) {
     const int N = a.N, P = a.pitch;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * N) return;
+    const int j = t / N, i = t - j * N;
     const int n = j * P + i;
     const unsigned m = a.mask[n];
-    if (!(m & kMaskSolid)) return false;
-    // solid nodes without fluid neighbours moved nothing this step (their
-    // flux entry is not maintained)
+    if (!(m & kMaskSolid)) return;
     const double held = mass[n], moved = a.flux[n];
     const double left = held - ((m & 0x1FEu) ? moved : 0.0);
     if (!(left <= 0.0)) {
         mass[n] = left;
-        return false;
+    } else {
+        mass[n] = 0.0;
+        solid[n] = 0;
     }
+}
+
+// Commit, second kernel (one lane per node; the nodes whose flag word says
+// solid and whose solid[] entry the first kernel cleared convert): f*_q =
+// w_q (1 - k) u_mean into a.dst, u_mean the mean concentration of the
+// node's fluid 8-neighbours (flag words before the commit) in q order.
+// Neighbour flags and populations are loaded at clamped coordinates first
+// and the values of solid or outside neighbours discarded, so a lane waits
+// for memory twice.
+template <typename S>
+__global__ void __launch_bounds__(kBlock) dissolve_convert_kernel(LbmArgs a, const uint8_t *__restrict__ solid) {
+    const int N = a.N, P = a.pitch;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * N) return;
+    const int j = t / N, i = t - j * N;
+    const int n = j * P + i;
+    if (!(a.mask[n] & kMaskSolid) || solid[n]) return;
     S *__restrict__ f = static_cast<S *>(a.dst);
     const int plane = static_cast<int>(a.plane);
     int x[kQ];
@@ -75,32 +100,6 @@ __device__ __forceinline__ bool commit_node(const LbmArgs &a, double *__restrict
     const double k = a.kfield ? double(static_cast<const typename Pop<S>::T *>(a.kfield)[n]) : a.k;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) f[q * plane + n] = Pop<S>::st(typename Pop<S>::T(kW[q] * ubar * (1.0 - k)), q, a);
-    mass[n] = 0.0;
-    solid[n] = 0;
-    return true;
-}
-
-// One lane per node of the patch.  Reads the flag words as they were
-// before the commit (bit 15: solid) and writes only solid[] and, at nodes
-// that convert, their populations and mass, so no lane reads what another
-// writes: a converted node's neighbours that enter its mean are fluid.
-// Loads are unconditional (neighbour coordinates clamped onto the patch,
-// values of solid or outside neighbours discarded afterwards), so each lane
-// waits for memory twice at most instead of once per neighbour.  Converted
-// nodes are counted with one atomic per wave (a single counter taking one
-// atomic per conversion serialised ~30k conversions per commit).
-template <typename S>
-__global__ void __launch_bounds__(kBlock) dissolve_commit_kernel(LbmArgs a, double *__restrict__ mass,
-                                                                  uint8_t *__restrict__ solid) {
-    const int N = a.N;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    bool conv = false;
-    if (t < N * N) {
-        const int j = t / N, i = t - j * N;
-        conv = commit_node<S>(a, mass, solid, i, j);
-    }
-    const unsigned long long hits = __ballot(conv);
-    if (hits && (threadIdx.x & 63) == 0) atomicAdd(&a.counters[kCntConverted], (unsigned long long)__popcll(hits));
 }
 
 // Flag words from solid[]: a solid node carries bit 15 and a bit for every
@@ -305,9 +304,10 @@ int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
 template <typename S>
 hipError_t commit_impl(const LbmArgs &a, double *mass, uint8_t *solid, uint16_t *mask, hipStream_t s) {
-    const long long nodes = (long long)a.N * a.N;
-    hipLaunchKernelGGL(dissolve_commit_kernel<S>, dim3(blocks_for(nodes)), dim3(kBlock), 0, s, a, mass, solid);
-    hipLaunchKernelGGL(mask_rebuild_kernel, dim3(blocks_for(nodes)), dim3(kBlock), 0, s, a.N, a.pitch, solid, mask);
+    const dim3 grid(blocks_for((long long)a.N * a.N)), block(kBlock);
+    hipLaunchKernelGGL(dissolve_decide_kernel, grid, block, 0, s, a, mass, solid);
+    hipLaunchKernelGGL(dissolve_convert_kernel<S>, grid, block, 0, s, a, solid);
+    hipLaunchKernelGGL(mask_rebuild_kernel, grid, block, 0, s, a.N, a.pitch, solid, mask);
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ constexpr double kW[kQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0
 constexpr uint16_t kMaskSolid = 1u << 15;
 
 // Device error counters (uint64 slots in the workspace).
-enum Counter { kCntInfeasible = 0, kCntNonfinite = 1, kCntConverted = 2, kCntSlots = 8 };
+enum Counter { kCntInfeasible = 0, kCntNonfinite = 1, kCntSlots = 8 };
 
 // Scalars of the coarse BiCGSTAB shared between its kernels.
 struct KrylovState {
@@ -228,8 +228,7 @@ hipError_t launch_f2c_transpose(const LbmArgs &lat, int prec, const int *node, c
 // per-node arrays are pitched like the flag words.
 // Commit of the geometry: at every solid node mass -= a.flux (solid nodes
 // with a fluid neighbour; the others moved nothing); a node whose mass is
-// then <= 0 becomes fluid (solid[] cleared, counters[kCntConverted] counts
-// it) and takes f*_q = w_q u_mean (1 - k) in a.dst (the committed state),
+// then <= 0 becomes fluid (solid[] cleared) and takes f*_q = w_q u_mean (1 - k) in a.dst (the committed state),
 // u_mean the mean concentration of its fluid neighbours there (flag words
 // before the commit).  Then every flag word is rebuilt from solid[].
 hipError_t launch_dissolve_commit(const LbmArgs &a, int prec, double *mass, uint8_t *solid, uint16_t *mask,
