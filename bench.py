@@ -161,9 +161,22 @@ def adjoint_rate(problem, precision, reps=3):
             rec_ms += ev[0].elapsed_time(ev[1])
             adj_ms += ev[1].elapsed_time(ev[2])
     lups = eta * N * N * reps
+    # algorithmic bytes of one reversed fine step (adj_step_kernel): per
+    # fluid node the cotangent read, the next state read (for dJ/dk), the
+    # result written (9 values each), flags, velocity and the FP64 dJ/dk
+    # read-modify-write; per solid node its flags and the zeros written
+    s = 8 if precision == "fp64" else 4
+    nfl = int((problem.solid == 0).sum())
+    step_bytes = nfl * (27 * s + 2 + 8 + 16) + (N * N - nfl) * (2 + 9 * s)
+    step_ms = adj_ms / (reps * eta)
     out = {"precision": precision, "value": round(lups / (adj_ms / 1e3) / 1e6, 1), "unit": "MLUPS",
-           "ms_per_fine_step": round(adj_ms / (reps * eta), 4),
+           "ms_per_fine_step": round(step_ms, 4),
            "record_forward_mlups": round(lups / (rec_ms / 1e3) / 1e6, 1),
+           "roofline": {"kernel": f"adj_step_kernel<{'double' if s == 8 else 'float'}, 64, 8, 256>", "bound": "hbm",
+                        "algorithmic_bytes_per_step": int(step_bytes),
+                        "achieved": round(step_bytes / (step_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(step_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "note": "time per reversed fine step includes the two packing kernels of the call"},
            "note": "dJ/df*, dJ/da, dJ/db, dJ/dk over one coarse step's fine steps (tape of eta + 4 states)"}
     g.close()
     return out

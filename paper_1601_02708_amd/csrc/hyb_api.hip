@@ -302,6 +302,7 @@ struct hyb_handle {
         a.c_sat = c_sat;
         a.flux = nullptr;
         a.flux_first = 0;
+        a.mid = nullptr;
         return a;
     }
     // buffer that is neither the committed state nor `a`
@@ -1082,17 +1083,30 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
     const size_t fb = h->lay.f_bytes;
     auto slot = [&](int t) { return static_cast<char *>(tape) + (size_t)t * fb; };
     HIP_TRY(h, hipMemcpyAsync(slot(0), h->f[h->frozen], fb, hipMemcpyDeviceToDevice, h->stream));
-    for (int t = 0; t < n_sub; ++t) {
+    // pairs of fine steps in one launch that also stores the state between
+    // them, while the two-step sweep serves (not with dissolving solids,
+    // whose steps sum link fluxes)
+    const bool pairs = use_two_step(h) && !h->dissolve_on;
+    for (int t = 0; t < n_sub;) {
         LbmArgs a = h->lbm_args(h->frozen, -1);
         a.src = slot(t);
-        a.dst = slot(t + 1);
         a.lam = (double)(t + 1) / (double)h->eta;
+        if (pairs && t + 2 <= n_sub) {
+            a.mid = slot(t + 1);
+            a.dst = slot(t + 2);
+            a.lam2 = (double)(t + 2) / (double)h->eta;
+            HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream));
+            t += 2;
+            continue;
+        }
+        a.dst = slot(t + 1);
         if (h->dissolve_on) {
             a.flux = h->flux;
             a.flux_first = t == 0;
             h->flux_valid = true;
         }
         HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
+        t += 1;
     }
     const int dst = h->spare(-1);
     HIP_TRY(h, hipMemcpyAsync(h->f[dst], slot(n_sub), fb, hipMemcpyDeviceToDevice, h->stream));
@@ -1209,17 +1223,28 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
             if ((rc = hyb_interface_exchange(h, HYB_C2F)) != HYB_OK) return rc;
             if (p == 0) HIP_TRY(h, hipMemcpyAsync(bc, h->bc_a, nslots * 8, hipMemcpyDeviceToDevice, h->stream));
             HIP_TRY(h, hipMemcpyAsync(bc + (1 + p) * nslots, h->bc_b, nslots * 8, hipMemcpyDeviceToDevice, h->stream));
-            for (int t = 1; t <= h->eta; ++t) {
+            const bool pairs = use_two_step(h) && !h->dissolve_on;
+            for (int t = 1; t <= h->eta;) {
                 LbmArgs a = h->lbm_args(h->frozen, -1);
                 a.src = state(p, t - 1);
-                a.dst = state(p, t);
                 a.lam = (double)t / (double)h->eta;
+                if (pairs && t + 1 <= h->eta) {
+                    // two fine steps, the state between them kept as well
+                    a.mid = state(p, t);
+                    a.dst = state(p, t + 1);
+                    a.lam2 = (double)(t + 1) / (double)h->eta;
+                    HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream));
+                    t += 2;
+                    continue;
+                }
+                a.dst = state(p, t);
                 if (h->dissolve_on) {
                     a.flux = h->flux;
                     a.flux_first = t == 1;
                     h->flux_valid = true;
                 }
                 HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
+                t += 1;
             }
             HIP_TRY(h, hipMemcpyAsync(h->f[out], state(p, h->eta), fb, hipMemcpyDeviceToDevice, h->stream));
             h->cur = out;

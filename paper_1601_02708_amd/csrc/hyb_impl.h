@@ -94,6 +94,10 @@ struct LbmArgs {
     // nullptr: not tracked
     double *flux;
     int flux_first;
+    // two-step launches: when set, the first fine step's results of the
+    // owned nodes are also stored here (a recording forward keeps every
+    // fine state); nullptr: not stored
+    void *mid;
 };
 
 // Population storage policy: FP64 and FP32 store what they compute; FP16

@@ -485,7 +485,7 @@ __device__ __forceinline__ void tile_of(const TileMap &m, int t, int &tx, int &t
 // values carry the surface reaction, and every owned solid node with fluid
 // neighbours adds the link fluxes of both fine steps to a.flux (step j+1
 // from the source buffer, step j+2 from the first half's results in LDS).
-template <typename S, int TW, int TH, int NT, int PART, bool FLUX>
+template <typename S, int TW, int TH, int NT, int PART, bool FLUX, bool MID = false>
 __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map) {
     typedef typename Pop<S>::T T;
     constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
@@ -605,6 +605,14 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
         // the second half reads what the next fine step would read from HBM
 #pragma unroll
         for (int q = 0; q < kQ; ++q) lds[q][r][c] = Pop<S>::ld(Pop<S>::st(f[q], q, a), q, a);
+        if constexpr (MID) {
+            // a recording forward keeps the intermediate state too
+            if (owned) {
+                const BufRsrc fmid = buf_rsrc(a.mid, kQ * SP * sz);
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(f[q], q, a), fmid, n * sz, q * SP * sz);
+            }
+        }
     }
 
     // flags and velocities of the owned nodes, fetched before the barrier
@@ -713,6 +721,12 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_kernel(LbmArgs a, TileMap map) 
 template <typename S, int TW, int TH, int NT>
 __global__ void __launch_bounds__(NT) lbm_sweep2_flux_kernel(LbmArgs a, TileMap map) {
     sweep2_body<S, TW, TH, NT, 0, true>(a, map);
+}
+
+// whole-patch two-step launch that also stores the intermediate state (a.mid)
+template <typename S, int TW, int TH, int NT>
+__global__ void __launch_bounds__(NT) lbm_sweep2_rec_kernel(LbmArgs a, TileMap map) {
+    sweep2_body<S, TW, TH, NT, 0, false, true>(a, map);
 }
 
 // ---------------------------------------------------------------------------
@@ -843,8 +857,13 @@ hipError_t step2_impl(const LbmArgs &a, int part, int depth, hipStream_t s) {
     if (m.count == 0) return hipSuccess;
     if (a.flux || a.kappa_s != 0.0) {
         // dissolving solids: whole-patch launches only
-        if (m.part != 0) return hipErrorInvalidValue;
+        if (m.part != 0 || a.mid) return hipErrorInvalidValue;
         hipLaunchKernelGGL((lbm_sweep2_flux_kernel<S, TW, TH, NT>), dim3(m.count), dim3(NT), 0, s, a, m);
+        return hipGetLastError();
+    }
+    if (a.mid) {
+        if (m.part != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((lbm_sweep2_rec_kernel<S, TW, TH, NT>), dim3(m.count), dim3(NT), 0, s, a, m);
         return hipGetLastError();
     }
     if (m.part == 0) hipLaunchKernelGGL((lbm_sweep2_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
