@@ -63,10 +63,16 @@ __global__ void __launch_bounds__(kThreads) hyb1d_init_kernel(Dev1D h, const dou
 // result; fine step j of eta receives u^p = (1 - j/eta) a + (j/eta) b.
 __global__ void __launch_bounds__(kThreads) hyb1d_run_kernel(Dev1D h, int n_steps) {
 #pragma clang fp contract(off)
-    __shared__ double sf[2][kMaxF];      // committed populations
+    __shared__ double sf[2][kMaxF];      // committed populations (with the rest, 112 KB of LDS)
     __shared__ double sF[2][kMaxF];      // populations of the running iteration
     __shared__ double sd[kMaxC], sd1[kMaxC], sr[kMaxC];
+    __shared__ double sta[kMaxC], stinv[kMaxC], stc[kMaxC];   // the factorisation of A, read by one lane
     const int nf = h.nf, nc = h.nc, tid = threadIdx.x;
+    for (int i = tid; i < nc; i += kThreads) {
+        sta[i] = h.ta[i];
+        stinv[i] = h.tinv[i];
+        stc[i] = h.tc[i];
+    }
     for (int i = tid; i < nf; i += kThreads) {
         sf[0][i] = h.fstar[i];
         sf[1][i] = h.fstar[nf + i];
@@ -87,13 +93,21 @@ __global__ void __launch_bounds__(kThreads) hyb1d_run_kernel(Dev1D h, int n_step
             }
             __syncthreads();
             if (tid == 0) {
-                double y = sr[0] * h.tinv[0];
+                // the recurrences from LDS, unrolled so that the next
+                // coefficients load while the previous element finishes
+                double y = sr[0] * stinv[0];
                 sd1[0] = y;
+#pragma unroll 8
                 for (int i = 1; i < nc; ++i) {
-                    y = (sr[i] - h.ta[i] * y) * h.tinv[i];
+                    y = (sr[i] - sta[i] * y) * stinv[i];
                     sd1[i] = y;
                 }
-                for (int i = nc - 2; i >= 0; --i) sd1[i] = sd1[i] - h.tc[i] * sd1[i + 1];
+                double x = y;
+#pragma unroll 8
+                for (int i = nc - 2; i >= 0; --i) {
+                    x = sd1[i] - stc[i] * x;
+                    sd1[i] = x;
+                }
             }
             for (int i = tid; i < nf; i += kThreads) {
                 sF[0][i] = sf[0][i];
