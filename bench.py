@@ -273,6 +273,88 @@ def dissolution_adjoint(g, cfg, substeps=1000, checkpoint_every=10):
                     "reverse; step_* are one coarse step's record and reverse alone on the GPU clock"}
 
 
+def differentiation(directions=2, eps=1e-3):
+    """The differentiation workload (diff512: 512^2 patch, porosity 0.6, in a
+    64^2 mesh; inlet x = 0 held at 1, the other outer edges natural; fine
+    rate field U[0, 2e-4]; 200 coarse steps of 10 substeps, one Schwarz
+    pass): J = the outflow moment through the patch's right edge summed over
+    the coarse steps, and its gradient in (k field, inlet value) through
+    hyb.trajectory_functional (checkpoints every 10 coarse steps = 100
+    substeps).  Per precision: the forward's MLUPS (J accumulated on the
+    device each step), the gradient's wall time and MLUPS over the
+    trajectory's lattice updates (backward = checkpointed forward, segment
+    re-runs, every step recorded and reversed), their ratio; FP64 also
+    central differences along `directions` seeded directions, and FP32's
+    gradient against FP64's."""
+    import numpy as np
+    import torch
+    from paper_1601_02708_amd import configs, hyb
+    cfg = configs.DIFF512
+    p = configs.build_problem(cfg)
+    N = cfg.N
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], np.float64)
+    w = np.zeros((9, N, N))
+    w[:, :, N - 1] = ex[:, None]
+    w[:, p.solid != 0] = 0.0
+    lups = cfg.steps * cfg.eta * cfg.max_iter * N * N
+    Functional = hyb.trajectory_functional()
+    out, grads = {}, {}
+    for prec in ("fp64", "fp32"):
+        g = hyb.Hybrid.from_problem(p, precision=prec, device="cuda:0")
+        start = g.checkpoint()
+
+        def J_of(kf, gv):
+            g.restore(start)
+            return Functional.apply(g, cfg.steps, cfg.max_iter, 10, w, None, kf, gv)
+
+        with torch.no_grad():                                  # warm-up
+            J_of(torch.from_numpy(p.k_field), torch.tensor(cfg.outer_value, dtype=torch.float64))
+        k = torch.tensor(p.k_field, dtype=torch.float64, requires_grad=True)
+        gv = torch.tensor(cfg.outer_value, dtype=torch.float64, requires_grad=True)
+        g.restore(start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = Functional.apply(g, cfg.steps, cfg.max_iter, 10, w, None, k, gv)
+        Jv = float(J.detach())
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        gk = k.grad.numpy().copy()
+        grads[prec] = (gk, float(gv.grad))
+        rec = {"J": Jv, "forward_s": round(t1 - t0, 4), "forward_mlups": round(lups / (t1 - t0) / 1e6, 1),
+               "gradient_s": round(t2 - t1, 4), "gradient_mlups": round(lups / (t2 - t1) / 1e6, 1),
+               "gradient_over_forward": round((t2 - t1) / (t1 - t0), 2),
+               "dJ_dg": float(gv.grad), "grad_k_l2": float(np.linalg.norm(gk))}
+        if prec == "fp64":
+            rng = np.random.default_rng(cfg.seed + 7000)
+            rels = []
+            with torch.no_grad():
+                for _ in range(directions):
+                    dk = rng.uniform(-1.0, 1.0, (N, N)) * p.k_field
+                    dk[p.solid != 0] = 0.0
+                    dg = float(rng.uniform(-1.0, 1.0))
+                    jp = float(J_of(torch.from_numpy(p.k_field + eps * dk),
+                                    torch.tensor(cfg.outer_value + eps * dg, dtype=torch.float64)))
+                    jm = float(J_of(torch.from_numpy(p.k_field - eps * dk),
+                                    torch.tensor(cfg.outer_value - eps * dg, dtype=torch.float64)))
+                    fd = (jp - jm) / (2 * eps)
+                    an = float(np.sum(gk * dk)) + grads[prec][1] * dg
+                    rels.append(abs(fd - an) / abs(fd))
+            rec["central_difference_rel"] = [float(f"{r:.3g}") for r in rels]
+        out[prec] = rec
+        g.close()
+    ref = grads["fp64"][0]
+    out["fp32"]["grad_k_rel_vs_fp64"] = float(np.abs(grads["fp32"][0] - ref).max() / np.abs(ref).max())
+    out["workload"] = (f"diff512: {N}^2 lattice (porosity {p.porosity:.4f}), {cfg.M}^2 mesh, inlet x=0 at "
+                       f"{cfg.outer_value}, other edges natural, k field U[0, {cfg.k_field_max}], "
+                       f"{cfg.steps} coarse steps x {cfg.eta} substeps, MaxIter {cfg.max_iter}")
+    out["note"] = ("J = sum over coarse steps of the x-moment of f* on the patch's right edge; gradient wall time "
+                   "includes the checkpointed re-run, every step's record and reverse (checkpoints every 100 "
+                   "substeps); MLUPS over the trajectory's lattice updates")
+    return out
+
+
 def dissolution_rate(steps=20, warmup=2, timing_steps=3, adjoint=True):
     """The dissolving-solid workload (4096^2, porosity 0.5, FP32, eta = 20,
     256^2 mesh, 2 Schwarz passes, surface reaction at every fluid-solid link,
@@ -437,6 +519,8 @@ def main():
     ap.add_argument("--no-dissolution", action="store_true", help="skip the dissolving-solid workload")
     ap.add_argument("--dissolution-only", action="store_true",
                     help="run only the dissolving-solid workload and print its record (for profiling)")
+    ap.add_argument("--differentiation-only", action="store_true",
+                    help="run only the differentiation workload (diff512 gradient) and print its record")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (a plain copy kernel of "
                          "known size, for calibrating HBM traffic counters)")
@@ -449,6 +533,9 @@ def main():
     import numpy as np
     from paper_1601_02708_amd import configs, hyb
 
+    if args.differentiation_only:
+        print(json.dumps({"differentiation": differentiation()}), flush=True)
+        return
     if args.dissolution_only:
         print(json.dumps({"dissolution": dissolution_rate(adjoint=not args.no_adjoint)}), flush=True)
         return
@@ -547,6 +634,8 @@ def main():
         print("[bench] adjoint", file=sys.stderr, flush=True)
         res["adjoint"] = adjoint_rate(problem, args.precision)
         res["step_adjoint"] = step_adjoint_rate(problem, args.precision)
+        print("[bench] differentiation workload (diff512)", file=sys.stderr, flush=True)
+        res["differentiation"] = differentiation()
     print("[bench] 1-D hybrid tables", file=sys.stderr, flush=True)
     res["hybrid1d"] = hybrid1d_tables()
     if not args.no_dissolution:

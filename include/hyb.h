@@ -74,10 +74,13 @@ typedef struct hyb_handle hyb_handle;
 typedef struct {
     int M;                  /* elements per side, >= 2 */
     double L;               /* side of the coarse domain [0, L]^2 */
-    double outer_value;     /* Dirichlet value on the four outer edges */
+    double outer_value;     /* Dirichlet value on the outer edges (those not natural) */
     int overlap_elems;      /* width of the overlap strip in elements, >= 1 */
     int supg;               /* 0: Galerkin, eq. (Galerkin); 1: SUPG, eqs. (SUPG), (SUPG_tau) */
     const double *d0;       /* host [(M+1)^2] initial nodal concentration, index l*(M+1)+k */
+    int outer_natural;      /* bit e set: outer edge e (0: x = 0, 1: x = L, 2: y = 0, 3: y = L)
+                               takes the natural condition of the weak form (zero diffusive
+                               flux) instead of the Dirichlet value; 0: all four Dirichlet */
 } hyb_mesh;
 
 /* Fine lattice (Sec. 4.1). */
@@ -110,7 +113,7 @@ typedef struct {
 /* First-order reaction s = -k u (per unit time; the fine step is 1). */
 typedef struct {
     double k;               /* uniform rate, 0 <= k < 1 */
-    const double *k_field;  /* host [N*N] per-node fine rate, or NULL for the uniform k;
+    const double *k_field;  /* host [N*N] per-node fine rate in [0, 1), or NULL for the uniform k;
                                the coarse model always uses the uniform k */
 } hyb_reaction;
 
@@ -187,12 +190,32 @@ int hyb_concentration(hyb_handle *h, int which, double *out, int out_is_device);
  * precision).  Velocity order: rest, +x, +y, -x, -y, (+,+), (-,+), (-,-), (+,-). */
 int hyb_get_populations(hyb_handle *h, double *out);
 int hyb_set_populations(hyb_handle *h, const double *f);
+/* The current fine state into device FP64 [9][N][N] (index (q*N + j)*N + i)
+ * on the handle's stream, no synchronisation; HYB_FP64 and HYB_FP32 storage
+ * only; values at solid nodes are unspecified. */
+int hyb_populations_device(hyb_handle *h, double *out);
 
 /* Replace the committed coarse solution d(t_n) with host FP64 d[(M+1)^2]
  * (node l*(M+1) + k); also taken as d(t_{n-1}) by the next step's
  * extrapolated first guess.  Like hyb_set_populations it abandons a coarse
  * step in progress.  Synchronises. */
 int hyb_set_coarse(hyb_handle *h, const double *d);
+
+/* Controls of the reverse mode, replaced between steps without re-creating
+ * the handle (the committed state is left as it is):
+ *   hyb_set_reaction_field: the fine per-node rate k of the reaction source
+ *     s = -k u (eq. CouplingPDE, Sec. 4.1), host FP64 [N*N] (node j*N + i),
+ *     every value in [0, 1), else HYB_EINVAL and nothing changes; stored in
+ *     the storage precision's arithmetic type (FP64 for HYB_FP64, FP32
+ *     otherwise); also allowed on a handle created with a uniform k, which
+ *     then uses the field.  The coarse model keeps the uniform k.
+ *     Synchronises.
+ *   hyb_set_outer_value: the Dirichlet value of the outer edges that are not
+ *     natural (hyb_mesh.outer_value; a strong Dirichlet row of eq.
+ *     FEM_discrete), finite, taken by the next coarse solve; HYB_EINVAL
+ *     without a coarse mesh. */
+int hyb_set_reaction_field(hyb_handle *h, const double *k_field);
+int hyb_set_outer_value(hyb_handle *h, double value);
 
 int hyb_stats(hyb_handle *h, hyb_run_stats *out);
 

@@ -25,21 +25,25 @@ import numpy as np
 from . import FemStepper, Lattice, fem_interpolate, fine_to_coarse, perimeter_nodes
 
 
-def coarse_dirichlet_sets(M, L, N, x0, y0, overlap_elems=1):
-    """(outer_nodes, interface_nodes): outer edge nodes of the mesh, and the
+def coarse_dirichlet_sets(M, L, N, x0, y0, overlap_elems=1, outer_natural=0):
+    """(outer_nodes, interface_nodes): the Dirichlet nodes of the outer edges
+    (edge e = 0: x = 0, 1: x = L, 2: y = 0, 3: y = L; edges whose bit is set
+    in outer_natural keep the natural condition of the weak form), and the
     coarse nodes that take Dirichlet data from the lattice (Gamma_{f->c})."""
     h = L / M
     s = M + 1
     kk, ll = np.meshgrid(np.arange(s), np.arange(s), indexing="xy")
     idx = ll * s + kk
-    outer = (kk == 0) | (kk == M) | (ll == 0) | (ll == M)
+    edge = (kk == 0) | (kk == M) | (ll == 0) | (ll == M)
+    outer = (((kk == 0) & (outer_natural & 1 == 0)) | ((kk == M) & (outer_natural & 2 == 0)) |
+             ((ll == 0) & (outer_natural & 4 == 0)) | ((ll == M) & (outer_natural & 8 == 0)))
     X, Y = kk * h, ll * h
     ov = overlap_elems * h
     tol = 1e-9 * h
     x1, y1 = x0 + (N - 1), y0 + (N - 1)
     inner = ((X - x0 >= ov - tol) & (x1 - X >= ov - tol) &
              (Y - y0 >= ov - tol) & (y1 - Y >= ov - tol))
-    inner &= ~outer
+    inner &= ~edge
     return np.sort(idx[outer]), np.sort(idx[inner])
 
 
@@ -63,7 +67,7 @@ def algorithm1_step(h):
 class HybridOracle:
     """State and steps of the two-subdomain hybrid method on the host."""
 
-    def __init__(self, problem, tau=None, eta=None, max_iter=None, outer_value=0.0):
+    def __init__(self, problem, tau=None, eta=None, max_iter=None, outer_value=None, outer_natural=None):
         cfg = problem.cfg
         self.p = problem
         self.N, self.M, self.L = cfg.N, cfg.M, problem.L
@@ -71,10 +75,14 @@ class HybridOracle:
         self.max_iter = cfg.max_iter if max_iter is None else max_iter
         self.k = cfg.k
         tau = cfg.tau_value if tau is None else tau
+        # outer edges and values as the workload states them unless given
+        outer_value = cfg.outer_value if outer_value is None else outer_value
+        outer_natural = cfg.outer_natural if outer_natural is None else outer_natural
+        kfine = cfg.k if getattr(problem, "k_field", None) is None else problem.k_field
         self.lat = Lattice(self.N, tau, problem.vx.astype(np.float64), problem.vy.astype(np.float64),
-                           solid=problem.solid, k=cfg.k, clamp=cfg.bc_clamp)
+                           solid=problem.solid, k=kfine, clamp=cfg.bc_clamp)
         self.outer, self.fc = coarse_dirichlet_sets(self.M, self.L, self.N, problem.x0, problem.y0,
-                                                    cfg.overlap_elems)
+                                                    cfg.overlap_elems, outer_natural)
         rows = np.sort(np.concatenate([self.outer, self.fc]))
         self.rows_sorted = rows
         pos = np.searchsorted(self.fc, rows)

@@ -121,11 +121,11 @@ def f2c_weights(N, solid, px, py):
 
 class HybridStepAdjoint:
     """Recorded forward and adjoint of one coarse step of a HybridOracle
-    (outer Dirichlet value 0, no clamp)."""
+    (no clamp: the step is then affine in the state)."""
 
     def __init__(self, o):
-        if o.outer_value != 0.0:
-            raise ValueError("the step is linear only with zero outer Dirichlet data")
+        # with outer Dirichlet data g != 0 the step is affine; its adjoint is
+        # that of the linear part (g enters only through dJ/dg)
         self.o = o
         cfg = o.p.cfg
         a, b = fem_matrices(o.M, o.L, cfg.D, cfg.k, float(o.eta), cfg.supg, o.p.vc)

@@ -17,6 +17,11 @@ step 1, coarse step = eta):
 * ``pore4096`` -- the same generators at 4096^2 with D = 1e-2, no reaction,
   16^2 mesh, 4 substeps x 100 coarse steps x 2 Schwarz iterations.
   Precision workload.
+* ``diff512`` -- the differentiation workload: 512^2 lattice with the
+  pore2048 generators, 64^2 mesh, D = 5e-3, 10 substeps x 200 coarse steps
+  (2000 fine steps) x 1 Schwarz iteration, a per-node fine reaction rate
+  U[0, 2e-4] (the coarse model takes its mean 1e-4), an inlet: the edge
+  x = 0 held at 1, the other three edges with the natural condition.
 * ``dissolve4096`` -- dissolving solids: the same generators at 4096^2 with
   porosity 0.5, D = 1e-2, bulk reaction k = 1e-4, 256^2 mesh, 20 substeps x
   500 coarse steps x 2 Schwarz iterations; a surface reaction of rate
@@ -62,6 +67,12 @@ class HybridConfig:
     kappa_s: float = 0.0        # surface reaction rate at fluid-solid links
     c_sat: float = 1.0          # concentration the surface reaction drives towards
     mass_range: tuple = (0.5, 1.0)   # per-solid-node mass, uniform
+    # outer edges (0: x = 0, 1: x = L, 2: y = 0, 3: y = L): bit e set = the
+    # natural condition (zero diffusive flux); the others Dirichlet at
+    # outer_value
+    outer_natural: int = 0
+    outer_value: float = 0.0
+    k_field_max: Optional[float] = None   # per-node fine rate U[0, k_field_max] (seeded); None: uniform k
 
     @property
     def L(self) -> float:
@@ -82,10 +93,12 @@ PORE2048 = HybridConfig(name="pore2048", N=2048, M=128, D=5e-3, eta=10, steps=20
 PORE4096 = HybridConfig(name="pore4096", N=4096, M=16, D=1e-2, eta=4, steps=100,
                         max_iter=2, k=0.0, porosity=0.6, velocity="stream")
 
+DIFF512 = HybridConfig(name="diff512", N=512, M=64, D=5e-3, eta=10, steps=200, max_iter=1, k=1e-4, porosity=0.6,
+                       velocity="stream", outer_natural=14, outer_value=1.0, k_field_max=2e-4)
 DISSOLVE4096 = HybridConfig(name="dissolve4096", N=4096, M=256, D=1e-2, eta=20, steps=500,
                             max_iter=2, k=1e-4, porosity=0.5, velocity="stream", kappa_s=0.01, c_sat=1.0)
 
-CONFIGS = {c.name: c for c in (SMALL, PORE2048, PORE4096, DISSOLVE4096)}
+CONFIGS = {c.name: c for c in (SMALL, PORE2048, PORE4096, DIFF512, DISSOLVE4096)}
 
 
 def solid_mass(cfg: HybridConfig, solid: np.ndarray) -> np.ndarray:
@@ -110,6 +123,7 @@ class Problem:
     x0: float
     y0: float
     L: float
+    k_field: Optional[np.ndarray] = None    # float64 [N, N] per-node fine rate, or None (uniform cfg.k)
 
 
 def build_problem(cfg: HybridConfig) -> Problem:
@@ -161,7 +175,8 @@ def build_problem(cfg: HybridConfig) -> Problem:
     u0_fine = pulse(X, Y)
     u0_fine[solid != 0] = 0.0
     u0_coarse = pulse(XC, YC).ravel()
-    return Problem(cfg=cfg, solid=solid, vx=vx, vy=vy, vc=np.ascontiguousarray(vc),
+    k_field = None if cfg.k_field_max is None else inputs.reaction_field(N, cfg.seed + 4000, cfg.k_field_max)
+    return Problem(cfg=cfg, solid=solid, vx=vx, vy=vy, vc=np.ascontiguousarray(vc), k_field=k_field,
                    u0_fine=u0_fine, u0_coarse=u0_coarse, porosity=porosity,
                    x0=x0, y0=x0, L=L)
 

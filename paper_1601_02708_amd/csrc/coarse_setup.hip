@@ -240,7 +240,7 @@ std::string patch_lists(int M, double L, const PatchGeom &g, CoarseHost &out) {
 
 std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
                          int overlap_elems, const std::vector<PatchGeom> &patches, CoarseHost &out,
-                         std::vector<CoarseHost> *more) {
+                         std::vector<CoarseHost> *more, int outer_natural) {
     if (patches.empty()) return "no lattice patch";
     const int m1 = M + 1;
     const int n = m1 * m1;
@@ -308,10 +308,17 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
     // Gamma_{f->c} of patch p: the coarse nodes inside it at least
     // overlap_elems elements from its boundary; indices run patch by patch
     // (each patch's transferred values are one contiguous run)
+    // outer edges 0: x = 0, 1: x = L, 2: y = 0, 3: y = L; an edge whose bit
+    // is set in outer_natural keeps its rows (the natural condition of the
+    // weak form, zero diffusive flux); a node on a Dirichlet edge is a
+    // Dirichlet row
     out.dkind.assign(n, -1);
     for (int l = 0; l < m1; ++l)
-        for (int kk = 0; kk < m1; ++kk)
-            if (kk == 0 || kk == M || l == 0 || l == M) out.dkind[l * m1 + kk] = -2;
+        for (int kk = 0; kk < m1; ++kk) {
+            const bool dir = (kk == 0 && !(outer_natural & 1)) || (kk == M && !(outer_natural & 2)) ||
+                             (l == 0 && !(outer_natural & 4)) || (l == M && !(outer_natural & 8));
+            if (dir) out.dkind[l * m1 + kk] = -2;
+        }
     const double ov = overlap_elems * h, tol = 1e-9 * h;
     std::vector<std::vector<int>> fcn(patches.size());
     int nfc_all = 0;
@@ -447,9 +454,9 @@ std::string build_coarse(int M, double L, double D, double k, double dt, int sup
 
 std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
                          int overlap_elems, int N, double x0, double y0, const uint8_t *solid, int pitch,
-                         CoarseHost &out) {
+                         CoarseHost &out, int outer_natural) {
     const std::vector<PatchGeom> one{PatchGeom{N, x0, y0, solid, pitch}};
-    return build_coarse(M, L, D, k, dt, supg, vnodes, overlap_elems, one, out, nullptr);
+    return build_coarse(M, L, D, k, dt, supg, vnodes, overlap_elems, one, out, nullptr, outer_natural);
 }
 
 }  // namespace hyb

@@ -351,8 +351,13 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     if (!(tau > 0.5)) return bail(HYB_EINVAL, "tau must exceed 1/2");
     const double kuni = k ? k->k : 0.0;
     if (!(kuni >= 0.0 && kuni < 1.0)) return bail(HYB_EINVAL, "reaction rate must lie in [0, 1)");
+    if (k && k->k_field)
+        for (size_t n = 0; n < (size_t)N * N; ++n)
+            if (!(k->k_field[n] >= 0.0 && k->k_field[n] < 1.0))
+                return bail(HYB_EINVAL, "reaction rates must lie in [0, 1)");
     if (mesh) {
-        if (mesh->M < 2 || !(mesh->L > 0.0) || !mesh->d0 || !u->coarse || mesh->overlap_elems < 1)
+        if (mesh->M < 2 || !(mesh->L > 0.0) || !mesh->d0 || !u->coarse || mesh->overlap_elems < 1 ||
+            (mesh->outer_natural & ~15))
             return bail(HYB_EINVAL, "invalid mesh");
         if (lat->x0 < 0 || lat->y0 < 0 || lat->x0 + (N - 1) > mesh->L || lat->y0 + (N - 1) > mesh->L)
             return bail(HYB_EINVAL, "lattice patch must lie inside the coarse domain");
@@ -497,7 +502,8 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     if (mesh) {
         CoarseHost ch;
         std::string msg = build_coarse(mesh->M, mesh->L, D, kuni, (double)lat->eta, mesh->supg, u->coarse,
-                                       mesh->overlap_elems, N, lat->x0, lat->y0, lat->solid, P, ch);
+                                       mesh->overlap_elems, N, lat->x0, lat->y0, lat->solid, P, ch,
+                                       mesh->outer_natural);
         if (!msg.empty()) return bail(HYB_EINVAL, msg);
         h->nfc = (int)ch.fc_nodes.size();
         h->c2f_idx = reinterpret_cast<int *>(h->ws + L.c2f_idx);
@@ -983,6 +989,14 @@ int hyb_concentration(hyb_handle *h, int which, double *out, int out_is_device) 
     return h->fail(HYB_EINVAL, "unknown field");
 }
 
+int hyb_populations_device(hyb_handle *h, double *out) {
+    if (!h || !out) return HYB_EINVAL;
+    if (h->prec == HYB_FP16S) return h->fail(HYB_EINVAL, "device readout supports HYB_FP64 and HYB_FP32 storage");
+    LbmArgs a = h->lbm_args(h->cur, -1);
+    HIP_TRY(h, launch_adjoint_pack(a, h->prec, out, h->f[h->cur], false, h->stream));
+    return HYB_OK;
+}
+
 int hyb_get_populations(hyb_handle *h, double *out) {
     if (!h || !out) return HYB_EINVAL;
     if (refresh_solid_host(h) != hipSuccess) return h->fail(HYB_EHIP, "could not read the solid flags");
@@ -1043,6 +1057,37 @@ int hyb_set_coarse(hyb_handle *h, const double *d) {
     h->solved_this_step = false;
     h->cur = h->frozen;
     h->jsub = 0;
+    return HYB_OK;
+}
+
+int hyb_set_reaction_field(hyb_handle *h, const double *k_field) {
+    if (!h || !k_field) return HYB_EINVAL;
+    const int N = h->N;
+    const size_t P = (size_t)h->lay.pitch, nodes = (size_t)N * P;
+    for (size_t n = 0; n < (size_t)N * N; ++n)
+        if (!(k_field[n] >= 0.0 && k_field[n] < 1.0)) return h->fail(HYB_EINVAL, "reaction rates must lie in [0, 1)");
+    if (h->fp64) {
+        std::vector<double> kf(nodes, 0.0);
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) kf[(size_t)j * P + i] = k_field[(size_t)j * N + i];
+        HIP_TRY(h, hipMemcpyAsync(h->kfield, kf.data(), nodes * 8, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<float> kf(nodes, 0.f);
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) kf[(size_t)j * P + i] = (float)k_field[(size_t)j * N + i];
+        HIP_TRY(h, hipMemcpyAsync(h->kfield, kf.data(), nodes * 4, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    h->has_kfield = true;
+    return HYB_OK;
+}
+
+int hyb_set_outer_value(hyb_handle *h, double value) {
+    if (!h) return HYB_EINVAL;
+    if (!h->has_mesh) return h->fail(HYB_EINVAL, "no coarse mesh");
+    if (!std::isfinite(value)) return h->fail(HYB_EINVAL, "outer value must be finite");
+    h->cd.outer_value = value;
     return HYB_OK;
 }
 
@@ -1688,7 +1733,7 @@ int hyb_group_create(const hyb_mesh *mesh, int n, hyb_handle *const *patches, do
     CoarseHost ch;
     std::vector<CoarseHost> more;
     const std::string msg = build_coarse(mesh->M, mesh->L, D, k, (double)patches[0]->eta, mesh->supg, vcoarse,
-                                         mesh->overlap_elems, geo, ch, &more);
+                                         mesh->overlap_elems, geo, ch, &more, mesh->outer_natural);
     if (!msg.empty()) {
         std::fprintf(stderr, "hyb_group_create: %s\n", msg.c_str());
         return HYB_EINVAL;

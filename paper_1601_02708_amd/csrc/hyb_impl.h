@@ -169,7 +169,7 @@ struct CoarseDev {
     const double *B9;        // [9][n]
     const double *AP;        // [n][kApW^2] stencil of A P
     const double *P;         // [kSpaiW^2][n] stencil of P
-    const int *dkind;        // [n] -1 free, -2 outer Dirichlet, >= 0 index into ufc
+    const int *dkind;        // [n] -1 free (natural outer edges too), -2 outer Dirichlet, >= 0 index into ufc
     double outer_value;
     const double *ufc;       // fine-to-coarse values
     double *xn;              // padded d(t_n)
@@ -303,7 +303,7 @@ struct CoarseHost {
 // fills the interface lists.  Returns an empty string or an error message.
 std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
                          int overlap_elems, int N, double x0, double y0, const uint8_t *solid, int pitch,
-                         CoarseHost &out);
+                         CoarseHost &out, int outer_natural = 0);
 // Several fine patches on one mesh (Algorithm 2): the Dirichlet rows take
 // every patch's Gamma_{f->c} (indices patch by patch: patch p's run starts
 // after the nodes of patches 0 .. p-1); out holds the operator and patch 0's
@@ -316,7 +316,7 @@ struct PatchGeom {
 };
 std::string build_coarse(int M, double L, double D, double k, double dt, int supg, const double *vnodes,
                          int overlap_elems, const std::vector<PatchGeom> &patches, CoarseHost &out,
-                         std::vector<CoarseHost> *more);
+                         std::vector<CoarseHost> *more, int outer_natural = 0);
 std::string patch_lists(int M, double L, const PatchGeom &g, CoarseHost &out);
 
 // Perimeter slot <-> node mapping shared by host and device code.

@@ -29,7 +29,8 @@ _d = ctypes.c_double
 
 
 class HybMesh(ctypes.Structure):
-    _fields_ = [("M", _i), ("L", _d), ("outer_value", _d), ("overlap_elems", _i), ("supg", _i), ("d0", _P)]
+    _fields_ = [("M", _i), ("L", _d), ("outer_value", _d), ("overlap_elems", _i), ("supg", _i), ("d0", _P),
+                ("outer_natural", _i)]
 
 
 class HybLattice(ctypes.Structure):
@@ -68,6 +69,7 @@ SIGNATURES = {
     "hyb_set_boundary": (_i, [_P, _P, _P, _P]),
     "hyb_concentration": (_i, [_P, _i, _P, _i]),
     "hyb_get_populations": (_i, [_P, _P]),
+    "hyb_populations_device": (_i, [_P, _P]),
     "hyb_set_populations": (_i, [_P, _P]),
     "hyb_stats": (_i, [_P, _P]),
     "hyb_layout": (_i, [_P, _P, _P]),
@@ -78,6 +80,8 @@ SIGNATURES = {
     "hyb_step_record": (_i, [_P, _i, _P]),
     "hyb_step_adjoint": (_i, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "hyb_set_coarse": (_i, [_P, _P]),
+    "hyb_set_reaction_field": (_i, [_P, _P]),
+    "hyb_set_outer_value": (_i, [_P, _d]),
     "hyb_set_dissolution": (_i, [_P, _d, _d, _P]),
     "hyb_dissolution_state": (_i, [_P, _P, _P, _P]),
     "hyb_set_solids": (_i, [_P, _P, _P]),
@@ -177,7 +181,8 @@ class Hybrid:
             d0 = host(np.asarray(mesh["d0"]).ravel(), np.float64)
             vc = host(np.asarray(mesh["v"]).reshape(-1, 2), np.float64)
             self.meshs = HybMesh(self.M, float(mesh["L"]), float(mesh.get("outer_value", 0.0)),
-                                 int(mesh.get("overlap_elems", 1)), int(mesh.get("supg", 1)), _ptr(d0))
+                                 int(mesh.get("overlap_elems", 1)), int(mesh.get("supg", 1)), _ptr(d0),
+                                 int(mesh.get("outer_natural", 0)))
         else:
             self.M = 0
         fb = ctypes.c_size_t()
@@ -209,11 +214,13 @@ class Hybrid:
         cfg = problem.cfg
         m = None
         if mesh:
-            m = dict(M=cfg.M, L=problem.L, outer_value=kw.pop("outer_value", 0.0), overlap_elems=cfg.overlap_elems,
-                     supg=cfg.supg, d0=problem.u0_coarse, v=problem.vc)
+            m = dict(M=cfg.M, L=problem.L, outer_value=kw.pop("outer_value", cfg.outer_value),
+                     overlap_elems=cfg.overlap_elems, supg=cfg.supg, d0=problem.u0_coarse, v=problem.vc,
+                     outer_natural=kw.pop("outer_natural", cfg.outer_natural))
         return cls(N=cfg.N, x0=problem.x0, y0=problem.y0, u0=problem.u0_fine, vx=problem.vx, vy=problem.vy,
                    D=cfg.D, eta=kw.pop("eta", cfg.eta), precision=precision,
                    tau=cfg.tau_value if tau is None else tau, solid=problem.solid, k=cfg.k,
+                   k_field=kw.pop("k_field", problem.k_field),
                    bc_clamp=cfg.bc_clamp, mesh=m, **kw)
 
     # -- calls ------------------------------------------------------------
@@ -258,6 +265,10 @@ class Hybrid:
         self._check(load().hyb_get_populations(self.h, out.ctypes.data))
         return out
 
+    def populations_device(self, out_tensor):
+        """Current fine state into a device FP64 tensor [9, N, N] (stream-ordered)."""
+        return self._check(load().hyb_populations_device(self.h, out_tensor.data_ptr()))
+
     def set_populations(self, f):
         f = np.ascontiguousarray(f, np.float64)
         return self._check(load().hyb_set_populations(self.h, f.ctypes.data))
@@ -296,6 +307,17 @@ class Hybrid:
         if d.size != (self.M + 1) ** 2:
             raise ValueError("coarse state must have (M+1)^2 entries")
         return self._check(load().hyb_set_coarse(self.h, _ptr(d)))
+
+    def set_reaction_field(self, k_field):
+        """Replace the fine per-node reaction rate (host [N, N], values in [0, 1))."""
+        k = np.ascontiguousarray(k_field, dtype=np.float64).reshape(-1)
+        if k.size != self.N * self.N:
+            raise ValueError("k_field must have N*N entries")
+        return self._check(load().hyb_set_reaction_field(self.h, _ptr(k)))
+
+    def set_outer_value(self, value):
+        """Replace the Dirichlet value of the outer edges that are not natural."""
+        return self._check(load().hyb_set_outer_value(self.h, float(value)))
 
     # -- device checkpoints ---------------------------------------------------
     def checkpoint(self):
@@ -436,8 +458,9 @@ def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8, state_in_co
     solids, geometry and masses) and each segment re-run from its
     checkpoint, so every step runs twice forwards and once backwards.
 
-    ``cotangent(n, F, d)`` returns (dJ/dF_n, dJ/dd_n) as host FP64 arrays
-    ([9, N, N], [(M+1)^2]; either may be None) for the state (F, d) after
+    ``cotangent(n, F, d)`` returns (dJ/dF_n, dJ/dd_n) as host FP64 arrays or
+    device tensors ([9, N, N], [(M+1)^2]; either may be None; a device FP64
+    tensor is added without a copy) for the state (F, d) after
     step n (n = 1 .. n_steps), so J may sum over the whole trajectory; with
     ``state_in_cotangent`` False it receives None for F and d (no host copy
     of the state is made).  Every step runs ``passes`` Schwarz passes
@@ -484,15 +507,93 @@ def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8, state_in_co
             else:
                 cf, cd = cotangent(n + 1, None, None)
             if cf is not None:
-                lam_f += torch.from_numpy(np.ascontiguousarray(cf, np.float64)).to(dev)
+                lam_f += (cf.to(device=dev, dtype=torch.float64) if torch.is_tensor(cf)
+                          else torch.from_numpy(np.ascontiguousarray(cf, np.float64)).to(dev))
             if cd is not None:
-                lam_d += torch.from_numpy(np.ascontiguousarray(cd, np.float64).reshape(-1)).to(dev)
+                lam_d += (cd.to(device=dev, dtype=torch.float64).reshape(-1) if torch.is_tensor(cd)
+                          else torch.from_numpy(np.ascontiguousarray(cd, np.float64).reshape(-1)).to(dev))
             g.step_adjoint(tape, lam_f, lam_d, out_f, out_d, gk, gouter)
             lam_f, out_f = out_f, lam_f
             lam_d, out_d = out_d, lam_d
         del seg
     g.restore(ckpt[n_steps])
     return lam_f.cpu().numpy(), lam_d.cpu().numpy(), gk.cpu().numpy(), gouter.cpu().numpy()
+
+
+def trajectory_functional():
+    """torch.autograd.Function for a linear functional summed over a
+    trajectory of coarse steps,
+
+        J(k, g) = sum_{n=1}^{n_steps} <w_f, F_n> + <w_d, d_n>,
+
+    as a function of the fine per-node reaction rate k and the Dirichlet
+    value g of the outer edges that are not natural, from the handle's
+    committed state at the call (the outlet flux of a patch edge is such a
+    functional: w_f = e_x on the edge nodes).  ``Functional =
+    trajectory_functional()`` then ``Functional.apply(hybrid, n_steps,
+    passes, checkpoint_every, w_f, w_d, k, g)`` with w_f host [9, N, N] (or
+    None), w_d host [(M+1)^2] (or None), k an FP64 tensor [N, N] and g a 0-d
+    FP64 tensor.  Forward sets the controls on the handle
+    (hyb_set_reaction_field, hyb_set_outer_value), runs the steps and
+    accumulates J on the device; backward returns to the start state and runs
+    steps_adjoint (checkpoints every ``checkpoint_every`` steps, every step's
+    adjoint on the GPU).  dJ/dk and dJ/dg are partial derivatives at a fixed
+    start state; the handle is left at the end of the rollout."""
+    import torch
+
+    class Functional(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, g, n_steps, passes, checkpoint_every, w_f, w_d, k, gval):
+            N, n1 = g.N, (g.M + 1) ** 2
+            dev = g.dev
+            kh = k.detach().to("cpu", torch.float64).numpy()
+            gv = float(gval)
+            ctx.start = g.checkpoint()
+            g.set_reaction_field(kh)
+            g.set_outer_value(gv)
+            J = torch.zeros((), dtype=torch.float64, device=dev)
+            wf = None if w_f is None else torch.from_numpy(np.ascontiguousarray(w_f, np.float64)).to(dev)
+            wd = None if w_d is None else torch.from_numpy(
+                np.ascontiguousarray(w_d, np.float64).reshape(-1)).to(dev)
+            fbuf = torch.empty((9, N, N), dtype=torch.float64, device=dev) if wf is not None else None
+            dbuf = torch.empty(n1, dtype=torch.float64, device=dev) if wd is not None else None
+            for _ in range(n_steps):
+                g.step(passes)
+                if wf is not None:
+                    g.populations_device(fbuf)
+                    J += (fbuf * wf).sum()
+                if wd is not None:
+                    g.concentration_device(dbuf, HYB_COARSE)
+                    J += (dbuf * wd).sum()
+            ctx.g, ctx.n_steps, ctx.passes, ctx.every = g, n_steps, passes, checkpoint_every
+            ctx.w = (w_f, w_d)
+            ctx.controls = (kh, gv)
+            ctx.k_meta = (k.dtype, k.device)
+            ctx.g_meta = (gval.dtype, gval.device) if torch.is_tensor(gval) else None
+            return J
+
+        @staticmethod
+        def backward(ctx, gJ):
+            g = ctx.g
+            g.restore(ctx.start)
+            g.set_reaction_field(ctx.controls[0])
+            g.set_outer_value(ctx.controls[1])
+            w_f, w_d = ctx.w
+            dev = g.dev
+            # the weights go to the device once; every step adds the same tensors
+            wf = None if w_f is None else torch.from_numpy(np.ascontiguousarray(w_f, np.float64)).to(dev)
+            wd = None if w_d is None else torch.from_numpy(
+                np.ascontiguousarray(w_d, np.float64).reshape(-1)).to(dev)
+            _, _, gk, go = steps_adjoint(g, ctx.n_steps, lambda n, F, d: (wf, wd), ctx.passes,
+                                         checkpoint_every=ctx.every, state_in_cotangent=False)
+            dt, dv = ctx.k_meta
+            grad_k = torch.from_numpy(gk).to(device=dv, dtype=dt) * gJ.to(dv)
+            grad_g = None
+            if ctx.g_meta is not None:
+                grad_g = (gJ * float(go.sum())).to(device=ctx.g_meta[1], dtype=ctx.g_meta[0])
+            return None, None, None, None, None, None, grad_k, grad_g
+
+    return Functional
 
 
 def rollout_function():
@@ -559,7 +660,8 @@ class HybridGroup:
         vc = np.ascontiguousarray(np.asarray(mesh["v"]).reshape(-1, 2), np.float64)
         self._keep = [d0, vc]
         self.meshs = HybMesh(self.M, float(mesh["L"]), float(mesh.get("outer_value", 0.0)),
-                             int(mesh.get("overlap_elems", 1)), int(mesh.get("supg", 1)), _ptr(d0))
+                             int(mesh.get("overlap_elems", 1)), int(mesh.get("supg", 1)), _ptr(d0),
+                             int(mesh.get("outer_natural", 0)))
         lats = (HybLattice * len(self.patches))()
         for i, p in enumerate(self.patches):
             lats[i] = p.lat

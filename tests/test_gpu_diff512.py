@@ -1,0 +1,315 @@
+"""The differentiation workload on the GPU: inlet Dirichlet value on the
+outer edge x = 0, the other three outer edges natural (zero diffusive flux),
+a seeded per-node reaction-rate field on the fine patch, one Schwarz pass per
+coarse step.  The objective is the outlet flux through the patch's right
+edge, integrated over the coarse steps:
+
+    J = sum_{n=1}^{n_steps} sum_{j} sum_q e_{x,q} f*_q(N-1, j; t_n),
+
+with its gradient with respect to the fine rate field k and the inlet value
+g from the checkpointed GPU reverse sweep (hyb_step_record /
+hyb_step_adjoint), checked against the oracle at small size and against
+central differences of the GPU forward at 512^2 over 2000 substeps."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1601_02708_amd import configs
+
+pytestmark = pytest.mark.gpu
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], np.float64)
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_02708_amd import hyb
+    return hyb, torch
+
+
+def _rel(x, y):
+    return float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+
+
+def _small(**over):
+    kw = dict(N=129, M=16, eta=5)
+    kw.update(over)
+    return configs.build_problem(configs.DIFF512.replace(**kw))
+
+
+def _outlet_weights(p):
+    """dJ/df* of one step's term: e_x at the fluid nodes of the right edge."""
+    N = p.cfg.N
+    w = np.zeros((9, N, N))
+    w[:, :, N - 1] = EX[:, None]
+    w[:, p.solid != 0] = 0.0
+    return w
+
+
+def _inlet_nodes(M):
+    """Coarse nodes on the outer edge x = 0 (node index j (M+1) + i)."""
+    return np.arange(M + 1) * (M + 1)
+
+
+def test_natural_edges_forward_matches_oracle(orc):
+    """Three coarse steps with the inlet held at 1 and natural edges elsewhere,
+    fine rate field: GPU FP64 equals the oracle to 1e-12."""
+    hyb, torch = _gpu()
+    p = _small()
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    o = orc.HybridOracle(p)
+    for _ in range(3):
+        g.step(p.cfg.max_iter)
+        o.step()
+    errs = {"fine": _rel(g.concentration(hyb.HYB_FINE), o.fine_concentration()),
+            "coarse": _rel(g.concentration(hyb.HYB_COARSE).reshape(-1), o.d.reshape(-1)),
+            "F": _rel(g.get_populations(), o.fstar)}
+    print(f"\nnatural edges forward: {errs}")
+    assert max(errs.values()) <= 1e-12, errs
+    d = g.concentration(hyb.HYB_COARSE).reshape(p.cfg.M + 1, p.cfg.M + 1)
+    assert np.abs(d[:, 0] - 1.0).max() <= 1e-12          # the inlet edge holds g
+
+
+def test_natural_edges_step_adjoint_matches_oracle(orc):
+    """Two coarse steps, the outlet-flux cotangent after each: dJ/dF_0,
+    dJ/dd_0, dJ/dk and dJ/d(outer values) equal the oracle's; the outer
+    gradient lives on the inlet edge only."""
+    from oracle.hybrid_adjoint import HybridStepAdjoint
+    hyb, torch = _gpu()
+    p = _small()
+    N, M, P = p.cfg.N, p.cfg.M, p.cfg.max_iter
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    F0 = g.get_populations()
+    d0 = g.concentration(hyb.HYB_COARSE).reshape(-1)
+    w = _outlet_weights(p)
+    lF, ld, gk, go = hyb.steps_adjoint(g, 2, lambda n, F, d: (w, None), P, checkpoint_every=1,
+                                       state_in_cotangent=False)
+    adj = HybridStepAdjoint(orc.HybridOracle(p))
+    F, d = F0, d0
+    tapes = []
+    for _ in range(2):
+        F, d, tp = adj.forward(F, d)
+        tapes.append(tp)
+    oF, od = np.zeros((9, N, N)), np.zeros((M + 1) ** 2)
+    ok, oo = np.zeros((N, N)), np.zeros((M + 1) ** 2)
+    for n in (1, 0):
+        oF, od, k, out = adj.adjoint(tapes[n], oF + w, od, outer=True)
+        ok += k
+        oo += out
+    # dJ/dg is the transposed coarse solve's solution on the inlet rows: two
+    # steps after the objective, the adjoint field that reaches the inlet
+    # is ~1e-8 of its size at the patch, so its error is measured on the
+    # scale of the coarse adjoint (dJ/dd_0), which the Krylov tolerance sets
+    scale = max(np.abs(od).max(), np.abs(oo).max())
+    errs = {"F": _rel(lF, oF), "d": _rel(ld, od), "k": _rel(gk, ok),
+            "outer": float(np.abs(go - oo).max() / scale)}
+    print(f"\nnatural edges step adjoint: {errs}, max|dJ/dg| / max|dJ/dd_0| = {np.abs(oo).max() / scale:.2e}")
+    assert max(errs.values()) <= 1e-12, errs
+    off = np.ones((M + 1) ** 2, bool)
+    off[_inlet_nodes(M)] = False
+    assert np.all(go[off] == 0.0) and np.abs(go[~off]).max() > 0.0
+
+
+def _objective(hyb, torch, p, k_field, g_in, state0, precision="fp64"):
+    """J of the GPU forward for a rate field and an inlet value from the
+    initial state state0 = (F_0, d_0) (fresh handle, accumulated on the
+    device).  The handle's own initial state -- f*(0) collided with its rate
+    field, the coarse nodes with its inlet value -- is replaced by state0:
+    the controls act on the dynamics, and dJ/dk, dJ/dg are the partial
+    derivatives at fixed (F_0, d_0)."""
+    N, P = p.cfg.N, p.cfg.max_iter
+    g = hyb.Hybrid.from_problem(p, precision=precision, k_field=k_field, outer_value=g_in)
+    g.set_populations(state0[0])
+    g.set_coarse(state0[1])
+    buf = torch.empty((9, N, N), dtype=torch.float64, device=g.dev)
+    w = torch.from_numpy(_outlet_weights(p)[:, :, N - 1].copy()).to(g.dev)
+    J = torch.zeros((), dtype=torch.float64, device=g.dev)
+    for _ in range(p.cfg.steps):
+        g.step(P)
+        g.populations_device(buf)
+        J += (buf[:, :, N - 1] * w).sum()
+    val = float(J)
+    g.close()
+    return val
+
+
+def test_diff512_gradient_by_central_differences():
+    """512^2 patch on a 64^2 mesh, 200 coarse steps of 10 substeps (2000
+    substeps), checkpoints every 10 coarse steps (100 substeps): the FP64
+    adjoint's directional derivative along 16 seeded directions in
+    (k field, inlet value) agrees with central differences of the GPU FP64
+    forward to 1e-4; the FP32 adjoint's gradient is compared with FP64's."""
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.DIFF512)
+    cfg = p.cfg
+    N, M = cfg.N, cfg.M
+    w = _outlet_weights(p)
+    t0 = time.perf_counter()
+    grads = {}
+    state0 = None
+    for prec in ("fp64", "fp32"):
+        g = hyb.Hybrid.from_problem(p, precision=prec)
+        if state0 is None:
+            state0 = (g.get_populations(), g.concentration(hyb.HYB_COARSE).copy())
+        _, _, gk, go = hyb.steps_adjoint(g, cfg.steps, lambda n, F, d: (w, None), cfg.max_iter,
+                                         checkpoint_every=10, state_in_cotangent=False)
+        grads[prec] = (gk, float(go.sum()), go)
+        g.close()
+        print(f"\n{prec} adjoint of {cfg.steps} steps: {time.perf_counter() - t0:.1f} s", flush=True)
+    gk, gg, go = grads["fp64"]
+    off = np.ones((M + 1) ** 2, bool)
+    off[_inlet_nodes(M)] = False
+    assert np.all(go[off] == 0.0)
+    assert np.all(gk[p.solid != 0] == 0.0)
+    e32 = {"k": _rel(grads["fp32"][0], gk), "g": abs(grads["fp32"][1] - gg) / abs(gg)}
+    print(f"FP32 adjoint vs FP64: {e32}", flush=True)
+    assert max(e32.values()) <= 1e-3, e32
+
+    rng = np.random.default_rng(cfg.seed + 5000)
+    eps = 1e-3
+    worst = 0.0
+    scale = 0.0
+    for r in range(17):
+        # 16 seeded mixed directions, then the inlet value alone
+        dk = rng.uniform(-1.0, 1.0, (N, N)) * p.k_field if r < 16 else np.zeros((N, N))
+        dk[p.solid != 0] = 0.0
+        dg = float(rng.uniform(-1.0, 1.0)) if r < 16 else 1.0
+        jp = _objective(hyb, torch, p, p.k_field + eps * dk, cfg.outer_value + eps * dg, state0)
+        jm = _objective(hyb, torch, p, p.k_field - eps * dk, cfg.outer_value - eps * dg, state0)
+        fd = (jp - jm) / (2 * eps)
+        an = float(np.sum(gk * dk)) + gg * dg
+        if r < 16:
+            rel = abs(fd - an) / max(abs(fd), 1e-300)
+            worst = max(worst, rel)
+            scale = max(scale, abs(fd))
+        else:
+            # the inlet is 255 lattice units upstream of the patch; over 2000
+            # substeps diffusion reaches ~5 and advection ~100 of them, so
+            # dJ/dg is zero to rounding here: checked on the scale of the
+            # mixed directions (the inlet-sensitive case below has its own)
+            rel = abs(fd - an) / scale
+        print(f"direction {r}: adjoint {an:.12e} central {fd:.12e} rel {rel:.2e} "
+              f"({time.perf_counter() - t0:.1f} s)", flush=True)
+        assert rel <= 1e-4, (r, an, fd)
+    print(f"worst relative difference over the mixed directions: {worst:.2e}")
+
+
+def test_inlet_gradient_matches_the_oracle():
+    """A case the inlet reaches: 33^2 patch on an 8^2 mesh (inlet 16 lattice
+    units upstream of the patch), D = 0.1, 200 coarse steps of 10 substeps.
+    J is affine in the inlet value g, so the oracle's J(1) - J(0) from the
+    same start state is dJ/dg exactly (up to rounding); the GPU adjoint's
+    dJ/dg (summed over the inlet rows) equals it, and the GPU forward's J
+    equals the oracle's."""
+    from oracle.hybrid import HybridOracle
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.DIFF512.replace(N=33, M=8, D=0.1, eta=10, steps=200))
+    cfg = p.cfg
+    N = cfg.N
+    w = _outlet_weights(p)
+
+    def oracle_J(gv):
+        """J and the sum of its terms' magnitudes (J, a signed sum over
+        200 steps, cancels: its error is stated on that scale)"""
+        o = HybridOracle(p, outer_value=gv)
+        J = Jabs = 0.0
+        for _ in range(cfg.steps):
+            o.step()
+            t = o.fstar[:, :, N - 1] * w[:, :, N - 1]
+            J += float(np.sum(t))
+            Jabs += float(np.sum(np.abs(t)))
+        return J, Jabs
+
+    (J1, J1abs), (J0, _) = oracle_J(1.0), oracle_J(0.0)
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    state0 = (g.get_populations(), g.concentration(hyb.HYB_COARSE).copy())
+    _, _, gk, go = hyb.steps_adjoint(g, cfg.steps, lambda n, F, d: (w, None), cfg.max_iter,
+                                     checkpoint_every=10, state_in_cotangent=False)
+    g.close()
+    Jg = _objective(hyb, torch, p, p.k_field, 1.0, state0)
+    print(f"\nJ(1) = {J1:.12e} (GPU {Jg:.12e}), dJ/dg oracle {J1 - J0:.12e} adjoint {go.sum():.12e}")
+    assert abs(Jg - J1) <= 1e-12 * J1abs, (Jg, J1, J1abs)
+    assert abs(J1 - J0) > 1e-3 * abs(J1)                  # the inlet matters here
+    assert abs(go.sum() - (J1 - J0)) <= 1e-9 * abs(J1 - J0)
+
+
+def test_trajectory_functional_autograd():
+    """torch.autograd through the outlet-flux objective at 512^2 over 2000
+    substeps: J equals the fresh-handle forward's, and the gradients in
+    (k, g) agree with central differences of the Function's own forward
+    (controls replaced on the same handle) along three mixed directions."""
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.DIFF512)
+    cfg = p.cfg
+    N, P = cfg.N, cfg.max_iter
+    w = _outlet_weights(p)
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    start = g.checkpoint()
+    state0 = (g.get_populations(), g.concentration(hyb.HYB_COARSE).copy())
+    Functional = hyb.trajectory_functional()
+    k = torch.tensor(p.k_field, dtype=torch.float64, requires_grad=True)
+    gv = torch.tensor(cfg.outer_value, dtype=torch.float64, requires_grad=True)
+    J = Functional.apply(g, cfg.steps, P, 10, w, None, k, gv)
+    J.backward()
+    j_ref = _objective(hyb, torch, p, p.k_field, cfg.outer_value, state0)
+    assert abs(float(J.detach()) - j_ref) <= 1e-14 * abs(j_ref), (float(J.detach()), j_ref)
+    gk, gg = k.grad.numpy(), float(gv.grad)
+    print(f"\nJ = {float(J.detach()):.12e}, dJ/dg = {gg:.6e}, max|dJ/dk| = {np.abs(gk).max():.6e}")
+    rng = np.random.default_rng(cfg.seed + 6000)
+    eps = 1e-3
+    with torch.no_grad():
+        for r in range(3):
+            dk = rng.uniform(-1.0, 1.0, (N, N)) * p.k_field
+            dk[p.solid != 0] = 0.0
+            dg = float(rng.uniform(-1.0, 1.0))
+            vals = []
+            for s in (1.0, -1.0):
+                g.restore(start)
+                vals.append(float(Functional.apply(g, cfg.steps, P, 10, w, None,
+                                                   torch.from_numpy(p.k_field + s * eps * dk),
+                                                   torch.tensor(cfg.outer_value + s * eps * dg,
+                                                                dtype=torch.float64))))
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            an = float(np.sum(gk * dk)) + gg * dg
+            rel = abs(fd - an) / abs(fd)
+            print(f"direction {r}: adjoint {an:.12e} central {fd:.12e} rel {rel:.2e}", flush=True)
+            assert rel <= 1e-4, (r, an, fd)
+    g.close()
+
+
+def test_control_setters():
+    """hyb_set_reaction_field on a uniform-k handle gives the run of a handle
+    created with that field; hyb_set_outer_value that of one created with
+    that value; out-of-range rates, non-finite values and a lattice-only
+    handle are rejected."""
+    hyb, torch = _gpu()
+    p = _small()
+    cfg = p.cfg
+    a = hyb.Hybrid.from_problem(p, precision="fp64", outer_value=0.3)
+    b = hyb.Hybrid.from_problem(p, precision="fp64", k_field=None, outer_value=0.0)
+    b.set_reaction_field(p.k_field)
+    b.set_outer_value(0.3)
+    # the start state of a (its f*(0) collided with the field) for both
+    b.set_populations(a.get_populations())
+    b.set_coarse(a.concentration(hyb.HYB_COARSE))
+    for h in (a, b):
+        for _ in range(3):
+            h.step(cfg.max_iter)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    assert np.array_equal(a.concentration(hyb.HYB_COARSE), b.concentration(hyb.HYB_COARSE))
+    bad = p.k_field.copy()
+    bad[3, 4] = 1.0
+    with pytest.raises(hyb.HybError):
+        b.set_reaction_field(bad)
+    bad[3, 4] = np.nan
+    with pytest.raises(hyb.HybError):
+        b.set_reaction_field(bad)
+    with pytest.raises(hyb.HybError):
+        b.set_outer_value(float("inf"))
+    z = np.zeros((8, 8))
+    lat_only = hyb.Hybrid(N=8, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.1, eta=2)
+    with pytest.raises(hyb.HybError):
+        lat_only.set_outer_value(1.0)

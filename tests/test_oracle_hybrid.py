@@ -96,3 +96,41 @@ def test_coupling_consistent_resolved_pulse(orc):
     jj, ii = np.meshgrid(np.arange(N)[sl], np.arange(N)[sl], indexing="ij")
     uc = orc.fem_interpolate(p.cfg.M, p.L, o.d, p.x0 + ii.ravel(), p.y0 + jj.ravel())
     assert np.abs(uc - u[jj, ii].ravel()).max() < 0.08 * u.max()
+
+
+def test_natural_outer_edges_keep_a_constant(orc):
+    """With every outer edge natural (zero diffusive flux) and no flow or
+    reaction, a constant state stays constant whatever the outer value;
+    with Dirichlet edges at another value it does not."""
+    from paper_1601_02708_amd import configs
+    cfg = configs.SMALL.replace(v_uniform=(0.0, 0.0))
+    p = configs.build_problem(cfg)
+    c = 0.6
+    p.u0_fine[:] = c
+    p.u0_coarse[:] = c
+    o = orc.HybridOracle(p, outer_value=0.0, outer_natural=15).run(3)
+    assert np.abs(o.d - c).max() <= 1e-13
+    assert np.abs(o.fine_concentration() - c).max() <= 1e-13
+    o2 = orc.HybridOracle(p, outer_value=0.0, outer_natural=0).run(3)
+    assert np.abs(o2.d - c).max() > 1e-2
+
+
+def test_inlet_with_natural_edges_is_mirror_symmetric(orc):
+    """Inlet edge x = 0 held at 1, the other three natural, flow along x:
+    the problem is symmetric about y = L/2, and so is the solution
+    (populations mirrored in y: q 2 <-> 4, 5 <-> 8, 6 <-> 7)."""
+    from paper_1601_02708_amd import configs, inputs
+    cfg = configs.SMALL.replace(v_uniform=(0.05, 0.0))
+    p = configs.build_problem(cfg)
+    pulse = inputs.Pulse(xc=0.45 * p.L, yc=0.5 * p.L, sigma=0.1 * p.L)
+    X, Y = inputs.fine_coords(cfg.N)
+    XC, YC = inputs.coarse_coords(cfg.M, p.L)
+    p.u0_fine[:] = pulse(X, Y)
+    p.u0_coarse[:] = pulse(XC, YC).ravel()
+    o = orc.HybridOracle(p, outer_value=1.0, outer_natural=14).run(3)
+    d = o.d.reshape(cfg.M + 1, cfg.M + 1)
+    assert np.abs(d - d[::-1, :]).max() <= 1e-12 * np.abs(d).max()
+    F = o.fstar
+    mirror_q = [0, 1, 4, 3, 2, 8, 7, 6, 5]
+    assert np.abs(F - F[mirror_q][:, ::-1, :]).max() <= 1e-12 * np.abs(F).max()
+    assert np.abs(d[:, 0] - 1.0).max() <= 1e-12 and d[:, -1].max() < 0.99   # the inlet holds, the far edge is free
