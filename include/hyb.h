@@ -284,33 +284,40 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape);
 int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_d, double *lam_f_out,
                      double *lam_d_out, double *grad_k, double *grad_outer);
 
-/* Overlap in hyb_step (default HYB_OVERLAP_AUTO): with two-step launches,
- * the deep interior tiles of each Schwarz pass's first `depth` launches run
- * on a second stream owned by the handle while the pass's fine-to-coarse
- * transfer, coarse solve and coarse-to-fine transfer run on the caller's
- * stream; the remaining tiles follow on the caller's stream.  Launch j
- * (j = 0 .. depth-1, fine steps 2j+1 and 2j+2) splits at the rectangle of
- * tiles whose one-node ring stays clear of the patch perimeter shrunk by j
- * tiles on every side: such tiles read no interface value and, with their
- * two-node halo, only the deep tiles of launch j-1.  Depth is capped at the
- * pass's number of two-step launches (eta / 2).  Results are bit-identical
- * to the serial order for every depth.  depth = 0 runs everything on the
- * caller's stream.  HYB_OVERLAP_AUTO: of the handle's next 1 + 3 (D + 1)
- * successful hyb_step calls (D = eta / 2), the first runs serially and the
- * others at depths 0 .. D three times over, each timed on the caller's
- * stream; later calls use the depth with the fastest step; hyb_stats
- * reports the depth (-1 while tuning).  Other negative depths: HYB_EINVAL. */
+/* Overlap in hyb_step (default HYB_OVERLAP_AUTO): with multi-step
+ * launches (hyb_set_steps_per_launch), the deep interior tiles of each
+ * Schwarz pass's first `depth` launches run on a second stream owned by the
+ * handle while the pass's fine-to-coarse transfer, coarse solve and
+ * coarse-to-fine transfer run on the caller's stream; the remaining tiles
+ * follow on the caller's stream.  Launch j (j = 0 .. depth-1, its two or
+ * three fine steps) splits at the rectangle of tiles whose ring (one node,
+ * or two in passes with three-step launches) stays clear of the patch
+ * perimeter, shrunk by j tiles on every side: such tiles read no interface
+ * value and, with their halo, only the deep tiles of launch j-1.  Depth is
+ * capped at D, the pass's number of leading multi-step launches (eta / 2
+ * with two-step launches; 4 at eta = 10 with three-step launches, 3 + 3 +
+ * 2 + 2).  Results are bit-identical to the serial order for every depth.
+ * depth = 0 runs everything on the caller's stream.  HYB_OVERLAP_AUTO: of
+ * the handle's next 1 + 3 (D + 1) successful hyb_step calls, the first runs
+ * serially and the others at depths 0 .. D three times over, each timed on
+ * the caller's stream; later calls use the depth with the fastest step;
+ * hyb_stats reports the depth (-1 while tuning).  Other negative depths:
+ * HYB_EINVAL. */
 int hyb_set_overlap(hyb_handle *h, int depth);
 
-/* Fine steps per lattice-sweep launch (1 or 2; default 2).  With 2, while
- * every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine steps in
- * pairs, each pair in one temporally blocked launch (the state between the
- * two steps stays on chip); an odd remainder, and every step when some
- * slot is Neumann, or when a population buffer reaches 4 GiB (the
- * two-step kernel uses 32-bit byte offsets), uses the single-step sweep.
- * Results agree with the single-step path to rounding (same operations
- * per node).  Returns HYB_EINVAL for other values.  Takes effect at the
- * next hyb_lbm_substeps. */
+/* Most fine steps per lattice-sweep launch (1, 2 or 3; default 3).  With 2
+ * or more, while every perimeter slot is Dirichlet, hyb_lbm_substeps takes
+ * fine steps in temporally blocked launches (the state between the steps of
+ * one launch stays on chip): with 2, in pairs; with 3, in threes for
+ * HYB_FP32 and HYB_FP16S storage and fixed solids, a remainder of 4 taken
+ * as two pairs and of 2 as one (eta = 10: 3 + 3 + 2 + 2), while HYB_FP64
+ * storage and dissolving solids take pairs.  A remaining single step, and
+ * every step when some slot is Neumann, or when a population buffer reaches
+ * 4 GiB (the multi-step kernels use 32-bit byte offsets), uses the
+ * single-step sweep.  Results agree with the single-step path to rounding
+ * (same operations per node; two- and three-step launches give the same
+ * bits).  Returns HYB_EINVAL for other values.  Takes effect at the next
+ * hyb_lbm_substeps and restarts the overlap tuning of HYB_OVERLAP_AUTO. */
 int hyb_set_steps_per_launch(hyb_handle *h, int steps);
 
 /* Measurement: while enabled, every hyb_lbm_substeps call records HIP

@@ -190,7 +190,7 @@ struct hyb_handle {
     double *bc_a = nullptr, *bc_b = nullptr;
     bool kinds_set = false;
     bool any_neumann = false;
-    int steps_per_launch = 2;          // 2: two-step sweep when every slot is Dirichlet
+    int steps_per_launch = 3;          // most fine steps per sweep launch (fuse_steps)
     const void *rec_tape = nullptr;     // last forward recording (hyb_lbm_substeps_record)
     int rec_n = 0;
     int *c2f_idx = nullptr, *fc_idx = nullptr;
@@ -676,12 +676,55 @@ namespace {
 // offsets, so it serves buffers below 4 GiB (N up to about 11500 in FP64)
 bool use_two_step(const hyb_handle *h) {
     const bool small_buf = 9.0 * (double)h->lay.plane * (double)storage_bytes(h->prec) < 4294967295.0;
-    return !h->any_neumann && h->steps_per_launch == 2 && small_buf;
+    return !h->any_neumann && h->steps_per_launch >= 2 && small_buf;
 }
 
-// largest overlap depth hyb_step may use: the pass's two-step launches
-// (none with dissolving solids, whose sweeps run whole-patch launches)
-int overlap_dmax(const hyb_handle *h) { return use_two_step(h) && !h->dissolve_on ? h->eta / 2 : 0; }
+// Most fine steps one launch of the forward sub-stepping takes: 3 with
+// hyb_set_steps_per_launch(3) for 4-byte and 2-byte storage and fixed
+// solids, 2 where two-step launches apply, else 1.
+int fuse_steps(const hyb_handle *h) {
+    if (!use_two_step(h)) return 1;
+    return h->steps_per_launch == 3 && h->prec != HYB_FP64 && !h->dissolve_on ? 3 : 2;
+}
+
+// Fine steps of the next launch when `rem` steps of the call remain: with
+// three-step launches a remainder of 4 is taken as 2 + 2 and of 1 as a
+// single step (eta = 10: 3, 3, 2, 2), else as many as allowed.
+int plan_take(int fuse, int rem) {
+    if (rem <= 1 || fuse == 1) return rem < 1 ? 0 : 1;
+    if (fuse == 2) return 2;
+    return rem == 2 || rem == 4 ? 2 : 3;
+}
+
+// Ring of the overlap rectangles of a pass: the three-step kernel reads
+// two nodes beyond its tile, and every launch of a pass uses the same
+// rectangles so that those of successive launches nest.
+int pass_ring(const hyb_handle *h) { return fuse_steps(h) == 3 ? 2 : 1; }
+
+// largest overlap depth hyb_step may use: the leading multi-step launches of
+// a pass (none with dissolving solids, whose sweeps run whole-patch launches)
+int overlap_dmax(const hyb_handle *h) {
+    if (!use_two_step(h) || h->dissolve_on) return 0;
+    const int fuse = fuse_steps(h);
+    int k = 0;
+    for (int rem = h->eta; rem > 0; ++k) {
+        const int t = plan_take(fuse, rem);
+        if (t < 2) break;
+        rem -= t;
+    }
+    return k;
+}
+
+// One multi-step launch of `take` fine steps (2 or 3) from a.src to a.dst,
+// fine steps j0 + 1 .. j0 + take of the pass (interface weights (j0+1)/eta,
+// ...).
+hipError_t launch_fused(const hyb_handle *h, LbmArgs a, int j0, int take, hipStream_t s, int part, int depth) {
+    a.lam = (double)(j0 + 1) / (double)h->eta;
+    a.lam2 = (double)(j0 + 2) / (double)h->eta;
+    a.lam3 = (double)(j0 + 3) / (double)h->eta;
+    if (take == 3) return launch_lbm_step3(a, h->prec, s, part, depth);
+    return launch_lbm_step2(a, h->prec, s, part, depth, pass_ring(h));
+}
 
 // the host copy of the solid flags after commits that may have converted
 // solids (waits for the stream)
@@ -720,7 +763,7 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, int deep
     // it)
     const bool timed = h->timing && h->N > 2 && n_sub > 0;
     const bool general = h->any_neumann;
-    const bool fuse2 = use_two_step(h);
+    const int fuse = fuse_steps(h);
     auto take_pair = [&](hipEvent_t *e0, hipEvent_t *e1) -> hipError_t {
         if (2 * (h->ev_used + 1) > h->ev_pool.size()) {
             for (int k = 0; k < 2; ++k) {
@@ -752,9 +795,9 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, int deep
             a.flux_first = h->jsub == 0;
             h->flux_valid = true;
         }
-        const int take = (fuse2 && n_sub - s >= 2) ? 2 : 1;
+        const int take = plan_take(fuse, n_sub - s);
         const bool split_now = launch < deep;
-        if (split_now && take != 2) return h->fail(HYB_EINVAL, "internal: split launch is not a two-step launch");
+        if (split_now && take < 2) return h->fail(HYB_EINVAL, "internal: split launch is not a multi-step launch");
         // the side stream's deep tiles this launch depends on
         if (deep > 0 && launch >= 1 && launch <= deep)
             HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_deep[launch - 1], 0));
@@ -763,9 +806,8 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, int deep
             gslot = h->ev_used - 1;
             HIP_TRY(h, hipEventRecord(g0, h->stream));
         }
-        if (take == 2) {
-            a.lam2 = (double)(h->jsub + 2) / (double)h->eta;
-            HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream, split_now ? 2 : 0, split_now ? launch : 0));
+        if (take >= 2) {
+            HIP_TRY(h, launch_fused(h, a, h->jsub, take, h->stream, split_now ? 2 : 0, split_now ? launch : 0));
         } else {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timed && general) {
@@ -798,11 +840,21 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, int deep
 // enqueues between the two calls (the buffer it reads may be the one that
 // launch 1 writes).
 int prelaunch_deep(hyb_handle *h, int dst, int deep, bool after_f2c) {
-    auto args = [&](int j, int src_buf, int dst_buf) {
-        LbmArgs a = h->lbm_args(src_buf, dst_buf);
-        a.lam = (double)(2 * j + 1) / (double)h->eta;
-        a.lam2 = (double)(2 * j + 2) / (double)h->eta;
-        return a;
+    // the pass's launch plan (as substeps_impl takes it for eta steps):
+    // launch j covers fine steps start[j] + 1 .. start[j] + take[j]
+    const int fuse = fuse_steps(h);
+    std::vector<int> start, take;
+    for (int rem = h->eta, j0 = 0; rem > 0 && (int)take.size() < deep;) {
+        const int t = plan_take(fuse, rem);
+        if (t < 2) return h->fail(HYB_EINVAL, "internal: overlap depth beyond the pass's multi-step launches");
+        start.push_back(j0);
+        take.push_back(t);
+        j0 += t;
+        rem -= t;
+    }
+    if ((int)take.size() < deep) return h->fail(HYB_EINVAL, "internal: overlap depth beyond the pass's launches");
+    auto launch = [&](int j, int src_buf, int dst_buf) {
+        return launch_fused(h, h->lbm_args(src_buf, dst_buf), start[j], take[j], h->side, 1, j);
     };
     while ((int)h->ev_deep.size() < deep) {
         hipEvent_t e;
@@ -812,7 +864,7 @@ int prelaunch_deep(hyb_handle *h, int dst, int deep, bool after_f2c) {
     if (!after_f2c) {
         HIP_TRY(h, hipEventRecord(h->ev_main, h->stream));
         HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_main, 0));
-        HIP_TRY(h, launch_lbm_step2(args(0, h->frozen, dst), h->prec, h->side, 1, 0));
+        HIP_TRY(h, launch(0, h->frozen, dst));
         HIP_TRY(h, hipEventRecord(h->ev_deep[0], h->side));
         return HYB_OK;
     }
@@ -822,7 +874,7 @@ int prelaunch_deep(hyb_handle *h, int dst, int deep, bool after_f2c) {
     int src = dst;
     for (int j = 1; j < deep; ++j) {
         const int out = h->spare(src);
-        HIP_TRY(h, launch_lbm_step2(args(j, src, out), h->prec, h->side, 1, j));
+        HIP_TRY(h, launch(j, src, out));
         HIP_TRY(h, hipEventRecord(h->ev_deep[j], h->side));
         src = out;
     }
@@ -1408,8 +1460,12 @@ extern "C" {
 
 int hyb_set_steps_per_launch(hyb_handle *h, int steps) {
     if (!h) return HYB_EINVAL;
-    if (steps != 1 && steps != 2) return h->fail(HYB_EINVAL, "steps per launch must be 1 or 2");
+    if (steps < 1 || steps > 3) return h->fail(HYB_EINVAL, "steps per launch must be 1, 2 or 3");
     h->steps_per_launch = steps;
+    // the launch plan sets the overlap depths available: tune again
+    h->tune_idx = 0;
+    h->tuned_depth = -1;
+    h->tune_ms.clear();
     return HYB_OK;
 }
 

@@ -730,6 +730,247 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_rec_kernel(LbmArgs a, TileMap m
 }
 
 // ---------------------------------------------------------------------------
+// Three fine steps per launch (4-byte and 2-byte storage)
+// ---------------------------------------------------------------------------
+// A workgroup owns a TW x TH tile.  Step j+1 runs on the tile grown by two
+// rings, from HBM into LDS (as the two-step kernel's first half, one ring
+// wider); step j+2 on the tile grown by one ring, from LDS, its results held
+// in registers across a barrier and written back over the values they
+// replace; step j+3 on the owned nodes, from LDS, stored to HBM.  Every node
+// takes exactly the single step's operations, and values pass through the
+// storage format between steps, so the result equals three single steps.
+// The state crosses HBM once per three fine steps; the extra ring costs
+// (TW+4)(TH+4) / ((TW+2)(TH+2)) more first-stage work than the two-step
+// kernel (1.24 at 64 x 8).
+template <typename S, int TW, int TH, int NT, int PART>
+__device__ __forceinline__ void sweep3_body(const LbmArgs &a, const TileMap &map) {
+    typedef typename Pop<S>::T T;
+    constexpr int W0 = TW + 4, H0 = TH + 4, R0 = W0 * H0;
+    constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
+    constexpr int ROUNDS0 = (R0 + NT - 1) / NT;
+    constexpr int ROUNDS1 = (R1 + NT - 1) / NT;
+    static_assert((TW * TH) % NT == 0 && NT % TW == 0, "third stage: whole rows per round");
+    constexpr int ROUNDS2 = TW * TH / NT;
+    constexpr int PL = H0 * W0;
+    constexpr unsigned sz = sizeof(S);
+    __shared__ T lds[kQ][H0][W0];
+    T *const L0 = &lds[0][0][0];
+
+    const int N = a.N;
+    const int P = a.pitch;
+    const unsigned SP = static_cast<unsigned>(a.plane);
+    const unsigned NP = static_cast<unsigned>(N) * static_cast<unsigned>(P);
+    const BufRsrc fsrc = buf_rsrc(a.src, kQ * SP * sz);
+    const BufRsrc fdst = buf_rsrc(a.dst, kQ * SP * sz);
+    const BufRsrc mrs = buf_rsrc(a.mask, NP * 2u);
+    const BufRsrc vxr = buf_rsrc(a.vx, NP * 4u);
+    const BufRsrc vyr = buf_rsrc(a.vy, NP * 4u);
+    const T omega = T(a.omega);
+    int tx, ty;
+    tile_of<PART>(map, xcd_tile(blockIdx.x, map.count), tx, ty);
+    const int x0 = tx * TW;
+    const int y0 = ty * TH;
+
+    // ---- stage 1: step j+1 on the tile and two rings, HBM -> LDS --------
+    S raw[ROUNDS0][kQ];
+    unsigned m[ROUNDS0];
+    float vx1[ROUNDS0], vy1[ROUNDS0];
+    int rr[ROUNDS0], cc[ROUNDS0];
+    rr[0] = threadIdx.x / W0;
+    cc[0] = threadIdx.x - rr[0] * W0;
+#pragma unroll
+    for (int k = 1; k < ROUNDS0; ++k) {
+        rr[k] = rr[k - 1] + NT / W0;
+        cc[k] = cc[k - 1] + NT % W0;
+        if (cc[k] >= W0) {
+            cc[k] -= W0;
+            rr[k] += 1;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ROUNDS0; ++k) {
+        const int i = x0 - 2 + cc[k], j = y0 - 2 + rr[k];
+        m[k] = kMaskSolid;
+        if (rr[k] < H0 && i >= 0 && j >= 0 && i < N && j < N)
+            m[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * static_cast<unsigned>(j * P + i), 0, 0);
+    }
+    unsigned K[kQ], D[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const unsigned pull = q * SP - static_cast<unsigned>(kCx[q] + kCy[q] * P);
+        const unsigned own = kOpp[q] * SP;
+        K[q] = pull * sz;
+        D[q] = (own - pull) * sz;            // modulo 2^32; the sum below is exact
+    }
+#pragma unroll
+    for (int k = 0; k < ROUNDS0; ++k) {
+        if (m[k] & kMaskSolid) continue;
+        const int i = x0 - 2 + cc[k], j = y0 - 2 + rr[k];
+        const unsigned n = static_cast<unsigned>(j * P + i);
+        vx1[k] = Buf<float>::load(vxr, 4u * n, 0);
+        vy1[k] = Buf<float>::load(vyr, 4u * n, 0);
+        if (i >= 1 && j >= 1 && i <= N - 2 && j <= N - 2) {
+            const unsigned nb = n * sz;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const unsigned sel = 0u - ((m[k] >> q) & 1u);
+                raw[k][q] = Buf<S>::load(fsrc, nb + K[q] + (sel & D[q]), 0);
+            }
+        } else {
+            const int jm = j > 0 ? j - 1 : 0, jp = j < N - 1 ? j + 1 : N - 1;
+            const int il = i > 0 ? i - 1 : 0, ir = i < N - 1 ? i + 1 : N - 1;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int sj = kCy[q] == 1 ? jm : kCy[q] == -1 ? jp : j;
+                const int si = kCx[q] == 1 ? il : kCx[q] == -1 ? ir : i;
+                const unsigned pull = q * SP + static_cast<unsigned>(sj * P + si);
+                const unsigned own = kOpp[q] * SP + n;
+                raw[k][q] = Buf<S>::load(fsrc, (((m[k] >> q) & 1u) ? own : pull) * sz, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ROUNDS0; ++k) {
+        if (m[k] & kMaskSolid) continue;
+        const int r = rr[k], c = cc[k];
+        const int i = x0 - 2 + c, j = y0 - 2 + r;
+        const unsigned n = static_cast<unsigned>(j * P + i);
+        const bool owned = r >= 2 && r < 2 + TH && c >= 2 && c < 2 + TW;
+        T f[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const T pulled = Pop<S>::ld(raw[k][q], q, a);
+            const T own = Pop<S>::ld(raw[k][q], kOpp[q], a);
+            f[q] = ((m[k] >> q) & 1u) ? own : pulled;
+        }
+        if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
+            const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
+            if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+        }
+        const T u = collide<T>(f, T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
+        if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) lds[q][r][c] = Pop<S>::ld(Pop<S>::st(f[q], q, a), q, a);
+    }
+
+    // flags and velocities of the one-ring region, fetched before the barrier
+    unsigned m1[ROUNDS1];
+    float vx2[ROUNDS1], vy2[ROUNDS1];
+    int r1[ROUNDS1], c1[ROUNDS1];
+    r1[0] = threadIdx.x / W1;
+    c1[0] = threadIdx.x - r1[0] * W1;
+#pragma unroll
+    for (int k = 1; k < ROUNDS1; ++k) {
+        r1[k] = r1[k - 1] + NT / W1;
+        c1[k] = c1[k - 1] + NT % W1;
+        if (c1[k] >= W1) {
+            c1[k] -= W1;
+            r1[k] += 1;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ROUNDS1; ++k) {
+        const int i = x0 - 1 + c1[k], j = y0 - 1 + r1[k];
+        m1[k] = kMaskSolid;
+        if (r1[k] < H1 && i >= 0 && j >= 0 && i < N && j < N) {
+            const unsigned n = static_cast<unsigned>(j * P + i);
+            m1[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * n, 0, 0);
+            vx2[k] = Buf<float>::load(vxr, 4u * n, 0);
+            vy2[k] = Buf<float>::load(vyr, 4u * n, 0);
+        }
+    }
+    __syncthreads();
+
+    // ---- stage 2: step j+2 on the tile and one ring, LDS -> registers --
+    T h2[ROUNDS1][kQ];
+#pragma unroll
+    for (int k = 0; k < ROUNDS1; ++k) {
+        if (m1[k] & kMaskSolid) continue;
+        const int r = r1[k], c = c1[k];
+        const int i = x0 - 1 + c, j = y0 - 1 + r;
+        const unsigned n = static_cast<unsigned>(j * P + i);
+        const bool owned = r >= 1 && r <= TH && c >= 1 && c <= TW;
+        const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
+        // one LDS read per direction at a selected address (upstream value,
+        // or the node's own opposite value for a solid upstream node);
+        // closure unknowns are overwritten below
+        const T *base = L0 + (r + 1) * W0 + (c + 1);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int pull = q * PL - kCy[q] * W0 - kCx[q];
+            const int back = kOpp[q] * PL;
+            const int sel = -static_cast<int>((m1[k] >> q) & 1u);
+            h2[k][q] = base[pull + (sel & (back - pull))];
+        }
+        if (perim) {
+            const bool bad = dirichlet_close<T>(a, h2[k], outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam2);
+            if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+        }
+        const T u = collide<T>(h2[k], T(vx2[k]), T(vy2[k]), omega, node_k<T>(a, static_cast<int>(n)));
+        if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) h2[k][q] = Pop<S>::ld(Pop<S>::st(h2[k][q], q, a), q, a);
+    }
+
+    // flags and velocities of the owned nodes, fetched before the barrier
+    unsigned m2[ROUNDS2];
+    float vx3[ROUNDS2], vy3[ROUNDS2];
+#pragma unroll
+    for (int k = 0; k < ROUNDS2; ++k) {
+        const int idx = threadIdx.x + NT * k;
+        const int i = x0 + idx % TW, j = y0 + idx / TW;
+        m2[k] = kMaskSolid;
+        if (i < N && j < N) {
+            const unsigned n = static_cast<unsigned>(j * P + i);
+            m2[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * n, 0, 0);
+            vx3[k] = Buf<float>::load(vxr, 4u * n, 0);
+            vy3[k] = Buf<float>::load(vyr, 4u * n, 0);
+        }
+    }
+    __syncthreads();                 // every stage-2 read of step j+1 values is done
+#pragma unroll
+    for (int k = 0; k < ROUNDS1; ++k) {
+        if (m1[k] & kMaskSolid) continue;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) lds[q][r1[k] + 1][c1[k] + 1] = h2[k][q];
+    }
+    __syncthreads();
+
+    // ---- stage 3: step j+3 on the owned nodes, LDS -> HBM --------------
+#pragma unroll
+    for (int k = 0; k < ROUNDS2; ++k) {
+        if (m2[k] & kMaskSolid) continue;
+        const int idx = threadIdx.x + NT * k;
+        const int r = idx / TW, c = idx % TW;
+        const int i = x0 + c, j = y0 + r;
+        const unsigned n = static_cast<unsigned>(j * P + i);
+        const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
+        T g[kQ];
+        const T *base = L0 + (r + 2) * W0 + (c + 2);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int pull = q * PL - kCy[q] * W0 - kCx[q];
+            const int back = kOpp[q] * PL;
+            const int sel = -static_cast<int>((m2[k] >> q) & 1u);
+            g[q] = base[pull + (sel & (back - pull))];
+        }
+        if (perim) {
+            const bool bad = dirichlet_close<T>(a, g, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam3);
+            if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+        }
+        const T u = collide<T>(g, T(vx3[k]), T(vy3[k]), omega, node_k<T>(a, static_cast<int>(n)));
+        if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(g[q], q, a), fdst, n * sz, q * SP * sz);
+    }
+}
+
+template <typename S, int TW, int TH, int NT, int PART>
+__global__ void __launch_bounds__(NT) lbm_sweep3_kernel(LbmArgs a, TileMap map) {
+    sweep3_body<S, TW, TH, NT, PART>(a, map);
+}
+
+// ---------------------------------------------------------------------------
 // initial state: f*(0) = collide(f^eq(u0)) at fluid nodes (Sec. 6.2, item i)
 // ---------------------------------------------------------------------------
 template <typename S>
@@ -831,20 +1072,24 @@ template <typename S> struct Tile2 { static constexpr int TW = SWEEP2_TW32, TH =
 template <> struct Tile2<double> { static constexpr int TW = SWEEP2_TW64, TH = SWEEP2_TH64, NT = SWEEP2_NT64; };
 
 template <typename S>
-hipError_t step2_impl(const LbmArgs &a, int part, int depth, hipStream_t s) {
+hipError_t step2_impl(const LbmArgs &a, int part, int depth, int ring, hipStream_t s) {
     constexpr int TW = Tile2<S>::TW, TH = Tile2<S>::TH, NT = Tile2<S>::NT;
     TileMap m{};
     m.tiles_x = (a.N + TW - 1) / TW;
     m.tiles_y = (a.N + TH - 1) / TH;
     m.part = part;
-    // depth-0 rectangle: tiles whose ring (x0 - 1 .. x0 + TW, y0 - 1 .. y0 + TH)
-    // lies within columns and rows 1 .. N-2 (all full tiles); depth d shrinks
-    // it by d tiles on every side
-    const bool fits = a.N - 2 - TW >= TW && a.N - 2 - TH >= TH;
+    // depth-0 rectangle: tiles whose ring of `ring` nodes (x0 - ring ..
+    // x0 + TW - 1 + ring, likewise in y) lies within columns and rows
+    // 1 .. N-2 (all full tiles); depth d shrinks it by d tiles on every side.
+    // The kernel reads a one-node ring; ring 2 gives the rectangles of the
+    // three-step launches of the same pass, so the rectangles of successive
+    // launches nest.
+    const int lx = a.N - 1 - ring - TW, ly = a.N - 1 - ring - TH;
+    const bool fits = lx >= TW && ly >= TH;
     m.ix0 = 1 + depth;
     m.iy0 = 1 + depth;
-    m.ix1 = (a.N - 2 - TW) / TW - depth;
-    m.iy1 = (a.N - 2 - TH) / TH - depth;
+    m.ix1 = (fits ? lx / TW : 0) - depth;
+    m.iy1 = (fits ? ly / TH : 0) - depth;
     const bool has_rect = fits && m.ix1 >= m.ix0 && m.iy1 >= m.iy0;
     const int all = m.tiles_x * m.tiles_y;
     const int inner = has_rect ? (m.ix1 - m.ix0 + 1) * (m.iy1 - m.iy0 + 1) : 0;
@@ -872,12 +1117,57 @@ hipError_t step2_impl(const LbmArgs &a, int part, int depth, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Tile of the three-step sweep (4-byte and 2-byte storage, FP32
+// arithmetic): LDS holds 9 planes of (TW+4) x (TH+4) values, 29.4 KB at
+// 64 x 8 (five workgroups per CU).
+struct Tile3 { static constexpr int TW = 64, TH = 8, NT = 256; };
+
+template <typename S>
+hipError_t step3_impl(const LbmArgs &a, int part, int depth, hipStream_t s) {
+    constexpr int TW = Tile3::TW, TH = Tile3::TH, NT = Tile3::NT;
+    TileMap m{};
+    m.tiles_x = (a.N + TW - 1) / TW;
+    m.tiles_y = (a.N + TH - 1) / TH;
+    m.part = part;
+    // depth-0 rectangle: tiles whose two-node ring (x0 - 2 .. x0 + TW + 1)
+    // lies within columns and rows 1 .. N-2; depth d shrinks it by d tiles
+    // on every side (a tile's ring lies within its neighbour tiles, which
+    // the previous launch's rectangle of depth d - 1 covers)
+    const int lx = a.N - 3 - TW, ly = a.N - 3 - TH;
+    const bool fits = lx >= TW && ly >= TH;
+    m.ix0 = 1 + depth;
+    m.iy0 = 1 + depth;
+    m.ix1 = (fits ? lx / TW : 0) - depth;
+    m.iy1 = (fits ? ly / TH : 0) - depth;
+    const bool has_rect = fits && m.ix1 >= m.ix0 && m.iy1 >= m.iy0;
+    const int all = m.tiles_x * m.tiles_y;
+    const int inner = has_rect ? (m.ix1 - m.ix0 + 1) * (m.iy1 - m.iy0 + 1) : 0;
+    if (part != 0 && !has_rect) {
+        if (part == 1) return hipSuccess;
+        m.part = 0;
+    }
+    m.count = m.part == 0 ? all : m.part == 1 ? inner : all - inner;
+    if (m.count == 0) return hipSuccess;
+    if (a.flux || a.kappa_s != 0.0 || a.mid) return hipErrorInvalidValue;
+    if (m.part == 0) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
+    else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
+    else hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part, int depth) {
-    if (prec == HYB_FP64) return step2_impl<double>(a, part, depth, s);
-    if (prec == HYB_FP32) return step2_impl<float>(a, part, depth, s);
-    return step2_impl<_Float16>(a, part, depth, s);
+hipError_t launch_lbm_step3(const LbmArgs &a, int prec, hipStream_t s, int part, int depth) {
+    if (prec == HYB_FP32) return step3_impl<float>(a, part, depth, s);
+    if (prec == HYB_FP16S) return step3_impl<_Float16>(a, part, depth, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part, int depth, int ring) {
+    if (ring != 1 && ring != 2) return hipErrorInvalidValue;
+    if (prec == HYB_FP64) return step2_impl<double>(a, part, depth, ring, s);
+    if (prec == HYB_FP32) return step2_impl<float>(a, part, depth, ring, s);
+    return step2_impl<_Float16>(a, part, depth, ring, s);
 }
 
 hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, hipStream_t s,

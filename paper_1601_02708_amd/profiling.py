@@ -49,10 +49,12 @@ def _per_kernel(path, counter):
 def traffic(fetch_csv, write_csv, out_path, workload, precision, copy_mib, commands):
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
-    tname = "float" if precision == "fp32" else "double"
-    # the dominant sweep kernel: the whole-patch two-step launch (tile part
-    # 0) when it ran, else the single-step one
-    sweep = [k for k in fetch if "lbm_sweep2_kernel" in k and f"<{tname}" in k and ", 0>" in k]
+    tname = {"fp32": "float", "fp64": "double", "fp16s": "_Float16"}[precision]
+    # the dominant sweep kernel: the whole-patch three-step launch (tile
+    # part 0) when it ran, else the whole-patch two-step launch, else the
+    # single-step one
+    sweep = [k for k in fetch if "lbm_sweep3_kernel" in k and f"<{tname}" in k and ", 0>" in k]
+    sweep = sweep or [k for k in fetch if "lbm_sweep2_kernel" in k and f"<{tname}" in k and ", 0>" in k]
     sweep = sweep or [k for k in fetch if "lbm_sweep_kernel" in k and f"<{tname}" in k]
     if not sweep:
         raise SystemExit("no sweep kernel in the counter file")

@@ -313,3 +313,25 @@ def test_control_setters():
     lat_only = hyb.Hybrid(N=8, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.1, eta=2)
     with pytest.raises(hyb.HybError):
         lat_only.set_outer_value(1.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_populations_device_matches_host_readout(precision):
+    """hyb_populations_device gives the fine state of hyb_get_populations
+    (bit for bit at fluid nodes) in FP64 and FP32 storage, and rejects FP16
+    shifted storage."""
+    hyb, torch = _gpu()
+    p = _small()
+    g = hyb.Hybrid.from_problem(p, precision=precision)
+    for _ in range(2):
+        g.step(p.cfg.max_iter)
+    N = p.cfg.N
+    buf = torch.full((9, N, N), float("nan"), dtype=torch.float64, device=g.dev)
+    g.populations_device(buf)
+    dev = buf.cpu().numpy()
+    host = g.get_populations()
+    fluid = p.solid == 0
+    assert np.array_equal(dev[:, fluid], host[:, fluid])
+    g16 = hyb.Hybrid.from_problem(p, precision="fp16s")
+    with pytest.raises(hyb.HybError):
+        g16.populations_device(buf)

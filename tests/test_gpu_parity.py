@@ -164,6 +164,136 @@ def test_two_step_sweep(orc, precision, N, clamp, k_field, eta):
     assert d <= (1e-14 if precision == "fp64" else 1e-6), d
 
 
+@pytest.mark.parametrize("N,clamp,k_field,eta", [(67, 0, False, 5), (130, 1, True, 9), (3, 0, False, 3),
+                                                  (4, 0, True, 6), (200, 0, False, 7), (65, 1, False, 10),
+                                                  (131, 0, True, 8)])
+def test_three_step_sweep(orc, N, clamp, k_field, eta):
+    """Fine steps taken three per launch (hyb_set_steps_per_launch(3), FP32;
+    the pass's plan: eta = 5 -> 3 + 2, 9 -> 3 + 3 + 3, 3 -> 3, 6 -> 3 + 3,
+    7 -> 3 + 2 + 2, 10 -> 3 + 3 + 2 + 2, 8 -> 3 + 3 + 2) against the oracle and
+    against the single-step sweep: random states, solids, every perimeter
+    slot Dirichlet with interface values that make some closures infeasible
+    (counted once per owned node, as by single steps), ragged tiles and
+    lattices smaller than one tile."""
+    hyb = _gpu()
+    solid, vx, vy, kf, tau = _lattice_case(N, 500 + N, porosity=0.75 if N > 8 else 1.0, k_field=k_field)
+    rng = np.random.default_rng(7 * N + eta)
+    P = 4 * (N - 1)
+    a = rng.uniform(0.2, 1.5, P)
+    b = rng.uniform(0.2, 1.5, P)
+    f0 = inputs.random_populations(N, 13 + N, lo=0.05, hi=0.4)
+    if solid is not None:
+        f0[:, solid != 0] = 0.0
+    lat = orc.Lattice(N, tau, vx.astype(np.float64), vy.astype(np.float64), solid=solid,
+                      k=kf if k_field else 1e-3, clamp=clamp)
+    f = f0.astype(np.float32).astype(np.float64)
+    bad = 0
+    for j in range(1, eta + 1):
+        lam = j / eta
+        f, nb = lat.substep(f, (1 - lam) * a + lam * b)
+        bad += nb
+    assert bad > 0
+    got = {}
+    for spl in (1, 3):
+        g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta,
+                       precision="fp32", tau=tau, solid=solid, k=0.0 if k_field else 1e-3, k_field=kf,
+                       bc_clamp=clamp)
+        g.set_steps_per_launch(spl)
+        g.set_populations(f0)
+        g.set_boundary(a, b)
+        g.lbm_substeps(eta, restart=1)
+        g.commit()
+        got[spl] = g.get_populations()
+        assert g.stats()["infeasible"] == bad, spl
+        err = np.abs(got[spl] - f).max() / np.abs(f).max()
+        assert err <= 2e-6, (spl, err)
+        g.close()
+    d = np.abs(got[3] - got[1]).max() / np.abs(got[1]).max()
+    assert d <= 1e-6, d
+
+
+def test_three_step_fp16s_matches_single_steps():
+    """FP16 shifted storage, three steps per launch: the same values as
+    single steps to the storage format's rounding (each step rounds through
+    binary16 in both)."""
+    hyb = _gpu()
+    N, eta = 97, 10
+    solid, vx, vy, kf, tau = _lattice_case(N, 777, porosity=0.7)
+    rng = np.random.default_rng(778)
+    P = 4 * (N - 1)
+    a = rng.uniform(0.2, 0.6, P)
+    b = rng.uniform(0.2, 0.6, P)
+    u0 = np.full((N, N), 0.4)
+    got = {}
+    for spl in (1, 3):
+        g = hyb.Hybrid(N=N, x0=0, y0=0, u0=u0, vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta, precision="fp16s",
+                       tau=tau, solid=solid, k=1e-3)
+        g.set_steps_per_launch(spl)
+        g.set_boundary(a, b)
+        g.lbm_substeps(eta, restart=1)
+        g.commit()
+        got[spl] = g.get_populations()
+        g.close()
+    d = np.abs(got[3] - got[1]).max() / np.abs(got[1]).max()
+    assert d <= 4e-3, d
+
+
+@pytest.mark.parametrize("over,steps,depths", [({"N": 600, "M": 32}, 3, (1, 2, 3, 4)),
+                                               ({"N": 1026, "M": 32}, 2, (1, 2, 4)),
+                                               ({"N": 257, "M": 32, "eta": 7}, 3, (1, 2, 3))])
+def test_three_step_overlapped_step_is_bit_identical(over, steps, depths):
+    """hyb_step with three-step launches (plan 3 + 3 + 2 + 2 at eta = 10,
+    3 + 2 + 2 at eta = 7) and the deep tiles of the first launches on the
+    side stream equals the serial order bit for bit at every depth; the
+    pass's two-step launches take the rectangles of the three-step ones
+    (at N = 1026 the one- and two-node-ring rectangles differ by a tile, so
+    rectangles that did not nest would read unwritten tiles).  Against
+    two-step launches the state agrees to FP32 rounding."""
+    hyb = _gpu()
+    p = problem("pore2048", **over)
+    out = []
+    for ov in (0,) + tuple(depths):
+        g = hyb.Hybrid.from_problem(p, precision="fp32")
+        g.set_steps_per_launch(3)
+        g.set_overlap(ov)
+        for _ in range(steps):
+            g.step(p.cfg.max_iter)
+        out.append((g.get_populations(), g.concentration(hyb.HYB_COARSE), g.stats()["infeasible"]))
+        g.close()
+    for d, o in zip(depths, out[1:]):
+        assert np.array_equal(o[0], out[0][0]), d
+        assert np.array_equal(o[1], out[0][1]), d
+        assert o[2] == out[0][2], d
+    g = hyb.Hybrid.from_problem(p, precision="fp32")
+    g.set_steps_per_launch(2)
+    g.set_overlap(0)
+    for _ in range(steps):
+        g.step(p.cfg.max_iter)
+    two = g.get_populations()
+    fluid = p.solid == 0
+    err = rel_l2(out[0][0], two, fluid)
+    print(f"\nthree-step vs two-step launches, {over}: rel L2 {err:.2e}")
+    assert err <= 1e-6, err
+
+
+def test_three_steps_fall_back_for_fp64():
+    """FP64 storage has no three-step kernel (its LDS tile would hold two
+    workgroups per CU): a setting of 3 runs the two-step launches, bit for
+    bit."""
+    hyb = _gpu()
+    p = problem("pore2048", N=257, M=32)
+    out = []
+    for spl in (2, 3):
+        g = hyb.Hybrid.from_problem(p, precision="fp64")
+        g.set_steps_per_launch(spl)
+        g.set_overlap(2)
+        for _ in range(2):
+            g.step(p.cfg.max_iter)
+        out.append(g.get_populations())
+        g.close()
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("name,over,precision,steps,depths",
                          [("small", {}, "fp64", 6, (1, 2)),
                           ("pore2048", {"N": 257, "M": 32}, "fp32", 4, (1, 2, 5)),
@@ -205,17 +335,20 @@ def test_overlap_rejects_negative_depth():
         g.set_overlap(-2)
 
 
-def test_overlap_auto_tunes_then_keeps_a_depth():
+@pytest.mark.parametrize("spl,D", [(2, 5), (3, 4)])
+def test_overlap_auto_tunes_then_keeps_a_depth(spl, D):
     """HYB_OVERLAP_AUTO (the default): one serial step, then three rounds
-    over depths 0 .. D (D = eta / 2), then one depth in 0 .. D stays; the
-    states equal the serial order's bit for bit throughout."""
+    over depths 0 .. D (D = the pass's multi-step launches at eta = 10:
+    5 pairs, or 3 + 3 + 2 + 2), then one depth in 0 .. D stays; the states
+    equal the serial order's bit for bit throughout."""
     hyb = _gpu()
     p = problem("pore2048", N=600, M=32)
-    D = p.cfg.eta // 2
     n_tune = 1 + 3 * (D + 1)
     ref = hyb.Hybrid.from_problem(p, precision="fp32")
+    ref.set_steps_per_launch(spl)
     ref.set_overlap(0)
     g = hyb.Hybrid.from_problem(p, precision="fp32")
+    g.set_steps_per_launch(spl)
     assert g.stats()["overlap_depth"] == -1
     for k in range(n_tune + 2):
         ref.step(p.cfg.max_iter)
@@ -231,7 +364,7 @@ def test_steps_per_launch_rejects_other_values():
     N = 8
     z = np.zeros((N, N))
     g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.1, eta=2)
-    for bad in (0, 3, -1):
+    for bad in (0, 4, -1):
         with pytest.raises(hyb.HybError):
             g.set_steps_per_launch(bad)
 
