@@ -52,12 +52,11 @@ ELEM = {"fp64": 8, "fp32": 4, "fp16s": 2}
 
 def dominant_launch(elem_bytes, steps_per_launch):
     """(kernel, fine steps per launch) of the dominant sweep launch: the
-    whole-patch launch (tile part 0) of the three-step sweep (4-byte and
-    2-byte storage at 3 steps per launch), of the two-step sweep, or the
-    single-step sweep."""
+    whole-patch launch (tile part 0) of the three-step sweep, of the
+    two-step sweep, or the single-step sweep."""
     t = {8: "double", 4: "float", 2: "_Float16"}[elem_bytes]
-    if steps_per_launch == 3 and elem_bytes != 8:
-        return f"lbm_sweep3_kernel<{t}, 64, 8, 256, 0>", 3
+    if steps_per_launch == 3:
+        return f"lbm_sweep3_kernel<{t}, 64, 8, {512 if elem_bytes == 8 else 256}, 0>", 3
     if steps_per_launch >= 2:
         return f"lbm_sweep2_kernel<{t}, 64, 8, {512 if elem_bytes == 8 else 256}, 0>", 2
     return f"lbm_sweep_kernel<{t}>", 1
@@ -526,8 +525,7 @@ def main():
     ap.add_argument("--workload", default="pore2048")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16s"])
     ap.add_argument("--steps-per-launch", type=int, default=3, choices=[1, 2, 3],
-                    help="most fine steps per lattice-sweep launch (3: temporally blocked threes for FP32 and "
-                         "FP16S storage, pairs for FP64; 2: pairs)")
+                    help="most fine steps per lattice-sweep launch (3: temporally blocked threes; 2: pairs)")
     ap.add_argument("--overlap", type=int, default=-1,
                     help="overlap depth of hyb_step (-1: the library's tuning, on a separate handle)")
     ap.add_argument("--timing-steps", type=int, default=10,

@@ -308,10 +308,9 @@ int hyb_set_overlap(hyb_handle *h, int depth);
 /* Most fine steps per lattice-sweep launch (1, 2 or 3; default 3).  With 2
  * or more, while every perimeter slot is Dirichlet, hyb_lbm_substeps takes
  * fine steps in temporally blocked launches (the state between the steps of
- * one launch stays on chip): with 2, in pairs; with 3, in threes for
- * HYB_FP32 and HYB_FP16S storage and fixed solids, a remainder of 4 taken
- * as two pairs and of 2 as one (eta = 10: 3 + 3 + 2 + 2), while HYB_FP64
- * storage and dissolving solids take pairs.  A remaining single step, and
+ * one launch stays on chip): with 2, in pairs; with 3, in threes, a
+ * remainder of 4 taken as two pairs and of 2 as one (eta = 10: 3 + 3 + 2 +
+ * 2), while dissolving solids take pairs.  A remaining single step, and
  * every step when some slot is Neumann, or when a population buffer reaches
  * 4 GiB (the multi-step kernels use 32-bit byte offsets), uses the
  * single-step sweep.  Results agree with the single-step path to rounding

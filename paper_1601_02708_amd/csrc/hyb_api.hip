@@ -680,11 +680,11 @@ bool use_two_step(const hyb_handle *h) {
 }
 
 // Most fine steps one launch of the forward sub-stepping takes: 3 with
-// hyb_set_steps_per_launch(3) for 4-byte and 2-byte storage and fixed
-// solids, 2 where two-step launches apply, else 1.
+// hyb_set_steps_per_launch(3) and fixed solids, 2 where two-step launches
+// apply, else 1.
 int fuse_steps(const hyb_handle *h) {
     if (!use_two_step(h)) return 1;
-    return h->steps_per_launch == 3 && h->prec != HYB_FP64 && !h->dissolve_on ? 3 : 2;
+    return h->steps_per_launch == 3 && !h->dissolve_on ? 3 : 2;
 }
 
 // Fine steps of the next launch when `rem` steps of the call remain: with

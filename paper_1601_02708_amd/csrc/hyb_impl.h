@@ -144,8 +144,8 @@ hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, h
 // rectangles of launch_lbm_step3 (for passes that mix the two).
 hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part = 0, int depth = 0,
                             int ring = 1);
-// Three fine steps in one launch (HYB_FP32 and HYB_FP16S; Dirichlet closure
-// on every slot, no surface reaction): a.src holds f*(j), a.dst receives
+// Three fine steps in one launch (Dirichlet closure on every slot, no
+// surface reaction): a.src holds f*(j), a.dst receives
 // f*(j+3); u^p at a.lam, a.lam2, a.lam3.  Parts as launch_lbm_step2, the
 // depth-0 rectangle being the tiles whose two-node ring stays clear of the
 // patch perimeter.

@@ -167,8 +167,9 @@ def test_two_step_sweep(orc, precision, N, clamp, k_field, eta):
 @pytest.mark.parametrize("N,clamp,k_field,eta", [(67, 0, False, 5), (130, 1, True, 9), (3, 0, False, 3),
                                                   (4, 0, True, 6), (200, 0, False, 7), (65, 1, False, 10),
                                                   (131, 0, True, 8)])
-def test_three_step_sweep(orc, N, clamp, k_field, eta):
-    """Fine steps taken three per launch (hyb_set_steps_per_launch(3), FP32;
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_three_step_sweep(orc, precision, N, clamp, k_field, eta):
+    """Fine steps taken three per launch (hyb_set_steps_per_launch(3);
     the pass's plan: eta = 5 -> 3 + 2, 9 -> 3 + 3 + 3, 3 -> 3, 6 -> 3 + 3,
     7 -> 3 + 2 + 2, 10 -> 3 + 3 + 2 + 2, 8 -> 3 + 3 + 2) against the oracle and
     against the single-step sweep: random states, solids, every perimeter
@@ -186,7 +187,7 @@ def test_three_step_sweep(orc, N, clamp, k_field, eta):
         f0[:, solid != 0] = 0.0
     lat = orc.Lattice(N, tau, vx.astype(np.float64), vy.astype(np.float64), solid=solid,
                       k=kf if k_field else 1e-3, clamp=clamp)
-    f = f0.astype(np.float32).astype(np.float64)
+    f = f0 if precision == "fp64" else f0.astype(np.float32).astype(np.float64)
     bad = 0
     for j in range(1, eta + 1):
         lam = j / eta
@@ -196,7 +197,7 @@ def test_three_step_sweep(orc, N, clamp, k_field, eta):
     got = {}
     for spl in (1, 3):
         g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta,
-                       precision="fp32", tau=tau, solid=solid, k=0.0 if k_field else 1e-3, k_field=kf,
+                       precision=precision, tau=tau, solid=solid, k=0.0 if k_field else 1e-3, k_field=kf,
                        bc_clamp=clamp)
         g.set_steps_per_launch(spl)
         g.set_populations(f0)
@@ -206,10 +207,10 @@ def test_three_step_sweep(orc, N, clamp, k_field, eta):
         got[spl] = g.get_populations()
         assert g.stats()["infeasible"] == bad, spl
         err = np.abs(got[spl] - f).max() / np.abs(f).max()
-        assert err <= 2e-6, (spl, err)
+        assert err <= (1e-13 if precision == "fp64" else 2e-6), (spl, err)
         g.close()
     d = np.abs(got[3] - got[1]).max() / np.abs(got[1]).max()
-    assert d <= 1e-6, d
+    assert d <= (1e-14 if precision == "fp64" else 1e-6), d
 
 
 def test_three_step_fp16s_matches_single_steps():
@@ -276,10 +277,9 @@ def test_three_step_overlapped_step_is_bit_identical(over, steps, depths):
     assert err <= 1e-6, err
 
 
-def test_three_steps_fall_back_for_fp64():
-    """FP64 storage has no three-step kernel (its LDS tile would hold two
-    workgroups per CU): a setting of 3 runs the two-step launches, bit for
-    bit."""
+def test_three_steps_fp64_equal_two_steps():
+    """FP64 storage, overlapped steps: three-step launches (512 lanes per
+    workgroup) give the two-step launches' state bit for bit."""
     hyb = _gpu()
     p = problem("pore2048", N=257, M=32)
     out = []
