@@ -50,16 +50,41 @@ def sweep_bytes(problem, elem_bytes):
 ELEM = {"fp64": 8, "fp32": 4, "fp16s": 2}
 
 
-def dominant_launch(elem_bytes, steps_per_launch):
-    """(kernel, fine steps per launch) of the dominant sweep launch: the
-    whole-patch launch (tile part 0) of the three-step sweep, of the
-    two-step sweep, or the single-step sweep."""
+def launch_plan(eta, steps_per_launch):
+    """Fine steps of each sweep launch of one Schwarz pass of eta fine steps,
+    as the library plans a pass (hyb_set_steps_per_launch; fixed solids,
+    every slot Dirichlet): as many steps as allowed, with no lone single
+    step where it can be avoided (eta = 10: 4 + 3 + 3 at 4, 3 + 3 + 2 + 2 at
+    3, five pairs at 2)."""
+    out, rem = [], eta
+    while rem > 0:
+        if rem <= 1 or steps_per_launch == 1:
+            t = 1
+        elif steps_per_launch == 2 or rem == 2:
+            t = 2
+        elif steps_per_launch == 3:
+            t = 2 if rem == 4 else 3
+        else:
+            t = 3 if rem in (3, 5, 6) else 4
+        out.append(t)
+        rem -= t
+    return out
+
+
+def default_steps_per_launch(precision):
+    """The library's default (hyb_set_steps_per_launch): 2 for FP16 shifted
+    storage, 4 otherwise."""
+    return 2 if precision == "fp16s" else 4
+
+
+def sweep_kernel(elem_bytes, take):
+    """Symbol of the whole-patch launch (tile part 0) of the sweep that
+    takes `take` fine steps per launch."""
     t = {8: "double", 4: "float", 2: "_Float16"}[elem_bytes]
-    if steps_per_launch == 3:
-        return f"lbm_sweep3_kernel<{t}, 64, 8, {512 if elem_bytes == 8 else 256}, 0>", 3
-    if steps_per_launch >= 2:
-        return f"lbm_sweep2_kernel<{t}, 64, 8, {512 if elem_bytes == 8 else 256}, 0>", 2
-    return f"lbm_sweep_kernel<{t}>", 1
+    nt = 512 if elem_bytes == 8 else 256
+    if take >= 2:
+        return f"lbm_sweep{take}_kernel<{t}, 64, 8, {nt}, 0>"
+    return f"lbm_sweep_kernel<{t}>"
 
 
 def load_traffic(workload, precision, kernel):
@@ -75,12 +100,12 @@ def load_traffic(workload, precision, kernel):
     return rec.get("bytes_per_launch")
 
 
-def tune_overlap(problem, precision, steps_per_launch=3):
+def tune_overlap(problem, precision, steps_per_launch=None):
     """Overlap depth the library's own tuning picks for this workload, found
     on a throwaway handle (its steps are not part of any measurement)."""
     from paper_1601_02708_amd import hyb
     g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
-    g.set_steps_per_launch(steps_per_launch)
+    g.set_steps_per_launch(steps_per_launch or default_steps_per_launch(precision))
     g.set_overlap(hyb.HYB_OVERLAP_AUTO)
     for _ in range(2 + 3 * (problem.cfg.eta // 2 + 1)):
         if g.stats()["overlap_depth"] >= 0:
@@ -91,19 +116,21 @@ def tune_overlap(problem, precision, steps_per_launch=3):
     return depth
 
 
-def run_gpu(problem, precision, steps, warmup, steps_per_launch=3, depth=None, timing_steps=10):
+def run_gpu(problem, precision, steps, warmup, steps_per_launch=None, depth=None, timing_steps=10):
     """W warmup and K timed coarse steps at the given overlap depth; then
     timing_steps more at depth 0 with kernel timing (every sweep launch
-    whole and on the handle's stream: the sweep time of a step), and
-    timing_steps chains of the dominant sweep kernel alone, for its
-    average launch duration: restarted passes of as many of its fine steps
-    as fit in eta (eta = 10, three-step kernel: 9, i.e. three launches, each
-    reading the previous one's output as inside a pass; a launch repeated
-    on one source buffer would re-read data left in the 256 MB last-level
-    cache and look faster than it runs in a pass), each call bracketed by
-    HIP events on the handle's stream."""
+    whole and on the handle's stream: the sweep time of a step), and, for
+    each kind of launch in the pass's plan, timing_steps chains of that
+    kind alone, for its average launch duration: restarted passes of as
+    many of its fine steps as fit in eta, taken by that kind only (eta = 10,
+    three-step launches: 9 steps in three launches, each reading the
+    previous one's output as inside a pass; a launch repeated on one source
+    buffer would re-read data left in the 256 MB last-level cache and look
+    faster than it runs in a pass), each call bracketed by HIP events on the
+    handle's stream.  Returns the average launch duration (ms) per kind."""
     import torch
     from paper_1601_02708_amd import hyb
+    steps_per_launch = steps_per_launch or default_steps_per_launch(precision)
     g = hyb.Hybrid.from_problem(problem, precision=precision, device="cuda:0")
     g.set_steps_per_launch(steps_per_launch)
     if depth is None:
@@ -133,18 +160,30 @@ def run_gpu(problem, precision, steps, warmup, steps_per_launch=3, depth=None, t
             g.step(mi)
         torch.cuda.synchronize()
         kms, launches = g.kernel_time()
-        _, take = dominant_launch(ELEM[precision], steps_per_launch)
-        chain = take * max(1, problem.cfg.eta // take)
-        for _ in range(timing_steps):
-            g.lbm_substeps(chain, restart=1)
-        torch.cuda.synchronize()
-        dom_ms, dom_n = g.kernel_time()
+        kinds = {}
+        eta = problem.cfg.eta
+        for take in sorted(set(launch_plan(eta, steps_per_launch))):
+            g.set_steps_per_launch(take)
+            for _ in range(timing_steps):
+                g.lbm_substeps(take * (eta // take), restart=1)
+            torch.cuda.synchronize()
+            ms_k, n_k = g.kernel_time()
+            kinds[take] = (ms_k / max(n_k, 1), n_k)
         g.kernel_timing(False)
+        g.set_steps_per_launch(steps_per_launch)
         g.lbm_substeps(0, restart=1)          # back to the committed state
         g.set_overlap(depth)
     else:
-        dom_ms, dom_n = 0.0, 0
-    return g, wall, gpu_ms, kms, launches, st, depth, dom_ms, dom_n
+        kinds = {}
+    return g, wall, gpu_ms, kms, launches, st, depth, kinds
+
+
+def dominant(kinds, eta, steps_per_launch):
+    """(fine steps per launch, average launch ms, launches timed) of the
+    launch kind with the most sweep time per pass."""
+    plan = launch_plan(eta, steps_per_launch)
+    take = max(kinds, key=lambda t: plan.count(t) * kinds[t][0])
+    return take, kinds[take][0], kinds[take][1]
 
 
 def adjoint_rate(problem, precision, reps=3):
@@ -524,8 +563,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pore2048")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16s"])
-    ap.add_argument("--steps-per-launch", type=int, default=3, choices=[1, 2, 3],
-                    help="most fine steps per lattice-sweep launch (3: temporally blocked threes; 2: pairs)")
+    ap.add_argument("--steps-per-launch", type=int, default=None, choices=[1, 2, 3, 4],
+                    help="most fine steps per lattice-sweep launch (temporal blocking; eta = 10 runs 4 + 3 + 3 "
+                         "at 4); default: the library's (4, or 2 for fp16s)")
     ap.add_argument("--overlap", type=int, default=-1,
                     help="overlap depth of hyb_step (-1: the library's tuning, on a separate handle)")
     ap.add_argument("--timing-steps", type=int, default=10,
@@ -568,13 +608,14 @@ def main():
     spl = args.steps_per_launch
     depth = tune_overlap(problem, args.precision, spl) if args.overlap < 0 else args.overlap
     print(f"[bench] overlap depth {depth}", file=sys.stderr, flush=True)
-    g, wall, gpu_ms, kms, launches, st, _, dom_ms, dom_n = run_gpu(problem, args.precision, args.steps, args.warmup,
-                                                                   spl, depth, args.timing_steps)
+    g, wall, gpu_ms, kms, launches, st, _, kinds = run_gpu(problem, args.precision, args.steps, args.warmup,
+                                                           spl, depth, args.timing_steps)
     ms_step = gpu_ms / args.steps
     value = lups_step * args.steps / (gpu_ms / 1e3) / 1e6
     bbytes, nfl, nsol, per_fluid = sweep_bytes(problem, elem)
-    kname, steps_launch = dominant_launch(elem, spl)
-    avg_kernel_ms = dom_ms / max(dom_n, 1)
+    spl = spl or default_steps_per_launch(args.precision)
+    steps_launch, avg_kernel_ms, dom_n = dominant(kinds, cfg.eta, spl)
+    kname = sweep_kernel(elem, steps_launch)
     # algorithmic bytes per launch = bytes per fluid lattice update x the
     # updates one launch performs (its fine steps over every fluid node)
     launch_bytes = bbytes * steps_launch
@@ -615,6 +656,8 @@ def main():
             "algorithmic_bytes_per_launch": int(launch_bytes),
             "avg_launch_ms": round(avg_kernel_ms, 5),
             "launches_timed": dom_n,
+            "pass_plan": launch_plan(cfg.eta, spl),
+            "avg_launch_ms_by_steps": {str(t): round(v[0], 5) for t, v in sorted(kinds.items())},
         },
         # sweep kernel time per coarse step (depth-0 timing steps) over the
         # step time of the timed (overlapped) steps
@@ -629,13 +672,13 @@ def main():
         conc = {args.precision: g.concentration()}
         for other in [p for p in ("fp64", "fp16s", "fp32") if p != args.precision]:
             print(f"[bench] comparison run {other}", file=sys.stderr, flush=True)
-            g2, _, gpu_ms2, kms2, launches2, _, d2, dom2, domn2 = run_gpu(problem, other, args.steps, args.warmup,
-                                                                          spl, None, args.timing_steps)
+            g2, _, gpu_ms2, kms2, launches2, _, d2, kinds2 = run_gpu(problem, other, args.steps, args.warmup,
+                                                                     args.steps_per_launch, None, args.timing_steps)
             conc[other] = g2.concentration()
             e2 = ELEM[other]
             b2, _, _, _ = sweep_bytes(problem, e2)
-            kname2, take2 = dominant_launch(e2, spl)
-            k2 = dom2 / max(domn2, 1)
+            take2, k2, _ = dominant(kinds2, cfg.eta, args.steps_per_launch or default_steps_per_launch(other))
+            kname2 = sweep_kernel(e2, take2)
             res[other] = {"value": round(lups_step * args.steps / (gpu_ms2 / 1e3) / 1e6, 1), "unit": "MLUPS",
                           "ms_per_step": round(gpu_ms2 / args.steps, 4), "overlap_depth": d2,
                           "sweep_kernel": kname2,

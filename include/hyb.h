@@ -289,14 +289,12 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
  * Schwarz pass's first `depth` launches run on a second stream owned by the
  * handle while the pass's fine-to-coarse transfer, coarse solve and
  * coarse-to-fine transfer run on the caller's stream; the remaining tiles
- * follow on the caller's stream.  Launch j (j = 0 .. depth-1, its two or
- * three fine steps) splits at the rectangle of tiles whose ring (one node,
- * or two in passes with three-step launches) stays clear of the patch
- * perimeter, shrunk by j tiles on every side: such tiles read no interface
+ * follow on the caller's stream.  Launch j (j = 0 .. depth-1, its fine
+ * steps) splits at the rectangle of tiles whose ring (one node, or K-1 in
+ * passes with K-step launches) stays clear of the patch perimeter, shrunk by j tiles on every side: such tiles read no interface
  * value and, with their halo, only the deep tiles of launch j-1.  Depth is
  * capped at D, the pass's number of leading multi-step launches (eta / 2
- * with two-step launches; 4 at eta = 10 with three-step launches, 3 + 3 +
- * 2 + 2).  Results are bit-identical to the serial order for every depth.
+ * with pairs; at eta = 10, 4 with 3 + 3 + 2 + 2 and 3 with 4 + 3 + 3).  Results are bit-identical to the serial order for every depth.
  * depth = 0 runs everything on the caller's stream.  HYB_OVERLAP_AUTO: of
  * the handle's next 1 + 3 (D + 1) successful hyb_step calls, the first runs
  * serially and the others at depths 0 .. D three times over, each timed on
@@ -305,12 +303,15 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
  * HYB_EINVAL. */
 int hyb_set_overlap(hyb_handle *h, int depth);
 
-/* Most fine steps per lattice-sweep launch (1, 2 or 3; default 3).  With 2
- * or more, while every perimeter slot is Dirichlet, hyb_lbm_substeps takes
- * fine steps in temporally blocked launches (the state between the steps of
- * one launch stays on chip): with 2, in pairs; with 3, in threes, a
- * remainder of 4 taken as two pairs and of 2 as one (eta = 10: 3 + 3 + 2 +
- * 2), while dissolving solids take pairs.  A remaining single step, and
+/* Most fine steps per lattice-sweep launch (1 to 4; default 4, or 2 for
+ * HYB_FP16S storage, the fastest measured for each).  With 2 or
+ * more, while every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine
+ * steps in temporally blocked launches (the state between the steps of one
+ * launch stays on chip), never leaving a lone single step where it can be
+ * avoided: with 2, in pairs; with 3, in threes, a remainder of 4 taken as
+ * two pairs (eta = 10: 3 + 3 + 2 + 2); with 4, in fours, remainders of 5 and
+ * 6 starting with a three (eta = 10: 4 + 3 + 3); dissolving solids take
+ * pairs.  A remaining single step, and
  * every step when some slot is Neumann, or when a population buffer reaches
  * 4 GiB (the multi-step kernels use 32-bit byte offsets), uses the
  * single-step sweep.  Results agree with the single-step path to rounding

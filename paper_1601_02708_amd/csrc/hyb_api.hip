@@ -190,7 +190,7 @@ struct hyb_handle {
     double *bc_a = nullptr, *bc_b = nullptr;
     bool kinds_set = false;
     bool any_neumann = false;
-    int steps_per_launch = 3;          // most fine steps per sweep launch (fuse_steps)
+    int steps_per_launch = 4;          // most fine steps per sweep launch (fuse_steps)
     const void *rec_tape = nullptr;     // last forward recording (hyb_lbm_substeps_record)
     int rec_n = 0;
     int *c2f_idx = nullptr, *fc_idx = nullptr;
@@ -364,6 +364,11 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     }
     h->N = N;
     h->prec = lat->precision;
+    // FP16 shifted storage decodes and encodes every value: its sweeps are
+    // bound by instruction issue, and deeper blocking measured slower (pore2048:
+    // 81.7, 80.5, 77.3 GLUPS at 2, 3, 4 steps per launch); the others gain
+    // up to 4 (FP32 84 -> 99-105, FP64 58 -> 67-69)
+    h->steps_per_launch = lat->precision == HYB_FP16S ? 2 : 4;
     h->fp64 = lat->precision == HYB_FP64;
     h->tau = tau;
     h->omega = 1.0 / tau;
@@ -679,27 +684,29 @@ bool use_two_step(const hyb_handle *h) {
     return !h->any_neumann && h->steps_per_launch >= 2 && small_buf;
 }
 
-// Most fine steps one launch of the forward sub-stepping takes: 3 with
-// hyb_set_steps_per_launch(3) and fixed solids, 2 where two-step launches
-// apply, else 1.
+// Most fine steps one launch of the forward sub-stepping takes: 3 or 4 with
+// hyb_set_steps_per_launch(3 or 4) and fixed solids, 2 where two-step
+// launches apply, else 1.
 int fuse_steps(const hyb_handle *h) {
     if (!use_two_step(h)) return 1;
-    return h->steps_per_launch == 3 && !h->dissolve_on ? 3 : 2;
+    return h->steps_per_launch >= 3 && !h->dissolve_on ? h->steps_per_launch : 2;
 }
 
-// Fine steps of the next launch when `rem` steps of the call remain: with
-// three-step launches a remainder of 4 is taken as 2 + 2 and of 1 as a
-// single step (eta = 10: 3, 3, 2, 2), else as many as allowed.
+// Fine steps of the next launch when `rem` steps of the call remain, never
+// leaving a lone single step where it can be avoided: with three-step
+// launches a remainder of 4 is taken as 2 + 2 (eta = 10: 3, 3, 2, 2); with
+// four-step launches remainders of 5 and 6 start with a 3 (eta = 10: 4, 3, 3).
 int plan_take(int fuse, int rem) {
     if (rem <= 1 || fuse == 1) return rem < 1 ? 0 : 1;
-    if (fuse == 2) return 2;
-    return rem == 2 || rem == 4 ? 2 : 3;
+    if (fuse == 2 || rem == 2) return 2;
+    if (fuse == 3) return rem == 4 ? 2 : 3;
+    return rem == 3 || rem == 5 || rem == 6 ? 3 : 4;
 }
 
-// Ring of the overlap rectangles of a pass: the three-step kernel reads
-// two nodes beyond its tile, and every launch of a pass uses the same
-// rectangles so that those of successive launches nest.
-int pass_ring(const hyb_handle *h) { return fuse_steps(h) == 3 ? 2 : 1; }
+// Ring of the overlap rectangles of a pass: a K-step kernel reads K-1 nodes
+// beyond its tile, and every launch of a pass uses the widest ring so that
+// the rectangles of successive launches nest.
+int pass_ring(const hyb_handle *h) { return fuse_steps(h) >= 3 ? fuse_steps(h) - 1 : 1; }
 
 // largest overlap depth hyb_step may use: the leading multi-step launches of
 // a pass (none with dissolving solids, whose sweeps run whole-patch launches)
@@ -715,14 +722,15 @@ int overlap_dmax(const hyb_handle *h) {
     return k;
 }
 
-// One multi-step launch of `take` fine steps (2 or 3) from a.src to a.dst,
+// One multi-step launch of `take` fine steps (2, 3 or 4) from a.src to a.dst,
 // fine steps j0 + 1 .. j0 + take of the pass (interface weights (j0+1)/eta,
 // ...).
 hipError_t launch_fused(const hyb_handle *h, LbmArgs a, int j0, int take, hipStream_t s, int part, int depth) {
     a.lam = (double)(j0 + 1) / (double)h->eta;
     a.lam2 = (double)(j0 + 2) / (double)h->eta;
     a.lam3 = (double)(j0 + 3) / (double)h->eta;
-    if (take == 3) return launch_lbm_step3(a, h->prec, s, part, depth);
+    a.lam4 = (double)(j0 + 4) / (double)h->eta;
+    if (take >= 3) return launch_lbm_stepk(a, h->prec, take, s, part, depth, pass_ring(h));
     return launch_lbm_step2(a, h->prec, s, part, depth, pass_ring(h));
 }
 
@@ -1460,7 +1468,7 @@ extern "C" {
 
 int hyb_set_steps_per_launch(hyb_handle *h, int steps) {
     if (!h) return HYB_EINVAL;
-    if (steps < 1 || steps > 3) return h->fail(HYB_EINVAL, "steps per launch must be 1, 2 or 3");
+    if (steps < 1 || steps > 4) return h->fail(HYB_EINVAL, "steps per launch must be 1, 2, 3 or 4");
     h->steps_per_launch = steps;
     // the launch plan sets the overlap depths available: tune again
     h->tune_idx = 0;

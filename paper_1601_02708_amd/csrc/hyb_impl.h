@@ -77,7 +77,8 @@ struct LbmArgs {
     const double *bc_b;
     double lam;              // j / eta of the step being taken
     double lam2;             // (j + 1) / eta: second step of a two-step launch
-    double lam3;             // (j + 2) / eta: third step of a three-step launch
+    double lam3;             // (j + 2) / eta: third step of a three- or four-step launch
+    double lam4;             // (j + 3) / eta: fourth step of a four-step launch
     int clamp;
     unsigned long long *counters;
     // FP16 shifted storage: stored g = (f - w_q c_ref) * scale (binary16);
@@ -140,16 +141,17 @@ hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, h
 // given depth (depth 0: the tiles whose one-node ring stays clear of the
 // patch perimeter, so they read no interface value; depth d: that rectangle
 // shrunk by d tiles on every side); part 2: the others.  Parts 1 and 2 of
-// one depth together update every node exactly as part 0.  ring 2: the
-// rectangles of launch_lbm_step3 (for passes that mix the two).
+// one depth together update every node exactly as part 0.  ring 2 or 3: the
+// rectangles of launch_lbm_stepk (ring K-1, for passes that mix them).
 hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part = 0, int depth = 0,
                             int ring = 1);
-// Three fine steps in one launch (Dirichlet closure on every slot, no
-// surface reaction): a.src holds f*(j), a.dst receives
-// f*(j+3); u^p at a.lam, a.lam2, a.lam3.  Parts as launch_lbm_step2, the
-// depth-0 rectangle being the tiles whose two-node ring stays clear of the
-// patch perimeter.
-hipError_t launch_lbm_step3(const LbmArgs &a, int prec, hipStream_t s, int part = 0, int depth = 0);
+// K = 3 or 4 fine steps in one launch (Dirichlet closure on every slot, no
+// surface reaction): a.src holds f*(j), a.dst receives f*(j+K); u^p at
+// a.lam, a.lam2, a.lam3 (, a.lam4).  Parts as launch_lbm_step2, the depth-0
+// rectangle being the tiles whose ring of `ring` >= K-1 nodes stays clear
+// of the patch perimeter.
+hipError_t launch_lbm_stepk(const LbmArgs &a, int prec, int K, hipStream_t s, int part = 0, int depth = 0,
+                            int ring = 0);
 // Adjoint of one fine step (adjoint_kernels.hip), HYB_FP64 or HYB_FP32:
 // a.src = the step's source state f*(t) (read only with clamped closures),
 // snext = f*(t+1), lam = dJ/df*(t+1); nu is scratch; out = dJ/df*(t);

@@ -730,31 +730,157 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_rec_kernel(LbmArgs a, TileMap m
 }
 
 // ---------------------------------------------------------------------------
-// Three fine steps per launch
+// K fine steps per launch (K = 3, 4)
 // ---------------------------------------------------------------------------
-// A workgroup owns a TW x TH tile.  Step j+1 runs on the tile grown by two
-// rings, from HBM into LDS (as the two-step kernel's first half, one ring
-// wider); step j+2 on the tile grown by one ring, from LDS, its results held
-// in registers across a barrier and written back over the values they
-// replace; step j+3 on the owned nodes, from LDS, stored to HBM.  Every node
-// takes exactly the single step's operations, and values pass through the
-// storage format between steps, so the result equals three single steps.
-// The state crosses HBM once per three fine steps; the extra ring costs
-// (TW+4)(TH+4) / ((TW+2)(TH+2)) more first-stage work than the two-step
-// kernel (1.24 at 64 x 8).
-template <typename S, int TW, int TH, int NT, int PART>
-__device__ __forceinline__ void sweep3_body(const LbmArgs &a, const TileMap &map) {
+// A workgroup owns a TW x TH tile.  Step j+1 runs on the tile grown by
+// G = K-1 rings, from HBM into LDS (as the two-step kernel's first half, with
+// wider rings); each next step runs on a region one ring narrower, from LDS,
+// its results held in registers across a barrier and written back over the
+// values they replace; step j+K runs on the owned nodes, from LDS, stored to
+// HBM.  Every node takes exactly the single step's operations, and values
+// pass through the storage format between steps, so the result equals K
+// single steps.  The state crosses HBM once per K fine steps; the first
+// stage does (TW+2G)(TH+2G) / ((TW+2)(TH+2)) of the two-step kernel's
+// first-half work (1.24 at K = 3, 1.48 at K = 4 for 64 x 8).
+
+// interface weight of stage s (1-based) of a multi-step launch
+__device__ __forceinline__ double stage_lam(const LbmArgs &a, int s) {
+    return s == 1 ? a.lam : s == 2 ? a.lam2 : s == 3 ? a.lam3 : a.lam4;
+}
+
+// Row and column of each round's node in a W-wide region of R nodes, NT
+// lanes per round, stepped without divisions.
+template <int W, int NT, int ROUNDS>
+__device__ __forceinline__ void region_coords(int (&rr)[ROUNDS], int (&cc)[ROUNDS]) {
+    rr[0] = threadIdx.x / W;
+    cc[0] = threadIdx.x - rr[0] * W;
+#pragma unroll
+    for (int k = 1; k < ROUNDS; ++k) {
+        rr[k] = rr[k - 1] + NT / W;
+        cc[k] = cc[k - 1] + NT % W;
+        if (cc[k] >= W) {
+            cc[k] -= W;
+            rr[k] += 1;
+        }
+    }
+}
+
+template <int TW, int TH, int NT, int RING>
+struct Region {
+    static constexpr int W = TW + 2 * RING, H = TH + 2 * RING, ROUNDS = (W * H + NT - 1) / NT;
+};
+
+// Flags and velocities of the nodes of the RING-ring region (solid flag for
+// rounds past the region or nodes off the patch).
+template <int TW, int TH, int NT, int RING>
+__device__ __forceinline__ void region_fields(int N, int P, int x0, int y0, const BufRsrc &mrs, const BufRsrc &vxr,
+                                              const BufRsrc &vyr, unsigned (&m)[Region<TW, TH, NT, RING>::ROUNDS],
+                                              float (&vx)[Region<TW, TH, NT, RING>::ROUNDS],
+                                              float (&vy)[Region<TW, TH, NT, RING>::ROUNDS],
+                                              int (&rr)[Region<TW, TH, NT, RING>::ROUNDS],
+                                              int (&cc)[Region<TW, TH, NT, RING>::ROUNDS]) {
+    typedef Region<TW, TH, NT, RING> R;
+    region_coords<R::W, NT, R::ROUNDS>(rr, cc);
+#pragma unroll
+    for (int k = 0; k < R::ROUNDS; ++k) {
+        const int i = x0 - RING + cc[k], j = y0 - RING + rr[k];
+        m[k] = kMaskSolid;
+        if (rr[k] < R::H && i >= 0 && j >= 0 && i < N && j < N) {
+            const unsigned n = static_cast<unsigned>(j * P + i);
+            m[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * n, 0, 0);
+            vx[k] = Buf<float>::load(vxr, 4u * n, 0);
+            vy[k] = Buf<float>::load(vyr, 4u * n, 0);
+        }
+    }
+}
+
+// Stages after the first: step j + G + 1 - RING on the RING-ring region from
+// LDS (LDS array of the G-ring region, W0 wide, planes PL apart).  RING > 0:
+// results to registers, the next region's fields fetched, barrier, results
+// written back in place, barrier, next stage.  RING = 0: the owned nodes,
+// stored to HBM.
+template <typename S, int TW, int TH, int NT, int G, int RING>
+__device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::T *L0, int x0, int y0,
+                                             const BufRsrc &fdst, const BufRsrc &mrs, const BufRsrc &vxr,
+                                             const BufRsrc &vyr,
+                                             const unsigned (&m)[Region<TW, TH, NT, RING>::ROUNDS],
+                                             const float (&vx)[Region<TW, TH, NT, RING>::ROUNDS],
+                                             const float (&vy)[Region<TW, TH, NT, RING>::ROUNDS],
+                                             const int (&rr)[Region<TW, TH, NT, RING>::ROUNDS],
+                                             const int (&cc)[Region<TW, TH, NT, RING>::ROUNDS]) {
     typedef typename Pop<S>::T T;
-    constexpr int W0 = TW + 4, H0 = TH + 4, R0 = W0 * H0;
-    constexpr int W1 = TW + 2, H1 = TH + 2, R1 = W1 * H1;
-    constexpr int ROUNDS0 = (R0 + NT - 1) / NT;
-    constexpr int ROUNDS1 = (R1 + NT - 1) / NT;
-    static_assert((TW * TH) % NT == 0 && NT % TW == 0, "third stage: whole rows per round");
-    constexpr int ROUNDS2 = TW * TH / NT;
-    constexpr int PL = H0 * W0;
+    typedef Region<TW, TH, NT, RING> R;
+    constexpr int W0 = TW + 2 * G, H0 = TH + 2 * G, PL = H0 * W0;
+    constexpr int OFF = G - RING;               // region origin in LDS coordinates
+    constexpr int STAGE = G + 1 - RING;
+    constexpr unsigned sz = sizeof(S);
+    const int N = a.N;
+    const int P = a.pitch;
+    const unsigned SP = static_cast<unsigned>(a.plane);
+    const T omega = T(a.omega);
+    const double lam = stage_lam(a, STAGE);
+    T h[R::ROUNDS][kQ];
+#pragma unroll
+    for (int k = 0; k < R::ROUNDS; ++k) {
+        if (m[k] & kMaskSolid) continue;
+        const int r = rr[k], c = cc[k];
+        const int i = x0 - RING + c, j = y0 - RING + r;
+        const unsigned n = static_cast<unsigned>(j * P + i);
+        const bool owned = r >= RING && r < RING + TH && c >= RING && c < RING + TW;
+        const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
+        // one LDS read per direction at a selected address (upstream value,
+        // or the node's own opposite value for a solid upstream node);
+        // closure unknowns are overwritten below
+        const T *base = L0 + (r + OFF) * W0 + (c + OFF);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int pull = q * PL - kCy[q] * W0 - kCx[q];
+            const int back = kOpp[q] * PL;
+            const int sel = -static_cast<int>((m[k] >> q) & 1u);
+            h[k][q] = base[pull + (sel & (back - pull))];
+        }
+        if (perim) {
+            const bool bad = dirichlet_close<T>(a, h[k], outside_bits(N, i, j), perimeter_slot(N, i, j), lam);
+            if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+        }
+        const T u = collide<T>(h[k], T(vx[k]), T(vy[k]), omega, node_k<T>(a, static_cast<int>(n)));
+        if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+        if constexpr (RING == 0) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(h[k][q], q, a), fdst, n * sz, q * SP * sz);
+        } else {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) h[k][q] = Pop<S>::ld(Pop<S>::st(h[k][q], q, a), q, a);
+        }
+    }
+    if constexpr (RING > 0) {
+        typedef Region<TW, TH, NT, RING - 1> R2;
+        unsigned m2[R2::ROUNDS];
+        float vx2[R2::ROUNDS], vy2[R2::ROUNDS];
+        int rr2[R2::ROUNDS], cc2[R2::ROUNDS];
+        region_fields<TW, TH, NT, RING - 1>(N, P, x0, y0, mrs, vxr, vyr, m2, vx2, vy2, rr2, cc2);
+        __syncthreads();             // every read of this stage's inputs is done
+#pragma unroll
+        for (int k = 0; k < R::ROUNDS; ++k) {
+            if (m[k] & kMaskSolid) continue;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) L0[q * PL + (rr[k] + OFF) * W0 + (cc[k] + OFF)] = h[k][q];
+        }
+        __syncthreads();
+        later_stages<S, TW, TH, NT, G, RING - 1>(a, L0, x0, y0, fdst, mrs, vxr, vyr, m2, vx2, vy2, rr2, cc2);
+    }
+}
+
+template <typename S, int TW, int TH, int NT, int PART, int K>
+__device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map) {
+    typedef typename Pop<S>::T T;
+    static_assert(K >= 3, "two-step launches use sweep2_body");
+    static_assert((TW * TH) % NT == 0 && NT % TW == 0, "last stage: whole rows per round");
+    constexpr int G = K - 1;
+    typedef Region<TW, TH, NT, G> R0;
+    constexpr int W0 = R0::W, H0 = R0::H, ROUNDS0 = R0::ROUNDS;
     constexpr unsigned sz = sizeof(S);
     __shared__ T lds[kQ][H0][W0];
-    T *const L0 = &lds[0][0][0];
 
     const int N = a.N;
     const int P = a.pitch;
@@ -771,41 +897,31 @@ __device__ __forceinline__ void sweep3_body(const LbmArgs &a, const TileMap &map
     const int x0 = tx * TW;
     const int y0 = ty * TH;
 
-    // ---- stage 1: step j+1 on the tile and two rings, HBM -> LDS --------
+    // ---- stage 1: step j+1 on the tile and G rings, HBM -> LDS ----------
     S raw[ROUNDS0][kQ];
     unsigned m[ROUNDS0];
     float vx1[ROUNDS0], vy1[ROUNDS0];
     int rr[ROUNDS0], cc[ROUNDS0];
-    rr[0] = threadIdx.x / W0;
-    cc[0] = threadIdx.x - rr[0] * W0;
-#pragma unroll
-    for (int k = 1; k < ROUNDS0; ++k) {
-        rr[k] = rr[k - 1] + NT / W0;
-        cc[k] = cc[k - 1] + NT % W0;
-        if (cc[k] >= W0) {
-            cc[k] -= W0;
-            rr[k] += 1;
-        }
-    }
+    region_coords<W0, NT, ROUNDS0>(rr, cc);
 #pragma unroll
     for (int k = 0; k < ROUNDS0; ++k) {
-        const int i = x0 - 2 + cc[k], j = y0 - 2 + rr[k];
+        const int i = x0 - G + cc[k], j = y0 - G + rr[k];
         m[k] = kMaskSolid;
         if (rr[k] < H0 && i >= 0 && j >= 0 && i < N && j < N)
             m[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * static_cast<unsigned>(j * P + i), 0, 0);
     }
-    unsigned K[kQ], D[kQ];
+    unsigned Kq[kQ], Dq[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         const unsigned pull = q * SP - static_cast<unsigned>(kCx[q] + kCy[q] * P);
         const unsigned own = kOpp[q] * SP;
-        K[q] = pull * sz;
-        D[q] = (own - pull) * sz;            // modulo 2^32; the sum below is exact
+        Kq[q] = pull * sz;
+        Dq[q] = (own - pull) * sz;           // modulo 2^32; the sum below is exact
     }
 #pragma unroll
     for (int k = 0; k < ROUNDS0; ++k) {
         if (m[k] & kMaskSolid) continue;
-        const int i = x0 - 2 + cc[k], j = y0 - 2 + rr[k];
+        const int i = x0 - G + cc[k], j = y0 - G + rr[k];
         const unsigned n = static_cast<unsigned>(j * P + i);
         vx1[k] = Buf<float>::load(vxr, 4u * n, 0);
         vy1[k] = Buf<float>::load(vyr, 4u * n, 0);
@@ -814,7 +930,7 @@ __device__ __forceinline__ void sweep3_body(const LbmArgs &a, const TileMap &map
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 const unsigned sel = 0u - ((m[k] >> q) & 1u);
-                raw[k][q] = Buf<S>::load(fsrc, nb + K[q] + (sel & D[q]), 0);
+                raw[k][q] = Buf<S>::load(fsrc, nb + Kq[q] + (sel & Dq[q]), 0);
             }
         } else {
             const int jm = j > 0 ? j - 1 : 0, jp = j < N - 1 ? j + 1 : N - 1;
@@ -833,9 +949,9 @@ __device__ __forceinline__ void sweep3_body(const LbmArgs &a, const TileMap &map
     for (int k = 0; k < ROUNDS0; ++k) {
         if (m[k] & kMaskSolid) continue;
         const int r = rr[k], c = cc[k];
-        const int i = x0 - 2 + c, j = y0 - 2 + r;
+        const int i = x0 - G + c, j = y0 - G + r;
         const unsigned n = static_cast<unsigned>(j * P + i);
-        const bool owned = r >= 2 && r < 2 + TH && c >= 2 && c < 2 + TW;
+        const bool owned = r >= G && r < G + TH && c >= G && c < G + TW;
         T f[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
@@ -853,121 +969,24 @@ __device__ __forceinline__ void sweep3_body(const LbmArgs &a, const TileMap &map
         for (int q = 0; q < kQ; ++q) lds[q][r][c] = Pop<S>::ld(Pop<S>::st(f[q], q, a), q, a);
     }
 
-    // flags and velocities of the one-ring region, fetched before the barrier
-    unsigned m1[ROUNDS1];
-    float vx2[ROUNDS1], vy2[ROUNDS1];
-    int r1[ROUNDS1], c1[ROUNDS1];
-    r1[0] = threadIdx.x / W1;
-    c1[0] = threadIdx.x - r1[0] * W1;
-#pragma unroll
-    for (int k = 1; k < ROUNDS1; ++k) {
-        r1[k] = r1[k - 1] + NT / W1;
-        c1[k] = c1[k - 1] + NT % W1;
-        if (c1[k] >= W1) {
-            c1[k] -= W1;
-            r1[k] += 1;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < ROUNDS1; ++k) {
-        const int i = x0 - 1 + c1[k], j = y0 - 1 + r1[k];
-        m1[k] = kMaskSolid;
-        if (r1[k] < H1 && i >= 0 && j >= 0 && i < N && j < N) {
-            const unsigned n = static_cast<unsigned>(j * P + i);
-            m1[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * n, 0, 0);
-            vx2[k] = Buf<float>::load(vxr, 4u * n, 0);
-            vy2[k] = Buf<float>::load(vyr, 4u * n, 0);
-        }
-    }
+    // the next region's flags and velocities, fetched before the barrier
+    typedef Region<TW, TH, NT, G - 1> R1;
+    unsigned m1[R1::ROUNDS];
+    float vx2[R1::ROUNDS], vy2[R1::ROUNDS];
+    int r1[R1::ROUNDS], c1[R1::ROUNDS];
+    region_fields<TW, TH, NT, G - 1>(N, P, x0, y0, mrs, vxr, vyr, m1, vx2, vy2, r1, c1);
     __syncthreads();
-
-    // ---- stage 2: step j+2 on the tile and one ring, LDS -> registers --
-    T h2[ROUNDS1][kQ];
-#pragma unroll
-    for (int k = 0; k < ROUNDS1; ++k) {
-        if (m1[k] & kMaskSolid) continue;
-        const int r = r1[k], c = c1[k];
-        const int i = x0 - 1 + c, j = y0 - 1 + r;
-        const unsigned n = static_cast<unsigned>(j * P + i);
-        const bool owned = r >= 1 && r <= TH && c >= 1 && c <= TW;
-        const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
-        // one LDS read per direction at a selected address (upstream value,
-        // or the node's own opposite value for a solid upstream node);
-        // closure unknowns are overwritten below
-        const T *base = L0 + (r + 1) * W0 + (c + 1);
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const int pull = q * PL - kCy[q] * W0 - kCx[q];
-            const int back = kOpp[q] * PL;
-            const int sel = -static_cast<int>((m1[k] >> q) & 1u);
-            h2[k][q] = base[pull + (sel & (back - pull))];
-        }
-        if (perim) {
-            const bool bad = dirichlet_close<T>(a, h2[k], outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam2);
-            if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
-        }
-        const T u = collide<T>(h2[k], T(vx2[k]), T(vy2[k]), omega, node_k<T>(a, static_cast<int>(n)));
-        if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) h2[k][q] = Pop<S>::ld(Pop<S>::st(h2[k][q], q, a), q, a);
-    }
-
-    // flags and velocities of the owned nodes, fetched before the barrier
-    unsigned m2[ROUNDS2];
-    float vx3[ROUNDS2], vy3[ROUNDS2];
-#pragma unroll
-    for (int k = 0; k < ROUNDS2; ++k) {
-        const int idx = threadIdx.x + NT * k;
-        const int i = x0 + idx % TW, j = y0 + idx / TW;
-        m2[k] = kMaskSolid;
-        if (i < N && j < N) {
-            const unsigned n = static_cast<unsigned>(j * P + i);
-            m2[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * n, 0, 0);
-            vx3[k] = Buf<float>::load(vxr, 4u * n, 0);
-            vy3[k] = Buf<float>::load(vyr, 4u * n, 0);
-        }
-    }
-    __syncthreads();                 // every stage-2 read of step j+1 values is done
-#pragma unroll
-    for (int k = 0; k < ROUNDS1; ++k) {
-        if (m1[k] & kMaskSolid) continue;
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) lds[q][r1[k] + 1][c1[k] + 1] = h2[k][q];
-    }
-    __syncthreads();
-
-    // ---- stage 3: step j+3 on the owned nodes, LDS -> HBM --------------
-#pragma unroll
-    for (int k = 0; k < ROUNDS2; ++k) {
-        if (m2[k] & kMaskSolid) continue;
-        const int idx = threadIdx.x + NT * k;
-        const int r = idx / TW, c = idx % TW;
-        const int i = x0 + c, j = y0 + r;
-        const unsigned n = static_cast<unsigned>(j * P + i);
-        const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
-        T g[kQ];
-        const T *base = L0 + (r + 2) * W0 + (c + 2);
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const int pull = q * PL - kCy[q] * W0 - kCx[q];
-            const int back = kOpp[q] * PL;
-            const int sel = -static_cast<int>((m2[k] >> q) & 1u);
-            g[q] = base[pull + (sel & (back - pull))];
-        }
-        if (perim) {
-            const bool bad = dirichlet_close<T>(a, g, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam3);
-            if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
-        }
-        const T u = collide<T>(g, T(vx3[k]), T(vy3[k]), omega, node_k<T>(a, static_cast<int>(n)));
-        if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(g[q], q, a), fdst, n * sz, q * SP * sz);
-    }
+    later_stages<S, TW, TH, NT, G, G - 1>(a, &lds[0][0][0], x0, y0, fdst, mrs, vxr, vyr, m1, vx2, vy2, r1, c1);
 }
 
 template <typename S, int TW, int TH, int NT, int PART>
 __global__ void __launch_bounds__(NT) lbm_sweep3_kernel(LbmArgs a, TileMap map) {
-    sweep3_body<S, TW, TH, NT, PART>(a, map);
+    sweepk_body<S, TW, TH, NT, PART, 3>(a, map);
+}
+
+template <typename S, int TW, int TH, int NT, int PART>
+__global__ void __launch_bounds__(NT) lbm_sweep4_kernel(LbmArgs a, TileMap map) {
+    sweepk_body<S, TW, TH, NT, PART, 4>(a, map);
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,18 +1144,19 @@ hipError_t step2_impl(const LbmArgs &a, int part, int depth, int ring, hipStream
 template <typename S> struct Tile3 { static constexpr int TW = 64, TH = 8, NT = 256; };
 template <> struct Tile3<double> { static constexpr int TW = 64, TH = 8, NT = 512; };
 
-template <typename S>
-hipError_t step3_impl(const LbmArgs &a, int part, int depth, hipStream_t s) {
+template <typename S, int K>
+hipError_t stepk_impl(const LbmArgs &a, int part, int depth, int ring, hipStream_t s) {
     constexpr int TW = Tile3<S>::TW, TH = Tile3<S>::TH, NT = Tile3<S>::NT;
     TileMap m{};
     m.tiles_x = (a.N + TW - 1) / TW;
     m.tiles_y = (a.N + TH - 1) / TH;
     m.part = part;
-    // depth-0 rectangle: tiles whose two-node ring (x0 - 2 .. x0 + TW + 1)
-    // lies within columns and rows 1 .. N-2; depth d shrinks it by d tiles
-    // on every side (a tile's ring lies within its neighbour tiles, which
-    // the previous launch's rectangle of depth d - 1 covers)
-    const int lx = a.N - 3 - TW, ly = a.N - 3 - TH;
+    // depth-0 rectangle: tiles whose ring of `ring` >= K-1 nodes lies within
+    // columns and rows 1 .. N-2; depth d shrinks it by d tiles on every side
+    // (a tile's ring lies within its neighbour tiles, which the previous
+    // launch's rectangle of depth d - 1 covers)
+    if (ring < K - 1) ring = K - 1;
+    const int lx = a.N - 1 - ring - TW, ly = a.N - 1 - ring - TH;
     const bool fits = lx >= TW && ly >= TH;
     m.ix0 = 1 + depth;
     m.iy0 = 1 + depth;
@@ -1152,23 +1172,36 @@ hipError_t step3_impl(const LbmArgs &a, int part, int depth, hipStream_t s) {
     m.count = m.part == 0 ? all : m.part == 1 ? inner : all - inner;
     if (m.count == 0) return hipSuccess;
     if (a.flux || a.kappa_s != 0.0 || a.mid) return hipErrorInvalidValue;
-    if (m.part == 0) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
-    else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
-    else hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);
+    if constexpr (K == 3) {
+        if (m.part == 0) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
+        else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
+        else hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);
+    } else {
+        if (m.part == 0) hipLaunchKernelGGL((lbm_sweep4_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
+        else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep4_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
+        else hipLaunchKernelGGL((lbm_sweep4_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);
+    }
     return hipGetLastError();
+}
+
+template <typename S>
+hipError_t stepk_dispatch(const LbmArgs &a, int K, int part, int depth, int ring, hipStream_t s) {
+    if (K == 3) return stepk_impl<S, 3>(a, part, depth, ring, s);
+    if (K == 4) return stepk_impl<S, 4>(a, part, depth, ring, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_lbm_step3(const LbmArgs &a, int prec, hipStream_t s, int part, int depth) {
-    if (prec == HYB_FP32) return step3_impl<float>(a, part, depth, s);
-    if (prec == HYB_FP16S) return step3_impl<_Float16>(a, part, depth, s);
-    if (prec == HYB_FP64) return step3_impl<double>(a, part, depth, s);
+hipError_t launch_lbm_stepk(const LbmArgs &a, int prec, int K, hipStream_t s, int part, int depth, int ring) {
+    if (prec == HYB_FP32) return stepk_dispatch<float>(a, K, part, depth, ring, s);
+    if (prec == HYB_FP16S) return stepk_dispatch<_Float16>(a, K, part, depth, ring, s);
+    if (prec == HYB_FP64) return stepk_dispatch<double>(a, K, part, depth, ring, s);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part, int depth, int ring) {
-    if (ring != 1 && ring != 2) return hipErrorInvalidValue;
+    if (ring < 1 || ring > 3) return hipErrorInvalidValue;
     if (prec == HYB_FP64) return step2_impl<double>(a, part, depth, ring, s);
     if (prec == HYB_FP32) return step2_impl<float>(a, part, depth, ring, s);
     return step2_impl<_Float16>(a, part, depth, ring, s);

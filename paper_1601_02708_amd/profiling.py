@@ -3,7 +3,7 @@ kept under profiles/ (run on the host after the GPU job).
 
     python -m paper_1601_02708_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
     python -m paper_1601_02708_amd.profiling traffic <fetch_counter_collection.csv> \
-        <write_counter_collection.csv> <out.json> <workload> <precision> <copy_mib> "<commands>"
+        <write_counter_collection.csv> <out.json> <workload> <precision> <copy_mib> "<commands>" [kernel]
 
 The traffic record scales the FETCH_SIZE / WRITE_SIZE counters of the
 lattice-sweep kernel by what the same counters read for the plain copy
@@ -46,14 +46,14 @@ def _per_kernel(path, counter):
     return out
 
 
-def traffic(fetch_csv, write_csv, out_path, workload, precision, copy_mib, commands):
+def traffic(fetch_csv, write_csv, out_path, workload, precision, copy_mib, commands, kernel="lbm_sweep3_kernel"):
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
     tname = {"fp32": "float", "fp64": "double", "fp16s": "_Float16"}[precision]
-    # the dominant sweep kernel: the whole-patch three-step launch (tile
-    # part 0) when it ran, else the whole-patch two-step launch, else the
-    # single-step one
-    sweep = [k for k in fetch if "lbm_sweep3_kernel" in k and f"<{tname}" in k and ", 0>" in k]
+    # the dominant sweep kernel: the whole-patch launch (tile part 0) of
+    # `kernel` (the bench's dominant kind) when it ran, else the whole-patch
+    # two-step launch, else the single-step one
+    sweep = [k for k in fetch if f"{kernel}<" in k and f"<{tname}" in k and ", 0>" in k]
     sweep = sweep or [k for k in fetch if "lbm_sweep2_kernel" in k and f"<{tname}" in k and ", 0>" in k]
     sweep = sweep or [k for k in fetch if "lbm_sweep_kernel" in k and f"<{tname}" in k]
     if not sweep:
@@ -84,4 +84,4 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:9])
+        traffic(*sys.argv[2:10])

@@ -168,11 +168,13 @@ def test_two_step_sweep(orc, precision, N, clamp, k_field, eta):
                                                   (4, 0, True, 6), (200, 0, False, 7), (65, 1, False, 10),
                                                   (131, 0, True, 8)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_three_step_sweep(orc, precision, N, clamp, k_field, eta):
-    """Fine steps taken three per launch (hyb_set_steps_per_launch(3);
-    the pass's plan: eta = 5 -> 3 + 2, 9 -> 3 + 3 + 3, 3 -> 3, 6 -> 3 + 3,
-    7 -> 3 + 2 + 2, 10 -> 3 + 3 + 2 + 2, 8 -> 3 + 3 + 2) against the oracle and
-    against the single-step sweep: random states, solids, every perimeter
+@pytest.mark.parametrize("spl", [3, 4])
+def test_three_step_sweep(orc, spl, precision, N, clamp, k_field, eta):
+    """Fine steps taken three or four per launch (hyb_set_steps_per_launch;
+    the pass's plan with 3: eta = 5 -> 3 + 2, 9 -> 3 + 3 + 3, 3 -> 3,
+    6 -> 3 + 3, 7 -> 3 + 2 + 2, 10 -> 3 + 3 + 2 + 2, 8 -> 3 + 3 + 2; with 4:
+    5 -> 3 + 2, 9 -> 4 + 3 + 2, 3 -> 3, 6 -> 3 + 3, 7 -> 4 + 3, 10 -> 4 + 3 + 3,
+    8 -> 4 + 4) against the oracle and against the single-step sweep: random states, solids, every perimeter
     slot Dirichlet with interface values that make some closures infeasible
     (counted once per owned node, as by single steps), ragged tiles and
     lattices smaller than one tile."""
@@ -195,21 +197,21 @@ def test_three_step_sweep(orc, precision, N, clamp, k_field, eta):
         bad += nb
     assert bad > 0
     got = {}
-    for spl in (1, 3):
+    for s in (1, spl):
         g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta,
                        precision=precision, tau=tau, solid=solid, k=0.0 if k_field else 1e-3, k_field=kf,
                        bc_clamp=clamp)
-        g.set_steps_per_launch(spl)
+        g.set_steps_per_launch(s)
         g.set_populations(f0)
         g.set_boundary(a, b)
         g.lbm_substeps(eta, restart=1)
         g.commit()
-        got[spl] = g.get_populations()
-        assert g.stats()["infeasible"] == bad, spl
-        err = np.abs(got[spl] - f).max() / np.abs(f).max()
-        assert err <= (1e-13 if precision == "fp64" else 2e-6), (spl, err)
+        got[s] = g.get_populations()
+        assert g.stats()["infeasible"] == bad, s
+        err = np.abs(got[s] - f).max() / np.abs(f).max()
+        assert err <= (1e-13 if precision == "fp64" else 2e-6), (s, err)
         g.close()
-    d = np.abs(got[3] - got[1]).max() / np.abs(got[1]).max()
+    d = np.abs(got[spl] - got[1]).max() / np.abs(got[1]).max()
     assert d <= (1e-14 if precision == "fp64" else 1e-6), d
 
 
@@ -239,10 +241,13 @@ def test_three_step_fp16s_matches_single_steps():
     assert d <= 4e-3, d
 
 
-@pytest.mark.parametrize("over,steps,depths", [({"N": 600, "M": 32}, 3, (1, 2, 3, 4)),
-                                               ({"N": 1026, "M": 32}, 2, (1, 2, 4)),
-                                               ({"N": 257, "M": 32, "eta": 7}, 3, (1, 2, 3))])
-def test_three_step_overlapped_step_is_bit_identical(over, steps, depths):
+@pytest.mark.parametrize("spl,over,steps,depths", [(3, {"N": 600, "M": 32}, 3, (1, 2, 3, 4)),
+                                                   (3, {"N": 1026, "M": 32}, 2, (1, 2, 4)),
+                                                   (3, {"N": 257, "M": 32, "eta": 7}, 3, (1, 2, 3)),
+                                                   (4, {"N": 600, "M": 32}, 3, (1, 2, 3)),
+                                                   (4, {"N": 1027, "M": 32}, 2, (1, 3)),
+                                                   (4, {"N": 600, "M": 32, "eta": 9}, 2, (1, 2, 3))])
+def test_three_step_overlapped_step_is_bit_identical(spl, over, steps, depths):
     """hyb_step with three-step launches (plan 3 + 3 + 2 + 2 at eta = 10,
     3 + 2 + 2 at eta = 7) and the deep tiles of the first launches on the
     side stream equals the serial order bit for bit at every depth; the
@@ -255,7 +260,7 @@ def test_three_step_overlapped_step_is_bit_identical(over, steps, depths):
     out = []
     for ov in (0,) + tuple(depths):
         g = hyb.Hybrid.from_problem(p, precision="fp32")
-        g.set_steps_per_launch(3)
+        g.set_steps_per_launch(spl)
         g.set_overlap(ov)
         for _ in range(steps):
             g.step(p.cfg.max_iter)
@@ -335,7 +340,7 @@ def test_overlap_rejects_negative_depth():
         g.set_overlap(-2)
 
 
-@pytest.mark.parametrize("spl,D", [(2, 5), (3, 4)])
+@pytest.mark.parametrize("spl,D", [(2, 5), (3, 4), (4, 3)])
 def test_overlap_auto_tunes_then_keeps_a_depth(spl, D):
     """HYB_OVERLAP_AUTO (the default): one serial step, then three rounds
     over depths 0 .. D (D = the pass's multi-step launches at eta = 10:
@@ -364,7 +369,7 @@ def test_steps_per_launch_rejects_other_values():
     N = 8
     z = np.zeros((N, N))
     g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.1, eta=2)
-    for bad in (0, 4, -1):
+    for bad in (0, 5, -1):
         with pytest.raises(hyb.HybError):
             g.set_steps_per_launch(bad)
 
