@@ -218,7 +218,8 @@ def adjoint_rate(problem, precision, reps=3):
             rec_ms += ev[0].elapsed_time(ev[1])
             adj_ms += ev[1].elapsed_time(ev[2])
     lups = eta * N * N * reps
-    # algorithmic bytes of one reversed fine step (adj_step_kernel): per
+    # algorithmic bytes of one reversed fine step (reversed in pairs, two
+    # per launch of adj_step2_kernel, the cotangent between them on chip): per
     # fluid node the cotangent read, the next state read (for dJ/dk), the
     # result written (9 values each), flags, velocity and the FP64 dJ/dk
     # read-modify-write; per solid node its flags and the zeros written
@@ -229,7 +230,8 @@ def adjoint_rate(problem, precision, reps=3):
     out = {"precision": precision, "value": round(lups / (adj_ms / 1e3) / 1e6, 1), "unit": "MLUPS",
            "ms_per_fine_step": round(step_ms, 4),
            "record_forward_mlups": round(lups / (rec_ms / 1e3) / 1e6, 1),
-           "roofline": {"kernel": f"adj_step_kernel<{'double' if s == 8 else 'float'}, 64, 8, 256>", "bound": "hbm",
+           "roofline": {"kernel": f"adj_step2_kernel<{'double' if s == 8 else 'float'}, 64, 8, 256> (two reversed "
+                                  "steps per launch)", "bound": "hbm",
                         "algorithmic_bytes_per_step": int(step_bytes),
                         "achieved": round(step_bytes / (step_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(step_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -31,13 +31,14 @@ __device__ __forceinline__ int slot_of(int N, int i, int j) {
     return 3 * N - 2 + j - 1;
 }
 
-// nu at node (i, j) (collision and closure transposed); gradients of the
-// closure and the reaction rate are accumulated when `owner` (every node has
-// exactly one owner tile, ring copies recompute nu only).
+// nu at node (i, j) (collision and closure transposed) from the node's
+// cotangent l = dJ/df*(t+1); gradients of the closure and the reaction rate
+// are accumulated when `owner` (every node has exactly one owner tile, ring
+// copies recompute nu only).
 template <typename T>
-__device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
-                                       const T *__restrict__ lam, bool owner, double *__restrict__ grad_a,
-                                       double *__restrict__ grad_b, double *__restrict__ grad_k, T (&nu)[kQ]) {
+__device__ __forceinline__ void adj_nu_of(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
+                                          const T (&l)[kQ], bool owner, double *__restrict__ grad_a,
+                                          double *__restrict__ grad_b, double *__restrict__ grad_k, T (&nu)[kQ]) {
     const int N = a.N, P = a.pitch;
     const int plane = static_cast<int>(a.plane);
     const int n = j * P + i;
@@ -51,11 +52,9 @@ __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *
     const T k = a.kfield ? static_cast<const T *>(a.kfield)[n] : T(a.k);
     const T omega = T(a.omega);
     const T vv = T(1.5) * (vx * vx + vy * vy);
-    T l[kQ];
     T S = T(0), wl = T(0);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-        l[q] = lam[q * plane + n];
         const T ev = T(kCx[q]) * vx + T(kCy[q]) * vy;
         const T Pq = T(1) + T(3) * ev + T(4.5) * ev * ev - vv;
         S += l[q] * T(kW[q]) * (omega * Pq - k);
@@ -116,6 +115,24 @@ __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *
     }
 }
 
+// nu at node (i, j) with the node's cotangent read from lam
+template <typename T>
+__device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
+                                       const T *__restrict__ lam, bool owner, double *__restrict__ grad_a,
+                                       double *__restrict__ grad_b, double *__restrict__ grad_k, T (&nu)[kQ]) {
+    const int plane = static_cast<int>(a.plane);
+    const int n = j * a.pitch + i;
+    T l[kQ];
+    if (a.mask[n] & kMaskSolid) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) nu[q] = T(0);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) l[q] = lam[q * plane + n];
+    adj_nu_of<T>(a, i, j, snext, l, owner, grad_a, grad_b, grad_k, nu);
+}
+
 // One reversed fine step.  Phase 1: nu for the tile grown by one ring (0
 // outside the patch and at solid nodes), into LDS.  Phase 2, per owned
 // fluid node y: dJ/df*_p(y) = nu_p(y + e_p) (zero when y + e_p is solid or
@@ -170,6 +187,103 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
     }
 }
 
+// Two reversed fine steps in one launch: step t (a1: its source state and
+// interface weight; snext1 = f*(t+1)) and then step t-1 (a2; snext2 =
+// f*(t)), from lam = dJ/df*(t+1) to out = dJ/df*(t-1).  Phase 1: nu of step
+// t for the tile grown by two rings, into LDS.  Phase 2: dJ/df*(t) gathered
+// for the tile grown by one ring (as one reversed step's output), and from
+// it nu of step t-1, held in registers across a barrier and written back in
+// place.  Phase 3: the owned nodes gather their outputs.  Every node takes
+// the single reversed step's operations (dJ/df*(t) never leaves the chip),
+// so the result equals two adj_step_kernel launches; gradients are added by
+// the owner of each node once per step, the two steps separated by a
+// barrier.
+template <typename T, int TW, int TH, int NT>
+__global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, const T *__restrict__ snext1,
+                                                       const T *__restrict__ snext2, const T *__restrict__ lam,
+                                                       T *__restrict__ out, double *__restrict__ grad_a,
+                                                       double *__restrict__ grad_b, double *__restrict__ grad_k,
+                                                       int tiles_x) {
+    constexpr int W2 = TW + 4, H2 = TH + 4, W1 = TW + 2, H1 = TH + 2;
+    constexpr int R1 = (W1 * H1 + NT - 1) / NT;
+    __shared__ T nus[kQ][H2][W2];
+    const int N = a1.N, P = a1.pitch;
+    const int plane = static_cast<int>(a1.plane);
+    const int x0 = (blockIdx.x % tiles_x) * TW, y0 = (blockIdx.x / tiles_x) * TH;
+    // ---- phase 1: nu of step t, two rings ---------------------------------
+    for (int r = threadIdx.x; r < W2 * H2; r += NT) {
+        const int lx = r % W2, ly = r / W2;
+        const int i = x0 - 2 + lx, j = y0 - 2 + ly;
+        T nu[kQ];
+        if (i < 0 || j < 0 || i >= N || j >= N) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) nu[q] = T(0);
+        } else {
+            const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
+            adj_nu<T>(a1, i, j, snext1, lam, owner, grad_a, grad_b, grad_k, nu);
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = nu[q];
+    }
+    __syncthreads();
+    // ---- phase 2: dJ/df*(t) on one ring, then nu of step t-1 --------------
+    const T keep = T(1.0 - a1.kappa_s);
+    T h[R1][kQ];
+#pragma unroll
+    for (int k = 0; k < R1; ++k) {
+        const int r = threadIdx.x + NT * k;
+        const int lx = 1 + r % W1, ly = 1 + r / W1;      // ring-2 coordinates of the one-ring node
+        const int i = x0 - 2 + lx, j = y0 - 2 + ly;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) h[k][q] = T(0);
+        if (r >= W1 * H1 || i < 0 || j < 0 || i >= N || j >= N) continue;
+        const int n = j * P + i;
+        const unsigned m = a1.mask[n];
+        if (m & kMaskSolid) continue;
+        T l[kQ];
+#pragma unroll
+        for (int p = 0; p < kQ; ++p) {
+            T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
+            const int q = kOpp[p];
+            if ((m >> q) & 1u) acc += keep * nus[q][ly][lx];
+            l[p] = acc;
+        }
+        const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
+        adj_nu_of<T>(a2, i, j, snext2, l, owner, grad_a, grad_b, grad_k, h[k]);
+    }
+    __syncthreads();             // every read of step t's nu is done
+#pragma unroll
+    for (int k = 0; k < R1; ++k) {
+        const int r = threadIdx.x + NT * k;
+        if (r >= W1 * H1) continue;
+        const int lx = 1 + r % W1, ly = 1 + r / W1;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = h[k][q];
+    }
+    __syncthreads();
+    // ---- phase 3: the owned nodes' dJ/df*(t-1) -----------------------------
+    const T keep2 = T(1.0 - a2.kappa_s);
+    for (int r = threadIdx.x; r < TW * TH; r += NT) {
+        const int lx = 2 + r % TW, ly = 2 + r / TW;
+        const int i = x0 + lx - 2, j = y0 + ly - 2;
+        if (i >= N || j >= N) continue;
+        const int n = j * P + i;
+        const unsigned m = a2.mask[n];
+        if (m & kMaskSolid) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+            continue;
+        }
+#pragma unroll
+        for (int p = 0; p < kQ; ++p) {
+            T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
+            const int q = kOpp[p];
+            if ((m >> q) & 1u) acc += keep2 * nus[q][ly][lx];
+            out[p * plane + n] = acc;
+        }
+    }
+}
+
 // dense FP64 [9][N][N] <-> pitched planes of T
 template <typename T>
 __global__ void __launch_bounds__(256) adj_pack_kernel(LbmArgs a, const double *__restrict__ dense, T *__restrict__ pitched,
@@ -210,7 +324,26 @@ hipError_t adjoint_step_impl(const LbmArgs &a, const void *snext, const void *la
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t adjoint_step2_impl(const LbmArgs &a1, const LbmArgs &a2, const void *snext1, const void *snext2,
+                              const void *lam, void *out, double *grad_a, double *grad_b, double *grad_k,
+                              hipStream_t s) {
+    constexpr int TW = 64, TH = 8, NT = 256;
+    const int tiles_x = (a1.N + TW - 1) / TW, tiles_y = (a1.N + TH - 1) / TH;
+    hipLaunchKernelGGL((adj_step2_kernel<T, TW, TH, NT>), dim3(tiles_x * tiles_y), dim3(NT), 0, s, a1, a2,
+                       static_cast<const T *>(snext1), static_cast<const T *>(snext2), static_cast<const T *>(lam),
+                       static_cast<T *>(out), grad_a, grad_b, grad_k, tiles_x);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_adjoint_step2(const LbmArgs &a1, const LbmArgs &a2, int prec, const void *snext1,
+                                const void *snext2, const void *lam, void *out, double *grad_a, double *grad_b,
+                                double *grad_k, hipStream_t s) {
+    if (prec == HYB_FP64) return adjoint_step2_impl<double>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, s);
+    return adjoint_step2_impl<float>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, s);
+}
 
 hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
                                double *grad_a, double *grad_b, double *grad_k, hipStream_t s) {

@@ -1235,10 +1235,26 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
     void *lcur = slot(n_sub + 1), *nu = slot(n_sub + 2), *lnext = slot(n_sub + 3);
     LbmArgs a = h->lbm_args(h->frozen, -1);
     HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_in, lcur, true, h->stream));
-    for (int t = n_sub - 1; t >= 0; --t) {
-        a.src = slot(t);
-        a.lam = (double)(t + 1) / (double)h->eta;
-        HIP_TRY(h, launch_adjoint_step(a, h->prec, slot(t + 1), lcur, nu, lnext, grad_a, grad_b, grad_k, h->stream));
+    // reversed steps in pairs (one launch each) unless single-step launches
+    // were asked for (hyb_set_steps_per_launch(1))
+    const bool pairs = h->steps_per_launch >= 2;
+    for (int t = n_sub - 1; t >= 0;) {
+        if (pairs && t >= 1) {
+            LbmArgs a1 = a, a2 = a;
+            a1.src = slot(t);
+            a1.lam = (double)(t + 1) / (double)h->eta;
+            a2.src = slot(t - 1);
+            a2.lam = (double)t / (double)h->eta;
+            HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, slot(t + 1), slot(t), lcur, lnext, grad_a, grad_b,
+                                            grad_k, h->stream));
+            t -= 2;
+        } else {
+            a.src = slot(t);
+            a.lam = (double)(t + 1) / (double)h->eta;
+            HIP_TRY(h, launch_adjoint_step(a, h->prec, slot(t + 1), lcur, nu, lnext, grad_a, grad_b, grad_k,
+                                           h->stream));
+            t -= 1;
+        }
         std::swap(lcur, lnext);
     }
     HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_out, lcur, false, h->stream));
@@ -1417,10 +1433,23 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
         HIP_TRY(h, hipMemsetAsync(ga, 0, 2 * nslots * 8, h->stream));
         a.bc_a = bc;
         a.bc_b = bc + (1 + p) * nslots;
-        for (int t = h->eta; t >= 1; --t) {
-            a.src = state(p, t - 1);
-            a.lam = (double)t / (double)h->eta;
-            HIP_TRY(h, launch_adjoint_step(a, h->prec, state(p, t), lcur, nu, lnext, ga, gb, grad_k, h->stream));
+        for (int t = h->eta; t >= 1;) {
+            if (h->steps_per_launch >= 2 && t >= 2) {
+                // steps t and t-1 reversed in one launch
+                LbmArgs a1 = a, a2 = a;
+                a1.src = state(p, t - 1);
+                a1.lam = (double)t / (double)h->eta;
+                a2.src = state(p, t - 2);
+                a2.lam = (double)(t - 1) / (double)h->eta;
+                HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, state(p, t), state(p, t - 1), lcur, lnext, ga, gb,
+                                                grad_k, h->stream));
+                t -= 2;
+            } else {
+                a.src = state(p, t - 1);
+                a.lam = (double)t / (double)h->eta;
+                HIP_TRY(h, launch_adjoint_step(a, h->prec, state(p, t), lcur, nu, lnext, ga, gb, grad_k, h->stream));
+                t -= 1;
+            }
             std::swap(lcur, lnext);
         }
         HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_f_out, lcur, false, h->stream, true));

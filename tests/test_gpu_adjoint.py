@@ -176,3 +176,45 @@ def test_adjoint_rejects_unsupported():
         g.adjoint(3, tape, lam, lam, ga, ga.clone())              # n_sub differs from the record
     with pytest.raises(hyb.HybError):
         g.substeps_record(4, g.adjoint_tape(4))                   # past eta
+
+
+@pytest.mark.parametrize("precision,N,clamp,eta", [("fp64", 130, 1, 7), ("fp32", 97, 0, 6), ("fp64", 4, 0, 5)])
+def test_paired_reversed_steps_equal_single_steps(precision, N, clamp, eta):
+    """hyb_lbm_adjoint with reversed steps in pairs (one launch for two
+    steps, dJ/df* between them kept on chip; the default) against one launch
+    per reversed step (hyb_set_steps_per_launch(1)): cotangents and every
+    gradient agree to rounding (same operations per node), odd step counts
+    ending with a single reversed step."""
+    hyb, torch = _gpu()
+    rng, solid, vx, vy, kf, tau = _case(N, 70 + N, k_field=True)
+    P = 4 * (N - 1)
+    a = rng.uniform(0.1, 0.6, P)
+    b = rng.uniform(0.1, 0.6, P)
+    f0 = inputs.random_populations(N, 19 + N, lo=0.01, hi=0.1)
+    f0[:, solid != 0] = 0.0
+    c = rng.standard_normal((9, N, N))
+    c[:, solid != 0] = 0.0
+    res = {}
+    for spl in (1, 4):
+        g = hyb.Hybrid(N=N, x0=0, y0=0, u0=np.zeros((N, N)), vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta,
+                       precision=precision, tau=tau, solid=solid, k_field=kf, bc_clamp=clamp)
+        g.set_steps_per_launch(spl)
+        g.set_populations(f0)
+        g.set_boundary(a, b)
+        tape = g.adjoint_tape(eta)
+        g.substeps_record(eta, tape)
+        dev = g.dev
+        lam = torch.from_numpy(c).to(dev)
+        lam_out = torch.empty_like(lam)
+        ga = torch.zeros(P, dtype=torch.float64, device=dev)
+        gb = torch.zeros_like(ga)
+        gk = torch.zeros((N, N), dtype=torch.float64, device=dev)
+        g.adjoint(eta, tape, lam, lam_out, ga, gb, gk)
+        torch.cuda.synchronize()
+        res[spl] = [x.cpu().numpy() for x in (lam_out, ga, gb, gk)]
+        g.close()
+    tol = 1e-14 if precision == "fp64" else 1e-6
+    errs = [_rel(x, y) for x, y in zip(res[4], res[1])]
+    same = all(np.array_equal(x, y) for x, y in zip(res[4], res[1]))
+    print(f"\npaired vs single reversed steps {precision} N={N}: {errs}, bitwise {same}")
+    assert max(errs) <= tol, errs

@@ -225,3 +225,23 @@ def test_rollout_autograd_by_central_differences():
         fd = float(((w * (Fp - Fm)).sum() + (v * (dp - dm)).sum()) / 2)
     an = float((F0.grad * dF).sum() + (d0.grad * dd).sum())
     assert abs(fd - an) <= 1e-9 * max(1.0, abs(an)), (fd, an)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-6)])
+def test_step_adjoint_paired_reversed_steps(precision, tol):
+    """The whole-step adjoint with its fine steps reversed in pairs (the
+    default) against one reversed step per launch: same cotangents and
+    gradients to rounding (eta = 5: two pairs and a single step per pass)."""
+    hyb, torch = _gpu()
+    p = _problem("pore2048", N=97, M=16, eta=5)
+    N, M = p.cfg.N, p.cfg.M
+    lam_f, lam_d = _cotangents(p, N, M, 71)
+    out = {}
+    for spl in (1, 4):
+        g = hyb.Hybrid.from_problem(p, precision=precision)
+        g.set_steps_per_launch(spl)
+        out[spl] = _gpu_adjoint(hyb, torch, g, p, p.cfg.max_iter, lam_f, lam_d)
+        g.close()
+    errs = [_rel(x, y) for x, y in zip(out[4], out[1])]
+    print(f"\nstep adjoint paired vs single {precision}: {errs}")
+    assert max(errs) <= tol, errs
