@@ -380,12 +380,14 @@ class Hybrid:
                                                   None if grad_k is None else grad_k.data_ptr()))
 
     def set_overlap(self, depth):
-        """Deep interior tiles of the first `depth` two-step launches of each
+        """Deep interior tiles of the first `depth` multi-step launches of each
         Schwarz pass overlap the pass's coarse work (0: serial order;
         HYB_OVERLAP_AUTO: the next steps tune the depth)."""
         return self._check(load().hyb_set_overlap(self.h, int(depth)))
 
     def set_steps_per_launch(self, steps):
+        """Most fine steps per sweep launch, 1 to 4 (default 4, 2 for fp16s);
+        2 or more also reverses the adjoint's fine steps in pairs."""
         return self._check(load().hyb_set_steps_per_launch(self.h, int(steps)))
 
     def kernel_timing(self, enable=True):
