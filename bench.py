@@ -81,7 +81,7 @@ def sweep_kernel(elem_bytes, take):
     """Symbol of the whole-patch launch (tile part 0) of the sweep that
     takes `take` fine steps per launch."""
     t = {8: "double", 4: "float", 2: "_Float16"}[elem_bytes]
-    nt = 512 if elem_bytes == 8 else 256
+    nt = 512 if elem_bytes == 8 or take >= 3 else 256
     if take >= 2:
         return f"lbm_sweep{take}_kernel<{t}, 64, 8, {nt}, 0>"
     return f"lbm_sweep_kernel<{t}>"

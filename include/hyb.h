@@ -315,8 +315,9 @@ int hyb_set_overlap(hyb_handle *h, int depth);
  * every step when some slot is Neumann, or when a population buffer reaches
  * 4 GiB (the multi-step kernels use 32-bit byte offsets), uses the
  * single-step sweep.  Results agree with the single-step path to rounding
- * (same operations per node; multi-step launches give the same bits as
- * pairs).  With 2 or more, hyb_lbm_adjoint and hyb_step_adjoint also reverse
+ * (same operations per node; pairs give its bits, and three- and four-step
+ * launches FP64 states identical to pairs' and FP32 ones within a few ulp,
+ * from the compiler's fusing of multiply-adds).  With 2 or more, hyb_lbm_adjoint and hyb_step_adjoint also reverse
  * fine steps in pairs, one launch each (same bits as single reversed
  * steps).  Returns HYB_EINVAL for other values.  Takes effect at the next
  * hyb_lbm_substeps or adjoint call and restarts the overlap tuning of

@@ -737,9 +737,11 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_rec_kernel(LbmArgs a, TileMap m
 // wider rings); each next step runs on a region one ring narrower, from LDS,
 // its results held in registers across a barrier and written back over the
 // values they replace; step j+K runs on the owned nodes, from LDS, stored to
-// HBM.  Every node takes exactly the single step's operations, and values
-// pass through the storage format between steps, so the result equals K
-// single steps.  The state crosses HBM once per K fine steps; the first
+// HBM.  Every node takes the single step's operations, and values pass
+// through the storage format between steps, so the result equals K single
+// steps up to how the compiler fuses multiply-adds in each kernel (FP64
+// states measured identical to the two-step launches', FP32 ones within a
+// few ulp).  The state crosses HBM once per K fine steps; the first
 // stage does (TW+2G)(TH+2G) / ((TW+2)(TH+2)) of the two-step kernel's
 // first-half work (1.24 at K = 3, 1.48 at K = 4 for 64 x 8).
 
@@ -1136,13 +1138,14 @@ hipError_t step2_impl(const LbmArgs &a, int part, int depth, int ring, hipStream
     return hipGetLastError();
 }
 
-// Tile of the three-step sweep: LDS holds 9 planes of (TW+4) x (TH+4)
-// values of the arithmetic type, 29.4 KB at 64 x 8 in FP32 (256 lanes, five
-// workgroups per CU), 58.8 KB in FP64 (512 lanes, two workgroups per CU;
-// measured 4.6% less sweep time per pass than the two-step launches, whose
-// tile leaves three).
-template <typename S> struct Tile3 { static constexpr int TW = 64, TH = 8, NT = 256; };
-template <> struct Tile3<double> { static constexpr int TW = 64, TH = 8, NT = 512; };
+// Tile of the multi-step sweeps (K = 3, 4): 64 x 8 owned nodes, 512 lanes
+// (one owned node per lane in the last stage); LDS holds 9 planes of
+// (TW+2K-2) x (TH+2K-2) values of the arithmetic type: 29.4 / 35.3 KB in
+// FP32, 58.8 / 70.6 KB in FP64.  Measured at pore2048 FP32 (4 + 3 + 3 per
+// pass): 0.783 ms per coarse step against 0.832 with 256 lanes; 64 x 16
+// with 512 lanes 0.808, 64 x 12 with 384 lanes 0.854.  In FP64, 512 lanes
+// cut the sweep time per pass by 4.6% against the two-step launches.
+template <typename S> struct Tile3 { static constexpr int TW = 64, TH = 8, NT = 512; };
 
 template <typename S, int K>
 hipError_t stepk_impl(const LbmArgs &a, int part, int depth, int ring, hipStream_t s) {
