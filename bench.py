@@ -64,17 +64,19 @@ def launch_plan(eta, steps_per_launch):
             t = 2
         elif steps_per_launch == 3:
             t = 2 if rem == 4 else 3
-        else:
+        elif steps_per_launch == 4:
             t = 3 if rem in (3, 5, 6) else 4
+        else:
+            t = 3 if rem == 6 else 4 if rem in (7, 8) else min(rem, 5)
         out.append(t)
         rem -= t
     return out
 
 
 def default_steps_per_launch(precision):
-    """The library's default (hyb_set_steps_per_launch): 2 for FP16 shifted
-    storage, 4 otherwise."""
-    return 2 if precision == "fp16s" else 4
+    """The library's default (hyb_set_steps_per_launch): 5 for FP32, 4 for
+    FP64, 2 for FP16 shifted storage."""
+    return {"fp32": 5, "fp64": 4, "fp16s": 2}[precision]
 
 
 def sweep_kernel(elem_bytes, take):
@@ -565,9 +567,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pore2048")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16s"])
-    ap.add_argument("--steps-per-launch", type=int, default=None, choices=[1, 2, 3, 4],
-                    help="most fine steps per lattice-sweep launch (temporal blocking; eta = 10 runs 4 + 3 + 3 "
-                         "at 4); default: the library's (4, or 2 for fp16s)")
+    ap.add_argument("--steps-per-launch", type=int, default=None, choices=[1, 2, 3, 4, 5],
+                    help="most fine steps per lattice-sweep launch (temporal blocking; eta = 10 runs 5 + 5 at 5, "
+                         "4 + 3 + 3 at 4); default: the library's (5 fp32, 4 fp64, 2 fp16s)")
     ap.add_argument("--overlap", type=int, default=-1,
                     help="overlap depth of hyb_step (-1: the library's tuning, on a separate handle)")
     ap.add_argument("--timing-steps", type=int, default=10,

@@ -294,7 +294,8 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
  * passes with K-step launches) stays clear of the patch perimeter, shrunk by j tiles on every side: such tiles read no interface
  * value and, with their halo, only the deep tiles of launch j-1.  Depth is
  * capped at D, the pass's number of leading multi-step launches (eta / 2
- * with pairs; at eta = 10, 4 with 3 + 3 + 2 + 2 and 3 with 4 + 3 + 3).  Results are bit-identical to the serial order for every depth.
+ * with pairs; at eta = 10, 4 with 3 + 3 + 2 + 2, 3 with 4 + 3 + 3 and 2 with
+ * 5 + 5).  Results are bit-identical to the serial order for every depth.
  * depth = 0 runs everything on the caller's stream.  HYB_OVERLAP_AUTO: of
  * the handle's next 1 + 3 (D + 1) successful hyb_step calls, the first runs
  * serially and the others at depths 0 .. D three times over, each timed on
@@ -303,15 +304,16 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
  * HYB_EINVAL. */
 int hyb_set_overlap(hyb_handle *h, int depth);
 
-/* Most fine steps per lattice-sweep launch (1 to 4; default 4, or 2 for
- * HYB_FP16S storage, the fastest measured for each).  With 2 or
+/* Most fine steps per lattice-sweep launch (1 to 5; default 5 for HYB_FP32,
+ * 4 for HYB_FP64 and 2 for HYB_FP16S storage, the fastest measured for each).  With 2 or
  * more, while every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine
  * steps in temporally blocked launches (the state between the steps of one
  * launch stays on chip), never leaving a lone single step where it can be
  * avoided: with 2, in pairs; with 3, in threes, a remainder of 4 taken as
  * two pairs (eta = 10: 3 + 3 + 2 + 2); with 4, in fours, remainders of 5 and
- * 6 starting with a three (eta = 10: 4 + 3 + 3); dissolving solids take
- * pairs.  A remaining single step, and
+ * 6 starting with a three (eta = 10: 4 + 3 + 3); with 5, in fives,
+ * remainders of 6, 7, 8 and 9 as 3 + 3, 4 + 3, 4 + 4 and 5 + 4 (eta = 10:
+ * 5 + 5); dissolving solids take pairs.  A remaining single step, and
  * every step when some slot is Neumann, or when a population buffer reaches
  * 4 GiB (the multi-step kernels use 32-bit byte offsets), uses the
  * single-step sweep.  Results agree with the single-step path to rounding

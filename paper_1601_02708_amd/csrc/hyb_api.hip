@@ -364,11 +364,12 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     }
     h->N = N;
     h->prec = lat->precision;
-    // FP16 shifted storage decodes and encodes every value: its sweeps are
-    // bound by instruction issue, and deeper blocking measured slower (pore2048:
-    // 81.7, 80.5, 77.3 GLUPS at 2, 3, 4 steps per launch); the others gain
-    // up to 4 (FP32 84 -> 99-105, FP64 58 -> 67-69)
-    h->steps_per_launch = lat->precision == HYB_FP16S ? 2 : 4;
+    // measured fastest per storage type at pore2048: FP32 5 (84 GLUPS with
+    // pairs, 107 with fours, 112 with fives), FP64 4 (58 -> 69; five steps
+    // leave one 83 KB workgroup per CU: 52), FP16 shifted storage 2 (it
+    // decodes and encodes every value, its sweeps are bound by instruction
+    // issue: 81.7, 80.5, 77.3 GLUPS at 2, 3, 4)
+    h->steps_per_launch = lat->precision == HYB_FP16S ? 2 : lat->precision == HYB_FP64 ? 4 : 5;
     h->fp64 = lat->precision == HYB_FP64;
     h->tau = tau;
     h->omega = 1.0 / tau;
@@ -700,7 +701,9 @@ int plan_take(int fuse, int rem) {
     if (rem <= 1 || fuse == 1) return rem < 1 ? 0 : 1;
     if (fuse == 2 || rem == 2) return 2;
     if (fuse == 3) return rem == 4 ? 2 : 3;
-    return rem == 3 || rem == 5 || rem == 6 ? 3 : 4;
+    if (fuse == 4) return rem == 3 || rem == 5 || rem == 6 ? 3 : 4;
+    // five: a remainder of 6 as 3 + 3, 7 as 4 + 3, 8 as 4 + 4, 9 as 5 + 4
+    return rem == 6 ? 3 : rem == 7 || rem == 8 ? 4 : rem >= 5 ? 5 : rem;
 }
 
 // Ring of the overlap rectangles of a pass: a K-step kernel reads K-1 nodes
@@ -730,6 +733,7 @@ hipError_t launch_fused(const hyb_handle *h, LbmArgs a, int j0, int take, hipStr
     a.lam2 = (double)(j0 + 2) / (double)h->eta;
     a.lam3 = (double)(j0 + 3) / (double)h->eta;
     a.lam4 = (double)(j0 + 4) / (double)h->eta;
+    a.lam5 = (double)(j0 + 5) / (double)h->eta;
     if (take >= 3) return launch_lbm_stepk(a, h->prec, take, s, part, depth, pass_ring(h));
     return launch_lbm_step2(a, h->prec, s, part, depth, pass_ring(h));
 }
@@ -1497,7 +1501,7 @@ extern "C" {
 
 int hyb_set_steps_per_launch(hyb_handle *h, int steps) {
     if (!h) return HYB_EINVAL;
-    if (steps < 1 || steps > 4) return h->fail(HYB_EINVAL, "steps per launch must be 1, 2, 3 or 4");
+    if (steps < 1 || steps > 5) return h->fail(HYB_EINVAL, "steps per launch must be 1 to 5");
     h->steps_per_launch = steps;
     // the launch plan sets the overlap depths available: tune again
     h->tune_idx = 0;

@@ -78,7 +78,8 @@ struct LbmArgs {
     double lam;              // j / eta of the step being taken
     double lam2;             // (j + 1) / eta: second step of a two-step launch
     double lam3;             // (j + 2) / eta: third step of a three- or four-step launch
-    double lam4;             // (j + 3) / eta: fourth step of a four-step launch
+    double lam4;             // (j + 3) / eta: fourth step of a four- or five-step launch
+    double lam5;             // (j + 4) / eta: fifth step of a five-step launch
     int clamp;
     unsigned long long *counters;
     // FP16 shifted storage: stored g = (f - w_q c_ref) * scale (binary16);

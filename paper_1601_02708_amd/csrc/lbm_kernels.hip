@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_rec_kernel(LbmArgs a, TileMap m
 
 // interface weight of stage s (1-based) of a multi-step launch
 __device__ __forceinline__ double stage_lam(const LbmArgs &a, int s) {
-    return s == 1 ? a.lam : s == 2 ? a.lam2 : s == 3 ? a.lam3 : a.lam4;
+    return s == 1 ? a.lam : s == 2 ? a.lam2 : s == 3 ? a.lam3 : s == 4 ? a.lam4 : a.lam5;
 }
 
 // Row and column of each round's node in a W-wide region of R nodes, NT
@@ -991,6 +991,11 @@ __global__ void __launch_bounds__(NT) lbm_sweep4_kernel(LbmArgs a, TileMap map) 
     sweepk_body<S, TW, TH, NT, PART, 4>(a, map);
 }
 
+template <typename S, int TW, int TH, int NT, int PART>
+__global__ void __launch_bounds__(NT) lbm_sweep5_kernel(LbmArgs a, TileMap map) {
+    sweepk_body<S, TW, TH, NT, PART, 5>(a, map);
+}
+
 // ---------------------------------------------------------------------------
 // initial state: f*(0) = collide(f^eq(u0)) at fluid nodes (Sec. 6.2, item i)
 // ---------------------------------------------------------------------------
@@ -1179,10 +1184,14 @@ hipError_t stepk_impl(const LbmArgs &a, int part, int depth, int ring, hipStream
         if (m.part == 0) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
         else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
         else hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);
-    } else {
+    } else if constexpr (K == 4) {
         if (m.part == 0) hipLaunchKernelGGL((lbm_sweep4_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
         else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep4_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
         else hipLaunchKernelGGL((lbm_sweep4_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);
+    } else {
+        if (m.part == 0) hipLaunchKernelGGL((lbm_sweep5_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
+        else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep5_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);
+        else hipLaunchKernelGGL((lbm_sweep5_kernel<S, TW, TH, NT, 2>), dim3(m.count), dim3(NT), 0, s, a, m);
     }
     return hipGetLastError();
 }
@@ -1191,6 +1200,7 @@ template <typename S>
 hipError_t stepk_dispatch(const LbmArgs &a, int K, int part, int depth, int ring, hipStream_t s) {
     if (K == 3) return stepk_impl<S, 3>(a, part, depth, ring, s);
     if (K == 4) return stepk_impl<S, 4>(a, part, depth, ring, s);
+    if (K == 5) return stepk_impl<S, 5>(a, part, depth, ring, s);
     return hipErrorInvalidValue;
 }
 
@@ -1204,7 +1214,7 @@ hipError_t launch_lbm_stepk(const LbmArgs &a, int prec, int K, hipStream_t s, in
 }
 
 hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part, int depth, int ring) {
-    if (ring < 1 || ring > 3) return hipErrorInvalidValue;
+    if (ring < 1 || ring > 4) return hipErrorInvalidValue;
     if (prec == HYB_FP64) return step2_impl<double>(a, part, depth, ring, s);
     if (prec == HYB_FP32) return step2_impl<float>(a, part, depth, ring, s);
     return step2_impl<_Float16>(a, part, depth, ring, s);

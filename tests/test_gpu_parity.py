@@ -168,13 +168,13 @@ def test_two_step_sweep(orc, precision, N, clamp, k_field, eta):
                                                   (4, 0, True, 6), (200, 0, False, 7), (65, 1, False, 10),
                                                   (131, 0, True, 8)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("spl", [3, 4])
+@pytest.mark.parametrize("spl", [3, 4, 5])
 def test_three_step_sweep(orc, spl, precision, N, clamp, k_field, eta):
     """Fine steps taken three or four per launch (hyb_set_steps_per_launch;
     the pass's plan with 3: eta = 5 -> 3 + 2, 9 -> 3 + 3 + 3, 3 -> 3,
     6 -> 3 + 3, 7 -> 3 + 2 + 2, 10 -> 3 + 3 + 2 + 2, 8 -> 3 + 3 + 2; with 4:
     5 -> 3 + 2, 9 -> 4 + 3 + 2, 3 -> 3, 6 -> 3 + 3, 7 -> 4 + 3, 10 -> 4 + 3 + 3,
-    8 -> 4 + 4) against the oracle and against the single-step sweep: random states, solids, every perimeter
+    8 -> 4 + 4; with 5: 9 -> 5 + 4, 10 -> 5 + 5, 8 -> 4 + 4, 7 -> 4 + 3) against the oracle and against the single-step sweep: random states, solids, every perimeter
     slot Dirichlet with interface values that make some closures infeasible
     (counted once per owned node, as by single steps), ragged tiles and
     lattices smaller than one tile."""
@@ -246,7 +246,9 @@ def test_three_step_fp16s_matches_single_steps():
                                                    (3, {"N": 257, "M": 32, "eta": 7}, 3, (1, 2, 3)),
                                                    (4, {"N": 600, "M": 32}, 3, (1, 2, 3)),
                                                    (4, {"N": 1027, "M": 32}, 2, (1, 3)),
-                                                   (4, {"N": 600, "M": 32, "eta": 9}, 2, (1, 2, 3))])
+                                                   (4, {"N": 600, "M": 32, "eta": 9}, 2, (1, 2, 3)),
+                                                   (5, {"N": 600, "M": 32}, 3, (1, 2)),
+                                                   (5, {"N": 1029, "M": 32, "eta": 9}, 2, (1, 2))])
 def test_three_step_overlapped_step_is_bit_identical(spl, over, steps, depths):
     """hyb_step with three-step launches (plan 3 + 3 + 2 + 2 at eta = 10,
     3 + 2 + 2 at eta = 7) and the deep tiles of the first launches on the
@@ -340,7 +342,7 @@ def test_overlap_rejects_negative_depth():
         g.set_overlap(-2)
 
 
-@pytest.mark.parametrize("spl,D", [(2, 5), (3, 4), (4, 3)])
+@pytest.mark.parametrize("spl,D", [(2, 5), (3, 4), (4, 3), (5, 2)])
 def test_overlap_auto_tunes_then_keeps_a_depth(spl, D):
     """HYB_OVERLAP_AUTO (the default): one serial step, then three rounds
     over depths 0 .. D (D = the pass's multi-step launches at eta = 10:
@@ -369,7 +371,7 @@ def test_steps_per_launch_rejects_other_values():
     N = 8
     z = np.zeros((N, N))
     g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z, vx=z, vy=z, D=0.1, eta=2)
-    for bad in (0, 5, -1):
+    for bad in (0, 6, -1):
         with pytest.raises(hyb.HybError):
             g.set_steps_per_launch(bad)
 
