@@ -386,7 +386,7 @@ class Hybrid:
         return self._check(load().hyb_set_overlap(self.h, int(depth)))
 
     def set_steps_per_launch(self, steps):
-        """Most fine steps per sweep launch, 1 to 4 (default 4, 2 for fp16s);
+        """Most fine steps per sweep launch, 1 to 5 (default 5 fp32, 4 fp64, 2 fp16s);
         2 or more also reverses the adjoint's fine steps in pairs."""
         return self._check(load().hyb_set_steps_per_launch(self.h, int(steps)))
 
