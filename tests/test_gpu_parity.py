@@ -215,10 +215,11 @@ def test_three_step_sweep(orc, spl, precision, N, clamp, k_field, eta):
     assert d <= (1e-14 if precision == "fp64" else 1e-6), d
 
 
-def test_three_step_fp16s_matches_single_steps():
-    """FP16 shifted storage, three steps per launch: the same values as
-    single steps to the storage format's rounding (each step rounds through
-    binary16 in both)."""
+@pytest.mark.parametrize("spl", [3, 4, 5])
+def test_three_step_fp16s_matches_single_steps(spl):
+    """FP16 shifted storage, three to five steps per launch: the same values
+    as single steps to the storage format's rounding (each step rounds
+    through binary16 in both)."""
     hyb = _gpu()
     N, eta = 97, 10
     solid, vx, vy, kf, tau = _lattice_case(N, 777, porosity=0.7)
@@ -228,16 +229,16 @@ def test_three_step_fp16s_matches_single_steps():
     b = rng.uniform(0.2, 0.6, P)
     u0 = np.full((N, N), 0.4)
     got = {}
-    for spl in (1, 3):
+    for s in (1, spl):
         g = hyb.Hybrid(N=N, x0=0, y0=0, u0=u0, vx=vx, vy=vy, D=(tau - 0.5) / 3, eta=eta, precision="fp16s",
                        tau=tau, solid=solid, k=1e-3)
-        g.set_steps_per_launch(spl)
+        g.set_steps_per_launch(s)
         g.set_boundary(a, b)
         g.lbm_substeps(eta, restart=1)
         g.commit()
-        got[spl] = g.get_populations()
+        got[s] = g.get_populations()
         g.close()
-    d = np.abs(got[3] - got[1]).max() / np.abs(got[1]).max()
+    d = np.abs(got[spl] - got[1]).max() / np.abs(got[1]).max()
     assert d <= 4e-3, d
 
 
