@@ -588,7 +588,7 @@ def main():
                          "known size, for calibrating HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the lattice patch is not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
 
