@@ -422,10 +422,10 @@ def dissolution_rate(steps=20, warmup=2, timing_steps=3, adjoint=True):
     seeded per-solid masses): K timed coarse steps after W warmup steps on
     the caller's stream (the commit's mass update, conversions and flag
     rebuild included), MLUPS over all nodes, the solids converted, and the
-    two-step sweep's average launch duration with its algorithmic bytes
-    (fluid nodes as in the plain sweep, for two fine steps; each solid node
-    with a fluid neighbour also reads and writes its FP64 link-flux sum once
-    per launch)."""
+    sweep's average launch duration with its algorithmic bytes (fluid nodes
+    as in the plain sweep, for the launch's fine steps -- five at eta = 20
+    with the library's default; each solid node with a fluid neighbour also
+    reads and writes its FP64 link-flux sum once per launch)."""
     import numpy as np
     import torch
     from paper_1601_02708_amd import configs, hyb
@@ -467,7 +467,9 @@ def dissolution_rate(steps=20, warmup=2, timing_steps=3, adjoint=True):
                 fluid_nb |= pad[1 + dj:1 + dj + N, 1 + di:1 + di + N]
     surface = int((s & fluid_nb).sum())
     nfl = int((~s).sum())
-    launch_bytes = 2 * (nfl * (18 * 4 + 8 + 2) + (N * N - nfl) * 2 + 4 * (N - 1) * 16) + surface * 16
+    plan = launch_plan(cfg.eta, default_steps_per_launch("fp32"))
+    k_avg = cfg.eta / len(plan)             # fine steps per launch (uniform at eta = 20: 5)
+    launch_bytes = k_avg * (nfl * (18 * 4 + 8 + 2) + (N * N - nfl) * 2 + 4 * (N - 1) * 16) + surface * 16
     avg = kms / max(launches, 1)
     lups = steps * cfg.max_iter * cfg.eta * N * N
     g.close()
@@ -480,7 +482,9 @@ def dissolution_rate(steps=20, warmup=2, timing_steps=3, adjoint=True):
             "ms_per_step": round(ms / steps, 4), "steps": steps, "warmup": warmup,
             "converted_in_timed_steps": int(conv1 - conv0), "converted_total": int(conv2),
             "solid_nodes_now": int(sol2.sum()),
-            "sweep_kernel": "lbm_sweep2_flux_kernel<float, 64, 8, 256> (two fine steps, link fluxes at solid nodes)",
+            "sweep_kernel": (f"lbm_sweepk_flux_kernel<float, 64, 8, 512, {plan[0]}> (launches {plan}, link fluxes at "
+                             "solid nodes)" if plan[0] >= 3 else
+                             "lbm_sweep2_flux_kernel<float, 64, 8, 256> (two fine steps, link fluxes at solid nodes)"),
             "sweep_avg_launch_ms": round(avg, 5),
             "sweep_algorithmic_bytes_per_launch": int(launch_bytes),
             "sweep_achieved_gbs": round(launch_bytes / (avg / 1e3) / 1e9, 1),

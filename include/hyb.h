@@ -313,7 +313,7 @@ int hyb_set_overlap(hyb_handle *h, int depth);
  * two pairs (eta = 10: 3 + 3 + 2 + 2); with 4, in fours, remainders of 5 and
  * 6 starting with a three (eta = 10: 4 + 3 + 3); with 5, in fives,
  * remainders of 6, 7, 8 and 9 as 3 + 3, 4 + 3, 4 + 4 and 5 + 4 (eta = 10:
- * 5 + 5); dissolving solids take pairs.  A remaining single step, and
+ * 5 + 5).  A remaining single step, and
  * every step when some slot is Neumann, or when a population buffer reaches
  * 4 GiB (the multi-step kernels use 32-bit byte offsets), uses the
  * single-step sweep.  Results agree with the single-step path to rounding

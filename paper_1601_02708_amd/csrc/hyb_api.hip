@@ -685,12 +685,11 @@ bool use_two_step(const hyb_handle *h) {
     return !h->any_neumann && h->steps_per_launch >= 2 && small_buf;
 }
 
-// Most fine steps one launch of the forward sub-stepping takes: 3 or 4 with
-// hyb_set_steps_per_launch(3 or 4) and fixed solids, 2 where two-step
-// launches apply, else 1.
+// Most fine steps one launch of the forward sub-stepping takes: the
+// handle's steps per launch where multi-step launches apply, else 1.
 int fuse_steps(const hyb_handle *h) {
     if (!use_two_step(h)) return 1;
-    return h->steps_per_launch >= 3 && !h->dissolve_on ? h->steps_per_launch : 2;
+    return h->steps_per_launch;
 }
 
 // Fine steps of the next launch when `rem` steps of the call remain, never

@@ -146,9 +146,10 @@ hipError_t launch_lbm_step(const LbmArgs &a, int prec, bool general_perimeter, h
 // rectangles of launch_lbm_stepk (ring K-1, for passes that mix them).
 hipError_t launch_lbm_step2(const LbmArgs &a, int prec, hipStream_t s, int part = 0, int depth = 0,
                             int ring = 1);
-// K = 3 or 4 fine steps in one launch (Dirichlet closure on every slot, no
-// surface reaction): a.src holds f*(j), a.dst receives f*(j+K); u^p at
-// a.lam, a.lam2, a.lam3 (, a.lam4).  Parts as launch_lbm_step2, the depth-0
+// K = 3, 4 or 5 fine steps in one launch (Dirichlet closure on every slot;
+// with the surface reaction of dissolving solids, and its link fluxes into
+// a.flux, whole-patch launches only): a.src holds f*(j), a.dst receives
+// f*(j+K); u^p at a.lam .. a.lam5.  Parts as launch_lbm_step2, the depth-0
 // rectangle being the tiles whose ring of `ring` >= K-1 nodes stays clear
 // of the patch perimeter.
 hipError_t launch_lbm_stepk(const LbmArgs &a, int prec, int K, hipStream_t s, int part = 0, int depth = 0,

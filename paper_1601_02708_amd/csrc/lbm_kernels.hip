@@ -801,7 +801,7 @@ __device__ __forceinline__ void region_fields(int N, int P, int x0, int y0, cons
 // results to registers, the next region's fields fetched, barrier, results
 // written back in place, barrier, next stage.  RING = 0: the owned nodes,
 // stored to HBM.
-template <typename S, int TW, int TH, int NT, int G, int RING>
+template <typename S, int TW, int TH, int NT, int G, int RING, bool FLUX>
 __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::T *L0, int x0, int y0,
                                              const BufRsrc &fdst, const BufRsrc &mrs, const BufRsrc &vxr,
                                              const BufRsrc &vyr,
@@ -809,7 +809,8 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
                                              const float (&vx)[Region<TW, TH, NT, RING>::ROUNDS],
                                              const float (&vy)[Region<TW, TH, NT, RING>::ROUNDS],
                                              const int (&rr)[Region<TW, TH, NT, RING>::ROUNDS],
-                                             const int (&cc)[Region<TW, TH, NT, RING>::ROUNDS]) {
+                                             const int (&cc)[Region<TW, TH, NT, RING>::ROUNDS],
+                                             const unsigned (&mo)[TW * TH / NT], double (&acc)[TW * TH / NT]) {
     typedef typename Pop<S>::T T;
     typedef Region<TW, TH, NT, RING> R;
     constexpr int W0 = TW + 2 * G, H0 = TH + 2 * G, PL = H0 * W0;
@@ -841,6 +842,11 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
             const int sel = -static_cast<int>((m[k] >> q) & 1u);
             h[k][q] = base[pull + (sel & (back - pull))];
         }
+        if constexpr (FLUX) {
+#pragma unroll
+            for (int q = 1; q < kQ; ++q)
+                if ((m[k] >> q) & 1u) h[k][q] = reactive<T>(a, h[k][q], q);
+        }
         if (perim) {
             const bool bad = dirichlet_close<T>(a, h[k], outside_bits(N, i, j), perimeter_slot(N, i, j), lam);
             if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
@@ -853,6 +859,27 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
         } else {
 #pragma unroll
             for (int q = 0; q < kQ; ++q) h[k][q] = Pop<S>::ld(Pop<S>::st(h[k][q], q, a), q, a);
+        }
+    }
+    if constexpr (FLUX) {
+        // link fluxes of this step at the owned solid nodes, in q order, from
+        // the step's input (still in LDS: the write-back comes after the
+        // barrier below)
+        constexpr int RO = TW * TH / NT;
+#pragma unroll
+        for (int k = 0; k < RO; ++k) {
+            if (!(mo[k] & kMaskSolid) || !(mo[k] & 0x1FEu)) continue;
+            const int idx = threadIdx.x + NT * k;
+            const T *base = L0 + (idx / TW + G) * W0 + (idx % TW + G);
+            double s = 0.0;
+#pragma unroll
+            for (int q = 1; q < kQ; ++q)
+                if ((mo[k] >> q) & 1u)
+                    s += a.kappa_s * (kW[q] * a.c_sat - double(base[kOpp[q] * PL + kCy[q] * W0 + kCx[q]]));
+            acc[k] += s;
+            if constexpr (RING == 0) {
+                if (a.flux) a.flux[(y0 + idx / TW) * P + x0 + idx % TW] = acc[k];
+            }
         }
     }
     if constexpr (RING > 0) {
@@ -869,11 +896,12 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
             for (int q = 0; q < kQ; ++q) L0[q * PL + (rr[k] + OFF) * W0 + (cc[k] + OFF)] = h[k][q];
         }
         __syncthreads();
-        later_stages<S, TW, TH, NT, G, RING - 1>(a, L0, x0, y0, fdst, mrs, vxr, vyr, m2, vx2, vy2, rr2, cc2);
+        later_stages<S, TW, TH, NT, G, RING - 1, FLUX>(a, L0, x0, y0, fdst, mrs, vxr, vyr, m2, vx2, vy2, rr2, cc2,
+                                                      mo, acc);
     }
 }
 
-template <typename S, int TW, int TH, int NT, int PART, int K>
+template <typename S, int TW, int TH, int NT, int PART, int K, bool FLUX = false>
 __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map) {
     typedef typename Pop<S>::T T;
     static_assert(K >= 3, "two-step launches use sweep2_body");
@@ -898,6 +926,41 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
     tile_of<PART>(map, xcd_tile(blockIdx.x, map.count), tx, ty);
     const int x0 = tx * TW;
     const int y0 = ty * TH;
+
+    // dissolving solids: flag words of the owned nodes, and for each owned
+    // solid node with fluid neighbours its running flux sum (the previous
+    // steps' sum unless this launch starts the pass) plus the link fluxes
+    // of step j+1, from the source buffer (the lines the bounce-back of its
+    // neighbours fetches)
+    constexpr int RO = TW * TH / NT;
+    unsigned mo[RO];
+    double acc[RO];
+    if constexpr (FLUX) {
+#pragma unroll
+        for (int k = 0; k < RO; ++k) {
+            const int idx = threadIdx.x + NT * k;
+            const int i = x0 + idx % TW, j = y0 + idx / TW;
+            mo[k] = 0u;
+            acc[k] = 0.0;
+            if (i < N && j < N)
+                mo[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * static_cast<unsigned>(j * P + i), 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < RO; ++k) {
+            if (!(mo[k] & kMaskSolid) || !(mo[k] & 0x1FEu)) continue;
+            const int idx = threadIdx.x + NT * k;
+            const unsigned n = static_cast<unsigned>((y0 + idx / TW) * P + x0 + idx % TW);
+            double s = 0.0;
+#pragma unroll
+            for (int q = 1; q < kQ; ++q)
+                if ((mo[k] >> q) & 1u) {
+                    const unsigned at = kOpp[q] * SP + static_cast<unsigned>(kCx[q] + kCy[q] * P);
+                    s += a.kappa_s *
+                         (kW[q] * a.c_sat - double(Pop<S>::ld(Buf<S>::load(fsrc, (n + at) * sz, 0), kOpp[q], a)));
+                }
+            acc[k] = ((a.flux_first || !a.flux) ? 0.0 : a.flux[n]) + s;
+        }
+    }
 
     // ---- stage 1: step j+1 on the tile and G rings, HBM -> LDS ----------
     S raw[ROUNDS0][kQ];
@@ -959,7 +1022,8 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
         for (int q = 0; q < kQ; ++q) {
             const T pulled = Pop<S>::ld(raw[k][q], q, a);
             const T own = Pop<S>::ld(raw[k][q], kOpp[q], a);
-            f[q] = ((m[k] >> q) & 1u) ? own : pulled;
+            if constexpr (FLUX) f[q] = ((m[k] >> q) & 1u) ? reactive<T>(a, own, q) : pulled;
+            else f[q] = ((m[k] >> q) & 1u) ? own : pulled;
         }
         if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
             const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
@@ -978,7 +1042,8 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
     int r1[R1::ROUNDS], c1[R1::ROUNDS];
     region_fields<TW, TH, NT, G - 1>(N, P, x0, y0, mrs, vxr, vyr, m1, vx2, vy2, r1, c1);
     __syncthreads();
-    later_stages<S, TW, TH, NT, G, G - 1>(a, &lds[0][0][0], x0, y0, fdst, mrs, vxr, vyr, m1, vx2, vy2, r1, c1);
+    later_stages<S, TW, TH, NT, G, G - 1, FLUX>(a, &lds[0][0][0], x0, y0, fdst, mrs, vxr, vyr, m1, vx2, vy2, r1,
+                                                c1, mo, acc);
 }
 
 template <typename S, int TW, int TH, int NT, int PART>
@@ -994,6 +1059,12 @@ __global__ void __launch_bounds__(NT) lbm_sweep4_kernel(LbmArgs a, TileMap map) 
 template <typename S, int TW, int TH, int NT, int PART>
 __global__ void __launch_bounds__(NT) lbm_sweep5_kernel(LbmArgs a, TileMap map) {
     sweepk_body<S, TW, TH, NT, PART, 5>(a, map);
+}
+
+// whole-patch K-step launch with the surface reaction of dissolving solids
+template <typename S, int TW, int TH, int NT, int K>
+__global__ void __launch_bounds__(NT) lbm_sweepk_flux_kernel(LbmArgs a, TileMap map) {
+    sweepk_body<S, TW, TH, NT, 0, K, true>(a, map);
 }
 
 // ---------------------------------------------------------------------------
@@ -1179,7 +1250,13 @@ hipError_t stepk_impl(const LbmArgs &a, int part, int depth, int ring, hipStream
     }
     m.count = m.part == 0 ? all : m.part == 1 ? inner : all - inner;
     if (m.count == 0) return hipSuccess;
-    if (a.flux || a.kappa_s != 0.0 || a.mid) return hipErrorInvalidValue;
+    if (a.mid) return hipErrorInvalidValue;
+    if (a.flux || a.kappa_s != 0.0) {
+        // dissolving solids: whole-patch launches only
+        if (m.part != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((lbm_sweepk_flux_kernel<S, TW, TH, NT, K>), dim3(m.count), dim3(NT), 0, s, a, m);
+        return hipGetLastError();
+    }
     if constexpr (K == 3) {
         if (m.part == 0) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 0>), dim3(m.count), dim3(NT), 0, s, a, m);
         else if (m.part == 1) hipLaunchKernelGGL((lbm_sweep3_kernel<S, TW, TH, NT, 1>), dim3(m.count), dim3(NT), 0, s, a, m);

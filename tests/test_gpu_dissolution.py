@@ -196,7 +196,7 @@ def test_dissolution_two_step_equals_single_step():
     N = p.cfg.N
     mass = np.random.default_rng(8).uniform(0.002, 0.01, (N, N))
     out = []
-    for spl in (1, 2):
+    for spl in (1, 2, 3, 4, 5):
         g = hyb.Hybrid.from_problem(p, precision="fp64", dissolution=True)
         g.set_steps_per_launch(spl)
         g.set_dissolution(0.2, 1.0, mass)
@@ -206,8 +206,9 @@ def test_dissolution_two_step_equals_single_step():
         sol, m, conv = g.dissolution_state()
         out.append((g.get_populations(), sol, m, conv))
         g.close()
-    assert np.array_equal(out[0][1], out[1][1]) and out[0][3] == out[1][3] > 0
-    assert _rel(out[1][0], out[0][0]) <= 1e-13 and _rel(out[1][2], out[0][2]) <= 1e-13
+    for o in out[1:]:
+        assert np.array_equal(out[0][1], o[1]) and out[0][3] == o[3] > 0
+        assert _rel(o[0], out[0][0]) <= 1e-13 and _rel(o[2], out[0][2]) <= 1e-13
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-4)])
