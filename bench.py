@@ -1,18 +1,20 @@
 """Benchmark: the hybrid multi-time-step FEM/LBM step on one MI355X.
 
-A "step" is one coarse step of Algorithm 1 on the pore-scale workload
-(2048^2 D2Q9 lattice with random solid disks at porosity 0.6, seeded
-8-mode stream-function velocity, D = 5e-3, reaction k = 1e-4, 128^2 Q1
-mesh, eta = 10 fine steps per coarse step, 2 Schwarz passes): 2 x
-{fine-to-coarse transfer, FP64 coarse solve, coarse-to-fine transfer,
-10 lattice sweeps}, then commit.  Inputs are synthetic and seeded and
+A "step" is one coarse step of Algorithm 1.  By default the workload is the
+precision form at 4096^2 (pore4096: D2Q9 lattice with random solid disks at
+porosity 0.6, seeded 8-mode stream-function velocity, D = 1e-2, 16^2 Q1
+mesh, eta = 4 fine steps per coarse step, 2 Schwarz passes) in FP64:
+2 x {fine-to-coarse transfer, FP64 coarse solve, coarse-to-fine transfer,
+4 lattice sweeps}, then commit.  Inputs are synthetic and seeded and
 already resident in HBM when the timed region starts.
 
 The printed JSON line reports lattice updates per second over all nodes
-(MLUPS), the roofline of the lattice-sweep kernel (algorithmic bytes per
-launch over its average duration, timed with HIP events on its stream),
-the FP64 path on the same GPU with the FP32 result's relative L2 error
-against it, and the CPU oracle timed on a bounded sample on this host.
+(MLUPS); the roofline of the dominant lattice-sweep kernel (algorithmic
+bytes per launch over its average duration, timed with HIP events on its
+stream, next to the HBM bytes the counters measured for it); FP32 and FP16
+shifted storage on the same GPU, with their relative L2 errors against FP64
+after the timed steps and after all of the workload's coarse steps; and the
+CPU oracle timed on a bounded sample on this host (all threads and one).
 """
 import argparse
 import hashlib
@@ -89,17 +91,55 @@ def sweep_kernel(elem_bytes, take):
     return f"lbm_sweep_kernel<{t}>"
 
 
-def load_traffic(workload, precision, kernel):
-    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
-    record of this kernel, or None when there is none or the kernel source
-    changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+def _profile_record(kind, workload, precision, kernel):
+    """A committed counter record profiles/<kind>_<workload>_<precision>.json
+    of this kernel, or None when there is none or the kernel source changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_sha") != kernel_hash() or kernel.split("<")[0] + "<" not in rec.get("kernel", ""):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def load_traffic(workload, precision, kernel):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
+    record of this kernel (scaled by a plain copy's counters), or None."""
+    rec = _profile_record("traffic", workload, precision, kernel)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def load_limiter(workload, precision, kernel):
+    """The limiter the committed SQ counter record of this kernel names
+    (its 'bound' and a one-line 'limiter' reading of the counters), or
+    None."""
+    rec = _profile_record("sq", workload, precision, kernel)
+    return None if rec is None else {"bound": rec.get("bound"), "limiter": rec.get("limiter")}
+
+
+def final_step_errors(problem, ref_precision, others):
+    """Each precision's fine (fluid nodes) and coarse concentration after
+    all of the workload's coarse steps, each from a fresh handle at the
+    library's default launch plan; relative L2 of the others against
+    ref_precision's.  (The parity tests hold the FP64 path to the oracle at
+    1e-12 at this step.)"""
+    import numpy as np
+    from paper_1601_02708_amd import hyb
+    cfg = problem.cfg
+    fluid = problem.solid == 0
+    res = {}
+    for prec in [ref_precision] + list(others):
+        g = hyb.Hybrid.from_problem(problem, precision=prec, device="cuda:0")
+        for _ in range(cfg.steps):
+            g.step(cfg.max_iter)
+        res[prec] = (g.concentration()[fluid], g.concentration(hyb.HYB_COARSE).reshape(-1))
+        g.close()
+    uf, dc = res[ref_precision]
+    return {p: {"fine": float(np.linalg.norm(res[p][0] - uf) / np.linalg.norm(uf)),
+                "coarse": float(np.linalg.norm(res[p][1] - dc) / np.linalg.norm(dc)),
+                "coarse_steps": cfg.steps} for p in others}
 
 
 def tune_overlap(problem, precision, steps_per_launch=None):
@@ -543,11 +583,25 @@ def cpu_baseline_1d(row, gpu_rows):
             "gpu_seconds": round(gpu["gpu_ms"] / 1e3, 4)}
 
 
-def cpu_baseline(problem, min_seconds=10.0, max_steps=6):
-    """The oracle as it stands on this host: whole coarse steps (2 Schwarz
-    passes x eta fine steps each, FP64, one thread) of the same workload,
-    repeated until at least min_seconds of CPU work have been timed."""
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or 'unknown'."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_steps(problem, threads, min_seconds, max_steps):
+    """Whole coarse steps of the oracle on `threads` threads (None: the
+    OpenMP default) until min_seconds have been timed; (steps, seconds,
+    threads used)."""
     import oracle
+    if threads is not None:
+        oracle.set_threads(threads)
+    used = oracle.get_threads()
     o = oracle.HybridOracle(problem)
     steps = 0
     t0 = time.perf_counter()
@@ -557,11 +611,27 @@ def cpu_baseline(problem, min_seconds=10.0, max_steps=6):
         dt = time.perf_counter() - t0
         if dt >= min_seconds or steps >= max_steps:
             break
-    lups = steps * problem.cfg.max_iter * problem.cfg.eta * problem.cfg.N ** 2
-    return {"value": round(lups / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{problem.cfg.name}: first {steps} coarse steps ({problem.cfg.max_iter} Schwarz passes x "
-                      f"{problem.cfg.eta} fine steps on {problem.cfg.N}^2 nodes, plus the {problem.cfg.M}^2 "
-                      f"coarse solves, per step), FP64, single thread, {dt:.1f} s"}
+    return steps, dt, used
+
+
+def cpu_baseline(problem, min_seconds=8.0, max_steps=6):
+    """The oracle as it stands on this host (its lattice loops split over
+    rows by OpenMP, the rest serial): whole coarse steps (Schwarz passes x
+    eta fine steps, FP64) of the same workload with every thread OpenMP
+    gives it, then on one thread, each repeated until min_seconds of CPU
+    work have been timed."""
+    import oracle
+    cfg = problem.cfg
+    lups_step = cfg.max_iter * cfg.eta * cfg.N ** 2
+    steps, dt, used = _oracle_steps(problem, None, min_seconds, max_steps)
+    steps1, dt1, _ = _oracle_steps(problem, 1, min_seconds, max_steps)
+    oracle.set_threads(used)
+    what = (f"{cfg.name}: first {{}} coarse steps ({cfg.max_iter} Schwarz passes x {cfg.eta} fine steps on "
+            f"{cfg.N}^2 nodes, plus the {cfg.M}^2 coarse solves, per step), FP64, {{}} thread(s), {{:.1f}} s")
+    return {"value": round(steps * lups_step / dt / 1e6, 3), "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": what.format(steps, used, dt), "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
+            "single_thread": {"value": round(steps1 * lups_step / dt1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": what.format(steps1, 1, dt1)}}
 
 
 def main():
@@ -569,8 +639,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pore2048")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16s"])
+    ap.add_argument("--workload", default="pore4096")
+    ap.add_argument("--precision", default="fp64", choices=["fp32", "fp64", "fp16s"])
     ap.add_argument("--steps-per-launch", type=int, default=None, choices=[1, 2, 3, 4, 5],
                     help="most fine steps per lattice-sweep launch (temporal blocking; eta = 10 runs 5 + 5 at 5, "
                          "4 + 3 + 3 at 4); default: the library's (5 fp32, 4 fp64, 2 fp16s)")
@@ -629,6 +699,7 @@ def main():
     launch_bytes = bbytes * steps_launch
     achieved = launch_bytes / (avg_kernel_ms / 1e3) / 1e9
     traffic = load_traffic(cfg.name, args.precision, kname)
+    lim = load_limiter(cfg.name, args.precision, kname)
     res = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -651,12 +722,18 @@ def main():
         },
         "mflups": round(value * fluid_frac, 1),
         "roofline": {
-            "bound": "hbm",
+            "bound": lim["bound"] if lim else "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            # what the kernel really moves: the counters' bytes over the same
+            # launch duration (the algorithmic figure counts every fine step
+            # of a temporally blocked launch, the state crosses HBM once)
+            "hbm_achieved": None if traffic is None else round(traffic / (avg_kernel_ms / 1e3) / 1e9, 1),
+            "hbm_frac": None if traffic is None else round(traffic / (avg_kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "limiter": lim["limiter"] if lim else None,
             "kernel": kname,
             "fine_steps_per_launch": steps_launch,
             "fluid_updates_per_launch": int(nfl * steps_launch),
@@ -700,6 +777,8 @@ def main():
             if p_ != "fp64":
                 key = "fp32_rel_l2_vs_fp64" if p_ == "fp32" else f"{p_}_rel_l2_vs_fp64"
                 res[key] = float(np.linalg.norm((u_ - ref)[fluid]) / nref)
+        print(f"[bench] final-step errors ({cfg.steps} coarse steps)", file=sys.stderr, flush=True)
+        res["final_step_rel_l2_vs_fp64"] = final_step_errors(problem, "fp64", ["fp32", "fp16s"])
     if not args.no_adjoint and args.precision in ("fp32", "fp64"):
         print("[bench] adjoint", file=sys.stderr, flush=True)
         res["adjoint"] = adjoint_rate(problem, args.precision)
@@ -713,7 +792,7 @@ def main():
         g.close()
         res["dissolution"] = dissolution_rate(adjoint=not args.no_adjoint)
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle, one coarse step)", file=sys.stderr, flush=True)
+        print("[bench] cpu baseline (oracle, all threads and one thread)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(problem)
         if "hybrid1d" in res:
             row = [r for r in hybrid1d_tables.rows if r[0] == "T1r3"][0]

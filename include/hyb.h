@@ -128,6 +128,10 @@ typedef struct {
     int64_t fine_steps;     /* fine steps run since creation (all Schwarz passes) */
     int32_t overlap_depth;  /* overlap depth hyb_step uses (-1 while it is still being tuned) */
     int32_t pad;
+    /* diagnostics of the current fine state, as hyb_diagnostics out[0..2] */
+    double mass;            /* sum over fluid nodes of the concentration */
+    double min_f;           /* smallest post-collision population at a fluid node */
+    double h_function;      /* Boltzmann H of eq. (BH) over the fluid nodes */
 } hyb_run_stats;
 
 /* Device memory the caller must provide for this problem. */
@@ -217,7 +221,23 @@ int hyb_set_coarse(hyb_handle *h, const double *d);
 int hyb_set_reaction_field(hyb_handle *h, const double *k_field);
 int hyb_set_outer_value(hyb_handle *h, double value);
 
+/* Counters, the last coarse solve's result and the diagnostics of the
+ * current fine state (runs hyb_diagnostics).  Synchronises. */
 int hyb_stats(hyb_handle *h, hyb_run_stats *out);
+
+/* Diagnostics of the current fine state f* (the committed state after
+ * hyb_commit, else the latest fine step), over the fluid nodes (Sec. 4.1):
+ *   out[0] = sum of the concentration u = sum_q f*_q / (1 - k)   (eq. LBM_Macro
+ *            with the reaction readout; the lattice's mass),
+ *   out[1] = smallest post-collision population f*_q (non-negativity, eq. NN_Cond),
+ *   out[2] = H = sum_q f*_q ln(f*_q / w_q) over f*_q > 0         (eq. BH),
+ *   out[3] = number of nodes holding a non-finite population.
+ * FP64 from the decoded stored values; the sums run in a fixed order, so the
+ * values are reproducible.  out: 4 doubles, host (out_is_device = 0: the
+ * call synchronises) or device (the call only enqueues work on the handle's
+ * stream).  Row partials use the handle's workspace, so calls on one
+ * handle are serialised by its stream. */
+int hyb_diagnostics(hyb_handle *h, double *out, int out_is_device);
 
 /* ---- differentiation form (reverse mode) of the fine sub-steps ----------
  *

@@ -33,7 +33,7 @@ class OrcLattice(ctypes.Structure):
     _fields_ = [("N", c_int), ("periodic_x", c_int), ("periodic_y", c_int),
                 ("tau", c_double), ("solid", c_void_p), ("vx", c_void_p), ("vy", c_void_p),
                 ("k", c_void_p), ("kval", c_double), ("bc_kind", c_void_p), ("clamp", c_int),
-                ("kappa_s", c_double), ("c_sat", c_double)]
+                ("kappa_s", c_double), ("c_sat", c_double), ("work_f", c_void_p), ("work_unknown", c_void_p)]
 
 
 def lib():
@@ -47,6 +47,8 @@ def lib():
         P = c_void_p
         sig = {
             "orc_d2q9": (None, [P, P, P, P]),
+            "orc_set_threads": (None, [c_int]),
+            "orc_get_threads": (c_int, []),
             "orc_feq": (None, [c_double, c_double, c_double, P]),
             "orc_perimeter_slot": (c_int, [c_int, c_int, c_int]),
             "orc_perimeter_node": (None, [c_int, c_int, P, P]),
@@ -98,6 +100,35 @@ def d2q9():
     opp = np.zeros(9, np.int32)
     lib().orc_d2q9(_p(ex), _p(ey), _p(w), _p(opp))
     return ex, ey, w, opp
+
+
+def set_threads(n):
+    """Threads of the oracle's row-parallel lattice loops (n >= 1; the
+    default is OpenMP's, OMP_NUM_THREADS when set).  Results do not depend
+    on it."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
+
+
+def sound_speed_sq():
+    """c_s^2 of the D2Q9 lattice as its second velocity moment,
+    sum_i w_i e_ix^2 (Sec. 4.1: c_s = dx / (sqrt(3) dt), so 1/3 in lattice
+    units)."""
+    ex, _, w, _ = d2q9()
+    return float(np.sum(w * ex.astype(np.float64) ** 2))
+
+
+def relaxation_time(D, tau=None):
+    """BGK relaxation time of the lattice-unit problem (fine step 1,
+    spacing 1): tau = 1/2 + D / c_s^2 (Sec. 4.1, the relation between the
+    diffusion coefficient and the relaxation time), unless an explicit
+    ``tau`` overrides it."""
+    if tau is not None:
+        return float(tau)
+    return 0.5 + float(D) / sound_speed_sq()
 
 
 def feq(u, vx, vy):
@@ -155,9 +186,13 @@ class Lattice:
         else:
             self.kfield, self.kval = _f64(k).reshape(N, N), 0.0
         self.bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, dtype=np.int8)
+        # scratch of one step, allocated once per lattice (no values carry
+        # over between steps)
+        self._work_f = np.empty((9, self.N, self.N))
+        self._work_unknown = np.empty((self.N, self.N), np.uint16)
         self.s = OrcLattice(self.N, int(periodic_x), int(periodic_y), self.tau, _p(self.solid),
                             _p(self.vx), _p(self.vy), _p(self.kfield), self.kval, _p(self.bc_kind),
-                            int(clamp), float(kappa_s), float(c_sat))
+                            int(clamp), float(kappa_s), float(c_sat), _p(self._work_f), _p(self._work_unknown))
         self.kappa_s, self.c_sat = float(kappa_s), float(c_sat)
 
     @property
@@ -170,12 +205,17 @@ class Lattice:
         lib().orc_lbm_init(self.ptr, _p(u0), _p(out))
         return out
 
-    def substep(self, fsrc, bc_value=None):
+    def substep(self, fsrc, bc_value=None, out=None):
+        """One fine step from fsrc into a new array, or into ``out`` (a
+        C-contiguous FP64 array of fsrc's shape that is not fsrc)."""
         fsrc = _f64(fsrc)
         if bc_value is None:
             bc_value = np.zeros(4 * (self.N - 1))
         bc_value = _f64(bc_value)
-        out = np.empty_like(fsrc)
+        if out is None:
+            out = np.empty_like(fsrc)
+        elif out is fsrc or out.shape != fsrc.shape or out.dtype != np.float64 or not out.flags.c_contiguous:
+            raise ValueError("out must be a separate C-contiguous FP64 array of the state's shape")
         inf = lib().orc_lbm_substep(self.ptr, _p(fsrc), _p(out), _p(bc_value))
         return out, int(inf)
 

@@ -1,5 +1,6 @@
 """Compile the CPU oracle into oracle/liboracle.so (plain gcc, FP64,
--O2, no FMA contraction).  Test infrastructure only."""
+-O2, no FMA contraction, OpenMP over lattice rows).  Test infrastructure
+only."""
 import os
 import subprocess
 import sys
@@ -11,7 +12,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+           "-fopenmp", "-Wall", "-Wextra", "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import Lattice, d2q9
+from . import Lattice, d2q9, relaxation_time
 from .hybrid import HybridOracle, algorithm1_step
 from .hybrid_adjoint import f2c_weights
 
@@ -117,7 +117,7 @@ class DissolvingHybrid(HybridOracle):
         sol0 = np.asarray(self.p.solid) != 0
         vx = np.where(sol0, 0.0, self.p.vx.astype(np.float64))
         vy = np.where(sol0, 0.0, self.p.vy.astype(np.float64))
-        self.lat = Lattice(self.N, cfg.tau_value, vx, vy, solid=self.solid, k=cfg.k, clamp=cfg.bc_clamp,
+        self.lat = Lattice(self.N, relaxation_time(cfg.D, cfg.tau), vx, vy, solid=self.solid, k=cfg.k, clamp=cfg.bc_clamp,
                            kappa_s=self.kappa_s, c_sat=self.c_sat)
 
     def transfer(self, u, solid):

@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import FemStepper, Lattice, fem_interpolate, fine_to_coarse, perimeter_nodes
+from . import FemStepper, Lattice, fem_interpolate, fine_to_coarse, perimeter_nodes, relaxation_time
 
 
 def coarse_dirichlet_sets(M, L, N, x0, y0, overlap_elems=1, outer_natural=0):
@@ -74,7 +74,7 @@ class HybridOracle:
         self.eta = cfg.eta if eta is None else eta
         self.max_iter = cfg.max_iter if max_iter is None else max_iter
         self.k = cfg.k
-        tau = cfg.tau_value if tau is None else tau
+        tau = relaxation_time(cfg.D, cfg.tau if tau is None else tau)
         # outer edges and values as the workload states them unless given
         outer_value = cfg.outer_value if outer_value is None else outer_value
         outer_natural = cfg.outer_natural if outer_natural is None else outer_natural
@@ -120,12 +120,15 @@ class HybridOracle:
     def lbm_substeps(self, fstar0, a, b, n_sub=None):
         F = fstar0
         n_sub = self.eta if n_sub is None else n_sub
+        if not hasattr(self, "_ping"):
+            self._ping = (np.empty_like(fstar0), np.empty_like(fstar0))
         for j in range(1, n_sub + 1):
             lam = j / self.eta
             up = (1.0 - lam) * a + lam * b
-            F, inf = self.lat.substep(F, up)
+            F, inf = self.lat.substep(F, up, out=self._ping[j % 2])
             self.infeasible += inf
-        return F
+        # the result leaves the step buffers (the caller keeps it as state)
+        return F.copy() if n_sub > 0 else F
 
     # -- Algorithm 1 -------------------------------------------------------
     def step(self):

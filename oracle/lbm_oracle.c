@@ -6,7 +6,12 @@
  *
  * Plain, slow and literal: each part of the method is a separate loop over
  * the lattice or the mesh, written in the order the paper states it.  No
- * SIMD, no blocking, no fusion.  Build: gcc -O2 -ffp-contract=off.
+ * SIMD, no blocking, no fusion.  Build: gcc -O2 -ffp-contract=off -fopenmp.
+ * The loops whose nodes are independent (streaming, collision, readout,
+ * initialisation) are split over rows between OpenMP threads; every node is
+ * still computed by one thread with the same operations in the same order,
+ * so the results do not depend on the thread count.  Loops that sum over
+ * nodes or scatter into shared entries stay serial.
  *
  * Lattice-unit conventions: fine spacing 1, fine step 1; node (i, j) of an
  * N x N lattice is stored at n = j*N + i; populations are planes [9][N*N].
@@ -26,6 +31,7 @@
  *   - coarse-to-fine and fine-to-coarse transfers               (Secs. 5.1, 6.2)
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -48,6 +54,13 @@ void orc_d2q9(int *ex, int *ey, double *w, int *opp) {
         opp[i] = OPP[i];
     }
 }
+
+/* Threads used by the row-parallel loops (n >= 1; the default is OpenMP's,
+ * OMP_NUM_THREADS when set). */
+void orc_set_threads(int n) {
+    if (n >= 1) omp_set_num_threads(n);
+}
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* Equilibrium, eq. (LBM_feq):
  *   f_i^eq = w_i u (1 + e.v/c_s^2 + (e.v)^2/(2 c_s^4) - v.v/(2 c_s^2)). */
@@ -74,6 +87,8 @@ typedef struct {
     int clamp;                   /* Dirichlet closure: 0 as printed, 1 clamp unknowns at 0 */
     double kappa_s;              /* surface reaction at fluid-solid links (0: plain bounce-back) */
     double c_sat;                /* concentration the surface reaction drives towards */
+    double *work_f;              /* [9*N*N] scratch of orc_lbm_substep, or NULL (allocated per call) */
+    uint16_t *work_unknown;      /* [N*N] scratch of orc_lbm_substep, or NULL */
 } orc_lattice;
 
 static int is_solid(const orc_lattice *L, int n) { return L->solid && L->solid[n]; }
@@ -114,6 +129,7 @@ void orc_lbm_init(const orc_lattice *L, const double *u0, double *fstar) {
     int N = L->N;
     size_t NN = (size_t)N * N;
     double *f = (double *)calloc(9 * NN, sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int n = 0; n < (int)NN; ++n) {
         if (is_solid(L, n)) continue;
         double feq[9];
@@ -138,6 +154,7 @@ void orc_lbm_init(const orc_lattice *L, const double *u0, double *fstar) {
 void orc_stream(const orc_lattice *L, const double *fstar, double *f, uint16_t *unknown) {
     int N = L->N;
     size_t NN = (size_t)N * N;
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < N; ++j) {
         for (int i = 0; i < N; ++i) {
             int n = j * N + i;
@@ -289,6 +306,7 @@ long orc_apply_bc(const orc_lattice *L, const double *fstar, double *f,
 void orc_collide(const orc_lattice *L, const double *f, double *fstar) {
     int N = L->N;
     size_t NN = (size_t)N * N;
+#pragma omp parallel for schedule(static)
     for (int n = 0; n < (int)NN; ++n) {
         if (is_solid(L, n)) {
             for (int q = 0; q < 9; ++q) fstar[q * NN + n] = 0.0;
@@ -311,13 +329,13 @@ void orc_collide(const orc_lattice *L, const double *f, double *fstar) {
 long orc_lbm_substep(const orc_lattice *L, const double *fsrc, double *fdst, const double *bc_value) {
     int N = L->N;
     size_t NN = (size_t)N * N;
-    double *f = (double *)malloc(9 * NN * sizeof(double));
-    uint16_t *unknown = (uint16_t *)malloc(NN * sizeof(uint16_t));
+    double *f = L->work_f ? L->work_f : (double *)malloc(9 * NN * sizeof(double));
+    uint16_t *unknown = L->work_unknown ? L->work_unknown : (uint16_t *)malloc(NN * sizeof(uint16_t));
     orc_stream(L, fsrc, f, unknown);
     long inf = orc_apply_bc(L, fsrc, f, unknown, bc_value);
     orc_collide(L, f, fdst);
-    free(f);
-    free(unknown);
+    if (!L->work_f) free(f);
+    if (!L->work_unknown) free(unknown);
     return inf;
 }
 
@@ -327,6 +345,7 @@ long orc_lbm_substep(const orc_lattice *L, const double *fsrc, double *fdst, con
 void orc_concentration(const orc_lattice *L, const double *fstar, double *u) {
     int N = L->N;
     size_t NN = (size_t)N * N;
+#pragma omp parallel for schedule(static)
     for (int n = 0; n < (int)NN; ++n) {
         if (is_solid(L, n)) { u[n] = 0.0; continue; }
         double s = 0.0;

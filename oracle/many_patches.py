@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import FemStepper, Lattice, fem_interpolate, fine_to_coarse, perimeter_nodes
+from . import FemStepper, Lattice, fem_interpolate, fine_to_coarse, perimeter_nodes, relaxation_time
 from .hybrid import coarse_dirichlet_sets
 
 
@@ -36,7 +36,7 @@ class ManyPatchOracle:
             o, fc = coarse_dirichlet_sets(M, L, p.N, p.x0, p.y0, mp.overlap_elems)
             outer = o
             self.fc.append(fc)
-            self.lat.append(Lattice(p.N, mp.tau_value, p.vx.astype(np.float64), p.vy.astype(np.float64),
+            self.lat.append(Lattice(p.N, relaxation_time(mp.D), p.vx.astype(np.float64), p.vy.astype(np.float64),
                                     solid=p.solid, k=mp.k, clamp=mp.bc_clamp))
             ii, jj = perimeter_nodes(p.N)
             self.perim.append((p.x0 + ii, p.y0 + jj))

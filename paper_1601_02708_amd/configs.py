@@ -28,8 +28,9 @@ step 1, coarse step = eta):
   kappa_s = 0.01 towards c_sat = 1 at every fluid-solid link and a seeded
   mass in U[0.5, 1.0] per solid node (``solid_mass``).
 
-The relaxation time follows the lattice-unit relation tau = 1/2 + D/c_s^2
-with c_s^2 = 1/3 (Sec. 4.1); the outer boundary of the coarse domain is
+The descriptors carry the diffusion coefficient D only (plus an optional
+relaxation-time override): the solvers derive the BGK relaxation time from
+D themselves (Sec. 4.1).  The outer boundary of the coarse domain is
 Dirichlet 0 on all four edges, and the initial condition is the seeded
 Gaussian pulse on both grids.
 """
@@ -62,7 +63,7 @@ class HybridConfig:
     supg: int = 1
     bc_clamp: int = 0           # maxent Dirichlet: 0 closed form as printed, 1 clamp at 0
     seed: int = 0
-    tau: Optional[float] = None  # None: 1/2 + 3 D
+    tau: Optional[float] = None  # BGK relaxation time override; None: each solver derives it from D
     # dissolving solids (kappa_s = 0: fixed solids)
     kappa_s: float = 0.0        # surface reaction rate at fluid-solid links
     c_sat: float = 1.0          # concentration the surface reaction drives towards
@@ -77,10 +78,6 @@ class HybridConfig:
     @property
     def L(self) -> float:
         return inputs.domain_side(self.N)
-
-    @property
-    def tau_value(self) -> float:
-        return self.tau if self.tau is not None else 0.5 + 3.0 * self.D
 
     def replace(self, **kw) -> "HybridConfig":
         return dataclasses.replace(self, **kw)
@@ -213,10 +210,6 @@ class MultiProblem:
     vc: np.ndarray            # [(M+1)^2, 2] coarse nodal velocity
     u0_coarse: np.ndarray     # [(M+1)^2]
     patches: list
-
-    @property
-    def tau_value(self) -> float:
-        return 0.5 + 3.0 * self.D
 
 
 def build_multi(N: int, M: int, L: float, origins, D: float = 1e-2, k: float = 0.0, eta: int = 4,

@@ -78,7 +78,7 @@ struct Layout {
     size_t f_bytes = 0;
     size_t mask = 0, vx = 0, vy = 0, kfield = 0, bc_kind = 0, bc_a = 0, bc_b = 0, c2f_idx = 0, c2f_w = 0;
     size_t fc_idx = 0, fc_w = 0, ufc = 0, A9 = 0, B9 = 0, AP = 0, P = 0, dkind = 0, vec = 0, partials = 0;
-    size_t counters = 0, barrier = 0, kres = 0, total = 0;
+    size_t counters = 0, barrier = 0, kres = 0, diag = 0, total = 0;
     size_t APT = 0, PT = 0, c2fT_ptr = 0, c2fT_slot = 0, c2fT_w = 0, f2cT_node = 0, f2cT_ptr = 0, f2cT_c = 0;
     size_t f2cT_w = 0, fc_row = 0;
     // dissolving solids (hyb_lattice.dissolution): per-node mass, link flux
@@ -114,6 +114,7 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
     L.bc_b = take(nslots * 8);
     L.counters = take(kCntSlots * 8);
     L.kres = take(sizeof(KrylovResult));
+    L.diag = take(((size_t)kDiagValues * N + kDiagValues) * 8);   // row partials, then the result
     if (lat->dissolution) {
         L.dissolve = true;
         L.mass = take(nodes * 8);
@@ -219,6 +220,7 @@ struct hyb_handle {
     CoarseDev cd{};
     unsigned long long *counters = nullptr;
     KrylovResult *kres = nullptr;
+    double *diag = nullptr;             // [kDiagValues N] row partials, then [kDiagValues] result
     // state machine
     int frozen = 0, cur = 0, jsub = 0;
     bool solved_this_step = false;
@@ -461,6 +463,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     h->bc_b = reinterpret_cast<double *>(h->ws + L.bc_b);
     h->counters = reinterpret_cast<unsigned long long *>(h->ws + L.counters);
     h->kres = reinterpret_cast<KrylovResult *>(h->ws + L.kres);
+    h->diag = reinterpret_cast<double *>(h->ws + L.diag);
     if (L.dissolve) {
         h->dissolve_ws = true;
         h->mass = reinterpret_cast<double *>(h->ws + L.mass);
@@ -1154,13 +1157,31 @@ int hyb_set_outer_value(hyb_handle *h, double value) {
     return HYB_OK;
 }
 
+int hyb_diagnostics(hyb_handle *h, double *out, int out_is_device) {
+    if (!h || !out) return HYB_EINVAL;
+    LbmArgs a = h->lbm_args(h->cur, -1);
+    double *res = out_is_device ? out : h->diag + (size_t)kDiagValues * h->N;
+    HIP_TRY(h, launch_diagnostics(a, h->prec, h->diag, res, h->stream));
+    if (!out_is_device) {
+        HIP_TRY(h, hipMemcpyAsync(out, res, kDiagValues * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    return HYB_OK;
+}
+
 int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
     if (!h || !out) return HYB_EINVAL;
     unsigned long long cnt[kCntSlots];
     KrylovResult kr{};
+    double dg[kDiagValues];
+    const int rc = hyb_diagnostics(h, dg, 0);
+    if (rc != HYB_OK) return rc;
     HIP_TRY(h, hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipMemcpyAsync(&kr, h->kres, sizeof(kr), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out->mass = dg[0];
+    out->min_f = dg[1];
+    out->h_function = dg[2];
     out->infeasible = (int64_t)cnt[kCntInfeasible];
     out->nonfinite = (int64_t)cnt[kCntNonfinite];
     out->krylov_iters = kr.iters;

@@ -173,6 +173,12 @@ hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, 
                                hipStream_t s, bool accumulate = false);
 hipError_t launch_lbm_init(const LbmArgs &a, const double *u0, int prec, hipStream_t s);
 hipError_t launch_concentration(const LbmArgs &a, double *out, int prec, hipStream_t s);
+// Diagnostics of the state a.src over the fluid nodes: out[0] = sum of the
+// concentration, out[1] = smallest population, out[2] = H of eq. (BH),
+// out[3] = nodes with a non-finite population (FP64, device).  part is
+// device scratch of 4 a.N doubles (row partials).
+hipError_t launch_diagnostics(const LbmArgs &a, int prec, double *part, double *out, hipStream_t s);
+constexpr int kDiagValues = 4;
 
 struct CoarseDev {
     int M;

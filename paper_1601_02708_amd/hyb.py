@@ -50,7 +50,8 @@ class HybReaction(ctypes.Structure):
 class HybRunStats(ctypes.Structure):
     _fields_ = [("infeasible", ctypes.c_int64), ("nonfinite", ctypes.c_int64), ("krylov_iters", ctypes.c_int32),
                 ("krylov_converged", ctypes.c_int32), ("krylov_relres", _d), ("coarse_steps", ctypes.c_int64),
-                ("fine_steps", ctypes.c_int64), ("overlap_depth", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("fine_steps", ctypes.c_int64), ("overlap_depth", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("mass", ctypes.c_double), ("min_f", ctypes.c_double), ("h_function", ctypes.c_double)]
 
 
 class Hyb1DParams(ctypes.Structure):
@@ -72,6 +73,7 @@ SIGNATURES = {
     "hyb_populations_device": (_i, [_P, _P]),
     "hyb_set_populations": (_i, [_P, _P]),
     "hyb_stats": (_i, [_P, _P]),
+    "hyb_diagnostics": (_i, [_P, _P, _i]),
     "hyb_layout": (_i, [_P, _P, _P]),
     "hyb_adjoint_query": (_i, [_P, _i, _P]),
     "hyb_lbm_substeps_record": (_i, [_P, _i, _P]),
@@ -219,7 +221,7 @@ class Hybrid:
                      outer_natural=kw.pop("outer_natural", cfg.outer_natural))
         return cls(N=cfg.N, x0=problem.x0, y0=problem.y0, u0=problem.u0_fine, vx=problem.vx, vy=problem.vy,
                    D=cfg.D, eta=kw.pop("eta", cfg.eta), precision=precision,
-                   tau=cfg.tau_value if tau is None else tau, solid=problem.solid, k=cfg.k,
+                   tau=(cfg.tau or 0.0) if tau is None else tau, solid=problem.solid, k=cfg.k,
                    k_field=kw.pop("k_field", problem.k_field),
                    bc_clamp=cfg.bc_clamp, mesh=m, **kw)
 
@@ -277,6 +279,19 @@ class Hybrid:
         s = HybRunStats()
         self._check(load().hyb_stats(self.h, ctypes.addressof(s)))
         return {k: getattr(s, k) for k, _ in HybRunStats._fields_}
+
+    def diagnostics(self, out=None):
+        """(mass, min f*, H, non-finite nodes) of the current fine state.
+        With ``out`` (a CUDA float64 tensor of >= 4 elements) the values are
+        written there on the handle's stream and nothing is returned."""
+        if out is not None:
+            if out.device.type != "cuda" or out.dtype != self.torch.float64 or out.numel() < 4:
+                raise ValueError("out must be a CUDA float64 tensor of at least 4 elements")
+            self._check(load().hyb_diagnostics(self.h, out.data_ptr(), 1))
+            return None
+        v = np.zeros(4)
+        self._check(load().hyb_diagnostics(self.h, v.ctypes.data, 0))
+        return {"mass": float(v[0]), "min_f": float(v[1]), "h_function": float(v[2]), "nonfinite": int(v[3])}
 
     # -- reverse mode of a whole coarse step ---------------------------------
     def step_tape(self, passes):

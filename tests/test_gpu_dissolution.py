@@ -188,11 +188,12 @@ def test_dissolution_invariants_at_pore4096_size():
 
 
 def test_dissolution_two_step_equals_single_step():
-    """The two-step sweep with link fluxes (steps in pairs, the second
-    step's fluxes from LDS) and the single-step sweep agree to rounding,
-    with identical conversions; hyb_step runs without overlap."""
+    """The multi-step sweeps with link fluxes (later steps' fluxes from LDS)
+    and the single-step sweep agree to rounding, with identical conversions;
+    hyb_step runs without overlap.  eta = 10 gives a different plan for each
+    setting: 10 x 1, 5 x 2, 3 + 3 + 2 + 2, 4 + 3 + 3, 5 + 5."""
     hyb, torch = _gpu()
-    p = configs.build_problem(configs.PORE2048.replace(N=193, M=16, eta=6))
+    p = configs.build_problem(configs.PORE2048.replace(N=193, M=16, eta=10))
     N = p.cfg.N
     mass = np.random.default_rng(8).uniform(0.002, 0.01, (N, N))
     out = []
@@ -209,6 +210,57 @@ def test_dissolution_two_step_equals_single_step():
     for o in out[1:]:
         assert np.array_equal(out[0][1], o[1]) and out[0][3] == o[3] > 0
         assert _rel(o[0], out[0][0]) <= 1e-13 and _rel(o[2], out[0][2]) <= 1e-13
+
+
+@pytest.mark.parametrize("precision,eta,spl,launches,tol", [
+    ("fp64", 10, 5, 2, 1e-12),     # 5 + 5
+    ("fp64", 20, 5, 4, 1e-12),     # 5 + 5 + 5 + 5, the plan of the 4096^2 workload
+    ("fp64", 10, 4, 3, 1e-12),     # 4 + 3 + 3
+    ("fp32", 20, 5, 4, 2e-5),
+    ("fp32", 10, 5, 2, 2e-5),
+])
+def test_dissolution_k_step_plans_match_oracle(orc, precision, eta, spl, launches, tol):
+    """The dissolving sweeps with four and five fine steps per launch (link
+    fluxes at solid nodes summed from LDS for the later steps): the launch
+    count confirms the plan; conversions, populations, coarse solution and
+    masses equal the oracle's dissolving step, and the single-step sweep's
+    run, after each of three coarse steps."""
+    from oracle.dissolution import DissolvingHybrid
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.PORE2048.replace(N=129, M=16, eta=eta))
+    N, P = p.cfg.N, p.cfg.max_iter
+    mass = np.random.default_rng(9).uniform(0.002, 0.01, (N, N))
+    kappa, c_sat = 0.2, 1.0
+    runs = {}
+    for k in (spl, 1):
+        g = hyb.Hybrid.from_problem(p, precision=precision, dissolution=True)
+        g.set_steps_per_launch(k)
+        g.set_dissolution(kappa, c_sat, mass)
+        g.kernel_timing(True)
+        states = []
+        for _ in range(3):
+            g.step(P)
+            sol, m, conv = g.dissolution_state()
+            states.append((g.get_populations(), g.concentration(hyb.HYB_COARSE).reshape(-1), sol, m, conv))
+        _, n_launch = g.kernel_time()
+        assert n_launch == 3 * P * (launches if k == spl else eta), (k, n_launch)
+        runs[k] = states
+        g.close()
+    o = DissolvingHybrid(p, mass, kappa_s=kappa, c_sat=c_sat)
+    if precision == "fp32":
+        o.fstar = o.fstar.astype(np.float32).astype(np.float64)
+    for s in range(3):
+        o.step()
+        F, d, sol, m, conv = runs[spl][s]
+        F1, d1, sol1, m1, conv1 = runs[1][s]
+        assert np.array_equal(sol, o.solid) and np.array_equal(sol1, sol), f"step {s}: solid sets differ"
+        assert conv == conv1 == o.converted
+        fluid = o.solid == 0
+        errs = {"f": _rel(F[:, fluid], o.fstar[:, fluid]), "d": _rel(d, o.d), "mass": _rel(m, o.mass),
+                "f_vs_single": _rel(F[:, fluid], F1[:, fluid]), "mass_vs_single": _rel(m, m1)}
+        print(f"\n{precision} eta {eta} spl {spl} step {s}: converted {conv} {errs}")
+        assert max(errs.values()) <= tol, errs
+    assert o.converted > 0
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-4)])

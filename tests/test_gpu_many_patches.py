@@ -23,7 +23,7 @@ def _rel(x, y):
 
 def _group(hyb, mp, precision):
     patches = [hyb.Hybrid(N=p.N, x0=p.x0, y0=p.y0, u0=p.u0_fine, vx=p.vx, vy=p.vy, D=mp.D, eta=mp.eta,
-                          precision=precision, tau=mp.tau_value, solid=p.solid, k=mp.k, bc_clamp=mp.bc_clamp)
+                          precision=precision, tau=0.0, solid=p.solid, k=mp.k, bc_clamp=mp.bc_clamp)
                for p in mp.patches]
     mesh = dict(M=mp.M, L=mp.L, outer_value=0.0, overlap_elems=mp.overlap_elems, supg=mp.supg, d0=mp.u0_coarse,
                 v=mp.vc)

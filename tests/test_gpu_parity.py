@@ -469,6 +469,25 @@ def test_coarse_solve_matches_direct(orc):
     assert rel_l2(g64.concentration(hyb.HYB_COARSE), ref) <= 1e-13
 
 
+@pytest.mark.parametrize("name,over,steps", [("small", {}, 20), ("pore2048", {"N": 129, "M": 16}, 6)])
+def test_library_derives_tau_from_D(orc, name, over, steps):
+    """The relaxation time comes from each side's own reading of Sec. 4.1:
+    the binding passes tau = 0, so hyb_create derives it from D, and the
+    oracle derives it from its lattice tables; the two runs agree to 1e-12."""
+    hyb = _gpu()
+    p = problem(name, **over)
+    assert p.cfg.tau is None
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    assert g.lat.tau == 0.0
+    for _ in range(steps):
+        g.step(p.cfg.max_iter)
+    o = _oracle_hybrid(orc, p, steps)
+    fluid = p.solid == 0
+    assert rel_l2(g.concentration(), o.fine_concentration(), fluid) <= 1e-12
+    assert rel_l2(g.concentration(hyb.HYB_COARSE), o.d) <= 1e-12
+    g.close()
+
+
 def test_hybrid_small_fp64_full_run(orc):
     """The 64^2 / 16^2 workload, all 100 coarse steps, FP64."""
     hyb = _gpu()

@@ -336,3 +336,35 @@ def test_gaussian_pulse_second_order(orc):
         errs.append(np.abs(lat.concentration(fs) - exact(T)).max())
     orders = np.log2(np.asarray(errs[:-1]) / np.asarray(errs[1:]))
     assert np.all((orders > 1.8) & (orders < 2.2)), orders
+
+
+@pytest.mark.parametrize("D,t1,t2", [(1e-2, 400, 600), (5e-3, 700, 900), (0.1, 60, 120)])
+def test_relaxation_time_gives_the_diffusion_coefficient(orc, D, t1, t2):
+    """Sec. 4.1 relates the relaxation time to the diffusion coefficient.
+    The oracle's own mapping tau(D) is checked against what the scheme does:
+    on a periodic box at rest, once the non-equilibrium start has decayed,
+    the spatial variance of a pulse grows by exactly 2 D per fine step (the
+    discrete second-moment balance).  A wrong mapping, e.g. D/c_s^2 with
+    c_s^2 = 1 or 1/2, is off by a factor of 3 or 1.5."""
+    tau = orc.relaxation_time(D)
+    N = 96
+    x = np.arange(N, dtype=np.float64)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = np.exp(-((X - 47.5) ** 2 + (Y - 47.5) ** 2) / (2 * 4.0 ** 2))
+    lat = _lattice(orc, N, tau)
+    fs = lat.init(u0)
+
+    def var_x(fs):
+        u = lat.concentration(fs)
+        m = u.sum()
+        cx = (u * X).sum() / m
+        return (u * (X - cx) ** 2).sum() / m
+
+    v = {}
+    for n in range(1, t2 + 1):
+        fs, _ = lat.substep(fs)
+        if n in (t1, t2):
+            v[n] = var_x(fs)
+    D_meas = (v[t2] - v[t1]) / (2.0 * (t2 - t1))
+    assert abs(D_meas / D - 1.0) < 1e-6, (D_meas, D, tau)
+    assert abs(orc.sound_speed_sq() - 1.0 / 3.0) < 1e-15
