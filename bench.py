@@ -653,6 +653,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision runs")
     ap.add_argument("--no-dissolution", action="store_true", help="skip the dissolving-solid workload")
+    ap.add_argument("--no-hybrid1d", action="store_true", help="skip the 1-D hybrid tables")
     ap.add_argument("--dissolution-only", action="store_true",
                     help="run only the dissolving-solid workload and print its record (for profiling)")
     ap.add_argument("--differentiation-only", action="store_true",
@@ -785,8 +786,9 @@ def main():
         res["step_adjoint"] = step_adjoint_rate(problem, args.precision)
         print("[bench] differentiation workload (diff512)", file=sys.stderr, flush=True)
         res["differentiation"] = differentiation()
-    print("[bench] 1-D hybrid tables", file=sys.stderr, flush=True)
-    res["hybrid1d"] = hybrid1d_tables()
+    if not args.no_hybrid1d:
+        print("[bench] 1-D hybrid tables", file=sys.stderr, flush=True)
+        res["hybrid1d"] = hybrid1d_tables()
     if not args.no_dissolution:
         print("[bench] dissolving solids (dissolve4096, fp32)", file=sys.stderr, flush=True)
         g.close()

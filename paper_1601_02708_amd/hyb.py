@@ -7,8 +7,11 @@ and the stream.  Importing this module does not need a GPU; creating a
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -111,6 +114,35 @@ SIGNATURES = {
 
 _LIB = None
 
+# Handles still open, closed by an exit hook before the interpreter and the
+# HIP runtime are torn down: a handle owns a HIP stream and events, and
+# destroying them after the runtime (or a profiler attached to it) has shut
+# down faults the process on its way out.  Groups close before the patch
+# handles they couple.
+_LIVE_GROUPS = weakref.WeakSet()
+_LIVE_HANDLES = weakref.WeakSet()
+_EXIT_HOOK = False
+
+
+def _close_live():
+    for objs in (_LIVE_GROUPS, _LIVE_HANDLES):
+        for o in list(objs):
+            try:
+                o.close()
+            except Exception:
+                pass
+
+
+def _track(obj, group=False):
+    global _EXIT_HOOK
+    if not _EXIT_HOOK:
+        # registered after torch's own hooks (torch is imported first), so it
+        # runs before them: Python runs exit hooks last-registered first
+        import torch  # noqa: F401
+        atexit.register(_close_live)
+        _EXIT_HOOK = True
+    (_LIVE_GROUPS if group else _LIVE_HANDLES).add(obj)
+
 
 class HybError(RuntimeError):
     def __init__(self, code, msg):
@@ -209,6 +241,7 @@ class Hybrid:
         if rc != HYB_OK:
             raise HybError(rc, "hyb_create failed (see stderr)")
         self.h = h
+        _track(self)
         self._keep.clear()
 
     @classmethod
@@ -426,6 +459,10 @@ class Hybrid:
             self.h = None
 
     def __del__(self):
+        # at interpreter shutdown the exit hook has closed every live handle;
+        # never call into the HIP runtime from a finaliser then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -695,6 +732,7 @@ class HybridGroup:
         if rc != HYB_OK:
             raise HybError(rc, "hyb_group_create failed (see stderr)")
         self.g = g
+        _track(self, group=True)
 
     def step(self, max_schwarz):
         rc = load().hyb_group_step(self.g, int(max_schwarz))
@@ -714,6 +752,10 @@ class HybridGroup:
             self.g = None
 
     def __del__(self):
+        # at interpreter shutdown the exit hook has closed every live handle;
+        # never call into the HIP runtime from a finaliser then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -764,6 +806,7 @@ class Hybrid1D:
         if rc != HYB_OK:
             raise HybError(rc, "hyb1d_create failed (see stderr)")
         self.h = h
+        _track(self)
         self.t = 0.0
 
     def run(self, n_steps):
@@ -787,6 +830,10 @@ class Hybrid1D:
             self.h = None
 
     def __del__(self):
+        # at interpreter shutdown the exit hook has closed every live handle;
+        # never call into the HIP runtime from a finaliser then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
