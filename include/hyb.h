@@ -239,6 +239,18 @@ int hyb_stats(hyb_handle *h, hyb_run_stats *out);
  * handle are serialised by its stream. */
 int hyb_diagnostics(hyb_handle *h, double *out, int out_is_device);
 
+/* hyb_diagnostics for callers that cannot allocate or synchronise (code
+ * under HIP graph capture, tight serving loops): the same kernels and
+ * results as hyb_diagnostics(h, out, 1), with the row partials in a static
+ * device array of the library instead of the handle's workspace.  out:
+ * device, 4 doubles as above; the call only enqueues work on the handle's
+ * stream and allocates nothing.  Limit: N <= 16384 (HYB_EINVAL beyond).
+ * The array is one per device and shared by every call on that device, so
+ * calls on one device whose work may overlap (several handles on different
+ * streams) race; serialise them.  Each call overwrites every partial it
+ * reads. */
+int hyb_diagnostics_noalloc(hyb_handle *h, double *out);
+
 /* ---- differentiation form (reverse mode) of the fine sub-steps ----------
  *
  * The fine step (Sec. 4.1: pull streaming with halfway bounce-back, the

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,32 @@ namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Scratch of hyb_diagnostics_noalloc: the row partials of the diagnostics
+// reduction for lattices of up to kNoAllocMaxRows rows.  Every device the
+// library runs on holds its own copy for the life of the process.  Host
+// code never passes `scratch` itself to a kernel (on the host it names a
+// stand-in, not device memory); it passes the device address that
+// hipGetSymbolAddress returned for the current device, kept per device.
+constexpr int kNoAllocMaxRows = 16384;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) double scratch[kDiagValues * kNoAllocMaxRows];
+namespace {
+std::mutex scratch_mu;
+double *scratch_ptr[kMaxDevices] = {};
+
+// Resolve the scratch's device address on `dev` (the current device), once.
+hipError_t scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_ptr[dev]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = static_cast<double *>(p);
+    return hipSuccess;
+}
 
 // Row pitch and plane stride (elements).  Rows start on 256-byte
 // boundaries; planes are skewed by 128 elements so the nine streams of a
@@ -174,6 +201,7 @@ struct hyb_handle {
     // problem
     int N = 0, M = 0, eta = 1, clamp = 0;
     int prec = HYB_FP64;                // population storage (HYB_FP64 / FP32 / FP16S)
+    int dev = 0;                        // device current at hyb_create
     bool fp64 = true, has_mesh = false, has_kfield = false;   // fp64: arithmetic type
     float hs_scale = 1.f, hs_inv = 1.f, hs_cref = 0.f;        // FP16S encoding
     std::vector<uint8_t> solid_host;    // [N*N] solid flags (readout zeroes solid nodes)
@@ -366,6 +394,11 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     }
     h->N = N;
     h->prec = lat->precision;
+    {
+        hipError_t e = hipGetDevice(&h->dev);
+        if (e == hipSuccess) e = scratch_setup(h->dev);
+        if (e != hipSuccess) return bail(HYB_EHIP, std::string("device set-up: ") + hipGetErrorString(e));
+    }
     // measured fastest per storage type at pore2048: FP32 5 (84 GLUPS with
     // pairs, 107 with fours, 112 with fives), FP64 4 (58 -> 69; five steps
     // leave one 83 KB workgroup per CU: 52), FP16 shifted storage 2 (it
@@ -1166,6 +1199,18 @@ int hyb_diagnostics(hyb_handle *h, double *out, int out_is_device) {
         HIP_TRY(h, hipMemcpyAsync(out, res, kDiagValues * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
     }
+    return HYB_OK;
+}
+
+int hyb_diagnostics_noalloc(hyb_handle *h, double *out) {
+    if (!h || !out) return HYB_EINVAL;
+    if (h->N > kNoAllocMaxRows)
+        return h->fail(HYB_EINVAL, "hyb_diagnostics_noalloc: the lattice has more rows than its static scratch "
+                                   "holds (N <= 16384)");
+    double *part = h->dev >= 0 && h->dev < kMaxDevices ? scratch_ptr[h->dev] : nullptr;
+    if (!part) return h->fail(HYB_EHIP, "hyb_diagnostics_noalloc: no scratch address for this device");
+    LbmArgs a = h->lbm_args(h->cur, -1);
+    HIP_TRY(h, launch_diagnostics(a, h->prec, part, out, h->stream));
     return HYB_OK;
 }
 

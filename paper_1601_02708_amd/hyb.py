@@ -77,6 +77,7 @@ SIGNATURES = {
     "hyb_set_populations": (_i, [_P, _P]),
     "hyb_stats": (_i, [_P, _P]),
     "hyb_diagnostics": (_i, [_P, _P, _i]),
+    "hyb_diagnostics_noalloc": (_i, [_P, _P]),
     "hyb_layout": (_i, [_P, _P, _P]),
     "hyb_adjoint_query": (_i, [_P, _i, _P]),
     "hyb_lbm_substeps_record": (_i, [_P, _i, _P]),
