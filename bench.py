@@ -77,8 +77,8 @@ def launch_plan(eta, steps_per_launch):
 
 def default_steps_per_launch(precision):
     """The library's default (hyb_set_steps_per_launch): 5 for FP32, 4 for
-    FP64, 2 for FP16 shifted storage."""
-    return {"fp32": 5, "fp64": 4, "fp16s": 2}[precision]
+    FP64, 4 for FP16 shifted storage."""
+    return {"fp32": 5, "fp64": 4, "fp16s": 4}[precision]
 
 
 def sweep_kernel(elem_bytes, take):

@@ -58,7 +58,10 @@ enum {
  * (round to nearest even), where c_ref is the mean of u0 over the fluid
  * nodes and 2^s the largest power of two with (4/9) U 2^s <= 16384,
  * U = max(1, max |u0 - c_ref|), both fixed at hyb_create; arithmetic in
- * FP32, closures in FP64.  Concentrations beyond about 4.5 U from c_ref
+ * FP32, closures in FP64; a sweep launch that takes several fine steps
+ * keeps its intermediate states in FP32 on chip and rounds to binary16 only
+ * when it stores, so results depend on the steps per launch to within a
+ * few binary16 roundings.  Concentrations beyond about 4.5 U from c_ref
  * overflow binary16 and are reported as non-finite (by the commit of the
  * coarse step whose fine steps read the overflowed value). */
 enum { HYB_FP64 = 0, HYB_FP32 = 1, HYB_FP16S = 2 };
@@ -101,6 +104,8 @@ typedef struct {
     void *stream;           /* hipStream_t for all work; NULL = default stream */
     int dissolution;        /* 1: reserve the workspace of dissolving solids
                                (hyb_set_dissolution); 0: solids are fixed */
+    int wall_closure;       /* 1: reserve the workspace of the maximum-entropy
+                               closure at solid walls (hyb_set_wall_normals) */
 } hyb_lattice;
 
 /* Advection velocity (divergence-free in the continuum, eq. AD). */
@@ -303,6 +308,10 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
  * hyb_step_adjoint: for the last record (tape pointer of that call; the
  *   handle may have committed that step since, but no later one):
  *   lam_f = dJ/df*(t_{n+1}) (device FP64 [9][N][N], index (q*N + j)*N + i),
+ *   lam_sub = the cotangent of every intermediate fine state of the
+ *   committed (last) pass, f*(t_n + j) for j = 1 .. eta-1 (same layout, or
+ *   NULL for none: an objective that integrates over every fine step
+ *   passes its per-state weight here and in lam_f),
  *   lam_d = dJ/dd^{n+1} (device FP64 [(M+1)^2], mesh node l*(M+1) + k, or
  *   NULL for zero); writes lam_f_out = dJ/df*(t_n) (may alias lam_f) and
  *   lam_d_out = dJ/dd^n; grad_k (device FP64 [N*N] or NULL) += dJ/dk of the
@@ -313,8 +322,8 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
  *   1e-14 relative residual. */
 int hyb_step_adjoint_query(const hyb_handle *h, int passes, size_t *tape_bytes);
 int hyb_step_record(hyb_handle *h, int passes, void *tape);
-int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_d, double *lam_f_out,
-                     double *lam_d_out, double *grad_k, double *grad_outer);
+int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_sub, const double *lam_d,
+                     double *lam_f_out, double *lam_d_out, double *grad_k, double *grad_outer);
 
 /* Overlap in hyb_step (default HYB_OVERLAP_AUTO): with multi-step
  * launches (hyb_set_steps_per_launch), the deep interior tiles of each
@@ -337,7 +346,7 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
 int hyb_set_overlap(hyb_handle *h, int depth);
 
 /* Most fine steps per lattice-sweep launch (1 to 5; default 5 for HYB_FP32,
- * 4 for HYB_FP64 and 2 for HYB_FP16S storage, the fastest measured for each).  With 2 or
+ * 4 for HYB_FP64 and HYB_FP16S storage, the fastest measured for each).  With 2 or
  * more, while every perimeter slot is Dirichlet, hyb_lbm_substeps takes fine
  * steps in temporally blocked launches (the state between the steps of one
  * launch stays on chip), never leaving a lone single step where it can be
@@ -346,12 +355,14 @@ int hyb_set_overlap(hyb_handle *h, int depth);
  * 6 starting with a three (eta = 10: 4 + 3 + 3); with 5, in fives,
  * remainders of 6, 7, 8 and 9 as 3 + 3, 4 + 3, 4 + 4 and 5 + 4 (eta = 10:
  * 5 + 5).  A remaining single step, and
- * every step when some slot is Neumann, or when a population buffer reaches
- * 4 GiB (the multi-step kernels use 32-bit byte offsets), uses the
- * single-step sweep.  Results agree with the single-step path to rounding
- * (same operations per node; pairs give its bits, and three- and four-step
- * launches FP64 states identical to pairs' and FP32 ones within a few ulp,
- * from the compiler's fusing of multiply-adds).  With 2 or more, hyb_lbm_adjoint and hyb_step_adjoint also reverse
+ * every step when some slot is Neumann, the wall closure is on, or a
+ * population buffer reaches 4 GiB (the multi-step kernels use 32-bit byte
+ * offsets), uses the single-step sweep.  Results agree with the single-step
+ * path to rounding (same operations per node; pairs give its bits, and
+ * three- to five-step launches FP64 states identical to pairs' and FP32
+ * ones within a few ulp, from the compiler's fusing of multiply-adds; FP16
+ * shifted storage rounds to binary16 once per launch instead of once per
+ * step).  With 2 or more, hyb_lbm_adjoint and hyb_step_adjoint also reverse
  * fine steps in pairs, one launch each (same bits as single reversed
  * steps).  Returns HYB_EINVAL for other values.  Takes effect at the next
  * hyb_lbm_substeps or adjoint call and restarts the overlap tuning of
@@ -410,6 +421,26 @@ int hyb_kernel_time(hyb_handle *h, double *total_ms, int64_t *launches);
  * (1 - k) factors enter dJ/dk); the conversion decision itself and the
  * masses are not differentiated (piecewise constant). */
 int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const double *mass);
+
+/* Maximum-entropy Neumann closure at the walls of the solid grains (Sec.
+ * 4.1.1, eq. LBM_Neu, with zero prescribed flux: an impermeable wall) in
+ * place of halfway bounce-back.  An interior fluid node (1 <= i, j <= N-2)
+ * with solid upstream nodes is a boundary point with normal n: all its
+ * populations with e_q.n < 0 (the set M- of the paper) become
+ * w_q exp(-1 - gamma e_q.n), gamma from an FP64 Newton solve of the flux
+ * condition sum_q (e_q.n) f_q = 0, and populations streamed from a solid
+ * node with e_q.n >= 0 (links the wall grazes) are bounced back.  No
+ * solution (the other populations carry no flux into the wall) sets M- to
+ * 0 and counts the node as infeasible.  Perimeter nodes keep their own
+ * closure.
+ * normals: host [2][N*N] FP32 (x plane, then y plane): the unit outward
+ * normal of the fluid domain (pointing into the solid) at every fluid node
+ * that has a solid neighbour, unit length within 1e-3, else HYB_EINVAL;
+ * other entries are ignored.  NULL switches back to bounce-back.  Needs
+ * hyb_lattice.wall_closure = 1 at creation and no pending fine steps; not
+ * with dissolving solids or the reverse mode (HYB_EINVAL).  Runs the
+ * single-step sweeps.  Synchronises. */
+int hyb_set_wall_normals(hyb_handle *h, const float *normals);
 int hyb_dissolution_state(hyb_handle *h, uint8_t *solid, double *mass, int64_t *converted);
 int hyb_set_solids(hyb_handle *h, const uint8_t *solid, const double *mass);
 

@@ -33,7 +33,8 @@ class OrcLattice(ctypes.Structure):
     _fields_ = [("N", c_int), ("periodic_x", c_int), ("periodic_y", c_int),
                 ("tau", c_double), ("solid", c_void_p), ("vx", c_void_p), ("vy", c_void_p),
                 ("k", c_void_p), ("kval", c_double), ("bc_kind", c_void_p), ("clamp", c_int),
-                ("kappa_s", c_double), ("c_sat", c_double), ("work_f", c_void_p), ("work_unknown", c_void_p)]
+                ("kappa_s", c_double), ("c_sat", c_double), ("work_f", c_void_p), ("work_unknown", c_void_p),
+                ("wall_nx", c_void_p), ("wall_ny", c_void_p)]
 
 
 def lib():
@@ -56,6 +57,8 @@ def lib():
             "orc_stream": (None, [P, P, P, P]),
             "orc_maxent_dirichlet": (c_int, [P, ctypes.c_uint, c_double, c_int]),
             "orc_maxent_neumann": (c_int, [P, ctypes.c_uint, c_int, c_int, c_double, P]),
+            "orc_maxent_neumann_normal": (c_int, [P, ctypes.c_uint, c_double, c_double, c_double, P]),
+            "orc_apply_wall_closure": (c_long, [P, P, P]),
             "orc_apply_bc": (c_long, [P, P, P, P, P]),
             "orc_collide": (None, [P, P, P]),
             "orc_lbm_substep": (c_long, [P, P, P, P]),
@@ -150,6 +153,14 @@ def maxent_neumann(f, unknown: int, sx: int, sy: int, qp: float, fstar_self):
     return f, int(inf)
 
 
+def maxent_neumann_normal(f, unknown: int, nx: float, ny: float, qp: float, fstar_self):
+    """eq. (LBM_Neu) for a real unit outward normal (nx, ny)."""
+    f = _f64(f).copy()
+    fs = _f64(fstar_self)
+    inf = lib().orc_maxent_neumann_normal(_p(f), int(unknown), float(nx), float(ny), float(qp), _p(fs))
+    return f, int(inf)
+
+
 def perimeter_slot(N, i, j):
     return lib().orc_perimeter_slot(N, i, j)
 
@@ -175,7 +186,7 @@ class Lattice:
     """An N x N D2Q9 lattice with its fields (all FP64 on the host)."""
 
     def __init__(self, N, tau, vx, vy, solid=None, k=0.0, bc_kind=None,
-                 periodic_x=False, periodic_y=False, clamp=False, kappa_s=0.0, c_sat=0.0):
+                 periodic_x=False, periodic_y=False, clamp=False, kappa_s=0.0, c_sat=0.0, wall_normals=None):
         self.N = int(N)
         self.tau = float(tau)
         self.vx = _f64(vx).reshape(N, N)
@@ -186,13 +197,22 @@ class Lattice:
         else:
             self.kfield, self.kval = _f64(k).reshape(N, N), 0.0
         self.bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, dtype=np.int8)
+        # wall_normals: [2, N, N] unit outward normals of the fluid domain
+        # at solid walls (the maximum-entropy zero-flux closure replaces
+        # bounce-back there), or None
+        if wall_normals is None:
+            self.wall_nx = self.wall_ny = None
+        else:
+            wn = _f64(wall_normals).reshape(2, N, N)
+            self.wall_nx, self.wall_ny = np.ascontiguousarray(wn[0]), np.ascontiguousarray(wn[1])
         # scratch of one step, allocated once per lattice (no values carry
         # over between steps)
         self._work_f = np.empty((9, self.N, self.N))
         self._work_unknown = np.empty((self.N, self.N), np.uint16)
         self.s = OrcLattice(self.N, int(periodic_x), int(periodic_y), self.tau, _p(self.solid),
                             _p(self.vx), _p(self.vy), _p(self.kfield), self.kval, _p(self.bc_kind),
-                            int(clamp), float(kappa_s), float(c_sat), _p(self._work_f), _p(self._work_unknown))
+                            int(clamp), float(kappa_s), float(c_sat), _p(self._work_f), _p(self._work_unknown),
+                            _p(self.wall_nx), _p(self.wall_ny))
         self.kappa_s, self.c_sat = float(kappa_s), float(c_sat)
 
     @property

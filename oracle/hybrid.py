@@ -67,7 +67,8 @@ def algorithm1_step(h):
 class HybridOracle:
     """State and steps of the two-subdomain hybrid method on the host."""
 
-    def __init__(self, problem, tau=None, eta=None, max_iter=None, outer_value=None, outer_natural=None):
+    def __init__(self, problem, tau=None, eta=None, max_iter=None, outer_value=None, outer_natural=None,
+                 wall_normals=None):
         cfg = problem.cfg
         self.p = problem
         self.N, self.M, self.L = cfg.N, cfg.M, problem.L
@@ -79,8 +80,10 @@ class HybridOracle:
         outer_value = cfg.outer_value if outer_value is None else outer_value
         outer_natural = cfg.outer_natural if outer_natural is None else outer_natural
         kfine = cfg.k if getattr(problem, "k_field", None) is None else problem.k_field
+        # wall_normals: maximum-entropy zero-flux closure at the grains' walls
+        # with these unit outward normals ([2, N, N]) instead of bounce-back
         self.lat = Lattice(self.N, tau, problem.vx.astype(np.float64), problem.vy.astype(np.float64),
-                           solid=problem.solid, k=kfine, clamp=cfg.bc_clamp)
+                           solid=problem.solid, k=kfine, clamp=cfg.bc_clamp, wall_normals=wall_normals)
         self.outer, self.fc = coarse_dirichlet_sets(self.M, self.L, self.N, problem.x0, problem.y0,
                                                     cfg.overlap_elems, outer_natural)
         rows = np.sort(np.concatenate([self.outer, self.fc]))

@@ -207,11 +207,14 @@ class HybridStepAdjoint:
             ufc_src = states[-1]
         return ufc_src, d1, tape
 
-    def adjoint(self, tape, lam_f, lam_d, outer=False):
+    def adjoint(self, tape, lam_f, lam_d, outer=False, lam_sub=None):
         """(dJ/dF, dJ/dd^n, dJ/dk) for cotangents lam_f = dJ/df*(t_{n+1})
         [9,N,N] and lam_d = dJ/dd^{n+1} [(M+1)^2]; with outer, also dJ/dg
         for the prescribed values g of the outer-edge Dirichlet rows (per
-        mesh node, zero elsewhere)."""
+        mesh node, zero elsewhere).  lam_sub [9,N,N]: J also holds
+        <lam_sub, f*(t_n + j)> for every intermediate fine state j = 1 ..
+        eta-1 of the committed (last) pass, so an objective can integrate
+        over every fine step."""
         o = self.o
         N = o.N
         # a tape may carry the lattice, transfer rows and fluid set of its
@@ -232,6 +235,8 @@ class HybridStepAdjoint:
                 lt = j / o.eta
                 up = (1 - lt) * rec["a"] + lt * rec["b"]
                 lam, gbc, kk = lat.adjoint_substep(rec["states"][j - 1], up, lam)
+                if lam_sub is not None and p == len(passes) - 1 and j - 1 >= 1:
+                    lam = lam + lam_sub
                 ga += (1 - lt) * gbc
                 gb += lt * gbc
                 gk += kk

@@ -89,6 +89,8 @@ typedef struct {
     double c_sat;                /* concentration the surface reaction drives towards */
     double *work_f;              /* [9*N*N] scratch of orc_lbm_substep, or NULL (allocated per call) */
     uint16_t *work_unknown;      /* [N*N] scratch of orc_lbm_substep, or NULL */
+    const double *wall_nx;       /* [N*N] unit outward normal of the fluid domain at solid walls */
+    const double *wall_ny;       /*   (towards the solid), or NULL: halfway bounce-back at walls */
 } orc_lattice;
 
 static int is_solid(const orc_lattice *L, int n) { return L->solid && L->solid[n]; }
@@ -233,17 +235,19 @@ static double neumann_lhs(const double *a, unsigned set, double gamma) {
     return s;
 }
 
-int orc_maxent_neumann(double *f, unsigned unknown, int sx, int sy, double qp,
-                       const double *fstar_self) {
-    double nrm = sqrt((double)(sx * sx + sy * sy));
+/* The same closure for any unit outward normal (nx, ny): unknowns with
+ * e_i.n < 0 are the maxent unknowns, the other unknowns (e_i.n >= 0, e.g.
+ * the tangential ones at a corner or where a curved wall grazes a link)
+ * are bounced back from the node's own post-collision populations. */
+int orc_maxent_neumann_normal(double *f, unsigned unknown, double nx, double ny, double qp,
+                              const double *fstar_self) {
     double a[9];
     unsigned mminus = 0;
     for (int q = 0; q < 9; ++q) {
-        int dot = EX[q] * sx + EY[q] * sy;
-        a[q] = dot / nrm;
+        a[q] = EX[q] * nx + EY[q] * ny;
         if (unknown & (1u << q)) {
-            if (dot < 0) mminus |= 1u << q;
-            else f[q] = fstar_self[OPP[q]];          /* tangential unknown at a corner */
+            if (a[q] < 0.0) mminus |= 1u << q;
+            else f[q] = fstar_self[OPP[q]];
         }
     }
     double rhs = qp;
@@ -266,6 +270,49 @@ int orc_maxent_neumann(double *f, unsigned unknown, int sx, int sy, double qp,
     for (int q = 0; q < 9; ++q)
         if (mminus & (1u << q)) f[q] = WT[q] * exp(-1.0 - gamma * a[q]);
     return 0;
+}
+
+/* Patch-edge form: outward direction (sx, sy), components in {-1, 0, 1}. */
+int orc_maxent_neumann(double *f, unsigned unknown, int sx, int sy, double qp,
+                       const double *fstar_self) {
+    double nrm = sqrt((double)(sx * sx + sy * sy));
+    return orc_maxent_neumann_normal(f, unknown, sx / nrm, sy / nrm, qp, fstar_self);
+}
+
+/* Maximum-entropy Neumann closure at solid walls, eq. (LBM_Neu) with
+ * q^p = 0 (an impermeable wall), in place of halfway bounce-back: every
+ * interior fluid node (1 <= i, j <= N-2) with a solid upstream node is a
+ * boundary point with the wall's unit outward normal (wall_nx, wall_ny).
+ * Its unknowns are the set M- of the paper, all populations with
+ * e_i.n < 0, whether their upstream node is solid or fluid; populations
+ * streamed from a solid node with e_i.n >= 0 (links the wall grazes) are
+ * bounced back.  Runs after streaming, which left the bounce-back values
+ * in f.  Returns the number of infeasible nodes. */
+long orc_apply_wall_closure(const orc_lattice *L, const double *fstar, double *f) {
+    int N = L->N;
+    size_t NN = (size_t)N * N;
+    long infeasible = 0;
+    if (!L->wall_nx || !L->wall_ny || !L->solid) return 0;
+    for (int j = 1; j < N - 1; ++j) {
+        for (int i = 1; i < N - 1; ++i) {
+            int n = j * N + i;
+            if (is_solid(L, n)) continue;
+            unsigned unknown = 0;
+            for (int q = 1; q < 9; ++q)
+                if (is_solid(L, (j - EY[q]) * N + (i - EX[q]))) unknown |= 1u << q;
+            if (!unknown) continue;
+            for (int q = 1; q < 9; ++q)
+                if (EX[q] * L->wall_nx[n] + EY[q] * L->wall_ny[n] < 0.0) unknown |= 1u << q;
+            double fn[9], fs[9];
+            for (int q = 0; q < 9; ++q) {
+                fn[q] = f[q * NN + n];
+                fs[q] = fstar[q * NN + n];
+            }
+            infeasible += orc_maxent_neumann_normal(fn, unknown, L->wall_nx[n], L->wall_ny[n], 0.0, fs);
+            for (int q = 0; q < 9; ++q) f[q * NN + n] = fn[q];
+        }
+    }
+    return infeasible;
 }
 
 /* Apply the boundary closures at every perimeter node that has unknowns.
@@ -332,7 +379,8 @@ long orc_lbm_substep(const orc_lattice *L, const double *fsrc, double *fdst, con
     double *f = L->work_f ? L->work_f : (double *)malloc(9 * NN * sizeof(double));
     uint16_t *unknown = L->work_unknown ? L->work_unknown : (uint16_t *)malloc(NN * sizeof(uint16_t));
     orc_stream(L, fsrc, f, unknown);
-    long inf = orc_apply_bc(L, fsrc, f, unknown, bc_value);
+    long inf = orc_apply_wall_closure(L, fsrc, f);
+    inf += orc_apply_bc(L, fsrc, f, unknown, bc_value);
     orc_collide(L, f, fdst);
     if (!L->work_f) free(f);
     if (!L->work_unknown) free(unknown);
@@ -392,6 +440,7 @@ int orc_lbm_adjoint_substep(const orc_lattice *L, const double *fsrc, const doub
                             const double *lam_in, double *lam_out, double *grad_bc, double *grad_k) {
     int N = L->N;
     size_t NN = (size_t)N * N;
+    if (L->wall_nx) return -1;
     if (L->bc_kind)
         for (int p = 0; p < 4 * (N - 1); ++p)
             if (L->bc_kind[p] != 0) return -1;

@@ -121,6 +121,7 @@ class Problem:
     y0: float
     L: float
     k_field: Optional[np.ndarray] = None    # float64 [N, N] per-node fine rate, or None (uniform cfg.k)
+    pack: Optional[inputs.DiskPack] = None   # the grains (patch lattice coordinates), or None
 
 
 def build_problem(cfg: HybridConfig) -> Problem:
@@ -135,6 +136,7 @@ def build_problem(cfg: HybridConfig) -> Problem:
         solid = pack.solid
         porosity = pack.porosity
     else:
+        pack = None
         solid = np.zeros((N, N), dtype=np.uint8)
         porosity = 1.0
 
@@ -175,7 +177,7 @@ def build_problem(cfg: HybridConfig) -> Problem:
     k_field = None if cfg.k_field_max is None else inputs.reaction_field(N, cfg.seed + 4000, cfg.k_field_max)
     return Problem(cfg=cfg, solid=solid, vx=vx, vy=vy, vc=np.ascontiguousarray(vc), k_field=k_field,
                    u0_fine=u0_fine, u0_coarse=u0_coarse, porosity=porosity,
-                   x0=x0, y0=x0, L=L)
+                   x0=x0, y0=x0, L=L, pack=pack)
 
 
 # ----------------------------------------------------------------------------

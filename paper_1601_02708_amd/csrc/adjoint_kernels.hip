@@ -139,11 +139,14 @@ __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *
 // outside: it pulled nothing from y) + (1 - kappa_s) nu_q(y), q = opp(p),
 // when y bounced back along q (kappa_s: surface reaction of dissolving
 // solids, 0 when off).
+// inj (or null): a cotangent added to the output at fluid nodes (an
+// objective that also reads the state the output belongs to).
 template <typename T, int TW, int TH, int NT>
 __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__restrict__ snext,
                                                       const T *__restrict__ lam, T *__restrict__ out,
                                                       double *__restrict__ grad_a, double *__restrict__ grad_b,
-                                                      double *__restrict__ grad_k, int tiles_x) {
+                                                      double *__restrict__ grad_k, int tiles_x,
+                                                      const T *__restrict__ inj) {
     constexpr int W1 = TW + 2, H1 = TH + 2;
     __shared__ T nus[kQ][H1][W1];
     const int N = a.N, P = a.pitch;
@@ -182,6 +185,7 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
             T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
             const int q = kOpp[p];
             if ((m >> q) & 1u) acc += keep * nus[q][ly][lx];
+            if (inj) acc += inj[p * plane + n];
             out[p * plane + n] = acc;
         }
     }
@@ -197,13 +201,15 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
 // the single reversed step's operations (dJ/df*(t) never leaves the chip),
 // so the result equals two adj_step_kernel launches; gradients are added by
 // the owner of each node once per step, the two steps separated by a
-// barrier.
+// barrier.  inj_mid, inj_out (or null): cotangents added at fluid nodes to
+// dJ/df*(t) (on chip) and to the output dJ/df*(t-1).
 template <typename T, int TW, int TH, int NT>
 __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, const T *__restrict__ snext1,
                                                        const T *__restrict__ snext2, const T *__restrict__ lam,
                                                        T *__restrict__ out, double *__restrict__ grad_a,
                                                        double *__restrict__ grad_b, double *__restrict__ grad_k,
-                                                       int tiles_x) {
+                                                       int tiles_x, const T *__restrict__ inj_mid,
+                                                       const T *__restrict__ inj_out) {
     constexpr int W2 = TW + 4, H2 = TH + 4, W1 = TW + 2, H1 = TH + 2;
     constexpr int R1 = (W1 * H1 + NT - 1) / NT;
     __shared__ T nus[kQ][H2][W2];
@@ -246,6 +252,7 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
             T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
             const int q = kOpp[p];
             if ((m >> q) & 1u) acc += keep * nus[q][ly][lx];
+            if (inj_mid) acc += inj_mid[p * plane + n];
             l[p] = acc;
         }
         const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
@@ -279,6 +286,7 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
             T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
             const int q = kOpp[p];
             if ((m >> q) & 1u) acc += keep2 * nus[q][ly][lx];
+            if (inj_out) acc += inj_out[p * plane + n];
             out[p * plane + n] = acc;
         }
     }
@@ -315,24 +323,25 @@ __global__ void __launch_bounds__(256) adj_unpack_kernel(LbmArgs a, const T *__r
 
 template <typename T>
 hipError_t adjoint_step_impl(const LbmArgs &a, const void *snext, const void *lam, void *out, double *grad_a,
-                             double *grad_b, double *grad_k, hipStream_t s) {
+                             double *grad_b, double *grad_k, const void *inj, hipStream_t s) {
     constexpr int TW = 64, TH = 8, NT = 256;
     const int tiles_x = (a.N + TW - 1) / TW, tiles_y = (a.N + TH - 1) / TH;
     hipLaunchKernelGGL((adj_step_kernel<T, TW, TH, NT>), dim3(tiles_x * tiles_y), dim3(NT), 0, s, a,
                        static_cast<const T *>(snext), static_cast<const T *>(lam), static_cast<T *>(out), grad_a,
-                       grad_b, grad_k, tiles_x);
+                       grad_b, grad_k, tiles_x, static_cast<const T *>(inj));
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t adjoint_step2_impl(const LbmArgs &a1, const LbmArgs &a2, const void *snext1, const void *snext2,
                               const void *lam, void *out, double *grad_a, double *grad_b, double *grad_k,
-                              hipStream_t s) {
+                              const void *inj_mid, const void *inj_out, hipStream_t s) {
     constexpr int TW = 64, TH = 8, NT = 256;
     const int tiles_x = (a1.N + TW - 1) / TW, tiles_y = (a1.N + TH - 1) / TH;
     hipLaunchKernelGGL((adj_step2_kernel<T, TW, TH, NT>), dim3(tiles_x * tiles_y), dim3(NT), 0, s, a1, a2,
                        static_cast<const T *>(snext1), static_cast<const T *>(snext2), static_cast<const T *>(lam),
-                       static_cast<T *>(out), grad_a, grad_b, grad_k, tiles_x);
+                       static_cast<T *>(out), grad_a, grad_b, grad_k, tiles_x, static_cast<const T *>(inj_mid),
+                       static_cast<const T *>(inj_out));
     return hipGetLastError();
 }
 
@@ -340,16 +349,18 @@ hipError_t adjoint_step2_impl(const LbmArgs &a1, const LbmArgs &a2, const void *
 
 hipError_t launch_adjoint_step2(const LbmArgs &a1, const LbmArgs &a2, int prec, const void *snext1,
                                 const void *snext2, const void *lam, void *out, double *grad_a, double *grad_b,
-                                double *grad_k, hipStream_t s) {
-    if (prec == HYB_FP64) return adjoint_step2_impl<double>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, s);
-    return adjoint_step2_impl<float>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, s);
+                                double *grad_k, hipStream_t s, const void *inj_mid, const void *inj_out) {
+    if (prec == HYB_FP64)
+        return adjoint_step2_impl<double>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, inj_mid, inj_out,
+                                          s);
+    return adjoint_step2_impl<float>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, inj_mid, inj_out, s);
 }
 
 hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
-                               double *grad_a, double *grad_b, double *grad_k, hipStream_t s) {
+                               double *grad_a, double *grad_b, double *grad_k, hipStream_t s, const void *inj) {
     (void)nu;    // scratch of the two-kernel form; the fused kernel keeps nu in LDS
-    if (prec == HYB_FP64) return adjoint_step_impl<double>(a, snext, lam, out, grad_a, grad_b, grad_k, s);
-    return adjoint_step_impl<float>(a, snext, lam, out, grad_a, grad_b, grad_k, s);
+    if (prec == HYB_FP64) return adjoint_step_impl<double>(a, snext, lam, out, grad_a, grad_b, grad_k, inj, s);
+    return adjoint_step_impl<float>(a, snext, lam, out, grad_a, grad_b, grad_k, inj, s);
 }
 
 hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,

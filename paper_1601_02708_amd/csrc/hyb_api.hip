@@ -112,6 +112,10 @@ struct Layout {
     // and solid flag; raw fine-to-coarse corners and fallbacks
     bool dissolve = false;
     size_t mass = 0, flux = 0, solid_now = 0, fcr_idx = 0, fcr_w = 0, fcr_fb = 0;
+    // maximum-entropy closure at solid walls (hyb_lattice.wall_closure):
+    // the wall normal's two FP32 planes
+    bool wall = false;
+    size_t wall_nx = 0, wall_ny = 0;
     size_t f2cD_node = 0, f2cD_ptr = 0, f2cD_c = 0, f2cD_m = 0;
     int n = 0, S = 0, grid = 0;
     size_t vec_len = 0;
@@ -142,6 +146,11 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
     L.counters = take(kCntSlots * 8);
     L.kres = take(sizeof(KrylovResult));
     L.diag = take(((size_t)kDiagValues * N + kDiagValues) * 8);   // row partials, then the result
+    if (lat->wall_closure) {
+        L.wall = true;
+        L.wall_nx = take(nodes * 4);
+        L.wall_ny = take(nodes * 4);
+    }
     if (lat->dissolution) {
         L.dissolve = true;
         L.mass = take(nodes * 8);
@@ -219,6 +228,9 @@ struct hyb_handle {
     double *bc_a = nullptr, *bc_b = nullptr;
     bool kinds_set = false;
     bool any_neumann = false;
+    // maximum-entropy zero-flux closure at solid walls (hyb_set_wall_normals)
+    bool wall_ws = false, wall_on = false;
+    float *wall_nx = nullptr, *wall_ny = nullptr;
     int steps_per_launch = 4;          // most fine steps per sweep launch (fuse_steps)
     const void *rec_tape = nullptr;     // last forward recording (hyb_lbm_substeps_record)
     int rec_n = 0;
@@ -333,6 +345,8 @@ struct hyb_handle {
         a.flux = nullptr;
         a.flux_first = 0;
         a.mid = nullptr;
+        a.wall_nx = wall_on ? wall_nx : nullptr;
+        a.wall_ny = wall_on ? wall_ny : nullptr;
         return a;
     }
     // buffer that is neither the committed state nor `a`
@@ -401,10 +415,10 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     }
     // measured fastest per storage type at pore2048: FP32 5 (84 GLUPS with
     // pairs, 107 with fours, 112 with fives), FP64 4 (58 -> 69; five steps
-    // leave one 83 KB workgroup per CU: 52), FP16 shifted storage 2 (it
-    // decodes and encodes every value, its sweeps are bound by instruction
-    // issue: 81.7, 80.5, 77.3 GLUPS at 2, 3, 4)
-    h->steps_per_launch = lat->precision == HYB_FP16S ? 2 : lat->precision == HYB_FP64 ? 4 : 5;
+    // leave one 83 KB workgroup per CU: 52), FP16 shifted storage 4 (its
+    // launches keep FP32 intermediates on chip: 82.4, 83.7, 88.9, 87.2 GLUPS
+    // at 2, 3, 4, 5)
+    h->steps_per_launch = lat->precision == HYB_FP16S ? 4 : lat->precision == HYB_FP64 ? 4 : 5;
     h->fp64 = lat->precision == HYB_FP64;
     h->tau = tau;
     h->omega = 1.0 / tau;
@@ -497,6 +511,11 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     h->counters = reinterpret_cast<unsigned long long *>(h->ws + L.counters);
     h->kres = reinterpret_cast<KrylovResult *>(h->ws + L.kres);
     h->diag = reinterpret_cast<double *>(h->ws + L.diag);
+    if (L.wall) {
+        h->wall_ws = true;
+        h->wall_nx = reinterpret_cast<float *>(h->ws + L.wall_nx);
+        h->wall_ny = reinterpret_cast<float *>(h->ws + L.wall_ny);
+    }
     if (L.dissolve) {
         h->dissolve_ws = true;
         h->mass = reinterpret_cast<double *>(h->ws + L.mass);
@@ -718,7 +737,7 @@ namespace {
 // offsets, so it serves buffers below 4 GiB (N up to about 11500 in FP64)
 bool use_two_step(const hyb_handle *h) {
     const bool small_buf = 9.0 * (double)h->lay.plane * (double)storage_bytes(h->prec) < 4294967295.0;
-    return !h->any_neumann && h->steps_per_launch >= 2 && small_buf;
+    return !h->any_neumann && !h->wall_on && h->steps_per_launch >= 2 && small_buf;
 }
 
 // Most fine steps one launch of the forward sub-stepping takes: the
@@ -809,7 +828,7 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, int deep
     // path brackets each interior kernel alone (its perimeter kernel follows
     // it)
     const bool timed = h->timing && h->N > 2 && n_sub > 0;
-    const bool general = h->any_neumann;
+    const bool general = h->any_neumann || h->wall_on;
     const int fuse = fuse_steps(h);
     auto take_pair = [&](hipEvent_t *e0, hipEvent_t *e1) -> hipError_t {
         if (2 * (h->ev_used + 1) > h->ev_pool.size()) {
@@ -1249,6 +1268,7 @@ int hyb_adjoint_query(const hyb_handle *h, int n_sub, size_t *tape_bytes) {
 }
 
 int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
+    if (h && h->wall_on) return h->fail(HYB_EINVAL, "the adjoint supports bounce-back walls only");
     if (!h) return HYB_EINVAL;
     if (h->prec == HYB_FP16S) return h->fail(HYB_EINVAL, "the adjoint supports HYB_FP64 and HYB_FP32 storage");
     if (h->any_neumann) return h->fail(HYB_EINVAL, "the adjoint supports Dirichlet perimeter slots only");
@@ -1372,6 +1392,7 @@ int step_adjoint_supported(hyb_handle *h) {
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "the step adjoint needs a coarse mesh");
     if (h->prec == HYB_FP16S) return h->fail(HYB_EINVAL, "the adjoint supports HYB_FP64 and HYB_FP32 storage");
     if (h->any_neumann) return h->fail(HYB_EINVAL, "the adjoint supports Dirichlet perimeter slots only");
+    if (h->wall_on) return h->fail(HYB_EINVAL, "the adjoint supports bounce-back walls only");
     return HYB_OK;
 }
 
@@ -1457,8 +1478,8 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
     return rc;
 }
 
-int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_d, double *lam_f_out,
-                     double *lam_d_out, double *grad_k, double *grad_outer) {
+int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const double *lam_sub, const double *lam_d,
+                     double *lam_f_out, double *lam_d_out, double *grad_k, double *grad_outer) {
     if (!h) return HYB_EINVAL;
     int rc = step_adjoint_supported(h);
     if (rc != HYB_OK) return rc;
@@ -1491,6 +1512,14 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
                                                state(passes - 1, h->eta), lcur, static_cast<double *>(nu), grad_k,
                                                h->stream));
     }
+    // the cotangent of the committed pass's intermediate fine states, in the
+    // storage layout (nu is free from here on: the fused reversed steps keep
+    // their nu on chip)
+    const void *inj = nullptr;
+    if (lam_sub) {
+        HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_sub, nu, true, h->stream));
+        inj = nu;
+    }
     HIP_TRY(h, hipMemsetAsync(lam_f_out, 0, dense_bytes, h->stream));
     // the padded coarse vectors keep a zero halo (stencils read it)
     HIP_TRY(h, hipMemsetAsync(base + T.coarse, 0, 4 * vs, h->stream));
@@ -1502,6 +1531,10 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
         HIP_TRY(h, hipMemsetAsync(ga, 0, 2 * nslots * 8, h->stream));
         a.bc_a = bc;
         a.bc_b = bc + (1 + p) * nslots;
+        // the committed pass's intermediate states t = 1 .. eta-1 take the
+        // substep cotangent (state eta takes lam_f, state 0 belongs to the
+        // previous coarse step)
+        const void *inj_p = p == passes - 1 ? inj : nullptr;
         for (int t = h->eta; t >= 1;) {
             if (h->steps_per_launch >= 2 && t >= 2) {
                 // steps t and t-1 reversed in one launch
@@ -1511,12 +1544,13 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
                 a2.src = state(p, t - 2);
                 a2.lam = (double)(t - 1) / (double)h->eta;
                 HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, state(p, t), state(p, t - 1), lcur, lnext, ga, gb,
-                                                grad_k, h->stream));
+                                                grad_k, h->stream, inj_p, t - 2 >= 1 ? inj_p : nullptr));
                 t -= 2;
             } else {
                 a.src = state(p, t - 1);
                 a.lam = (double)t / (double)h->eta;
-                HIP_TRY(h, launch_adjoint_step(a, h->prec, state(p, t), lcur, nu, lnext, ga, gb, grad_k, h->stream));
+                HIP_TRY(h, launch_adjoint_step(a, h->prec, state(p, t), lcur, nu, lnext, ga, gb, grad_k, h->stream,
+                                               t - 1 >= 1 ? inj_p : nullptr));
                 t -= 1;
             }
             std::swap(lcur, lnext);
@@ -1607,6 +1641,45 @@ void hyb_destroy(hyb_handle *h) { delete h; }
 
 const char *hyb_last_error(const hyb_handle *h) { return h ? h->err.c_str() : "null handle"; }
 
+int hyb_set_wall_normals(hyb_handle *h, const float *normals) {
+    if (!h) return HYB_EINVAL;
+    if (!h->wall_ws) return h->fail(HYB_EINVAL, "the handle was created without the wall closure");
+    if (h->jsub != 0 || h->cur != h->frozen)
+        return h->fail(HYB_EINVAL, "set the wall closure between coarse steps (fine steps are pending)");
+    if (!normals) {
+        h->wall_on = false;
+        return HYB_OK;
+    }
+    if (h->dissolve_on) return h->fail(HYB_EINVAL, "dissolving solids need bounce-back walls");
+    if (refresh_solid_host(h) != hipSuccess) return h->fail(HYB_EHIP, "could not read the solid flags");
+    const int N = h->N, P = h->lay.pitch;
+    const size_t NN = (size_t)N * N;
+    std::vector<float> nx((size_t)N * P, 0.f), ny((size_t)N * P, 0.f);
+    auto solid = [&](int i, int j) { return h->solid_host[(size_t)j * N + i] != 0; };
+    for (int j = 1; j < N - 1; ++j)
+        for (int i = 1; i < N - 1; ++i) {
+            if (solid(i, j)) continue;
+            bool wall = false;
+            for (int q = 1; q < kQ; ++q) wall = wall || solid(i - kCx[q], j - kCy[q]);
+            if (!wall) continue;
+            const float x = normals[(size_t)j * N + i], y = normals[NN + (size_t)j * N + i];
+            const double len = std::sqrt((double)x * x + (double)y * y);
+            if (!std::isfinite(len) || std::fabs(len - 1.0) > 1e-3)
+                return h->fail(HYB_EINVAL, "every fluid node next to a solid needs a unit wall normal");
+            nx[(size_t)j * P + i] = x;
+            ny[(size_t)j * P + i] = y;
+        }
+    HIP_TRY(h, hipMemcpyAsync(h->wall_nx, nx.data(), nx.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->wall_ny, ny.data(), ny.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->wall_on = true;
+    // the sweeps change (single steps, no overlap), so the depth is tuned again
+    h->tune_idx = 0;
+    h->tuned_depth = -1;
+    h->tune_ms.clear();
+    return HYB_OK;
+}
+
 int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const double *mass) {
     if (!h) return HYB_EINVAL;
     if (!h->dissolve_ws) return h->fail(HYB_EINVAL, "the handle was created without dissolution");
@@ -1614,6 +1687,8 @@ int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const doubl
     if (!std::isfinite(c_sat)) return h->fail(HYB_EINVAL, "c_sat must be finite");
     if (h->jsub != 0 || h->cur != h->frozen)
         return h->fail(HYB_EINVAL, "set the dissolution between coarse steps (fine steps are pending)");
+    if (h->wall_on && kappa_s > 0.0)
+        return h->fail(HYB_EINVAL, "dissolving solids need bounce-back walls (the wall closure is on)");
     if (refresh_solid_host(h) != hipSuccess) return h->fail(HYB_EHIP, "could not read the solid flags");
     if (mass) {
         const int N = h->N, P = h->lay.pitch;

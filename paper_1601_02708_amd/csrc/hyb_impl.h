@@ -101,6 +101,11 @@ struct LbmArgs {
     // owned nodes are also stored here (a recording forward keeps every
     // fine state); nullptr: not stored
     void *mid;
+    // maximum-entropy zero-flux closure at solid walls (single-step general
+    // path): the fluid domain's unit outward normal per node (pitched FP32
+    // planes); nullptr: halfway bounce-back
+    const float *wall_nx;
+    const float *wall_ny;
 };
 
 // Population storage policy: FP64 and FP32 store what they compute; FP16
@@ -158,15 +163,21 @@ hipError_t launch_lbm_stepk(const LbmArgs &a, int prec, int K, hipStream_t s, in
 // a.src = the step's source state f*(t) (read only with clamped closures),
 // snext = f*(t+1), lam = dJ/df*(t+1); nu is scratch; out = dJ/df*(t);
 // grad_a, grad_b [4(N-1)] and grad_k (dense [N][N] or null) accumulate.
+// inj (or null, storage type, pitched): a cotangent added to the output at
+// fluid nodes.
 hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
-                               double *grad_a, double *grad_b, double *grad_k, hipStream_t s);
+                               double *grad_a, double *grad_b, double *grad_k, hipStream_t s,
+                               const void *inj = nullptr);
 // Two reversed fine steps in one launch: step t (a1.src = f*(t), a1.lam,
 // snext1 = f*(t+1)) then step t-1 (a2.src = f*(t-1), a2.lam, snext2 = f*(t)),
 // lam = dJ/df*(t+1) -> out = dJ/df*(t-1); gradients as launch_adjoint_step
 // for both steps.  Same results as two launch_adjoint_step calls.
+// inj_mid, inj_out (or null): cotangents added at fluid nodes to dJ/df*(t)
+// and to the output dJ/df*(t-1).
 hipError_t launch_adjoint_step2(const LbmArgs &a1, const LbmArgs &a2, int prec, const void *snext1,
                                 const void *snext2, const void *lam, void *out, double *grad_a, double *grad_b,
-                                double *grad_k, hipStream_t s);
+                                double *grad_k, hipStream_t s, const void *inj_mid = nullptr,
+                                const void *inj_out = nullptr);
 // dense FP64 [9][N][N] to pitched planes (to_pitched) or back; back with
 // accumulate adds to the dense array instead of overwriting it
 hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,

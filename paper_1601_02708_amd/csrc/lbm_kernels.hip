@@ -141,11 +141,17 @@ __device__ __forceinline__ void solid_link_flux(const LbmArgs &a, const S *__res
     a.flux[n] = a.flux_first ? s : a.flux[n] + s;
 }
 
+__device__ int closure_neumann(double (&f)[kQ], unsigned unknown, double nx, double ny, double qp,
+                               const double (&own)[kQ]);
+
 // Interior node (1 <= i, j <= N-2): every upstream node is inside the
 // patch.  The nine pulls are issued before the flag word is known;
 // bounce-back values replace them afterwards.  Stores are non-temporal: the
 // destination plane is not read again before the sweep has finished.
-template <typename S>
+// WALL: at a node with solid upstream nodes the maximum-entropy zero-flux
+// closure of eq. (LBM_Neu) with the wall's normal (a.wall_nx, a.wall_ny)
+// replaces bounce-back (FP64 Newton, the perimeter's closure).
+template <typename S, bool WALL = false>
 __device__ __forceinline__ void interior_node(const LbmArgs &a, const S *__restrict__ src, S *__restrict__ dst,
                                               int n, int plane, int P) {
     typedef typename Pop<S>::T T;
@@ -161,7 +167,22 @@ __device__ __forceinline__ void interior_node(const LbmArgs &a, const S *__restr
     T f[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) f[q] = Pop<S>::ld(raw[q], q, a);
-    if (m & 0x1FEu) {
+    if (WALL && (m & 0x1FEu)) {
+        // unknowns: every population with e.n < 0 (the set M- of eq.
+        // LBM_Neu), and the solid-sourced ones (bounced back where e.n >= 0)
+        const double nx = double(a.wall_nx[n]), ny = double(a.wall_ny[n]);
+        unsigned unknown = m & 0x1FEu;
+        double fd[kQ], own[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            own[q] = double(Pop<S>::ld(src[q * plane + n], q, a));
+            fd[q] = double(f[q]);
+            if (q > 0 && kCx[q] * nx + kCy[q] * ny < 0.0) unknown |= 1u << q;
+        }
+        if (closure_neumann(fd, unknown, nx, ny, 0.0, own)) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) f[q] = T(fd[q]);
+    } else if (m & 0x1FEu) {
 #pragma unroll
         for (int q = 1; q < kQ; ++q)
             if ((m >> q) & 1u) f[q] = Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a);
@@ -226,14 +247,14 @@ __global__ void __launch_bounds__(256) lbm_sweep_kernel(LbmArgs a, int tiles, in
 
 // Interior only (with the general perimeter kernel when some slots carry
 // the Neumann closure).
-template <typename S>
+template <typename S, bool WALL>
 __global__ void __launch_bounds__(256) lbm_bulk_kernel(LbmArgs a, int row_blocks) {
     const int P = a.pitch;
     const int j = 1 + blockIdx.x / row_blocks;
     const int i = 1 + (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
     if (i <= a.N - 2)
-        interior_node<S>(a, static_cast<const S *>(a.src), static_cast<S *>(a.dst), j * P + i,
-                         static_cast<int>(a.plane), P);
+        interior_node<S, WALL>(a, static_cast<const S *>(a.src), static_cast<S *>(a.dst), j * P + i,
+                               static_cast<int>(a.plane), P);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,13 +262,15 @@ __global__ void __launch_bounds__(256) lbm_bulk_kernel(LbmArgs a, int row_blocks
 //
 // Dirichlet, eq. (LBM_Dir): as dirichlet_close.
 //
-// Neumann, eq. (LBM_Neu): unknowns with e_i.n < 0 are w_i exp(-1 + g s_i),
+// Neumann, eq. (LBM_Neu), for a unit outward normal n (a patch edge or
+// corner, or a solid wall): unknowns with e_i.n < 0 are w_i exp(-1 + g s_i),
 // s_i = -e_i.n > 0, where the Lagrange multiplier g solves
 //   ln sum_i w_i s_i exp(-1 + g s_i) = ln R',  R' = sum_known (e.n) f - q^p.
 // The left side is convex and increasing in g; Newton from the closed-form
 // start (exact when all s_i are equal, i.e. on a flat edge) converges
-// monotonically after its first step.  Tangential unknowns at a corner
-// (e_i.n = 0) are bounced back from the node's own post-collision value.
+// monotonically after its first step.  Unknowns with e_i.n >= 0 (the
+// tangential ones at a corner, links a curved wall grazes) are bounced back
+// from the node's own post-collision value.
 // ---------------------------------------------------------------------------
 __device__ int closure_dirichlet(double (&f)[kQ], unsigned unknown, double up, int clamp) {
     double known = 0.0, wsum = 0.0;
@@ -266,19 +289,18 @@ __device__ int closure_dirichlet(double (&f)[kQ], unsigned unknown, double up, i
     return bad;
 }
 
-__device__ int closure_neumann(double (&f)[kQ], unsigned unknown, int sx, int sy, double qp,
+__device__ int closure_neumann(double (&f)[kQ], unsigned unknown, double nx, double ny, double qp,
                                const double (&own)[kQ]) {
-    const double inv_norm = rsqrt(double(sx * sx + sy * sy));
     unsigned out = 0;      // M-: unknowns with e.n < 0
     double flux_known = 0.0;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-        const int dot = kCx[q] * sx + kCy[q] * sy;
+        const double dot = kCx[q] * nx + kCy[q] * ny;
         if ((unknown >> q) & 1u) {
-            if (dot < 0) { out |= 1u << q; continue; }
+            if (dot < 0.0) { out |= 1u << q; continue; }
             f[q] = own[kOpp[q]];
         }
-        flux_known += dot * inv_norm * f[q];
+        flux_known += dot * f[q];
     }
     const double Rp = flux_known - qp;
     if (!(Rp > 0.0)) {
@@ -291,7 +313,7 @@ __device__ int closure_neumann(double (&f)[kQ], unsigned unknown, int sx, int sy
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         if ((out >> q) & 1u) {
-            const double s = -(kCx[q] * sx + kCy[q] * sy) * inv_norm;
+            const double s = -(kCx[q] * nx + kCy[q] * ny);
             sw += kW[q] * s;
             sw2 += kW[q] * s * s;
         }
@@ -303,7 +325,7 @@ __device__ int closure_neumann(double (&f)[kQ], unsigned unknown, int sx, int sy
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             if ((out >> q) & 1u) {
-                const double s = -(kCx[q] * sx + kCy[q] * sy) * inv_norm;
+                const double s = -(kCx[q] * nx + kCy[q] * ny);
                 const double e = kW[q] * s * exp(-1.0 + g * s);
                 s0 += e;
                 s1 += e * s;
@@ -316,7 +338,7 @@ __device__ int closure_neumann(double (&f)[kQ], unsigned unknown, int sx, int sy
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         if ((out >> q) & 1u) {
-            const double s = -(kCx[q] * sx + kCy[q] * sy) * inv_norm;
+            const double s = -(kCx[q] * nx + kCy[q] * ny);
             f[q] = kW[q] * exp(-1.0 + g * s);
         }
     }
@@ -363,7 +385,8 @@ __global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
     } else {
         const int sx = (i == 0) ? -1 : (i == N - 1) ? 1 : 0;
         const int sy = (j == 0) ? -1 : (j == N - 1) ? 1 : 0;
-        bad = closure_neumann(f, unknown, sx, sy, value, own);
+        const double inv_norm = rsqrt(double(sx * sx + sy * sy));
+        bad = closure_neumann(f, unknown, sx * inv_norm, sy * inv_norm, value, own);
     }
     if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
 
@@ -602,9 +625,10 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
         }
         const T u = collide<T>(f, T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
         if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
-        // the second half reads what the next fine step would read from HBM
+        // the second half reads the first step's result in the arithmetic
+        // type (FP16 shifted storage rounds to binary16 only at the store)
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) lds[q][r][c] = Pop<S>::ld(Pop<S>::st(f[q], q, a), q, a);
+        for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[q];
         if constexpr (MID) {
             // a recording forward keeps the intermediate state too
             if (owned) {
@@ -856,9 +880,6 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
         if constexpr (RING == 0) {
 #pragma unroll
             for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(h[k][q], q, a), fdst, n * sz, q * SP * sz);
-        } else {
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) h[k][q] = Pop<S>::ld(Pop<S>::st(h[k][q], q, a), q, a);
         }
     }
     if constexpr (FLUX) {
@@ -1032,7 +1053,7 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
         const T u = collide<T>(f, T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
         if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) lds[q][r][c] = Pop<S>::ld(Pop<S>::st(f[q], q, a), q, a);
+        for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[q];
     }
 
     // the next region's flags and velocities, fetched before the barrier
@@ -1213,8 +1234,13 @@ hipError_t step_impl(const LbmArgs &a, bool general_perimeter, hipStream_t s, hi
                            interior_blocks, row_blocks);
         if (e1) (void)hipEventRecord(e1, s);
     } else {
-        if (interior_blocks > 0)
-            hipLaunchKernelGGL(lbm_bulk_kernel<S>, dim3(interior_blocks), dim3(256), 0, s, a, row_blocks);
+        if (interior_blocks > 0) {
+            if (a.wall_nx)
+                hipLaunchKernelGGL((lbm_bulk_kernel<S, true>), dim3(interior_blocks), dim3(256), 0, s, a, row_blocks);
+            else
+                hipLaunchKernelGGL((lbm_bulk_kernel<S, false>), dim3(interior_blocks), dim3(256), 0, s, a,
+                                   row_blocks);
+        }
         if (e1) (void)hipEventRecord(e1, s);
         hipLaunchKernelGGL(lbm_perimeter_kernel<S>, dim3((np + 127) / 128), dim3(128), 0, s, a);
     }

@@ -39,7 +39,7 @@ class HybMesh(ctypes.Structure):
 class HybLattice(ctypes.Structure):
     _fields_ = [("N", _i), ("x0", _d), ("y0", _d), ("precision", _i), ("tau", _d), ("eta", _i),
                 ("bc_clamp", _i), ("solid", _P), ("u0", _P), ("f_buf", _P * 3), ("workspace", _P),
-                ("stream", _P), ("dissolution", _i)]
+                ("stream", _P), ("dissolution", _i), ("wall_closure", _i)]
 
 
 class HybVelocity(ctypes.Structure):
@@ -76,6 +76,7 @@ SIGNATURES = {
     "hyb_populations_device": (_i, [_P, _P]),
     "hyb_set_populations": (_i, [_P, _P]),
     "hyb_stats": (_i, [_P, _P]),
+    "hyb_set_wall_normals": (_i, [_P, _P]),
     "hyb_diagnostics": (_i, [_P, _P, _i]),
     "hyb_diagnostics_noalloc": (_i, [_P, _P]),
     "hyb_layout": (_i, [_P, _P, _P]),
@@ -84,7 +85,7 @@ SIGNATURES = {
     "hyb_lbm_adjoint": (_i, [_P, _i, _P, _P, _P, _P, _P, _P]),
     "hyb_step_adjoint_query": (_i, [_P, _i, _P]),
     "hyb_step_record": (_i, [_P, _i, _P]),
-    "hyb_step_adjoint": (_i, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "hyb_step_adjoint": (_i, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "hyb_set_coarse": (_i, [_P, _P]),
     "hyb_set_reaction_field": (_i, [_P, _P]),
     "hyb_set_outer_value": (_i, [_P, _d]),
@@ -175,7 +176,7 @@ class Hybrid:
     coarse mesh around it.  Arrays follow include/hyb.h."""
 
     def __init__(self, *, N, x0, y0, u0, vx, vy, D, eta, precision="fp64", tau=0.0, solid=None,
-                 k=0.0, k_field=None, bc_clamp=0, mesh=None, device=None, dissolution=False):
+                 k=0.0, k_field=None, bc_clamp=0, mesh=None, device=None, dissolution=False, wall_closure=False):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -208,6 +209,7 @@ class Hybrid:
         self.lat.solid = _ptr(solidh)
         self.lat.u0 = _ptr(u0h)
         self.lat.dissolution = int(bool(dissolution))
+        self.lat.wall_closure = int(bool(wall_closure))
         self.dissolution = bool(dissolution)
         self.meshs = None
         vc = None
@@ -337,18 +339,52 @@ class Hybrid:
     def step_record(self, passes, tape):
         return self._check(load().hyb_step_record(self.h, int(passes), tape.data_ptr()))
 
-    def step_adjoint(self, tape, lam_f, lam_d, lam_f_out, lam_d_out, grad_k=None, grad_outer=None):
+    def step_adjoint(self, tape, lam_f, lam_d, lam_f_out, lam_d_out, grad_k=None, grad_outer=None, lam_sub=None):
         """Device FP64 tensors: lam_f/lam_f_out [9, N, N], lam_d/lam_d_out
         [(M+1)^2] (lam_d may be None), grad_k [N, N] and grad_outer
-        [(M+1)^2] or None (added to)."""
+        [(M+1)^2] or None (added to); lam_sub [9, N, N] or None: the
+        cotangent of every intermediate fine state of the committed pass."""
         t = self.torch
-        for x in (lam_f, lam_f_out, lam_d_out) + tuple(v for v in (lam_d, grad_k, grad_outer) if v is not None):
+        for x in (lam_f, lam_f_out, lam_d_out) + tuple(v for v in (lam_d, grad_k, grad_outer, lam_sub)
+                                                         if v is not None):
             if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
                 raise ValueError("adjoint arrays must be contiguous FP64 device tensors")
         ptr = lambda v: None if v is None else v.data_ptr()
-        return self._check(load().hyb_step_adjoint(self.h, tape.data_ptr(), lam_f.data_ptr(), ptr(lam_d),
-                                                   lam_f_out.data_ptr(), lam_d_out.data_ptr(), ptr(grad_k),
-                                                   ptr(grad_outer)))
+        return self._check(load().hyb_step_adjoint(self.h, tape.data_ptr(), lam_f.data_ptr(), ptr(lam_sub),
+                                                   ptr(lam_d), lam_f_out.data_ptr(), lam_d_out.data_ptr(),
+                                                   ptr(grad_k), ptr(grad_outer)))
+
+    def step_reading_substeps(self, passes, read):
+        """One coarse step of Algorithm 1 through the separate calls
+        (transfers, coarse solve, fine steps, commit) so that ``read()`` can
+        look at every intermediate fine state f*(t_n + j), j = 1 .. eta-1, of
+        the committed (last) pass; the step's result equals hyb_step's (in
+        FP64 bit for bit: the same per-node operations, single-step
+        launches).  A coarse solve that ran out of its launch budget repeats
+        the step from the untouched committed state; ``read`` returns a value
+        for each state and the values of the attempt that committed are
+        returned."""
+        lib = load()
+        for attempt in range(20):
+            vals = []
+            self.lbm_substeps(0, restart=1)          # the fine state read first is the committed one
+            for it in range(passes):
+                self.interface_exchange(HYB_F2C)
+                self.coarse_step(200)
+                self.interface_exchange(HYB_C2F)
+                if it < passes - 1:
+                    self.lbm_substeps(self.eta, restart=1)
+                    continue
+                for j in range(1, self.eta + 1):
+                    self.lbm_substeps(1, restart=1 if j == 1 else 0)
+                    if j < self.eta:
+                        vals.append(read())
+            rc = lib.hyb_commit(self.h)
+            if rc == HYB_OK:
+                return vals
+            if rc != HYB_ENOCONV:
+                self._check(rc)
+        raise HybError(HYB_ENOCONV, "coarse solve did not converge in 20 attempts")
 
     def set_coarse(self, d):
         """Replace the committed coarse solution (host [(M+1)^2] FP64)."""
@@ -382,6 +418,17 @@ class Hybrid:
         return self._check(load().hyb_checkpoint_load(self.h, ckpt.data_ptr()))
 
     # -- dissolving solids ---------------------------------------------------
+    def set_wall_normals(self, normals):
+        """Maximum-entropy zero-flux closure at solid walls with the given
+        unit outward normals (host [2, N, N], pointing into the solid), or
+        bounce-back again with None (handle created with wall_closure=True)."""
+        if normals is None:
+            return self._check(load().hyb_set_wall_normals(self.h, None))
+        n = np.ascontiguousarray(normals, dtype=np.float32).reshape(-1)
+        if n.size != 2 * self.N * self.N:
+            raise ValueError("normals must have 2*N*N entries")
+        return self._check(load().hyb_set_wall_normals(self.h, n.ctypes.data))
+
     def set_dissolution(self, kappa_s, c_sat, mass=None):
         """Surface reaction rate and saturation concentration at fluid-solid
         links, and the solid masses (host [N, N], read at solid nodes)."""
@@ -435,7 +482,7 @@ class Hybrid:
         return self._check(load().hyb_set_overlap(self.h, int(depth)))
 
     def set_steps_per_launch(self, steps):
-        """Most fine steps per sweep launch, 1 to 5 (default 5 fp32, 4 fp64, 2 fp16s);
+        """Most fine steps per sweep launch, 1 to 5 (default 5 fp32, 4 fp64, 4 fp16s);
         2 or more also reverses the adjoint's fine steps in pairs."""
         return self._check(load().hyb_set_steps_per_launch(self.h, int(steps)))
 
@@ -505,7 +552,7 @@ def lattice_substeps_function():
 
 
 
-def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8, state_in_cotangent=True):
+def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8, state_in_cotangent=True, substep_weight=None):
     """Reverse mode of n_steps coarse steps from the handle's committed state
     (which is left at the end of the rollout), with the committed state
     checkpointed on the device every ``checkpoint_every`` steps
@@ -522,12 +569,19 @@ def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8, state_in_co
     (hyb_step with that count).  Returns host FP64 arrays (dJ/dF_0, dJ/dd_0,
     dJ/dk, dJ/dg_outer): the initial state, the fine per-node reaction rate
     and the outer-edge Dirichlet values (per coarse node, summed over the
-    steps).  Each step's adjoint runs on the GPU through hyb_step_record and
-    hyb_step_adjoint; this function only orchestrates."""
+    steps).  ``substep_weight`` ([9, N, N] host array or device tensor, or
+    None): J also holds <w, f*(t)> for every intermediate fine state of
+    every step's committed pass (so, with the same w in ``cotangent``, J can
+    sum over every fine step).  Each step's adjoint runs on the GPU through
+    hyb_step_record and hyb_step_adjoint; this function only orchestrates."""
     import torch
     N, M = g.N, g.M
     dev = g.dev
     n1 = (M + 1) ** 2
+    lam_sub = None
+    if substep_weight is not None:
+        lam_sub = (substep_weight.to(device=dev, dtype=torch.float64).contiguous() if torch.is_tensor(substep_weight)
+                   else torch.from_numpy(np.ascontiguousarray(substep_weight, np.float64)).to(dev))
 
     # forward rollout, checkpointing the state at every segment start
     ckpt = {}
@@ -567,7 +621,7 @@ def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8, state_in_co
             if cd is not None:
                 lam_d += (cd.to(device=dev, dtype=torch.float64).reshape(-1) if torch.is_tensor(cd)
                           else torch.from_numpy(np.ascontiguousarray(cd, np.float64).reshape(-1)).to(dev))
-            g.step_adjoint(tape, lam_f, lam_d, out_f, out_d, gk, gouter)
+            g.step_adjoint(tape, lam_f, lam_d, out_f, out_d, gk, gouter, lam_sub)
             lam_f, out_f = out_f, lam_f
             lam_d, out_d = out_d, lam_d
         del seg
@@ -575,11 +629,19 @@ def steps_adjoint(g, n_steps, cotangent, passes, checkpoint_every=8, state_in_co
     return lam_f.cpu().numpy(), lam_d.cpu().numpy(), gk.cpu().numpy(), gouter.cpu().numpy()
 
 
-def trajectory_functional():
+def trajectory_functional(every_substep=False):
     """torch.autograd.Function for a linear functional summed over a
     trajectory of coarse steps,
 
         J(k, g) = sum_{n=1}^{n_steps} <w_f, F_n> + <w_d, d_n>,
+
+    or, with ``every_substep``, over every fine step,
+
+        J(k, g) = sum_{n} [ sum_{j=1}^{eta} <w_f, f*(t_{n-1} + j)> + <w_d, d_n> ]
+
+    (the fine states of each step's committed Schwarz pass; the forward then
+    runs each step through the separate calls, Hybrid.step_reading_substeps,
+    and the backward injects w_f at every reversed fine state),
 
     as a function of the fine per-node reaction rate k and the Dirichlet
     value g of the outer edges that are not natural, from the handle's
@@ -612,8 +674,16 @@ def trajectory_functional():
                 np.ascontiguousarray(w_d, np.float64).reshape(-1)).to(dev)
             fbuf = torch.empty((9, N, N), dtype=torch.float64, device=dev) if wf is not None else None
             dbuf = torch.empty(n1, dtype=torch.float64, device=dev) if wd is not None else None
+            def read():
+                g.populations_device(fbuf)
+                return (fbuf * wf).sum()
+
             for _ in range(n_steps):
-                g.step(passes)
+                if every_substep and wf is not None:
+                    for v in g.step_reading_substeps(passes, read):
+                        J += v
+                else:
+                    g.step(passes)
                 if wf is not None:
                     g.populations_device(fbuf)
                     J += (fbuf * wf).sum()
@@ -640,7 +710,8 @@ def trajectory_functional():
             wd = None if w_d is None else torch.from_numpy(
                 np.ascontiguousarray(w_d, np.float64).reshape(-1)).to(dev)
             _, _, gk, go = steps_adjoint(g, ctx.n_steps, lambda n, F, d: (wf, wd), ctx.passes,
-                                         checkpoint_every=ctx.every, state_in_cotangent=False)
+                                         checkpoint_every=ctx.every, state_in_cotangent=False,
+                                         substep_weight=wf if every_substep else None)
             dt, dv = ctx.k_meta
             grad_k = torch.from_numpy(gk).to(device=dv, dtype=dt) * gJ.to(dv)
             grad_g = None

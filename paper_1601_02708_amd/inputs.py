@@ -140,6 +140,38 @@ def random_disks(N: int, porosity: float, seed: int, r_min: float = 6.0,
                     porosity=1.0 - count / float(N * N))
 
 
+def wall_normals(pack: DiskPack) -> np.ndarray:
+    """Unit outward normal of the fluid domain (pointing into the grain) at
+    every fluid node next to a solid node, float32 [2, N, N] (x plane then
+    y plane, zero elsewhere): the unit vector from the node towards the
+    centre of the grain whose surface is nearest to it."""
+    solid = pack.solid != 0
+    N = solid.shape[0]
+    out = np.zeros((2, N, N), np.float32)
+    pad = np.pad(solid, 1)
+    near = np.zeros_like(solid)
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            near |= pad[1 + dj:1 + dj + N, 1 + di:1 + di + N]
+    jj, ii = np.nonzero(near & ~solid)
+    if len(jj) == 0 or len(pack.radii) == 0:
+        return out
+    best = np.full(len(jj), np.inf)
+    nx = np.zeros(len(jj))
+    ny = np.zeros(len(jj))
+    for (ci, cj), r in zip(pack.centers, pack.radii):
+        dx, dy = ci - ii, cj - jj
+        d = np.hypot(dx, dy)
+        gap = d - r
+        take = gap < best
+        best = np.where(take, gap, best)
+        nx = np.where(take, dx / d, nx)
+        ny = np.where(take, dy / d, ny)
+    out[0, jj, ii] = nx
+    out[1, jj, ii] = ny
+    return out
+
+
 # ----------------------------------------------------------------------------
 # divergence-free advection velocity from a seeded stream function
 # ----------------------------------------------------------------------------

@@ -280,6 +280,53 @@ def test_trajectory_functional_autograd():
     g.close()
 
 
+def test_every_substep_objective_autograd():
+    """The differentiation workload's objective as the time integral over
+    every one of the 2000 fine steps (J sums the outlet moment of each fine
+    state): the autograd gradient in (k, g) against central differences of
+    the Function's own forward along two mixed directions, and J against the
+    sum of the coarse-step-end samples it contains."""
+    hyb, torch = _gpu()
+    p = configs.build_problem(configs.DIFF512)
+    cfg = p.cfg
+    N, P = cfg.N, cfg.max_iter
+    w = _outlet_weights(p)
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    start = g.checkpoint()
+    every = hyb.trajectory_functional(every_substep=True)
+    ends = hyb.trajectory_functional()
+    k = torch.tensor(p.k_field, dtype=torch.float64, requires_grad=True)
+    gv = torch.tensor(cfg.outer_value, dtype=torch.float64, requires_grad=True)
+    J = every.apply(g, cfg.steps, P, 10, w, None, k, gv)
+    J.backward()
+    gk, gg = k.grad.numpy(), float(gv.grad)
+    g.restore(start)
+    with torch.no_grad():
+        J_ends = float(ends.apply(g, cfg.steps, P, 10, w, None, torch.from_numpy(p.k_field),
+                                  torch.tensor(cfg.outer_value, dtype=torch.float64)))
+    print(f"\nJ over every fine step {float(J.detach()):.12e}, at coarse-step ends {J_ends:.12e}")
+    assert abs(float(J.detach())) > 5.0 * abs(J_ends)
+    rng = np.random.default_rng(cfg.seed + 8000)
+    eps = 1e-3
+    with torch.no_grad():
+        for r in range(2):
+            dk = rng.uniform(-1.0, 1.0, (N, N)) * p.k_field
+            dk[p.solid != 0] = 0.0
+            dg = float(rng.uniform(-1.0, 1.0))
+            vals = []
+            for s in (1.0, -1.0):
+                g.restore(start)
+                vals.append(float(every.apply(g, cfg.steps, P, 10, w, None,
+                                              torch.from_numpy(p.k_field + s * eps * dk),
+                                              torch.tensor(cfg.outer_value + s * eps * dg, dtype=torch.float64))))
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            an = float(np.sum(gk * dk)) + gg * dg
+            rel = abs(fd - an) / abs(fd)
+            print(f"direction {r}: adjoint {an:.12e} central {fd:.12e} rel {rel:.2e}", flush=True)
+            assert rel <= 1e-4, (r, an, fd)
+    g.close()
+
+
 def test_control_setters():
     """hyb_set_reaction_field on a uniform-k handle gives the run of a handle
     created with that field; hyb_set_outer_value that of one created with

@@ -78,6 +78,45 @@ def test_step_adjoint_matches_oracle(orc, name, over, precision, tol):
     assert max(errs.values()) <= tol, errs
 
 
+@pytest.mark.parametrize("name,over,precision,spl,tol", [
+    ("small", {"k": 2e-3, "eta": 5}, "fp64", 2, 1e-11),     # pairs: 5 = 2 + 2 + 1
+    ("small", {"k": 2e-3, "eta": 5}, "fp64", 1, 1e-11),     # single reversed steps
+    ("pore2048", {"N": 97, "M": 16, "eta": 4}, "fp64", 2, 1e-11),
+    ("small", {"k": 2e-3, "eta": 5}, "fp32", 2, 1e-4),
+])
+def test_step_adjoint_substep_cotangent_matches_oracle(orc, name, over, precision, spl, tol):
+    """A cotangent at every intermediate fine state of the committed pass
+    (hyb_step_adjoint's lam_sub: an objective that integrates over every
+    fine step), in paired and single reversed steps, against the oracle's
+    adjoint with the same lam_sub."""
+    from oracle.hybrid_adjoint import HybridStepAdjoint
+    hyb, torch = _gpu()
+    p = _problem(name, **over)
+    N, M = p.cfg.N, p.cfg.M
+    g = hyb.Hybrid.from_problem(p, precision=precision)
+    g.set_steps_per_launch(spl)
+    F0 = g.get_populations()
+    d0 = g.concentration(hyb.HYB_COARSE).reshape(-1)
+    lam_f, lam_d = _cotangents(p, N, M, 31)
+    w, _ = _cotangents(p, N, M, 32)
+    dev = g.dev
+    lf, ld = torch.from_numpy(lam_f).to(dev), torch.from_numpy(lam_d).to(dev)
+    lw = torch.from_numpy(w).to(dev)
+    lf_out, ld_out = torch.empty_like(lf), torch.empty_like(ld)
+    gk = torch.zeros((N, N), dtype=torch.float64, device=dev)
+    tape = g.step_tape(p.cfg.max_iter)
+    g.step_record(p.cfg.max_iter, tape)
+    g.step_adjoint(tape, lf, ld, lf_out, ld_out, gk, lam_sub=lw)
+    torch.cuda.synchronize()
+    adj = HybridStepAdjoint(orc.HybridOracle(p))
+    _, _, otape = adj.forward(F0, d0)
+    oF, od, ok = adj.adjoint(otape, lam_f, lam_d, lam_sub=w)
+    errs = {"f": _rel(lf_out.cpu().numpy(), oF), "d": _rel(ld_out.cpu().numpy(), od), "k": _rel(gk.cpu().numpy(), ok)}
+    print(f"\nstep adjoint with substep cotangent {name} {precision} spl={spl}: {errs}")
+    assert max(errs.values()) <= tol, errs
+    g.close()
+
+
 def test_step_adjoint_dot_product_identity_on_gpu():
     """<(lam_f, lam_d), Step(F, d)> = <lam_F, F> + <lam_dn, d> with the GPU
     forward (recorded step) and adjoint, 257^2 patch on a 32^2 mesh (ragged

@@ -134,6 +134,33 @@ def test_step_dot_product_identity(request, case):
     assert _rel(lhs, rhs) <= 1e-11, (lhs, rhs)
 
 
+@pytest.mark.parametrize("case", ["small", "pore"])
+def test_step_dot_product_identity_with_substep_cotangent(request, case):
+    """An objective that also reads every intermediate fine state of the
+    committed pass, J = <lam_f, F1> + <lam_d, d1> + sum_{j=1}^{eta-1}
+    <w, f*(t_n + j)>, against the adjoint with lam_sub = w (linear step)."""
+    p, o, adj = request.getfixturevalue(case)
+    rng = np.random.default_rng(15)
+    F = rng.uniform(0.0, 0.2, (9, o.N, o.N))
+    if p.solid is not None:
+        F[:, p.solid != 0] = 0.0
+    d = rng.standard_normal((o.M + 1) ** 2)
+    lam_f = rng.standard_normal((9, o.N, o.N))
+    w = rng.standard_normal((9, o.N, o.N))
+    if p.solid is not None:
+        lam_f[:, p.solid != 0] = 0.0
+        w[:, p.solid != 0] = 0.0
+    lam_d = rng.standard_normal((o.M + 1) ** 2)
+    F1, d1, tape = adj.forward(F, d)
+    states = tape["passes"][-1]["states"]
+    lF, ld, _ = adj.adjoint(tape, lam_f, lam_d, lam_sub=w)
+    lhs = float(np.sum(lam_f * F1)) + float(lam_d @ d1) + sum(float(np.sum(w * s)) for s in states[1:-1])
+    rhs = float(np.sum(lF * F)) + float(ld @ d)
+    assert _rel(lhs, rhs) <= 1e-11, (lhs, rhs)
+    lF0, _, _ = adj.adjoint(tape, lam_f, lam_d)
+    assert not np.allclose(lF, lF0)
+
+
 def test_step_rate_gradient_by_central_differences(small, orc):
     from oracle.hybrid_adjoint import HybridStepAdjoint
     p, o, adj = small

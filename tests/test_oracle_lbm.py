@@ -368,3 +368,98 @@ def test_relaxation_time_gives_the_diffusion_coefficient(orc, D, t1, t2):
     D_meas = (v[t2] - v[t1]) / (2.0 * (t2 - t1))
     assert abs(D_meas / D - 1.0) < 1e-6, (D_meas, D, tau)
     assert abs(orc.sound_speed_sq() - 1.0 / 3.0) < 1e-15
+
+
+@pytest.mark.parametrize("sx,sy", [(-1, 0), (1, 0), (0, -1), (0, 1), (-1, -1), (1, -1), (-1, 1), (1, 1)])
+def test_maxent_neumann_normal_matches_edge_form(orc, sx, sy):
+    """The closure for a real unit normal reproduces the patch-edge form
+    (integer direction) bit for bit at axis and diagonal normals."""
+    ex, ey, _, _ = orc.d2q9()
+    rng = np.random.default_rng(40 + 3 * sx + sy)
+    unknown = sum(1 << q for q in range(9) if ex[q] * sx + ey[q] * sy < 0 or (sx and sy and ex[q] * sx + ey[q] * sy == 0
+                                                                              and q > 0))
+    f = rng.uniform(0.05, 0.3, 9)
+    fs = rng.uniform(0.05, 0.3, 9)
+    n = np.hypot(sx, sy)
+    a, ia = orc.maxent_neumann(f, unknown, sx, sy, -0.02, fs)
+    b, ib = orc.maxent_neumann_normal(f, unknown, sx / n, sy / n, -0.02, fs)
+    assert ia == ib == 0 and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.1, 2.0, 3.9, 5.5])
+def test_maxent_neumann_curved_normal(orc, theta):
+    """eq. (LBM_Neu) at a curved impermeable wall (q^p = 0, normal at an
+    angle the lattice does not resolve): the unknowns with e.n < 0 are the
+    minimiser of H under the flux constraint (generic optimiser), KKT holds
+    with one gamma, the normal flux of the closed node is zero, and the
+    unknown links with e.n >= 0 (grazed by the wall) are bounced back."""
+    from scipy.optimize import minimize
+    ex, ey, w, opp = orc.d2q9()
+    nx, ny = np.cos(theta), np.sin(theta)
+    a = ex * nx + ey * ny
+    rng = np.random.default_rng(int(theta * 100))
+    # populations that stream out of the wall: e.n < 0, plus the link with
+    # the smallest positive e.n (a grazing link whose upstream node is solid)
+    Mm = [q for q in range(1, 9) if a[q] < 0]
+    graze = min((q for q in range(1, 9) if a[q] >= 0), key=lambda q: a[q])
+    unknown = sum(1 << q for q in Mm) | (1 << graze)
+    f = rng.uniform(0.05, 0.3, 9)
+    fs = rng.uniform(0.05, 0.3, 9)
+    out, inf = orc.maxent_neumann_normal(f, unknown, nx, ny, 0.0, fs)
+    assert inf == 0
+    assert out[graze] == fs[opp[graze]]
+    assert abs(np.dot(out, a)) <= 1e-13 * np.sum(np.abs(a * out))
+    gam = -(np.log(out[Mm] / w[Mm]) + 1.0) / a[Mm]
+    assert np.ptp(gam) < 1e-11 * max(1.0, abs(gam[0]))
+    assert np.all(out[Mm] > 0)
+    rhs = -sum(a[q] * out[q] for q in range(9) if q not in Mm)
+    res = minimize(lambda z: _h(z, w[Mm]), x0=np.full(len(Mm), 0.1),
+                   constraints=[{"type": "eq", "fun": lambda z: np.dot(z, a[Mm]) - rhs}],
+                   bounds=[(1e-14, None)] * len(Mm), method="SLSQP", options={"ftol": 1e-15, "maxiter": 500})
+    assert np.allclose(res.x, out[Mm], rtol=1e-5)
+
+
+def test_wall_closure_zero_flux_on_the_lattice(orc):
+    """On a pore lattice (disks, flow, near-equilibrium state), after
+    streaming, the wall closure leaves every interior fluid node next to a
+    grain with zero normal flux sum_q (e_q.n) f_q and positive populations
+    in M- (all e_q.n < 0, where the other populations carry flux into the
+    wall), keeps bounce-back on the links the wall grazes, and changes the
+    bounce-back values elsewhere."""
+    from paper_1601_02708_amd import inputs
+    ex, ey, w, _ = orc.d2q9()
+    N = 65
+    pack = inputs.random_disks(N, 0.75, seed=3, r_min=3, r_max=7)
+    wn = inputs.wall_normals(pack)
+    rng = np.random.default_rng(5)
+    vx = rng.uniform(-0.04, 0.04, (N, N))
+    vy = rng.uniform(-0.04, 0.04, (N, N))
+    lat = orc.Lattice(N, 0.7, vx, vy, solid=pack.solid, wall_normals=wn)
+    u = rng.uniform(0.5, 1.5, (N, N))
+    fs = w[:, None, None] * u[None] * (1 + 0.05 * rng.standard_normal((9, N, N)))
+    fs[:, pack.solid != 0] = 0.0
+    f, _ = lat.stream(fs)
+    bb = f.copy()
+    inf = orc.lib().orc_apply_wall_closure(lat.ptr, fs.ctypes.data, f.ctypes.data)
+    solid = pack.solid != 0
+    checked = 0
+    for j in range(1, N - 1):
+        for i in range(1, N - 1):
+            if solid[j, i]:
+                continue
+            S = [q for q in range(1, 9) if solid[j - ey[q], i - ex[q]]]
+            if not S:
+                continue
+            a = ex * wn[0, j, i] + ey * wn[1, j, i]
+            Mm = [q for q in range(1, 9) if a[q] < 0]            # the unknowns of eq. (LBM_Neu)
+            for q in S:
+                if a[q] >= 0:                                      # grazed link: bounce-back
+                    assert f[q, j, i] == bb[q, j, i]
+            known_flux = sum(a[q] * f[q, j, i] for q in range(9) if q not in Mm)
+            if known_flux <= 0:
+                continue
+            assert abs(np.dot(a, f[:, j, i])) <= 1e-13 * np.sum(np.abs(a * f[:, j, i]))
+            assert all(f[q, j, i] > 0 for q in Mm)
+            checked += 1
+    assert checked > 200 and inf >= 0
+    assert not np.array_equal(f, bb)
