@@ -31,6 +31,21 @@ __device__ __forceinline__ int slot_of(int N, int i, int j) {
     return 3 * N - 2 + j - 1;
 }
 
+// Dense FP64 ends of a reversed sweep, folded into its first and last
+// launches: lam_dense (or null) is read in place of the pitched cotangent
+// (index (q*N + j)*N + i, converted to T as a separate packing pass would),
+// out_dense (or null) receives the output in that layout (added to it when
+// accumulate), in place of the pitched output.
+struct AdjDense {
+    const double *lam_dense;
+    double *out_dense;
+    int accumulate;
+};
+
+__device__ __forceinline__ size_t dense_at(int N, int q, int i, int j) {
+    return ((size_t)q * N + j) * N + i;
+}
+
 // nu at node (i, j) (collision and closure transposed) from the node's
 // cotangent l = dJ/df*(t+1); gradients of the closure and the reaction rate
 // are accumulated when `owner` (every node has exactly one owner tile, ring
@@ -118,8 +133,9 @@ __device__ __forceinline__ void adj_nu_of(const LbmArgs &a, int i, int j, const 
 // nu at node (i, j) with the node's cotangent read from lam
 template <typename T>
 __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
-                                       const T *__restrict__ lam, bool owner, double *__restrict__ grad_a,
-                                       double *__restrict__ grad_b, double *__restrict__ grad_k, T (&nu)[kQ]) {
+                                       const T *__restrict__ lam, const double *__restrict__ lam_dense, bool owner,
+                                       double *__restrict__ grad_a, double *__restrict__ grad_b,
+                                       double *__restrict__ grad_k, T (&nu)[kQ]) {
     const int plane = static_cast<int>(a.plane);
     const int n = j * a.pitch + i;
     T l[kQ];
@@ -128,8 +144,13 @@ __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *
         for (int q = 0; q < kQ; ++q) nu[q] = T(0);
         return;
     }
+    if (lam_dense) {
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) l[q] = lam[q * plane + n];
+        for (int q = 0; q < kQ; ++q) l[q] = T(lam_dense[dense_at(a.N, q, i, j)]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) l[q] = lam[q * plane + n];
+    }
     adj_nu_of<T>(a, i, j, snext, l, owner, grad_a, grad_b, grad_k, nu);
 }
 
@@ -146,7 +167,7 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
                                                       const T *__restrict__ lam, T *__restrict__ out,
                                                       double *__restrict__ grad_a, double *__restrict__ grad_b,
                                                       double *__restrict__ grad_k, int tiles_x,
-                                                      const T *__restrict__ inj) {
+                                                      const T *__restrict__ inj, AdjDense dn) {
     constexpr int W1 = TW + 2, H1 = TH + 2;
     __shared__ T nus[kQ][H1][W1];
     const int N = a.N, P = a.pitch;
@@ -161,7 +182,7 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
             for (int q = 0; q < kQ; ++q) nu[q] = T(0);
         } else {
             const bool owner = lx >= 1 && lx <= TW && ly >= 1 && ly <= TH;
-            adj_nu<T>(a, i, j, snext, lam, owner, grad_a, grad_b, grad_k, nu);
+            adj_nu<T>(a, i, j, snext, lam, dn.lam_dense, owner, grad_a, grad_b, grad_k, nu);
         }
 #pragma unroll
         for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = nu[q];
@@ -174,8 +195,14 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
         const int n = j * P + i;
         const unsigned m = a.mask[n];
         if (m & kMaskSolid) {
+            if (dn.out_dense) {
+                if (!dn.accumulate)
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+                    for (int q = 0; q < kQ; ++q) dn.out_dense[dense_at(N, q, i, j)] = 0.0;
+            } else {
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+            }
             continue;
         }
         // a reactive link returns 1 - kappa_s of the population (1 when off)
@@ -186,7 +213,12 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
             const int q = kOpp[p];
             if ((m >> q) & 1u) acc += keep * nus[q][ly][lx];
             if (inj) acc += inj[p * plane + n];
-            out[p * plane + n] = acc;
+            if (dn.out_dense) {
+                const size_t d = dense_at(N, p, i, j);
+                dn.out_dense[d] = dn.accumulate ? dn.out_dense[d] + double(acc) : double(acc);
+            } else {
+                out[p * plane + n] = acc;
+            }
         }
     }
 }
@@ -209,7 +241,7 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
                                                        T *__restrict__ out, double *__restrict__ grad_a,
                                                        double *__restrict__ grad_b, double *__restrict__ grad_k,
                                                        int tiles_x, const T *__restrict__ inj_mid,
-                                                       const T *__restrict__ inj_out) {
+                                                       const T *__restrict__ inj_out, AdjDense dn) {
     constexpr int W2 = TW + 4, H2 = TH + 4, W1 = TW + 2, H1 = TH + 2;
     constexpr int R1 = (W1 * H1 + NT - 1) / NT;
     __shared__ T nus[kQ][H2][W2];
@@ -226,7 +258,7 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
             for (int q = 0; q < kQ; ++q) nu[q] = T(0);
         } else {
             const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
-            adj_nu<T>(a1, i, j, snext1, lam, owner, grad_a, grad_b, grad_k, nu);
+            adj_nu<T>(a1, i, j, snext1, lam, dn.lam_dense, owner, grad_a, grad_b, grad_k, nu);
         }
 #pragma unroll
         for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = nu[q];
@@ -277,8 +309,14 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
         const int n = j * P + i;
         const unsigned m = a2.mask[n];
         if (m & kMaskSolid) {
+            if (dn.out_dense) {
+                if (!dn.accumulate)
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+                    for (int q = 0; q < kQ; ++q) dn.out_dense[dense_at(N, q, i, j)] = 0.0;
+            } else {
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+            }
             continue;
         }
 #pragma unroll
@@ -287,7 +325,12 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
             const int q = kOpp[p];
             if ((m >> q) & 1u) acc += keep2 * nus[q][ly][lx];
             if (inj_out) acc += inj_out[p * plane + n];
-            out[p * plane + n] = acc;
+            if (dn.out_dense) {
+                const size_t d = dense_at(N, p, i, j);
+                dn.out_dense[d] = dn.accumulate ? dn.out_dense[d] + double(acc) : double(acc);
+            } else {
+                out[p * plane + n] = acc;
+            }
         }
     }
 }
@@ -321,27 +364,33 @@ __global__ void __launch_bounds__(256) adj_unpack_kernel(LbmArgs a, const T *__r
     }
 }
 
+// Lanes per workgroup: 512 in FP64, whose LDS tile (two rings of nu, 58.8 KB
+// for the paired kernel) allows two workgroups per CU -- 16 waves rather than
+// the 8 of 256-lane groups; 256 in FP32 (29.4 KB, five groups per CU).
+template <typename T>
+constexpr int adj_lanes() { return sizeof(T) == 8 ? 512 : 256; }
+
 template <typename T>
 hipError_t adjoint_step_impl(const LbmArgs &a, const void *snext, const void *lam, void *out, double *grad_a,
-                             double *grad_b, double *grad_k, const void *inj, hipStream_t s) {
-    constexpr int TW = 64, TH = 8, NT = 256;
+                             double *grad_b, double *grad_k, const void *inj, AdjDense dn, hipStream_t s) {
+    constexpr int TW = 64, TH = 8, NT = adj_lanes<T>();
     const int tiles_x = (a.N + TW - 1) / TW, tiles_y = (a.N + TH - 1) / TH;
     hipLaunchKernelGGL((adj_step_kernel<T, TW, TH, NT>), dim3(tiles_x * tiles_y), dim3(NT), 0, s, a,
                        static_cast<const T *>(snext), static_cast<const T *>(lam), static_cast<T *>(out), grad_a,
-                       grad_b, grad_k, tiles_x, static_cast<const T *>(inj));
+                       grad_b, grad_k, tiles_x, static_cast<const T *>(inj), dn);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t adjoint_step2_impl(const LbmArgs &a1, const LbmArgs &a2, const void *snext1, const void *snext2,
                               const void *lam, void *out, double *grad_a, double *grad_b, double *grad_k,
-                              const void *inj_mid, const void *inj_out, hipStream_t s) {
-    constexpr int TW = 64, TH = 8, NT = 256;
+                              const void *inj_mid, const void *inj_out, AdjDense dn, hipStream_t s) {
+    constexpr int TW = 64, TH = 8, NT = adj_lanes<T>();
     const int tiles_x = (a1.N + TW - 1) / TW, tiles_y = (a1.N + TH - 1) / TH;
     hipLaunchKernelGGL((adj_step2_kernel<T, TW, TH, NT>), dim3(tiles_x * tiles_y), dim3(NT), 0, s, a1, a2,
                        static_cast<const T *>(snext1), static_cast<const T *>(snext2), static_cast<const T *>(lam),
                        static_cast<T *>(out), grad_a, grad_b, grad_k, tiles_x, static_cast<const T *>(inj_mid),
-                       static_cast<const T *>(inj_out));
+                       static_cast<const T *>(inj_out), dn);
     return hipGetLastError();
 }
 
@@ -349,18 +398,23 @@ hipError_t adjoint_step2_impl(const LbmArgs &a1, const LbmArgs &a2, const void *
 
 hipError_t launch_adjoint_step2(const LbmArgs &a1, const LbmArgs &a2, int prec, const void *snext1,
                                 const void *snext2, const void *lam, void *out, double *grad_a, double *grad_b,
-                                double *grad_k, hipStream_t s, const void *inj_mid, const void *inj_out) {
+                                double *grad_k, hipStream_t s, const void *inj_mid, const void *inj_out,
+                                const double *lam_dense, double *out_dense, bool accumulate) {
+    const AdjDense dn{lam_dense, out_dense, accumulate ? 1 : 0};
     if (prec == HYB_FP64)
         return adjoint_step2_impl<double>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, inj_mid, inj_out,
-                                          s);
-    return adjoint_step2_impl<float>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, inj_mid, inj_out, s);
+                                          dn, s);
+    return adjoint_step2_impl<float>(a1, a2, snext1, snext2, lam, out, grad_a, grad_b, grad_k, inj_mid, inj_out, dn,
+                                     s);
 }
 
 hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
-                               double *grad_a, double *grad_b, double *grad_k, hipStream_t s, const void *inj) {
+                               double *grad_a, double *grad_b, double *grad_k, hipStream_t s, const void *inj,
+                               const double *lam_dense, double *out_dense, bool accumulate) {
     (void)nu;    // scratch of the two-kernel form; the fused kernel keeps nu in LDS
-    if (prec == HYB_FP64) return adjoint_step_impl<double>(a, snext, lam, out, grad_a, grad_b, grad_k, inj, s);
-    return adjoint_step_impl<float>(a, snext, lam, out, grad_a, grad_b, grad_k, inj, s);
+    const AdjDense dn{lam_dense, out_dense, accumulate ? 1 : 0};
+    if (prec == HYB_FP64) return adjoint_step_impl<double>(a, snext, lam, out, grad_a, grad_b, grad_k, inj, dn, s);
+    return adjoint_step_impl<float>(a, snext, lam, out, grad_a, grad_b, grad_k, inj, dn, s);
 }
 
 hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,

@@ -1323,11 +1323,24 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
     auto slot = [&](int t) { return base + (size_t)t * fb; };
     void *lcur = slot(n_sub + 1), *nu = slot(n_sub + 2), *lnext = slot(n_sub + 3);
     LbmArgs a = h->lbm_args(h->frozen, -1);
-    HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_in, lcur, true, h->stream));
     // reversed steps in pairs (one launch each) unless single-step launches
     // were asked for (hyb_set_steps_per_launch(1))
     const bool pairs = h->steps_per_launch >= 2;
-    for (int t = n_sub - 1; t >= 0;) {
+    int launches = 0;
+    for (int t = n_sub - 1; t >= 0; ++launches) t -= (pairs && t >= 1) ? 2 : 1;
+    if (launches == 0) {
+        HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_in, lcur, true, h->stream));
+        HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_out, lcur, false, h->stream));
+        return HYB_OK;
+    }
+    // the first launch reads lam_in in its dense layout and the last writes
+    // lam_out in it (no packing passes), unless a single launch would read
+    // and write the same array (lam_out may alias lam_in)
+    const bool dense_out = launches >= 2 || lam_out != lam_in;
+    int k = 0;
+    for (int t = n_sub - 1; t >= 0; ++k) {
+        const double *din = k == 0 ? lam_in : nullptr;
+        double *dout = k == launches - 1 && dense_out ? lam_out : nullptr;
         if (pairs && t >= 1) {
             LbmArgs a1 = a, a2 = a;
             a1.src = slot(t);
@@ -1335,18 +1348,18 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
             a2.src = slot(t - 1);
             a2.lam = (double)t / (double)h->eta;
             HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, slot(t + 1), slot(t), lcur, lnext, grad_a, grad_b,
-                                            grad_k, h->stream));
+                                            grad_k, h->stream, nullptr, nullptr, din, dout, false));
             t -= 2;
         } else {
             a.src = slot(t);
             a.lam = (double)(t + 1) / (double)h->eta;
             HIP_TRY(h, launch_adjoint_step(a, h->prec, slot(t + 1), lcur, nu, lnext, grad_a, grad_b, grad_k,
-                                           h->stream));
+                                           h->stream, nullptr, din, dout, false));
             t -= 1;
         }
         std::swap(lcur, lnext);
     }
-    HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_out, lcur, false, h->stream));
+    if (!dense_out) HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_out, lcur, false, h->stream));
     return HYB_OK;
 }
 
@@ -1505,7 +1518,11 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
     LbmArgs a = h->lbm_args(h->frozen, -1);
     const bool dissolving = h->dissolve_ws;
     if (dissolving) a.mask = reinterpret_cast<const uint16_t *>(base + T.mask);   // the step's geometry
-    HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_f, lcur, true, h->stream));
+    // the first reversed launch reads lam_f in its dense layout (no packing
+    // pass) unless the conversion's transpose works on it first or lam_f_out
+    // (cleared below) aliases it
+    const bool dense_in = !dissolving && lam_f_out != lam_f;
+    if (!dense_in) HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_f, lcur, true, h->stream));
     if (dissolving) {
         // the commit's conversion, transposed (nu is free until the first reversed fine step)
         HIP_TRY(h, launch_conversion_transpose(a, h->prec, reinterpret_cast<const uint8_t *>(base + T.after),
@@ -1535,7 +1552,13 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
         // substep cotangent (state eta takes lam_f, state 0 belongs to the
         // previous coarse step)
         const void *inj_p = p == passes - 1 ? inj : nullptr;
-        for (int t = h->eta; t >= 1;) {
+        int launches = 0;
+        for (int t = h->eta; t >= 1; ++launches) t -= (h->steps_per_launch >= 2 && t >= 2) ? 2 : 1;
+        int k = 0;
+        for (int t = h->eta; t >= 1; ++k) {
+            // the pass's last launch adds its output to lam_f_out directly
+            const double *din = dense_in && p == passes - 1 && k == 0 ? lam_f : nullptr;
+            double *dout = k == launches - 1 ? lam_f_out : nullptr;
             if (h->steps_per_launch >= 2 && t >= 2) {
                 // steps t and t-1 reversed in one launch
                 LbmArgs a1 = a, a2 = a;
@@ -1544,18 +1567,18 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
                 a2.src = state(p, t - 2);
                 a2.lam = (double)(t - 1) / (double)h->eta;
                 HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, state(p, t), state(p, t - 1), lcur, lnext, ga, gb,
-                                                grad_k, h->stream, inj_p, t - 2 >= 1 ? inj_p : nullptr));
+                                                grad_k, h->stream, inj_p, t - 2 >= 1 ? inj_p : nullptr, din, dout,
+                                                true));
                 t -= 2;
             } else {
                 a.src = state(p, t - 1);
                 a.lam = (double)t / (double)h->eta;
                 HIP_TRY(h, launch_adjoint_step(a, h->prec, state(p, t), lcur, nu, lnext, ga, gb, grad_k, h->stream,
-                                               t - 1 >= 1 ? inj_p : nullptr));
+                                               t - 1 >= 1 ? inj_p : nullptr, din, dout, true));
                 t -= 1;
             }
             std::swap(lcur, lnext);
         }
-        HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_f_out, lcur, false, h->stream, true));
         // coarse-to-fine, coarse solve and right-hand side, transposed
         HIP_TRY(h, launch_c2f_transpose(h->cd, h->c2fT_ptr, h->c2fT_slot, h->c2fT_w, ga, gb,
                                         p == passes - 1 ? lam_d : nullptr, lam_dn, lam_d1, h->stream));

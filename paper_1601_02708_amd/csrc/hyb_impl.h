@@ -164,10 +164,14 @@ hipError_t launch_lbm_stepk(const LbmArgs &a, int prec, int K, hipStream_t s, in
 // snext = f*(t+1), lam = dJ/df*(t+1); nu is scratch; out = dJ/df*(t);
 // grad_a, grad_b [4(N-1)] and grad_k (dense [N][N] or null) accumulate.
 // inj (or null, storage type, pitched): a cotangent added to the output at
-// fluid nodes.
+// fluid nodes.  lam_dense (or null): the cotangent read from a dense FP64
+// [9][N][N] array instead of lam; out_dense (or null): the output written
+// (accumulate: added) there instead of out -- the packing passes folded into
+// the first and last launches of a reversed sweep.
 hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, const void *lam, void *nu, void *out,
                                double *grad_a, double *grad_b, double *grad_k, hipStream_t s,
-                               const void *inj = nullptr);
+                               const void *inj = nullptr, const double *lam_dense = nullptr,
+                               double *out_dense = nullptr, bool accumulate = false);
 // Two reversed fine steps in one launch: step t (a1.src = f*(t), a1.lam,
 // snext1 = f*(t+1)) then step t-1 (a2.src = f*(t-1), a2.lam, snext2 = f*(t)),
 // lam = dJ/df*(t+1) -> out = dJ/df*(t-1); gradients as launch_adjoint_step
@@ -177,7 +181,8 @@ hipError_t launch_adjoint_step(const LbmArgs &a, int prec, const void *snext, co
 hipError_t launch_adjoint_step2(const LbmArgs &a1, const LbmArgs &a2, int prec, const void *snext1,
                                 const void *snext2, const void *lam, void *out, double *grad_a, double *grad_b,
                                 double *grad_k, hipStream_t s, const void *inj_mid = nullptr,
-                                const void *inj_out = nullptr);
+                                const void *inj_out = nullptr, const double *lam_dense = nullptr,
+                                double *out_dense = nullptr, bool accumulate = false);
 // dense FP64 [9][N][N] to pitched planes (to_pitched) or back; back with
 // accumulate adds to the dense array instead of overwriting it
 hipError_t launch_adjoint_pack(const LbmArgs &a, int prec, const double *dense, void *pitched, bool to_pitched,

@@ -4,6 +4,8 @@ kept under profiles/ (run on the host after the GPU job).
     python -m paper_1601_02708_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
     python -m paper_1601_02708_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <out.json> <workload> <precision> <copy_mib> "<commands>" [kernel]
+    python -m paper_1601_02708_amd.profiling sq <out.json> <workload> <precision> <kernel> "<commands>" \
+        <counter_collection.csv> ...
 
 The traffic record scales the FETCH_SIZE / WRITE_SIZE counters of the
 lattice-sweep kernel by what the same counters read for the plain copy
@@ -80,8 +82,65 @@ def traffic(fetch_csv, write_csv, out_path, workload, precision, copy_mib, comma
     print(json.dumps(rec))
 
 
+def _per_kernel_all(paths):
+    out = {}
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            out.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def sq(out_path, workload, precision, kernel, commands, *csv_paths):
+    """Shader-sequencer counters of the dominant sweep kernel (whole-patch
+    launches of `kernel`, mean per dispatch) from several --pmc passes, with
+    the derived utilisations and the limiter they point to:
+      valu_busy   VALU issue cycles per SIMD cycle (one wave instruction per
+                  4 cycles per SIMD, 4 SIMDs per CU, 256 CUs)
+      waves_per_cu  mean resident waves per CU (SQ_WAVE_CYCLES counts
+                  quad-cycles, SQ_BUSY_CU_CYCLES cycles)
+      mem_wait    share of wave time waiting at s_waitcnt
+      lds_conflict  LDS bank-conflict cycles per LDS-active cycle
+    """
+    data = _per_kernel_all(csv_paths)
+    tname = {"fp32": "float", "fp64": "double", "fp16s": "_Float16"}[precision]
+    mname = {"fp32": "f", "fp64": "d", "fp16s": "DF16_"}[precision]
+    ks = [k for k in data if (f"{kernel}<{tname}" in k and ", 0>" in k) or
+          (kernel in k and f"I{mname}" in k and "Li0EEE" in k)]
+    if not ks:
+        raise SystemExit("kernel not found in the counter files")
+    m = {c: statistics.mean(v) for c, v in data[ks[0]].items()}
+    xcd_cycles = m["GRBM_GUI_ACTIVE"] / 8.0             # the counter sums the 8 XCDs
+    simd_quads = 256 * 4 * xcd_cycles / 4.0
+    rec = {
+        "kernel": ks[0][:120], "workload": workload, "precision": precision, "kernel_sha": kernel_hash(),
+        "counters": {c: m[c] for c in sorted(m)},
+        "duration_us": xcd_cycles / 2400.0,
+        "valu_busy": m["SQ_ACTIVE_INST_VALU"] / simd_quads,
+        "waves_per_cu": 4.0 * m["SQ_WAVE_CYCLES"] / m["SQ_BUSY_CU_CYCLES"],
+        "mem_wait": m["SQ_WAIT_INST_ANY"] / m["SQ_WAVE_CYCLES"],
+        "lds_conflict": m["SQ_LDS_BANK_CONFLICT"] / m["SQ_LDS_IDX_ACTIVE"],
+        "valu_insts_per_wave": m["SQ_INSTS_VALU"] / m["SQ_WAVES"],
+        "salu_insts_per_wave": m["SQ_INSTS_SALU"] / m["SQ_WAVES"],
+        "commands": commands,
+    }
+    busy = rec["valu_busy"]
+    if busy >= 0.7:
+        rec["bound"] = "alu"
+        rec["limiter"] = (f"VALU issue: {100 * busy:.0f}% of SIMD issue slots, {rec['waves_per_cu']:.1f} waves/CU, "
+                          f"{100 * rec['mem_wait']:.0f}% of wave time in memory waits")
+    else:
+        rec["bound"] = "latency"
+        rec["limiter"] = (f"latency and occupancy: VALU {100 * busy:.0f}% of SIMD issue slots, "
+                          f"{rec['waves_per_cu']:.1f} waves/CU, {100 * rec['mem_wait']:.0f}% of wave time in "
+                          f"memory waits, LDS conflicts {100 * rec['lds_conflict']:.0f}%")
+    json.dump(rec, open(out_path, "w"), indent=1)
+    print(json.dumps({k: v for k, v in rec.items() if k != "counters"}))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
+    elif sys.argv[1] == "sq":
+        sq(*sys.argv[2:])
