@@ -253,6 +253,8 @@ int orc_maxent_neumann_normal(double *f, unsigned unknown, double nx, double ny,
     double rhs = qp;
     for (int q = 0; q < 9; ++q)
         if (!(mminus & (1u << q))) rhs -= a[q] * f[q];
+    /* no population of M- to solve with: infeasible unless already met */
+    if (!mminus) return rhs != 0.0;
     if (!(rhs < 0.0)) {
         for (int q = 0; q < 9; ++q) if (mminus & (1u << q)) f[q] = 0.0;
         return 1;

@@ -303,6 +303,8 @@ __device__ int closure_neumann(double (&f)[kQ], unsigned unknown, double nx, dou
         flux_known += dot * f[q];
     }
     const double Rp = flux_known - qp;
+    // no population of M- to solve with: infeasible unless already met
+    if (!out) return Rp != 0.0;
     if (!(Rp > 0.0)) {
 #pragma unroll
         for (int q = 0; q < kQ; ++q)
