@@ -1161,17 +1161,28 @@ __global__ void __launch_bounds__(256) lbm_diag_rows_kernel(LbmArgs a, double *_
     const int P = a.pitch;
     const S *__restrict__ src = static_cast<const S *>(a.src);
     double m = 0.0, h = 0.0, bad = 0.0, mn = __builtin_inf();
+    // ln(f / w) as ln f - ln w: one logarithm and no division per value
+    double lnw[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) lnw[q] = log(kW[q]);
+    // every node's values are loaded before its flag decides (no branch
+    // between the loads of successive nodes, so they overlap)
+#pragma unroll 4
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const int n = j * P + i;
+        S v[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) v[q] = src[q * a.plane + n];
         if (a.mask[n] & kMaskSolid) continue;
         double sum = 0.0;
         bool fin = true;
+#pragma unroll
         for (int q = 0; q < kQ; ++q) {
-            const double f = double(Pop<S>::ld(src[q * a.plane + n], q, a));
+            const double f = double(Pop<S>::ld(v[q], q, a));
             sum += f;
             fin = fin && finite_val(f);
             mn = f < mn ? f : mn;
-            if (f > 0.0) h += f * log(f / kW[q]);
+            if (f > 0.0) h += f * (log(f) - lnw[q]);
         }
         m += sum / (1.0 - double(node_k<T>(a, n)));
         bad += fin ? 0.0 : 1.0;

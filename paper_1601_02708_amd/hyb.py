@@ -506,10 +506,11 @@ class Hybrid:
             load().hyb_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the exit hook has closed every live handle;
-        # never call into the HIP runtime from a finaliser then
-        if sys.is_finalizing():
+        # never call into the HIP runtime from a finaliser then (the check is
+        # bound here: module globals such as sys may already be None)
+        if _finalizing():
             return
         try:
             self.close()
@@ -823,10 +824,11 @@ class HybridGroup:
             load().hyb_group_destroy(self.g)
             self.g = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the exit hook has closed every live handle;
-        # never call into the HIP runtime from a finaliser then
-        if sys.is_finalizing():
+        # never call into the HIP runtime from a finaliser then (the check is
+        # bound here: module globals such as sys may already be None)
+        if _finalizing():
             return
         try:
             self.close()
@@ -901,10 +903,11 @@ class Hybrid1D:
             load().hyb1d_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the exit hook has closed every live handle;
-        # never call into the HIP runtime from a finaliser then
-        if sys.is_finalizing():
+        # never call into the HIP runtime from a finaliser then (the check is
+        # bound here: module globals such as sys may already be None)
+        if _finalizing():
             return
         try:
             self.close()
