@@ -17,7 +17,6 @@ after the timed steps and after all of the workload's coarse steps; and the
 CPU oracle timed on a bounded sample on this host (all threads and one).
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -26,14 +25,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1601_02708_amd.profiling import kernel_hash  # noqa: E402
+
 METRIC = "ADE-LBM MLUPS + % HBM peak; FP32/adjoint vs FP64 plain at stated L2 error"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1601_02708_amd", "csrc", "lbm_kernels.hip")
-
-
-def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
-
 
 def sweep_bytes(problem, elem_bytes):
     """Algorithmic HBM bytes of one lattice-sweep launch (every node of the

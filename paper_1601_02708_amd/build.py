@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["lbm_kernels.hip", "adjoint_kernels.hip", "coarse_kernels.hip", "coarse_adjoint.hip", "coarse_setup.hip",
-           "dissolve_kernels.hip", "hyb1d.hip",
+           "dissolve_kernels.hip", "diag_kernels.hip", "hyb1d.hip",
            "hyb_api.hip"]
 LIB = os.path.join(HERE, "libhyb.so")
 ARCH = "gfx950"

@@ -21,11 +21,16 @@ import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SRC = os.path.join(ROOT, "paper_1601_02708_amd", "csrc", "lbm_kernels.hip")
+# the sweep kernels and the header they are built with: a counter record
+# stays valid while neither changes
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1601_02708_amd", "csrc", f) for f in ("lbm_kernels.hip", "hyb_impl.h")]
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def stats(csv_path, out_path, command):
