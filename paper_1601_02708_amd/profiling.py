@@ -60,7 +60,10 @@ def traffic(fetch_csv, write_csv, out_path, workload, precision, copy_mib, comma
     # the dominant sweep kernel: the whole-patch launch (tile part 0) of
     # `kernel` (the bench's dominant kind) when it ran, else the whole-patch
     # two-step launch, else the single-step one
-    sweep = [k for k in fetch if f"{kernel}<" in k and f"<{tname}" in k and ", 0>" in k]
+    mname = {"fp32": "f", "fp64": "d", "fp16s": "DF16_"}[precision]
+    # demangled, or (where the demangler gives up, as for _Float16) mangled
+    sweep = [k for k in fetch if (f"{kernel}<" in k and f"<{tname}" in k and ", 0>" in k) or
+             (f"{kernel}I{mname}Li" in k and "ELi0EEEv" in k)]
     sweep = sweep or [k for k in fetch if "lbm_sweep2_kernel" in k and f"<{tname}" in k and ", 0>" in k]
     sweep = sweep or [k for k in fetch if "lbm_sweep_kernel" in k and f"<{tname}" in k]
     if not sweep:
