@@ -49,11 +49,15 @@ __device__ __forceinline__ size_t dense_at(int N, int q, int i, int j) {
 // nu at node (i, j) (collision and closure transposed) from the node's
 // cotangent l = dJ/df*(t+1); gradients of the closure and the reaction rate
 // are accumulated when `owner` (every node has exactly one owner tile, ring
-// copies recompute nu only).
+// copies recompute nu only).  The dJ/dk term of the step goes to *stash
+// when given (a paired launch then adds both steps' terms at once), else
+// grad_k becomes (grad_k - prior) - term: prior is the term of the reversed
+// step before, held back, so the sum is that of two separate updates.
 template <typename T>
 __device__ __forceinline__ void adj_nu_of(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
                                           const T (&l)[kQ], bool owner, double *__restrict__ grad_a,
-                                          double *__restrict__ grad_b, double *__restrict__ grad_k, T (&nu)[kQ]) {
+                                          double *__restrict__ grad_b, double *__restrict__ grad_k, T (&nu)[kQ],
+                                          double *stash = nullptr, double prior = 0.0) {
     const int N = a.N, P = a.pitch;
     const int plane = static_cast<int>(a.plane);
     const int n = j * P + i;
@@ -78,11 +82,24 @@ __device__ __forceinline__ void adj_nu_of(const LbmArgs &a, int i, int j, const 
 #pragma unroll
     for (int q = 0; q < kQ; ++q) nu[q] = (T(1) - omega) * l[q] + S;
     if (grad_k && owner) {
-        // u at the step's collision: sum f*(t+1) = (1 - k) u
-        T s = T(0);
+        // u at the step's collision: recorded by the forward, or from the
+        // next state, sum f*(t+1) = (1 - k) u
+        T u;
+        if (a.u_rec) {
+            u = static_cast<const T *>(a.u_rec)[n];
+        } else {
+            T s = T(0);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) s += snext[q * plane + n];
-        grad_k[(size_t)j * N + i] -= double(s / (T(1) - k)) * double(wl);
+            for (int q = 0; q < kQ; ++q) s += snext[q * plane + n];
+            u = s / (T(1) - k);
+        }
+        const double term = double(u) * double(wl);
+        if (stash) {
+            *stash = term;
+        } else {
+            const size_t at = (size_t)j * N + i;
+            grad_k[at] = (grad_k[at] - prior) - term;
+        }
     }
     if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
         unsigned unknown = 0;
@@ -135,7 +152,7 @@ template <typename T>
 __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
                                        const T *__restrict__ lam, const double *__restrict__ lam_dense, bool owner,
                                        double *__restrict__ grad_a, double *__restrict__ grad_b,
-                                       double *__restrict__ grad_k, T (&nu)[kQ]) {
+                                       double *__restrict__ grad_k, T (&nu)[kQ], double *stash = nullptr) {
     const int plane = static_cast<int>(a.plane);
     const int n = j * a.pitch + i;
     T l[kQ];
@@ -151,7 +168,7 @@ __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *
 #pragma unroll
         for (int q = 0; q < kQ; ++q) l[q] = lam[q * plane + n];
     }
-    adj_nu_of<T>(a, i, j, snext, l, owner, grad_a, grad_b, grad_k, nu);
+    adj_nu_of<T>(a, i, j, snext, l, owner, grad_a, grad_b, grad_k, nu, stash);
 }
 
 // One reversed fine step.  Phase 1: nu for the tile grown by one ring (0
@@ -232,9 +249,10 @@ __global__ void __launch_bounds__(NT) adj_step_kernel(LbmArgs a, const T *__rest
 // place.  Phase 3: the owned nodes gather their outputs.  Every node takes
 // the single reversed step's operations (dJ/df*(t) never leaves the chip),
 // so the result equals two adj_step_kernel launches; gradients are added by
-// the owner of each node once per step, the two steps separated by a
-// barrier.  inj_mid, inj_out (or null): cotangents added at fluid nodes to
-// dJ/df*(t) (on chip) and to the output dJ/df*(t-1).
+// the owner of each node, step t before step t-1 (in FP64 the dJ/dk terms
+// of both steps in one update, (g - term_t) - term_t-1, as two updates
+// would leave it).  inj_mid, inj_out (or null): cotangents added at fluid
+// nodes to dJ/df*(t) (on chip) and to the output dJ/df*(t-1).
 template <typename T, int TW, int TH, int NT>
 __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, const T *__restrict__ snext1,
                                                        const T *__restrict__ snext2, const T *__restrict__ lam,
@@ -244,7 +262,11 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
                                                        const T *__restrict__ inj_out, AdjDense dn) {
     constexpr int W2 = TW + 4, H2 = TH + 4, W1 = TW + 2, H1 = TH + 2;
     constexpr int R1 = (W1 * H1 + NT - 1) / NT;
+    // FP64: the owned nodes' dJ/dk terms of step t wait in LDS and step
+    // t-1 adds both (one read-modify-write of grad_k per pair)
+    constexpr bool STASH = sizeof(T) == 8;
     __shared__ T nus[kQ][H2][W2];
+    __shared__ double kst[STASH ? TH : 1][STASH ? TW : 1];
     const int N = a1.N, P = a1.pitch;
     const int plane = static_cast<int>(a1.plane);
     const int x0 = (blockIdx.x % tiles_x) * TW, y0 = (blockIdx.x / tiles_x) * TH;
@@ -258,7 +280,8 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
             for (int q = 0; q < kQ; ++q) nu[q] = T(0);
         } else {
             const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
-            adj_nu<T>(a1, i, j, snext1, lam, dn.lam_dense, owner, grad_a, grad_b, grad_k, nu);
+            adj_nu<T>(a1, i, j, snext1, lam, dn.lam_dense, owner, grad_a, grad_b, grad_k, nu,
+                      STASH && owner ? &kst[STASH ? ly - 2 : 0][STASH ? lx - 2 : 0] : nullptr);
         }
 #pragma unroll
         for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = nu[q];
@@ -288,7 +311,8 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
             l[p] = acc;
         }
         const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
-        adj_nu_of<T>(a2, i, j, snext2, l, owner, grad_a, grad_b, grad_k, h[k]);
+        adj_nu_of<T>(a2, i, j, snext2, l, owner, grad_a, grad_b, grad_k, h[k], nullptr,
+                     STASH && owner ? kst[STASH ? ly - 2 : 0][STASH ? lx - 2 : 0] : 0.0);
     }
     __syncthreads();             // every read of step t's nu is done
 #pragma unroll

@@ -103,6 +103,7 @@ struct Layout {
     int pitch = 0;
     long long plane = 0;
     size_t f_bytes = 0;
+    size_t u_bytes = 0;     // one plane of the arithmetic type (recorded u of a fine step)
     size_t mask = 0, vx = 0, vy = 0, kfield = 0, bc_kind = 0, bc_a = 0, bc_b = 0, c2f_idx = 0, c2f_w = 0;
     size_t fc_idx = 0, fc_w = 0, ufc = 0, A9 = 0, B9 = 0, AP = 0, P = 0, dkind = 0, vec = 0, partials = 0;
     size_t counters = 0, barrier = 0, kres = 0, diag = 0, total = 0;
@@ -128,6 +129,7 @@ Layout make_layout(const hyb_mesh *mesh, const hyb_lattice *lat, bool has_kfield
     L.pitch = choose_pitch(N);
     L.plane = choose_plane(N, L.pitch);
     L.f_bytes = align_up((size_t)9 * L.plane * elem, kAlign);
+    L.u_bytes = align_up((size_t)L.plane * (lat->precision == HYB_FP64 ? 8 : 4), kAlign);
     const size_t nodes = (size_t)N * L.pitch;
     const size_t nslots = 4 * (size_t)(N - 1);
     size_t off = 0;
@@ -1262,8 +1264,9 @@ int hyb_stats(hyb_handle *h, hyb_run_stats *out) {
 
 int hyb_adjoint_query(const hyb_handle *h, int n_sub, size_t *tape_bytes) {
     if (!h || !tape_bytes || n_sub < 1) return HYB_EINVAL;
-    // states f*(0) .. f*(n_sub), two adjoint fields and one scratch field
-    *tape_bytes = (size_t)(n_sub + 4) * h->lay.f_bytes;
+    // states f*(0) .. f*(n_sub), two adjoint fields and one scratch field,
+    // then u of the collisions of fine steps 1 .. n_sub
+    *tape_bytes = (size_t)(n_sub + 4) * h->lay.f_bytes + (size_t)n_sub * h->lay.u_bytes;
     return HYB_OK;
 }
 
@@ -1276,6 +1279,13 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
     if (!tape || reinterpret_cast<uintptr_t>(tape) % kAlign) return h->fail(HYB_EINVAL, "tape must be 256-byte aligned");
     const size_t fb = h->lay.f_bytes;
     auto slot = [&](int t) { return static_cast<char *>(tape) + (size_t)t * fb; };
+    // u of step t's collision (t = 1 .. n_sub), after the states and the
+    // three adjoint fields (not with dissolving solids, whose reversed steps
+    // read the states)
+    auto uplane = [&](int t) -> void * {
+        if (h->dissolve_on) return nullptr;
+        return static_cast<char *>(tape) + (size_t)(n_sub + 4) * fb + (size_t)(t - 1) * h->lay.u_bytes;
+    };
     HIP_TRY(h, hipMemcpyAsync(slot(0), h->f[h->frozen], fb, hipMemcpyDeviceToDevice, h->stream));
     // pairs of fine steps in one launch that also stores the state between
     // them, while the two-step sweep serves (not with dissolving solids,
@@ -1285,9 +1295,11 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
         LbmArgs a = h->lbm_args(h->frozen, -1);
         a.src = slot(t);
         a.lam = (double)(t + 1) / (double)h->eta;
+        a.u_out = uplane(t + 1);
         if (pairs && t + 2 <= n_sub) {
             a.mid = slot(t + 1);
             a.dst = slot(t + 2);
+            a.u_out2 = uplane(t + 2);
             a.lam2 = (double)(t + 2) / (double)h->eta;
             HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream));
             t += 2;
@@ -1321,6 +1333,10 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
     const size_t fb = h->lay.f_bytes;
     char *base = static_cast<char *>(const_cast<void *>(tape));
     auto slot = [&](int t) { return base + (size_t)t * fb; };
+    auto uplane = [&](int t) -> const void * {
+        if (h->dissolve_on) return nullptr;
+        return base + (size_t)(n_sub + 4) * fb + (size_t)(t - 1) * h->lay.u_bytes;
+    };
     void *lcur = slot(n_sub + 1), *nu = slot(n_sub + 2), *lnext = slot(n_sub + 3);
     LbmArgs a = h->lbm_args(h->frozen, -1);
     // reversed steps in pairs (one launch each) unless single-step launches
@@ -1345,14 +1361,17 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
             LbmArgs a1 = a, a2 = a;
             a1.src = slot(t);
             a1.lam = (double)(t + 1) / (double)h->eta;
+            a1.u_rec = uplane(t + 1);
             a2.src = slot(t - 1);
             a2.lam = (double)t / (double)h->eta;
+            a2.u_rec = uplane(t);
             HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, slot(t + 1), slot(t), lcur, lnext, grad_a, grad_b,
                                             grad_k, h->stream, nullptr, nullptr, din, dout, false));
             t -= 2;
         } else {
             a.src = slot(t);
             a.lam = (double)(t + 1) / (double)h->eta;
+            a.u_rec = uplane(t + 1);
             HIP_TRY(h, launch_adjoint_step(a, h->prec, slot(t + 1), lcur, nu, lnext, grad_a, grad_b, grad_k,
                                            h->stream, nullptr, din, dout, false));
             t -= 1;
@@ -1369,9 +1388,11 @@ namespace {
 
 // Tape of hyb_step_record: f*(t_n), then eta fine states per pass; three
 // adjoint fields; the interface arrays a and b of every pass; dJ/da, dJ/db;
-// four padded coarse vectors; dJ/du_fc; one solver result per pass.
+// four padded coarse vectors; dJ/du_fc; one solver result per pass; u of
+// every fine step's collision.
 struct StepTape {
     size_t states = 0, scratch = 0, bc = 0, gab = 0, coarse = 0, lufc = 0, kres = 0, total = 0;
+    size_t u = 0;                   // u of every fine step's collision, eta per pass
     size_t mask = 0, after = 0;     // dissolving solids: flag words before, solid flags after the commit
 };
 
@@ -1392,6 +1413,7 @@ StepTape step_tape_layout(const hyb_handle *h, int passes) {
     T.coarse = take(4 * align_up(h->lay.vec_len * 8, kAlign));
     T.lufc = take((size_t)h->lay.n * 8);
     T.kres = take((size_t)passes * sizeof(KrylovResult));
+    T.u = take((size_t)passes * h->eta * h->lay.u_bytes);
     if (h->dissolve_ws) {
         const size_t nodes = (size_t)h->N * h->lay.pitch;
         T.mask = take(nodes * 2);
@@ -1430,6 +1452,12 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
     const size_t nslots = 4 * (size_t)(h->N - 1);
     char *base = static_cast<char *>(tape);
     auto state = [&](int p, int t) { return base + T.states + (t == 0 ? 0 : (1 + (size_t)p * h->eta + t - 1) * fb); };
+    // u of fine step t of pass p (t = 1 .. eta; not with dissolving solids,
+    // whose reversed steps read the states)
+    auto uplane = [&](int p, int t) -> void * {
+        if (h->dissolve_ws) return nullptr;
+        return base + T.u + ((size_t)p * h->eta + t - 1) * h->lay.u_bytes;
+    };
     double *bc = reinterpret_cast<double *>(base + T.bc);
     h->rec_step_tape = nullptr;
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -1452,10 +1480,12 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
                 LbmArgs a = h->lbm_args(h->frozen, -1);
                 a.src = state(p, t - 1);
                 a.lam = (double)t / (double)h->eta;
+                a.u_out = uplane(p, t);
                 if (pairs && t + 1 <= h->eta) {
                     // two fine steps, the state between them kept as well
                     a.mid = state(p, t);
                     a.dst = state(p, t + 1);
+                    a.u_out2 = uplane(p, t + 1);
                     a.lam2 = (double)(t + 1) / (double)h->eta;
                     HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream));
                     t += 2;
@@ -1504,6 +1534,10 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
     const size_t nslots = 4 * (size_t)(h->N - 1);
     char *base = static_cast<char *>(const_cast<void *>(tape));
     auto state = [&](int p, int t) { return base + T.states + (t == 0 ? 0 : (1 + (size_t)p * h->eta + t - 1) * fb); };
+    auto uplane = [&](int p, int t) -> const void * {
+        if (h->dissolve_ws) return nullptr;
+        return base + T.u + ((size_t)p * h->eta + t - 1) * h->lay.u_bytes;
+    };
     void *lcur = base + T.scratch, *nu = base + T.scratch + fb, *lnext = base + T.scratch + 2 * fb;
     double *bc = reinterpret_cast<double *>(base + T.bc);
     double *ga = reinterpret_cast<double *>(base + T.gab), *gb = ga + nslots;
@@ -1564,8 +1598,10 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
                 LbmArgs a1 = a, a2 = a;
                 a1.src = state(p, t - 1);
                 a1.lam = (double)t / (double)h->eta;
+                a1.u_rec = uplane(p, t);
                 a2.src = state(p, t - 2);
                 a2.lam = (double)(t - 1) / (double)h->eta;
+                a2.u_rec = uplane(p, t - 1);
                 HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, state(p, t), state(p, t - 1), lcur, lnext, ga, gb,
                                                 grad_k, h->stream, inj_p, t - 2 >= 1 ? inj_p : nullptr, din, dout,
                                                 true));
@@ -1573,6 +1609,7 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
             } else {
                 a.src = state(p, t - 1);
                 a.lam = (double)t / (double)h->eta;
+                a.u_rec = uplane(p, t);
                 HIP_TRY(h, launch_adjoint_step(a, h->prec, state(p, t), lcur, nu, lnext, ga, gb, grad_k, h->stream,
                                                t - 1 >= 1 ? inj_p : nullptr, din, dout, true));
                 t -= 1;

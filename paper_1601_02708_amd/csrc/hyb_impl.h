@@ -106,6 +106,16 @@ struct LbmArgs {
     // planes); nullptr: halfway bounce-back
     const float *wall_nx;
     const float *wall_ny;
+    // reverse mode: a recording forward also stores u of each fine step's
+    // collision at the fluid nodes, a plane of the arithmetic type pitched
+    // like a population plane (u_out: the launch's first step; u_out2: the
+    // second step of a two-step launch); a reversed step reads the recorded u
+    // of the collision it transposes from u_rec (for dJ/dk) instead of
+    // summing the next state's nine populations.  nullptr: not stored / from
+    // the state.
+    void *u_out;
+    void *u_out2;
+    const void *u_rec;
 };
 
 // Population storage policy: FP64 and FP32 store what they compute; FP16

@@ -196,6 +196,7 @@ __device__ __forceinline__ void interior_node(const LbmArgs &a, const S *__restr
     if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(Pop<S>::st(f[q], q, a), &dst[q * plane + n]);
+    if (a.u_out) static_cast<T *>(a.u_out)[n] = u;
 }
 
 // Perimeter slot p with the Dirichlet closure.
@@ -222,6 +223,7 @@ __device__ __forceinline__ void perimeter_dirichlet_node(const LbmArgs &a, const
     if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) dst[q * plane + n] = Pop<S>::st(f[q], q, a);
+    if (a.u_out) static_cast<T *>(a.u_out)[n] = u;
 }
 
 // One fine step over the whole patch in one launch: the first `tiles`
@@ -632,11 +634,12 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
 #pragma unroll
         for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[q];
         if constexpr (MID) {
-            // a recording forward keeps the intermediate state too
+            // a recording forward keeps the intermediate state too, and u
             if (owned) {
                 const BufRsrc fmid = buf_rsrc(a.mid, kQ * SP * sz);
 #pragma unroll
                 for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(f[q], q, a), fmid, n * sz, q * SP * sz);
+                if (a.u_out) static_cast<T *>(a.u_out)[n] = u;
             }
         }
     }
@@ -735,6 +738,9 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
         if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
 #pragma unroll
         for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(g[q], q, a), fdst, n * sz, q * SP * sz);
+        if constexpr (MID) {
+            if (a.u_out2) static_cast<T *>(a.u_out2)[n] = u;
+        }
     }
 }
 
