@@ -271,10 +271,12 @@ int hyb_diagnostics_noalloc(hyb_handle *h, double *out);
  * perimeter slot Dirichlet; HYB_EINVAL otherwise.
  *
  * hyb_adjoint_query: device bytes of the tape for n_sub >= 1 fine steps,
- *   (n_sub + 4) population buffers (f_bytes each).
- * hyb_lbm_substeps_record: like hyb_lbm_substeps(h, n_sub, 1) (single-step
- *   launches), recording f*(0) .. f*(n_sub) in the caller's device tape
- *   (256-byte aligned, >= tape bytes); 1 <= n_sub <= eta.
+ *   (n_sub + 4) population buffers (f_bytes each) and n_sub planes of the
+ *   arithmetic type.
+ * hyb_lbm_substeps_record: like hyb_lbm_substeps(h, n_sub, 1), recording
+ *   f*(0) .. f*(n_sub) and, without dissolving solids, u of each fine step's
+ *   collision (the reversed steps read it for dJ/dk) in the caller's device
+ *   tape (256-byte aligned, >= tape bytes); 1 <= n_sub <= eta.
  * hyb_lbm_adjoint: tape and n_sub of the last record (the interface values
  *   and the handle must be unchanged since); lam_in, lam_out: device FP64
  *   [9][N][N] (index (q*N + j)*N + i), lam_in = dJ/df*(n_sub) (kept),
@@ -301,10 +303,12 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
  * mesh is required.
  *
  * hyb_step_adjoint_query: device bytes of the tape for `passes` >= 1.
- * hyb_step_record: hyb_step(h, passes) run with single-step launches,
- *   recording the fine states, interface arrays and the state the transfers
- *   read in the caller's device tape (256-byte aligned); commits the step
- *   as hyb_step does (same errors; nothing is recorded on an error).
+ * hyb_step_record: hyb_step(h, passes) run with one- and two-step
+ *   launches, recording the fine states (and, without dissolving solids, u
+ *   of each fine step's collision), interface arrays and the state the
+ *   transfers read in the caller's device tape (256-byte aligned); commits
+ *   the step as hyb_step does (same errors; nothing is recorded on an
+ *   error).
  * hyb_step_adjoint: for the last record (tape pointer of that call; the
  *   handle may have committed that step since, but no later one):
  *   lam_f = dJ/df*(t_{n+1}) (device FP64 [9][N][N], index (q*N + j)*N + i),
