@@ -94,7 +94,9 @@ def _profile_record(kind, workload, precision, kernel):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_sha") != kernel_hash() or kernel.split("<")[0] + "<" not in rec.get("kernel", ""):
+    name = kernel.split("<")[0]
+    if rec.get("kernel_sha") != kernel_hash(name) or not (name + "<" in rec.get("kernel", "") or
+                                                         name + "I" in rec.get("kernel", "")):
         return None
     return rec
 
@@ -106,11 +108,11 @@ def load_traffic(workload, precision, kernel):
     return None if rec is None else rec.get("bytes_per_launch")
 
 
-def load_limiter(workload, precision, kernel):
+def load_limiter(workload, precision, kernel, kind="sq"):
     """The limiter the committed SQ counter record of this kernel names
     (its 'bound' and a one-line 'limiter' reading of the counters), or
     None."""
-    rec = _profile_record("sq", workload, precision, kernel)
+    rec = _profile_record(kind, workload, precision, kernel)
     return None if rec is None else {"bound": rec.get("bound"), "limiter": rec.get("limiter")}
 
 
@@ -257,24 +259,27 @@ def adjoint_rate(problem, precision, reps=3):
     lups = eta * N * N * reps
     # algorithmic bytes of one reversed fine step (reversed in pairs, two
     # per launch of adj_step2_kernel, the cotangent between them on chip): per
-    # fluid node the cotangent read, the next state read (for dJ/dk), the
-    # result written (9 values each), flags, velocity and the FP64 dJ/dk
-    # read-modify-write; per solid node its flags and the zeros written
+    # fluid node the cotangent read and the result written (9 values each),
+    # the recorded u of the step's collision (one value, for dJ/dk), flags,
+    # velocity and the FP64 dJ/dk read-modify-write; per solid node its flags
+    # and the zeros written
     s = 8 if precision == "fp64" else 4
     nfl = int((problem.solid == 0).sum())
-    step_bytes = nfl * (27 * s + 2 + 8 + 16) + (N * N - nfl) * (2 + 9 * s)
+    step_bytes = nfl * (19 * s + 2 + 8 + 16) + (N * N - nfl) * (2 + 9 * s)
+    kernel = f"adj_step2_kernel<{'double, 64, 8, 512' if s == 8 else 'float, 64, 8, 256'}>"
+    lim = load_limiter(problem.cfg.name, precision, kernel, kind="sq_adjoint")
     step_ms = adj_ms / (reps * eta)
     out = {"precision": precision, "value": round(lups / (adj_ms / 1e3) / 1e6, 1), "unit": "MLUPS",
            "ms_per_fine_step": round(step_ms, 4),
            "record_forward_mlups": round(lups / (rec_ms / 1e3) / 1e6, 1),
-           "roofline": {"kernel": f"adj_step2_kernel<{'double, 64, 8, 512' if s == 8 else 'float, 64, 8, 256'}> "
-                                  "(two reversed steps per launch)", "bound": "hbm",
+           "roofline": {"kernel": kernel + " (two reversed steps per launch)",
+                        "bound": lim["bound"] if lim else "hbm", "limiter": lim["limiter"] if lim else None,
                         "algorithmic_bytes_per_step": int(step_bytes),
                         "achieved": round(step_bytes / (step_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(step_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                         "note": "time per reversed fine step of the whole call (the dense FP64 cotangent is "
                                 "read and written by the first and last reversed launches, no packing passes)"},
-           "note": "dJ/df*, dJ/da, dJ/db, dJ/dk over one coarse step's fine steps (tape of eta + 4 states)"}
+           "note": "dJ/df*, dJ/da, dJ/db, dJ/dk over one coarse step's fine steps (tape of eta + 4 states and eta recorded u planes)"}
     g.close()
     return out
 

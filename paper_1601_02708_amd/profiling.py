@@ -21,14 +21,17 @@ import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-# the sweep kernels and the header they are built with: a counter record
-# stays valid while neither changes
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1601_02708_amd", "csrc", f) for f in ("lbm_kernels.hip", "hyb_impl.h")]
+# the source of a kernel and the header it is built with: a counter record
+# stays valid while neither changes (the reversed-step kernels live in
+# adjoint_kernels.hip, the sweeps in lbm_kernels.hip)
+def _srcs(kernel):
+    f = "adjoint_kernels.hip" if kernel.startswith("adj_") else "lbm_kernels.hip"
+    return [os.path.join(ROOT, "paper_1601_02708_amd", "csrc", n) for n in (f, "hyb_impl.h")]
 
 
-def kernel_hash():
+def kernel_hash(kernel="lbm_sweep"):
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
+    for path in _srcs(kernel):
         h.update(open(path, "rb").read())
     return h.hexdigest()[:16]
 
@@ -79,7 +82,7 @@ def traffic(fetch_csv, write_csv, out_path, workload, precision, copy_mib, comma
     f = statistics.mean(fetch[k])
     w = statistics.mean(write[k])
     rec = {
-        "kernel": k[:120], "workload": workload, "precision": precision, "kernel_sha": kernel_hash(),
+        "kernel": k[:120], "workload": workload, "precision": precision, "kernel_sha": kernel_hash(kernel),
         "fetch_kib_per_launch": f, "write_kib_per_launch": w,
         "copy_kib": copy_bytes_kib, "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
         "fetch_scale": f_scale, "write_scale": w_scale,
@@ -112,15 +115,18 @@ def sq(out_path, workload, precision, kernel, commands, *csv_paths):
     data = _per_kernel_all(csv_paths)
     tname = {"fp32": "float", "fp64": "double", "fp16s": "_Float16"}[precision]
     mname = {"fp32": "f", "fp64": "d", "fp16s": "DF16_"}[precision]
-    ks = [k for k in data if (f"{kernel}<{tname}" in k and ", 0>" in k) or
-          (kernel in k and f"I{mname}" in k and "Li0EEE" in k)]
+    # the whole-patch launch (tile part 0) of a sweep; the reversed-step
+    # kernels have no parts
+    whole = kernel.startswith("adj_")
+    ks = [k for k in data if (f"{kernel}<{tname}" in k and (whole or ", 0>" in k)) or
+          (kernel in k and f"I{mname}" in k and (whole or "Li0EEE" in k))]
     if not ks:
         raise SystemExit("kernel not found in the counter files")
     m = {c: statistics.mean(v) for c, v in data[ks[0]].items()}
     xcd_cycles = m["GRBM_GUI_ACTIVE"] / 8.0             # the counter sums the 8 XCDs
     simd_quads = 256 * 4 * xcd_cycles / 4.0
     rec = {
-        "kernel": ks[0][:120], "workload": workload, "precision": precision, "kernel_sha": kernel_hash(),
+        "kernel": ks[0][:120], "workload": workload, "precision": precision, "kernel_sha": kernel_hash(kernel),
         "counters": {c: m[c] for c in sorted(m)},
         "duration_us": xcd_cycles / 2400.0,
         "valu_busy": m["SQ_ACTIVE_INST_VALU"] / simd_quads,
