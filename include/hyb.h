@@ -274,11 +274,14 @@ int hyb_diagnostics_noalloc(hyb_handle *h, double *out);
  *   (n_sub + 4) population buffers (f_bytes each) and n_sub planes of the
  *   arithmetic type.
  * hyb_lbm_substeps_record: like hyb_lbm_substeps(h, n_sub, 1), recording
- *   f*(0) .. f*(n_sub) and, without dissolving solids, u of each fine step's
- *   collision (the reversed steps read it for dJ/dk) in the caller's device
- *   tape (256-byte aligned, >= tape bytes); 1 <= n_sub <= eta.
- * hyb_lbm_adjoint: tape and n_sub of the last record (the interface values
- *   and the handle must be unchanged since); lam_in, lam_out: device FP64
+ *   the intermediate states f*(1) .. f*(n_sub - 1) and, without dissolving
+ *   solids, u of each fine step's collision (the reversed steps read it for
+ *   dJ/dk) in the caller's device tape (256-byte aligned, >= tape bytes);
+ *   f*(0) and f*(n_sub) stay in the handle's committed and current buffers.
+ *   1 <= n_sub <= eta.
+ * hyb_lbm_adjoint: tape and n_sub of the last record; the handle must be
+ *   unchanged since (HYB_EINVAL after any call that steps, commits, or sets
+ *   populations, interface values or rates); lam_in, lam_out: device FP64
  *   [9][N][N] (index (q*N + j)*N + i), lam_in = dJ/df*(n_sub) (kept),
  *   lam_out = dJ/df*(0) (may alias lam_in); grad_a, grad_b: device FP64
  *   [4(N-1)] and grad_k: device FP64 [N*N] or NULL, each ADDED to.  The

@@ -236,6 +236,11 @@ struct hyb_handle {
     int steps_per_launch = 4;          // most fine steps per sweep launch (fuse_steps)
     const void *rec_tape = nullptr;     // last forward recording (hyb_lbm_substeps_record)
     int rec_n = 0;
+    // bumped by every call that changes the fine state, the interface
+    // values or the rate field; the fine-step adjoint reads the recorded
+    // start and end states from the handle's buffers, so it requires the
+    // count the record left (rec_gen)
+    unsigned long long gen = 0, rec_gen = 0;
     int *c2f_idx = nullptr, *fc_idx = nullptr;
     double *c2f_w = nullptr, *fc_w = nullptr, *ufc = nullptr;
     int nfc = 0;
@@ -694,6 +699,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
 
 int hyb_interface_exchange(hyb_handle *h, int direction) {
     if (!h) return HYB_EINVAL;
+    ++h->gen;
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "interface exchange needs a coarse mesh");
     if (direction == HYB_F2C) {
         LbmArgs a = h->lbm_args(h->cur, -1);
@@ -955,6 +961,7 @@ extern "C" {
 
 int hyb_lbm_substeps(hyb_handle *h, int n_sub, int restart) {
     if (!h) return HYB_EINVAL;
+    ++h->gen;
     return substeps_impl(h, n_sub, restart, -1, 0);
 }
 
@@ -970,6 +977,7 @@ int hyb_set_overlap(hyb_handle *h, int depth) {
 
 int hyb_commit(hyb_handle *h) {
     if (!h) return HYB_EINVAL;
+    ++h->gen;
     unsigned long long cnt[kCntSlots];
     KrylovResult kr{};
     HIP_TRY(h, hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
@@ -1011,6 +1019,7 @@ int hyb_commit(hyb_handle *h) {
 
 int hyb_step(hyb_handle *h, int max_schwarz) {
     if (!h) return HYB_EINVAL;
+    ++h->gen;
     if (!h->has_mesh) return h->fail(HYB_EINVAL, "hyb_step needs a coarse mesh");
     if (max_schwarz < 1) return h->fail(HYB_EINVAL, "max_schwarz must be >= 1");
     // overlap depth: fixed, tuned, or the next candidate while tuning (one
@@ -1065,6 +1074,7 @@ int hyb_step(hyb_handle *h, int max_schwarz) {
 
 int hyb_set_boundary(hyb_handle *h, const int8_t *kind, const double *a, const double *b) {
     if (!h || !a) return HYB_EINVAL;
+    ++h->gen;
     const size_t ns = 4 * (size_t)(h->N - 1);
     if (kind) {
         for (size_t p = 0; p < ns; ++p)
@@ -1143,6 +1153,7 @@ int hyb_get_populations(hyb_handle *h, double *out) {
 
 int hyb_set_populations(hyb_handle *h, const double *fin) {
     if (!h || !fin) return HYB_EINVAL;
+    ++h->gen;
     const int N = h->N, P = h->lay.pitch;
     const size_t elem = storage_bytes(h->prec);
     std::vector<char> stage((size_t)9 * h->lay.plane * elem, 0);
@@ -1182,6 +1193,7 @@ int hyb_set_coarse(hyb_handle *h, const double *d) {
 
 int hyb_set_reaction_field(hyb_handle *h, const double *k_field) {
     if (!h || !k_field) return HYB_EINVAL;
+    ++h->gen;
     const int N = h->N;
     const size_t P = (size_t)h->lay.pitch, nodes = (size_t)N * P;
     for (size_t n = 0; n < (size_t)N * N; ++n)
@@ -1273,12 +1285,21 @@ int hyb_adjoint_query(const hyb_handle *h, int n_sub, size_t *tape_bytes) {
 int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
     if (h && h->wall_on) return h->fail(HYB_EINVAL, "the adjoint supports bounce-back walls only");
     if (!h) return HYB_EINVAL;
+    ++h->gen;
     if (h->prec == HYB_FP16S) return h->fail(HYB_EINVAL, "the adjoint supports HYB_FP64 and HYB_FP32 storage");
     if (h->any_neumann) return h->fail(HYB_EINVAL, "the adjoint supports Dirichlet perimeter slots only");
     if (n_sub < 1 || n_sub > h->eta) return h->fail(HYB_EINVAL, "n_sub must lie in 1..eta");
     if (!tape || reinterpret_cast<uintptr_t>(tape) % kAlign) return h->fail(HYB_EINVAL, "tape must be 256-byte aligned");
     const size_t fb = h->lay.f_bytes;
-    auto slot = [&](int t) { return static_cast<char *>(tape) + (size_t)t * fb; };
+    // f*(0) is the committed buffer and f*(n_sub) goes straight to a spare
+    // buffer of the handle, which becomes its current state; the states in
+    // between go to the tape
+    const int dst = h->spare(-1);
+    auto state = [&](int t) -> void * {
+        if (t == 0) return h->f[h->frozen];
+        if (t == n_sub) return h->f[dst];
+        return static_cast<char *>(tape) + (size_t)t * fb;
+    };
     // u of step t's collision (t = 1 .. n_sub), after the states and the
     // three adjoint fields (not with dissolving solids, whose reversed steps
     // read the states)
@@ -1286,26 +1307,25 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
         if (h->dissolve_on) return nullptr;
         return static_cast<char *>(tape) + (size_t)(n_sub + 4) * fb + (size_t)(t - 1) * h->lay.u_bytes;
     };
-    HIP_TRY(h, hipMemcpyAsync(slot(0), h->f[h->frozen], fb, hipMemcpyDeviceToDevice, h->stream));
     // pairs of fine steps in one launch that also stores the state between
     // them, while the two-step sweep serves (not with dissolving solids,
     // whose steps sum link fluxes)
     const bool pairs = use_two_step(h) && !h->dissolve_on;
     for (int t = 0; t < n_sub;) {
         LbmArgs a = h->lbm_args(h->frozen, -1);
-        a.src = slot(t);
+        a.src = state(t);
         a.lam = (double)(t + 1) / (double)h->eta;
         a.u_out = uplane(t + 1);
         if (pairs && t + 2 <= n_sub) {
-            a.mid = slot(t + 1);
-            a.dst = slot(t + 2);
+            a.mid = state(t + 1);
+            a.dst = state(t + 2);
             a.u_out2 = uplane(t + 2);
             a.lam2 = (double)(t + 2) / (double)h->eta;
             HIP_TRY(h, launch_lbm_step2(a, h->prec, h->stream));
             t += 2;
             continue;
         }
-        a.dst = slot(t + 1);
+        a.dst = state(t + 1);
         if (h->dissolve_on) {
             a.flux = h->flux;
             a.flux_first = t == 0;
@@ -1314,13 +1334,12 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
         HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
         t += 1;
     }
-    const int dst = h->spare(-1);
-    HIP_TRY(h, hipMemcpyAsync(h->f[dst], slot(n_sub), fb, hipMemcpyDeviceToDevice, h->stream));
     h->cur = dst;
     h->jsub = n_sub;
     h->fine_steps += n_sub;
     h->rec_tape = tape;
     h->rec_n = n_sub;
+    h->rec_gen = h->gen;
     return HYB_OK;
 }
 
@@ -1329,10 +1348,19 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
     if (!h) return HYB_EINVAL;
     if (!tape || tape != h->rec_tape || n_sub != h->rec_n)
         return h->fail(HYB_EINVAL, "the tape and n_sub must be those of the last hyb_lbm_substeps_record");
+    if (h->gen != h->rec_gen) return h->fail(HYB_EINVAL, "the handle changed since hyb_lbm_substeps_record");
     if (!lam_in || !lam_out || !grad_a || !grad_b) return h->fail(HYB_EINVAL, "null adjoint argument");
     const size_t fb = h->lay.f_bytes;
     char *base = static_cast<char *>(const_cast<void *>(tape));
     auto slot = [&](int t) { return base + (size_t)t * fb; };
+    // the recorded states: f*(0) in the committed buffer, f*(n_sub) in the
+    // current one (the handle is unchanged since the record), the others in
+    // the tape
+    auto state = [&](int t) -> void * {
+        if (t == 0) return h->f[h->frozen];
+        if (t == n_sub) return h->f[h->cur];
+        return slot(t);
+    };
     auto uplane = [&](int t) -> const void * {
         if (h->dissolve_on) return nullptr;
         return base + (size_t)(n_sub + 4) * fb + (size_t)(t - 1) * h->lay.u_bytes;
@@ -1359,20 +1387,20 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
         double *dout = k == launches - 1 && dense_out ? lam_out : nullptr;
         if (pairs && t >= 1) {
             LbmArgs a1 = a, a2 = a;
-            a1.src = slot(t);
+            a1.src = state(t);
             a1.lam = (double)(t + 1) / (double)h->eta;
             a1.u_rec = uplane(t + 1);
-            a2.src = slot(t - 1);
+            a2.src = state(t - 1);
             a2.lam = (double)t / (double)h->eta;
             a2.u_rec = uplane(t);
-            HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, slot(t + 1), slot(t), lcur, lnext, grad_a, grad_b,
+            HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, state(t + 1), state(t), lcur, lnext, grad_a, grad_b,
                                             grad_k, h->stream, nullptr, nullptr, din, dout, false));
             t -= 2;
         } else {
-            a.src = slot(t);
+            a.src = state(t);
             a.lam = (double)(t + 1) / (double)h->eta;
             a.u_rec = uplane(t + 1);
-            HIP_TRY(h, launch_adjoint_step(a, h->prec, slot(t + 1), lcur, nu, lnext, grad_a, grad_b, grad_k,
+            HIP_TRY(h, launch_adjoint_step(a, h->prec, state(t + 1), lcur, nu, lnext, grad_a, grad_b, grad_k,
                                            h->stream, nullptr, din, dout, false));
             t -= 1;
         }
@@ -1443,6 +1471,7 @@ int hyb_step_adjoint_query(const hyb_handle *h, int passes, size_t *tape_bytes) 
 
 int hyb_step_record(hyb_handle *h, int passes, void *tape) {
     if (!h) return HYB_EINVAL;
+    ++h->gen;
     int rc = step_adjoint_supported(h);
     if (rc != HYB_OK) return rc;
     if (passes < 1) return h->fail(HYB_EINVAL, "passes must be >= 1");
@@ -1703,6 +1732,7 @@ const char *hyb_last_error(const hyb_handle *h) { return h ? h->err.c_str() : "n
 
 int hyb_set_wall_normals(hyb_handle *h, const float *normals) {
     if (!h) return HYB_EINVAL;
+    ++h->gen;
     if (!h->wall_ws) return h->fail(HYB_EINVAL, "the handle was created without the wall closure");
     if (h->jsub != 0 || h->cur != h->frozen)
         return h->fail(HYB_EINVAL, "set the wall closure between coarse steps (fine steps are pending)");
@@ -1742,6 +1772,7 @@ int hyb_set_wall_normals(hyb_handle *h, const float *normals) {
 
 int hyb_set_dissolution(hyb_handle *h, double kappa_s, double c_sat, const double *mass) {
     if (!h) return HYB_EINVAL;
+    ++h->gen;
     if (!h->dissolve_ws) return h->fail(HYB_EINVAL, "the handle was created without dissolution");
     if (!(kappa_s >= 0.0 && kappa_s <= 1.0)) return h->fail(HYB_EINVAL, "kappa_s must lie in [0, 1]");
     if (!std::isfinite(c_sat)) return h->fail(HYB_EINVAL, "c_sat must be finite");
@@ -1841,6 +1872,7 @@ int hyb_checkpoint_save(hyb_handle *h, void *ckpt) {
 
 int hyb_checkpoint_load(hyb_handle *h, const void *ckpt) {
     if (!h || !ckpt || reinterpret_cast<uintptr_t>(ckpt) % kAlign) return HYB_EINVAL;
+    ++h->gen;
     const CkptLayout C = ckpt_layout(h);
     const char *b = static_cast<const char *>(ckpt);
     const size_t nodes = (size_t)h->N * h->lay.pitch;
@@ -1867,6 +1899,7 @@ int hyb_checkpoint_load(hyb_handle *h, const void *ckpt) {
 
 int hyb_set_solids(hyb_handle *h, const uint8_t *solid, const double *mass) {
     if (!h || !solid || !mass) return HYB_EINVAL;
+    ++h->gen;
     if (!h->dissolve_ws) return h->fail(HYB_EINVAL, "the handle was created without dissolution");
     if (h->jsub != 0 || h->cur != h->frozen)
         return h->fail(HYB_EINVAL, "set the solids between coarse steps (fine steps are pending)");

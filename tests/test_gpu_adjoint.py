@@ -178,6 +178,37 @@ def test_adjoint_rejects_unsupported():
         g.substeps_record(4, g.adjoint_tape(4))                   # past eta
 
 
+def test_adjoint_requires_the_recorded_handle():
+    """The reversed steps read the recorded start and end states from the
+    handle's buffers: any call that changes the handle between the record and
+    the adjoint (new interface values, populations, a commit, more fine
+    steps) makes hyb_lbm_adjoint fail instead of reversing other data."""
+    hyb, torch = _gpu()
+    N, P = 16, 4 * 15
+    z = np.zeros((N, N))
+    g = hyb.Hybrid(N=N, x0=0, y0=0, u0=z + 0.5, vx=z, vy=z, D=0.05, eta=3)
+    lam = torch.ones((9, N, N), dtype=torch.float64, device=g.dev)
+    out = torch.empty_like(lam)
+    ga = torch.zeros(P, dtype=torch.float64, device=g.dev)
+    gb = torch.zeros_like(ga)
+    tape = g.adjoint_tape(2)
+    changes = [lambda: g.set_boundary(np.full(P, 0.3), np.full(P, 0.4)),
+               lambda: g.set_populations(g.get_populations()),
+               lambda: g.lbm_substeps(1, restart=0),
+               lambda: g.commit()]
+    for change in changes:
+        g.substeps_record(2, tape)
+        change()
+        with pytest.raises(hyb.HybError):
+            g.adjoint(2, tape, lam, out, ga, gb)
+    g.substeps_record(2, tape)
+    g.get_populations()                                            # reading changes nothing
+    g.stats()
+    g.adjoint(2, tape, lam, out, ga, gb)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all()
+
+
 @pytest.mark.parametrize("precision,N,clamp,eta", [("fp64", 130, 1, 7), ("fp32", 97, 0, 6), ("fp64", 4, 0, 5)])
 def test_paired_reversed_steps_equal_single_steps(precision, N, clamp, eta):
     """hyb_lbm_adjoint with reversed steps in pairs (one launch for two
