@@ -309,11 +309,12 @@ int hyb_lbm_adjoint(hyb_handle *h, int n_sub, const void *tape, const double *la
  * hyb_step_record: hyb_step(h, passes) run with one- and two-step
  *   launches, recording the fine states (and, without dissolving solids, u
  *   of each fine step's collision), interface arrays and the state the
- *   transfers read in the caller's device tape (256-byte aligned); commits
- *   the step as hyb_step does (same errors; nothing is recorded on an
- *   error).
+ *   transfers read in the caller's device tape (256-byte aligned); f*(t_n)
+ *   and the step's end state stay in the handle's buffers.  Commits the step
+ *   as hyb_step does (same errors; nothing is recorded on an error).
  * hyb_step_adjoint: for the last record (tape pointer of that call; the
- *   handle may have committed that step since, but no later one):
+ *   handle must be unchanged since, HYB_EINVAL after any call that steps,
+ *   commits, or sets populations, interface values or rates):
  *   lam_f = dJ/df*(t_{n+1}) (device FP64 [9][N][N], index (q*N + j)*N + i),
  *   lam_sub = the cotangent of every intermediate fine state of the
  *   committed (last) pass, f*(t_n + j) for j = 1 .. eta-1 (same layout, or

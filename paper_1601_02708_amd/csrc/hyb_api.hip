@@ -251,6 +251,9 @@ struct hyb_handle {
     double *c2fT_w = nullptr, *f2cT_w = nullptr;
     int f2cT_n = 0;
     const void *rec_step_tape = nullptr;    // last hyb_step_record
+    // the record's start and end states stay in these buffers (checked by gen)
+    int rec_step_f0 = -1, rec_step_out = -1;
+    unsigned long long rec_step_gen = 0;
     int rec_step_passes = 0;
     // dissolving solids: workspace reserved (dissolve_ws), reaction on
     // (dissolve_on, from hyb_set_dissolution); flux_valid: the fine steps
@@ -1480,7 +1483,15 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
     const size_t fb = h->lay.f_bytes;
     const size_t nslots = 4 * (size_t)(h->N - 1);
     char *base = static_cast<char *>(tape);
-    auto state = [&](int p, int t) { return base + T.states + (t == 0 ? 0 : (1 + (size_t)p * h->eta + t - 1) * fb); };
+    // f*(t_n) stays in the committed buffer and the last pass's end state
+    // is written straight to the buffer the commit makes current; the other
+    // fine states go to the tape
+    const int f0 = h->frozen, out = h->spare(-1);
+    auto state = [&](int p, int t) -> char * {
+        if (t == 0) return static_cast<char *>(h->f[f0]);
+        if (p == passes - 1 && t == h->eta) return static_cast<char *>(h->f[out]);
+        return base + T.states + (1 + (size_t)p * h->eta + t - 1) * fb;
+    };
     // u of fine step t of pass p (t = 1 .. eta; not with dissolving solids,
     // whose reversed steps read the states)
     auto uplane = [&](int p, int t) -> void * {
@@ -1493,11 +1504,9 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
         h->cur = h->frozen;
         h->jsub = 0;
         h->solved_this_step = false;
-        HIP_TRY(h, hipMemcpyAsync(state(0, 0), h->f[h->frozen], fb, hipMemcpyDeviceToDevice, h->stream));
         if (h->dissolve_ws)
             HIP_TRY(h, hipMemcpyAsync(base + T.mask, h->mask, (size_t)h->N * h->lay.pitch * 2, hipMemcpyDeviceToDevice,
                                       h->stream));
-        const int out = h->spare(-1);
         for (int p = 0; p < passes; ++p) {
             if ((rc = hyb_interface_exchange(h, HYB_F2C)) != HYB_OK) return rc;
             if ((rc = hyb_coarse_step(h, 200)) != HYB_OK) return rc;
@@ -1529,7 +1538,9 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
                 HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
                 t += 1;
             }
-            HIP_TRY(h, hipMemcpyAsync(h->f[out], state(p, h->eta), fb, hipMemcpyDeviceToDevice, h->stream));
+            // the next pass's fine-to-coarse transfer reads the current buffer
+            if (p < passes - 1)
+                HIP_TRY(h, hipMemcpyAsync(h->f[out], state(p, h->eta), fb, hipMemcpyDeviceToDevice, h->stream));
             h->cur = out;
             h->jsub = h->eta;
             h->fine_steps += h->eta;
@@ -1546,6 +1557,9 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
                                       hipMemcpyDeviceToDevice, h->stream));
         h->rec_step_tape = tape;
         h->rec_step_passes = passes;
+        h->rec_step_f0 = f0;
+        h->rec_step_out = out;
+        h->rec_step_gen = h->gen;
     }
     return rc;
 }
@@ -1556,13 +1570,18 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
     int rc = step_adjoint_supported(h);
     if (rc != HYB_OK) return rc;
     if (!tape || tape != h->rec_step_tape) return h->fail(HYB_EINVAL, "the tape must be that of the last hyb_step_record");
+    if (h->gen != h->rec_step_gen) return h->fail(HYB_EINVAL, "the handle changed since hyb_step_record");
     if (!lam_f || !lam_f_out || !lam_d_out) return h->fail(HYB_EINVAL, "null adjoint argument");
     const int passes = h->rec_step_passes;
     const StepTape T = step_tape_layout(h, passes);
     const size_t fb = h->lay.f_bytes;
     const size_t nslots = 4 * (size_t)(h->N - 1);
     char *base = static_cast<char *>(const_cast<void *>(tape));
-    auto state = [&](int p, int t) { return base + T.states + (t == 0 ? 0 : (1 + (size_t)p * h->eta + t - 1) * fb); };
+    auto state = [&](int p, int t) -> char * {
+        if (t == 0) return static_cast<char *>(h->f[h->rec_step_f0]);
+        if (p == passes - 1 && t == h->eta) return static_cast<char *>(h->f[h->rec_step_out]);
+        return base + T.states + (1 + (size_t)p * h->eta + t - 1) * fb;
+    };
     auto uplane = [&](int p, int t) -> const void * {
         if (h->dissolve_ws) return nullptr;
         return base + T.u + ((size_t)p * h->eta + t - 1) * h->lay.u_bytes;

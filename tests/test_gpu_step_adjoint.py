@@ -182,6 +182,38 @@ def test_step_adjoint_rejects():
         g2.step_record(1, g.step_tape(1))
 
 
+def test_step_adjoint_requires_the_recorded_handle():
+    """f*(t_n) and the step's end state stay in the handle's buffers: a call
+    that changes the handle between hyb_step_record and hyb_step_adjoint
+    (another step, fine steps, a commit, new populations or interface values)
+    makes the adjoint fail; reading the state does not."""
+    hyb, torch = _gpu()
+    p = _problem("small")
+    N, M = p.cfg.N, p.cfg.M
+    g = hyb.Hybrid.from_problem(p, precision="fp64")
+    tape = g.step_tape(2)
+    lf = torch.ones((9, N, N), dtype=torch.float64, device=g.dev)
+    ld = torch.zeros((M + 1) ** 2, dtype=torch.float64, device=g.dev)
+    of, od = torch.empty_like(lf), torch.empty_like(ld)
+    changes = [lambda: g.step(2),
+               lambda: g.lbm_substeps(1, restart=1),
+               lambda: g.commit(),
+               lambda: g.set_populations(g.get_populations()),
+               lambda: g.interface_exchange(hyb.HYB_C2F)]
+    for change in changes:
+        g.step_record(2, tape)
+        change()
+        with pytest.raises(hyb.HybError):
+            g.step_adjoint(tape, lf, ld, of, od)
+    g.step_record(2, tape)
+    g.get_populations()
+    g.concentration(hyb.HYB_COARSE)
+    g.step_adjoint(tape, lf, ld, of, od)
+    torch.cuda.synchronize()
+    assert torch.isfinite(of).all() and torch.isfinite(od).all()
+    g.close()
+
+
 def test_set_coarse_round_trip():
     hyb, torch = _gpu()
     p = _problem("small")
