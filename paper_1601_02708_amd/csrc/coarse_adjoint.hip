@@ -3,7 +3,8 @@
 // with strong Dirichlet rows (eq. FEM_discrete) and of the fine-to-coarse
 // transfer (Sec. 6.2, item ii).  Every transpose is a gather over lists or
 // stencils built on the host, so each output element is written by one lane
-// and summed in a fixed order (deterministic, no atomics).
+// (or one wavefront) and summed in a fixed order (deterministic, no
+// atomics).
 #include "hyb_impl.h"
 
 namespace hyb {
@@ -17,20 +18,32 @@ __device__ __forceinline__ int pad_of(const CoarseDev &c, int node) {
 }
 
 // lam_dn += C^T ga, lam_d1 = C^T gb (+ lam_d_dense) at every mesh node
-__global__ void c2f_transpose_kernel(CoarseDev c, const int *__restrict__ ptr, const int *__restrict__ slot,
-                                     const double *__restrict__ w, const double *__restrict__ ga,
-                                     const double *__restrict__ gb, const double *__restrict__ lam_d_dense,
-                                     double *__restrict__ lam_dn, double *__restrict__ lam_d1) {
-    const int node = blockIdx.x * blockDim.x + threadIdx.x;
-    if (node >= c.n) return;
+// One wavefront per mesh node: a node of an element the patch perimeter
+// crosses gathers thousands of slots, so lane l sums entries l, l + 64, ...
+// of the node's list and the lanes combine in a fixed tree (deterministic).
+constexpr int kGatherLanes = 64;
+__global__ void __launch_bounds__(kGatherLanes)
+    c2f_transpose_kernel(CoarseDev c, const int *__restrict__ ptr, const int *__restrict__ slot,
+                         const double *__restrict__ w, const double *__restrict__ ga, const double *__restrict__ gb,
+                         const double *__restrict__ lam_d_dense, double *__restrict__ lam_dn,
+                         double *__restrict__ lam_d1) {
+    const int node = blockIdx.x;
+    const int lane = threadIdx.x;
     double sa = 0.0, sb = 0.0;
-    for (int e = ptr[node]; e < ptr[node + 1]; ++e) {
+    for (int e = ptr[node] + lane; e < ptr[node + 1]; e += kGatherLanes) {
         sa += w[e] * ga[slot[e]];
         sb += w[e] * gb[slot[e]];
     }
-    const int pi = pad_of(c, node);
-    lam_dn[pi] += sa;
-    lam_d1[pi] = lam_d_dense ? sb + lam_d_dense[node] : sb;
+#pragma unroll
+    for (int off = kGatherLanes / 2; off > 0; off >>= 1) {
+        sa += __shfl_down(sa, off, kGatherLanes);
+        sb += __shfl_down(sb, off, kGatherLanes);
+    }
+    if (lane == 0) {
+        const int pi = pad_of(c, node);
+        lam_dn[pi] += sa;
+        lam_d1[pi] = lam_d_dense ? sb + lam_d_dense[node] : sb;
+    }
 }
 
 // out = S in at every mesh node, S offset-major of width W (halo >= W/2)
@@ -127,7 +140,7 @@ int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 hipError_t launch_c2f_transpose(const CoarseDev &c, const int *ptr, const int *slot, const double *w, const double *ga,
                                 const double *gb, const double *lam_d_dense, double *lam_dn, double *lam_d1,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(c2f_transpose_kernel, dim3(blocks_for(c.n)), dim3(kBlock), 0, s, c, ptr, slot, w, ga, gb,
+    hipLaunchKernelGGL(c2f_transpose_kernel, dim3(c.n), dim3(kGatherLanes), 0, s, c, ptr, slot, w, ga, gb,
                        lam_d_dense, lam_dn, lam_d1);
     return hipGetLastError();
 }

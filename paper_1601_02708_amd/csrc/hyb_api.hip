@@ -1596,7 +1596,6 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
     double *mu = reinterpret_cast<double *>(base + T.coarse + 3 * vs);
     double *lam_ufc = reinterpret_cast<double *>(base + T.lufc);
     KrylovResult *kr = reinterpret_cast<KrylovResult *>(base + T.kres);
-    const size_t dense_bytes = (size_t)9 * h->N * h->N * 8;
     LbmArgs a = h->lbm_args(h->frozen, -1);
     const bool dissolving = h->dissolve_ws;
     if (dissolving) a.mask = reinterpret_cast<const uint16_t *>(base + T.mask);   // the step's geometry
@@ -1619,7 +1618,8 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
         HIP_TRY(h, launch_adjoint_pack(a, h->prec, lam_sub, nu, true, h->stream));
         inj = nu;
     }
-    HIP_TRY(h, hipMemsetAsync(lam_f_out, 0, dense_bytes, h->stream));
+    // lam_f_out: the last reversed launch of the first pass reversed writes
+    // it whole (zeros at solid nodes), the other passes and the transfer add
     // the padded coarse vectors keep a zero halo (stencils read it)
     HIP_TRY(h, hipMemsetAsync(base + T.coarse, 0, 4 * vs, h->stream));
     CoarseDev ct = h->cd;
@@ -1641,6 +1641,7 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
             // the pass's last launch adds its output to lam_f_out directly
             const double *din = dense_in && p == passes - 1 && k == 0 ? lam_f : nullptr;
             double *dout = k == launches - 1 ? lam_f_out : nullptr;
+            const bool add = p != passes - 1;
             if (h->steps_per_launch >= 2 && t >= 2) {
                 // steps t and t-1 reversed in one launch
                 LbmArgs a1 = a, a2 = a;
@@ -1652,14 +1653,14 @@ int hyb_step_adjoint(hyb_handle *h, const void *tape, const double *lam_f, const
                 a2.u_rec = uplane(p, t - 1);
                 HIP_TRY(h, launch_adjoint_step2(a1, a2, h->prec, state(p, t), state(p, t - 1), lcur, lnext, ga, gb,
                                                 grad_k, h->stream, inj_p, t - 2 >= 1 ? inj_p : nullptr, din, dout,
-                                                true));
+                                                add));
                 t -= 2;
             } else {
                 a.src = state(p, t - 1);
                 a.lam = (double)t / (double)h->eta;
                 a.u_rec = uplane(p, t);
                 HIP_TRY(h, launch_adjoint_step(a, h->prec, state(p, t), lcur, nu, lnext, ga, gb, grad_k, h->stream,
-                                               t - 1 >= 1 ? inj_p : nullptr, din, dout, true));
+                                               t - 1 >= 1 ? inj_p : nullptr, din, dout, add));
                 t -= 1;
             }
             std::swap(lcur, lnext);
