@@ -1311,14 +1311,19 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
         return static_cast<char *>(tape) + (size_t)(n_sub + 4) * fb + (size_t)(t - 1) * h->lay.u_bytes;
     };
     // pairs of fine steps in one launch that also stores the state between
-    // them, while the two-step sweep serves (not with dissolving solids,
-    // whose steps sum link fluxes)
-    const bool pairs = use_two_step(h) && !h->dissolve_on;
+    // them, while the two-step sweep serves (with dissolving solids the pair
+    // also sums both steps' link fluxes)
+    const bool pairs = use_two_step(h);
     for (int t = 0; t < n_sub;) {
         LbmArgs a = h->lbm_args(h->frozen, -1);
         a.src = state(t);
         a.lam = (double)(t + 1) / (double)h->eta;
         a.u_out = uplane(t + 1);
+        if (h->dissolve_on) {
+            a.flux = h->flux;
+            a.flux_first = t == 0;
+            h->flux_valid = true;
+        }
         if (pairs && t + 2 <= n_sub) {
             a.mid = state(t + 1);
             a.dst = state(t + 2);
@@ -1329,11 +1334,6 @@ int hyb_lbm_substeps_record(hyb_handle *h, int n_sub, void *tape) {
             continue;
         }
         a.dst = state(t + 1);
-        if (h->dissolve_on) {
-            a.flux = h->flux;
-            a.flux_first = t == 0;
-            h->flux_valid = true;
-        }
         HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
         t += 1;
     }
@@ -1513,12 +1513,17 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
             if ((rc = hyb_interface_exchange(h, HYB_C2F)) != HYB_OK) return rc;
             if (p == 0) HIP_TRY(h, hipMemcpyAsync(bc, h->bc_a, nslots * 8, hipMemcpyDeviceToDevice, h->stream));
             HIP_TRY(h, hipMemcpyAsync(bc + (1 + p) * nslots, h->bc_b, nslots * 8, hipMemcpyDeviceToDevice, h->stream));
-            const bool pairs = use_two_step(h) && !h->dissolve_on;
+            const bool pairs = use_two_step(h);
             for (int t = 1; t <= h->eta;) {
                 LbmArgs a = h->lbm_args(h->frozen, -1);
                 a.src = state(p, t - 1);
                 a.lam = (double)t / (double)h->eta;
                 a.u_out = uplane(p, t);
+                if (h->dissolve_on) {
+                    a.flux = h->flux;
+                    a.flux_first = t == 1;
+                    h->flux_valid = true;
+                }
                 if (pairs && t + 1 <= h->eta) {
                     // two fine steps, the state between them kept as well
                     a.mid = state(p, t);
@@ -1530,11 +1535,6 @@ int hyb_step_record(hyb_handle *h, int passes, void *tape) {
                     continue;
                 }
                 a.dst = state(p, t);
-                if (h->dissolve_on) {
-                    a.flux = h->flux;
-                    a.flux_first = t == 1;
-                    h->flux_valid = true;
-                }
                 HIP_TRY(h, launch_lbm_step(a, h->prec, false, h->stream));
                 t += 1;
             }

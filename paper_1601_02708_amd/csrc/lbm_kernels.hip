@@ -112,6 +112,13 @@ __device__ __forceinline__ int xcd_tile(int b, int T) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// Whether the region of rows y0 - r .. y0 + h - 1 + r and columns x0 - r ..
+// x0 + w - 1 + r reaches the patch perimeter (uniform across a workgroup:
+// the per-node perimeter test only runs in tiles where it can hold).
+__device__ __forceinline__ bool reaches_perimeter(int N, int x0, int y0, int w, int h, int r) {
+    return x0 - r <= 0 || y0 - r <= 0 || x0 + w - 1 + r >= N - 1 || y0 + h - 1 + r >= N - 1;
+}
+
 // ---------------------------------------------------------------------------
 // Single fine step
 // ---------------------------------------------------------------------------
@@ -536,6 +543,7 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
     tile_of<PART>(map, xcd_tile(blockIdx.x, map.count), tx, ty);
     const int x0 = tx * TW;
     const int y0 = ty * TH;
+    const bool edge = reaches_perimeter(N, x0, y0, TW, TH, 1), edge2 = reaches_perimeter(N, x0, y0, TW, TH, 0);
 
     // ---- first half: step j+1 on the tile and its ring, into LDS --------
     // Pull x - e_q reads plane q at row j - cy_q, column i - cx_q, both
@@ -623,7 +631,7 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
             if constexpr (FLUX) f[q] = ((m[k] >> q) & 1u) ? reactive<T>(a, own, q) : pulled;
             else f[q] = ((m[k] >> q) & 1u) ? own : pulled;
         }
-        if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
+        if (edge && (i == 0 || j == 0 || i == N - 1 || j == N - 1)) {
             const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
             if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
         }
@@ -709,7 +717,7 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
         const int r = idx / TW, c = idx % TW;
         const int i = x0 + c, j = y0 + r;
         const unsigned n = static_cast<unsigned>(j * P + i);
-        const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
+        const bool perim = edge2 && (i == 0 || j == 0 || i == N - 1 || j == N - 1);
         const unsigned unknown = perim ? outside_bits(N, i, j) : 0u;
         T g[kQ];
         {
@@ -759,6 +767,12 @@ __global__ void __launch_bounds__(NT) lbm_sweep2_flux_kernel(LbmArgs a, TileMap 
 template <typename S, int TW, int TH, int NT>
 __global__ void __launch_bounds__(NT) lbm_sweep2_rec_kernel(LbmArgs a, TileMap map) {
     sweep2_body<S, TW, TH, NT, 0, false, true>(a, map);
+}
+
+// the same with the surface reaction of dissolving solids and its link fluxes
+template <typename S, int TW, int TH, int NT>
+__global__ void __launch_bounds__(NT) lbm_sweep2_flux_rec_kernel(LbmArgs a, TileMap map) {
+    sweep2_body<S, TW, TH, NT, 0, true, true>(a, map);
 }
 
 // ---------------------------------------------------------------------------
@@ -854,6 +868,7 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
     const unsigned SP = static_cast<unsigned>(a.plane);
     const T omega = T(a.omega);
     const double lam = stage_lam(a, STAGE);
+    const bool edge = reaches_perimeter(N, x0, y0, TW, TH, RING);
     T h[R::ROUNDS][kQ];
 #pragma unroll
     for (int k = 0; k < R::ROUNDS; ++k) {
@@ -862,7 +877,7 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
         const int i = x0 - RING + c, j = y0 - RING + r;
         const unsigned n = static_cast<unsigned>(j * P + i);
         const bool owned = r >= RING && r < RING + TH && c >= RING && c < RING + TW;
-        const bool perim = i == 0 || j == 0 || i == N - 1 || j == N - 1;
+        const bool perim = edge && (i == 0 || j == 0 || i == N - 1 || j == N - 1);
         // one LDS read per direction at a selected address (upstream value,
         // or the node's own opposite value for a solid upstream node);
         // closure unknowns are overwritten below
@@ -955,6 +970,7 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
     tile_of<PART>(map, xcd_tile(blockIdx.x, map.count), tx, ty);
     const int x0 = tx * TW;
     const int y0 = ty * TH;
+    const bool edge = reaches_perimeter(N, x0, y0, TW, TH, G);
 
     // dissolving solids: flag words of the owned nodes, and for each owned
     // solid node with fluid neighbours its running flux sum (the previous
@@ -1054,7 +1070,7 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
             if constexpr (FLUX) f[q] = ((m[k] >> q) & 1u) ? reactive<T>(a, own, q) : pulled;
             else f[q] = ((m[k] >> q) & 1u) ? own : pulled;
         }
-        if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
+        if (edge && (i == 0 || j == 0 || i == N - 1 || j == N - 1)) {
             const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
             if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
         }
@@ -1233,8 +1249,11 @@ hipError_t step2_impl(const LbmArgs &a, int part, int depth, int ring, hipStream
     if (m.count == 0) return hipSuccess;
     if (a.flux || a.kappa_s != 0.0) {
         // dissolving solids: whole-patch launches only
-        if (m.part != 0 || a.mid) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((lbm_sweep2_flux_kernel<S, TW, TH, NT>), dim3(m.count), dim3(NT), 0, s, a, m);
+        if (m.part != 0) return hipErrorInvalidValue;
+        if (a.mid)
+            hipLaunchKernelGGL((lbm_sweep2_flux_rec_kernel<S, TW, TH, NT>), dim3(m.count), dim3(NT), 0, s, a, m);
+        else
+            hipLaunchKernelGGL((lbm_sweep2_flux_kernel<S, TW, TH, NT>), dim3(m.count), dim3(NT), 0, s, a, m);
         return hipGetLastError();
     }
     if (a.mid) {
