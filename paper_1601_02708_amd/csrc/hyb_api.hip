@@ -292,6 +292,10 @@ struct hyb_handle {
     int overlap = HYB_OVERLAP_AUTO;
     hipStream_t side = nullptr;
     hipEvent_t ev_main = nullptr, ev_f2c = nullptr;
+    // the previous pass's fine-to-coarse transfer, recorded after it reads
+    // the fine state: when a pass is one launch, the next pass's deep tiles
+    // only wait for that read (see hyb_step)
+    hipEvent_t ev_read = nullptr;
     std::vector<hipEvent_t> ev_deep;
     // depth tuning (HYB_OVERLAP_AUTO): step times per depth, best of two
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
@@ -301,6 +305,7 @@ struct hyb_handle {
     ~hyb_handle() {
         if (ev_main) (void)hipEventDestroy(ev_main);
         if (ev_f2c) (void)hipEventDestroy(ev_f2c);
+        if (ev_read) (void)hipEventDestroy(ev_read);
         if (ev_t0) (void)hipEventDestroy(ev_t0);
         if (ev_t1) (void)hipEventDestroy(ev_t1);
         for (hipEvent_t e : ev_deep) (void)hipEventDestroy(e);
@@ -448,6 +453,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
     if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_f2c, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_read, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&h->ev_t0) != hipSuccess || hipEventCreate(&h->ev_t1) != hipSuccess)
         return bail(HYB_EHIP, "could not create the handle's side stream and events");
     h->lay = make_layout(mesh, lat, true);
@@ -916,7 +922,7 @@ int substeps_impl(hyb_handle *h, int n_sub, int restart, int first_dst, int deep
 // launches also follow the fine-to-coarse transfer, which the caller
 // enqueues between the two calls (the buffer it reads may be the one that
 // launch 1 writes).
-int prelaunch_deep(hyb_handle *h, int dst, int deep, bool after_f2c) {
+int prelaunch_deep(hyb_handle *h, int dst, int deep, bool after_f2c, bool after_read = false) {
     // the pass's launch plan (as substeps_impl takes it for eta steps):
     // launch j covers fine steps start[j] + 1 .. start[j] + take[j]
     const int fuse = fuse_steps(h);
@@ -939,8 +945,16 @@ int prelaunch_deep(hyb_handle *h, int dst, int deep, bool after_f2c) {
         h->ev_deep.push_back(e);
     }
     if (!after_f2c) {
-        HIP_TRY(h, hipEventRecord(h->ev_main, h->stream));
-        HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_main, 0));
+        // after_read: the pass's first launch is its only one, so its deep
+        // tiles overwrite only the buffer the previous pass's fine-to-coarse
+        // transfer read (they read the frozen state, and the previous pass
+        // wrote the other buffer): waiting for that read suffices
+        if (after_read) {
+            HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_read, 0));
+        } else {
+            HIP_TRY(h, hipEventRecord(h->ev_main, h->stream));
+            HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_main, 0));
+        }
         HIP_TRY(h, launch(0, h->frozen, dst));
         HIP_TRY(h, hipEventRecord(h->ev_deep[0], h->side));
         return HYB_OK;
@@ -1036,6 +1050,8 @@ int hyb_step(hyb_handle *h, int max_schwarz) {
         depth = dmax == 0 ? 0 : !tuning ? h->tuned_depth : h->tune_idx == 0 ? 0 : (h->tune_idx - 1) % ncand;
     if (tuning) HIP_TRY(h, hipEventRecord(h->ev_t0, h->stream));
     int rc = HYB_OK;
+    // a pass of one multi-step launch (eta fine steps in one launch)
+    const bool one_launch = fuse_steps(h) >= 2 && plan_take(fuse_steps(h), h->eta) == h->eta;
     for (int attempt = 0; attempt < 2; ++attempt) {
         h->cur = h->frozen;
         h->jsub = 0;
@@ -1047,9 +1063,10 @@ int hyb_step(hyb_handle *h, int max_schwarz) {
             int first_dst = -1;
             if (deep > 0) {
                 first_dst = h->cur == h->frozen ? h->spare(-1) : h->spare(h->cur);
-                if ((rc = prelaunch_deep(h, first_dst, deep, false)) != HYB_OK) return rc;
+                if ((rc = prelaunch_deep(h, first_dst, deep, false, it > 0 && one_launch)) != HYB_OK) return rc;
             }
             if ((rc = hyb_interface_exchange(h, HYB_F2C)) != HYB_OK) return rc;
+            if (one_launch && deep > 0) HIP_TRY(h, hipEventRecord(h->ev_read, h->stream));
             if (deep > 1 && (rc = prelaunch_deep(h, first_dst, deep, true)) != HYB_OK) return rc;
             if ((rc = hyb_coarse_step(h, 200)) != HYB_OK) return rc;
             if ((rc = hyb_interface_exchange(h, HYB_C2F)) != HYB_OK) return rc;
