@@ -297,6 +297,14 @@ struct hyb_handle {
     // only wait for that read (see hyb_step)
     hipEvent_t ev_read = nullptr;
     std::vector<hipEvent_t> ev_deep;
+    // pinned host copy of the counters and the last coarse solve's result,
+    // which every commit reads back (a copy into pageable memory stalls the
+    // host for tens of microseconds per step)
+    struct ReadBack {
+        unsigned long long cnt[kCntSlots];
+        KrylovResult kr;
+    };
+    ReadBack *rb = nullptr;
     // depth tuning (HYB_OVERLAP_AUTO): step times per depth, best of two
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
     int tune_idx = 0, tuned_depth = -1;
@@ -306,6 +314,7 @@ struct hyb_handle {
         if (ev_main) (void)hipEventDestroy(ev_main);
         if (ev_f2c) (void)hipEventDestroy(ev_f2c);
         if (ev_read) (void)hipEventDestroy(ev_read);
+        if (rb) (void)hipHostFree(rb);
         if (ev_t0) (void)hipEventDestroy(ev_t0);
         if (ev_t1) (void)hipEventDestroy(ev_t1);
         for (hipEvent_t e : ev_deep) (void)hipEventDestroy(e);
@@ -456,6 +465,9 @@ int hyb_create(const hyb_mesh *mesh, const hyb_lattice *lat, double D, const hyb
         hipEventCreateWithFlags(&h->ev_read, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&h->ev_t0) != hipSuccess || hipEventCreate(&h->ev_t1) != hipSuccess)
         return bail(HYB_EHIP, "could not create the handle's side stream and events");
+    if (hipHostMalloc(reinterpret_cast<void **>(&h->rb), sizeof(hyb_handle::ReadBack), hipHostMallocDefault) !=
+        hipSuccess)
+        return bail(HYB_EHIP, "could not allocate the handle's pinned read-back buffer");
     h->lay = make_layout(mesh, lat, true);
     const Layout &L = h->lay;
     if ((long long)9 * L.plane >= (1LL << 31)) return bail(HYB_EINVAL, "lattice too large for 32-bit indexing");
@@ -995,12 +1007,13 @@ int hyb_set_overlap(hyb_handle *h, int depth) {
 int hyb_commit(hyb_handle *h) {
     if (!h) return HYB_EINVAL;
     ++h->gen;
-    unsigned long long cnt[kCntSlots];
-    KrylovResult kr{};
-    HIP_TRY(h, hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipMemcpyAsync(&kr, h->kres, sizeof(kr), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->rb->cnt, h->counters, sizeof(h->rb->cnt), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&h->rb->kr, h->kres, sizeof(KrylovResult), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     HIP_TRY(h, h->drain_events());
+    unsigned long long cnt[kCntSlots];
+    for (int k = 0; k < kCntSlots; ++k) cnt[k] = h->rb->cnt[k];
+    const KrylovResult kr = h->rb->kr;
     if (cnt[kCntNonfinite] != h->seen_nonfinite) {
         h->seen_nonfinite = cnt[kCntNonfinite];
         return h->fail(HYB_ENONFINITE, "non-finite concentration in the fine subdomain; state not committed");
