@@ -25,7 +25,9 @@
  * after it returns.  Device memory is owned by the caller: three population
  * buffers of hyb_query()'s f_bytes and one workspace of ws_bytes, all
  * 256-byte aligned, which must outlive the handle.  The library allocates
- * no device memory.  Every call enqueues work on the lattice's stream and
+ * no device memory (a handle holds a small pinned host buffer for the
+ * commit's read-back, a second stream and events).  Every call enqueues
+ * work on the lattice's stream and
  * returns without waiting, except hyb_commit, hyb_stats, hyb_concentration,
  * hyb_get_populations, hyb_set_populations and hyb_create, which synchronise
  * that stream.  A handle is not thread-safe.
