@@ -52,6 +52,55 @@ __device__ __forceinline__ T collide(T (&f)[kQ], T vx, T vy, T omega, T k) {
 __device__ __forceinline__ bool finite_val(double x) { return x - x == 0.0; }
 __device__ __forceinline__ bool finite_val(float x) { return x - x == 0.0f; }
 
+// Adds the number of active lanes whose flag is set to *ctr with one atomic
+// per wavefront (the one-node-per-thread kernels).
+__device__ __forceinline__ void count_lanes(unsigned long long *ctr, bool flag) {
+    const unsigned long long lanes = __ballot(flag);
+    if (lanes == 0ull) return;
+    if (__lane_id() == __ffsll(static_cast<long long>(lanes)) - 1) atomicAdd(ctr, static_cast<unsigned long long>(__popcll(lanes)));
+}
+
+// Event counts of one lane over a whole multi-step launch.  At the patch
+// edge a wavefront holds one perimeter node per round, so per-wavefront
+// aggregation still leaves one atomic per event; and device-scope atomics
+// on one address, issued from every XCD, serialise at the memory side and
+// hold up the sweep's own loads and stores there.  The sweeps therefore
+// count in registers and add to the device counters once per workgroup.
+struct Tally {
+    unsigned bad = 0u;          // infeasible closures at owned perimeter nodes
+    unsigned nonfinite = 0u;    // owned nodes whose concentration is not finite
+};
+
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Adds a workgroup's tallies to the device counters.  `edge` is uniform
+// over the workgroup (whether the tile with its ring reaches the patch
+// perimeter) and false where no closure ran, so only edge tiles take the
+// extra barrier; a non-finite value is rare enough to count per wavefront.
+template <int NT>
+__device__ __forceinline__ void flush_tally(const LbmArgs &a, const Tally &t, bool edge) {
+    if (__ballot(t.nonfinite != 0u) != 0ull) {
+        const unsigned s = wave_sum(t.nonfinite);
+        if (__lane_id() == 0) atomicAdd(&a.counters[kCntNonfinite], static_cast<unsigned long long>(s));
+    }
+    if (edge) {
+        __shared__ unsigned part[NT / 64];
+        const unsigned s = wave_sum(t.bad);
+        if (__lane_id() == 0) part[threadIdx.x / 64] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long sum = 0ull;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) sum += part[w];
+            if (sum != 0ull) atomicAdd(&a.counters[kCntInfeasible], sum);
+        }
+    }
+}
+
 // per-node reaction rate (k field in the arithmetic type) or the uniform one
 template <typename T>
 __device__ __forceinline__ T node_k(const LbmArgs &a, int n) {
@@ -186,7 +235,7 @@ __device__ __forceinline__ void interior_node(const LbmArgs &a, const S *__restr
             fd[q] = double(f[q]);
             if (q > 0 && kCx[q] * nx + kCy[q] * ny < 0.0) unknown |= 1u << q;
         }
-        if (closure_neumann(fd, unknown, nx, ny, 0.0, own)) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+        count_lanes(&a.counters[kCntInfeasible], closure_neumann(fd, unknown, nx, ny, 0.0, own));
 #pragma unroll
         for (int q = 0; q < kQ; ++q) f[q] = T(fd[q]);
     } else if (m & 0x1FEu) {
@@ -200,7 +249,7 @@ __device__ __forceinline__ void interior_node(const LbmArgs &a, const S *__restr
         }
     }
     const T u = collide<T>(f, T(vx), T(vy), T(a.omega), node_k<T>(a, n));
-    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+    count_lanes(&a.counters[kCntNonfinite], !finite_val(u));
 #pragma unroll
     for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(Pop<S>::st(f[q], q, a), &dst[q * plane + n]);
     if (a.u_out) static_cast<T *>(a.u_out)[n] = u;
@@ -225,9 +274,9 @@ __device__ __forceinline__ void perimeter_dirichlet_node(const LbmArgs &a, const
         else if ((m >> q) & 1u) f[q] = reactive<T>(a, Pop<S>::ld(src[kOpp[q] * plane + n], kOpp[q], a), q);
         else f[q] = Pop<S>::ld(src[q * plane + (j - kCy[q]) * P + i - kCx[q]], q, a);
     }
-    if (dirichlet_close<T>(a, f, unknown, p, a.lam)) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+    count_lanes(&a.counters[kCntInfeasible], dirichlet_close<T>(a, f, unknown, p, a.lam));
     const T u = collide<T>(f, T(a.vx[n]), T(a.vy[n]), T(a.omega), node_k<T>(a, n));
-    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+    count_lanes(&a.counters[kCntNonfinite], !finite_val(u));
 #pragma unroll
     for (int q = 0; q < kQ; ++q) dst[q * plane + n] = Pop<S>::st(f[q], q, a);
     if (a.u_out) static_cast<T *>(a.u_out)[n] = u;
@@ -399,13 +448,13 @@ __global__ void __launch_bounds__(128) lbm_perimeter_kernel(LbmArgs a) {
         const double inv_norm = rsqrt(double(sx * sx + sy * sy));
         bad = closure_neumann(f, unknown, sx * inv_norm, sy * inv_norm, value, own);
     }
-    if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+    count_lanes(&a.counters[kCntInfeasible], bad);
 
     T g[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) g[q] = T(f[q]);
     const T u = collide<T>(g, T(a.vx[n]), T(a.vy[n]), T(a.omega), node_k<T>(a, n));
-    if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+    count_lanes(&a.counters[kCntNonfinite], !finite_val(u));
 #pragma unroll
     for (int q = 0; q < kQ; ++q) dst[q * plane + n] = Pop<S>::st(g[q], q, a);
 }
@@ -544,6 +593,7 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
     const int x0 = tx * TW;
     const int y0 = ty * TH;
     const bool edge = reaches_perimeter(N, x0, y0, TW, TH, 1), edge2 = reaches_perimeter(N, x0, y0, TW, TH, 0);
+    Tally tally;
 
     // ---- first half: step j+1 on the tile and its ring, into LDS --------
     // Pull x - e_q reads plane q at row j - cy_q, column i - cx_q, both
@@ -633,10 +683,10 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
         }
         if (edge && (i == 0 || j == 0 || i == N - 1 || j == N - 1)) {
             const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
-            if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+            tally.bad += bad && owned;
         }
         const T u = collide<T>(f, T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
-        if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+        tally.nonfinite += owned && !finite_val(u);
         // the second half reads the first step's result in the arithmetic
         // type (FP16 shifted storage rounds to binary16 only at the store)
 #pragma unroll
@@ -740,16 +790,17 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
         }
         if (perim) {
             const bool bad = dirichlet_close<T>(a, g, unknown, perimeter_slot(N, i, j), a.lam2);
-            if (bad) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+            tally.bad += bad;
         }
         const T u = collide<T>(g, T(vx2[k]), T(vy2[k]), omega, node_k<T>(a, static_cast<int>(n)));
-        if (!finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+        tally.nonfinite += !finite_val(u);
 #pragma unroll
         for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(g[q], q, a), fdst, n * sz, q * SP * sz);
         if constexpr (MID) {
             if (a.u_out2) static_cast<T *>(a.u_out2)[n] = u;
         }
     }
+    flush_tally<NT>(a, tally, edge);
 }
 
 template <typename S, int TW, int TH, int NT, int PART>
@@ -856,7 +907,8 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
                                              const float (&vy)[Region<TW, TH, NT, RING>::ROUNDS],
                                              const int (&rr)[Region<TW, TH, NT, RING>::ROUNDS],
                                              const int (&cc)[Region<TW, TH, NT, RING>::ROUNDS],
-                                             const unsigned (&mo)[TW * TH / NT], double (&acc)[TW * TH / NT]) {
+                                             const unsigned (&mo)[TW * TH / NT], double (&acc)[TW * TH / NT],
+                                             Tally &tally) {
     typedef typename Pop<S>::T T;
     typedef Region<TW, TH, NT, RING> R;
     constexpr int W0 = TW + 2 * G, H0 = TH + 2 * G, PL = H0 * W0;
@@ -896,10 +948,10 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
         }
         if (perim) {
             const bool bad = dirichlet_close<T>(a, h[k], outside_bits(N, i, j), perimeter_slot(N, i, j), lam);
-            if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+            tally.bad += bad && owned;
         }
         const T u = collide<T>(h[k], T(vx[k]), T(vy[k]), omega, node_k<T>(a, static_cast<int>(n)));
-        if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+        tally.nonfinite += owned && !finite_val(u);
         if constexpr (RING == 0) {
 #pragma unroll
             for (int q = 0; q < kQ; ++q) Buf<S>::store_nt(Pop<S>::st(h[k][q], q, a), fdst, n * sz, q * SP * sz);
@@ -941,7 +993,7 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
         }
         __syncthreads();
         later_stages<S, TW, TH, NT, G, RING - 1, FLUX>(a, L0, x0, y0, fdst, mrs, vxr, vyr, m2, vx2, vy2, rr2, cc2,
-                                                      mo, acc);
+                                                      mo, acc, tally);
     }
 }
 
@@ -971,6 +1023,7 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
     const int x0 = tx * TW;
     const int y0 = ty * TH;
     const bool edge = reaches_perimeter(N, x0, y0, TW, TH, G);
+    Tally tally;
 
     // dissolving solids: flag words of the owned nodes, and for each owned
     // solid node with fluid neighbours its running flux sum (the previous
@@ -1072,10 +1125,10 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
         }
         if (edge && (i == 0 || j == 0 || i == N - 1 || j == N - 1)) {
             const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
-            if (bad && owned) atomicAdd(&a.counters[kCntInfeasible], 1ull);
+            tally.bad += bad && owned;
         }
         const T u = collide<T>(f, T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
-        if (owned && !finite_val(u)) atomicAdd(&a.counters[kCntNonfinite], 1ull);
+        tally.nonfinite += owned && !finite_val(u);
 #pragma unroll
         for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[q];
     }
@@ -1088,7 +1141,8 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
     region_fields<TW, TH, NT, G - 1>(N, P, x0, y0, mrs, vxr, vyr, m1, vx2, vy2, r1, c1);
     __syncthreads();
     later_stages<S, TW, TH, NT, G, G - 1, FLUX>(a, &lds[0][0][0], x0, y0, fdst, mrs, vxr, vyr, m1, vx2, vy2, r1,
-                                                c1, mo, acc);
+                                                c1, mo, acc, tally);
+    flush_tally<NT>(a, tally, edge);
 }
 
 template <typename S, int TW, int TH, int NT, int PART>
