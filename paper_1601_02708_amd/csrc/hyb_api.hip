@@ -363,7 +363,7 @@ struct hyb_handle {
         a.counters = counters;
         a.hs_scale = hs_scale;
         a.hs_inv = hs_inv;
-        for (int q = 0; q < kQ; ++q) a.hs_wc[q] = (float)kW[q] * hs_cref;
+        for (int q = 0; q < kQ; ++q) a.hs_wc[kWClass[q]] = (float)kW[q] * hs_cref;
         a.kappa_s = dissolve_on ? kappa_s : 0.0;
         a.c_sat = c_sat;
         a.flux = nullptr;

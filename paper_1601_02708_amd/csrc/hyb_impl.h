@@ -22,6 +22,10 @@ constexpr int kCy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int kOpp[kQ] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr double kW[kQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+// weight class of each direction (rest, axis, diagonal); w_q depends on q
+// only through it, and a direction and its opposite share it
+constexpr int kWClass[kQ] = {0, 1, 1, 1, 1, 2, 2, 2, 2};
+constexpr int kWClasses = 3;
 
 // Per-node lattice flags (uint16).  Fluid node: bit q (1..8) = the upstream
 // neighbour x - e_q is a solid node inside the patch (halfway bounce-back).
@@ -83,10 +87,13 @@ struct LbmArgs {
     int clamp;
     unsigned long long *counters;
     // FP16 shifted storage: stored g = (f - w_q c_ref) * scale (binary16);
-    // f = g / scale + w_q c_ref.  hs_wc[q] = w_q c_ref, scale a power of two.
+    // f = g / scale + w_q c_ref, scale a power of two.  hs_wc[c] = w c_ref
+    // for weight class c (three values rather than nine: fewer scalar
+    // registers, and a population decodes alike from plane q or its
+    // opposite, so a bounce-back select needs one decode).
     float hs_scale;
     float hs_inv;
-    float hs_wc[kQ];
+    float hs_wc[kWClasses];
     // surface reaction at fluid-solid links (dissolving solids): the
     // bounce-back value relaxes towards w_q c_sat at rate kappa_s (0: off)
     double kappa_s;
@@ -136,11 +143,11 @@ template <> struct Pop<_Float16> {
     typedef float T;
     // g * (1 / scale) is exact (power of two), so the FMA rounds once
     static __device__ __forceinline__ float ld(_Float16 x, int q, const LbmArgs &a) {
-        return __builtin_fmaf(static_cast<float>(x), a.hs_inv, a.hs_wc[q]);
+        return __builtin_fmaf(static_cast<float>(x), a.hs_inv, a.hs_wc[kWClass[q]]);
     }
     // round to nearest even
     static __device__ __forceinline__ _Float16 st(float f, int q, const LbmArgs &a) {
-        return static_cast<_Float16>((f - a.hs_wc[q]) * a.hs_scale);
+        return static_cast<_Float16>((f - a.hs_wc[kWClass[q]]) * a.hs_scale);
     }
 };
 
