@@ -19,6 +19,8 @@
 // FP64 Newton solve would otherwise lower the occupancy of the sweep).
 #include "hyb_impl.h"
 
+#include <type_traits>
+
 namespace hyb {
 namespace {
 
@@ -99,6 +101,24 @@ __device__ __forceinline__ void flush_tally(const LbmArgs &a, const Tally &t, bo
             if (sum != 0ull) atomicAdd(&a.counters[kCntInfeasible], sum);
         }
     }
+}
+
+// Address of the value a node pulls along q from an LDS stage: the upstream
+// slot `pull` or, where the upstream node is solid (flag bit q set), the
+// node's own opposite slot `back` (halfway bounce-back); both in elements
+// from the node's slot.  The flag bit goes through an empty asm statement so
+// that the compiler cannot see its 0/1 range: it would turn
+// bit * (back - pull) into a compare and a select between two constants it
+// first moves into registers (six VALU instructions per direction); as an
+// opaque product it is a bit-field extract and one 24-bit multiply-add.  An
+// LDS byte offset always fits the multiply's signed 24 bits.
+template <typename T>
+__device__ __forceinline__ const T *pull_or_back(const T *node, unsigned m, int q, int pull, int back) {
+    int bit = static_cast<int>(__builtin_amdgcn_ubfe(m, static_cast<unsigned>(q), 1u));
+    asm("" : "+v"(bit));
+    constexpr int sz = static_cast<int>(sizeof(T));
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(node) + pull * sz +
+                                       __mul24(bit, (back - pull) * sz));
 }
 
 // per-node reaction rate (k field in the arithmetic type) or the uniform one
@@ -576,6 +596,7 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
     static_assert((TW * TH) % NT == 0 && NT % TW == 0, "second half: whole rows per round");
     constexpr int ROUNDS2 = TW * TH / NT;
     constexpr unsigned sz = sizeof(S);
+    static_assert(sizeof(T) * kQ * R1 < (1u << 23), "pull_or_back: LDS byte offsets within 24 bits");
     __shared__ T lds[kQ][H1][W1];
 
     const int N = a.N;
@@ -776,12 +797,8 @@ __device__ __forceinline__ void sweep2_body(const LbmArgs &a, const TileMap &map
             // node); closure unknowns are overwritten below
             const T *base = &lds[0][0][0] + (r + 1) * W1 + (c + 1);
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const int pull = q * (H1 * W1) - kCy[q] * W1 - kCx[q];
-                const int back = kOpp[q] * (H1 * W1);
-                const int sel = -static_cast<int>((m2[k] >> q) & 1u);
-                g[q] = base[pull + (sel & (back - pull))];
-            }
+            for (int q = 0; q < kQ; ++q)
+                g[q] = *pull_or_back(base, m2[k], q, q * (H1 * W1) - kCy[q] * W1 - kCx[q], kOpp[q] * (H1 * W1));
             if constexpr (FLUX) {
 #pragma unroll
                 for (int q = 1; q < kQ; ++q)
@@ -898,7 +915,7 @@ __device__ __forceinline__ void region_fields(int N, int P, int x0, int y0, cons
 // results to registers, the next region's fields fetched, barrier, results
 // written back in place, barrier, next stage.  RING = 0: the owned nodes,
 // stored to HBM.
-template <typename S, int TW, int TH, int NT, int G, int RING, bool FLUX>
+template <typename S, int TW, int TH, int NT, int G, int RING, bool FLUX, bool EDGE>
 __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::T *L0, int x0, int y0,
                                              const BufRsrc &fdst, const BufRsrc &mrs, const BufRsrc &vxr,
                                              const BufRsrc &vyr,
@@ -914,13 +931,16 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
     constexpr int W0 = TW + 2 * G, H0 = TH + 2 * G, PL = H0 * W0;
     constexpr int OFF = G - RING;               // region origin in LDS coordinates
     constexpr int STAGE = G + 1 - RING;
+    static_assert(sizeof(T) * kQ * PL < (1u << 23), "pull_or_back: LDS byte offsets within 24 bits");
     constexpr unsigned sz = sizeof(S);
     const int N = a.N;
     const int P = a.pitch;
     const unsigned SP = static_cast<unsigned>(a.plane);
     const T omega = T(a.omega);
     const double lam = stage_lam(a, STAGE);
-    const bool edge = reaches_perimeter(N, x0, y0, TW, TH, RING);
+    // EDGE false: the caller found that no stage of this tile reaches the
+    // perimeter, so the node loop carries no perimeter test or closure
+    const bool edge = EDGE && reaches_perimeter(N, x0, y0, TW, TH, RING);
     T h[R::ROUNDS][kQ];
 #pragma unroll
     for (int k = 0; k < R::ROUNDS; ++k) {
@@ -935,12 +955,7 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
         // closure unknowns are overwritten below
         const T *base = L0 + (r + OFF) * W0 + (c + OFF);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const int pull = q * PL - kCy[q] * W0 - kCx[q];
-            const int back = kOpp[q] * PL;
-            const int sel = -static_cast<int>((m[k] >> q) & 1u);
-            h[k][q] = base[pull + (sel & (back - pull))];
-        }
+        for (int q = 0; q < kQ; ++q) h[k][q] = *pull_or_back(base, m[k], q, q * PL - kCy[q] * W0 - kCx[q], kOpp[q] * PL);
         if constexpr (FLUX) {
 #pragma unroll
             for (int q = 1; q < kQ; ++q)
@@ -992,8 +1007,8 @@ __device__ __forceinline__ void later_stages(const LbmArgs &a, typename Pop<S>::
             for (int q = 0; q < kQ; ++q) L0[q * PL + (rr[k] + OFF) * W0 + (cc[k] + OFF)] = h[k][q];
         }
         __syncthreads();
-        later_stages<S, TW, TH, NT, G, RING - 1, FLUX>(a, L0, x0, y0, fdst, mrs, vxr, vyr, m2, vx2, vy2, rr2, cc2,
-                                                      mo, acc, tally);
+        later_stages<S, TW, TH, NT, G, RING - 1, FLUX, EDGE>(a, L0, x0, y0, fdst, mrs, vxr, vyr, m2, vx2, vy2, rr2,
+                                                            cc2, mo, acc, tally);
     }
 }
 
@@ -1060,88 +1075,97 @@ __device__ __forceinline__ void sweepk_body(const LbmArgs &a, const TileMap &map
         }
     }
 
-    // ---- stage 1: step j+1 on the tile and G rings, HBM -> LDS ----------
-    S raw[ROUNDS0][kQ];
-    unsigned m[ROUNDS0];
-    float vx1[ROUNDS0], vy1[ROUNDS0];
-    int rr[ROUNDS0], cc[ROUNDS0];
-    region_coords<W0, NT, ROUNDS0>(rr, cc);
+    // The stages run in one of two compiled copies: tiles whose widest
+    // region reaches the perimeter take the perimeter tests, the clamped
+    // patch-edge loads and the closures; every other tile (most of them) a
+    // copy without them.
+    auto stages = [&](auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
+        // ---- stage 1: step j+1 on the tile and G rings, HBM -> LDS ----------
+        S raw[ROUNDS0][kQ];
+        unsigned m[ROUNDS0];
+        float vx1[ROUNDS0], vy1[ROUNDS0];
+        int rr[ROUNDS0], cc[ROUNDS0];
+        region_coords<W0, NT, ROUNDS0>(rr, cc);
 #pragma unroll
-    for (int k = 0; k < ROUNDS0; ++k) {
-        const int i = x0 - G + cc[k], j = y0 - G + rr[k];
-        m[k] = kMaskSolid;
-        if (rr[k] < H0 && i >= 0 && j >= 0 && i < N && j < N)
-            m[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * static_cast<unsigned>(j * P + i), 0, 0);
-    }
-    unsigned Kq[kQ], Dq[kQ];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        const unsigned pull = q * SP - static_cast<unsigned>(kCx[q] + kCy[q] * P);
-        const unsigned own = kOpp[q] * SP;
-        Kq[q] = pull * sz;
-        Dq[q] = (own - pull) * sz;           // modulo 2^32; the sum below is exact
-    }
-#pragma unroll
-    for (int k = 0; k < ROUNDS0; ++k) {
-        if (m[k] & kMaskSolid) continue;
-        const int i = x0 - G + cc[k], j = y0 - G + rr[k];
-        const unsigned n = static_cast<unsigned>(j * P + i);
-        vx1[k] = Buf<float>::load(vxr, 4u * n, 0);
-        vy1[k] = Buf<float>::load(vyr, 4u * n, 0);
-        if (i >= 1 && j >= 1 && i <= N - 2 && j <= N - 2) {
-            const unsigned nb = n * sz;
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const unsigned sel = 0u - ((m[k] >> q) & 1u);
-                raw[k][q] = Buf<S>::load(fsrc, nb + Kq[q] + (sel & Dq[q]), 0);
-            }
-        } else {
-            const int jm = j > 0 ? j - 1 : 0, jp = j < N - 1 ? j + 1 : N - 1;
-            const int il = i > 0 ? i - 1 : 0, ir = i < N - 1 ? i + 1 : N - 1;
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const int sj = kCy[q] == 1 ? jm : kCy[q] == -1 ? jp : j;
-                const int si = kCx[q] == 1 ? il : kCx[q] == -1 ? ir : i;
-                const unsigned pull = q * SP + static_cast<unsigned>(sj * P + si);
-                const unsigned own = kOpp[q] * SP + n;
-                raw[k][q] = Buf<S>::load(fsrc, (((m[k] >> q) & 1u) ? own : pull) * sz, 0);
-            }
+        for (int k = 0; k < ROUNDS0; ++k) {
+            const int i = x0 - G + cc[k], j = y0 - G + rr[k];
+            m[k] = kMaskSolid;
+            if (rr[k] < H0 && (!EDGE || (i >= 0 && j >= 0 && i < N && j < N)))
+                m[k] = __builtin_amdgcn_raw_buffer_load_b16(mrs, 2u * static_cast<unsigned>(j * P + i), 0, 0);
         }
-    }
-#pragma unroll
-    for (int k = 0; k < ROUNDS0; ++k) {
-        if (m[k] & kMaskSolid) continue;
-        const int r = rr[k], c = cc[k];
-        const int i = x0 - G + c, j = y0 - G + r;
-        const unsigned n = static_cast<unsigned>(j * P + i);
-        const bool owned = r >= G && r < G + TH && c >= G && c < G + TW;
-        T f[kQ];
+        unsigned Kq[kQ], Dq[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
-            const T pulled = Pop<S>::ld(raw[k][q], q, a);
-            const T own = Pop<S>::ld(raw[k][q], kOpp[q], a);
-            if constexpr (FLUX) f[q] = ((m[k] >> q) & 1u) ? reactive<T>(a, own, q) : pulled;
-            else f[q] = ((m[k] >> q) & 1u) ? own : pulled;
+            const unsigned pull = q * SP - static_cast<unsigned>(kCx[q] + kCy[q] * P);
+            const unsigned own = kOpp[q] * SP;
+            Kq[q] = pull * sz;
+            Dq[q] = (own - pull) * sz;           // modulo 2^32; the sum below is exact
         }
-        if (edge && (i == 0 || j == 0 || i == N - 1 || j == N - 1)) {
-            const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
-            tally.bad += bad && owned;
-        }
-        const T u = collide<T>(f, T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
-        tally.nonfinite += owned && !finite_val(u);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[q];
-    }
+        for (int k = 0; k < ROUNDS0; ++k) {
+            if (m[k] & kMaskSolid) continue;
+            const int i = x0 - G + cc[k], j = y0 - G + rr[k];
+            const unsigned n = static_cast<unsigned>(j * P + i);
+            vx1[k] = Buf<float>::load(vxr, 4u * n, 0);
+            vy1[k] = Buf<float>::load(vyr, 4u * n, 0);
+            if (!EDGE || (i >= 1 && j >= 1 && i <= N - 2 && j <= N - 2)) {
+                const unsigned nb = n * sz;
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    const unsigned sel = 0u - ((m[k] >> q) & 1u);
+                    raw[k][q] = Buf<S>::load(fsrc, nb + Kq[q] + (sel & Dq[q]), 0);
+                }
+            } else {
+                const int jm = j > 0 ? j - 1 : 0, jp = j < N - 1 ? j + 1 : N - 1;
+                const int il = i > 0 ? i - 1 : 0, ir = i < N - 1 ? i + 1 : N - 1;
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    const int sj = kCy[q] == 1 ? jm : kCy[q] == -1 ? jp : j;
+                    const int si = kCx[q] == 1 ? il : kCx[q] == -1 ? ir : i;
+                    const unsigned pull = q * SP + static_cast<unsigned>(sj * P + si);
+                    const unsigned own = kOpp[q] * SP + n;
+                    raw[k][q] = Buf<S>::load(fsrc, (((m[k] >> q) & 1u) ? own : pull) * sz, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ROUNDS0; ++k) {
+            if (m[k] & kMaskSolid) continue;
+            const int r = rr[k], c = cc[k];
+            const int i = x0 - G + c, j = y0 - G + r;
+            const unsigned n = static_cast<unsigned>(j * P + i);
+            const bool owned = r >= G && r < G + TH && c >= G && c < G + TW;
+            T f[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const T pulled = Pop<S>::ld(raw[k][q], q, a);
+                const T own = Pop<S>::ld(raw[k][q], kOpp[q], a);
+                if constexpr (FLUX) f[q] = ((m[k] >> q) & 1u) ? reactive<T>(a, own, q) : pulled;
+                else f[q] = ((m[k] >> q) & 1u) ? own : pulled;
+            }
+            if (EDGE && (i == 0 || j == 0 || i == N - 1 || j == N - 1)) {
+                const bool bad = dirichlet_close<T>(a, f, outside_bits(N, i, j), perimeter_slot(N, i, j), a.lam);
+                tally.bad += bad && owned;
+            }
+            const T u = collide<T>(f, T(vx1[k]), T(vy1[k]), omega, node_k<T>(a, static_cast<int>(n)));
+            tally.nonfinite += owned && !finite_val(u);
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) lds[q][r][c] = f[q];
+        }
 
-    // the next region's flags and velocities, fetched before the barrier
-    typedef Region<TW, TH, NT, G - 1> R1;
-    unsigned m1[R1::ROUNDS];
-    float vx2[R1::ROUNDS], vy2[R1::ROUNDS];
-    int r1[R1::ROUNDS], c1[R1::ROUNDS];
-    region_fields<TW, TH, NT, G - 1>(N, P, x0, y0, mrs, vxr, vyr, m1, vx2, vy2, r1, c1);
-    __syncthreads();
-    later_stages<S, TW, TH, NT, G, G - 1, FLUX>(a, &lds[0][0][0], x0, y0, fdst, mrs, vxr, vyr, m1, vx2, vy2, r1,
-                                                c1, mo, acc, tally);
+        // the next region's flags and velocities, fetched before the barrier
+        typedef Region<TW, TH, NT, G - 1> R1;
+        unsigned m1[R1::ROUNDS];
+        float vx2[R1::ROUNDS], vy2[R1::ROUNDS];
+        int r1[R1::ROUNDS], c1[R1::ROUNDS];
+        region_fields<TW, TH, NT, G - 1>(N, P, x0, y0, mrs, vxr, vyr, m1, vx2, vy2, r1, c1);
+        __syncthreads();
+        later_stages<S, TW, TH, NT, G, G - 1, FLUX, EDGE>(a, &lds[0][0][0], x0, y0, fdst, mrs, vxr, vyr, m1, vx2,
+                                                          vy2, r1, c1, mo, acc, tally);
+    };
+    if (edge) stages(std::true_type{});
+    else stages(std::false_type{});
     flush_tally<NT>(a, tally, edge);
 }
 
