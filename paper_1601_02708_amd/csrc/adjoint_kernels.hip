@@ -21,6 +21,8 @@
 // sweep.
 #include "hyb_impl.h"
 
+#include <type_traits>
+
 namespace hyb {
 namespace {
 
@@ -53,7 +55,7 @@ __device__ __forceinline__ size_t dense_at(int N, int q, int i, int j) {
 // when given (a paired launch then adds both steps' terms at once), else
 // grad_k becomes (grad_k - prior) - term: prior is the term of the reversed
 // step before, held back, so the sum is that of two separate updates.
-template <typename T>
+template <typename T, bool EDGE = true>
 __device__ __forceinline__ void adj_nu_of(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
                                           const T (&l)[kQ], bool owner, double *__restrict__ grad_a,
                                           double *__restrict__ grad_b, double *__restrict__ grad_k, T (&nu)[kQ],
@@ -101,7 +103,7 @@ __device__ __forceinline__ void adj_nu_of(const LbmArgs &a, int i, int j, const 
             grad_k[at] = (grad_k[at] - prior) - term;
         }
     }
-    if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
+    if (EDGE && (i == 0 || j == 0 || i == N - 1 || j == N - 1)) {
         unsigned unknown = 0;
 #pragma unroll
         for (int q = 1; q < kQ; ++q) {
@@ -148,7 +150,7 @@ __device__ __forceinline__ void adj_nu_of(const LbmArgs &a, int i, int j, const 
 }
 
 // nu at node (i, j) with the node's cotangent read from lam
-template <typename T>
+template <typename T, bool EDGE = true>
 __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *__restrict__ snext,
                                        const T *__restrict__ lam, const double *__restrict__ lam_dense, bool owner,
                                        double *__restrict__ grad_a, double *__restrict__ grad_b,
@@ -168,7 +170,7 @@ __device__ __forceinline__ void adj_nu(const LbmArgs &a, int i, int j, const T *
 #pragma unroll
         for (int q = 0; q < kQ; ++q) l[q] = lam[q * plane + n];
     }
-    adj_nu_of<T>(a, i, j, snext, l, owner, grad_a, grad_b, grad_k, nu, stash);
+    adj_nu_of<T, EDGE>(a, i, j, snext, l, owner, grad_a, grad_b, grad_k, nu, stash);
 }
 
 // One reversed fine step.  Phase 1: nu for the tile grown by one ring (0
@@ -270,93 +272,102 @@ __global__ void __launch_bounds__(NT) adj_step2_kernel(LbmArgs a1, LbmArgs a2, c
     const int N = a1.N, P = a1.pitch;
     const int plane = static_cast<int>(a1.plane);
     const int x0 = (blockIdx.x % tiles_x) * TW, y0 = (blockIdx.x / tiles_x) * TH;
-    // ---- phase 1: nu of step t, two rings ---------------------------------
-    for (int r = threadIdx.x; r < W2 * H2; r += NT) {
-        const int lx = r % W2, ly = r / W2;
-        const int i = x0 - 2 + lx, j = y0 - 2 + ly;
-        T nu[kQ];
-        if (i < 0 || j < 0 || i >= N || j >= N) {
+    // Two compiled copies: a tile whose two-ring region reaches the patch
+    // perimeter (or its end) takes the bounds tests and the closure's
+    // transpose; every other tile (most of them) a copy without them.
+    const bool edge = x0 - 2 <= 0 || y0 - 2 <= 0 || x0 + TW + 1 >= N - 1 || y0 + TH + 1 >= N - 1;
+    auto phases = [&](auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
+        // ---- phase 1: nu of step t, two rings ---------------------------------
+        for (int r = threadIdx.x; r < W2 * H2; r += NT) {
+            const int lx = r % W2, ly = r / W2;
+            const int i = x0 - 2 + lx, j = y0 - 2 + ly;
+            T nu[kQ];
+            if (EDGE && (i < 0 || j < 0 || i >= N || j >= N)) {
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) nu[q] = T(0);
-        } else {
+                for (int q = 0; q < kQ; ++q) nu[q] = T(0);
+            } else {
+                const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
+                adj_nu<T, EDGE>(a1, i, j, snext1, lam, dn.lam_dense, owner, grad_a, grad_b, grad_k, nu,
+                          STASH && owner ? &kst[STASH ? ly - 2 : 0][STASH ? lx - 2 : 0] : nullptr);
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = nu[q];
+        }
+        __syncthreads();
+        // ---- phase 2: dJ/df*(t) on one ring, then nu of step t-1 --------------
+        const T keep = T(1.0 - a1.kappa_s);
+        T h[R1][kQ];
+#pragma unroll
+        for (int k = 0; k < R1; ++k) {
+            const int r = threadIdx.x + NT * k;
+            const int lx = 1 + r % W1, ly = 1 + r / W1;      // ring-2 coordinates of the one-ring node
+            const int i = x0 - 2 + lx, j = y0 - 2 + ly;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) h[k][q] = T(0);
+            if (r >= W1 * H1 || (EDGE && (i < 0 || j < 0 || i >= N || j >= N))) continue;
+            const int n = j * P + i;
+            const unsigned m = a1.mask[n];
+            if (m & kMaskSolid) continue;
+            T l[kQ];
+#pragma unroll
+            for (int p = 0; p < kQ; ++p) {
+                T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
+                const int q = kOpp[p];
+                if ((m >> q) & 1u) acc += keep * nus[q][ly][lx];
+                if (inj_mid) acc += inj_mid[p * plane + n];
+                l[p] = acc;
+            }
             const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
-            adj_nu<T>(a1, i, j, snext1, lam, dn.lam_dense, owner, grad_a, grad_b, grad_k, nu,
-                      STASH && owner ? &kst[STASH ? ly - 2 : 0][STASH ? lx - 2 : 0] : nullptr);
+            adj_nu_of<T, EDGE>(a2, i, j, snext2, l, owner, grad_a, grad_b, grad_k, h[k], nullptr,
+                         STASH && owner ? kst[STASH ? ly - 2 : 0][STASH ? lx - 2 : 0] : 0.0);
         }
+        __syncthreads();             // every read of step t's nu is done
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = nu[q];
-    }
-    __syncthreads();
-    // ---- phase 2: dJ/df*(t) on one ring, then nu of step t-1 --------------
-    const T keep = T(1.0 - a1.kappa_s);
-    T h[R1][kQ];
+        for (int k = 0; k < R1; ++k) {
+            const int r = threadIdx.x + NT * k;
+            if (r >= W1 * H1) continue;
+            const int lx = 1 + r % W1, ly = 1 + r / W1;
 #pragma unroll
-    for (int k = 0; k < R1; ++k) {
-        const int r = threadIdx.x + NT * k;
-        const int lx = 1 + r % W1, ly = 1 + r / W1;      // ring-2 coordinates of the one-ring node
-        const int i = x0 - 2 + lx, j = y0 - 2 + ly;
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) h[k][q] = T(0);
-        if (r >= W1 * H1 || i < 0 || j < 0 || i >= N || j >= N) continue;
-        const int n = j * P + i;
-        const unsigned m = a1.mask[n];
-        if (m & kMaskSolid) continue;
-        T l[kQ];
-#pragma unroll
-        for (int p = 0; p < kQ; ++p) {
-            T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
-            const int q = kOpp[p];
-            if ((m >> q) & 1u) acc += keep * nus[q][ly][lx];
-            if (inj_mid) acc += inj_mid[p * plane + n];
-            l[p] = acc;
+            for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = h[k][q];
         }
-        const bool owner = lx >= 2 && lx <= TW + 1 && ly >= 2 && ly <= TH + 1;
-        adj_nu_of<T>(a2, i, j, snext2, l, owner, grad_a, grad_b, grad_k, h[k], nullptr,
-                     STASH && owner ? kst[STASH ? ly - 2 : 0][STASH ? lx - 2 : 0] : 0.0);
-    }
-    __syncthreads();             // every read of step t's nu is done
+        __syncthreads();
+        // ---- phase 3: the owned nodes' dJ/df*(t-1) -----------------------------
+        const T keep2 = T(1.0 - a2.kappa_s);
+        for (int r = threadIdx.x; r < TW * TH; r += NT) {
+            const int lx = 2 + r % TW, ly = 2 + r / TW;
+            const int i = x0 + lx - 2, j = y0 + ly - 2;
+            if (EDGE && (i >= N || j >= N)) continue;
+            const int n = j * P + i;
+            const unsigned m = a2.mask[n];
+            if (m & kMaskSolid) {
+                if (dn.out_dense) {
+                    if (!dn.accumulate)
 #pragma unroll
-    for (int k = 0; k < R1; ++k) {
-        const int r = threadIdx.x + NT * k;
-        if (r >= W1 * H1) continue;
-        const int lx = 1 + r % W1, ly = 1 + r / W1;
+                        for (int q = 0; q < kQ; ++q) dn.out_dense[dense_at(N, q, i, j)] = 0.0;
+                } else {
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) nus[q][ly][lx] = h[k][q];
-    }
-    __syncthreads();
-    // ---- phase 3: the owned nodes' dJ/df*(t-1) -----------------------------
-    const T keep2 = T(1.0 - a2.kappa_s);
-    for (int r = threadIdx.x; r < TW * TH; r += NT) {
-        const int lx = 2 + r % TW, ly = 2 + r / TW;
-        const int i = x0 + lx - 2, j = y0 + ly - 2;
-        if (i >= N || j >= N) continue;
-        const int n = j * P + i;
-        const unsigned m = a2.mask[n];
-        if (m & kMaskSolid) {
-            if (dn.out_dense) {
-                if (!dn.accumulate)
-#pragma unroll
-                    for (int q = 0; q < kQ; ++q) dn.out_dense[dense_at(N, q, i, j)] = 0.0;
-            } else {
-#pragma unroll
-                for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+                    for (int q = 0; q < kQ; ++q) out[q * plane + n] = T(0);
+                }
+                continue;
             }
-            continue;
-        }
 #pragma unroll
-        for (int p = 0; p < kQ; ++p) {
-            T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
-            const int q = kOpp[p];
-            if ((m >> q) & 1u) acc += keep2 * nus[q][ly][lx];
-            if (inj_out) acc += inj_out[p * plane + n];
-            if (dn.out_dense) {
-                const size_t d = dense_at(N, p, i, j);
-                dn.out_dense[d] = dn.accumulate ? dn.out_dense[d] + double(acc) : double(acc);
-            } else {
-                out[p * plane + n] = acc;
+            for (int p = 0; p < kQ; ++p) {
+                T acc = nus[p][ly + kCy[p]][lx + kCx[p]];
+                const int q = kOpp[p];
+                if ((m >> q) & 1u) acc += keep2 * nus[q][ly][lx];
+                if (inj_out) acc += inj_out[p * plane + n];
+                if (dn.out_dense) {
+                    const size_t d = dense_at(N, p, i, j);
+                    dn.out_dense[d] = dn.accumulate ? dn.out_dense[d] + double(acc) : double(acc);
+                } else {
+                    out[p * plane + n] = acc;
+                }
             }
         }
-    }
+    };
+    if (edge) phases(std::true_type{});
+    else phases(std::false_type{});
 }
 
 // dense FP64 [9][N][N] <-> pitched planes of T
