@@ -646,7 +646,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp32", "fp64", "fp16s"])
     ap.add_argument("--steps-per-launch", type=int, default=None, choices=[1, 2, 3, 4, 5],
                     help="most fine steps per lattice-sweep launch (temporal blocking; eta = 10 runs 5 + 5 at 5, "
-                         "4 + 3 + 3 at 4); default: the library's (5 fp32, 4 fp64, 2 fp16s)")
+                         "4 + 3 + 3 at 4); default: the library's (5 fp32, 4 fp64, 4 fp16s)")
     ap.add_argument("--overlap", type=int, default=-1,
                     help="overlap depth of hyb_step (-1: the library's tuning, on a separate handle)")
     ap.add_argument("--timing-steps", type=int, default=10,
